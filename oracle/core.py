@@ -1,0 +1,130 @@
+"""Geometry and FP64 projectors of the reference oracle (test infrastructure only).
+
+The paper's operators are ASTRA's explicit matrices (Sec. 6.1); here the forward
+projector A is the line model (exact ray/pixel intersection lengths), A^T its exact
+transpose, and B the unmatched back projector that interpolates linearly on the
+detector at each pixel centre. Conventions are spelled out in ``projectors.c``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle_proj.so")
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            from .build import build
+            build()
+        lib = ctypes.CDLL(_LIB_PATH)
+        dp = ctypes.POINTER(ctypes.c_double)
+        for name in ("orc_forward", "orc_adjoint", "orc_backproject_hat"):
+            f = getattr(lib, name)
+            f.restype = None
+            f.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, ctypes.c_int, ctypes.c_double, dp, dp]
+        lib.orc_num_threads.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def angle_table(n_ang: int, ang_range: float = 180.0, ang_start: float = 0.0, angles_deg=None):
+    """theta_a = start + a*range/n_ang degrees (Table 6.1: 0,1,..,179 and 0,0.3,..,179.7).
+
+    cos/sin are exact (0, +-1) at multiples of 90 degrees so that axis-aligned rays are
+    recognised as such.
+    """
+    if angles_deg is None:
+        th = ang_start + (np.arange(n_ang, dtype=np.float64) * ang_range) / n_ang
+    else:
+        th = np.asarray(angles_deg, dtype=np.float64)
+    rad = th * (np.pi / 180.0)
+    c = np.cos(rad)
+    s = np.sin(rad)
+    for a, t in enumerate(th):
+        if np.fmod(t, 90.0) == 0.0:
+            quadrant = int(round(t / 90.0)) % 4
+            c[a], s[a] = [(1.0, 0.0), (0.0, 1.0), (-1.0, 0.0), (0.0, -1.0)][quadrant]
+    return th, c, s
+
+
+class Geometry:
+    """2-D parallel-beam scan of an N x N unit-pixel image: n = N^2, m = n_ang*n_det."""
+
+    def __init__(self, N: int, n_ang: int, n_det: int, ang_range: float = 180.0,
+                 ang_start: float = 0.0, angles_deg=None, det_spacing: float = 1.0):
+        self.N = int(N)
+        self.n_det = int(n_det)
+        self.ds = float(det_spacing)
+        self.theta, self.cos, self.sin = angle_table(n_ang, ang_range, ang_start, angles_deg)
+        self.n_ang = len(self.theta)
+        self.n = self.N * self.N
+        self.m = self.n_ang * self.n_det
+
+    @property
+    def s(self) -> np.ndarray:
+        """Detector bin centres s_i = (i - (n_det-1)/2) * ds."""
+        return (np.arange(self.n_det, dtype=np.float64) - 0.5 * (self.n_det - 1)) * self.ds
+
+    def _call(self, name, src, n_out):
+        src = np.ascontiguousarray(src, dtype=np.float64)
+        out = np.empty(n_out, dtype=np.float64)
+        getattr(_load(), name)(self.N, self.n_ang, _ptr(self.cos), _ptr(self.sin), self.n_det,
+                               self.ds, _ptr(src), _ptr(out))
+        return out
+
+    def A(self, x: np.ndarray) -> np.ndarray:
+        """Forward projection y = A x (line model)."""
+        assert x.size == self.n
+        return self._call("orc_forward", x, self.m)
+
+    def AT(self, y: np.ndarray) -> np.ndarray:
+        """Matched back projection x = A^T y."""
+        assert y.size == self.m
+        return self._call("orc_adjoint", y, self.n)
+
+    def B_hat(self, y: np.ndarray) -> np.ndarray:
+        """Unmatched back projection x = B y (linear interpolation on the detector)."""
+        assert y.size == self.m
+        return self._call("orc_backproject_hat", y, self.n)
+
+    def back(self, kind: str):
+        return {"hat": self.B_hat, "adj": self.AT}[kind]
+
+
+def assemble_dense(g: Geometry):
+    """Explicit A (m x n), A^T-kernel and B (n x m) by applying the operators to unit
+    vectors -- only for tiny geometries."""
+    A = np.zeros((g.m, g.n))
+    for j in range(g.n):
+        e = np.zeros(g.n)
+        e[j] = 1.0
+        A[:, j] = g.A(e)
+    AT = np.zeros((g.n, g.m))
+    B = np.zeros((g.n, g.m))
+    for i in range(g.m):
+        e = np.zeros(g.m)
+        e[i] = 1.0
+        AT[:, i] = g.AT(e)
+        B[:, i] = g.B_hat(e)
+    return A, AT, B
+
+
+def basis_storage(method: str, k: int, m: int, n: int) -> int:
+    """Number of stored basis entries after k iterations: AB keeps k vectors of length
+    m, BA k vectors of length n (Sec. 6.2, storage rows of Table 6.3)."""
+    return k * (m if method == "ab" else n)
+
+
+def num_threads() -> int:
+    return int(_load().orc_num_threads())

@@ -1,0 +1,153 @@
+/*
+ * FP64 reference projectors for 2-D parallel-beam CT -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Part of the reference oracle: only the test-suite, the smoke check and the CPU
+ * baseline of the benchmark load this library. It shares no code with the GPU path.
+ *
+ * Conventions (the paper leaves them open; Sec. 6.1 and Table 6.1 fix only sizes):
+ *   image  : N x N unit pixels centred on the origin; pixel (r, c), linear index
+ *            j = r*N + c, covers [c-N/2, c-N/2+1] x [r-N/2, r-N/2+1].
+ *   angles : omega_a = (cos th_a, sin th_a), passed in by the caller.
+ *   rays   : line {p : <p, omega_a> = s_i}, s_i = (i - (n_det-1)/2) * ds,
+ *            sinogram index a*n_det + i.
+ *
+ * A (line model, eq. 1.1's forward projector): A[(a,i), j] = length of ray (a,i)
+ * inside pixel j. For a unit square whose centre projects to t0 on omega, this
+ * length is a trapezoid in t = s - t0: with p = max(|cos|,|sin|), q = min(...),
+ *     1/p                     for |t| <= (p-q)/2,
+ *     ((p+q)/2 - |t|)/(p q)   for (p-q)/2 < |t| < (p+q)/2,
+ *     0                       otherwise;
+ * for q = 0 (axis-aligned rays) it is 1 for |t| < 1/2, 0 for |t| > 1/2 and 1/2 at
+ * |t| = 1/2: a ray along a pixel edge is split evenly between the two pixels.
+ *
+ * B (unmatched back projector): B[j, (a,i)] = max(0, 1 - |u - i|) / ds with
+ * u = (<c_j, omega_a> - s_0)/ds: linear interpolation of the sinogram row at the
+ * detector position of the pixel centre, scaled so that B approximates A^T.
+ *
+ * The three operators are evaluated pixel-driven from these closed forms, with an
+ * explicit loop over the detector bins each pixel can reach.
+ */
+#include <math.h>
+#include <stddef.h>
+
+static double trap(double t, double p, double q)
+{
+    double at = fabs(t);
+    if (q == 0.0) {
+        if (at < 0.5) return 1.0 / p;
+        if (at == 0.5) return 0.5 / p;
+        return 0.0;
+    }
+    double flat = 0.5 * (p - q), outer = 0.5 * (p + q);
+    if (at <= flat) return 1.0 / p;
+    if (at >= outer) return 0.0;
+    return (outer - at) / (p * q);
+}
+
+static double hat(double v)
+{
+    double a = 1.0 - fabs(v);
+    return a > 0.0 ? a : 0.0;
+}
+
+static void pixel_centre(int N, int j, double *xc, double *yc)
+{
+    int r = j / N, c = j % N;
+    *xc = (double)c - 0.5 * N + 0.5;
+    *yc = (double)r - 0.5 * N + 0.5;
+}
+
+/* Range of bins i whose centre s_i lies within `reach` of position t0. */
+static void bin_range(double t0, double reach, double s0, double ds, int n_det,
+                      int *i_lo, int *i_hi)
+{
+    int lo = (int)floor((t0 - reach - s0) / ds) - 1;
+    int hi = (int)ceil((t0 + reach - s0) / ds) + 1;
+    if (lo < 0) lo = 0;
+    if (hi > n_det - 1) hi = n_det - 1;
+    *i_lo = lo;
+    *i_hi = hi;
+}
+
+/* y = A x. Each thread owns whole sinogram rows (one angle), so no two threads
+ * write the same entry and the summation order is fixed. */
+void orc_forward(int N, int n_ang, const double *cs, const double *sn, int n_det,
+                 double ds, const double *x, double *y)
+{
+    const double s0 = -0.5 * (n_det - 1) * ds;
+    #pragma omp parallel for schedule(dynamic, 1)
+    for (int a = 0; a < n_ang; ++a) {
+        double c = cs[a], s = sn[a];
+        double p = fmax(fabs(c), fabs(s)), q = fmin(fabs(c), fabs(s));
+        double *row = y + (size_t)a * n_det;
+        for (int i = 0; i < n_det; ++i) row[i] = 0.0;
+        for (int j = 0; j < N * N; ++j) {
+            if (x[j] == 0.0) continue;
+            double xc, yc;
+            pixel_centre(N, j, &xc, &yc);
+            double t0 = xc * c + yc * s;
+            int lo, hi;
+            bin_range(t0, 0.5 * (p + q), s0, ds, n_det, &lo, &hi);
+            for (int i = lo; i <= hi; ++i) {
+                double si = s0 + i * ds;
+                row[i] += trap(si - t0, p, q) * x[j];
+            }
+        }
+    }
+}
+
+/* x = A^T y, one pixel per loop iteration. */
+void orc_adjoint(int N, int n_ang, const double *cs, const double *sn, int n_det,
+                 double ds, const double *y, double *x)
+{
+    const double s0 = -0.5 * (n_det - 1) * ds;
+    #pragma omp parallel for schedule(static)
+    for (int j = 0; j < N * N; ++j) {
+        double xc, yc, acc = 0.0;
+        pixel_centre(N, j, &xc, &yc);
+        for (int a = 0; a < n_ang; ++a) {
+            double c = cs[a], s = sn[a];
+            double p = fmax(fabs(c), fabs(s)), q = fmin(fabs(c), fabs(s));
+            double t0 = xc * c + yc * s;
+            int lo, hi;
+            bin_range(t0, 0.5 * (p + q), s0, ds, n_det, &lo, &hi);
+            for (int i = lo; i <= hi; ++i) {
+                double si = s0 + i * ds;
+                acc += trap(si - t0, p, q) * y[(size_t)a * n_det + i];
+            }
+        }
+        x[j] = acc;
+    }
+}
+
+/* x = B y with the pixel-driven linear-interpolation back projector. */
+void orc_backproject_hat(int N, int n_ang, const double *cs, const double *sn, int n_det,
+                         double ds, const double *y, double *x)
+{
+    const double s0 = -0.5 * (n_det - 1) * ds;
+    #pragma omp parallel for schedule(static)
+    for (int j = 0; j < N * N; ++j) {
+        double xc, yc, acc = 0.0;
+        pixel_centre(N, j, &xc, &yc);
+        for (int a = 0; a < n_ang; ++a) {
+            double t0 = xc * cs[a] + yc * sn[a];
+            double u = (t0 - s0) / ds;
+            int lo, hi;
+            bin_range(t0, ds, s0, ds, n_det, &lo, &hi);
+            for (int i = lo; i <= hi; ++i)
+                acc += hat(u - i) * y[(size_t)a * n_det + i];
+        }
+        x[j] = acc / ds;
+    }
+}
+
+/* Number of threads OpenMP will use (reported with CPU timings). */
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    extern int omp_get_max_threads(void);
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
