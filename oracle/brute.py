@@ -10,14 +10,14 @@ from __future__ import annotations
 
 import numpy as np
 
-from .core import Geometry
+from .core import EDGE_TIE, Geometry
 
 
 def _clip(o, d, lo, hi):
     """Parametric interval of the line o + t d inside the closed slab [lo, hi] (arrays)."""
     if d == 0.0:
-        inside = (o >= lo) & (o <= hi)
-        on_edge = (o == lo) | (o == hi)
+        inside = (o >= lo - EDGE_TIE) & (o <= hi + EDGE_TIE)
+        on_edge = (np.abs(o - lo) <= EDGE_TIE) | (np.abs(o - hi) <= EDGE_TIE)
         t0 = np.where(inside, -np.inf, np.inf)
         t1 = np.where(inside, np.inf, -np.inf)
         return t0, t1, on_edge

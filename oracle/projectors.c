@@ -30,12 +30,18 @@
 #include <math.h>
 #include <stddef.h>
 
+/* An axis-aligned ray counts as lying on a pixel edge when its offset from the pixel
+ * centre is within EDGE_TIE of 1/2: bin positions s0 + i*ds carry rounding error, and
+ * a ray that lies on the edge in exact arithmetic must be recognised as such. */
+#define EDGE_TIE 1e-9
+
 static double trap(double t, double p, double q)
 {
     double at = fabs(t);
     if (q == 0.0) {
+        /* on a pixel edge (|t| = 1/2 up to rounding of the bin position) */
+        if (fabs(at - 0.5) <= EDGE_TIE) return 0.5 / p;
         if (at < 0.5) return 1.0 / p;
-        if (at == 0.5) return 0.5 / p;
         return 0.0;
     }
     double flat = 0.5 * (p - q), outer = 0.5 * (p + q);

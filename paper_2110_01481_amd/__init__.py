@@ -1,0 +1,13 @@
+"""MI355X (gfx950) AB-GMRES / BA-GMRES for CT with an unmatched back projector.
+
+Python face of libabgmres (include/abgmres.h). Importing the package loads nothing;
+the first Geometry or solver call loads the HIP library and fails loudly if it is
+missing.
+"""
+from ._binding import (AbgError, Geometry, SolveResult, ab_gmres, ba_gmres, gmres,
+                       load_library, profile_enable, profile_read, workspace_bytes,
+                       EXPORTS, LIB_PATH)
+
+__all__ = ["AbgError", "Geometry", "SolveResult", "ab_gmres", "ba_gmres", "gmres",
+           "load_library", "profile_enable", "profile_read", "workspace_bytes", "EXPORTS",
+           "LIB_PATH"]

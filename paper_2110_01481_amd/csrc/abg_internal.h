@@ -1,0 +1,138 @@
+// Internal declarations shared by the HIP translation units of libabgmres.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+#include "../../include/abgmres.h"
+
+namespace abg {
+
+// Zero columns on each side of the padded image copies read by the forward projector.
+constexpr int kPad = 4;
+
+// Per-angle constants, computed on the host in FP64 when the geometry is created.
+struct AngleParams {
+    double c, s;        // cos(theta), sin(theta); exact 0 / +-1 at multiples of 90 degrees
+    double p, q;        // max(|c|,|s|), min(|c|,|s|)
+    // ray-driven forward projector: the ray advances one pixel along its major axis
+    // (rows when |c| >= |s|, columns otherwise) per step and moves `m` pixels along
+    // the minor axis; it is 1/p long inside each major-axis band.
+    double m;           // -s/c (steep) or -c/s (flat)
+    double inv;         // 1/c (steep) or 1/s (flat)
+    double len;         // 1/p
+    double invq;        // 1/q (0 when q == 0)
+    int steep;          // 1: walk image rows, 0: walk image columns
+    int axis;           // 1 when q == 0 (ray parallel to a pixel edge)
+};
+
+struct Geometry {
+    int N = 0, n_ang = 0, n_det = 0;
+    double ds = 1.0;
+    int device = 0;
+    std::vector<double> theta;
+    std::vector<AngleParams> host;
+    AngleParams *dev = nullptr;
+    long long n() const { return (long long)N * N; }
+    long long m() const { return (long long)n_ang * n_det; }
+    int padded_stride() const { return N + 2 * kPad; }
+};
+
+// bf16 storage: raw 16-bit pattern, round-to-nearest-even on the way in.
+struct bf16 {
+    uint16_t bits;
+};
+
+inline size_t dtype_size(int t) { return t == ABG_F64 ? 8 : (t == ABG_F32 ? 4 : 2); }
+inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+// ---- launchers (projectors.hip) ------------------------------------------------------
+size_t fp_workspace_bytes(const Geometry &g, int dtype);
+hipError_t launch_forward(const Geometry &g, int dtype, const void *x, void *y, void *ws,
+                          hipStream_t s);
+hipError_t launch_back(const Geometry &g, int kind, int dtype, const void *y, void *x,
+                       hipStream_t s);
+
+// ---- Krylov kernels (krylov.hip) -----------------------------------------------------
+struct DevState {
+    double beta;         // ||r_0||
+    double qnorm0;       // ||q_k|| before orthogonalisation
+    double hnext;        // h_{k+1,k}
+    double ls;           // |g_{k+1}|
+    double res;          // norm written by the last residual / norm reduction
+    double ncp;          // d_k
+    int breakdown;
+    int error;           // sticky: grid-barrier timeout or singular triangle
+    int stop;            // when nonzero, Arnoldi kernels return at entry
+    int pad_;
+};
+
+struct MgsLaunch {
+    int tx, tv;                  // dtypes of q / cur and of the basis
+    const void *q;               // q_k, L elements of tx
+    const void *V;               // basis, vector i at V + i*ldv elements
+    size_t ldv;
+    int k;                       // orthogonalise against w_1..w_k (k may be 0)
+    long long L;
+    double *hcol;                // out: k+1 values h_{1,k}..h_{k+1,k}
+    void *vout;                  // out: w_{k+1} (tv), at V + k*ldv
+    void *cur;                   // out: w_{k+1} converted back to tx
+    double *partials;            // scratch: 4 * kMaxGrid doubles
+    unsigned *bar;               // zeroed counter for this launch
+    DevState *st;
+    double bd_rel;               // breakdown: h_{k+1,k} <= bd_rel * ||q_k||
+};
+constexpr int kMaxGrid = 2048;
+hipError_t launch_mgs(const MgsLaunch &a, hipStream_t s);
+
+// out = base_coef*base + sum_{j<kk} sgn*coef[j]*V_j  (FP64 accumulation); optional
+// partial sums of out^2 per block into partials (then reduce_partials).
+hipError_t launch_combine(int tout, const void *base, double base_coef, int tv, const void *V,
+                          size_t ldv, int kk, const double *coef, double sgn, void *out,
+                          long long L, double *partials, int *nblocks, const DevState *st,
+                          hipStream_t s);
+// out = a - b with partial sums of out^2.
+hipError_t launch_sub_norm(int t, const void *a, const void *b, void *out, long long L,
+                           double *partials, int *nblocks, hipStream_t s);
+// dst = sqrt(sum partials[0..nb)) (fixed order, one block).
+hipError_t launch_reduce_sqrt(const double *partials, int nb, double *dst, hipStream_t s);
+hipError_t launch_givens(double *H, int ld, double *R, double *cs, double *sn, double *g,
+                         double *y, double *rho, double beta, int k, int need_y, DevState *st,
+                         hipStream_t s);
+void set_mgs_target_blocks(int blocks);
+hipError_t launch_fill_u32(unsigned *p, size_t n, unsigned v, hipStream_t s);
+hipError_t launch_fill_f64(double *p, size_t n, double v, hipStream_t s);
+hipError_t launch_axpy_inplace(int t, void *x, const void *x0, long long L, hipStream_t s);
+
+// ---- NCP (ncp.hip) ------------------------------------------------------------------
+size_t ncp_scratch_bytes(const Geometry &g);
+hipError_t launch_ncp(const Geometry &g, int t, const void *r, double *scratch, double *dst,
+                      hipStream_t s);
+
+// ---- solvers (solver.hip) -----------------------------------------------------------
+size_t solver_workspace_bytes(const Geometry &g, int method, int k_max, abg_precision p,
+                              abg_stop st);
+int run_solver(const Geometry &g, int method, int kind, const void *b, const void *x0,
+               void *x, int k_max, abg_stop st, abg_precision p, void *ws, size_t ws_bytes,
+               abg_info *info, hipStream_t s);
+
+// ---- profiling (capi.cpp) -----------------------------------------------------------
+enum ProfKind { kProfFwd = 0, kProfBack = 1, kProfMgs = 2, kProfCombine = 3 };
+bool profiling_on();
+struct ProfScope {
+    ProfScope(int kind, hipStream_t s);
+    ~ProfScope();
+    int kind;
+    hipStream_t s;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+};
+void profile_flush();
+
+}  // namespace abg
+
+struct abg_geometry {
+    abg::Geometry g;
+};

@@ -1,0 +1,292 @@
+// extern "C" entry points of libabgmres: argument checking, geometry set-up (angle
+// table, Table 6.1 parameters), dispatch to the HIP launchers, and launch timing.
+#include <cmath>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "abg_internal.h"
+
+namespace abg {
+namespace {
+
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+long long g_prof_count[4] = {0, 0, 0, 0};
+double g_prof_ms[4] = {0, 0, 0, 0};
+struct Pending {
+    int kind;
+    hipEvent_t e0, e1;
+};
+std::vector<Pending> g_pending;
+
+bool valid_dtype_proj(int t) { return t == ABG_F64 || t == ABG_F32; }
+
+int current_device_matches(const Geometry &g)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return ABG_EHIP;
+    return dev == g.device ? ABG_OK : ABG_EINVAL;
+}
+
+AngleParams make_angle(double theta_deg)
+{
+    AngleParams P{};
+    const double rad = theta_deg * (M_PI / 180.0);
+    double c = std::cos(rad), s = std::sin(rad);
+    if (std::fmod(theta_deg, 90.0) == 0.0) {
+        long long quadrant = std::llround(theta_deg / 90.0);
+        quadrant = ((quadrant % 4) + 4) % 4;
+        static const double cq[4] = {1.0, 0.0, -1.0, 0.0};
+        static const double sq[4] = {0.0, 1.0, 0.0, -1.0};
+        c = cq[quadrant];
+        s = sq[quadrant];
+    }
+    P.c = c;
+    P.s = s;
+    P.p = std::fmax(std::fabs(c), std::fabs(s));
+    P.q = std::fmin(std::fabs(c), std::fabs(s));
+    P.steep = std::fabs(c) >= std::fabs(s) ? 1 : 0;
+    P.m = P.steep ? -s / c : -c / s;
+    P.inv = P.steep ? 1.0 / c : 1.0 / s;
+    P.len = 1.0 / P.p;
+    P.axis = P.q == 0.0 ? 1 : 0;
+    P.invq = P.axis ? 0.0 : 1.0 / P.q;
+    if (P.axis) P.m = 0.0;
+    return P;
+}
+
+}  // namespace
+
+bool profiling_on() { return g_prof_on; }
+
+ProfScope::ProfScope(int kind_, hipStream_t s_) : kind(kind_), s(s_)
+{
+    if (!g_prof_on) return;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        e0 = e1 = nullptr;
+        return;
+    }
+    (void)hipEventRecord(e0, s);
+}
+
+ProfScope::~ProfScope()
+{
+    if (!e0) return;
+    (void)hipEventRecord(e1, s);
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_pending.push_back({kind, e0, e1});
+}
+
+void profile_flush()
+{
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    for (auto &p : g_pending) {
+        float ms = 0.f;
+        (void)hipEventSynchronize(p.e1);
+        if (hipEventElapsedTime(&ms, p.e0, p.e1) == hipSuccess) {
+            g_prof_ms[p.kind] += ms;
+            g_prof_count[p.kind] += 1;
+        }
+        (void)hipEventDestroy(p.e0);
+        (void)hipEventDestroy(p.e1);
+    }
+    g_pending.clear();
+}
+
+}  // namespace abg
+
+using namespace abg;
+
+extern "C" {
+
+int abg_create_geometry(int N, int n_ang, double ang_start_deg, double ang_range_deg,
+                        const double *angles_deg, int n_det, double det_spacing,
+                        abg_geometry **out)
+{
+    if (!out) return ABG_EINVAL;
+    *out = nullptr;
+    if (N < 1 || N > 32768 || n_ang < 1 || n_det < 1 || n_det > (1 << 24)) return ABG_EINVAL;
+    if (!(det_spacing >= 0.75 && det_spacing <= 64.0)) return ABG_EINVAL;
+    if (!angles_deg && !(std::isfinite(ang_start_deg) && std::isfinite(ang_range_deg)))
+        return ABG_EINVAL;
+    abg_geometry *h = new (std::nothrow) abg_geometry;
+    if (!h) return ABG_ENOMEM;
+    Geometry &g = h->g;
+    g.N = N;
+    g.n_ang = n_ang;
+    g.n_det = n_det;
+    g.ds = det_spacing;
+    g.theta.resize(n_ang);
+    g.host.resize(n_ang);
+    for (int a = 0; a < n_ang; ++a) {
+        const double th = angles_deg ? angles_deg[a]
+                                     : ang_start_deg + ((double)a * ang_range_deg) / n_ang;
+        if (!std::isfinite(th)) {
+            delete h;
+            return ABG_EINVAL;
+        }
+        g.theta[a] = th;
+        g.host[a] = make_angle(th);
+    }
+    if (hipGetDevice(&g.device) != hipSuccess ||
+        hipMalloc((void **)&g.dev, sizeof(AngleParams) * n_ang) != hipSuccess) {
+        delete h;
+        return ABG_EHIP;
+    }
+    if (hipMemcpy(g.dev, g.host.data(), sizeof(AngleParams) * n_ang, hipMemcpyHostToDevice) !=
+        hipSuccess) {
+        (void)hipFree(g.dev);
+        delete h;
+        return ABG_EHIP;
+    }
+    *out = h;
+    return ABG_OK;
+}
+
+int abg_destroy_geometry(abg_geometry *h)
+{
+    if (!h) return ABG_OK;
+    int rc = ABG_OK;
+    if (h->g.dev && hipFree(h->g.dev) != hipSuccess) rc = ABG_EHIP;
+    delete h;
+    return rc;
+}
+
+int abg_geometry_sizes(const abg_geometry *h, long long *n, long long *m)
+{
+    if (!h) return ABG_EINVAL;
+    if (n) *n = h->g.n();
+    if (m) *m = h->g.m();
+    return ABG_OK;
+}
+
+size_t abg_fp_workspace_bytes(const abg_geometry *h, int dtype)
+{
+    if (!h || !valid_dtype_proj(dtype)) return 0;
+    return fp_workspace_bytes(h->g, dtype);
+}
+
+int abg_fp_apply(const abg_geometry *h, int dtype, const void *x, void *y, void *ws,
+                 size_t ws_bytes, void *stream)
+{
+    if (!h || !x || !y || !ws || !valid_dtype_proj(dtype)) return ABG_EINVAL;
+    if (reinterpret_cast<uintptr_t>(ws) % 256) return ABG_EINVAL;
+    if (ws_bytes < fp_workspace_bytes(h->g, dtype)) return ABG_ENOMEM;
+    int rc = current_device_matches(h->g);
+    if (rc) return rc;
+    return launch_forward(h->g, dtype, x, y, ws, static_cast<hipStream_t>(stream)) == hipSuccess
+               ? ABG_OK
+               : ABG_EHIP;
+}
+
+int abg_bp_apply(const abg_geometry *h, int kind, int dtype, const void *y, void *x,
+                 void *stream)
+{
+    if (!h || !x || !y || !valid_dtype_proj(dtype)) return ABG_EINVAL;
+    if (kind != ABG_BP_HAT && kind != ABG_BP_ADJ) return ABG_EINVAL;
+    int rc = current_device_matches(h->g);
+    if (rc) return rc;
+    return launch_back(h->g, kind, dtype, y, x, static_cast<hipStream_t>(stream)) == hipSuccess
+               ? ABG_OK
+               : ABG_EHIP;
+}
+
+static int check_solver_args(const abg_geometry *h, int method, int k_max, abg_precision p,
+                             abg_stop st)
+{
+    if (!h) return ABG_EINVAL;
+    if (method != ABG_METHOD_AB && method != ABG_METHOD_BA) return ABG_EINVAL;
+    if (k_max < 1 || k_max > 500) return ABG_EINVAL;
+    if (!valid_dtype_proj(p.proj)) return ABG_EINVAL;
+    if (p.basis != ABG_F64 && p.basis != ABG_F32 && p.basis != ABG_BF16) return ABG_EINVAL;
+    if (dtype_size(p.basis) > dtype_size(p.proj)) return ABG_EINVAL;
+    if (st.kind == ABG_STOP_DP) {
+        if (!(st.tau >= 1.0) || !(st.noise_norm > 0.0) || !std::isfinite(st.tau * st.noise_norm))
+            return ABG_EINVAL;
+    } else if (st.kind == ABG_STOP_NCP) {
+        if (h->g.n_det < 2 || h->g.n_det / 2 > 2048) return ABG_EINVAL;
+    } else if (st.kind != ABG_STOP_NONE) {
+        return ABG_EINVAL;
+    }
+    return ABG_OK;
+}
+
+size_t abg_workspace_bytes(const abg_geometry *h, int method, int k_max, abg_precision p,
+                           abg_stop st)
+{
+    if (check_solver_args(h, method, k_max, p, st) != ABG_OK) return 0;
+    return solver_workspace_bytes(h->g, method, k_max, p, st);
+}
+
+static int solve_entry(int method, const abg_geometry *h, int bp_kind, const void *b,
+                       const void *x0, void *x, int k_max, abg_stop st, abg_precision p,
+                       void *ws, size_t ws_bytes, abg_info *info, void *stream)
+{
+    int rc = check_solver_args(h, method, k_max, p, st);
+    if (rc) return rc;
+    if (bp_kind != ABG_BP_HAT && bp_kind != ABG_BP_ADJ) return ABG_EINVAL;
+    if (!b || !x || !ws || x == b || (x0 && x == x0)) return ABG_EINVAL;
+    if (reinterpret_cast<uintptr_t>(ws) % 256) return ABG_EINVAL;
+    if ((rc = current_device_matches(h->g))) return rc;
+    rc = run_solver(h->g, method, bp_kind, b, x0, x, k_max, st, p, ws, ws_bytes, info,
+                    static_cast<hipStream_t>(stream));
+    if (info) info->status = rc;
+    return rc;
+}
+
+int abg_ab_gmres(const abg_geometry *h, int bp_kind, const void *b, const void *x0, void *x,
+                 int k_max, abg_stop st, abg_precision p, void *ws, size_t ws_bytes,
+                 abg_info *info, void *stream)
+{
+    return solve_entry(ABG_METHOD_AB, h, bp_kind, b, x0, x, k_max, st, p, ws, ws_bytes, info,
+                       stream);
+}
+
+int abg_ba_gmres(const abg_geometry *h, int bp_kind, const void *b, const void *x0, void *x,
+                 int k_max, abg_stop st, abg_precision p, void *ws, size_t ws_bytes,
+                 abg_info *info, void *stream)
+{
+    return solve_entry(ABG_METHOD_BA, h, bp_kind, b, x0, x, k_max, st, p, ws, ws_bytes, info,
+                       stream);
+}
+
+const char *abg_status_string(int status)
+{
+    switch (status) {
+    case ABG_OK: return "ok";
+    case ABG_EINVAL: return "invalid argument";
+    case ABG_ENOMEM: return "workspace too small";
+    case ABG_EHIP: return "HIP runtime error";
+    case ABG_ENAN: return "NaN or Inf in a norm";
+    case ABG_EDEVICE: return "device-side wait exceeded its bound";
+    case ABG_NOT_CONVERGED: return "discrepancy principle not met by k_max";
+    case ABG_BREAKDOWN: return "Arnoldi breakdown (Krylov space exhausted)";
+    case ABG_ZERO_RHS: return "zero initial residual";
+    default: return "unknown status";
+    }
+}
+
+int abg_profile_enable(int on)
+{
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_on = on != 0;
+    return ABG_OK;
+}
+
+int abg_profile_read(long long counts[4], double ms[4], int reset)
+{
+    profile_flush();
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    for (int i = 0; i < 4; ++i) {
+        if (counts) counts[i] = g_prof_count[i];
+        if (ms) ms[i] = g_prof_ms[i];
+        if (reset) {
+            g_prof_count[i] = 0;
+            g_prof_ms[i] = 0.0;
+        }
+    }
+    return ABG_OK;
+}
+
+}  // extern "C"

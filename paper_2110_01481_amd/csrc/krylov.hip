@@ -1,0 +1,547 @@
+// Arnoldi machinery of AB-/BA-GMRES (Sec. 2) for gfx950:
+//   mgs     modified Gram-Schmidt of q_k against w_1..w_k, h_{k+1,k} = ||q_k||,
+//           w_{k+1} = q_k / h_{k+1,k}; one cooperative launch per Arnoldi step that keeps
+//           q_k in FP64 registers, reads each basis vector once, and takes one grid-wide
+//           reduction per inner product (the listing's sequential i loop is kept).
+//   givens  FP64 Givens update of the Hessenberg least squares problem, back
+//           substitution for y_k and the small residual vector ||r_0|| e_1 - H_k y_k.
+//   combine basis combinations base + sum_j c_j v_j (iterates and residual vectors)
+//           with FP64 accumulation and a fixed-order norm reduction.
+// Every reduction runs in a fixed order, so results are identical run to run.
+#include <cmath>
+#include <mutex>
+#include <unordered_map>
+
+#include "abg_internal.h"
+
+namespace abg {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kWaves = kBlock / 64;
+constexpr unsigned kSpinLimit = 1u << 22;
+constexpr int kMaxCoef = 512;
+
+// ---- element access ------------------------------------------------------------------
+__device__ inline double to_f64(double v) { return v; }
+__device__ inline double to_f64(float v) { return (double)v; }
+__device__ inline double to_f64(bf16 v) { return (double)__uint_as_float((unsigned)v.bits << 16); }
+
+template <typename T> __device__ inline T from_f64(double v);
+template <> __device__ inline double from_f64<double>(double v) { return v; }
+template <> __device__ inline float from_f64<float>(double v) { return (float)v; }
+template <> __device__ inline bf16 from_f64<bf16>(double v)
+{
+    // round to float, then to the nearest bf16 (ties to even); NaN stays NaN
+    const unsigned u = __float_as_uint((float)v);
+    bf16 r;
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) {
+        r.bits = (uint16_t)((u >> 16) | 0x40u);
+    } else {
+        const unsigned lsb = (u >> 16) & 1u;
+        r.bits = (uint16_t)((u + 0x7fffu + lsb) >> 16);
+    }
+    return r;
+}
+template <typename T> __device__ inline T zero_of();
+template <> __device__ inline double zero_of<double>() { return 0.0; }
+template <> __device__ inline float zero_of<float>() { return 0.0f; }
+template <> __device__ inline bf16 zero_of<bf16>() { return bf16{0}; }
+
+// ---- reductions ----------------------------------------------------------------------
+// Butterfly sum: lanes l and l^d add the same two operands, so every lane ends with the
+// same value regardless of position.
+__device__ inline double wave_sum(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Block sum returned to every thread, fixed order.
+__device__ inline double block_sum(double v, double *lds)
+{
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) lds[w] = v;
+    __syncthreads();
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < kWaves; ++i) s += lds[i];
+    return s;
+}
+
+__device__ inline double agent_load(const double *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void agent_store(double *p, double v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Grid-wide barrier for a cooperative launch: each block adds one to the counter and
+// waits until it reaches `target`. The wait is bounded; on timeout the sticky error
+// flag is raised and every later barrier returns at once.
+__device__ inline void grid_barrier(unsigned *bar, unsigned target, int *err)
+{
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        unsigned spins = 0;
+        while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            __builtin_amdgcn_s_sleep(1);
+            if (++spins > kSpinLimit) {
+                __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+            if ((spins & 255u) == 0 &&
+                __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+                break;
+        }
+    }
+    __syncthreads();
+}
+
+// Sum of the G per-block partials, the same in every block.
+__device__ inline double grid_total(const double *part, int G, double *lds)
+{
+    double s = 0.0;
+    for (int j = threadIdx.x; j < G; j += kBlock) s += agent_load(part + j);
+    return block_sum(s, lds);
+}
+
+struct MgsDev {
+    const void *q;
+    const void *V;
+    size_t ldv;
+    int k;
+    long long L;
+    double *hcol;
+    void *vout;
+    void *cur;
+    double *partials;
+    unsigned *bar;
+    DevState *st;
+    double bd_rel;
+};
+
+template <typename TX, typename TV, int E>
+__global__ __launch_bounds__(kBlock) void mgs_kernel(MgsDev a)
+{
+    __shared__ double lds[kWaves];
+    if (*(volatile int *)&a.st->stop) return;
+    const int G = gridDim.x;
+    const long long T = (long long)G * kBlock;
+    const long long gt = (long long)blockIdx.x * kBlock + threadIdx.x;
+    const TX *q = static_cast<const TX *>(a.q);
+    const TV *V = static_cast<const TV *>(a.V);
+    int *err = &a.st->error;
+
+    double qv[E];
+    TV wv[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const long long l = gt + e * T;
+        qv[e] = l < a.L ? to_f64(q[l]) : 0.0;
+    }
+    unsigned nb = 0;
+    double qq = 0.0;
+    for (int i = 0; i < a.k; ++i) {
+        const TV *w = V + (size_t)i * a.ldv;
+        double d = 0.0, s2 = 0.0;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const long long l = gt + e * T;
+            wv[e] = l < a.L ? w[l] : zero_of<TV>();
+            d = fma(qv[e], to_f64(wv[e]), d);
+            if (i == 0) s2 = fma(qv[e], qv[e], s2);
+        }
+        double *slot = a.partials + (size_t)(nb & 1u) * 2 * G;
+        d = block_sum(d, lds);
+        if (i == 0) s2 = block_sum(s2, lds);
+        if (threadIdx.x == 0) {
+            agent_store(slot + blockIdx.x, d);
+            if (i == 0) agent_store(slot + G + blockIdx.x, s2);
+        }
+        ++nb;
+        grid_barrier(a.bar, nb * (unsigned)G, err);
+        const double h = grid_total(slot, G, lds);
+        if (i == 0) qq = grid_total(slot + G, G, lds);
+        if (blockIdx.x == 0 && threadIdx.x == 0) a.hcol[i] = h;
+#pragma unroll
+        for (int e = 0; e < E; ++e) qv[e] = fma(-h, to_f64(wv[e]), qv[e]);
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) s = fma(qv[e], qv[e], s);
+    double *slot = a.partials + (size_t)(nb & 1u) * 2 * G;
+    s = block_sum(s, lds);
+    if (threadIdx.x == 0) agent_store(slot + blockIdx.x, s);
+    ++nb;
+    grid_barrier(a.bar, nb * (unsigned)G, err);
+    const double hn2 = grid_total(slot, G, lds);
+    if (a.k == 0) qq = hn2;
+    const double hn = sqrt(hn2);
+    const double q0 = sqrt(qq);
+    const bool finite = isfinite(hn) && isfinite(q0);
+    const bool bd = !(hn > a.bd_rel * q0);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        a.hcol[a.k] = hn;
+        a.st->hnext = hn;
+        a.st->qnorm0 = q0;
+        a.st->breakdown = bd ? 1 : 0;
+        if (!finite) a.st->error |= 2;
+    }
+    TV *vo = static_cast<TV *>(a.vout);
+    TX *cu = static_cast<TX *>(a.cur);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const long long l = gt + e * T;
+        if (l < a.L) {
+            const TV w = (bd || !finite) ? zero_of<TV>() : from_f64<TV>(qv[e] / hn);
+            vo[l] = w;
+            cu[l] = (TX)to_f64(w);
+        }
+    }
+}
+
+// ---- cooperative launch bookkeeping --------------------------------------------------
+struct CoopInfo {
+    int max_blocks = 0;
+};
+std::mutex g_coop_mu;
+std::unordered_map<const void *, CoopInfo> g_coop;
+
+hipError_t coop_capacity(const void *fn, int *max_blocks)
+{
+    std::lock_guard<std::mutex> lk(g_coop_mu);
+    auto it = g_coop.find(fn);
+    if (it != g_coop.end()) {
+        *max_blocks = it->second.max_blocks;
+        return hipSuccess;
+    }
+    int dev = 0, per_cu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, dev);
+    if (e != hipSuccess) return e;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kBlock, 0);
+    if (e != hipSuccess) return e;
+    CoopInfo ci;
+    ci.max_blocks = per_cu * prop.multiProcessorCount;
+    g_coop[fn] = ci;
+    *max_blocks = ci.max_blocks;
+    return hipSuccess;
+}
+
+int g_target_blocks = 256;
+
+template <typename TX, typename TV, int E>
+hipError_t mgs_go(const MgsDev &d, int G, hipStream_t s)
+{
+    const void *fn = reinterpret_cast<const void *>(&mgs_kernel<TX, TV, E>);
+    int cap = 0;
+    hipError_t e = coop_capacity(fn, &cap);
+    if (e != hipSuccess) return e;
+    if (G > cap || G > kMaxGrid) return hipErrorCooperativeLaunchTooLarge;
+    MgsDev arg = d;
+    void *args[] = {&arg};
+    return hipLaunchCooperativeKernel(fn, dim3(G), dim3(kBlock), args, 0, s);
+}
+
+template <typename TX, typename TV>
+hipError_t mgs_dispatch(const MgsDev &d, hipStream_t s)
+{
+    // Smallest register tile E per thread such that target blocks cover L; beyond the
+    // largest tile the grid grows instead.
+    const long long L = d.L;
+    const int maxE = sizeof(TV) == 8 ? 32 : 64;
+    int E = 1;
+    while (E < maxE && (long long)g_target_blocks * kBlock * E < L) E *= 2;
+    long long G = (L + (long long)kBlock * E - 1) / ((long long)kBlock * E);
+    if (G < 1) G = 1;
+    const int Gi = (int)G;
+    switch (E) {
+    case 1: return mgs_go<TX, TV, 1>(d, Gi, s);
+    case 2: return mgs_go<TX, TV, 2>(d, Gi, s);
+    case 4: return mgs_go<TX, TV, 4>(d, Gi, s);
+    case 8: return mgs_go<TX, TV, 8>(d, Gi, s);
+    case 16: return mgs_go<TX, TV, 16>(d, Gi, s);
+    case 32: return mgs_go<TX, TV, 32>(d, Gi, s);
+    default:
+        if constexpr (sizeof(TV) < 8) return mgs_go<TX, TV, 64>(d, Gi, s);
+        return hipErrorInvalidValue;
+    }
+}
+
+// ---- combinations, norms -------------------------------------------------------------
+template <typename TO, typename TB, typename TV>
+__global__ __launch_bounds__(kBlock) void combine_kernel(const TB *__restrict__ base, double bcoef,
+                                                         const TV *__restrict__ V, size_t ldv,
+                                                         int kk, const double *__restrict__ coef,
+                                                         double sgn, TO *__restrict__ out,
+                                                         long long L, double *partials,
+                                                         const DevState *st)
+{
+    __shared__ double cf[kMaxCoef];
+    __shared__ double lds[kWaves];
+    if (st && *(volatile const int *)&st->stop) return;
+    for (int j = threadIdx.x; j < kk; j += kBlock) cf[j] = sgn * coef[j];
+    __syncthreads();
+    const long long T = (long long)gridDim.x * kBlock;
+    double ss = 0.0;
+    for (long long l = (long long)blockIdx.x * kBlock + threadIdx.x; l < L; l += T) {
+        double acc = base ? bcoef * to_f64(base[l]) : 0.0;
+        const TV *v = V + l;
+        int j = 0;
+        for (; j + 4 <= kk; j += 4) {
+            const double v0 = to_f64(v[(size_t)(j + 0) * ldv]);
+            const double v1 = to_f64(v[(size_t)(j + 1) * ldv]);
+            const double v2 = to_f64(v[(size_t)(j + 2) * ldv]);
+            const double v3 = to_f64(v[(size_t)(j + 3) * ldv]);
+            acc = fma(cf[j + 0], v0, acc);
+            acc = fma(cf[j + 1], v1, acc);
+            acc = fma(cf[j + 2], v2, acc);
+            acc = fma(cf[j + 3], v3, acc);
+        }
+        for (; j < kk; ++j) acc = fma(cf[j], to_f64(v[(size_t)j * ldv]), acc);
+        out[l] = (TO)acc;
+        ss = fma(acc, acc, ss);
+    }
+    if (partials) {
+        ss = block_sum(ss, lds);
+        if (threadIdx.x == 0) partials[blockIdx.x] = ss;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void sub_norm_kernel(const T *__restrict__ a, const T *__restrict__ b,
+                                                          T *__restrict__ out, long long L,
+                                                          double *partials)
+{
+    __shared__ double lds[kWaves];
+    const long long T_ = (long long)gridDim.x * kBlock;
+    double ss = 0.0;
+    for (long long l = (long long)blockIdx.x * kBlock + threadIdx.x; l < L; l += T_) {
+        const double v = (double)a[l] - (double)b[l];
+        out[l] = (T)v;
+        ss = fma(v, v, ss);
+    }
+    ss = block_sum(ss, lds);
+    if (threadIdx.x == 0) partials[blockIdx.x] = ss;
+}
+
+__global__ __launch_bounds__(kBlock) void reduce_sqrt_kernel(const double *partials, int nb, double *dst)
+{
+    __shared__ double lds[kWaves];
+    double s = 0.0;
+    for (int j = threadIdx.x; j < nb; j += kBlock) s += partials[j];
+    s = block_sum(s, lds);
+    if (threadIdx.x == 0) *dst = sqrt(s);
+}
+
+template <typename T>
+__global__ void axpy_inplace_kernel(T *x, const T *x0, long long L)
+{
+    const long long l = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (l < L) x[l] = (T)((double)x[l] + (double)x0[l]);
+}
+
+__global__ void fill_u32_kernel(unsigned *p, size_t n, unsigned v)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+__global__ void fill_f64_kernel(double *p, size_t n, double v)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// One wave. Column k-1 of H has just been written by mgs. R holds the rotated columns.
+__global__ __launch_bounds__(64) void givens_kernel(double *H, int ld, double *R, double *cs,
+                                                    double *sn, double *g, double *y,
+                                                    double *rho, double beta, int k, int need_y,
+                                                    DevState *st)
+{
+    __shared__ double gg[kMaxCoef];
+    __shared__ double ys[kMaxCoef];
+    if (*(volatile int *)&st->stop) return;
+    const int lane = threadIdx.x;
+    const int j = k - 1;
+    double *Hc = H + (size_t)j * ld;
+    double *Rc = R + (size_t)j * ld;
+    const int bd = st->breakdown;
+    for (int i = lane; i <= k; i += 64) Rc[i] = (i == k && bd) ? 0.0 : Hc[i];
+    __syncthreads();
+    if (lane == 0) {
+        for (int i = 0; i < j; ++i) {
+            const double a = Rc[i], b = Rc[i + 1];
+            Rc[i] = cs[i] * a + sn[i] * b;
+            Rc[i + 1] = -sn[i] * a + cs[i] * b;
+        }
+        const double a = Rc[j], b = Rc[k];
+        const double r = hypot(a, b);
+        double c = 1.0, s = 0.0;
+        if (r > 0.0) {
+            c = a / r;
+            s = b / r;
+        } else {
+            st->error |= 4;
+        }
+        cs[j] = c;
+        sn[j] = s;
+        Rc[j] = r;
+        Rc[k] = 0.0;
+        const double gj = g[j];
+        g[j] = c * gj;
+        g[k] = -s * gj;
+        st->ls = fabs(g[k]);
+    }
+    __syncthreads();
+    if (!need_y) return;
+    for (int i = lane; i < k; i += 64) gg[i] = g[i];
+    __syncthreads();
+    for (int jj = k - 1; jj >= 0; --jj) {
+        const double yj = gg[jj] / R[(size_t)jj * ld + jj];
+        if (lane == 0) ys[jj] = yj;
+        for (int i = lane; i < jj; i += 64) gg[i] -= R[(size_t)jj * ld + i] * yj;
+        __syncthreads();
+    }
+    for (int i = lane; i < k; i += 64) y[i] = ys[i];
+    if (rho) {
+        for (int i = lane; i <= k; i += 64) {
+            double acc = (i == 0) ? beta : 0.0;
+            for (int jj = (i > 0 ? i - 1 : 0); jj < k; ++jj) acc -= H[(size_t)jj * ld + i] * ys[jj];
+            rho[i] = acc;
+        }
+    }
+}
+
+int blocks_for(long long L)
+{
+    long long b = (L + kBlock - 1) / kBlock;
+    if (b > 1024) b = 1024;
+    if (b < 1) b = 1;
+    return (int)b;
+}
+
+template <typename TO, typename TB, typename TV>
+hipError_t combine_go(const void *base, double bcoef, const void *V, size_t ldv, int kk,
+                      const double *coef, double sgn, void *out, long long L, double *partials,
+                      int *nblocks, const DevState *st, hipStream_t s)
+{
+    const int nb = blocks_for(L);
+    if (nblocks) *nblocks = nb;
+    combine_kernel<TO, TB, TV><<<nb, kBlock, 0, s>>>(
+        static_cast<const TB *>(base), bcoef, static_cast<const TV *>(V), ldv, kk, coef, sgn,
+        static_cast<TO *>(out), L, partials, st);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+void set_mgs_target_blocks(int blocks)
+{
+    g_target_blocks = blocks < 1 ? 1 : (blocks > kMaxGrid ? kMaxGrid : blocks);
+}
+
+hipError_t launch_mgs(const MgsLaunch &m, hipStream_t s)
+{
+    MgsDev d;
+    d.q = m.q;
+    d.V = m.V;
+    d.ldv = m.ldv;
+    d.k = m.k;
+    d.L = m.L;
+    d.hcol = m.hcol;
+    d.vout = m.vout;
+    d.cur = m.cur;
+    d.partials = m.partials;
+    d.bar = m.bar;
+    d.st = m.st;
+    d.bd_rel = m.bd_rel;
+    ProfScope ps(kProfMgs, s);
+    if (m.tx == ABG_F64) {
+        if (m.tv == ABG_F64) return mgs_dispatch<double, double>(d, s);
+        if (m.tv == ABG_F32) return mgs_dispatch<double, float>(d, s);
+        return mgs_dispatch<double, bf16>(d, s);
+    }
+    if (m.tv == ABG_F32) return mgs_dispatch<float, float>(d, s);
+    if (m.tv == ABG_BF16) return mgs_dispatch<float, bf16>(d, s);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_combine(int tout, const void *base, double base_coef, int tv, const void *V,
+                          size_t ldv, int kk, const double *coef, double sgn, void *out,
+                          long long L, double *partials, int *nblocks, const DevState *st,
+                          hipStream_t s)
+{
+    if (kk > kMaxCoef) return hipErrorInvalidValue;
+    ProfScope ps(kProfCombine, s);
+    if (tout == ABG_F64) {
+        if (tv == ABG_F64) return combine_go<double, double, double>(base, base_coef, V, ldv, kk, coef, sgn, out, L, partials, nblocks, st, s);
+        if (tv == ABG_F32) return combine_go<double, double, float>(base, base_coef, V, ldv, kk, coef, sgn, out, L, partials, nblocks, st, s);
+        return combine_go<double, double, bf16>(base, base_coef, V, ldv, kk, coef, sgn, out, L, partials, nblocks, st, s);
+    }
+    if (tv == ABG_F32) return combine_go<float, float, float>(base, base_coef, V, ldv, kk, coef, sgn, out, L, partials, nblocks, st, s);
+    if (tv == ABG_BF16) return combine_go<float, float, bf16>(base, base_coef, V, ldv, kk, coef, sgn, out, L, partials, nblocks, st, s);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_sub_norm(int t, const void *a, const void *b, void *out, long long L,
+                           double *partials, int *nblocks, hipStream_t s)
+{
+    const int nb = blocks_for(L);
+    *nblocks = nb;
+    if (t == ABG_F64)
+        sub_norm_kernel<double><<<nb, kBlock, 0, s>>>(static_cast<const double *>(a), static_cast<const double *>(b),
+                                                      static_cast<double *>(out), L, partials);
+    else
+        sub_norm_kernel<float><<<nb, kBlock, 0, s>>>(static_cast<const float *>(a), static_cast<const float *>(b),
+                                                     static_cast<float *>(out), L, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_sqrt(const double *partials, int nb, double *dst, hipStream_t s)
+{
+    reduce_sqrt_kernel<<<1, kBlock, 0, s>>>(partials, nb, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_givens(double *H, int ld, double *R, double *cs, double *sn, double *g,
+                         double *y, double *rho, double beta, int k, int need_y, DevState *st,
+                         hipStream_t s)
+{
+    if (k + 1 > kMaxCoef) return hipErrorInvalidValue;
+    givens_kernel<<<1, 64, 0, s>>>(H, ld, R, cs, sn, g, y, rho, beta, k, need_y, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(unsigned *p, size_t n, unsigned v, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    fill_u32_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_f64(double *p, size_t n, double v, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    fill_f64_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_axpy_inplace(int t, void *x, const void *x0, long long L, hipStream_t s)
+{
+    const unsigned nb = (unsigned)((L + 255) / 256);
+    if (t == ABG_F64)
+        axpy_inplace_kernel<double><<<nb, 256, 0, s>>>(static_cast<double *>(x), static_cast<const double *>(x0), L);
+    else
+        axpy_inplace_kernel<float><<<nb, 256, 0, s>>>(static_cast<float *>(x), static_cast<const float *>(x0), L);
+    return hipGetLastError();
+}
+
+}  // namespace abg

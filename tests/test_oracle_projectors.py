@@ -20,6 +20,7 @@ TINY = [
     dict(N=8, n_ang=16, n_det=12, ang_range=180.0),       # even n_det: half-integer bins
     dict(N=7, n_ang=0, n_det=11, angles_deg=[0.0, 90.0, 45.0, 13.7, 101.3, 179.9, 33.3333, 135.0]),
     dict(N=4, n_ang=6, n_det=7, ang_range=180.0, det_spacing=1.3),
+    dict(N=30, n_ang=4, n_det=31, ang_range=180.0, det_spacing=1.3),  # edge rays at s = +-13
 ]
 
 
@@ -172,6 +173,17 @@ def test_unmatchedness_is_of_the_order_the_paper_reports():
     A, AT, B = assemble_dense(g)
     ratio = np.linalg.norm(B - AT) / np.linalg.norm(A)
     assert 0.05 < ratio < 0.8, ratio
+
+
+@pytest.mark.parametrize("kind", ["hat", "adj"])
+def test_pixel_spot_checks_equal_full_back_projection(kind):
+    """The per-pixel NumPy evaluation used for large-size spot checks agrees with the
+    C back projectors on every pixel of a small geometry (incl. axis angles)."""
+    g = O.Geometry(20, 24, 31, det_spacing=1.0)
+    y = np.random.default_rng(6).standard_normal(g.m)
+    full = g.back(kind)(y)
+    pix = np.arange(g.n)
+    assert np.abs(g.back_pixels(kind, y, pix) - full).max() <= 1e-12 * np.abs(full).max()
 
 
 def test_storage_matches_table_6_3():
