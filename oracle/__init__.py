@@ -21,13 +21,13 @@ Contents:
 from .core import (Geometry, angle_table, assemble_dense, basis_storage)
 from .brute import brute_force_matrix, chord_length_in_square
 from .stopping import ncp_distance, dp_index, ncp_index
-from .gmres import ab_gmres, ba_gmres, GmresResult
+from .gmres import ab_gmres, ba_gmres, GmresResult, bf16_round
 from .krylov import krylov_basis, min_residual_iterate, golub_kahan_lsqr, golub_kahan_lsmr
 
 __all__ = [
     "Geometry", "angle_table", "assemble_dense", "basis_storage",
     "brute_force_matrix", "chord_length_in_square",
     "ncp_distance", "dp_index", "ncp_index",
-    "ab_gmres", "ba_gmres", "GmresResult",
+    "ab_gmres", "ba_gmres", "GmresResult", "bf16_round",
     "krylov_basis", "min_residual_iterate", "golub_kahan_lsqr", "golub_kahan_lsmr",
 ]

@@ -11,6 +11,10 @@ For k = 1, 2, ...:
   r_k = b - A x_k, then the stopping rule.
 with r_0 = b - A x_0 (AB) and r_0 = B b - B A x_0 (BA), w_1 = r_0/||r_0||.
 
+Optional `basis_round` rounds every stored basis vector w_k (e.g. bf16_round): the
+reduced-precision storage variant, in which the operator is applied to the stored
+vector; everything else stays FP64.
+
 Readings where the listing is silent: x_0 = 0 unless given; the stopping rule is
 checked from k = 1; a breakdown h_{k+1,k} <= 1e-14 ||A B w_k|| (resp. ||B A w_k||)
 ends the iteration with y_k from the square k x k part of H_k; the discrepancy
@@ -44,8 +48,20 @@ class GmresResult:
     beta: float = 0.0
 
 
+def bf16_round(v: np.ndarray) -> np.ndarray:
+    """Round to float32 (nearest), then to the nearest bfloat16 (8 significant bits,
+    ties to even), returned as float64. Storage rounding of the reduced-precision basis
+    variant, which is not part of the paper's method."""
+    f = np.asarray(v, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    lsb = (u >> np.uint64(16)) & np.uint64(1)
+    r = ((u + np.uint64(0x7FFF) + lsb) >> np.uint64(16)) << np.uint64(16)
+    out = r.astype(np.uint32).view(np.float32).astype(np.float64)
+    return np.where(np.isfinite(f), out, f.astype(np.float64))
+
+
 def _gmres(method, A, B, b, k_max, stop="none", tau=1.0, noise_norm=0.0, x0=None,
-           ncp_shape=None, keep_iterates=False, keep_basis=False):
+           ncp_shape=None, keep_iterates=False, keep_basis=False, basis_round=None):
     b = np.asarray(b, dtype=np.float64)
     n = B(np.zeros_like(b)).size
     x0 = np.zeros(n) if x0 is None else np.asarray(x0, dtype=np.float64)
@@ -60,6 +76,8 @@ def _gmres(method, A, B, b, k_max, stop="none", tau=1.0, noise_norm=0.0, x0=None
     W = np.zeros((k_max + 1, L))
     H = np.zeros((k_max + 1, k_max))
     W[0] = r0 / beta
+    if basis_round is not None:
+        W[0] = basis_round(W[0])
     thr = tau * noise_norm
     prev_x = None
     best = (np.inf, 0, None)
@@ -80,6 +98,8 @@ def _gmres(method, A, B, b, k_max, stop="none", tau=1.0, noise_norm=0.0, x0=None
             y = np.linalg.lstsq(H[:k, :k], rhs[:k], rcond=None)[0]
         else:
             W[k] = q / hk
+            if basis_round is not None:
+                W[k] = basis_round(W[k])
             y = np.linalg.lstsq(H[:k + 1, :k], rhs, rcond=None)[0]
         t = W[:k].T @ y
         x = x0 + (B(t) if method == "ab" else t)

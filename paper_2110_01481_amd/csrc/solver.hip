@@ -360,10 +360,11 @@ int run_solver(const Geometry &g, int method, int kind, const void *b, const voi
                 finished = true;
             }
         }
-        // explicit residual of the returned iterate
+        // explicit residual of the returned iterate; a NaN/Inf anywhere in b shows here
         if ((rc = S.literal_residual(b, x))) return rc;
         if ((rc = S.sync_state(hs))) return rc;
         res_final = hs.res;
+        if (!std::isfinite(res_final)) return ABG_ENAN;
     }
 
 done:

@@ -184,3 +184,16 @@ def test_ncp_stop_returns_previous_iterate(cfg1):
     k, increased = O.ncp_index(full.ncp)
     assert full.k_stop == k
     assert np.array_equal(full.x, full.iterates[k - 1])
+
+
+def test_bf16_rounding_known_values():
+    """bfloat16 keeps 8 significant bits and rounds to nearest, ties to even."""
+    ulp = 2.0 ** -7
+    v = np.array([1.0, 1.0 + ulp / 2, 1.0 + 3 * ulp / 2, 1.0 + ulp / 4, 1.0 + 3 * ulp / 4,
+                  -2.5, 3.0e38, 1e-40, np.inf, -np.inf])
+    want = np.array([1.0, 1.0, 1.0 + 2 * ulp, 1.0, 1.0 + ulp, -2.5])
+    got = O.bf16_round(v)
+    assert np.array_equal(got[:6], want[:6])
+    assert abs(got[6] / 3.0e38 - 1) < 2 ** -8
+    assert got[7] != 0 and abs(got[7] / 1e-40 - 1) < 0.1   # subnormal: fewer bits
+    assert np.isposinf(got[8]) and np.isneginf(got[9]) and np.isnan(O.bf16_round(np.array([np.nan])))[0]
