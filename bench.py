@@ -1,0 +1,245 @@
+"""Benchmark: GMRES iterations per second of AB- and BA-GMRES on one MI355X.
+
+Workload (default): the single-solve case -- 512 x 512 image, 720 angles in [0,180),
+725 bins, 20-ellipse phantom, 2% Gaussian noise, FP32 projectors with the FP64
+Hessenberg/Givens solve, discrepancy-principle stop (tau = 1.02, k_max = 100), unmatched
+pair (line-model A, interpolating B). One step = one AB-GMRES solve plus one BA-GMRES
+solve; the metric counts their Arnoldi iterations.
+
+Prints one JSON line. `roofline` covers the kernel with the largest share of the timed
+region, measured with HIP events on the solver's stream; `cpu_baseline` times the FP64
+oracle (AB-GMRES, literal algorithm) on a bounded number of iterations of the same
+workload on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import workloads as W  # noqa: E402
+
+HBM_PEAK_GBPS = 8000.0
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+
+
+def line_model_nnz(N: int, theta_deg: np.ndarray, n_det: int, ds: float = 1.0) -> int:
+    """Expected number of (ray, pixel) pairs with positive intersection length: a chord
+    of length L in direction (-sin, cos) crosses grid lines at rate |cos| + |sin| per
+    unit length, so it touches 1 + L(|cos| + |sin|) pixels (axis-aligned edge rays touch
+    two pixels per band). Used only to count the algorithmic work of a forward apply."""
+    total = 0.0
+    s = (np.arange(n_det) - 0.5 * (n_det - 1)) * ds
+    h = N / 2.0
+    for th in theta_deg:
+        rad = th * math.pi / 180.0
+        c, sn = abs(math.cos(rad)), abs(math.sin(rad))
+        if min(c, sn) < 1e-15:
+            on_edge = np.abs((s + h) - np.round(s + h)) < 1e-9
+            inside = np.abs(s) <= h
+            total += float(np.sum(np.where(inside, np.where(on_edge, 2 * N, N), 0)))
+            continue
+        # chord of the line x cos + y sin = s through the square [-h, h]^2
+        px, py = s * math.cos(rad), s * math.sin(rad)
+        dx, dy = -math.sin(rad), math.cos(rad)
+        ta, tb = (-h - px) / dx, (h - px) / dx
+        tc, td = (-h - py) / dy, (h - py) / dy
+        t0 = np.maximum(np.minimum(ta, tb), np.minimum(tc, td))
+        t1 = np.minimum(np.maximum(ta, tb), np.maximum(tc, td))
+        L = np.maximum(t1 - t0, 0.0)
+        total += float(np.sum(np.where(L > 0, 1.0 + L * (c + sn), 0.0)))
+    return int(round(total))
+
+
+def cpu_oracle_baseline(w, b_np, enorm, budget_s=15.0, max_iters=10):
+    """Times the FP64 oracle's AB-GMRES (unmatched pair) on the same workload for as
+    many Arnoldi iterations as fit in ~budget_s seconds."""
+    import oracle as O
+    from oracle.core import num_threads
+    g = O.Geometry(w.N, w.n_ang, w.n_det)
+    k = 1
+    t_used = 0.0
+    # grow the iteration count until the budget is used (each run starts from scratch)
+    while True:
+        t0 = time.perf_counter()
+        O.ab_gmres(g.A, g.B_hat, b_np, k)
+        dt = time.perf_counter() - t0
+        t_used += dt
+        if dt * 2.2 > budget_s or k >= max_iters:
+            return {"value": k / dt, "unit": "GMRES iters/s", "cores": num_threads(),
+                    "kind": "oracle",
+                    "sample": f"FP64 oracle AB-GMRES, {k} Arnoldi iterations from x0=0 on the "
+                              f"{w.N}^2 / {w.n_ang}x{w.n_det} workload (literal x_k and b-Ax_k "
+                              f"each step), {dt:.2f} s; host {os.cpu_count()} logical CPUs"}
+        k = min(max_iters, k * 2)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3])
+    ap.add_argument("--basis", default="f32", choices=["f32", "bf16"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus N > 1 is not supported "
+                                   "(multi-GPU sharding is a design note, not built)"}))
+        sys.exit(2)
+
+    import torch
+    import paper_2110_01481_amd as abg
+
+    torch.cuda.set_device(0)
+    abg.load_library()
+    w = {1: W.CONFIG1, 2: W.CONFIG2, 3: W.CONFIG3}[args.config]
+    k_max = w.k_max
+    gg = abg.Geometry(w.N, w.n_ang, w.n_det, ang_range=w.ang_range)
+    dev = torch.device("cuda:0")
+    xb = w.phantom()
+    bbar = gg.fp(torch.tensor(xb, dtype=torch.float64, device=dev)).cpu().numpy()
+    b_np, enorm = W.add_noise(bbar, w.eta, w.noise_dir())
+    b32 = torch.tensor(b_np, dtype=torch.float32, device=dev)
+    b64 = torch.tensor(b_np, dtype=torch.float64, device=dev)
+    stop = "dp" if w.stop == "dp" else w.stop
+    tau = w.tau if stop == "dp" else 1.0
+    if args.config == 1:
+        stop, tau = "dp", 1.0
+
+    def make(method, b, basis):
+        nb = abg.workspace_bytes(gg, method, k_max, proj="f64" if b.dtype == torch.float64 else "f32",
+                                 basis=basis, stop=stop)
+        return (torch.empty(nb, dtype=torch.uint8, device=dev),
+                torch.empty(gg.n, dtype=b.dtype, device=dev))
+
+    methods = ["ab", "ba"] if args.config != 3 else ["ba"]
+    bufs = {m: make(m, b32, args.basis) for m in methods}
+
+    def step(b, basis, bset):
+        iters = 0
+        res = {}
+        for m in methods:
+            ws, out = bset[m]
+            r = abg.gmres(m, gg, b, k_max, stop=stop, tau=tau, noise_norm=enorm, basis=basis,
+                          workspace=ws, out=out)
+            iters += r.k_done
+            res[m] = r
+        return iters, res
+
+    for _ in range(args.warmup):
+        step(b32, args.basis, bufs)
+    torch.cuda.synchronize()
+    abg.profile_enable(True)
+    abg.profile_read(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters = 0
+    last = None
+    for _ in range(args.steps):
+        n, last = step(b32, args.basis, bufs)
+        iters += n
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = abg.profile_read(reset=True)
+    abg.profile_enable(False)
+    elapsed = t1 - t0
+    value = iters / elapsed
+    ms_per_step = 1e3 * elapsed / args.steps
+
+    # kernel shares of the timed region
+    share = {k: v[1] for k, v in prof.items()}
+    dominant = max(share, key=share.get)
+    fwd_n, fwd_ms = prof["forward"]
+    bck_n, bck_ms = prof["back"]
+    mgs_n, mgs_ms = prof["mgs"]
+    fwd_avg_ms = fwd_ms / max(fwd_n, 1)
+    bck_avg_ms = bck_ms / max(bck_n, 1)
+    th = (np.arange(w.n_ang) * w.ang_range) / w.n_ang
+    nnz = line_model_nnz(w.N, th, w.n_det)
+    n_pix_ang = w.n * w.n_ang
+    # algorithmic work per apply: one multiply-add per nonzero of A (forward) and two
+    # interpolation taps per pixel-angle pair (back); bytes of the equivalent explicit
+    # sparse matrix-vector product (4-byte index + 4-byte value per nonzero + vectors)
+    spmv_bytes = nnz * 8 + (w.n + w.m) * 4
+    fwd_tflops = 2.0 * nnz / (fwd_avg_ms * 1e-3) / 1e12
+    bck_tflops = 4.0 * n_pix_ang / (bck_avg_ms * 1e-3) / 1e12
+    if dominant == "back":
+        roof = {"bound": "alu", "kernel": "back_kernel (pixel-driven B, FP32)",
+                "achieved": round(bck_tflops, 3), "peak": FP32_VECTOR_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(bck_tflops / FP32_VECTOR_PEAK_TFLOPS, 4),
+                "traffic": None, "avg_launch_ms": round(bck_avg_ms, 4),
+                "work_per_launch": f"{n_pix_ang} pixel-angle pairs x 4 flop"}
+    elif dominant == "mgs":
+        L_avg = (w.m + w.n) / 2
+        roof = {"bound": "hbm", "kernel": "mgs_kernel", "achieved": None, "peak": HBM_PEAK_GBPS,
+                "unit": "GB/s", "frac": None, "traffic": None,
+                "avg_launch_ms": round(mgs_ms / max(mgs_n, 1), 4)}
+    else:
+        roof = {"bound": "alu", "kernel": "forward_kernel (ray-driven line model A, FP32)",
+                "achieved": round(fwd_tflops, 3), "peak": FP32_VECTOR_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(fwd_tflops / FP32_VECTOR_PEAK_TFLOPS, 4),
+                "traffic": None, "avg_launch_ms": round(fwd_avg_ms, 4),
+                "work_per_launch": f"{nnz} ray-pixel intersections x 2 flop"}
+
+    extra = {
+        "A_applies_per_s": round(1e3 / fwd_avg_ms, 1) if fwd_n else None,
+        "B_applies_per_s": round(1e3 / bck_avg_ms, 1) if bck_n else None,
+        "A_spmv_equiv_GBps": round(spmv_bytes / (fwd_avg_ms * 1e-3) / 1e9, 1) if fwd_n else None,
+        "B_spmv_equiv_GBps": round(spmv_bytes / (bck_avg_ms * 1e-3) / 1e9, 1) if bck_n else None,
+        "nnz_A": nnz,
+        "kernel_ms": {k: [v[0], round(v[1], 3)] for k, v in prof.items()},
+        "k_stop": {m: last[m].k_stop for m in methods},
+        "k_done": {m: last[m].k_done for m in methods},
+        "n_literal": {m: last[m].n_literal for m in methods},
+    }
+
+    if not args.no_fp64:
+        b64bufs = {m: make(m, b64, "f64") for m in methods}
+        step(b64, "f64", b64bufs)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        n64, r64 = step(b64, "f64", b64bufs)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        extra["fp64_plain_iters_per_s"] = round(n64 / (t3 - t2), 2)
+        extra["fp64_plain_k_stop"] = {m: r64[m].k_stop for m in methods}
+        extra["f32_vs_f64_iterate_rel"] = {
+            m: float(torch.linalg.vector_norm(last[m].x.double() - r64[m].x) /
+                     torch.linalg.vector_norm(r64[m].x)) for m in methods}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_oracle_baseline(w, b_np, enorm)
+
+    out = {
+        "metric": "GMRES iters/s", "value": round(value, 2), "unit": "iters/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{w.N}x{w.N} image, {w.n_ang} angles in [0,{w.ang_range:g}), "
+                               f"{w.n_det} bins, {w.n_ellipses}-ellipse phantom, "
+                               f"{100 * w.eta:g}% noise; " + "+".join(m.upper() for m in methods) +
+                               f"-GMRES {stop.upper()} stop, k_max={k_max}, FP32 projectors, "
+                               f"{args.basis.upper()} basis, FP64 Hessenberg/Givens, unmatched pair",
+                   "global_batch": len(methods), "parallelism": "single GPU"},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "extra": extra,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -25,6 +25,10 @@ struct AngleParams {
     double inv;         // 1/c (steep) or 1/s (flat)
     double len;         // 1/p
     double invq;        // 1/q (0 when q == 0)
+    // pixel-driven back projectors: detector coordinate u = <c_j, omega>/ds - s0/ds
+    double cu, su;      // cos/ds, sin/ds: change of u per pixel step in x and in y
+    double half;        // (p+q)/2: half-width of the line-model trapezoid
+    double invpq;       // 1/(p q) (0 when q == 0)
     int steep;          // 1: walk image rows, 0: walk image columns
     int axis;           // 1 when q == 0 (ray parallel to a pixel edge)
 };

@@ -19,6 +19,20 @@ struct Pending {
     hipEvent_t e0, e1;
 };
 std::vector<Pending> g_pending;
+std::vector<hipEvent_t> g_event_pool;   // recycled so timing adds no event creation
+
+hipEvent_t take_event()
+{
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (!g_event_pool.empty()) {
+        hipEvent_t e = g_event_pool.back();
+        g_event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
 
 bool valid_dtype_proj(int t) { return t == ABG_F64 || t == ABG_F32; }
 
@@ -29,7 +43,7 @@ int current_device_matches(const Geometry &g)
     return dev == g.device ? ABG_OK : ABG_EINVAL;
 }
 
-AngleParams make_angle(double theta_deg)
+AngleParams make_angle(double theta_deg, double ds)
 {
     AngleParams P{};
     const double rad = theta_deg * (M_PI / 180.0);
@@ -53,6 +67,10 @@ AngleParams make_angle(double theta_deg)
     P.axis = P.q == 0.0 ? 1 : 0;
     P.invq = P.axis ? 0.0 : 1.0 / P.q;
     if (P.axis) P.m = 0.0;
+    P.cu = c / ds;
+    P.su = s / ds;
+    P.half = 0.5 * (P.p + P.q);
+    P.invpq = P.axis ? 0.0 : 1.0 / (P.p * P.q);
     return P;
 }
 
@@ -63,7 +81,9 @@ bool profiling_on() { return g_prof_on; }
 ProfScope::ProfScope(int kind_, hipStream_t s_) : kind(kind_), s(s_)
 {
     if (!g_prof_on) return;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    e0 = take_event();
+    e1 = take_event();
+    if (!e0 || !e1) {
         e0 = e1 = nullptr;
         return;
     }
@@ -88,8 +108,8 @@ void profile_flush()
             g_prof_ms[p.kind] += ms;
             g_prof_count[p.kind] += 1;
         }
-        (void)hipEventDestroy(p.e0);
-        (void)hipEventDestroy(p.e1);
+        g_event_pool.push_back(p.e0);
+        g_event_pool.push_back(p.e1);
     }
     g_pending.clear();
 }
@@ -127,7 +147,7 @@ int abg_create_geometry(int N, int n_ang, double ang_start_deg, double ang_range
             return ABG_EINVAL;
         }
         g.theta[a] = th;
-        g.host[a] = make_angle(th);
+        g.host[a] = make_angle(th, det_spacing);
     }
     if (hipGetDevice(&g.device) != hipSuccess ||
         hipMalloc((void **)&g.dev, sizeof(AngleParams) * n_ang) != hipSuccess) {

@@ -75,21 +75,27 @@ __device__ inline double agent_load(const double *p)
 {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+// Publishes a partial sum at device scope and waits until the write has been performed
+// (the exchange's returned value is consumed), so that a later counter increment
+// cannot overtake it. Partials are read back only with device-scope atomic loads, so
+// the barrier needs no release/acquire cache maintenance.
 __device__ inline void agent_store(double *p, double v)
 {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const double old = __hip_atomic_exchange(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    asm volatile("" ::"v"(old));
 }
 
 // Grid-wide barrier for a cooperative launch: each block adds one to the counter and
 // waits until it reaches `target`. The wait is bounded; on timeout the sticky error
-// flag is raised and every later barrier returns at once.
+// flag is raised and every later barrier returns at once. Only values written with
+// agent_store and read with agent_load cross it.
 __device__ inline void grid_barrier(unsigned *bar, unsigned target, int *err)
 {
     __syncthreads();
     if (threadIdx.x == 0) {
-        __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         unsigned spins = 0;
-        while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
             __builtin_amdgcn_s_sleep(1);
             if (++spins > kSpinLimit) {
                 __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

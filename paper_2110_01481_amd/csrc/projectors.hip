@@ -9,9 +9,11 @@
 //           of one image row; steep rays read the row-major copy, flat rays a transposed
 //           copy, both zero-padded so that no per-tap bounds test is needed.
 //  back     x = B y (unmatched, linear interpolation on the detector) or x = A^T y,
-//           one thread per pixel of a 16 x 16 tile. For a block of 32 angles the tile's
-//           detector footprint (at most 32 bins per angle) is staged in LDS, then every
-//           pixel reads its two taps per angle from LDS.
+//           pixel-driven: a block owns a 16 x 16 tile, each lane 4 of its pixels, and the
+//           four waves split the angles. For a round of 128 angles the tile's detector
+//           footprint (at most 32 bins per angle) is staged in LDS; every pixel then
+//           reads its two taps per angle from LDS, and the four wave partials are summed
+//           in a fixed order at the end.
 #include <cmath>
 
 #include "abg_internal.h"
@@ -27,8 +29,14 @@ constexpr double kEdgeTie = 1e-9;
 template <typename T> __device__ inline T edge_tie();
 template <> __device__ inline double edge_tie<double>() { return 1e-9; }
 template <> __device__ inline float edge_tie<float>() { return 2e-5f; }
+// back projector: a 16 x 16 pixel tile per block, 4 pixels per lane, the 4 waves
+// splitting the angles; the tile's detector footprint for 128 angles is staged per
+// round (at most 30 bins per angle for det_spacing >= 0.75, plus margins)
 constexpr int kTile = 16;
-constexpr int kAngBlock = 32;
+constexpr int kBackWaves = 4;
+constexpr int kBackThreads = 64 * kBackWaves;
+constexpr int kPixPerLane = kTile * kTile / 64;
+constexpr int kAngBlock = 128;
 constexpr int kWin = 32;
 
 __device__ inline int wave_min_i(int v)
@@ -79,6 +87,63 @@ __global__ void pad_zero_kernel(T *__restrict__ xr, T *__restrict__ xc, int N, i
     const int col = k < kPad ? k : N + k;   // [0,kPad) and [N+kPad, N+2kPad)
     T *base = row < N ? xr + (size_t)row * S : xc + (size_t)(row - N) * S;
     base[col] = T(0);
+}
+
+// Position of a ray inside the current band of pixels: the band holds the minor-axis
+// interval [lo, lo + |m|] (pixels from the image edge) and the walk advances lo by m.
+// FP64 data: lo in FP64. FP32 data: lo in 24.40 fixed point biased by kPad, so a band
+// step is one 64-bit add, the pixel index is the integer part and the top 32 fraction
+// bits give the weight (position error ~1e-9 px after 32768 steps).
+template <typename T> struct Band;
+template <typename T> struct BandWeights {
+    T invq, len;
+    __device__ BandWeights(double iq, double l) : invq(T(iq)), len(T(l)) {}
+};
+
+template <> struct Band<double> {
+    double lo, m;
+    __device__ Band(double lo0, double m_) : lo(lo0), m(m_) {}
+    __device__ void next() { lo += m; }
+    __device__ unsigned column(unsigned cmax) const
+    {
+        return min((unsigned)((int)floor(lo) + kPad), cmax);
+    }
+    // length of the band segment left of the pixel edge at floor(lo) + 1
+    __device__ double left_length(const BandWeights<double> &b) const
+    {
+        return fmin(b.len, fma(floor(lo) - lo, b.invq, b.invq));
+    }
+};
+
+template <> struct Band<float> {
+    long long fx, mfx;
+    __device__ Band(double lo0, double m)
+        : fx(__double2ll_rn((lo0 + kPad) * 0x1p40)), mfx(__double2ll_rn(m * 0x1p40)) {}
+    __device__ void next() { fx += mfx; }
+    __device__ unsigned column(unsigned cmax) const
+    {
+        // negative positions wrap to large values and clamp into the right-hand padding
+        return min((unsigned)(int)(fx >> 40), cmax);
+    }
+    __device__ float left_length(const BandWeights<float> &b) const
+    {
+        const float frac = (float)(unsigned)(fx >> 8);      // top 32 fraction bits
+        const float w = fmaf(frac, -b.invq * 0x1p-32f, b.invq);
+        return __builtin_amdgcn_fmed3f(w, b.len, -1e30f);   // min(w, len)
+    }
+};
+
+// The two adjacent pixels a band segment can touch, fetched with one load from a
+// wave-uniform row pointer plus a 32-bit byte offset (one wide gather is cheaper for
+// the texture address unit than two narrow ones).
+template <typename T> struct alignas(sizeof(T)) Taps {
+    T a, b;
+};
+template <typename T>
+__device__ inline Taps<T> load_taps(const T *row, unsigned col)
+{
+    const unsigned boff = col * (unsigned)sizeof(T);
+    return *reinterpret_cast<const Taps<T> *>(reinterpret_cast<const char *>(row) + boff);
 }
 
 template <typename T>
@@ -140,34 +205,59 @@ __global__ __launch_bounds__(kFwdBlock) void forward_kernel(
             r0 = N;
             r1 = 0;
         }
-        const int wr0 = wave_min_i(r0);
-        const int wr1 = wave_max_i(r1);
-        double lo = fma((double)wr0, P.m, lo0);
-        const T *row = img + (size_t)wr0 * S;
-        const double invq = P.invq, len = P.len;
-        const T lenT = T(len);
-        for (int r = wr0; r < wr1; ++r) {
-            const double lc = fmin(fmax(lo, lo_clamp), hi_clamp);
-            const double fl = floor(lc);
-            const int c = (int)fl;
-            // part of the band segment left of the edge at fl+1
-            const T wlo = T(fmin(len, ((fl + 1.0) - lc) * invq));
-            const T whi = lenT - wlo;
-            acc = fma(wlo, row[c], acc);
-            acc = fma(whi, row[c + 1], acc);
-            lo += P.m;
+        // wave-uniform band range: lanes outside their own chord read zero padding
+        const int wr0 = __builtin_amdgcn_readfirstlane(wave_min_i(r0));
+        const int wr1 = __builtin_amdgcn_readfirstlane(wave_max_i(r1));
+        Band<T> band(fma((double)wr0, P.m, lo0), P.m);
+        // row-start pointer (padding included): column offsets are unsigned
+        const T *row = img - kPad + (size_t)wr0 * S;
+        const BandWeights<T> bw(P.invq, P.len);
+        const unsigned cmax = (unsigned)(N + 2 * kPad - 2);
+        int r = wr0;
+        // four bands per trip, all loads issued before their use
+        for (; r + 4 <= wr1; r += 4) {
+            unsigned c[4];
+            T w[4], v0[4], v1[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                c[j] = band.column(cmax);
+                w[j] = band.left_length(bw);
+                band.next();
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const Taps<T> t = load_taps(row + (size_t)j * S, c[j]);
+                v0[j] = t.a;
+                v1[j] = t.b;
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                acc = fma(w[j], v0[j], acc);
+                acc = fma(bw.len - w[j], v1[j], acc);
+            }
+            row += 4 * (size_t)S;
+        }
+        for (; r < wr1; ++r) {
+            const unsigned c = band.column(cmax);
+            const T w = band.left_length(bw);
+            band.next();
+            const Taps<T> t = load_taps(row, c);
+            acc = fma(w, t.a, acc);
+            acc = fma(bw.len - w, t.b, acc);
             row += S;
         }
     }
     if (i < n_det) y[(size_t)a * n_det + i] = acc;
 }
 
+// Per staged angle: position of the tile's reference pixel in the window (f), the
+// change of u per pixel step (cu, su), the window's first bin, and the line-model
+// trapezoid of the matched back projector.
 template <typename T>
 struct alignas(16) BackStage {
-    T f;       // u of the tile's reference pixel relative to the staged window start
-    T cu, su;  // du per pixel step in x and in y
+    T f, cu, su;
+    int ib;
     T invp, half, invpq;
-    int ib;    // first staged bin
     int axis;
 };
 
@@ -183,63 +273,102 @@ __device__ inline T trapezoid(T at, const BackStage<T> &P)
     return fmin(P.invp, fmax(T(0), (P.half - at) * P.invpq));
 }
 
+template <typename T> __device__ inline T fract_of(T u);
+template <> __device__ inline float fract_of<float>(float u) { return __builtin_amdgcn_fractf(u); }
+template <> __device__ inline double fract_of<double>(double u) { return __builtin_amdgcn_fract(u); }
+
+// Staged window entry: the bin's value and the difference to the next bin.
+template <typename T> struct alignas(2 * sizeof(T)) BinPair {
+    T v, d;
+};
+
+// One pixel's contribution at detector coordinate u (window-relative, u >= 1 by
+// construction, so truncation is floor).
 template <typename T, bool ADJ>
-__global__ __launch_bounds__(kTile *kTile) void back_kernel(
+__device__ inline T back_tap(const BinPair<T> *wrow, T u, const BackStage<T> &P, T dsT)
+{
+    const T w = fract_of(u);
+    const int k = min(max((int)u, 0), kWin - 2);
+    const BinPair<T> b = wrow[k];
+    if (!ADJ) return fma(w, b.d, b.v);
+    return trapezoid(w * dsT, P) * b.v + trapezoid((T(1) - w) * dsT, P) * (b.v + b.d);
+}
+
+template <typename T, bool ADJ>
+__global__ __launch_bounds__(kBackThreads) void back_kernel(
     const T *__restrict__ y, T *__restrict__ x, const AngleParams *__restrict__ ang, int N,
     int n_ang, int n_det, double ds, double s0)
 {
-    __shared__ T win[kAngBlock][kWin];
+    __shared__ BinPair<T> win[kAngBlock][kWin];
     __shared__ BackStage<T> prm[kAngBlock];
-    const int tx = threadIdx.x % kTile, ty = threadIdx.x / kTile;
+    __shared__ T part[kBackWaves - 1][kTile * kTile];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    // lane owns pixels (tx, ty0 + 4j), j = 0..3, of the 16 x 16 tile
+    const int tx = lane & 15, ty0 = lane >> 4;
     const int c0 = blockIdx.x * kTile, r0 = blockIdx.y * kTile;
     const double xref = c0 - 0.5 * N + 0.5, yref = r0 - 0.5 * N + 0.5;
-    const T ftx = T(tx), fty = T(ty);
+    const double s0u = s0 / ds;
+    const T ftx = T(tx), fty = T(ty0);
     const T dsT = T(ds);
-    T acc = T(0);
+    T acc[kPixPerLane] = {};
     for (int a0 = 0; a0 < n_ang; a0 += kAngBlock) {
         const int na = min(kAngBlock, n_ang - a0);
         __syncthreads();
         if (threadIdx.x < na) {
             const AngleParams P = ang[a0 + threadIdx.x];
-            const double cu = P.c / ds, su = P.s / ds;
-            const double uref = (fma(xref, P.c, yref * P.s) - s0) / ds;
-            const double umin = uref + (kTile - 1) * (fmin(cu, 0.0) + fmin(su, 0.0));
+            const double uref = fma(xref, P.cu, fma(yref, P.su, -s0u));
+            const double umin = uref + (kTile - 1) * (fmin(P.cu, 0.0) + fmin(P.su, 0.0));
             const double ib = floor(umin) - 1.0;
             BackStage<T> st;
             st.f = T(uref - ib);
-            st.cu = T(cu);
-            st.su = T(su);
-            st.invp = T(1.0 / P.p);
-            st.half = T(0.5 * (P.p + P.q));
-            st.invpq = P.axis ? T(0) : T(1.0 / (P.p * P.q));
+            st.cu = T(P.cu);
+            st.su = T(P.su);
             st.ib = (int)ib;
+            st.invp = T(P.len);
+            st.half = T(P.half);
+            st.invpq = T(P.invpq);
             st.axis = P.axis;
             prm[threadIdx.x] = st;
         }
         __syncthreads();
-        for (int e = threadIdx.x; e < na * kWin; e += kTile * kTile) {
+        for (int e = threadIdx.x; e < na * kWin; e += kBackThreads) {
             const int t = e / kWin, k = e % kWin;
             const int bin = prm[t].ib + k;
-            win[t][k] = (bin >= 0 && bin < n_det) ? y[(size_t)(a0 + t) * n_det + bin] : T(0);
+            const T *row = y + (size_t)(a0 + t) * n_det;
+            const T v0 = (bin >= 0 && bin < n_det) ? row[bin] : T(0);
+            const T v1 = (bin + 1 >= 0 && bin + 1 < n_det) ? row[bin + 1] : T(0);
+            win[t][k] = BinPair<T>{v0, v1 - v0};
         }
         __syncthreads();
-        for (int t = 0; t < na; ++t) {
+        // the block's waves take interleaved angles of the staged round
+        for (int t = wave; t < na; t += kBackWaves) {
             const BackStage<T> P = prm[t];
-            const T u = fma(ftx, P.cu, fma(fty, P.su, P.f));
-            const T fl = floor(u);
-            const T w = u - fl;
-            const int k = min(max((int)fl, 0), kWin - 2);
-            const T v0 = win[t][k], v1 = win[t][k + 1];
-            if (!ADJ) {
-                acc += fma(w, v1 - v0, v0);
-            } else {
-                acc = fma(trapezoid(w * dsT, P), v0, acc);
-                acc = fma(trapezoid((T(1) - w) * dsT, P), v1, acc);
-            }
+            const T u0 = fma(ftx, P.cu, fma(fty, P.su, P.f));
+            const T du = T(4) * P.su;
+#pragma unroll
+            for (int j = 0; j < kPixPerLane; ++j)
+                acc[j] += back_tap<T, ADJ>(win[t], fma(T(j), du, u0), P, dsT);
         }
     }
-    const int c = c0 + tx, r = r0 + ty;
-    if (r < N && c < N) x[(size_t)r * N + c] = ADJ ? acc : acc * T(1.0 / ds);
+    // fixed-order sum of the four waves' partials
+#pragma unroll
+    for (int j = 0; j < kPixPerLane; ++j) {
+        const int pix = (ty0 + 4 * j) * kTile + tx;
+        if (wave > 0) part[wave - 1][pix] = acc[j];
+    }
+    __syncthreads();
+    if (wave == 0) {
+#pragma unroll
+        for (int j = 0; j < kPixPerLane; ++j) {
+            const int pix = (ty0 + 4 * j) * kTile + tx;
+            T sum = acc[j];
+#pragma unroll
+            for (int v = 0; v < kBackWaves - 1; ++v) sum += part[v][pix];
+            const int c = c0 + tx, r = r0 + ty0 + 4 * j;
+            if (r < N && c < N) x[(size_t)r * N + c] = ADJ ? sum : sum * T(1.0 / ds);
+        }
+    }
 }
 
 template <typename T>
@@ -269,10 +398,10 @@ hipError_t back_t(const Geometry &g, int kind, const void *y, void *x, hipStream
     const double s0 = -0.5 * (g.n_det - 1) * g.ds;
     ProfScope ps(kProfBack, s);
     if (kind == ABG_BP_ADJ)
-        back_kernel<T, true><<<grid, kTile * kTile, 0, s>>>(
+        back_kernel<T, true><<<grid, kBackThreads, 0, s>>>(
             static_cast<const T *>(y), static_cast<T *>(x), g.dev, g.N, g.n_ang, g.n_det, g.ds, s0);
     else
-        back_kernel<T, false><<<grid, kTile * kTile, 0, s>>>(
+        back_kernel<T, false><<<grid, kBackThreads, 0, s>>>(
             static_cast<const T *>(y), static_cast<T *>(x), g.dev, g.N, g.n_ang, g.n_det, g.ds, s0);
     return hipGetLastError();
 }
