@@ -50,29 +50,52 @@ struct bf16 {
     uint16_t bits;
 };
 
+struct DevState;
+
 inline size_t dtype_size(int t) { return t == ABG_F64 ? 8 : (t == ABG_F32 ? 4 : 2); }
 inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 // ---- launchers (projectors.hip) ------------------------------------------------------
 size_t fp_workspace_bytes(const Geometry &g, int dtype);
+// `st`/`k`: when st is given, the launch is part of Arnoldi step k and returns at once
+// if the solve is halted.
 hipError_t launch_forward(const Geometry &g, int dtype, const void *x, void *y, void *ws,
-                          hipStream_t s);
+                          hipStream_t s, const DevState *st = nullptr, int k = 0);
 hipError_t launch_back(const Geometry &g, int kind, int dtype, const void *y, void *x,
-                       hipStream_t s);
+                       hipStream_t s, const DevState *st = nullptr, int k = 0);
 
 // ---- Krylov kernels (krylov.hip) -----------------------------------------------------
+// Scalars of one solve, in device memory. Per-step kernels of step k return at entry
+// when the solve is halted: a stop raised by an earlier step, or an Arnoldi breakdown
+// at an earlier step. The host reads a copy after every step.
 struct DevState {
     double beta;         // ||r_0||
     double qnorm0;       // ||q_k|| before orthogonalisation
     double hnext;        // h_{k+1,k}
-    double ls;           // |g_{k+1}|
-    double res;          // norm written by the last residual / norm reduction
+    double ls;           // |g_{k+1}|: GMRES residual of the small least-squares problem
+    double res;          // norm written by the last residual reduction
     double ncp;          // d_k
-    int breakdown;
-    int error;           // sticky: grid-barrier timeout or singular triangle
-    int stop;            // when nonzero, Arnoldi kernels return at entry
-    int pad_;
+    double ncp_prev;     // d_{k-1}
+    double dp_thr;       // DP candidate threshold tau*||e||*(1+slack); 0 without DP
+    int k;               // step that last completed its Givens update
+    int bd_k;            // step at which h_{k+1,k} fell below the breakdown bound (0: none)
+    int error;           // sticky: 1 grid-barrier timeout, 2 non-finite norm, 4 singular R
+    int stop;            // raised by the last kernel of a step: later steps return at entry
+    int stop_k;          // step that raised it
+    int stop_reason;     // kStop*
+    int pad_[2];
 };
+enum { kStopNone = 0, kStopDP = 1, kStopNCP = 2, kStopError = 3 };
+
+#ifdef __HIPCC__
+// True when per-step kernels of step k must not run.
+__device__ inline bool halted(const DevState *st, int k)
+{
+    if (!st) return false;
+    const volatile DevState *v = st;
+    return v->stop != 0 || (v->bd_k != 0 && v->bd_k < k) || v->error != 0;
+}
+#endif
 
 struct MgsLaunch {
     int tx, tv;                  // dtypes of q / cur and of the basis
@@ -88,24 +111,32 @@ struct MgsLaunch {
     unsigned *bar;               // zeroed counter for this launch
     DevState *st;
     double bd_rel;               // breakdown: h_{k+1,k} <= bd_rel * ||q_k||
+    int step;                    // Arnoldi step (0: the initial normalisation)
 };
 constexpr int kMaxGrid = 2048;
 hipError_t launch_mgs(const MgsLaunch &a, hipStream_t s);
 
-// out = base_coef*base + sum_{j<kk} sgn*coef[j]*V_j  (FP64 accumulation); optional
-// partial sums of out^2 per block into partials (then reduce_partials).
+// out = base_coef*base + sum_{j<kk} sgn*coef[j]*V_j  (FP64 accumulation). With `norm`
+// set, ||out||_2 is reduced in a fixed order by the last block to finish and written to
+// *norm; when st is given the launch belongs to step k (halt check) and, if
+// st->dp_thr > 0 and ||out|| <= dp_thr, raises the DP stop for step k. `count` is a
+// zeroed counter that the last block resets.
 hipError_t launch_combine(int tout, const void *base, double base_coef, int tv, const void *V,
                           size_t ldv, int kk, const double *coef, double sgn, void *out,
-                          long long L, double *partials, int *nblocks, const DevState *st,
-                          hipStream_t s);
+                          long long L, double *partials, unsigned *count, double *norm,
+                          DevState *st, int k, hipStream_t s);
 // out = a - b with partial sums of out^2.
 hipError_t launch_sub_norm(int t, const void *a, const void *b, void *out, long long L,
                            double *partials, int *nblocks, hipStream_t s);
 // dst = sqrt(sum partials[0..nb)) (fixed order, one block).
 hipError_t launch_reduce_sqrt(const double *partials, int nb, double *dst, hipStream_t s);
+// Givens update of column k of H, y_k into y (k entries), and rho = beta e_1 - H_k y_k
+// when rho is given.
 hipError_t launch_givens(double *H, int ld, double *R, double *cs, double *sn, double *g,
-                         double *y, double *rho, double beta, int k, int need_y, DevState *st,
+                         double *y, double *rho, double beta, int k, DevState *st,
                          hipStream_t s);
+// Clears the stop flag (after a DP candidate that the explicit residual rejected).
+hipError_t launch_clear_stop(DevState *st, hipStream_t s);
 void set_mgs_target_blocks(int blocks);
 hipError_t launch_fill_u32(unsigned *p, size_t n, unsigned v, hipStream_t s);
 hipError_t launch_fill_f64(double *p, size_t n, double v, hipStream_t s);
@@ -113,8 +144,10 @@ hipError_t launch_axpy_inplace(int t, void *x, const void *x0, long long L, hipS
 
 // ---- NCP (ncp.hip) ------------------------------------------------------------------
 size_t ncp_scratch_bytes(const Geometry &g);
-hipError_t launch_ncp(const Geometry &g, int t, const void *r, double *scratch, double *dst,
-                      hipStream_t s);
+// d_k of the residual r into st->ncp; raises the NCP stop for step k when k >= 2 and
+// d_k > d_{k-1}.
+hipError_t launch_ncp(const Geometry &g, int t, const void *r, double *scratch, DevState *st,
+                      int k, hipStream_t s);
 
 // ---- solvers (solver.hip) -----------------------------------------------------------
 size_t solver_workspace_bytes(const Geometry &g, int method, int k_max, abg_precision p,
@@ -126,14 +159,23 @@ int run_solver(const Geometry &g, int method, int kind, const void *b, const voi
 // ---- profiling (capi.cpp) -----------------------------------------------------------
 enum ProfKind { kProfFwd = 0, kProfBack = 1, kProfMgs = 2, kProfCombine = 3 };
 bool profiling_on();
+// Brackets one launch with timing events when profiling is on. `step` tags launches
+// that belong to an Arnoldi step of the solve running on this thread; launches of
+// steps that a solve enqueued but never ran (past its stop) are dropped at its end.
 struct ProfScope {
-    ProfScope(int kind, hipStream_t s);
+    ProfScope(int kind, hipStream_t s, int step = 0);
     ~ProfScope();
-    int kind;
+    int kind, step;
     hipStream_t s;
     hipEvent_t e0 = nullptr, e1 = nullptr;
 };
 void profile_flush();
+void profile_solve_begin();
+// Drops this thread's pending launches of steps > last_step (enqueued past the stop).
+void profile_solve_end(int last_step);
+// Drops this thread's pending launches of `step` enqueued so far (a step that was
+// skipped and is about to be enqueued again).
+void profile_drop_step(int step);
 
 }  // namespace abg
 

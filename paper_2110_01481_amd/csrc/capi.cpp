@@ -1,5 +1,6 @@
 // extern "C" entry points of libabgmres: argument checking, geometry set-up (angle
 // table, Table 6.1 parameters), dispatch to the HIP launchers, and launch timing.
+#include <atomic>
 #include <cmath>
 #include <mutex>
 #include <new>
@@ -17,7 +18,11 @@ double g_prof_ms[4] = {0, 0, 0, 0};
 struct Pending {
     int kind;
     hipEvent_t e0, e1;
+    long long solve;   // solve id of the launching thread (0: outside a solve)
+    int step;
 };
+std::atomic<long long> g_solve_ids{0};
+thread_local long long t_solve = 0;
 std::vector<Pending> g_pending;
 std::vector<hipEvent_t> g_event_pool;   // recycled so timing adds no event creation
 
@@ -78,7 +83,7 @@ AngleParams make_angle(double theta_deg, double ds)
 
 bool profiling_on() { return g_prof_on; }
 
-ProfScope::ProfScope(int kind_, hipStream_t s_) : kind(kind_), s(s_)
+ProfScope::ProfScope(int kind_, hipStream_t s_, int step_) : kind(kind_), step(step_), s(s_)
 {
     if (!g_prof_on) return;
     e0 = take_event();
@@ -95,7 +100,49 @@ ProfScope::~ProfScope()
     if (!e0) return;
     (void)hipEventRecord(e1, s);
     std::lock_guard<std::mutex> lk(g_prof_mu);
-    g_pending.push_back({kind, e0, e1});
+    g_pending.push_back({kind, e0, e1, t_solve, step});
+}
+
+void profile_solve_begin()
+{
+    if (!g_prof_on) return;
+    t_solve = ++g_solve_ids;
+}
+
+namespace {
+// Removes pending launches of the current solve selected by `pred` (caller holds the lock).
+template <typename Pred>
+void drop_pending(long long id, Pred pred)
+{
+    std::vector<Pending> keep;
+    keep.reserve(g_pending.size());
+    for (auto &p : g_pending) {
+        if (p.solve == id && p.step > 0 && pred(p.step)) {
+            (void)hipEventSynchronize(p.e1);
+            g_event_pool.push_back(p.e0);
+            g_event_pool.push_back(p.e1);
+        } else {
+            keep.push_back(p);
+        }
+    }
+    g_pending.swap(keep);
+}
+}  // namespace
+
+void profile_solve_end(int last_step)
+{
+    const long long id = t_solve;
+    t_solve = 0;
+    if (!g_prof_on || id == 0) return;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    drop_pending(id, [&](int step) { return step > last_step; });
+}
+
+void profile_drop_step(int step)
+{
+    if (!g_prof_on || t_solve == 0) return;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    drop_pending(t_solve, [&](int st) { return st == step; });
 }
 
 void profile_flush()

@@ -9,6 +9,7 @@
 //           with FP64 accumulation and a fixed-order norm reduction.
 // Every reduction runs in a fixed order, so results are identical run to run.
 #include <cmath>
+#include <cstdlib>
 #include <mutex>
 #include <unordered_map>
 
@@ -130,13 +131,14 @@ struct MgsDev {
     unsigned *bar;
     DevState *st;
     double bd_rel;
+    int step;
 };
 
 template <typename TX, typename TV, int E>
 __global__ __launch_bounds__(kBlock) void mgs_kernel(MgsDev a)
 {
     __shared__ double lds[kWaves];
-    if (*(volatile int *)&a.st->stop) return;
+    if (halted(a.st, a.step)) return;
     const int G = gridDim.x;
     const long long T = (long long)G * kBlock;
     const long long gt = (long long)blockIdx.x * kBlock + threadIdx.x;
@@ -196,7 +198,7 @@ __global__ __launch_bounds__(kBlock) void mgs_kernel(MgsDev a)
         a.hcol[a.k] = hn;
         a.st->hnext = hn;
         a.st->qnorm0 = q0;
-        a.st->breakdown = bd ? 1 : 0;
+        if (bd && a.step > 0) a.st->bd_k = a.step;
         if (!finite) a.st->error |= 2;
     }
     TV *vo = static_cast<TV *>(a.vout);
@@ -242,7 +244,16 @@ hipError_t coop_capacity(const void *fn, int *max_blocks)
     return hipSuccess;
 }
 
-int g_target_blocks = 256;
+// Blocks of the cooperative MGS launch when the vector is long enough (fewer blocks make
+// the grid-wide reductions cheaper, more blocks keep more loads in flight). The
+// environment variable ABG_MGS_BLOCKS overrides it.
+int default_target_blocks()
+{
+    const char *e = getenv("ABG_MGS_BLOCKS");
+    const int v = e ? atoi(e) : 0;
+    return v > 0 ? v : 256;
+}
+int g_target_blocks = default_target_blocks();
 
 template <typename TX, typename TV, int E>
 hipError_t mgs_go(const MgsDev &d, int G, hipStream_t s)
@@ -289,11 +300,13 @@ __global__ __launch_bounds__(kBlock) void combine_kernel(const TB *__restrict__ 
                                                          int kk, const double *__restrict__ coef,
                                                          double sgn, TO *__restrict__ out,
                                                          long long L, double *partials,
-                                                         const DevState *st)
+                                                         unsigned *count, double *norm,
+                                                         DevState *st, int k)
 {
     __shared__ double cf[kMaxCoef];
     __shared__ double lds[kWaves];
-    if (st && *(volatile const int *)&st->stop) return;
+    __shared__ int last;
+    if (halted(st, k)) return;
     for (int j = threadIdx.x; j < kk; j += kBlock) cf[j] = sgn * coef[j];
     __syncthreads();
     const long long T = (long long)gridDim.x * kBlock;
@@ -316,9 +329,33 @@ __global__ __launch_bounds__(kBlock) void combine_kernel(const TB *__restrict__ 
         out[l] = (TO)acc;
         ss = fma(acc, acc, ss);
     }
-    if (partials) {
-        ss = block_sum(ss, lds);
-        if (threadIdx.x == 0) partials[blockIdx.x] = ss;
+    if (!norm) return;
+    // fixed-order norm: per-block partials, summed by the last block to finish
+    ss = block_sum(ss, lds);
+    if (threadIdx.x == 0) {
+        agent_store(partials + blockIdx.x, ss);
+        const unsigned prev = __hip_atomic_fetch_add(count, 1u, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT);
+        last = prev == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!last) return;
+    double t = 0.0;
+    for (int j = threadIdx.x; j < (int)gridDim.x; j += kBlock) t += agent_load(partials + j);
+    t = block_sum(t, lds);
+    if (threadIdx.x == 0) {
+        __hip_atomic_store(count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const double r = sqrt(t);
+        *norm = r;
+        if (st) {
+            if (!isfinite(r)) {
+                st->error |= 2;
+            } else if (st->dp_thr > 0.0 && r <= st->dp_thr && !st->stop) {
+                st->stop = 1;
+                st->stop_k = k;
+                st->stop_reason = kStopDP;
+            }
+        }
     }
 }
 
@@ -366,20 +403,22 @@ __global__ void fill_f64_kernel(double *p, size_t n, double v)
     if (i < n) p[i] = v;
 }
 
-// One wave. Column k-1 of H has just been written by mgs. R holds the rotated columns.
+// One wave. Column k-1 of H has just been written by mgs; R holds the rotated columns,
+// cs/sn the rotations, g the rotated right-hand side. Writes y_k (k entries) and, when
+// rho is given, rho = beta e_1 - H_k y_k.
 __global__ __launch_bounds__(64) void givens_kernel(double *H, int ld, double *R, double *cs,
                                                     double *sn, double *g, double *y,
-                                                    double *rho, double beta, int k, int need_y,
+                                                    double *rho, double beta, int k,
                                                     DevState *st)
 {
     __shared__ double gg[kMaxCoef];
     __shared__ double ys[kMaxCoef];
-    if (*(volatile int *)&st->stop) return;
+    if (halted(st, k)) return;
     const int lane = threadIdx.x;
     const int j = k - 1;
     double *Hc = H + (size_t)j * ld;
     double *Rc = R + (size_t)j * ld;
-    const int bd = st->breakdown;
+    const bool bd = st->bd_k == k;
     for (int i = lane; i <= k; i += 64) Rc[i] = (i == k && bd) ? 0.0 : Hc[i];
     __syncthreads();
     if (lane == 0) {
@@ -405,9 +444,9 @@ __global__ __launch_bounds__(64) void givens_kernel(double *H, int ld, double *R
         g[j] = c * gj;
         g[k] = -s * gj;
         st->ls = fabs(g[k]);
+        st->k = k;
     }
     __syncthreads();
-    if (!need_y) return;
     for (int i = lane; i < k; i += 64) gg[i] = g[i];
     __syncthreads();
     for (int jj = k - 1; jj >= 0; --jj) {
@@ -426,10 +465,19 @@ __global__ __launch_bounds__(64) void givens_kernel(double *H, int ld, double *R
     }
 }
 
-int blocks_for(long long L)
+__global__ void clear_stop_kernel(DevState *st)
+{
+    if (threadIdx.x == 0) {
+        st->stop = 0;
+        st->stop_k = 0;
+        st->stop_reason = kStopNone;
+    }
+}
+
+int blocks_for(long long L, long long cap = 1024)
 {
     long long b = (L + kBlock - 1) / kBlock;
-    if (b > 1024) b = 1024;
+    if (b > cap) b = cap;
     if (b < 1) b = 1;
     return (int)b;
 }
@@ -437,13 +485,13 @@ int blocks_for(long long L)
 template <typename TO, typename TB, typename TV>
 hipError_t combine_go(const void *base, double bcoef, const void *V, size_t ldv, int kk,
                       const double *coef, double sgn, void *out, long long L, double *partials,
-                      int *nblocks, const DevState *st, hipStream_t s)
+                      unsigned *count, double *norm, DevState *st, int k, hipStream_t s)
 {
-    const int nb = blocks_for(L);
-    if (nblocks) *nblocks = nb;
+    // with a norm, every block signals completion on one counter: keep the grid small
+    const int nb = blocks_for(L, norm ? 160 : 1024);
     combine_kernel<TO, TB, TV><<<nb, kBlock, 0, s>>>(
         static_cast<const TB *>(base), bcoef, static_cast<const TV *>(V), ldv, kk, coef, sgn,
-        static_cast<TO *>(out), L, partials, st);
+        static_cast<TO *>(out), L, partials, count, norm, st, k);
     return hipGetLastError();
 }
 
@@ -469,7 +517,8 @@ hipError_t launch_mgs(const MgsLaunch &m, hipStream_t s)
     d.bar = m.bar;
     d.st = m.st;
     d.bd_rel = m.bd_rel;
-    ProfScope ps(kProfMgs, s);
+    d.step = m.step;
+    ProfScope ps(kProfMgs, s, m.step);
     if (m.tx == ABG_F64) {
         if (m.tv == ABG_F64) return mgs_dispatch<double, double>(d, s);
         if (m.tv == ABG_F32) return mgs_dispatch<double, float>(d, s);
@@ -482,18 +531,21 @@ hipError_t launch_mgs(const MgsLaunch &m, hipStream_t s)
 
 hipError_t launch_combine(int tout, const void *base, double base_coef, int tv, const void *V,
                           size_t ldv, int kk, const double *coef, double sgn, void *out,
-                          long long L, double *partials, int *nblocks, const DevState *st,
-                          hipStream_t s)
+                          long long L, double *partials, unsigned *count, double *norm,
+                          DevState *st, int k, hipStream_t s)
 {
     if (kk > kMaxCoef) return hipErrorInvalidValue;
-    ProfScope ps(kProfCombine, s);
+    ProfScope ps(kProfCombine, s, st ? k : 0);
+#define ABG_COMBINE(TO, TB, TV) \
+    combine_go<TO, TB, TV>(base, base_coef, V, ldv, kk, coef, sgn, out, L, partials, count, norm, st, k, s)
     if (tout == ABG_F64) {
-        if (tv == ABG_F64) return combine_go<double, double, double>(base, base_coef, V, ldv, kk, coef, sgn, out, L, partials, nblocks, st, s);
-        if (tv == ABG_F32) return combine_go<double, double, float>(base, base_coef, V, ldv, kk, coef, sgn, out, L, partials, nblocks, st, s);
-        return combine_go<double, double, bf16>(base, base_coef, V, ldv, kk, coef, sgn, out, L, partials, nblocks, st, s);
+        if (tv == ABG_F64) return ABG_COMBINE(double, double, double);
+        if (tv == ABG_F32) return ABG_COMBINE(double, double, float);
+        return ABG_COMBINE(double, double, bf16);
     }
-    if (tv == ABG_F32) return combine_go<float, float, float>(base, base_coef, V, ldv, kk, coef, sgn, out, L, partials, nblocks, st, s);
-    if (tv == ABG_BF16) return combine_go<float, float, bf16>(base, base_coef, V, ldv, kk, coef, sgn, out, L, partials, nblocks, st, s);
+    if (tv == ABG_F32) return ABG_COMBINE(float, float, float);
+    if (tv == ABG_BF16) return ABG_COMBINE(float, float, bf16);
+#undef ABG_COMBINE
     return hipErrorInvalidValue;
 }
 
@@ -518,11 +570,16 @@ hipError_t launch_reduce_sqrt(const double *partials, int nb, double *dst, hipSt
 }
 
 hipError_t launch_givens(double *H, int ld, double *R, double *cs, double *sn, double *g,
-                         double *y, double *rho, double beta, int k, int need_y, DevState *st,
-                         hipStream_t s)
+                         double *y, double *rho, double beta, int k, DevState *st, hipStream_t s)
 {
     if (k + 1 > kMaxCoef) return hipErrorInvalidValue;
-    givens_kernel<<<1, 64, 0, s>>>(H, ld, R, cs, sn, g, y, rho, beta, k, need_y, st);
+    givens_kernel<<<1, 64, 0, s>>>(H, ld, R, cs, sn, g, y, rho, beta, k, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_clear_stop(DevState *st, hipStream_t s)
+{
+    clear_stop_kernel<<<1, 64, 0, s>>>(st);
     return hipGetLastError();
 }
 

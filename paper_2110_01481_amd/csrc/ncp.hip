@@ -16,10 +16,12 @@ constexpr int kBlock = 256;
 
 template <typename T, int J>
 __global__ __launch_bounds__(kBlock) void ncp_rows_kernel(const T *__restrict__ r, int n_det,
-                                                          int q, double *__restrict__ crow)
+                                                          int q, double *__restrict__ crow,
+                                                          const DevState *st, int k)
 {
     extern __shared__ double row[];
     __shared__ double chunk[kBlock];
+    if (halted(st, k)) return;
     const int a = blockIdx.x;
     const T *src = r + (size_t)a * n_det;
     for (int i = threadIdx.x; i < n_det; i += kBlock) row[i] = (double)src[i];
@@ -76,9 +78,11 @@ __global__ __launch_bounds__(kBlock) void ncp_rows_kernel(const T *__restrict__ 
 }
 
 __global__ __launch_bounds__(kBlock) void ncp_mean_kernel(const double *__restrict__ crow, int n_ang,
-                                                          int q, double *__restrict__ partials)
+                                                          int q, double *__restrict__ partials,
+                                                          const DevState *st, int k)
 {
     __shared__ double lds[kBlock / 64];
+    if (halted(st, k)) return;
     const int j = blockIdx.x * kBlock + threadIdx.x;
     double d2 = 0.0;
     if (j < q) {
@@ -97,30 +101,45 @@ __global__ __launch_bounds__(kBlock) void ncp_mean_kernel(const double *__restri
     }
 }
 
-__global__ void ncp_final_kernel(const double *partials, int nb, double *dst)
+// d_k = sqrt(sum of partials); the NCP stop is raised at the first k >= 2 whose d_k
+// exceeds d_{k-1} (the iterate to return is then x_{k-1}).
+__global__ void ncp_final_kernel(const double *partials, int nb, DevState *st, int k)
 {
+    if (halted(st, k)) return;
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         double t = 0.0;
         for (int b = 0; b < nb; ++b) t += partials[b];
-        *dst = sqrt(t);
+        const double d = sqrt(t);
+        st->ncp = d;
+        if (!isfinite(d)) {
+            st->error |= 2;
+        } else if (k >= 2 && d > st->ncp_prev && !st->stop) {
+            st->stop = 1;
+            st->stop_k = k;
+            st->stop_reason = kStopNCP;
+        }
+        st->ncp_prev = d;
     }
 }
 
 template <typename T, int J>
-hipError_t rows_go(const Geometry &g, const void *r, double *crow, int q, hipStream_t s)
+hipError_t rows_go(const Geometry &g, const void *r, double *crow, int q, const DevState *st,
+                   int k, hipStream_t s)
 {
     const size_t lds = (size_t)g.n_det * sizeof(double);
-    ncp_rows_kernel<T, J><<<g.n_ang, kBlock, lds, s>>>(static_cast<const T *>(r), g.n_det, q, crow);
+    ncp_rows_kernel<T, J><<<g.n_ang, kBlock, lds, s>>>(static_cast<const T *>(r), g.n_det, q, crow,
+                                                       st, k);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t rows_dispatch(const Geometry &g, const void *r, double *crow, int q, hipStream_t s)
+hipError_t rows_dispatch(const Geometry &g, const void *r, double *crow, int q,
+                         const DevState *st, int k, hipStream_t s)
 {
-    if (q <= kBlock) return rows_go<T, 1>(g, r, crow, q, s);
-    if (q <= 2 * kBlock) return rows_go<T, 2>(g, r, crow, q, s);
-    if (q <= 4 * kBlock) return rows_go<T, 4>(g, r, crow, q, s);
-    if (q <= 8 * kBlock) return rows_go<T, 8>(g, r, crow, q, s);
+    if (q <= kBlock) return rows_go<T, 1>(g, r, crow, q, st, k, s);
+    if (q <= 2 * kBlock) return rows_go<T, 2>(g, r, crow, q, st, k, s);
+    if (q <= 4 * kBlock) return rows_go<T, 4>(g, r, crow, q, st, k, s);
+    if (q <= 8 * kBlock) return rows_go<T, 8>(g, r, crow, q, st, k, s);
     return hipErrorInvalidValue;
 }
 
@@ -133,19 +152,19 @@ size_t ncp_scratch_bytes(const Geometry &g)
     return align256((size_t)g.n_ang * q * sizeof(double)) + align256((nb + 1) * sizeof(double));
 }
 
-hipError_t launch_ncp(const Geometry &g, int t, const void *r, double *scratch, double *dst,
-                      hipStream_t s)
+hipError_t launch_ncp(const Geometry &g, int t, const void *r, double *scratch, DevState *st,
+                      int k, hipStream_t s)
 {
     const int q = g.n_det / 2;
     if (q < 1) return hipErrorInvalidValue;
     double *crow = scratch;
     double *part = scratch + align256((size_t)g.n_ang * q * sizeof(double)) / sizeof(double);
-    hipError_t e = t == ABG_F64 ? rows_dispatch<double>(g, r, crow, q, s)
-                                : rows_dispatch<float>(g, r, crow, q, s);
+    hipError_t e = t == ABG_F64 ? rows_dispatch<double>(g, r, crow, q, st, k, s)
+                                : rows_dispatch<float>(g, r, crow, q, st, k, s);
     if (e != hipSuccess) return e;
     const int nb = (q + kBlock - 1) / kBlock;
-    ncp_mean_kernel<<<nb, kBlock, 0, s>>>(crow, g.n_ang, q, part);
-    ncp_final_kernel<<<1, 64, 0, s>>>(part, nb, dst);
+    ncp_mean_kernel<<<nb, kBlock, 0, s>>>(crow, g.n_ang, q, part, st, k);
+    ncp_final_kernel<<<1, 64, 0, s>>>(part, nb, st, k);
     return hipGetLastError();
 }
 

@@ -55,9 +55,11 @@ __device__ inline int wave_max_i(int v)
 template <typename T>
 __global__ __launch_bounds__(256) void pad_transpose_kernel(const T *__restrict__ x,
                                                             T *__restrict__ xr,
-                                                            T *__restrict__ xc, int N, int S)
+                                                            T *__restrict__ xc, int N, int S,
+                                                            const DevState *st, int k)
 {
     __shared__ T tile[32][33];
+    if (halted(st, k)) return;
     const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
     for (int j = ty; j < 32; j += 8) {
@@ -78,13 +80,15 @@ __global__ __launch_bounds__(256) void pad_transpose_kernel(const T *__restrict_
 
 // Zeroes the kPad columns on both sides of the 2N padded rows of xr and xc.
 template <typename T>
-__global__ void pad_zero_kernel(T *__restrict__ xr, T *__restrict__ xc, int N, int S)
+__global__ void pad_zero_kernel(T *__restrict__ xr, T *__restrict__ xc, int N, int S,
+                                const DevState *st, int k)
 {
+    if (halted(st, k)) return;
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     const int per_row = 2 * kPad;
     if (idx >= 2 * N * per_row) return;
-    const int row = idx / per_row, k = idx % per_row;
-    const int col = k < kPad ? k : N + k;   // [0,kPad) and [N+kPad, N+2kPad)
+    const int row = idx / per_row, e = idx % per_row;
+    const int col = e < kPad ? e : N + e;   // [0,kPad) and [N+kPad, N+2kPad)
     T *base = row < N ? xr + (size_t)row * S : xc + (size_t)(row - N) * S;
     base[col] = T(0);
 }
@@ -149,8 +153,10 @@ __device__ inline Taps<T> load_taps(const T *row, unsigned col)
 template <typename T>
 __global__ __launch_bounds__(kFwdBlock) void forward_kernel(
     const T *__restrict__ xr, const T *__restrict__ xc, T *__restrict__ y,
-    const AngleParams *__restrict__ ang, int N, int S, int n_det, double ds, double s0)
+    const AngleParams *__restrict__ ang, int N, int S, int n_det, double ds, double s0,
+    const DevState *st, int k)
 {
+    if (halted(st, k)) return;
     const int a = blockIdx.y;
     const int i = blockIdx.x * kFwdBlock + threadIdx.x;
     const AngleParams P = ang[a];
@@ -297,9 +303,10 @@ __device__ inline T back_tap(const BinPair<T> *wrow, T u, const BackStage<T> &P,
 template <typename T, bool ADJ>
 __global__ __launch_bounds__(kBackThreads) void back_kernel(
     const T *__restrict__ y, T *__restrict__ x, const AngleParams *__restrict__ ang, int N,
-    int n_ang, int n_det, double ds, double s0)
+    int n_ang, int n_det, double ds, double s0, const DevState *st, int k)
 {
     __shared__ BinPair<T> win[kAngBlock][kWin];
+    if (halted(st, k)) return;
     __shared__ BackStage<T> prm[kAngBlock];
     __shared__ T part[kBackWaves - 1][kTile * kTile];
     const int lane = threadIdx.x & 63;
@@ -372,37 +379,41 @@ __global__ __launch_bounds__(kBackThreads) void back_kernel(
 }
 
 template <typename T>
-hipError_t forward_t(const Geometry &g, const void *x, void *y, void *ws, hipStream_t s)
+hipError_t forward_t(const Geometry &g, const void *x, void *y, void *ws, hipStream_t s,
+                     const DevState *st, int k)
 {
     const int N = g.N, S = g.padded_stride();
     T *xr = static_cast<T *>(ws);
     T *xc = xr + (size_t)N * S;
     dim3 tgrid((N + 31) / 32, (N + 31) / 32);
-    pad_transpose_kernel<T><<<tgrid, 256, 0, s>>>(static_cast<const T *>(x), xr, xc, N, S);
+    pad_transpose_kernel<T><<<tgrid, 256, 0, s>>>(static_cast<const T *>(x), xr, xc, N, S, st, k);
     const int npad = 2 * N * 2 * kPad;
-    pad_zero_kernel<T><<<(npad + 255) / 256, 256, 0, s>>>(xr, xc, N, S);
+    pad_zero_kernel<T><<<(npad + 255) / 256, 256, 0, s>>>(xr, xc, N, S, st, k);
     dim3 grid((g.n_det + kFwdBlock - 1) / kFwdBlock, g.n_ang);
     const double s0 = -0.5 * (g.n_det - 1) * g.ds;
     {
-        ProfScope ps(kProfFwd, s);
+        ProfScope ps(kProfFwd, s, st ? k : 0);
         forward_kernel<T><<<grid, kFwdBlock, 0, s>>>(xr, xc, static_cast<T *>(y), g.dev, N, S,
-                                                     g.n_det, g.ds, s0);
+                                                     g.n_det, g.ds, s0, st, k);
     }
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t back_t(const Geometry &g, int kind, const void *y, void *x, hipStream_t s)
+hipError_t back_t(const Geometry &g, int kind, const void *y, void *x, hipStream_t s,
+                  const DevState *st, int k)
 {
     dim3 grid((g.N + kTile - 1) / kTile, (g.N + kTile - 1) / kTile);
     const double s0 = -0.5 * (g.n_det - 1) * g.ds;
-    ProfScope ps(kProfBack, s);
+    ProfScope ps(kProfBack, s, st ? k : 0);
     if (kind == ABG_BP_ADJ)
         back_kernel<T, true><<<grid, kBackThreads, 0, s>>>(
-            static_cast<const T *>(y), static_cast<T *>(x), g.dev, g.N, g.n_ang, g.n_det, g.ds, s0);
+            static_cast<const T *>(y), static_cast<T *>(x), g.dev, g.N, g.n_ang, g.n_det, g.ds, s0,
+            st, k);
     else
         back_kernel<T, false><<<grid, kBackThreads, 0, s>>>(
-            static_cast<const T *>(y), static_cast<T *>(x), g.dev, g.N, g.n_ang, g.n_det, g.ds, s0);
+            static_cast<const T *>(y), static_cast<T *>(x), g.dev, g.N, g.n_ang, g.n_det, g.ds, s0,
+            st, k);
     return hipGetLastError();
 }
 
@@ -414,15 +425,17 @@ size_t fp_workspace_bytes(const Geometry &g, int dtype)
 }
 
 hipError_t launch_forward(const Geometry &g, int dtype, const void *x, void *y, void *ws,
-                          hipStream_t s)
+                          hipStream_t s, const DevState *st, int k)
 {
-    return dtype == ABG_F64 ? forward_t<double>(g, x, y, ws, s) : forward_t<float>(g, x, y, ws, s);
+    return dtype == ABG_F64 ? forward_t<double>(g, x, y, ws, s, st, k)
+                            : forward_t<float>(g, x, y, ws, s, st, k);
 }
 
 hipError_t launch_back(const Geometry &g, int kind, int dtype, const void *y, void *x,
-                       hipStream_t s)
+                       hipStream_t s, const DevState *st, int k)
 {
-    return dtype == ABG_F64 ? back_t<double>(g, kind, y, x, s) : back_t<float>(g, kind, y, x, s);
+    return dtype == ABG_F64 ? back_t<double>(g, kind, y, x, s, st, k)
+                            : back_t<float>(g, kind, y, x, s, st, k);
 }
 
 }  // namespace abg

@@ -1,12 +1,18 @@
 // AB-GMRES and BA-GMRES drivers (Sec. 2) with discrepancy-principle and NCP stopping
-// (Sec. 6.3). The host thread only sequences kernels and reads back a few scalars per
-// Arnoldi step; every vector operation runs in the kernels of this library.
+// (Sec. 6.3). The host thread sequences kernels; every vector operation runs in the
+// kernels of this library.
 //
-// Per step k (BA):  z = A w_k (kept as column k of Z when a stopping rule needs the
-// residual), q = B z, MGS, Givens, then r_k = (b - A x_0) - Z y_k.
-// Per step k (AB):  t = B w_k, q = A t, MGS, Givens, then r_k = W_{k+1}(||r_0|| e_1 - H_k y_k).
+// Step k (BA):  z = A w_k (column k of Z when a stopping rule needs the residual),
+//               q = B z, MGS, Givens, then r_k = (b - A x_0) - Z y_k.
+// Step k (AB):  t = B w_k, q = A t, MGS, Givens, then r_k = W_{k+1}(||r_0|| e_1 - H_k y_k).
 // Both residual forms equal b - A x_k by linearity and the Arnoldi relation; the
 // discrepancy principle confirms a candidate stop with the explicit b - A x_k.
+//
+// Pipelining: the host enqueues step k+1 before it waits for step k's scalars. Stops are
+// decided on the device by the last kernel of a step (DP candidate, NCP increase) or by
+// MGS (breakdown); the kernels of every later step then return at entry, so a step that
+// was enqueued past the stop costs only its launches. y_k is kept for every k, so the
+// iterate of any step can be formed afterwards.
 #include <cmath>
 #include <cstring>
 
@@ -16,8 +22,8 @@ namespace abg {
 namespace {
 
 struct Layout {
-    size_t V, Z, cur, q, rb0, tm, tn, fpws, H, R, cs, sn, g, y, yprev, ybest, rho;
-    size_t part, mgs_part, bar, st, ncp, total;
+    size_t V, Z, cur, q, rb0, tm, tn, fpws, H, R, cs, sn, g, Y, rho;
+    size_t part, mgs_part, bar, count, st, ncp, total;
     long long L, ldv, mp, np;
 };
 
@@ -52,26 +58,59 @@ Layout make_layout(const Geometry &g, int method, int k_max, abg_precision p, ab
     ly.cs = take((size_t)k_max * 8);
     ly.sn = take((size_t)k_max * 8);
     ly.g = take(ld * 8);
-    ly.y = take(ld * 8);
-    ly.yprev = take(ld * 8);
-    ly.ybest = take(ld * 8);
+    ly.Y = take((size_t)k_max * k_max * 8);
     ly.rho = take((ld + 1) * 8);
     ly.part = take(2048 * 8);
     ly.mgs_part = take(4 * (size_t)kMaxGrid * 8);
     ly.bar = take((ld + 2) * 4);
+    ly.count = take(64);
     ly.st = take(sizeof(DevState));
     ly.ncp = st.kind == ABG_STOP_NCP ? take(ncp_scratch_bytes(g)) : 0;
     ly.total = off;
     return ly;
 }
 
-struct HostState {
-    DevState *h = nullptr;
-    ~HostState()
-    {
-        if (h) (void)hipHostFree(h);
-    }
+constexpr int kRing = 4;
+
+// Pinned scalar slots and step events, cached per host thread (allocating pinned memory
+// and events on every call costs more than a short solve). They are kept until the
+// process ends.
+struct HostRes {
+    DevState *slots = nullptr;
+    int capacity = 0;
+    int device = -1;
+    hipEvent_t ev[kRing] = {};
 };
+
+hipError_t host_resources(HostRes &h, int k_max)
+{
+    thread_local HostRes cache;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (cache.device != dev) {
+        for (auto &ev : cache.ev) ev = nullptr;   // events of another device are left alone
+        for (auto &ev : cache.ev) {
+            e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+            if (e != hipSuccess) return e;
+        }
+        cache.slots = nullptr;
+        cache.capacity = 0;
+        cache.device = dev;
+    }
+    if (cache.capacity < k_max + 1) {
+        if (cache.slots) (void)hipHostFree(cache.slots);
+        cache.slots = nullptr;
+        e = hipHostMalloc((void **)&cache.slots, sizeof(DevState) * (k_max + 1), hipHostMallocDefault);
+        if (e != hipSuccess) {
+            cache.capacity = 0;
+            return e;
+        }
+        cache.capacity = k_max + 1;
+    }
+    h = cache;
+    return hipSuccess;
+}
 
 #define CK(expr)                                   \
     do {                                           \
@@ -79,26 +118,35 @@ struct HostState {
         if (e_ != hipSuccess) return ABG_EHIP;     \
     } while (0)
 
+#define RC(expr)                                   \
+    do {                                           \
+        int r_ = (expr);                           \
+        if (r_ != ABG_OK) return r_;               \
+    } while (0)
+
 struct Solve {
     const Geometry &g;
-    int method, kind, k_max;
+    int method, kind, k_max, ld;
     abg_stop st;
     abg_precision p;
     hipStream_t s;
     Layout ly;
     char *W;
-    // views
     void *V, *Z, *cur, *q, *rb0, *tm, *tn, *fpws;
-    double *H, *R, *cs, *sn, *gv, *y, *yprev, *ybest, *rho, *part, *mgs_part;
-    unsigned *bar;
+    double *H, *R, *cs, *sn, *gv, *Y, *rho, *part, *mgs_part;
+    unsigned *bar, *count;
     DevState *dst;
     double *ncp;
-    HostState hs;
+    HostRes hr;
     size_t sX;
+    bool need_res;
+    double bd_rel;
+    double beta = 0.0;   // ||r_0||, known after the initial normalisation
 
     Solve(const Geometry &g_, int method_, int kind_, int k_max_, abg_stop st_,
           abg_precision p_, hipStream_t s_, void *ws)
-        : g(g_), method(method_), kind(kind_), k_max(k_max_), st(st_), p(p_), s(s_)
+        : g(g_), method(method_), kind(kind_), k_max(k_max_), ld(k_max_ + 1), st(st_), p(p_),
+          s(s_)
     {
         ly = make_layout(g, method, k_max, p, st);
         W = static_cast<char *>(ws);
@@ -115,63 +163,121 @@ struct Solve {
         cs = reinterpret_cast<double *>(W + ly.cs);
         sn = reinterpret_cast<double *>(W + ly.sn);
         gv = reinterpret_cast<double *>(W + ly.g);
-        y = reinterpret_cast<double *>(W + ly.y);
-        yprev = reinterpret_cast<double *>(W + ly.yprev);
-        ybest = reinterpret_cast<double *>(W + ly.ybest);
+        Y = reinterpret_cast<double *>(W + ly.Y);
         rho = reinterpret_cast<double *>(W + ly.rho);
         part = reinterpret_cast<double *>(W + ly.part);
         mgs_part = reinterpret_cast<double *>(W + ly.mgs_part);
         bar = reinterpret_cast<unsigned *>(W + ly.bar);
+        count = reinterpret_cast<unsigned *>(W + ly.count);
         dst = reinterpret_cast<DevState *>(W + ly.st);
         ncp = ly.ncp ? reinterpret_cast<double *>(W + ly.ncp) : nullptr;
         sX = dtype_size(p.proj);
+        need_res = st.kind != ABG_STOP_NONE;
+        bd_rel = (p.basis == ABG_F64 && p.proj == ABG_F64) ? 1e-14 : 1e-6;
     }
 
     char *vec(int i) const { return static_cast<char *>(V) + (size_t)i * ly.ldv * dtype_size(p.basis); }
     char *zcol(int i) const { return static_cast<char *>(Z) + (size_t)i * ly.mp * sX; }
+    double *ycol(int k) const { return Y + (size_t)(k - 1) * k_max; }
 
-    int sync_state(DevState &out)
+    int fwd(const void *x, void *yv, const DevState *sst = nullptr, int k = 0)
     {
-        CK(hipMemcpyAsync(hs.h, dst, sizeof(DevState), hipMemcpyDeviceToHost, s));
+        CK(launch_forward(g, p.proj, x, yv, fpws, s, sst, k));
+        return ABG_OK;
+    }
+    int back(const void *yv, void *x, const DevState *sst = nullptr, int k = 0)
+    {
+        CK(launch_back(g, kind, p.proj, yv, x, s, sst, k));
+        return ABG_OK;
+    }
+
+    MgsLaunch mgs_args(const void *qin, int k) const
+    {
+        MgsLaunch M{};
+        M.tx = p.proj;
+        M.tv = p.basis;
+        M.V = V;
+        M.ldv = (size_t)ly.ldv;
+        M.L = ly.L;
+        M.partials = mgs_part;
+        M.st = dst;
+        M.bd_rel = bd_rel;
+        M.q = qin;
+        M.k = k;
+        M.step = k;
+        M.hcol = k == 0 ? gv : H + (size_t)(k - 1) * ld;
+        M.vout = vec(k);
+        M.cur = cur;
+        M.bar = bar + k;
+        return M;
+    }
+
+    // All kernels of Arnoldi step k, then a copy of the scalars into slot k.
+    int enqueue_step(int k)
+    {
+        if (method == ABG_METHOD_BA) {
+            void *z = Z ? zcol(k - 1) : tm;
+            RC(fwd(cur, z, dst, k));
+            RC(back(z, q, dst, k));
+        } else {
+            RC(back(cur, tn, dst, k));
+            RC(fwd(tn, q, dst, k));
+        }
+        CK(launch_mgs(mgs_args(q, k), s));
+        CK(launch_givens(H, ld, R, cs, sn, gv, ycol(k),
+                         (method == ABG_METHOD_AB && need_res) ? rho : nullptr, beta, k, dst, s));
+        if (need_res) {
+            if (method == ABG_METHOD_BA)
+                CK(launch_combine(p.proj, rb0, 1.0, p.proj, Z, ly.mp, k, ycol(k), -1.0, tm, g.m(),
+                                  part, count, &dst->res, dst, k, s));
+            else
+                CK(launch_combine(p.proj, nullptr, 0.0, p.basis, V, ly.ldv, k + 1, rho, 1.0, tm,
+                                  g.m(), part, count, &dst->res, dst, k, s));
+            if (st.kind == ABG_STOP_NCP) CK(launch_ncp(g, p.proj, tm, ncp, dst, k, s));
+        }
+        CK(hipMemcpyAsync(&hr.slots[k], dst, sizeof(DevState), hipMemcpyDeviceToHost, s));
+        CK(hipEventRecord(hr.ev[k % kRing], s));
+        return ABG_OK;
+    }
+
+    int wait_step(int k, DevState &out)
+    {
+        CK(hipEventSynchronize(hr.ev[k % kRing]));
+        out = hr.slots[k];
+        return ABG_OK;
+    }
+
+    int sync_read(DevState &out)
+    {
+        CK(hipMemcpyAsync(&hr.slots[0], dst, sizeof(DevState), hipMemcpyDeviceToHost, s));
         CK(hipStreamSynchronize(s));
-        out = *hs.h;
+        out = hr.slots[0];
         return ABG_OK;
     }
 
-    int fwd(const void *x, void *yv) { CK(launch_forward(g, p.proj, x, yv, fpws, s)); return ABG_OK; }
-    int back(const void *yv, void *x) { CK(launch_back(g, kind, p.proj, yv, x, s)); return ABG_OK; }
-
-    // norm of (a - b) into dst->res; result vector in out
-    int sub_norm(const void *a, const void *b, void *out, long long L)
-    {
-        int nb = 0;
-        CK(launch_sub_norm(p.proj, a, b, out, L, part, &nb, s));
-        CK(launch_reduce_sqrt(part, nb, &dst->res, s));
-        return ABG_OK;
-    }
-
-    // x = x0 + (BA) W[0..kk) c   or   x = x0 + B (W[0..kk) c)  (AB)
+    // x = x0 + W[0..kk) c (BA)  or  x = x0 + B (W[0..kk) c)  (AB)
     int build_x(const double *c, int kk, const void *x0, void *x)
     {
         if (method == ABG_METHOD_BA) {
             CK(launch_combine(p.proj, x0, x0 ? 1.0 : 0.0, p.basis, V, ly.ldv, kk, c, 1.0, x,
-                              g.n(), nullptr, nullptr, nullptr, s));
+                              g.n(), nullptr, nullptr, nullptr, nullptr, 0, s));
         } else {
             CK(launch_combine(p.proj, nullptr, 0.0, p.basis, V, ly.ldv, kk, c, 1.0, tm, g.m(),
-                              nullptr, nullptr, nullptr, s));
-            int rc = back(tm, x);
-            if (rc) return rc;
+                              nullptr, nullptr, nullptr, nullptr, 0, s));
+            RC(back(tm, x));
             if (x0) CK(launch_axpy_inplace(p.proj, x, x0, g.n(), s));
         }
         return ABG_OK;
     }
 
-    // explicit ||b - A x|| into dst->res (uses tm)
+    // ||b - A x|| into dst->res (uses tm); caller synchronises
     int literal_residual(const void *b, const void *x)
     {
-        int rc = fwd(x, tm);
-        if (rc) return rc;
-        return sub_norm(b, tm, tm, g.m());
+        RC(fwd(x, tm));
+        int nb = 0;
+        CK(launch_sub_norm(p.proj, b, tm, tm, g.m(), part, &nb, s));
+        CK(launch_reduce_sqrt(part, nb, &dst->res, s));
+        return ABG_OK;
     }
 };
 
@@ -194,180 +300,144 @@ int run_solver(const Geometry &g, int method, int kind, const void *b, const voi
 {
     Solve S(g, method, kind, k_max, st, p, s, ws);
     if (ws_bytes < S.ly.total) return ABG_ENOMEM;
-    CK(hipHostMalloc((void **)&S.hs.h, sizeof(DevState), hipHostMallocDefault));
-    const long long m = g.m(), n = g.n(), L = S.ly.L;
-    const int ld = k_max + 1;
-    const bool need_res = st.kind != ABG_STOP_NONE;
+    CK(host_resources(S.hr, k_max));
+    // launches of steps enqueued past the stop are left out of the launch timing
+    struct ProfSolve {
+        int last = 0;
+        bool done = false;
+        ProfSolve() { profile_solve_begin(); }
+        void finish()
+        {
+            if (!done) profile_solve_end(last);
+            done = true;
+        }
+        ~ProfSolve() { finish(); }
+    } prof;
+    const long long m = g.m(), n = g.n();
     const double thr = st.kind == ABG_STOP_DP ? st.tau * st.noise_norm : 0.0;
-    const double bd_rel = p.basis == ABG_F64 && p.proj == ABG_F64 ? 1e-14 : 1e-6;
     int k_stop = 0, k_done = 0, status = ABG_OK, n_literal = 0;
     double res_final = 0.0, ncp_final = 0.0;
     auto hist = [&](double *arr, int k, double v) {
         if (info && arr && k - 1 < info->hist_len) arr[k - 1] = v;
     };
 
-    // small state to zero
-    CK(launch_fill_u32(S.bar, (size_t)ld + 2, 0u, s));
-    CK(launch_fill_u32(reinterpret_cast<unsigned *>(S.dst), sizeof(DevState) / 4, 0u, s));
-    CK(launch_fill_f64(S.H, (size_t)ld * k_max, 0.0, s));
-    CK(launch_fill_f64(S.gv, (size_t)ld, 0.0, s));
+    // device scalars: zero, with the DP candidate threshold
+    DevState init{};
+    init.dp_thr = st.kind == ABG_STOP_DP ? thr * (1.0 + dp_slack(p.basis)) : 0.0;
+    S.hr.slots[0] = init;
+    CK(hipMemcpyAsync(S.dst, &S.hr.slots[0], sizeof(DevState), hipMemcpyHostToDevice, s));
+    CK(launch_fill_u32(S.bar, (size_t)S.ld + 2, 0u, s));
+    CK(launch_fill_u32(S.count, 16, 0u, s));
+    CK(launch_fill_f64(S.H, (size_t)S.ld * k_max, 0.0, s));
+    CK(launch_fill_f64(S.gv, (size_t)S.ld, 0.0, s));
 
-    // b - A x0, r0, beta, w1
-    int rc;
+    // b - A x0, r0 = (B)(b - A x0), beta = ||r0|| into g[0], w_1
     if (x0) {
-        if ((rc = S.fwd(x0, S.tm))) return rc;
-        if ((rc = S.sub_norm(b, S.tm, S.rb0, m))) return rc;
+        RC(S.fwd(x0, S.tm));
+        int nb = 0;
+        CK(launch_sub_norm(p.proj, b, S.tm, S.rb0, m, S.part, &nb, s));
     } else {
         CK(hipMemcpyAsync(S.rb0, b, (size_t)m * S.sX, hipMemcpyDeviceToDevice, s));
     }
     const void *r0 = S.rb0;
     if (method == ABG_METHOD_BA) {
-        if ((rc = S.back(S.rb0, S.q))) return rc;
+        RC(S.back(S.rb0, S.q));
         r0 = S.q;
     }
-    MgsLaunch M{};
-    M.tx = p.proj;
-    M.tv = p.basis;
-    M.V = S.V;
-    M.ldv = (size_t)S.ly.ldv;
-    M.L = L;
-    M.partials = S.mgs_part;
-    M.st = S.dst;
-    M.bd_rel = bd_rel;
-    M.q = r0;
-    M.k = 0;
-    M.hcol = S.gv;          // g[0] = beta
-    M.vout = S.vec(0);
-    M.cur = S.cur;
-    M.bar = S.bar + 0;
-    CK(launch_mgs(M, s));
+    CK(launch_mgs(S.mgs_args(r0, 0), s));
     DevState hs;
-    if ((rc = S.sync_state(hs))) return rc;
+    RC(S.sync_read(hs));
     if (hs.error & 1) return ABG_EDEVICE;
     const double beta = hs.hnext;
-    if (!std::isfinite(beta)) return ABG_ENAN;
+    if (!std::isfinite(beta) || (hs.error & 2)) return ABG_ENAN;
     if (info) info->beta = beta;
+    S.beta = beta;
     if (beta == 0.0) {
         if (x0) CK(hipMemcpyAsync(x, x0, (size_t)n * S.sX, hipMemcpyDeviceToDevice, s));
-        else CK(launch_combine(p.proj, nullptr, 0.0, p.basis, S.V, S.ly.ldv, 0, S.y, 1.0, x, n,
-                               nullptr, nullptr, nullptr, s));
-        status = ABG_ZERO_RHS;
-        if ((rc = S.literal_residual(b, x))) return rc;
-        if ((rc = S.sync_state(hs))) return rc;
+        else CK(launch_combine(p.proj, nullptr, 0.0, p.basis, S.V, S.ly.ldv, 0, S.Y, 1.0, x, n,
+                               nullptr, nullptr, nullptr, nullptr, 0, s));
+        RC(S.literal_residual(b, x));
+        RC(S.sync_read(hs));
         res_final = hs.res;
-        goto done;
-    }
-
-    {
-        double ncp_prev = 0.0, ncp_best = INFINITY;
+        status = ABG_ZERO_RHS;
+    } else {
+        double ncp_best = INFINITY, ncp_prev = 0.0;
         int best_k = 0;
-        bool finished = false;
-        for (int k = 1; k <= k_max && !finished; ++k) {
-            // q_k = AB w_k or BA w_k
-            if (method == ABG_METHOD_BA) {
-                void *z = S.Z ? S.zcol(k - 1) : S.tm;
-                if ((rc = S.fwd(S.cur, z))) return rc;
-                if ((rc = S.back(z, S.q))) return rc;
-            } else {
-                if ((rc = S.back(S.cur, S.tn))) return rc;
-                if ((rc = S.fwd(S.tn, S.q))) return rc;
-            }
-            M.q = S.q;
-            M.k = k;
-            M.hcol = S.H + (size_t)(k - 1) * ld;
-            M.vout = S.vec(k);
-            M.bar = S.bar + k;
-            CK(launch_mgs(M, s));
-            if (st.kind == ABG_STOP_NCP && k > 1)
-                CK(hipMemcpyAsync(S.yprev, S.y, (size_t)(k - 1) * 8, hipMemcpyDeviceToDevice, s));
-            CK(launch_givens(S.H, ld, S.R, S.cs, S.sn, S.gv, S.y,
-                             (method == ABG_METHOD_AB && need_res) ? S.rho : nullptr, beta, k, 1,
-                             S.dst, s));
-            if (need_res) {
-                int nb = 0;
-                if (method == ABG_METHOD_BA)
-                    CK(launch_combine(p.proj, S.rb0, 1.0, p.proj, S.Z, S.ly.mp, k, S.y, -1.0, S.tm,
-                                      m, S.part, &nb, S.dst, s));
-                else
-                    CK(launch_combine(p.proj, nullptr, 0.0, p.basis, S.V, S.ly.ldv, k + 1, S.rho,
-                                      1.0, S.tm, m, S.part, &nb, S.dst, s));
-                CK(launch_reduce_sqrt(S.part, nb, &S.dst->res, s));
-                if (st.kind == ABG_STOP_NCP) CK(launch_ncp(g, p.proj, S.tm, S.ncp, &S.dst->ncp, s));
-            }
-            if ((rc = S.sync_state(hs))) return rc;
-            if (hs.error & 1) return ABG_EDEVICE;
-            if ((hs.error & 2) || !std::isfinite(hs.ls)) return ABG_ENAN;
-            if (hs.error & 4) return ABG_ENAN;
+        int k_sel = 0;        // step whose iterate is returned
+        bool x_built = false; // x already holds x_{k_sel}
+        RC(S.enqueue_step(1));
+        for (int k = 1; k <= k_max && k_sel == 0; ++k) {
+            if (k < k_max) RC(S.enqueue_step(k + 1));
+            DevState sk;
+            RC(S.wait_step(k, sk));
+            if (sk.error & 1) return ABG_EDEVICE;
+            if (sk.error) return ABG_ENAN;
             k_done = k;
-            hist(info ? info->ls_hist : nullptr, k, hs.ls);
-            const bool breakdown = hs.breakdown != 0;
+            prof.last = k;
+            hist(info ? info->ls_hist : nullptr, k, sk.ls);
+            const bool stop_here = sk.stop && sk.stop_k == k;
             if (st.kind == ABG_STOP_DP) {
-                double rk = hs.res;
-                if (!std::isfinite(rk)) return ABG_ENAN;
-                if (rk <= thr * (1.0 + dp_slack(p.basis))) {
-                    // confirm with the explicit residual of x_k
-                    if ((rc = S.build_x(S.y, k, x0, x))) return rc;
-                    if ((rc = S.literal_residual(b, x))) return rc;
+                double rk = sk.res;
+                if (stop_here) {
+                    // candidate: confirm with the explicit residual of x_k
+                    RC(S.build_x(S.ycol(k), k, x0, x));
+                    RC(S.literal_residual(b, x));
                     DevState h2;
-                    if ((rc = S.sync_state(h2))) return rc;
+                    RC(S.sync_read(h2));
                     ++n_literal;
                     rk = h2.res;
                     if (rk <= thr) {
-                        hist(info ? info->res_hist : nullptr, k, rk);
-                        k_stop = k;
-                        status = ABG_OK;
-                        res_final = rk;
-                        finished = true;
-                        break;
+                        k_sel = k;
+                        x_built = true;
+                    } else {
+                        // rejected: resume; step k+1 was skipped, run it again
+                        CK(launch_clear_stop(S.dst, s));
+                        if (k < k_max) {
+                            profile_drop_step(k + 1);
+                            RC(S.enqueue_step(k + 1));
+                        }
                     }
                 }
                 hist(info ? info->res_hist : nullptr, k, rk);
             } else if (st.kind == ABG_STOP_NCP) {
-                hist(info ? info->res_hist : nullptr, k, hs.res);
-                hist(info ? info->ncp_hist : nullptr, k, hs.ncp);
-                if (k >= 2 && hs.ncp > ncp_prev) {
-                    if ((rc = S.build_x(S.yprev, k - 1, x0, x))) return rc;
-                    k_stop = k - 1;
+                hist(info ? info->res_hist : nullptr, k, sk.res);
+                hist(info ? info->ncp_hist : nullptr, k, sk.ncp);
+                if (stop_here) {
+                    k_sel = k - 1;   // d_k > d_{k-1}: x_{k-1} was closest to white noise
                     ncp_final = ncp_prev;
-                    status = ABG_OK;
-                    finished = true;
                     break;
                 }
-                if (hs.ncp < ncp_best) {
-                    ncp_best = hs.ncp;
+                if (sk.ncp < ncp_best) {
+                    ncp_best = sk.ncp;
                     best_k = k;
-                    CK(hipMemcpyAsync(S.ybest, S.y, (size_t)k * 8, hipMemcpyDeviceToDevice, s));
                 }
-                ncp_prev = hs.ncp;
+                ncp_prev = sk.ncp;
             }
-            if (breakdown) {
-                if ((rc = S.build_x(S.y, k, x0, x))) return rc;
-                k_stop = k;
+            if (k_sel) break;
+            if (sk.bd_k == k) {
+                k_sel = k;
                 status = ABG_BREAKDOWN;
-                finished = true;
                 break;
             }
             if (k == k_max) {
                 if (st.kind == ABG_STOP_NCP) {
-                    if ((rc = S.build_x(S.ybest, best_k, x0, x))) return rc;
-                    k_stop = best_k;
+                    k_sel = best_k;
                     ncp_final = ncp_best;
                 } else {
-                    if ((rc = S.build_x(S.y, k, x0, x))) return rc;
-                    k_stop = k;
+                    k_sel = k;
                     status = st.kind == ABG_STOP_DP ? ABG_NOT_CONVERGED : ABG_OK;
                 }
-                finished = true;
             }
         }
+        k_stop = k_sel;
+        if (!x_built) RC(S.build_x(S.ycol(k_sel), k_sel, x0, x));
         // explicit residual of the returned iterate; a NaN/Inf anywhere in b shows here
-        if ((rc = S.literal_residual(b, x))) return rc;
-        if ((rc = S.sync_state(hs))) return rc;
+        RC(S.literal_residual(b, x));
+        RC(S.sync_read(hs));
         res_final = hs.res;
         if (!std::isfinite(res_final)) return ABG_ENAN;
     }
 
-done:
     if (info) {
         info->k_stop = k_stop;
         info->k_done = k_done;
@@ -376,10 +446,11 @@ done:
         info->res_norm = res_final;
         info->ncp_dist = ncp_final;
         if (info->H && k_done > 0) {
-            CK(hipMemcpyAsync(info->H, S.H, (size_t)ld * k_max * 8, hipMemcpyDeviceToHost, s));
+            CK(hipMemcpyAsync(info->H, S.H, (size_t)S.ld * k_max * 8, hipMemcpyDeviceToHost, s));
             CK(hipStreamSynchronize(s));
         }
     }
+    prof.finish();
     if (profiling_on()) profile_flush();
     return status;
 }
