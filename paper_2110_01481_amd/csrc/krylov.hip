@@ -22,6 +22,7 @@ constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
 constexpr unsigned kSpinLimit = 1u << 22;
 constexpr int kMaxCoef = 512;
+constexpr int kCombU = 4;
 
 // ---- element access ------------------------------------------------------------------
 __device__ inline double to_f64(double v) { return v; }
@@ -309,25 +310,33 @@ __global__ __launch_bounds__(kBlock) void combine_kernel(const TB *__restrict__ 
     if (halted(st, k)) return;
     for (int j = threadIdx.x; j < kk; j += kBlock) cf[j] = sgn * coef[j];
     __syncthreads();
+    // each thread combines kCombU elements per trip, all of a column's loads in flight
     const long long T = (long long)gridDim.x * kBlock;
     double ss = 0.0;
-    for (long long l = (long long)blockIdx.x * kBlock + threadIdx.x; l < L; l += T) {
-        double acc = base ? bcoef * to_f64(base[l]) : 0.0;
-        const TV *v = V + l;
-        int j = 0;
-        for (; j + 4 <= kk; j += 4) {
-            const double v0 = to_f64(v[(size_t)(j + 0) * ldv]);
-            const double v1 = to_f64(v[(size_t)(j + 1) * ldv]);
-            const double v2 = to_f64(v[(size_t)(j + 2) * ldv]);
-            const double v3 = to_f64(v[(size_t)(j + 3) * ldv]);
-            acc = fma(cf[j + 0], v0, acc);
-            acc = fma(cf[j + 1], v1, acc);
-            acc = fma(cf[j + 2], v2, acc);
-            acc = fma(cf[j + 3], v3, acc);
+    for (long long l0 = (long long)blockIdx.x * kBlock + threadIdx.x; l0 < L; l0 += kCombU * T) {
+        double acc[kCombU];
+        bool in[kCombU];
+#pragma unroll
+        for (int u = 0; u < kCombU; ++u) {
+            const long long l = l0 + u * T;
+            in[u] = l < L;
+            acc[u] = (in[u] && base) ? bcoef * to_f64(base[l]) : 0.0;
         }
-        for (; j < kk; ++j) acc = fma(cf[j], to_f64(v[(size_t)j * ldv]), acc);
-        out[l] = (TO)acc;
-        ss = fma(acc, acc, ss);
+        for (int j = 0; j < kk; ++j) {
+            const TV *v = V + (size_t)j * ldv + l0;
+            double x[kCombU];
+#pragma unroll
+            for (int u = 0; u < kCombU; ++u) x[u] = in[u] ? to_f64(v[u * T]) : 0.0;
+#pragma unroll
+            for (int u = 0; u < kCombU; ++u) acc[u] = fma(cf[j], x[u], acc[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < kCombU; ++u) {
+            if (in[u]) {
+                out[l0 + u * T] = (TO)acc[u];
+                ss = fma(acc[u], acc[u], ss);
+            }
+        }
     }
     if (!norm) return;
     // fixed-order norm: per-block partials, summed by the last block to finish
@@ -487,8 +496,8 @@ hipError_t combine_go(const void *base, double bcoef, const void *V, size_t ldv,
                       const double *coef, double sgn, void *out, long long L, double *partials,
                       unsigned *count, double *norm, DevState *st, int k, hipStream_t s)
 {
-    // with a norm, every block signals completion on one counter: keep the grid small
-    const int nb = blocks_for(L, norm ? 160 : 1024);
+    // with a norm, every block signals completion on one counter: keep the grid moderate
+    const int nb = blocks_for((L + kCombU - 1) / kCombU, norm ? 512 : 1024);
     combine_kernel<TO, TB, TV><<<nb, kBlock, 0, s>>>(
         static_cast<const TB *>(base), bcoef, static_cast<const TV *>(V), ldv, kk, coef, sgn,
         static_cast<TO *>(out), L, partials, count, norm, st, k);

@@ -215,3 +215,45 @@ def test_not_converged_and_errors(gpu_lib, cfg1):
     assert e.value.code == -4
     with pytest.raises(abg.AbgError):
         abg.gmres("ab", gg, bt, 5, stop="dp", tau=0.5, noise_norm=enorm)
+
+
+def _fingerprint_errors(x, fp):
+    """Relative errors of a GPU iterate against the oracle's stored fingerprint."""
+    rng = np.random.default_rng(99)
+    pix = np.asarray(fp["pixels"])
+    rng.choice(x.size, size=min(len(pix), x.size), replace=False)   # same stream as the writer
+    probes = [rng.standard_normal(x.size) for _ in range(len(fp["probe_dots"]))]
+    e_norm = abs(np.linalg.norm(x) - fp["norm"]) / fp["norm"]
+    e_pix = np.linalg.norm(x[pix] - np.asarray(fp["values"])) / np.linalg.norm(fp["values"])
+    e_dot = max(abs(v @ x - d) / (np.linalg.norm(v) * fp["norm"]) for v, d in zip(probes, fp["probe_dots"]))
+    return e_norm, e_pix, e_dot
+
+
+@pytest.mark.parametrize("solve", ["ab-hat", "ab-adj", "ba-hat", "ba-adj"])
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+def test_full_size_discrepancy_principle(gpu_lib, solve, dt):
+    """512^2 image, 720 x 725 sinogram, DP with tau = 1.02: the GPU stops at the oracle's
+    k and its iterate matches the oracle's (stored fingerprint written by
+    tests/golden/make_oracle_golden.py) within 1e-4."""
+    import json
+    import os
+    import torch
+    import paper_2110_01481_amd as abg
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "oracle_config2.json")))
+    ref = gold["solves"][solve]
+    w = W.CONFIG2
+    go = O.Geometry(w.N, w.n_ang, w.n_det)
+    b, enorm = W.add_noise(go.A(w.phantom()), w.eta, w.noise_dir())
+    assert abs(enorm - gold["noise_norm"]) <= 1e-9 * enorm
+    gg = abg.Geometry(w.N, w.n_ang, w.n_det)
+    method, kind = solve.split("-")
+    tdt = torch.float64 if dt == "f64" else torch.float32
+    r = abg.gmres(method, gg, torch.tensor(b, dtype=tdt, device="cuda"), w.k_max, stop="dp",
+                  tau=w.tau, noise_norm=enorm, bp=kind)
+    assert r.status == "ok" and r.k_stop == ref["k_stop"], (r.k_stop, ref["k_stop"])
+    margin = ref["dp_margin"][ref["k_stop"] - 1]
+    print(f"{solve} {dt}: k={r.k_stop}, DP margin at stop {margin:.2e}, n_literal={r.n_literal}")
+    e = _fingerprint_errors(r.x.double().cpu().numpy(), ref["x"])
+    print(f"  iterate errors vs oracle: norm {e[0]:.2e} pixels {e[1]:.2e} probes {e[2]:.2e}")
+    assert max(e) <= 1e-4, e
+    assert abs(r.res_norm - ref["res_norms"][ref["k_stop"] - 1]) <= 1e-5 * ref["res_norms"][0]
