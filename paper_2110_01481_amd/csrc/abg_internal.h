@@ -59,8 +59,10 @@ inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 size_t fp_workspace_bytes(const Geometry &g, int dtype);
 // `st`/`k`: when st is given, the launch is part of Arnoldi step k and returns at once
 // if the solve is halted.
+// `pads_zero`: the caller guarantees that the padding columns of ws are already zero.
 hipError_t launch_forward(const Geometry &g, int dtype, const void *x, void *y, void *ws,
-                          hipStream_t s, const DevState *st = nullptr, int k = 0);
+                          hipStream_t s, const DevState *st = nullptr, int k = 0,
+                          bool pads_zero = false);
 hipError_t launch_back(const Geometry &g, int kind, int dtype, const void *y, void *x,
                        hipStream_t s, const DevState *st = nullptr, int k = 0);
 
@@ -83,7 +85,8 @@ struct DevState {
     int stop;            // raised by the last kernel of a step: later steps return at entry
     int stop_k;          // step that raised it
     int stop_reason;     // kStop*
-    int pad_[2];
+    int kcur;            // batched solves: step being run (0: instance idle this step)
+    int pad_;
 };
 enum { kStopNone = 0, kStopDP = 1, kStopNCP = 2, kStopError = 3 };
 

@@ -1,0 +1,174 @@
+// Device helpers of the Krylov kernels (conversions, fixed-order reductions, device-scope
+// publication of partial sums, the Givens update), shared by the single-problem kernels
+// (krylov.hip) and the batched kernels (batch.hip).
+#pragma once
+
+#include <cmath>
+
+#include "abg_internal.h"
+
+namespace abg {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kWaves = kBlock / 64;
+constexpr unsigned kSpinLimit = 1u << 22;
+constexpr int kMaxCoef = 512;
+
+// ---- element access ------------------------------------------------------------------
+__device__ inline double to_f64(double v) { return v; }
+__device__ inline double to_f64(float v) { return (double)v; }
+__device__ inline double to_f64(bf16 v) { return (double)__uint_as_float((unsigned)v.bits << 16); }
+
+template <typename T> __device__ inline T from_f64(double v);
+template <> __device__ inline double from_f64<double>(double v) { return v; }
+template <> __device__ inline float from_f64<float>(double v) { return (float)v; }
+template <> __device__ inline bf16 from_f64<bf16>(double v)
+{
+    // round to float, then to the nearest bf16 (ties to even); NaN stays NaN
+    const unsigned u = __float_as_uint((float)v);
+    bf16 r;
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) {
+        r.bits = (uint16_t)((u >> 16) | 0x40u);
+    } else {
+        const unsigned lsb = (u >> 16) & 1u;
+        r.bits = (uint16_t)((u + 0x7fffu + lsb) >> 16);
+    }
+    return r;
+}
+template <typename T> __device__ inline T zero_of();
+template <> __device__ inline double zero_of<double>() { return 0.0; }
+template <> __device__ inline float zero_of<float>() { return 0.0f; }
+template <> __device__ inline bf16 zero_of<bf16>() { return bf16{0}; }
+
+// ---- reductions ----------------------------------------------------------------------
+// Butterfly sum: lanes l and l^d add the same two operands, so every lane ends with the
+// same value regardless of position.
+__device__ inline double wave_sum(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Block sum returned to every thread, fixed order.
+__device__ inline double block_sum(double v, double *lds)
+{
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) lds[w] = v;
+    __syncthreads();
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < kWaves; ++i) s += lds[i];
+    return s;
+}
+
+__device__ inline double agent_load(const double *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Publishes a partial sum at device scope and waits until the write has been performed
+// (the exchange's returned value is consumed), so that a later counter increment
+// cannot overtake it. Partials are read back only with device-scope atomic loads, so
+// the barrier needs no release/acquire cache maintenance.
+__device__ inline void agent_store(double *p, double v)
+{
+    const double old = __hip_atomic_exchange(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    asm volatile("" ::"v"(old));
+}
+
+// Grid-wide barrier for a cooperative launch: each block adds one to the counter and
+// waits until it reaches `target`. The wait is bounded; on timeout the sticky error
+// flag is raised and every later barrier returns at once. Only values written with
+// agent_store and read with agent_load cross it.
+__device__ inline void grid_barrier(unsigned *bar, unsigned target, int *err)
+{
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        unsigned spins = 0;
+        while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            __builtin_amdgcn_s_sleep(1);
+            if (++spins > kSpinLimit) {
+                __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+            if ((spins & 255u) == 0 &&
+                __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+                break;
+        }
+    }
+    __syncthreads();
+}
+
+// Sum of the G per-block partials, the same in every block.
+__device__ inline double grid_total(const double *part, int G, double *lds)
+{
+    double s = 0.0;
+    for (int j = threadIdx.x; j < G; j += kBlock) s += agent_load(part + j);
+    return block_sum(s, lds);
+}
+
+// One wave. Column k-1 of H has just been written by mgs; R holds the rotated columns,
+// cs/sn the rotations, g the rotated right-hand side. Writes y_k (k entries) and, when
+// rho is given, rho = beta e_1 - H_k y_k.
+__device__ inline void givens_step(double *H, int ld, double *R, double *cs, double *sn,
+                                   double *g, double *y, double *rho, double beta, int k,
+                                   DevState *st)
+{
+    __shared__ double gg[kMaxCoef];
+    __shared__ double ys[kMaxCoef];
+    const int lane = threadIdx.x;
+    const int j = k - 1;
+    double *Hc = H + (size_t)j * ld;
+    double *Rc = R + (size_t)j * ld;
+    const bool bd = st->bd_k == k;
+    for (int i = lane; i <= k; i += 64) Rc[i] = (i == k && bd) ? 0.0 : Hc[i];
+    __syncthreads();
+    if (lane == 0) {
+        for (int i = 0; i < j; ++i) {
+            const double a = Rc[i], b = Rc[i + 1];
+            Rc[i] = cs[i] * a + sn[i] * b;
+            Rc[i + 1] = -sn[i] * a + cs[i] * b;
+        }
+        const double a = Rc[j], b = Rc[k];
+        const double r = hypot(a, b);
+        double c = 1.0, s = 0.0;
+        if (r > 0.0) {
+            c = a / r;
+            s = b / r;
+        } else {
+            st->error |= 4;
+        }
+        cs[j] = c;
+        sn[j] = s;
+        Rc[j] = r;
+        Rc[k] = 0.0;
+        const double gj = g[j];
+        g[j] = c * gj;
+        g[k] = -s * gj;
+        st->ls = fabs(g[k]);
+        st->k = k;
+    }
+    __syncthreads();
+    for (int i = lane; i < k; i += 64) gg[i] = g[i];
+    __syncthreads();
+    for (int jj = k - 1; jj >= 0; --jj) {
+        const double yj = gg[jj] / R[(size_t)jj * ld + jj];
+        if (lane == 0) ys[jj] = yj;
+        for (int i = lane; i < jj; i += 64) gg[i] -= R[(size_t)jj * ld + i] * yj;
+        __syncthreads();
+    }
+    for (int i = lane; i < k; i += 64) y[i] = ys[i];
+    if (rho) {
+        for (int i = lane; i <= k; i += 64) {
+            double acc = (i == 0) ? beta : 0.0;
+            for (int jj = (i > 0 ? i - 1 : 0); jj < k; ++jj) acc -= H[(size_t)jj * ld + i] * ys[jj];
+            rho[i] = acc;
+        }
+    }
+}
+
+}  // namespace
+}  // namespace abg

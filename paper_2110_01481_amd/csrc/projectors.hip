@@ -14,140 +14,27 @@
 //           footprint (at most 32 bins per angle) is staged in LDS; every pixel then
 //           reads its two taps per angle from LDS, and the four wave partials are summed
 //           in a fixed order at the end.
-#include <cmath>
-
-#include "abg_internal.h"
+#include "proj_body.h"
 
 namespace abg {
 namespace {
 
-constexpr int kFwdBlock = 256;
-// An axis-aligned ray lies on a pixel edge when its offset from the edge is below this
-// (in pixels): bin positions carry rounding error, and an edge ray in exact arithmetic
-// must split evenly. FP32 back projection evaluates offsets with ~4e-6 error.
-constexpr double kEdgeTie = 1e-9;
-template <typename T> __device__ inline T edge_tie();
-template <> __device__ inline double edge_tie<double>() { return 1e-9; }
-template <> __device__ inline float edge_tie<float>() { return 2e-5f; }
-// back projector: a 16 x 16 pixel tile per block, 4 pixels per lane, the 4 waves
-// splitting the angles; the tile's detector footprint for 128 angles is staged per
-// round (at most 30 bins per angle for det_spacing >= 0.75, plus margins)
-constexpr int kTile = 16;
-constexpr int kBackWaves = 4;
-constexpr int kBackThreads = 64 * kBackWaves;
-constexpr int kPixPerLane = kTile * kTile / 64;
-constexpr int kAngBlock = 128;
-constexpr int kWin = 32;
-
-__device__ inline int wave_min_i(int v)
-{
-    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
-    return v;
-}
-__device__ inline int wave_max_i(int v)
-{
-    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
-    return v;
-}
-
-// Writes the zero-padded row-major copy xr (N x S, image column c at c + kPad) and the
-// transposed copy xc (row c of xc = column c of the image), through a 32 x 33 LDS tile.
 template <typename T>
 __global__ __launch_bounds__(256) void pad_transpose_kernel(const T *__restrict__ x,
                                                             T *__restrict__ xr,
                                                             T *__restrict__ xc, int N, int S,
                                                             const DevState *st, int k)
 {
-    __shared__ T tile[32][33];
     if (halted(st, k)) return;
-    const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
-    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
-    for (int j = ty; j < 32; j += 8) {
-        const int r = by + j, c = bx + tx;
-        T v = T(0);
-        if (r < N && c < N) {
-            v = x[(size_t)r * N + c];
-            xr[(size_t)r * S + c + kPad] = v;
-        }
-        tile[j][tx] = v;
-    }
-    __syncthreads();
-    for (int j = ty; j < 32; j += 8) {
-        const int c = bx + j, r = by + tx;
-        if (c < N && r < N) xc[(size_t)c * S + r + kPad] = tile[tx][j];
-    }
+    pad_transpose_tile(x, xr, xc, N, S, blockIdx.x * 32, blockIdx.y * 32);
 }
 
-// Zeroes the kPad columns on both sides of the 2N padded rows of xr and xc.
 template <typename T>
 __global__ void pad_zero_kernel(T *__restrict__ xr, T *__restrict__ xc, int N, int S,
                                 const DevState *st, int k)
 {
     if (halted(st, k)) return;
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    const int per_row = 2 * kPad;
-    if (idx >= 2 * N * per_row) return;
-    const int row = idx / per_row, e = idx % per_row;
-    const int col = e < kPad ? e : N + e;   // [0,kPad) and [N+kPad, N+2kPad)
-    T *base = row < N ? xr + (size_t)row * S : xc + (size_t)(row - N) * S;
-    base[col] = T(0);
-}
-
-// Position of a ray inside the current band of pixels: the band holds the minor-axis
-// interval [lo, lo + |m|] (pixels from the image edge) and the walk advances lo by m.
-// FP64 data: lo in FP64. FP32 data: lo in 24.40 fixed point biased by kPad, so a band
-// step is one 64-bit add, the pixel index is the integer part and the top 32 fraction
-// bits give the weight (position error ~1e-9 px after 32768 steps).
-template <typename T> struct Band;
-template <typename T> struct BandWeights {
-    T invq, len;
-    __device__ BandWeights(double iq, double l) : invq(T(iq)), len(T(l)) {}
-};
-
-template <> struct Band<double> {
-    double lo, m;
-    __device__ Band(double lo0, double m_) : lo(lo0), m(m_) {}
-    __device__ void next() { lo += m; }
-    __device__ unsigned column(unsigned cmax) const
-    {
-        return min((unsigned)((int)floor(lo) + kPad), cmax);
-    }
-    // length of the band segment left of the pixel edge at floor(lo) + 1
-    __device__ double left_length(const BandWeights<double> &b) const
-    {
-        return fmin(b.len, fma(floor(lo) - lo, b.invq, b.invq));
-    }
-};
-
-template <> struct Band<float> {
-    long long fx, mfx;
-    __device__ Band(double lo0, double m)
-        : fx(__double2ll_rn((lo0 + kPad) * 0x1p40)), mfx(__double2ll_rn(m * 0x1p40)) {}
-    __device__ void next() { fx += mfx; }
-    __device__ unsigned column(unsigned cmax) const
-    {
-        // negative positions wrap to large values and clamp into the right-hand padding
-        return min((unsigned)(int)(fx >> 40), cmax);
-    }
-    __device__ float left_length(const BandWeights<float> &b) const
-    {
-        const float frac = (float)(unsigned)(fx >> 8);      // top 32 fraction bits
-        const float w = fmaf(frac, -b.invq * 0x1p-32f, b.invq);
-        return __builtin_amdgcn_fmed3f(w, b.len, -1e30f);   // min(w, len)
-    }
-};
-
-// The two adjacent pixels a band segment can touch, fetched with one load from a
-// wave-uniform row pointer plus a 32-bit byte offset (one wide gather is cheaper for
-// the texture address unit than two narrow ones).
-template <typename T> struct alignas(sizeof(T)) Taps {
-    T a, b;
-};
-template <typename T>
-__device__ inline Taps<T> load_taps(const T *row, unsigned col)
-{
-    const unsigned boff = col * (unsigned)sizeof(T);
-    return *reinterpret_cast<const Taps<T> *>(reinterpret_cast<const char *>(row) + boff);
+    pad_zero_item(xr, xc, N, S, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 template <typename T>
@@ -157,147 +44,8 @@ __global__ __launch_bounds__(kFwdBlock) void forward_kernel(
     const DevState *st, int k)
 {
     if (halted(st, k)) return;
-    const int a = blockIdx.y;
-    const int i = blockIdx.x * kFwdBlock + threadIdx.x;
-    const AngleParams P = ang[a];
-    const T *img = (P.steep ? xr : xc) + kPad;
-    const double half = 0.5 * N;
-    const double si = s0 + (double)i * ds;
-    // minor-axis coordinate, in pixels from the image edge, where the ray enters band 0
-    const double u0 = fma(si, P.inv, fma(-half, P.m, half));
-    const double lo_clamp = -(double)kPad, hi_clamp = (double)(N + kPad - 2);
-    T acc = T(0);
-
-    if (P.axis) {
-        // The ray stays in one column (or row) of pixels; on a pixel edge it is split
-        // evenly between the two pixels that share the edge.
-        const double uc = fmin(fmax(u0, lo_clamp), hi_clamp);
-        const double nearest = rint(uc);
-        int c0;
-        T w0, w1;
-        if (fabs(uc - nearest) <= kEdgeTie) {
-            c0 = (int)nearest - 1;
-            w0 = w1 = T(0.5 * P.len);
-        } else {
-            c0 = (int)floor(uc);
-            w0 = T(P.len);
-            w1 = T(0);
-        }
-        if (u0 < lo_clamp || u0 > hi_clamp) c0 = -kPad;   // outside: read zero padding
-        c0 = min(max(c0, -kPad), N + kPad - 2);           // both taps inside the padded row
-        const T *p = img + c0;
-        for (int r = 0; r < N; ++r) {
-            acc = fma(w0, p[0], acc);
-            acc = fma(w1, p[1], acc);
-            p += S;
-        }
-    } else {
-        // Band r holds the minor-axis interval [lo_r, lo_r + |m|], lo_r = lo0 + r*m.
-        const double lo0 = u0 + fmin(P.m, 0.0);
-        const double am = fabs(P.m);
-        double ra, rb;
-        if (P.m > 0.0) {
-            ra = (-1.0 - am - lo0) / am;
-            rb = (N + 1.0 - lo0) / am;
-        } else {
-            ra = (lo0 - (N + 1.0)) / am;
-            rb = (lo0 + 1.0 + am) / am;
-        }
-        ra = fmin(fmax(ra, 0.0), (double)N);
-        rb = fmin(fmax(rb, 0.0), (double)N);
-        int r0 = (int)floor(ra);
-        int r1 = min((int)ceil(rb) + 1, N);
-        if (i >= n_det) {
-            r0 = N;
-            r1 = 0;
-        }
-        // wave-uniform band range: lanes outside their own chord read zero padding
-        const int wr0 = __builtin_amdgcn_readfirstlane(wave_min_i(r0));
-        const int wr1 = __builtin_amdgcn_readfirstlane(wave_max_i(r1));
-        Band<T> band(fma((double)wr0, P.m, lo0), P.m);
-        // row-start pointer (padding included): column offsets are unsigned
-        const T *row = img - kPad + (size_t)wr0 * S;
-        const BandWeights<T> bw(P.invq, P.len);
-        const unsigned cmax = (unsigned)(N + 2 * kPad - 2);
-        int r = wr0;
-        // four bands per trip, all loads issued before their use
-        for (; r + 4 <= wr1; r += 4) {
-            unsigned c[4];
-            T w[4], v0[4], v1[4];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                c[j] = band.column(cmax);
-                w[j] = band.left_length(bw);
-                band.next();
-            }
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const Taps<T> t = load_taps(row + (size_t)j * S, c[j]);
-                v0[j] = t.a;
-                v1[j] = t.b;
-            }
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                acc = fma(w[j], v0[j], acc);
-                acc = fma(bw.len - w[j], v1[j], acc);
-            }
-            row += 4 * (size_t)S;
-        }
-        for (; r < wr1; ++r) {
-            const unsigned c = band.column(cmax);
-            const T w = band.left_length(bw);
-            band.next();
-            const Taps<T> t = load_taps(row, c);
-            acc = fma(w, t.a, acc);
-            acc = fma(bw.len - w, t.b, acc);
-            row += S;
-        }
-    }
-    if (i < n_det) y[(size_t)a * n_det + i] = acc;
-}
-
-// Per staged angle: position of the tile's reference pixel in the window (f), the
-// change of u per pixel step (cu, su), the window's first bin, and the line-model
-// trapezoid of the matched back projector.
-template <typename T>
-struct alignas(16) BackStage {
-    T f, cu, su;
-    int ib;
-    T invp, half, invpq;
-    int axis;
-};
-
-// Length of a ray at offset |t| from a unit pixel's centre projection (the trapezoid of
-// the line model); on an axis-aligned ray at exactly |t| = 1/2 the two pixels share it.
-template <typename T>
-__device__ inline T trapezoid(T at, const BackStage<T> &P)
-{
-    if (P.axis) {
-        if (fabs(at - T(0.5)) <= edge_tie<T>()) return T(0.5) * P.invp;
-        return at < T(0.5) ? P.invp : T(0);
-    }
-    return fmin(P.invp, fmax(T(0), (P.half - at) * P.invpq));
-}
-
-template <typename T> __device__ inline T fract_of(T u);
-template <> __device__ inline float fract_of<float>(float u) { return __builtin_amdgcn_fractf(u); }
-template <> __device__ inline double fract_of<double>(double u) { return __builtin_amdgcn_fract(u); }
-
-// Staged window entry: the bin's value and the difference to the next bin.
-template <typename T> struct alignas(2 * sizeof(T)) BinPair {
-    T v, d;
-};
-
-// One pixel's contribution at detector coordinate u (window-relative, u >= 1 by
-// construction, so truncation is floor).
-template <typename T, bool ADJ>
-__device__ inline T back_tap(const BinPair<T> *wrow, T u, const BackStage<T> &P, T dsT)
-{
-    const T w = fract_of(u);
-    const int k = min(max((int)u, 0), kWin - 2);
-    const BinPair<T> b = wrow[k];
-    if (!ADJ) return fma(w, b.d, b.v);
-    return trapezoid(w * dsT, P) * b.v + trapezoid((T(1) - w) * dsT, P) * (b.v + b.d);
+    forward_ray(xr, xc, y, ang, blockIdx.y, blockIdx.x * kFwdBlock + threadIdx.x, N, S, n_det,
+                ds, s0);
 }
 
 template <typename T, bool ADJ>
@@ -305,90 +53,23 @@ __global__ __launch_bounds__(kBackThreads) void back_kernel(
     const T *__restrict__ y, T *__restrict__ x, const AngleParams *__restrict__ ang, int N,
     int n_ang, int n_det, double ds, double s0, const DevState *st, int k)
 {
-    __shared__ BinPair<T> win[kAngBlock][kWin];
     if (halted(st, k)) return;
-    __shared__ BackStage<T> prm[kAngBlock];
-    __shared__ T part[kBackWaves - 1][kTile * kTile];
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    // lane owns pixels (tx, ty0 + 4j), j = 0..3, of the 16 x 16 tile
-    const int tx = lane & 15, ty0 = lane >> 4;
-    const int c0 = blockIdx.x * kTile, r0 = blockIdx.y * kTile;
-    const double xref = c0 - 0.5 * N + 0.5, yref = r0 - 0.5 * N + 0.5;
-    const double s0u = s0 / ds;
-    const T ftx = T(tx), fty = T(ty0);
-    const T dsT = T(ds);
-    T acc[kPixPerLane] = {};
-    for (int a0 = 0; a0 < n_ang; a0 += kAngBlock) {
-        const int na = min(kAngBlock, n_ang - a0);
-        __syncthreads();
-        if (threadIdx.x < na) {
-            const AngleParams P = ang[a0 + threadIdx.x];
-            const double uref = fma(xref, P.cu, fma(yref, P.su, -s0u));
-            const double umin = uref + (kTile - 1) * (fmin(P.cu, 0.0) + fmin(P.su, 0.0));
-            const double ib = floor(umin) - 1.0;
-            BackStage<T> st;
-            st.f = T(uref - ib);
-            st.cu = T(P.cu);
-            st.su = T(P.su);
-            st.ib = (int)ib;
-            st.invp = T(P.len);
-            st.half = T(P.half);
-            st.invpq = T(P.invpq);
-            st.axis = P.axis;
-            prm[threadIdx.x] = st;
-        }
-        __syncthreads();
-        for (int e = threadIdx.x; e < na * kWin; e += kBackThreads) {
-            const int t = e / kWin, k = e % kWin;
-            const int bin = prm[t].ib + k;
-            const T *row = y + (size_t)(a0 + t) * n_det;
-            const T v0 = (bin >= 0 && bin < n_det) ? row[bin] : T(0);
-            const T v1 = (bin + 1 >= 0 && bin + 1 < n_det) ? row[bin + 1] : T(0);
-            win[t][k] = BinPair<T>{v0, v1 - v0};
-        }
-        __syncthreads();
-        // the block's waves take interleaved angles of the staged round
-        for (int t = wave; t < na; t += kBackWaves) {
-            const BackStage<T> P = prm[t];
-            const T u0 = fma(ftx, P.cu, fma(fty, P.su, P.f));
-            const T du = T(4) * P.su;
-#pragma unroll
-            for (int j = 0; j < kPixPerLane; ++j)
-                acc[j] += back_tap<T, ADJ>(win[t], fma(T(j), du, u0), P, dsT);
-        }
-    }
-    // fixed-order sum of the four waves' partials
-#pragma unroll
-    for (int j = 0; j < kPixPerLane; ++j) {
-        const int pix = (ty0 + 4 * j) * kTile + tx;
-        if (wave > 0) part[wave - 1][pix] = acc[j];
-    }
-    __syncthreads();
-    if (wave == 0) {
-#pragma unroll
-        for (int j = 0; j < kPixPerLane; ++j) {
-            const int pix = (ty0 + 4 * j) * kTile + tx;
-            T sum = acc[j];
-#pragma unroll
-            for (int v = 0; v < kBackWaves - 1; ++v) sum += part[v][pix];
-            const int c = c0 + tx, r = r0 + ty0 + 4 * j;
-            if (r < N && c < N) x[(size_t)r * N + c] = ADJ ? sum : sum * T(1.0 / ds);
-        }
-    }
+    back_tile<T, ADJ>(y, x, ang, N, n_ang, n_det, ds, s0, blockIdx.x * kTile, blockIdx.y * kTile);
 }
 
 template <typename T>
 hipError_t forward_t(const Geometry &g, const void *x, void *y, void *ws, hipStream_t s,
-                     const DevState *st, int k)
+                     const DevState *st, int k, bool pads_zero)
 {
     const int N = g.N, S = g.padded_stride();
     T *xr = static_cast<T *>(ws);
     T *xc = xr + (size_t)N * S;
     dim3 tgrid((N + 31) / 32, (N + 31) / 32);
     pad_transpose_kernel<T><<<tgrid, 256, 0, s>>>(static_cast<const T *>(x), xr, xc, N, S, st, k);
-    const int npad = 2 * N * 2 * kPad;
-    pad_zero_kernel<T><<<(npad + 255) / 256, 256, 0, s>>>(xr, xc, N, S, st, k);
+    if (!pads_zero) {
+        const int npad = 2 * N * 2 * kPad;
+        pad_zero_kernel<T><<<(npad + 255) / 256, 256, 0, s>>>(xr, xc, N, S, st, k);
+    }
     dim3 grid((g.n_det + kFwdBlock - 1) / kFwdBlock, g.n_ang);
     const double s0 = -0.5 * (g.n_det - 1) * g.ds;
     {
@@ -425,10 +106,10 @@ size_t fp_workspace_bytes(const Geometry &g, int dtype)
 }
 
 hipError_t launch_forward(const Geometry &g, int dtype, const void *x, void *y, void *ws,
-                          hipStream_t s, const DevState *st, int k)
+                          hipStream_t s, const DevState *st, int k, bool pads_zero)
 {
-    return dtype == ABG_F64 ? forward_t<double>(g, x, y, ws, s, st, k)
-                            : forward_t<float>(g, x, y, ws, s, st, k);
+    return dtype == ABG_F64 ? forward_t<double>(g, x, y, ws, s, st, k, pads_zero)
+                            : forward_t<float>(g, x, y, ws, s, st, k, pads_zero);
 }
 
 hipError_t launch_back(const Geometry &g, int kind, int dtype, const void *y, void *x,

@@ -180,9 +180,10 @@ struct Solve {
     char *zcol(int i) const { return static_cast<char *>(Z) + (size_t)i * ly.mp * sX; }
     double *ycol(int k) const { return Y + (size_t)(k - 1) * k_max; }
 
+    // the padding of the forward projector's scratch is zeroed once per solve
     int fwd(const void *x, void *yv, const DevState *sst = nullptr, int k = 0)
     {
-        CK(launch_forward(g, p.proj, x, yv, fpws, s, sst, k));
+        CK(launch_forward(g, p.proj, x, yv, fpws, s, sst, k, true));
         return ABG_OK;
     }
     int back(const void *yv, void *x, const DevState *sst = nullptr, int k = 0)
@@ -330,6 +331,7 @@ int run_solver(const Geometry &g, int method, int kind, const void *b, const voi
     CK(launch_fill_u32(S.count, 16, 0u, s));
     CK(launch_fill_f64(S.H, (size_t)S.ld * k_max, 0.0, s));
     CK(launch_fill_f64(S.gv, (size_t)S.ld, 0.0, s));
+    CK(launch_fill_u32(reinterpret_cast<unsigned *>(S.fpws), fp_workspace_bytes(g, p.proj) / 4, 0u, s));
 
     // b - A x0, r0 = (B)(b - A x0), beta = ||r0|| into g[0], w_1
     if (x0) {
