@@ -52,6 +52,7 @@ extern "C" {
 #define ABG_EHIP (-3)          /* a HIP runtime call failed                              */
 #define ABG_ENAN (-4)          /* a norm became NaN or Inf                               */
 #define ABG_EDEVICE (-5)       /* a device-side wait exceeded its bound (grid barrier)   */
+#define ABG_EFULL (-6)         /* batched engine: every slot holds an unfinished problem  */
 #define ABG_NOT_CONVERGED 1    /* DP never satisfied up to k_max: x_{k_max} returned     */
 #define ABG_BREAKDOWN 2        /* h_{k+1,k} ~ 0: Krylov space exhausted, x_k returned    */
 #define ABG_ZERO_RHS 3         /* ||r_0|| = 0: x = x_0 returned with k = 0               */
@@ -155,6 +156,76 @@ int abg_ba_gmres(const abg_geometry *g, int bp_kind, const void *b, const void *
 
 /* Static description of a status code. */
 const char *abg_status_string(int status);
+
+/* ---- batched engine: many independent solves advanced together ---------------------- */
+/*
+ * An engine advances every problem it holds by one Arnoldi step per round (the same
+ * AB-/BA-GMRES iteration as above: A, B, modified Gram-Schmidt, FP64 Givens, the DP
+ * test), with all problems' work in one fixed sequence of kernels that is captured once
+ * in a HIP graph and replayed. Problems of any geometry, method, back projector and
+ * iteration cap share a round; each stops on its own rule, and a new problem can be
+ * submitted between any two rounds (continuous batching). A problem's result does not
+ * depend on which other problems share its rounds.
+ *
+ * Threading: one host thread per engine. All device work is enqueued on the engine's
+ * stream. Stopping rules: ABG_STOP_NONE and ABG_STOP_DP (NCP is single-solve only);
+ * info->H and info->ncp_hist are not filled.
+ */
+typedef struct abg_engine abg_engine;
+
+typedef struct {
+    const abg_geometry *g;   /* geometry on the engine's device; must outlive the request */
+    int method;              /* ABG_METHOD_AB or ABG_METHOD_BA                             */
+    int bp_kind;             /* ABG_BP_HAT or ABG_BP_ADJ                                   */
+    int k_max;               /* 1..500                                                     */
+    abg_stop stop;           /* ABG_STOP_NONE or ABG_STOP_DP                               */
+    const void *b;           /* m elements of the engine's proj dtype (device)             */
+    const void *x0;          /* n elements, or NULL for x_0 = 0                            */
+    void *x;                 /* n elements: the result (device)                            */
+    void *ws;                /* abg_request_bytes(...) bytes, 256-byte aligned (device)    */
+    size_t ws_bytes;
+    abg_info *info;          /* host, may be NULL; filled when the request is finished      */
+    long long tag;           /* caller's identifier, reported by abg_engine_poll          */
+} abg_request;
+
+/* Device memory one request needs (its Krylov basis, Hessenberg state and scratch): the
+ * unit of admission against a memory budget. Same value as abg_workspace_bytes. */
+size_t abg_request_bytes(const abg_geometry *g, int method, int k_max, abg_precision p,
+                         abg_stop st);
+
+/* Creates an engine on the current device for up to max_slots (1..4096) concurrent
+ * problems. p: {F64,F64}, {F32,F32} or {F32,BF16}. The engine owns a few small device
+ * and pinned host buffers (descriptors, work lists, scalar copies). */
+int abg_engine_create(abg_precision p, int max_slots, void *stream, abg_engine **out);
+
+/* Synchronises the stream and releases the engine; unfinished problems are abandoned. */
+int abg_engine_destroy(abg_engine *e);
+
+/* Adds a problem. Its buffers (b, x0, x, ws) belong to the engine until abg_engine_poll
+ * has returned its tag. Enqueues the initialisation (r_0, beta, w_1) without waiting.
+ * Returns ABG_EFULL when no slot is free, ABG_EINVAL on bad arguments (including a basis
+ * vector too long for one block group). */
+int abg_engine_submit(abg_engine *e, const abg_request *r);
+
+/* Runs one round: enqueues one Arnoldi step of every running problem and processes the
+ * scalars of the previous round (at most one round is left in flight). Problems found
+ * finished become available to abg_engine_poll. *n_active (may be NULL) receives the
+ * number of problems not yet finished. */
+int abg_engine_step(abg_engine *e, int *n_active);
+
+/* Returns up to `max` finished problems (tags and statuses, in finishing order). After
+ * this, their x holds the result and their buffers are the caller's again. */
+int abg_engine_poll(abg_engine *e, long long *tags, int *status, int max, int *n);
+
+/* Tile shape of the forward projector's work items: rays per angle in one block (64,
+ * 128 or 256; a block of 256 threads takes 256/rays angles). Takes effect next round. */
+int abg_engine_set_tiles(abg_engine *e, int rays);
+int abg_engine_get_tiles(const abg_engine *e, int *rays);
+
+/* Convenience: solves n requests together on a new engine and returns when all are
+ * finished (each request's status in its info, if given). Returns the first error, or
+ * ABG_OK. `rays` <= 0 keeps the default tile shape. */
+int abg_batch_solve(const abg_request *r, int n, abg_precision p, int rays, void *stream);
 
 /* ---- instrumentation -------------------------------------------------------------- */
 

@@ -4,10 +4,10 @@ Python face of libabgmres (include/abgmres.h). Importing the package loads nothi
 the first Geometry or solver call loads the HIP library and fails loudly if it is
 missing.
 """
-from ._binding import (AbgError, Geometry, SolveResult, ab_gmres, ba_gmres, gmres,
-                       load_library, profile_enable, profile_read, workspace_bytes,
-                       EXPORTS, LIB_PATH)
+from ._binding import (AbgError, Engine, Geometry, Problem, SolveResult, ab_gmres, ba_gmres,
+                       batch_solve, gmres, load_library, profile_enable, profile_read,
+                       request_bytes, workspace_bytes, EXPORTS, LIB_PATH)
 
-__all__ = ["AbgError", "Geometry", "SolveResult", "ab_gmres", "ba_gmres", "gmres",
-           "load_library", "profile_enable", "profile_read", "workspace_bytes", "EXPORTS",
-           "LIB_PATH"]
+__all__ = ["AbgError", "Engine", "Geometry", "Problem", "SolveResult", "ab_gmres", "ba_gmres",
+           "batch_solve", "gmres", "load_library", "profile_enable", "profile_read",
+           "request_bytes", "workspace_bytes", "EXPORTS", "LIB_PATH"]

@@ -20,11 +20,13 @@ STOP_NONE, STOP_DP, STOP_NCP = 0, 1, 2
 METHOD_AB, METHOD_BA = 0, 1
 
 STATUS = {0: "ok", -1: "einval", -2: "enomem", -3: "ehip", -4: "enan", -5: "edevice",
-          1: "not_converged", 2: "breakdown", 3: "zero_rhs"}
+          -6: "efull", 1: "not_converged", 2: "breakdown", 3: "zero_rhs"}
 EXPORTS = ["abg_create_geometry", "abg_destroy_geometry", "abg_geometry_sizes",
            "abg_fp_workspace_bytes", "abg_fp_apply", "abg_bp_apply", "abg_workspace_bytes",
            "abg_ab_gmres", "abg_ba_gmres", "abg_status_string", "abg_profile_enable",
-           "abg_profile_read"]
+           "abg_profile_read", "abg_request_bytes", "abg_engine_create", "abg_engine_destroy",
+           "abg_engine_submit", "abg_engine_step", "abg_engine_poll", "abg_engine_set_tiles",
+           "abg_engine_get_tiles", "abg_batch_solve"]
 
 
 class AbgError(RuntimeError):
@@ -50,6 +52,14 @@ class Info(ctypes.Structure):
                 ("ncp_dist", ctypes.c_double), ("beta", ctypes.c_double),
                 ("res_hist", _dp), ("ls_hist", _dp), ("ncp_hist", _dp),
                 ("hist_len", ctypes.c_int), ("H", _dp)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("g", ctypes.c_void_p), ("method", ctypes.c_int), ("bp_kind", ctypes.c_int),
+                ("k_max", ctypes.c_int), ("stop", Stop), ("b", ctypes.c_void_p),
+                ("x0", ctypes.c_void_p), ("x", ctypes.c_void_p), ("ws", ctypes.c_void_p),
+                ("ws_bytes", ctypes.c_size_t), ("info", ctypes.POINTER(Info)),
+                ("tag", ctypes.c_longlong)]
 
 
 _lib = None
@@ -82,6 +92,17 @@ def load_library(path: str | None = None):
     lib.abg_status_string.restype = ctypes.c_char_p
     lib.abg_profile_enable.argtypes = [i]
     lib.abg_profile_read.argtypes = [ctypes.POINTER(ctypes.c_longlong), _dp, i]
+    lib.abg_request_bytes.argtypes = [vp, i, i, Precision, Stop]
+    lib.abg_request_bytes.restype = sz
+    lib.abg_engine_create.argtypes = [Precision, i, vp, ctypes.POINTER(vp)]
+    lib.abg_engine_destroy.argtypes = [vp]
+    lib.abg_engine_submit.argtypes = [vp, ctypes.POINTER(Request)]
+    lib.abg_engine_step.argtypes = [vp, ctypes.POINTER(i)]
+    lib.abg_engine_poll.argtypes = [vp, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(i), i,
+                                    ctypes.POINTER(i)]
+    lib.abg_engine_set_tiles.argtypes = [vp, i]
+    lib.abg_engine_get_tiles.argtypes = [vp, ctypes.POINTER(i)]
+    lib.abg_batch_solve.argtypes = [ctypes.POINTER(Request), i, Precision, i, vp]
     _lib = lib
     return lib
 
@@ -283,3 +304,187 @@ def profile_read(reset: bool = True):
     load_library().abg_profile_read(counts, ms, 1 if reset else 0)
     names = ["forward", "back", "mgs", "combine"]
     return {nm: (int(counts[i]), float(ms[i])) for i, nm in enumerate(names)}
+
+
+# ---- batched engine -----------------------------------------------------------------------
+
+def request_bytes(g: Geometry, method: str, k_max: int, proj="f32", basis="f32",
+                  stop="dp") -> int:
+    """Device bytes one engine request needs (basis, Hessenberg state, scratch)."""
+    st = Stop({"none": STOP_NONE, "dp": STOP_DP}[stop], 1.0, 1.0)
+    return int(load_library().abg_request_bytes(g.handle, METHOD_AB if method == "ab" else METHOD_BA,
+                                                int(k_max), Precision(_DTYPES[proj], _DTYPES[basis]), st))
+
+
+@dataclass
+class Problem:
+    """One solve for the batched engine. b: CUDA tensor of m elements (engine's proj dtype)."""
+    g: Geometry
+    method: str
+    b: object
+    k_max: int
+    stop: str = "dp"
+    tau: float = 1.0
+    noise_norm: float = 0.0
+    bp: str = "hat"
+    x0: object = None
+    tag: int = 0
+
+
+class _Pending:
+    def __init__(self, prob: Problem, x, ws, k_max: int):
+        self.prob = prob
+        self.x = x
+        self.ws = ws
+        self.res = np.zeros(k_max)
+        self.ls = np.zeros(k_max)
+        self.info = Info()
+        self.info.res_hist = self.res.ctypes.data_as(_dp)
+        self.info.ls_hist = self.ls.ctypes.data_as(_dp)
+        self.info.ncp_hist = None
+        self.info.hist_len = k_max
+        self.info.H = None
+
+    def result(self, code: int) -> SolveResult:
+        i = self.info
+        kd = i.k_done
+        return SolveResult(x=self.x, status=STATUS.get(code, str(code)), k_stop=i.k_stop,
+                           k_done=kd, res_norm=i.res_norm, ncp_dist=0.0, beta=i.beta,
+                           n_literal=i.n_literal, res_hist=self.res[:kd].copy(),
+                           ls_hist=self.ls[:kd].copy(), ncp_hist=np.zeros(0),
+                           extra={"tag": self.prob.tag})
+
+
+class Engine:
+    """Batched AB-/BA-GMRES engine (abg_engine_*): submit problems at any time, advance all
+    of them one Arnoldi step per round, collect finished ones with poll()."""
+
+    def __init__(self, proj="f32", basis="f32", max_slots=64, stream=None, device=None):
+        torch = _torch()
+        self.lib = load_library()
+        self.proj, self.basis = proj, basis
+        self.prec = Precision(_DTYPES[proj], _DTYPES[basis])
+        self.device = device if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.stream = stream
+        h = ctypes.c_void_p()
+        _check(self.lib.abg_engine_create(self.prec, int(max_slots), _stream_ptr(stream),
+                                          ctypes.byref(h)), "abg_engine_create")
+        self._h = h
+        self.max_slots = int(max_slots)
+        self._pending: dict[int, _Pending] = {}
+        self._next_tag = 1
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self.lib.abg_engine_destroy(self._h)
+            self._h = None
+            self._pending.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_tiles(self, rays: int):
+        _check(self.lib.abg_engine_set_tiles(self._h, int(rays)), "abg_engine_set_tiles")
+
+    def get_tiles(self) -> int:
+        r = ctypes.c_int()
+        _check(self.lib.abg_engine_get_tiles(self._h, ctypes.byref(r)), "abg_engine_get_tiles")
+        return r.value
+
+    def submit(self, prob: Problem, x=None, workspace=None) -> int | None:
+        """Adds a problem; returns its engine tag, or None when every slot is busy."""
+        torch = _torch()
+        g = prob.g
+        b = prob.b
+        assert b.is_cuda and b.is_contiguous() and b.numel() == g.m
+        assert _dtype_code(b.dtype) == self.prec.proj, "b must be in the engine's proj dtype"
+        meth = METHOD_AB if prob.method == "ab" else METHOD_BA
+        st = Stop({"none": STOP_NONE, "dp": STOP_DP}[prob.stop], float(prob.tau), float(prob.noise_norm))
+        nb = self.lib.abg_request_bytes(g.handle, meth, int(prob.k_max), self.prec, st)
+        if nb == 0:
+            raise AbgError(-1, "abg_request_bytes")
+        ws = workspace if workspace is not None else _dev_empty(nb, b.device)
+        x = x if x is not None else torch.empty(g.n, dtype=b.dtype, device=b.device)
+        tag = self._next_tag
+        self._next_tag += 1
+        pend = _Pending(prob, x, ws, int(prob.k_max))
+        r = Request(g.handle, meth, BP_ADJ if prob.bp == "adj" else BP_HAT, int(prob.k_max), st,
+                    ctypes.c_void_p(b.data_ptr()),
+                    ctypes.c_void_p(prob.x0.data_ptr()) if prob.x0 is not None else None,
+                    ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                    ctypes.pointer(pend.info), tag)
+        rc = self.lib.abg_engine_submit(self._h, ctypes.byref(r))
+        if rc == -6:
+            return None
+        _check(rc, "abg_engine_submit")
+        self._pending[tag] = pend
+        return tag
+
+    def step(self) -> int:
+        """One round; returns the number of problems not yet finished."""
+        n = ctypes.c_int()
+        _check(self.lib.abg_engine_step(self._h, ctypes.byref(n)), "abg_engine_step")
+        return n.value
+
+    def poll(self) -> list:
+        """Finished problems since the last poll: list of (tag, SolveResult)."""
+        out = []
+        cap = max(1, len(self._pending))
+        tags = (ctypes.c_longlong * cap)()
+        sts = (ctypes.c_int * cap)()
+        n = ctypes.c_int()
+        _check(self.lib.abg_engine_poll(self._h, tags, sts, cap, ctypes.byref(n)), "abg_engine_poll")
+        for i in range(n.value):
+            pend = self._pending.pop(int(tags[i]))
+            out.append((int(tags[i]), pend.result(int(sts[i]))))
+        return out
+
+    def run(self, problems, max_rounds: int = 100000) -> list:
+        """Solves the problems together; returns SolveResults in input order."""
+        tags = []
+        for p in problems:
+            t = self.submit(p)
+            if t is None:
+                raise AbgError(-6, "Engine.run: more problems than slots")
+            tags.append(t)
+        done = {}
+        rounds = 0
+        while len(done) < len(tags):
+            self.step()
+            for t, r in self.poll():
+                done[t] = r
+            rounds += 1
+            if rounds > max_rounds:
+                raise AbgError(-5, "Engine.run: no progress")
+        return [done[t] for t in tags]
+
+
+def batch_solve(problems, proj="f32", basis="f32", rays: int = 0, stream=None) -> list:
+    """abg_batch_solve: all problems on a new engine; returns SolveResults in input order."""
+    torch = _torch()
+    lib = load_library()
+    prec = Precision(_DTYPES[proj], _DTYPES[basis])
+    keep = []
+    reqs = (Request * len(problems))()
+    for i, prob in enumerate(problems):
+        g, b = prob.g, prob.b
+        meth = METHOD_AB if prob.method == "ab" else METHOD_BA
+        st = Stop({"none": STOP_NONE, "dp": STOP_DP}[prob.stop], float(prob.tau), float(prob.noise_norm))
+        nb = lib.abg_request_bytes(g.handle, meth, int(prob.k_max), prec, st)
+        if nb == 0:
+            raise AbgError(-1, "abg_request_bytes")
+        ws = _dev_empty(nb, b.device)
+        x = torch.empty(g.n, dtype=b.dtype, device=b.device)
+        pend = _Pending(prob, x, ws, int(prob.k_max))
+        keep.append(pend)
+        reqs[i] = Request(g.handle, meth, BP_ADJ if prob.bp == "adj" else BP_HAT, int(prob.k_max),
+                          st, ctypes.c_void_p(b.data_ptr()),
+                          ctypes.c_void_p(prob.x0.data_ptr()) if prob.x0 is not None else None,
+                          ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                          ctypes.pointer(pend.info), i)
+    _check(lib.abg_batch_solve(reqs, len(problems), prec, int(rays), _stream_ptr(stream)),
+           "abg_batch_solve")
+    return [p.result(p.info.status) for p in keep]

@@ -85,10 +85,17 @@ struct DevState {
     int stop;            // raised by the last kernel of a step: later steps return at entry
     int stop_k;          // step that raised it
     int stop_reason;     // kStop*
-    int kcur;            // batched solves: step being run (0: instance idle this step)
-    int pad_;
+    // batched solves only
+    int kcur;            // step being run this round (0: the instance sits it out)
+    int active;          // initialised, with beta > 0
+    int done;            // final: x holds x_{k_sel}, lit = ||b - A x||, status set
+    int k_sel;           // step whose iterate x holds
+    int status;          // ABG_* status of the finished instance
+    int n_lit;           // DP candidates checked with the explicit residual
+    int gen;             // admission counter of the slot (tells a reused slot's copies apart)
+    double lit;          // ||b - A x|| of the last iterate formed
 };
-enum { kStopNone = 0, kStopDP = 1, kStopNCP = 2, kStopError = 3 };
+enum { kStopNone = 0, kStopDP = 1, kStopNCP = 2, kStopError = 3, kStopZero = 4 };
 
 #ifdef __HIPCC__
 // True when per-step kernels of step k must not run.
@@ -159,6 +166,41 @@ int run_solver(const Geometry &g, int method, int kind, const void *b, const voi
                void *x, int k_max, abg_stop st, abg_precision p, void *ws, size_t ws_bytes,
                abg_info *info, hipStream_t s);
 
+// ---- one problem of the batched engine (solver.hip) ------------------------------------
+// Buffers inside a solve's workspace (the same layout as a single solve).
+struct InstanceView {
+    void *V, *Z, *cur, *q, *rb0, *tm, *tn, *fpws;
+    double *H, *R, *cs, *sn, *g, *Y, *rho, *part, *mgs_part;
+    unsigned *bar, *count;
+    long long L, ldv, mp, np;
+    int part_cap, mgs_part_cap;   // doubles in part / mgs_part
+};
+InstanceView instance_view(const Geometry &g, int method, int k_max, abg_precision p,
+                           abg_stop st, void *ws);
+// Enqueues the initialisation (clears, r0, MGS step 0 into *dst); no host wait.
+int instance_init(const Geometry &g, int method, int kind, int k_max, abg_stop st,
+                  abg_precision p, void *ws, const void *b, const void *x0, DevState *dst,
+                  hipStream_t s);
+// Enqueues x = x_k (k = 0: x0 or zero) and ||b - A x|| into *lit; no host wait.
+int instance_form_x(const Geometry &g, int method, int kind, int k_max, abg_stop st,
+                    abg_precision p, void *ws, int k, const void *b, const void *x0, void *x,
+                    DevState *dst, double *lit, hipStream_t s);
+
+// ---- batched engine (batch.hip) ---------------------------------------------------------
+struct Engine;
+int engine_create(abg_precision p, int max_slots, hipStream_t s, Engine **out);
+void engine_destroy(Engine *e);
+int engine_submit(Engine *e, const Geometry &g, const abg_request &r);
+int engine_step(Engine *e, int *n_running);
+int engine_poll(Engine *e, long long *tags, int *status, int max, int *n);
+int engine_pending(const Engine *e);
+int engine_set_tiles(Engine *e, int rays);
+int engine_get_tiles(const Engine *e, int *rays);
+int engine_device(const Engine *e);
+hipStream_t engine_stream(const Engine *e);
+int engine_precision(const Engine *e, abg_precision *p);
+long long engine_rounds(const Engine *e);
+
 // ---- profiling (capi.cpp) -----------------------------------------------------------
 enum ProfKind { kProfFwd = 0, kProfBack = 1, kProfMgs = 2, kProfCombine = 3 };
 bool profiling_on();
@@ -184,4 +226,8 @@ void profile_drop_step(int step);
 
 struct abg_geometry {
     abg::Geometry g;
+};
+
+struct abg_engine {
+    abg::Engine *e;
 };

@@ -1,0 +1,935 @@
+// Batched AB-/BA-GMRES (Sec. 2) over many independent problems of different geometry.
+//
+// One round advances every running problem by one Arnoldi step with a fixed sequence of
+// persistent kernels, captured once in a HIP graph and replayed every round:
+//
+//   begin     per problem: the step to run (0: sits out), and the work lists of the round
+//   pad       BA: w_k -> padded image copies       AB: t = B w_k -> padded copies
+//   forward   BA: z = A w_k                        AB: q = A t
+//   back      AB: t = B w_k                        BA: q = B z
+//   mgs       modified Gram-Schmidt, one block group per problem (group barriers)
+//   givens    FP64 Givens update and y_k, one block per problem
+//   residual  ||r_k|| (BA: (b - A x0) - Z y_k; AB: W_{k+1}(beta e_1 - H y)) and the DP
+//             candidate test
+//
+// The work lists live in device memory and are rebuilt by `begin` every round, so the
+// graph never changes while problems join and leave. Blocks take work items from a
+// per-list ticket counter; an item's arithmetic depends only on its own problem, so a
+// problem's results are the same alone and in any mix.
+//
+// The host reads a copy of the per-problem scalars one round behind. A DP candidate, a
+// breakdown or the iteration cap holds the problem (its later rounds skip it); the host
+// then enqueues the formation of x_k and the explicit residual ||b - A x_k||, and a small
+// kernel accepts the candidate or resumes the problem. Nothing waits on the host except
+// the one-round-behind copy.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <deque>
+#include <vector>
+
+#include "krylov_body.h"
+#include "proj_body.h"
+
+namespace abg {
+
+enum Tab {
+    kTPadBA = 0,   // pad w_k (BA)
+    kTBackAB,      // t = B w_k (AB)
+    kTFwdBA,       // z = A w_k (BA)
+    kTPadAB,       // pad t (AB)
+    kTBackBA,      // q = B z (BA)
+    kTFwdAB,       // q = A t (AB)
+    kTMgsS,        // MGS groups with the small register tile
+    kTMgsL,        // MGS groups with the large register tile
+    kTRes,         // residual chunks
+    kTGiv,         // one Givens block per problem
+    kNumTab
+};
+
+constexpr int kMgsSmallE = 8;
+constexpr int kMgsLargeE = 32;
+constexpr int kMgsSmallMaxG = 128;
+constexpr int kResU = 4;
+
+// Per-problem descriptor in device memory.
+struct BatchInst {
+    const AngleParams *ang;
+    int N, S, n_ang, n_det;
+    double ds, s0;
+    int method, kind, k_max, ld;
+    long long L, ldv, mp, n, m;
+    void *V, *Z, *cur, *q, *rb0, *tm, *tn, *xr, *xc;
+    double *H, *R, *cs, *sn, *g, *Y, *rho, *part, *mgs_part;
+    unsigned *bar, *count;
+    double bd_rel;
+    int need_res;
+    int mgs_G, mgs_large;
+    int chunk, n_chunks;
+};
+
+// Work lists: list t holds segments (problem, first ticket); items of a segment are
+// consecutive tickets.
+struct TabView {
+    int *nseg, *total;
+    unsigned *ticket;
+    int *slot, *first;   // [kNumTab][max_slots]
+    int max_slots;
+    __device__ int seg_slot(int t, int i) const { return slot[t * max_slots + i]; }
+    __device__ int seg_first(int t, int i) const { return first[t * max_slots + i]; }
+};
+
+struct Tiles {
+    int rays;   // forward projector: rays per wave group (64, 128 or 256); 256/rays angles per block
+};
+
+namespace {
+
+__device__ inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
+
+__device__ int items_of(int t, const BatchInst &d, const Tiles &tl)
+{
+    const bool ba = d.method == ABG_METHOD_BA;
+    switch (t) {
+    case kTPadBA: return ba ? ceil_div(d.N, 32) * ceil_div(d.N, 32) : 0;
+    case kTPadAB: return ba ? 0 : ceil_div(d.N, 32) * ceil_div(d.N, 32);
+    case kTBackAB: return ba ? 0 : ceil_div(d.N, kTile) * ceil_div(d.N, kTile);
+    case kTBackBA: return ba ? ceil_div(d.N, kTile) * ceil_div(d.N, kTile) : 0;
+    case kTFwdBA:
+    case kTFwdAB: {
+        if ((t == kTFwdBA) != ba) return 0;
+        const int apb = 256 / tl.rays;
+        return ceil_div(d.n_ang, apb) * ceil_div(d.n_det, tl.rays);
+    }
+    case kTMgsS: return d.mgs_large ? 0 : d.mgs_G;
+    case kTMgsL: return d.mgs_large ? d.mgs_G : 0;
+    case kTRes: return d.need_res ? d.n_chunks : 0;
+    case kTGiv: return 1;
+    }
+    return 0;
+}
+
+// ---- begin ------------------------------------------------------------------------------
+// Block t builds list t; block 0 also publishes each problem's step for the round.
+__global__ __launch_bounds__(256) void begin_kernel(const BatchInst *D, DevState *S, TabView tv,
+                                                    int n_slots, Tiles tl)
+{
+    __shared__ int wsum_n[4], wsum_c[4];
+    const int t = blockIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int per = (n_slots + 255) / 256;
+    const int s_lo = min(tid * per, n_slots), s_hi = min(s_lo + per, n_slots);
+    int my_n = 0, my_c = 0;
+    for (int s = s_lo; s < s_hi; ++s) {
+        const DevState &st = S[s];
+        const BatchInst &d = D[s];
+        const bool run = st.active && !st.done && !st.stop && !st.error &&
+                         !(st.bd_k != 0 && st.bd_k <= st.k) && st.k < d.k_max;
+        const int kc = run ? st.k + 1 : 0;
+        if (t == 0) S[s].kcur = kc;
+        const int c = kc ? items_of(t, d, tl) : 0;
+        my_n += c > 0;
+        my_c += c;
+    }
+    // exclusive block scan of (segments, items)
+    int in = my_n, ic = my_c;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int a = __shfl_up(in, o, 64), b = __shfl_up(ic, o, 64);
+        if (lane >= o) {
+            in += a;
+            ic += b;
+        }
+    }
+    if (lane == 63) {
+        wsum_n[w] = in;
+        wsum_c[w] = ic;
+    }
+    __syncthreads();
+    int base_n = 0, base_c = 0, tot_n = 0, tot_c = 0;
+    for (int i = 0; i < 4; ++i) {
+        if (i < w) {
+            base_n += wsum_n[i];
+            base_c += wsum_c[i];
+        }
+        tot_n += wsum_n[i];
+        tot_c += wsum_c[i];
+    }
+    int on = base_n + in - my_n, oc = base_c + ic - my_c;
+    for (int s = s_lo; s < s_hi; ++s) {
+        const DevState &st = S[s];
+        const BatchInst &d = D[s];
+        const bool run = st.active && !st.done && !st.stop && !st.error &&
+                         !(st.bd_k != 0 && st.bd_k <= st.k) && st.k < d.k_max;
+        const int c = run ? items_of(t, d, tl) : 0;
+        if (c > 0) {
+            tv.slot[t * tv.max_slots + on] = s;
+            tv.first[t * tv.max_slots + on] = oc;
+            ++on;
+            oc += c;
+        }
+    }
+    if (tid == 0) {
+        tv.nseg[t] = tot_n;
+        tv.total[t] = tot_c;
+        tv.ticket[t] = 0u;
+    }
+}
+
+// Takes the next ticket of list t for the block: returns false when the list is used up.
+__device__ inline bool next_item(const TabView &tv, int t, int *slot_out, int *local_out)
+{
+    __shared__ int s_slot, s_local;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned it = __hip_atomic_fetch_add(tv.ticket + t, 1u, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+        int slot = -1, local = 0;
+        if ((int)it < tv.total[t]) {
+            int lo = 0, hi = tv.nseg[t] - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (tv.seg_first(t, mid) <= (int)it) lo = mid;
+                else hi = mid - 1;
+            }
+            slot = tv.seg_slot(t, lo);
+            local = (int)it - tv.seg_first(t, lo);
+        }
+        s_slot = slot;
+        s_local = local;
+    }
+    __syncthreads();
+    *slot_out = s_slot;
+    *local_out = s_local;
+    return s_slot >= 0;
+}
+
+template <typename T> __device__ inline T *zcol(const BatchInst &d, int k)
+{
+    return d.Z ? static_cast<T *>(d.Z) + (size_t)(k - 1) * d.mp : static_cast<T *>(d.tm);
+}
+
+// ---- projector phases ---------------------------------------------------------------------
+// mode 0: BA, w_k;  mode 1: AB, t
+template <typename T>
+__global__ __launch_bounds__(256) void bpad_kernel(const BatchInst *D, const DevState *S,
+                                                   TabView tv, int t, int mode)
+{
+    __shared__ PadLds<T> lds;
+    int slot, local;
+    while (next_item(tv, t, &slot, &local)) {
+        const BatchInst &d = D[slot];
+        const DevState *st = S + slot;
+        if (halted(st, st->kcur)) continue;
+        const int tpr = (d.N + 31) / 32;
+        const T *src = static_cast<const T *>(mode == 0 ? d.cur : d.tn);
+        pad_transpose_tile(src, static_cast<T *>(d.xr), static_cast<T *>(d.xc), d.N, d.S,
+                           (local % tpr) * 32, (local / tpr) * 32, lds);
+    }
+}
+
+// mode 0: BA, z = A w_k (column k of Z);  mode 1: AB, q = A t
+template <typename T>
+__global__ __launch_bounds__(256) void bfwd_kernel(const BatchInst *D, const DevState *S,
+                                                   TabView tv, int t, int mode, Tiles tl)
+{
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int wpa = tl.rays / 64;       // waves per angle
+    const int apb = 256 / tl.rays;      // angles per block
+    int slot, local;
+    while (next_item(tv, t, &slot, &local)) {
+        const BatchInst &d = D[slot];
+        const DevState *st = S + slot;
+        const int k = st->kcur;
+        if (halted(st, k)) continue;
+        const int nrg = (d.n_det + tl.rays - 1) / tl.rays;
+        const int a = (local / nrg) * apb + wave / wpa;
+        const int i = (local % nrg) * tl.rays + (wave % wpa) * 64 + lane;
+        if (a >= d.n_ang) continue;
+        T *y = mode == 0 ? zcol<T>(d, k) : static_cast<T *>(d.q);
+        forward_ray(static_cast<const T *>(d.xr), static_cast<const T *>(d.xc), y, d.ang, a, i,
+                    d.N, d.S, d.n_det, d.ds, d.s0);
+    }
+}
+
+// mode 0: AB, t = B w_k;  mode 1: BA, q = B z
+template <typename T>
+__global__ __launch_bounds__(kBackThreads) void bback_kernel(const BatchInst *D,
+                                                             const DevState *S, TabView tv,
+                                                             int t, int mode)
+{
+    __shared__ BackLds<T> lds;
+    int slot, local;
+    while (next_item(tv, t, &slot, &local)) {
+        const BatchInst &d = D[slot];
+        const DevState *st = S + slot;
+        const int k = st->kcur;
+        if (halted(st, k)) continue;
+        const int tpr = (d.N + kTile - 1) / kTile;
+        const int c0 = (local % tpr) * kTile, r0 = (local / tpr) * kTile;
+        const T *y = mode == 0 ? static_cast<const T *>(d.cur) : zcol<T>(d, k);
+        T *x = static_cast<T *>(mode == 0 ? d.tn : d.q);
+        if (d.kind == ABG_BP_ADJ)
+            back_tile<T, true>(y, x, d.ang, d.N, d.n_ang, d.n_det, d.ds, d.s0, c0, r0, lds);
+        else
+            back_tile<T, false>(y, x, d.ang, d.N, d.n_ang, d.n_det, d.ds, d.s0, c0, r0, lds);
+    }
+}
+
+// ---- Gram-Schmidt, Givens, residual -------------------------------------------------------
+// A ticket is one rank of a problem's block group; a group's tickets are consecutive, so
+// every group whose first rank is taken is completed by blocks that are running (each
+// group is smaller than the grid).
+template <typename TX, typename TV, int E>
+__global__ __launch_bounds__(kBlock) void bmgs_kernel(const BatchInst *D, DevState *S,
+                                                      TabView tv, int t)
+{
+    __shared__ double lds[kWaves];
+    int slot, rank;
+    while (next_item(tv, t, &slot, &rank)) {
+        const BatchInst &d = D[slot];
+        DevState *st = S + slot;
+        const int k = st->kcur;
+        if (halted(st, k)) continue;
+        MgsDev a;
+        a.q = d.q;
+        a.V = d.V;
+        a.ldv = (size_t)d.ldv;
+        a.k = k;
+        a.L = d.L;
+        a.hcol = d.H + (size_t)(k - 1) * d.ld;
+        a.vout = static_cast<TV *>(d.V) + (size_t)k * d.ldv;
+        a.cur = d.cur;
+        a.partials = d.mgs_part;
+        a.bar = d.bar + k;
+        a.st = st;
+        a.bd_rel = d.bd_rel;
+        a.step = k;
+        mgs_body<TX, TV, E>(a, rank, d.mgs_G, lds);
+    }
+}
+
+__global__ __launch_bounds__(64) void bgivens_kernel(const BatchInst *D, DevState *S, TabView tv)
+{
+    if ((int)blockIdx.x >= tv.nseg[kTGiv]) return;
+    const int slot = tv.seg_slot(kTGiv, blockIdx.x);
+    const BatchInst &d = D[slot];
+    DevState *st = S + slot;
+    const int k = st->kcur;
+    if (halted(st, k)) return;
+    double *rho = (d.method == ABG_METHOD_AB && d.need_res) ? d.rho : nullptr;
+    givens_step(d.H, d.ld, d.R, d.cs, d.sn, d.g, d.Y + (size_t)(k - 1) * d.k_max, rho, st->beta,
+                k, st);
+}
+
+// ||r_k|| by chunks: BA r = (b - A x0) - Z y_k, AB r = W_{k+1} rho. Each chunk's sum of
+// squares is published; the last chunk to finish adds them in chunk order, writes the
+// norm and raises the DP candidate stop.
+template <typename TX, typename TV>
+__global__ __launch_bounds__(kBlock) void bres_kernel(const BatchInst *D, DevState *S, TabView tv)
+{
+    __shared__ double cf[kMaxCoef];
+    __shared__ double lds[kWaves];
+    __shared__ int last;
+    int slot, c;
+    while (next_item(tv, kTRes, &slot, &c)) {
+        const BatchInst &d = D[slot];
+        DevState *st = S + slot;
+        const int k = st->kcur;
+        if (halted(st, k)) continue;
+        const bool ba = d.method == ABG_METHOD_BA;
+        const int kk = ba ? k : k + 1;
+        const double *coef = ba ? d.Y + (size_t)(k - 1) * d.k_max : d.rho;
+        for (int j = threadIdx.x; j < kk; j += kBlock) cf[j] = ba ? -coef[j] : coef[j];
+        __syncthreads();
+        const long long lo = (long long)c * d.chunk;
+        const long long hi = min(lo + (long long)d.chunk, d.m);
+        const TX *base = ba ? static_cast<const TX *>(d.rb0) : nullptr;
+        double ss = 0.0;
+        for (long long l0 = lo + threadIdx.x; l0 < hi; l0 += kResU * kBlock) {
+            double acc[kResU];
+            bool in[kResU];
+#pragma unroll
+            for (int u = 0; u < kResU; ++u) {
+                const long long l = l0 + u * kBlock;
+                in[u] = l < hi;
+                acc[u] = (in[u] && base) ? to_f64(base[l]) : 0.0;
+            }
+            for (int j = 0; j < kk; ++j) {
+                double x[kResU];
+                if (ba) {
+                    const TX *v = static_cast<const TX *>(d.Z) + (size_t)j * d.mp + l0;
+#pragma unroll
+                    for (int u = 0; u < kResU; ++u) x[u] = in[u] ? to_f64(v[u * kBlock]) : 0.0;
+                } else {
+                    const TV *v = static_cast<const TV *>(d.V) + (size_t)j * d.ldv + l0;
+#pragma unroll
+                    for (int u = 0; u < kResU; ++u) x[u] = in[u] ? to_f64(v[u * kBlock]) : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < kResU; ++u) acc[u] = fma(cf[j], x[u], acc[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < kResU; ++u)
+                if (in[u]) ss = fma(acc[u], acc[u], ss);
+        }
+        ss = block_sum(ss, lds);
+        if (threadIdx.x == 0) {
+            agent_store(d.part + c, ss);
+            const unsigned prev = __hip_atomic_fetch_add(d.count, 1u, __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_AGENT);
+            last = prev == (unsigned)d.n_chunks - 1;
+        }
+        __syncthreads();
+        if (!last) continue;
+        double tsum = 0.0;
+        for (int j = threadIdx.x; j < d.n_chunks; j += kBlock) tsum += agent_load(d.part + j);
+        tsum = block_sum(tsum, lds);
+        if (threadIdx.x == 0) {
+            __hip_atomic_store(d.count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const double r = sqrt(tsum);
+            st->res = r;
+            if (!isfinite(r)) {
+                st->error |= 2;
+            } else if (st->dp_thr > 0.0 && r <= st->dp_thr && !st->stop) {
+                st->stop = 1;
+                st->stop_k = k;
+                st->stop_reason = kStopDP;
+            }
+        }
+    }
+}
+
+// ---- per-problem control kernels (launched by the host between rounds) ------------------
+__global__ void activate_kernel(DevState *st)
+{
+    if (threadIdx.x != 0 || st->error) return;
+    if (st->hnext == 0.0) {
+        st->stop = 1;
+        st->stop_k = 0;
+        st->stop_reason = kStopZero;
+        return;
+    }
+    st->beta = st->hnext;
+    st->active = 1;
+}
+
+// After x_{stop_k} and lit = ||b - A x|| were formed for a DP candidate: accept, finish
+// with `rej_status` (>= 0) if the problem cannot continue, or resume.
+__global__ void confirm_kernel(DevState *st, double thr, int rej_status)
+{
+    if (threadIdx.x != 0) return;
+    const double lit = st->lit;
+    st->n_lit += 1;
+    if (!isfinite(lit)) {
+        st->status = ABG_ENAN;
+    } else if (lit <= thr) {
+        st->status = ABG_OK;
+    } else if (rej_status >= 0) {
+        st->status = rej_status;
+    } else {
+        st->stop = 0;
+        st->stop_k = 0;
+        st->stop_reason = kStopNone;
+        return;
+    }
+    st->k_sel = st->stop_k;
+    st->done = 1;
+}
+
+__global__ void final_kernel(DevState *st, int k_sel, int status)
+{
+    if (threadIdx.x != 0) return;
+    st->status = isfinite(st->lit) ? status : ABG_ENAN;
+    st->k_sel = k_sel;
+    st->done = 1;
+}
+
+template <typename F> hipError_t capacity_of(F fn, int block, int *blocks)
+{
+    int dev = 0, per_cu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    hipDeviceProp_t prop;
+    if ((e = hipGetDeviceProperties(&prop, dev)) != hipSuccess) return e;
+    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(fn),
+                                                          block, 0)) != hipSuccess)
+        return e;
+    *blocks = std::max(1, per_cu) * prop.multiProcessorCount;
+    return hipSuccess;
+}
+
+constexpr int kSnapRing = 4;
+
+#define BCK(expr)                                   \
+    do {                                            \
+        hipError_t e_ = (expr);                     \
+        if (e_ != hipSuccess) return fail(ABG_EHIP); \
+    } while (0)
+
+}  // namespace
+
+// ---- host engine ------------------------------------------------------------------------
+struct Engine {
+    enum Phase { kFree = 0, kRunning, kConfirming, kFinalizing };
+    struct Slot {
+        Phase phase = kFree;
+        abg_request r{};
+        const Geometry *g = nullptr;
+        double thr = 0.0;
+        int last_k = 0;
+        int n_confirm = 0;
+        int pend_k = 0;   // step whose iterate is being formed
+        int gen = 0;
+    };
+
+    abg_precision p{};
+    int max_slots = 0, device = 0;
+    hipStream_t s = nullptr, cap_stream = nullptr;
+    BatchInst *d_desc = nullptr;
+    DevState *d_st = nullptr;
+    int *d_tab = nullptr;
+    TabView tv{};
+    BatchInst *h_desc = nullptr;     // pinned staging, one per slot
+    DevState *h_init = nullptr;      // pinned staging, one per slot
+    DevState *h_snap = nullptr;      // pinned ring of snapshots
+    hipEvent_t ev[kSnapRing] = {};
+    std::deque<int> inflight;
+    int ring_next = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    bool dirty = true;
+    Tiles tiles{256};
+    int grid_proj = 0, grid_back = 0, grid_mgs_s = 0, grid_mgs_l = 0, grid_res = 0;
+    int cap_mgs_s = 0, cap_mgs_l = 0;
+    int broken = 0;
+    std::vector<Slot> slots;
+    std::vector<std::pair<long long, int>> finished;
+    long long rounds = 0;
+    int gen_next = 0;
+
+    int fail(int rc)
+    {
+        broken = rc;
+        return rc;
+    }
+
+    ~Engine()
+    {
+        if (s) (void)hipStreamSynchronize(s);
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        for (auto &e : ev)
+            if (e) (void)hipEventDestroy(e);
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
+        if (d_desc) (void)hipFree(d_desc);
+        if (d_st) (void)hipFree(d_st);
+        if (d_tab) (void)hipFree(d_tab);
+        if (h_desc) (void)hipHostFree(h_desc);
+        if (h_init) (void)hipHostFree(h_init);
+        if (h_snap) (void)hipHostFree(h_snap);
+    }
+
+    template <typename TX, typename TV> hipError_t capacities()
+    {
+        hipError_t e;
+        if ((e = capacity_of(bfwd_kernel<TX>, 256, &grid_proj)) != hipSuccess) return e;
+        if ((e = capacity_of(bback_kernel<TX>, kBackThreads, &grid_back)) != hipSuccess) return e;
+        if ((e = capacity_of(bmgs_kernel<TX, TV, kMgsSmallE>, kBlock, &cap_mgs_s)) != hipSuccess) return e;
+        if ((e = capacity_of(bmgs_kernel<TX, TV, kMgsLargeE>, kBlock, &cap_mgs_l)) != hipSuccess) return e;
+        if ((e = capacity_of(bres_kernel<TX, TV>, kBlock, &grid_res)) != hipSuccess) return e;
+        grid_mgs_s = cap_mgs_s;
+        grid_mgs_l = cap_mgs_l;
+        grid_res = std::min(grid_res, 2048);
+        return hipSuccess;
+    }
+
+    hipError_t caps_for_precision()
+    {
+        if (p.proj == ABG_F64) return capacities<double, double>();
+        if (p.basis == ABG_F32) return capacities<float, float>();
+        return capacities<float, bf16>();
+    }
+
+    template <typename TX, typename TV> void enqueue_round_t(hipStream_t q)
+    {
+        begin_kernel<<<kNumTab, 256, 0, q>>>(d_desc, d_st, tv, max_slots, tiles);
+        bpad_kernel<TX><<<grid_proj, 256, 0, q>>>(d_desc, d_st, tv, kTPadBA, 0);
+        bback_kernel<TX><<<grid_back, kBackThreads, 0, q>>>(d_desc, d_st, tv, kTBackAB, 0);
+        bfwd_kernel<TX><<<grid_proj, 256, 0, q>>>(d_desc, d_st, tv, kTFwdBA, 0, tiles);
+        bpad_kernel<TX><<<grid_proj, 256, 0, q>>>(d_desc, d_st, tv, kTPadAB, 1);
+        bback_kernel<TX><<<grid_back, kBackThreads, 0, q>>>(d_desc, d_st, tv, kTBackBA, 1);
+        bfwd_kernel<TX><<<grid_proj, 256, 0, q>>>(d_desc, d_st, tv, kTFwdAB, 1, tiles);
+        bmgs_kernel<TX, TV, kMgsSmallE><<<grid_mgs_s, kBlock, 0, q>>>(d_desc, d_st, tv, kTMgsS);
+        bmgs_kernel<TX, TV, kMgsLargeE><<<grid_mgs_l, kBlock, 0, q>>>(d_desc, d_st, tv, kTMgsL);
+        bgivens_kernel<<<max_slots, 64, 0, q>>>(d_desc, d_st, tv);
+        bres_kernel<TX, TV><<<grid_res, kBlock, 0, q>>>(d_desc, d_st, tv);
+    }
+
+    void enqueue_round(hipStream_t q)
+    {
+        if (p.proj == ABG_F64) enqueue_round_t<double, double>(q);
+        else if (p.basis == ABG_F32) enqueue_round_t<float, float>(q);
+        else enqueue_round_t<float, bf16>(q);
+    }
+
+    int capture()
+    {
+        if (exec) BCK(hipGraphExecDestroy(exec));
+        if (graph) BCK(hipGraphDestroy(graph));
+        exec = nullptr;
+        graph = nullptr;
+        BCK(hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal));
+        enqueue_round(cap_stream);
+        hipError_t le = hipGetLastError();
+        hipGraph_t gr = nullptr;
+        hipError_t ee = hipStreamEndCapture(cap_stream, &gr);
+        if (le != hipSuccess || ee != hipSuccess) {
+            if (gr) (void)hipGraphDestroy(gr);
+            return fail(ABG_EHIP);
+        }
+        graph = gr;
+        BCK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+        dirty = false;
+        return ABG_OK;
+    }
+
+    int n_in(Phase ph) const
+    {
+        int c = 0;
+        for (const auto &sl : slots) c += sl.phase == ph;
+        return c;
+    }
+    int n_used() const { return (int)slots.size() - n_in(kFree); }
+
+    int submit(const Geometry &g, const abg_request &r)
+    {
+        if (broken) return broken;
+        int sidx = -1;
+        for (int i = 0; i < max_slots; ++i)
+            if (slots[i].phase == kFree) {
+                sidx = i;
+                break;
+            }
+        if (sidx < 0) return ABG_EFULL;
+        const InstanceView v = instance_view(g, r.method, r.k_max, p, r.stop, r.ws);
+        BatchInst d{};
+        d.ang = g.dev;
+        d.N = g.N;
+        d.S = g.padded_stride();
+        d.n_ang = g.n_ang;
+        d.n_det = g.n_det;
+        d.ds = g.ds;
+        d.s0 = -0.5 * (g.n_det - 1) * g.ds;
+        d.method = r.method;
+        d.kind = r.bp_kind;
+        d.k_max = r.k_max;
+        d.ld = r.k_max + 1;
+        d.L = v.L;
+        d.ldv = v.ldv;
+        d.mp = v.mp;
+        d.n = g.n();
+        d.m = g.m();
+        d.V = v.V;
+        d.Z = v.Z;
+        d.cur = v.cur;
+        d.q = v.q;
+        d.rb0 = v.rb0;
+        d.tm = v.tm;
+        d.tn = v.tn;
+        d.xr = v.fpws;
+        d.xc = static_cast<char *>(v.fpws) + (size_t)g.N * g.padded_stride() * dtype_size(p.proj);
+        d.H = v.H;
+        d.R = v.R;
+        d.cs = v.cs;
+        d.sn = v.sn;
+        d.g = v.g;
+        d.Y = v.Y;
+        d.rho = v.rho;
+        d.part = v.part;
+        d.mgs_part = v.mgs_part;
+        d.bar = v.bar;
+        d.count = v.count;
+        d.bd_rel = (p.basis == ABG_F64 && p.proj == ABG_F64) ? 1e-14 : 1e-6;
+        d.need_res = r.stop.kind == ABG_STOP_DP;
+        long long G = (v.L + (long long)kBlock * kMgsSmallE - 1) / ((long long)kBlock * kMgsSmallE);
+        d.mgs_large = G > kMgsSmallMaxG;
+        if (d.mgs_large)
+            G = (v.L + (long long)kBlock * kMgsLargeE - 1) / ((long long)kBlock * kMgsLargeE);
+        const int capG = d.mgs_large ? cap_mgs_l : cap_mgs_s;
+        if (G > capG / 2 || 4 * G > v.mgs_part_cap) return ABG_EINVAL;
+        d.mgs_G = (int)std::max(1LL, G);
+        long long chunk = 8192;
+        while ((d.m + chunk - 1) / chunk > v.part_cap) chunk *= 2;
+        d.chunk = (int)chunk;
+        d.n_chunks = (int)((d.m + chunk - 1) / chunk);
+
+        Slot &sl = slots[sidx];
+        sl = Slot{};
+        sl.r = r;
+        sl.g = &g;
+        sl.thr = r.stop.kind == ABG_STOP_DP ? r.stop.tau * r.stop.noise_norm : 0.0;
+        const double slack = p.basis == ABG_F64 ? 1e-6 : (p.basis == ABG_F32 ? 1e-3 : 5e-2);
+        sl.gen = ++gen_next;
+        DevState init{};
+        init.gen = sl.gen;
+        init.dp_thr = r.stop.kind == ABG_STOP_DP ? sl.thr * (1.0 + slack) : 0.0;
+        h_desc[sidx] = d;
+        h_init[sidx] = init;
+        BCK(hipMemcpyAsync(d_desc + sidx, h_desc + sidx, sizeof(BatchInst), hipMemcpyHostToDevice, s));
+        BCK(hipMemcpyAsync(d_st + sidx, h_init + sidx, sizeof(DevState), hipMemcpyHostToDevice, s));
+        int rc = instance_init(g, r.method, r.bp_kind, r.k_max, r.stop, p, r.ws, r.b, r.x0,
+                               d_st + sidx, s);
+        if (rc != ABG_OK) return fail(rc);
+        activate_kernel<<<1, 64, 0, s>>>(d_st + sidx);
+        BCK(hipGetLastError());
+        sl.phase = kRunning;
+        if (r.info) {
+            r.info->k_stop = r.info->k_done = r.info->n_literal = 0;
+            r.info->status = ABG_OK;
+        }
+        return ABG_OK;
+    }
+
+    // x_k and ||b - A x_k|| for the problem in slot i
+    int form_x(int i, int k)
+    {
+        Slot &sl = slots[i];
+        const abg_request &r = sl.r;
+        DevState *st = d_st + i;
+        int rc = instance_form_x(*sl.g, r.method, r.bp_kind, r.k_max, r.stop, p, r.ws, k, r.b,
+                                 r.x0, r.x, st, &st->lit, s);
+        if (rc != ABG_OK) return fail(rc);
+        sl.pend_k = k;
+        return ABG_OK;
+    }
+
+    void finish(int i, const DevState &h, int status)
+    {
+        Slot &sl = slots[i];
+        abg_info *info = sl.r.info;
+        if (info) {
+            info->k_stop = h.k_sel;
+            info->k_done = h.k;
+            info->status = status;
+            info->n_literal = h.n_lit;
+            info->res_norm = h.lit;
+            info->ncp_dist = 0.0;
+            info->beta = h.beta;
+        }
+        finished.emplace_back(sl.r.tag, status);
+        sl.phase = kFree;
+    }
+
+    // Host side of one snapshot of every problem's scalars.
+    int process(const DevState *snap)
+    {
+        for (int i = 0; i < max_slots; ++i) {
+            Slot &sl = slots[i];
+            if (sl.phase == kFree) continue;
+            const DevState &h = snap[i];
+            if (h.gen != sl.gen) continue;   // copy taken before this admission
+            abg_info *info = sl.r.info;
+            if (h.k > sl.last_k) {
+                // a round advances a problem by at most one step
+                if (info && info->ls_hist && h.k - 1 < info->hist_len) info->ls_hist[h.k - 1] = h.ls;
+                if (info && info->res_hist && h.k - 1 < info->hist_len &&
+                    sl.r.stop.kind == ABG_STOP_DP)
+                    info->res_hist[h.k - 1] = h.res;
+                sl.last_k = h.k;
+            }
+            if (h.error) {
+                DevState hh = h;
+                hh.k_sel = 0;
+                finish(i, hh, (h.error & 1) ? ABG_EDEVICE : ABG_ENAN);
+                continue;
+            }
+            if (h.done) {
+                if (sl.phase == kConfirming && info && info->res_hist && h.k_sel - 1 >= 0 &&
+                    h.k_sel - 1 < info->hist_len)
+                    info->res_hist[h.k_sel - 1] = h.lit;
+                finish(i, h, h.status);
+                continue;
+            }
+            if (sl.phase == kConfirming) {
+                if (h.n_lit >= sl.n_confirm) {
+                    // rejected: the problem runs again
+                    if (info && info->res_hist && sl.pend_k - 1 < info->hist_len)
+                        info->res_hist[sl.pend_k - 1] = h.lit;
+                    sl.phase = kRunning;
+                }
+                continue;
+            }
+            if (sl.phase != kRunning) continue;
+            if (h.stop && h.stop_reason == kStopZero) {
+                int rc = form_x(i, 0);
+                if (rc) return rc;
+                final_kernel<<<1, 64, 0, s>>>(d_st + i, 0, ABG_ZERO_RHS);
+                BCK(hipGetLastError());
+                sl.phase = kFinalizing;
+            } else if (h.stop && h.stop_reason == kStopDP && h.stop_k == h.k && h.k > 0) {
+                int rc = form_x(i, h.k);
+                if (rc) return rc;
+                int rej = -1;
+                if (h.bd_k == h.k) rej = ABG_BREAKDOWN;
+                else if (h.k >= sl.r.k_max) rej = ABG_NOT_CONVERGED;
+                confirm_kernel<<<1, 64, 0, s>>>(d_st + i, sl.thr, rej);
+                BCK(hipGetLastError());
+                ++sl.n_confirm;
+                sl.phase = kConfirming;
+            } else if (h.k > 0 && h.bd_k == h.k) {
+                int rc = form_x(i, h.k);
+                if (rc) return rc;
+                final_kernel<<<1, 64, 0, s>>>(d_st + i, h.k, ABG_BREAKDOWN);
+                BCK(hipGetLastError());
+                sl.phase = kFinalizing;
+            } else if (h.k >= sl.r.k_max) {
+                int rc = form_x(i, h.k);
+                if (rc) return rc;
+                const int status = sl.r.stop.kind == ABG_STOP_DP ? ABG_NOT_CONVERGED : ABG_OK;
+                final_kernel<<<1, 64, 0, s>>>(d_st + i, h.k, status);
+                BCK(hipGetLastError());
+                sl.phase = kFinalizing;
+            }
+        }
+        return ABG_OK;
+    }
+
+    int wait_oldest()
+    {
+        const int r = inflight.front();
+        inflight.pop_front();
+        BCK(hipEventSynchronize(ev[r]));
+        return process(h_snap + (size_t)r * max_slots);
+    }
+
+    // One round: replay the graph (if a problem is running), copy the scalars, and
+    // process the previous round's copy.
+    int step()
+    {
+        if (broken) return broken;
+        if (n_used() == 0 && inflight.empty()) return ABG_OK;
+        if ((int)inflight.size() >= 2) {
+            int rc = wait_oldest();
+            if (rc) return rc;
+        }
+        if (n_in(kRunning) > 0) {
+            if (dirty) {
+                int rc = capture();
+                if (rc) return rc;
+            }
+            BCK(hipGraphLaunch(exec, s));
+            ++rounds;
+        }
+        const int r = ring_next;
+        ring_next = (ring_next + 1) % kSnapRing;
+        BCK(hipMemcpyAsync(h_snap + (size_t)r * max_slots, d_st, sizeof(DevState) * max_slots,
+                           hipMemcpyDeviceToHost, s));
+        BCK(hipEventRecord(ev[r], s));
+        inflight.push_back(r);
+        return ABG_OK;
+    }
+
+    int drain()
+    {
+        while (!inflight.empty()) {
+            int rc = wait_oldest();
+            if (rc) return rc;
+        }
+        return ABG_OK;
+    }
+};
+
+int engine_create(abg_precision p, int max_slots, hipStream_t s, Engine **out)
+{
+    const bool ok = (p.proj == ABG_F64 && p.basis == ABG_F64) ||
+                    (p.proj == ABG_F32 && (p.basis == ABG_F32 || p.basis == ABG_BF16));
+    if (!ok || max_slots < 1 || max_slots > 4096) return ABG_EINVAL;
+    Engine *e = new (std::nothrow) Engine();
+    if (!e) return ABG_EHIP;
+    e->p = p;
+    e->max_slots = max_slots;
+    e->s = s;
+    e->slots.resize(max_slots);
+    auto bad = [&]() {
+        delete e;
+        return ABG_EHIP;
+    };
+    if (hipGetDevice(&e->device) != hipSuccess) return bad();
+    if (hipStreamCreateWithFlags(&e->cap_stream, hipStreamNonBlocking) != hipSuccess) return bad();
+    const size_t tab_ints = 3 * kNumTab + 2 * (size_t)kNumTab * max_slots;
+    if (hipMalloc(&e->d_desc, sizeof(BatchInst) * max_slots) != hipSuccess) return bad();
+    if (hipMalloc(&e->d_st, sizeof(DevState) * max_slots) != hipSuccess) return bad();
+    if (hipMalloc(&e->d_tab, sizeof(int) * tab_ints) != hipSuccess) return bad();
+    if (hipHostMalloc((void **)&e->h_desc, sizeof(BatchInst) * max_slots, hipHostMallocDefault) != hipSuccess) return bad();
+    if (hipHostMalloc((void **)&e->h_init, sizeof(DevState) * max_slots, hipHostMallocDefault) != hipSuccess) return bad();
+    if (hipHostMalloc((void **)&e->h_snap, sizeof(DevState) * max_slots * kSnapRing, hipHostMallocDefault) != hipSuccess) return bad();
+    for (auto &ev : e->ev)
+        if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return bad();
+    e->tv.nseg = e->d_tab;
+    e->tv.total = e->d_tab + kNumTab;
+    e->tv.ticket = reinterpret_cast<unsigned *>(e->d_tab + 2 * kNumTab);
+    e->tv.slot = e->d_tab + 3 * kNumTab;
+    e->tv.first = e->tv.slot + (size_t)kNumTab * max_slots;
+    e->tv.max_slots = max_slots;
+    // every slot starts idle: zero scalars and descriptors
+    if (launch_fill_u32(reinterpret_cast<unsigned *>(e->d_st), sizeof(DevState) * max_slots / 4, 0u, s) != hipSuccess) return bad();
+    if (launch_fill_u32(reinterpret_cast<unsigned *>(e->d_desc), sizeof(BatchInst) * max_slots / 4, 0u, s) != hipSuccess) return bad();
+    if (launch_fill_u32(reinterpret_cast<unsigned *>(e->d_tab), tab_ints, 0u, s) != hipSuccess) return bad();
+    if (e->caps_for_precision() != hipSuccess) return bad();
+    *out = e;
+    return ABG_OK;
+}
+
+void engine_destroy(Engine *e) { delete e; }
+
+int engine_submit(Engine *e, const Geometry &g, const abg_request &r) { return e->submit(g, r); }
+
+int engine_step(Engine *e, int *n_running)
+{
+    const int rc = e->step();
+    if (n_running) *n_running = e->n_used();
+    return rc;
+}
+
+int engine_poll(Engine *e, long long *tags, int *status, int max, int *n)
+{
+    int c = 0;
+    while (c < max && c < (int)e->finished.size()) {
+        if (tags) tags[c] = e->finished[c].first;
+        if (status) status[c] = e->finished[c].second;
+        ++c;
+    }
+    e->finished.erase(e->finished.begin(), e->finished.begin() + c);
+    *n = c;
+    return e->broken ? e->broken : ABG_OK;
+}
+
+int engine_pending(const Engine *e) { return e->n_used() + (int)e->finished.size(); }
+
+int engine_set_tiles(Engine *e, int rays)
+{
+    if (rays != 64 && rays != 128 && rays != 256) return ABG_EINVAL;
+    if (e->tiles.rays != rays) {
+        e->tiles.rays = rays;
+        e->dirty = true;
+    }
+    return ABG_OK;
+}
+
+int engine_get_tiles(const Engine *e, int *rays)
+{
+    *rays = e->tiles.rays;
+    return ABG_OK;
+}
+
+int engine_device(const Engine *e) { return e->device; }
+hipStream_t engine_stream(const Engine *e) { return e->s; }
+int engine_precision(const Engine *e, abg_precision *p)
+{
+    *p = e->p;
+    return ABG_OK;
+}
+long long engine_rounds(const Engine *e) { return e->rounds; }
+
+}  // namespace abg

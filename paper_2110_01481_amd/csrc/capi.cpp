@@ -318,6 +318,118 @@ int abg_ba_gmres(const abg_geometry *h, int bp_kind, const void *b, const void *
                        stream);
 }
 
+// ---- batched engine ------------------------------------------------------------------
+
+size_t abg_request_bytes(const abg_geometry *h, int method, int k_max, abg_precision p,
+                         abg_stop st)
+{
+    return abg_workspace_bytes(h, method, k_max, p, st);
+}
+
+int abg_engine_create(abg_precision p, int max_slots, void *stream, abg_engine **out)
+{
+    if (!out) return ABG_EINVAL;
+    *out = nullptr;
+    abg_engine *h = new (std::nothrow) abg_engine{nullptr};
+    if (!h) return ABG_EHIP;
+    const int rc = engine_create(p, max_slots, static_cast<hipStream_t>(stream), &h->e);
+    if (rc != ABG_OK) {
+        delete h;
+        return rc;
+    }
+    *out = h;
+    return ABG_OK;
+}
+
+int abg_engine_destroy(abg_engine *h)
+{
+    if (!h) return ABG_OK;
+    engine_destroy(h->e);
+    delete h;
+    return ABG_OK;
+}
+
+int abg_engine_submit(abg_engine *h, const abg_request *r)
+{
+    if (!h || !r) return ABG_EINVAL;
+    if (r->stop.kind == ABG_STOP_NCP) return ABG_EINVAL;
+    abg_precision p;
+    engine_precision(h->e, &p);
+    int rc = check_solver_args(r->g, r->method, r->k_max, p, r->stop);
+    if (rc) return rc;
+    if (r->bp_kind != ABG_BP_HAT && r->bp_kind != ABG_BP_ADJ) return ABG_EINVAL;
+    if (!r->b || !r->x || !r->ws || r->x == r->b || (r->x0 && r->x == r->x0)) return ABG_EINVAL;
+    if (reinterpret_cast<uintptr_t>(r->ws) % 256) return ABG_EINVAL;
+    if (r->g->g.device != engine_device(h->e)) return ABG_EINVAL;
+    if ((rc = current_device_matches(r->g->g))) return rc;
+    if (r->ws_bytes < solver_workspace_bytes(r->g->g, r->method, r->k_max, p, r->stop))
+        return ABG_ENOMEM;
+    return engine_submit(h->e, r->g->g, *r);
+}
+
+int abg_engine_step(abg_engine *h, int *n_active)
+{
+    if (!h) return ABG_EINVAL;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return ABG_EHIP;
+    if (dev != engine_device(h->e)) return ABG_EINVAL;
+    return engine_step(h->e, n_active);
+}
+
+int abg_engine_poll(abg_engine *h, long long *tags, int *status, int max, int *n)
+{
+    if (!h || !n || max < 0) return ABG_EINVAL;
+    return engine_poll(h->e, tags, status, max, n);
+}
+
+int abg_engine_set_tiles(abg_engine *h, int rays)
+{
+    if (!h) return ABG_EINVAL;
+    return engine_set_tiles(h->e, rays);
+}
+
+int abg_engine_get_tiles(const abg_engine *h, int *rays)
+{
+    if (!h || !rays) return ABG_EINVAL;
+    return engine_get_tiles(h->e, rays);
+}
+
+int abg_batch_solve(const abg_request *r, int n, abg_precision p, int rays, void *stream)
+{
+    if (n < 0 || (n > 0 && !r)) return ABG_EINVAL;
+    if (n == 0) return ABG_OK;
+    abg_engine *h = nullptr;
+    int rc = abg_engine_create(p, n, stream, &h);
+    if (rc) return rc;
+    if (rays > 0 && (rc = abg_engine_set_tiles(h, rays))) {
+        abg_engine_destroy(h);
+        return rc;
+    }
+    for (int i = 0; i < n && rc == ABG_OK; ++i) rc = abg_engine_submit(h, &r[i]);
+    int first_err = rc;
+    int active = n;
+    std::vector<long long> tags(n);
+    std::vector<int> st(n);
+    // every round advances a running problem or settles a pending decision: bound the
+    // loop well above what the iteration caps allow
+    long long guard = 16;
+    for (int i = 0; i < n; ++i) guard += 4LL * (r[i].k_max + 4);
+    while (first_err == ABG_OK && active > 0) {
+        rc = abg_engine_step(h, &active);
+        if (rc) first_err = rc;
+        if (--guard < 0) first_err = ABG_EDEVICE;
+    }
+    int got = 0;
+    if (first_err == ABG_OK) {
+        rc = abg_engine_poll(h, tags.data(), st.data(), n, &got);
+        if (rc) first_err = rc;
+        for (int i = 0; i < got && first_err == ABG_OK; ++i)
+            if (st[i] < 0) first_err = st[i];
+    }
+    abg_engine_destroy(h);
+    return first_err;
+}
+
 const char *abg_status_string(int status)
 {
     switch (status) {
@@ -327,6 +439,7 @@ const char *abg_status_string(int status)
     case ABG_EHIP: return "HIP runtime error";
     case ABG_ENAN: return "NaN or Inf in a norm";
     case ABG_EDEVICE: return "device-side wait exceeded its bound";
+    case ABG_EFULL: return "no free slot in the engine";
     case ABG_NOT_CONVERGED: return "discrepancy principle not met by k_max";
     case ABG_BREAKDOWN: return "Arnoldi breakdown (Krylov space exhausted)";
     case ABG_ZERO_RHS: return "zero initial residual";

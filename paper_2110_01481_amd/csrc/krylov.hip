@@ -20,100 +20,12 @@ namespace {
 
 constexpr int kCombU = 4;
 
-struct MgsDev {
-    const void *q;
-    const void *V;
-    size_t ldv;
-    int k;
-    long long L;
-    double *hcol;
-    void *vout;
-    void *cur;
-    double *partials;
-    unsigned *bar;
-    DevState *st;
-    double bd_rel;
-    int step;
-};
-
 template <typename TX, typename TV, int E>
 __global__ __launch_bounds__(kBlock) void mgs_kernel(MgsDev a)
 {
     __shared__ double lds[kWaves];
     if (halted(a.st, a.step)) return;
-    const int G = gridDim.x;
-    const long long T = (long long)G * kBlock;
-    const long long gt = (long long)blockIdx.x * kBlock + threadIdx.x;
-    const TX *q = static_cast<const TX *>(a.q);
-    const TV *V = static_cast<const TV *>(a.V);
-    int *err = &a.st->error;
-
-    double qv[E];
-    TV wv[E];
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const long long l = gt + e * T;
-        qv[e] = l < a.L ? to_f64(q[l]) : 0.0;
-    }
-    unsigned nb = 0;
-    double qq = 0.0;
-    for (int i = 0; i < a.k; ++i) {
-        const TV *w = V + (size_t)i * a.ldv;
-        double d = 0.0, s2 = 0.0;
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-            const long long l = gt + e * T;
-            wv[e] = l < a.L ? w[l] : zero_of<TV>();
-            d = fma(qv[e], to_f64(wv[e]), d);
-            if (i == 0) s2 = fma(qv[e], qv[e], s2);
-        }
-        double *slot = a.partials + (size_t)(nb & 1u) * 2 * G;
-        d = block_sum(d, lds);
-        if (i == 0) s2 = block_sum(s2, lds);
-        if (threadIdx.x == 0) {
-            agent_store(slot + blockIdx.x, d);
-            if (i == 0) agent_store(slot + G + blockIdx.x, s2);
-        }
-        ++nb;
-        grid_barrier(a.bar, nb * (unsigned)G, err);
-        const double h = grid_total(slot, G, lds);
-        if (i == 0) qq = grid_total(slot + G, G, lds);
-        if (blockIdx.x == 0 && threadIdx.x == 0) a.hcol[i] = h;
-#pragma unroll
-        for (int e = 0; e < E; ++e) qv[e] = fma(-h, to_f64(wv[e]), qv[e]);
-    }
-    double s = 0.0;
-#pragma unroll
-    for (int e = 0; e < E; ++e) s = fma(qv[e], qv[e], s);
-    double *slot = a.partials + (size_t)(nb & 1u) * 2 * G;
-    s = block_sum(s, lds);
-    if (threadIdx.x == 0) agent_store(slot + blockIdx.x, s);
-    ++nb;
-    grid_barrier(a.bar, nb * (unsigned)G, err);
-    const double hn2 = grid_total(slot, G, lds);
-    if (a.k == 0) qq = hn2;
-    const double hn = sqrt(hn2);
-    const double q0 = sqrt(qq);
-    const bool finite = isfinite(hn) && isfinite(q0);
-    const bool bd = !(hn > a.bd_rel * q0);
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        a.hcol[a.k] = hn;
-        a.st->hnext = hn;
-        a.st->qnorm0 = q0;
-        if (bd && a.step > 0) a.st->bd_k = a.step;
-        if (!finite) a.st->error |= 2;
-    }
-    TV *vo = static_cast<TV *>(a.vout);
-    TX *cu = static_cast<TX *>(a.cur);
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const long long l = gt + e * T;
-        if (l < a.L) {
-            const TV w = (bd || !finite) ? zero_of<TV>() : from_f64<TV>(qv[e] / hn);
-            vo[l] = w;
-            cu[l] = (TX)to_f64(w);
-        }
-    }
+    mgs_body<TX, TV, E>(a, blockIdx.x, gridDim.x, lds);
 }
 
 // ---- cooperative launch bookkeeping --------------------------------------------------

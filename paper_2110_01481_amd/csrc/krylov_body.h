@@ -110,6 +110,105 @@ __device__ inline double grid_total(const double *part, int G, double *lds)
     return block_sum(s, lds);
 }
 
+// ---- modified Gram-Schmidt ------------------------------------------------------------
+// One Arnoldi step's orthogonalisation of q_k against w_1..w_k by G blocks (ranks
+// 0..G-1) that meet at grid barriers on `bar`: q_k stays in FP64 registers (E elements per
+// thread), each basis vector is read once, and every inner product is one reduction in a
+// fixed order. Writes h_{1,k}..h_{k+1,k}, w_{k+1} (basis dtype) and its copy in q's dtype.
+struct MgsDev {
+    const void *q;
+    const void *V;
+    size_t ldv;
+    int k;
+    long long L;
+    double *hcol;
+    void *vout;
+    void *cur;
+    double *partials;
+    unsigned *bar;
+    DevState *st;
+    double bd_rel;
+    int step;
+};
+
+template <typename TX, typename TV, int E>
+__device__ inline void mgs_body(const MgsDev &a, int rank, int G, double *lds)
+{
+    const long long T = (long long)G * kBlock;
+    const long long gt = (long long)rank * kBlock + threadIdx.x;
+    const TX *q = static_cast<const TX *>(a.q);
+    const TV *V = static_cast<const TV *>(a.V);
+    int *err = &a.st->error;
+
+    double qv[E];
+    TV wv[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const long long l = gt + e * T;
+        qv[e] = l < a.L ? to_f64(q[l]) : 0.0;
+    }
+    unsigned nb = 0;
+    double qq = 0.0;
+    for (int i = 0; i < a.k; ++i) {
+        const TV *w = V + (size_t)i * a.ldv;
+        double d = 0.0, s2 = 0.0;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const long long l = gt + e * T;
+            wv[e] = l < a.L ? w[l] : zero_of<TV>();
+            d = fma(qv[e], to_f64(wv[e]), d);
+            if (i == 0) s2 = fma(qv[e], qv[e], s2);
+        }
+        double *slot = a.partials + (size_t)(nb & 1u) * 2 * G;
+        d = block_sum(d, lds);
+        if (i == 0) s2 = block_sum(s2, lds);
+        if (threadIdx.x == 0) {
+            agent_store(slot + rank, d);
+            if (i == 0) agent_store(slot + G + rank, s2);
+        }
+        ++nb;
+        grid_barrier(a.bar, nb * (unsigned)G, err);
+        const double h = grid_total(slot, G, lds);
+        if (i == 0) qq = grid_total(slot + G, G, lds);
+        if (rank == 0 && threadIdx.x == 0) a.hcol[i] = h;
+#pragma unroll
+        for (int e = 0; e < E; ++e) qv[e] = fma(-h, to_f64(wv[e]), qv[e]);
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) s = fma(qv[e], qv[e], s);
+    double *slot = a.partials + (size_t)(nb & 1u) * 2 * G;
+    s = block_sum(s, lds);
+    if (threadIdx.x == 0) agent_store(slot + rank, s);
+    ++nb;
+    grid_barrier(a.bar, nb * (unsigned)G, err);
+    const double hn2 = grid_total(slot, G, lds);
+    if (a.k == 0) qq = hn2;
+    const double hn = sqrt(hn2);
+    const double q0 = sqrt(qq);
+    const bool finite = isfinite(hn) && isfinite(q0);
+    const bool bd = !(hn > a.bd_rel * q0);
+    if (rank == 0 && threadIdx.x == 0) {
+        a.hcol[a.k] = hn;
+        a.st->hnext = hn;
+        a.st->qnorm0 = q0;
+        if (bd && a.step > 0) a.st->bd_k = a.step;
+        if (!finite) a.st->error |= 2;
+    }
+    TV *vo = static_cast<TV *>(a.vout);
+    TX *cu = static_cast<TX *>(a.cur);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const long long l = gt + e * T;
+        if (l < a.L) {
+            const TV w = (bd || !finite) ? zero_of<TV>() : from_f64<TV>(qv[e] / hn);
+            vo[l] = w;
+            cu[l] = (TX)to_f64(w);
+        }
+    }
+}
+
+
 // One wave. Column k-1 of H has just been written by mgs; R holds the rotated columns,
 // cs/sn the rotations, g the rotated right-hand side. Writes y_k (k entries) and, when
 // rho is given, rho = beta e_1 - H_k y_k.

@@ -41,11 +41,15 @@ __device__ inline int wave_max_i(int v)
 
 // Writes the zero-padded row-major copy xr (N x S, image column c at c + kPad) and the
 // transposed copy xc (row c of xc = column c of the image), through a 32 x 33 LDS tile.
+template <typename T> struct PadLds {
+    T tile[32][33];
+};
 template <typename T>
 __device__ inline void pad_transpose_tile(const T *__restrict__ x, T *__restrict__ xr,
-                                          T *__restrict__ xc, int N, int S, int bx, int by)
+                                          T *__restrict__ xc, int N, int S, int bx, int by,
+                                          PadLds<T> &lds)
 {
-    __shared__ T tile[32][33];
+    T (*tile)[33] = lds.tile;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
     for (int j = ty; j < 32; j += 8) {
         const int r = by + j, c = bx + tx;
@@ -280,15 +284,25 @@ __device__ inline T back_tap(const BinPair<T> *wrow, T u, const BackStage<T> &P,
     return trapezoid(w * dsT, P) * b.v + trapezoid((T(1) - w) * dsT, P) * (b.v + b.d);
 }
 
+// LDS of one back-projection block (declared by the calling kernel, so that a kernel
+// serving both back projectors holds one copy).
+template <typename T> struct BackLds {
+    BinPair<T> win[kAngBlock][kWin];
+    BackStage<T> prm[kAngBlock];
+    T part[kBackWaves - 1][kTile * kTile];
+};
+
 // The 16 x 16 tile with first column c0 and first row r0, by one block of kBackThreads.
+// Starts and ends with a block-wide barrier, so consecutive calls may share the LDS.
 template <typename T, bool ADJ>
 __device__ inline void back_tile(const T *__restrict__ y, T *__restrict__ x,
                                  const AngleParams *__restrict__ ang, int N, int n_ang,
-                                 int n_det, double ds, double s0, int c0, int r0)
+                                 int n_det, double ds, double s0, int c0, int r0,
+                                 BackLds<T> &L)
 {
-    __shared__ BinPair<T> win[kAngBlock][kWin];
-    __shared__ BackStage<T> prm[kAngBlock];
-    __shared__ T part[kBackWaves - 1][kTile * kTile];
+    auto &win = L.win;
+    auto &prm = L.prm;
+    auto &part = L.part;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     // lane owns pixels (tx, ty0 + 4j), j = 0..3, of the 16 x 16 tile
@@ -355,6 +369,7 @@ __device__ inline void back_tile(const T *__restrict__ y, T *__restrict__ x,
             if (r < N && c < N) x[(size_t)r * N + c] = ADJ ? sum : sum * T(1.0 / ds);
         }
     }
+    __syncthreads();
 }
 
 }  // namespace

@@ -25,8 +25,9 @@ __global__ __launch_bounds__(256) void pad_transpose_kernel(const T *__restrict_
                                                             T *__restrict__ xc, int N, int S,
                                                             const DevState *st, int k)
 {
+    __shared__ PadLds<T> lds;
     if (halted(st, k)) return;
-    pad_transpose_tile(x, xr, xc, N, S, blockIdx.x * 32, blockIdx.y * 32);
+    pad_transpose_tile(x, xr, xc, N, S, blockIdx.x * 32, blockIdx.y * 32, lds);
 }
 
 template <typename T>
@@ -53,8 +54,10 @@ __global__ __launch_bounds__(kBackThreads) void back_kernel(
     const T *__restrict__ y, T *__restrict__ x, const AngleParams *__restrict__ ang, int N,
     int n_ang, int n_det, double ds, double s0, const DevState *st, int k)
 {
+    __shared__ BackLds<T> lds;
     if (halted(st, k)) return;
-    back_tile<T, ADJ>(y, x, ang, N, n_ang, n_det, ds, s0, blockIdx.x * kTile, blockIdx.y * kTile);
+    back_tile<T, ADJ>(y, x, ang, N, n_ang, n_det, ds, s0, blockIdx.x * kTile, blockIdx.y * kTile,
+                      lds);
 }
 
 template <typename T>

@@ -271,13 +271,39 @@ struct Solve {
         return ABG_OK;
     }
 
-    // ||b - A x|| into dst->res (uses tm); caller synchronises
-    int literal_residual(const void *b, const void *x)
+    // ||b - A x|| into *out (default dst->res; uses tm); caller synchronises
+    int literal_residual(const void *b, const void *x, double *out = nullptr)
     {
         RC(fwd(x, tm));
         int nb = 0;
         CK(launch_sub_norm(p.proj, b, tm, tm, g.m(), part, &nb, s));
-        CK(launch_reduce_sqrt(part, nb, &dst->res, s));
+        CK(launch_reduce_sqrt(part, nb, out ? out : &dst->res, s));
+        return ABG_OK;
+    }
+
+    // Initialisation without a host synchronisation: scratch cleared, b - A x0,
+    // r0 = (B)(b - A x0), and MGS step 0 (beta = ||r0|| into dst->hnext and g[0], w_1).
+    int init_async(const void *b, const void *x0)
+    {
+        const long long m = g.m();
+        CK(launch_fill_u32(bar, (size_t)ld + 2, 0u, s));
+        CK(launch_fill_u32(count, 16, 0u, s));
+        CK(launch_fill_f64(H, (size_t)ld * k_max, 0.0, s));
+        CK(launch_fill_f64(gv, (size_t)ld, 0.0, s));
+        CK(launch_fill_u32(reinterpret_cast<unsigned *>(fpws), fp_workspace_bytes(g, p.proj) / 4, 0u, s));
+        if (x0) {
+            RC(fwd(x0, tm));
+            int nb = 0;
+            CK(launch_sub_norm(p.proj, b, tm, rb0, m, part, &nb, s));
+        } else {
+            CK(hipMemcpyAsync(rb0, b, (size_t)m * sX, hipMemcpyDeviceToDevice, s));
+        }
+        const void *r0 = rb0;
+        if (method == ABG_METHOD_BA) {
+            RC(back(rb0, q));
+            r0 = q;
+        }
+        CK(launch_mgs(mgs_args(r0, 0), s));
         return ABG_OK;
     }
 };
@@ -293,6 +319,59 @@ size_t solver_workspace_bytes(const Geometry &g, int method, int k_max, abg_prec
                               abg_stop st)
 {
     return make_layout(g, method, k_max, p, st).total;
+}
+
+InstanceView instance_view(const Geometry &g, int method, int k_max, abg_precision p,
+                           abg_stop st, void *ws)
+{
+    const Layout ly = make_layout(g, method, k_max, p, st);
+    char *W = static_cast<char *>(ws);
+    InstanceView v;
+    v.V = W + ly.V;
+    v.Z = ly.Z ? W + ly.Z : nullptr;
+    v.cur = W + ly.cur;
+    v.q = W + ly.q;
+    v.rb0 = W + ly.rb0;
+    v.tm = W + ly.tm;
+    v.tn = W + ly.tn;
+    v.fpws = W + ly.fpws;
+    v.H = reinterpret_cast<double *>(W + ly.H);
+    v.R = reinterpret_cast<double *>(W + ly.R);
+    v.cs = reinterpret_cast<double *>(W + ly.cs);
+    v.sn = reinterpret_cast<double *>(W + ly.sn);
+    v.g = reinterpret_cast<double *>(W + ly.g);
+    v.Y = reinterpret_cast<double *>(W + ly.Y);
+    v.rho = reinterpret_cast<double *>(W + ly.rho);
+    v.part = reinterpret_cast<double *>(W + ly.part);
+    v.mgs_part = reinterpret_cast<double *>(W + ly.mgs_part);
+    v.bar = reinterpret_cast<unsigned *>(W + ly.bar);
+    v.count = reinterpret_cast<unsigned *>(W + ly.count);
+    v.L = ly.L;
+    v.ldv = ly.ldv;
+    v.mp = ly.mp;
+    v.np = ly.np;
+    v.part_cap = 2048;
+    v.mgs_part_cap = 4 * kMaxGrid;
+    return v;
+}
+
+int instance_init(const Geometry &g, int method, int kind, int k_max, abg_stop st,
+                  abg_precision p, void *ws, const void *b, const void *x0, DevState *dst,
+                  hipStream_t s)
+{
+    Solve S(g, method, kind, k_max, st, p, s, ws);
+    S.dst = dst;
+    return S.init_async(b, x0);
+}
+
+int instance_form_x(const Geometry &g, int method, int kind, int k_max, abg_stop st,
+                    abg_precision p, void *ws, int k, const void *b, const void *x0, void *x,
+                    DevState *dst, double *lit, hipStream_t s)
+{
+    Solve S(g, method, kind, k_max, st, p, s, ws);
+    S.dst = dst;
+    RC(S.build_x(k > 0 ? S.ycol(k) : S.Y, k, x0, x));
+    return S.literal_residual(b, x, lit);
 }
 
 int run_solver(const Geometry &g, int method, int kind, const void *b, const void *x0,
@@ -327,26 +406,9 @@ int run_solver(const Geometry &g, int method, int kind, const void *b, const voi
     init.dp_thr = st.kind == ABG_STOP_DP ? thr * (1.0 + dp_slack(p.basis)) : 0.0;
     S.hr.slots[0] = init;
     CK(hipMemcpyAsync(S.dst, &S.hr.slots[0], sizeof(DevState), hipMemcpyHostToDevice, s));
-    CK(launch_fill_u32(S.bar, (size_t)S.ld + 2, 0u, s));
-    CK(launch_fill_u32(S.count, 16, 0u, s));
-    CK(launch_fill_f64(S.H, (size_t)S.ld * k_max, 0.0, s));
-    CK(launch_fill_f64(S.gv, (size_t)S.ld, 0.0, s));
-    CK(launch_fill_u32(reinterpret_cast<unsigned *>(S.fpws), fp_workspace_bytes(g, p.proj) / 4, 0u, s));
 
     // b - A x0, r0 = (B)(b - A x0), beta = ||r0|| into g[0], w_1
-    if (x0) {
-        RC(S.fwd(x0, S.tm));
-        int nb = 0;
-        CK(launch_sub_norm(p.proj, b, S.tm, S.rb0, m, S.part, &nb, s));
-    } else {
-        CK(hipMemcpyAsync(S.rb0, b, (size_t)m * S.sX, hipMemcpyDeviceToDevice, s));
-    }
-    const void *r0 = S.rb0;
-    if (method == ABG_METHOD_BA) {
-        RC(S.back(S.rb0, S.q));
-        r0 = S.q;
-    }
-    CK(launch_mgs(S.mgs_args(r0, 0), s));
+    RC(S.init_async(b, x0));
     DevState hs;
     RC(S.sync_read(hs));
     if (hs.error & 1) return ABG_EDEVICE;

@@ -1,0 +1,220 @@
+"""GPU tests of the batched engine (abg_engine_* / abg_batch_solve through the C ABI).
+
+* A mix of small problems of different geometry, method, back projector and stopping
+  rule, solved together in FP64, against the FP64 oracle solving each one alone: same
+  stopping iteration and status, iterate within the FP64 bound of the single-solve tests.
+* A problem's result is bit-for-bit the same alone and in a mix, under continuous
+  admission through a few slots, and for every forward-projector tile shape.
+* The 64-problem batched workload at full size (FP32): every problem stops at the same
+  iteration as the single-solve path and its iterate agrees within 1e-4; the DP stopping
+  property holds for each.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+# (N, n_ang, n_det, range, method, kind, stop, eta, k_max, det_spacing, x0)
+MIX = [
+    (40, 48, 57, 180.0, "ab", "hat", "dp", 0.02, 40, 1.0, False),
+    (48, 60, 69, 120.0, "ba", "hat", "dp", 0.02, 40, 1.0, False),
+    (32, 36, 45, 180.0, "ab", "adj", "dp", 0.03, 40, 1.0, False),
+    (56, 72, 81, 180.0, "ba", "adj", "dp", 0.01, 40, 1.0, False),
+    (33, 41, 47, 180.0, "ab", "hat", "none", 0.01, 12, 1.0, False),
+    (64, 90, 91, 180.0, "ba", "hat", "none", 0.01, 10, 1.0, False),
+    (24, 30, 35, 180.0, "ab", "hat", "dp", 0.02, 40, 1.0, True),
+    (40, 50, 45, 180.0, "ba", "hat", "dp", 0.02, 40, 1.3, True),
+]
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+class _Case:
+    def __init__(self, i, spec):
+        N, n_ang, n_det, rng_deg, method, kind, stop, eta, k_max, ds, use_x0 = spec
+        self.method, self.kind, self.stop, self.k_max = method, kind, stop, k_max
+        self.go = O.Geometry(N, n_ang, n_det, ang_range=rng_deg, det_spacing=ds)
+        gen = W.rng(90, i, 0)
+        self.xb = W.ellipse_phantom(N, 4, gen)
+        self.b, self.enorm = W.add_noise(self.go.A(self.xb), eta, W.rng(90, i, 1).standard_normal(self.go.m))
+        self.x0 = 0.3 * self.xb.ravel() if use_x0 else None
+        self.spec = spec
+
+    def oracle(self):
+        f = O.ab_gmres if self.method == "ab" else O.ba_gmres
+        kw = dict(stop="dp", tau=1.02, noise_norm=self.enorm) if self.stop == "dp" else {}
+        return f(self.go.A, self.go.back(self.kind), self.b, self.k_max, x0=self.x0, **kw)
+
+    def problem(self, abg, dtype, tag=0, gg=None):
+        import torch
+        N, n_ang, n_det, rng_deg = self.spec[:4]
+        gg = gg or abg.Geometry(N, n_ang, n_det, ang_range=rng_deg, det_spacing=self.spec[9])
+        bt = torch.tensor(self.b, dtype=dtype, device="cuda")
+        x0 = torch.tensor(self.x0, dtype=dtype, device="cuda") if self.x0 is not None else None
+        return abg.Problem(g=gg, method=self.method, b=bt, k_max=self.k_max, stop=self.stop,
+                           tau=1.02, noise_norm=self.enorm, bp=self.kind, x0=x0, tag=tag)
+
+
+@pytest.fixture(scope="module")
+def mix():
+    return [_Case(i, s) for i, s in enumerate(MIX)]
+
+
+@pytest.fixture(scope="module")
+def oracle_results(mix):
+    return [c.oracle() for c in mix]
+
+
+def test_mix_fp64_matches_oracle(gpu_lib, mix, oracle_results):
+    import torch
+    abg = gpu_lib
+    probs = [c.problem(abg, torch.float64, tag=i) for i, c in enumerate(mix)]
+    eng = abg.Engine(proj="f64", basis="f64", max_slots=len(probs))
+    res = eng.run(probs)
+    for c, r, ref in zip(mix, res, oracle_results):
+        err = _rel(r.x.cpu().numpy(), ref.x)
+        print(c.spec, r.status, r.k_stop, ref.k_stop, f"{err:.2e}")
+        assert r.k_stop == ref.k_stop
+        assert r.status == ("ok" if ref.status == "ok" else ref.status)
+        assert err <= 1e-6
+        if c.stop == "dp":
+            thr = 1.02 * c.enorm
+            assert r.res_norm <= thr
+            assert abs(r.res_norm - ref.res_norms[-1]) <= 1e-8 * thr
+
+
+def test_alone_equals_mix_bitwise(gpu_lib, mix):
+    import torch
+    abg = gpu_lib
+    eng = abg.Engine(proj="f32", basis="f32", max_slots=len(mix))
+    in_mix = eng.run([c.problem(abg, torch.float32, tag=i) for i, c in enumerate(mix)])
+    for i in (0, 1, 3, 6):
+        alone = abg.Engine(proj="f32", basis="f32", max_slots=1).run([mix[i].problem(abg, torch.float32)])[0]
+        assert alone.k_stop == in_mix[i].k_stop and alone.status == in_mix[i].status
+        assert torch.equal(alone.x, in_mix[i].x), i
+        assert np.array_equal(alone.ls_hist, in_mix[i].ls_hist)
+
+
+def test_continuous_admission_through_few_slots(gpu_lib, mix):
+    """Eight problems through three slots, submitted as slots free up (slots are reused
+    while other problems are mid-solve): results equal the all-at-once mix bit for bit."""
+    import torch
+    abg = gpu_lib
+    ref = abg.Engine(proj="f32", basis="f32", max_slots=len(mix)).run(
+        [c.problem(abg, torch.float32) for c in mix])
+    eng = abg.Engine(proj="f32", basis="f32", max_slots=3)
+    queue = list(range(len(mix)))
+    tag_of = {}
+    done = {}
+    rounds = 0
+    while len(done) < len(mix):
+        while queue:
+            t = eng.submit(mix[queue[0]].problem(abg, torch.float32))
+            if t is None:
+                break
+            tag_of[t] = queue.pop(0)
+        eng.step()
+        for t, r in eng.poll():
+            done[tag_of[t]] = r
+        rounds += 1
+        assert rounds < 2000
+    for i in range(len(mix)):
+        assert done[i].k_stop == ref[i].k_stop
+        assert torch.equal(done[i].x, ref[i].x), i
+
+
+@pytest.mark.parametrize("rays", [64, 128])
+def test_tile_shape_does_not_change_results(gpu_lib, mix, rays):
+    import torch
+    abg = gpu_lib
+    base = abg.batch_solve([c.problem(abg, torch.float32) for c in mix], proj="f32", basis="f32")
+    other = abg.batch_solve([c.problem(abg, torch.float32) for c in mix], proj="f32", basis="f32",
+                            rays=rays)
+    for a, b in zip(base, other):
+        assert a.k_stop == b.k_stop and torch.equal(a.x, b.x)
+
+
+def test_fp32_and_bf16_basis_against_oracle(gpu_lib, mix, oracle_results):
+    """FP32 engine: same stopping iteration as the FP64 oracle and iterate within 1e-4.
+    BF16 basis: AB within 0.1; BA only reported. BA-GMRES with a BF16 basis is unstable
+    on these problems (the FP64 oracle with the same rounding of its stored basis vectors
+    shows the same error growth), so the single-solve BF16 tests pin that path against a
+    BF16-rounded oracle instead."""
+    import torch
+    abg = gpu_lib
+    r32 = abg.Engine(proj="f32", basis="f32", max_slots=8).run([c.problem(abg, torch.float32) for c in mix])
+    r16 = abg.Engine(proj="f32", basis="bf16", max_slots=8).run([c.problem(abg, torch.float32) for c in mix])
+    for c, a, h, ref in zip(mix, r32, r16, oracle_results):
+        e32 = _rel(a.x.double().cpu().numpy(), ref.x)
+        e16 = _rel(h.x.double().cpu().numpy(), ref.x)
+        print(c.spec[:8], "f32", a.k_stop, ref.k_stop, f"{e32:.1e}", "bf16", h.k_stop, f"{e16:.1e}")
+        assert a.k_stop == ref.k_stop
+        assert e32 <= 1e-4
+        assert np.isfinite(e16)
+        if c.method == "ab":
+            assert e16 <= 0.1
+
+
+def test_zero_rhs_nan_full_and_invalid(gpu_lib, mix):
+    import torch
+    abg = gpu_lib
+    c = mix[0]
+    eng = abg.Engine(proj="f32", basis="f32", max_slots=2)
+    pz = c.problem(abg, torch.float32)
+    pz.b = torch.zeros_like(pz.b)
+    pn = c.problem(abg, torch.float32)
+    pn.b = pn.b.clone()
+    pn.b[pn.b.numel() // 2] = float("nan")
+    res = eng.run([pz, pn])
+    assert res[0].status == "zero_rhs" and res[0].k_stop == 0
+    assert torch.count_nonzero(res[0].x) == 0
+    assert res[1].status == "enan"
+    # no free slot
+    eng2 = abg.Engine(proj="f32", basis="f32", max_slots=1)
+    assert eng2.submit(c.problem(abg, torch.float32)) is not None
+    assert eng2.submit(c.problem(abg, torch.float32)) is None
+    # precision pairs outside {f64/f64, f32/f32, f32/bf16}
+    with pytest.raises(abg.AbgError):
+        abg.Engine(proj="f64", basis="f32", max_slots=1)
+
+
+def _config4(abg, torch):
+    ws = W.batched_workloads()
+    cases = []
+    for w in ws:
+        gg = abg.Geometry(w.N, w.n_ang, w.n_det, ang_range=w.ang_range)
+        xt = torch.tensor(w.phantom().ravel(), dtype=torch.float32, device="cuda")
+        bc = gg.fp(xt).double().cpu().numpy()   # clean sinogram (GPU forward projector)
+        b, enorm = W.add_noise(bc, w.eta, w.noise_dir())
+        cases.append((w, gg, torch.tensor(b, dtype=torch.float32, device="cuda"), enorm))
+    return cases
+
+
+def test_config4_batched_equals_single_solves(gpu_lib):
+    """The 64-problem mix at full size (N up to 1024, up to 720 angles, half limited
+    angle): FP32 engine vs the single-solve FP32 path, problem by problem."""
+    import torch
+    abg = gpu_lib
+    cases = _config4(abg, torch)
+    probs = [abg.Problem(g=gg, method=w.method, b=b, k_max=w.k_max, stop="dp", tau=w.tau,
+                         noise_norm=enorm) for w, gg, b, enorm in cases]
+    res = abg.batch_solve(probs, proj="f32", basis="f32")
+    ks = []
+    for (w, gg, b, enorm), r in zip(cases, res):
+        s = abg.gmres(w.method, gg, b, w.k_max, stop="dp", tau=w.tau, noise_norm=enorm)
+        err = _rel(r.x.double().cpu().numpy(), s.x.double().cpu().numpy())
+        ks.append(r.k_stop)
+        assert r.status == s.status, (w.instance, r.status, s.status)
+        assert r.k_stop == s.k_stop, (w.instance, r.k_stop, s.k_stop)
+        assert err <= 1e-4, (w.instance, err)
+        thr = w.tau * enorm
+        if r.status == "ok":
+            assert r.res_norm <= thr
+            if r.k_stop > 1:
+                assert r.res_hist[r.k_stop - 2] > thr * (1 - 1e-3)
+    print("config4 k_stop:", sorted(ks))
