@@ -107,6 +107,11 @@ __device__ inline bool halted(const DevState *st, int k)
 }
 #endif
 
+// Vectors that Gram-Schmidt reads or writes (q, the basis columns, the current vector) are
+// allocated with a length rounded up to a multiple of kVecPad elements, zero past their
+// logical length, so that every register tile of the MGS kernels lies inside them.
+constexpr long long kVecPad = 16384;
+
 struct MgsLaunch {
     int tx, tv;                  // dtypes of q / cur and of the basis
     const void *q;               // q_k, L elements of tx
@@ -117,8 +122,8 @@ struct MgsLaunch {
     double *hcol;                // out: k+1 values h_{1,k}..h_{k+1,k}
     void *vout;                  // out: w_{k+1} (tv), at V + k*ldv
     void *cur;                   // out: w_{k+1} converted back to tx
-    double *partials;            // scratch: 4 * kMaxGrid doubles
-    unsigned *bar;               // zeroed counter for this launch
+    double *partials;            // reduction slot tables: 2 x rows x G doubles
+    int rows;                    // rows per table (>= k + 3 for every step of the solve)
     DevState *st;
     double bd_rel;               // breakdown: h_{k+1,k} <= bd_rel * ||q_k||
     int step;                    // Arnoldi step (0: the initial normalisation)
@@ -150,6 +155,8 @@ hipError_t launch_clear_stop(DevState *st, hipStream_t s);
 void set_mgs_target_blocks(int blocks);
 hipError_t launch_fill_u32(unsigned *p, size_t n, unsigned v, hipStream_t s);
 hipError_t launch_fill_f64(double *p, size_t n, double v, hipStream_t s);
+// Marks MGS reduction slots empty (n doubles).
+hipError_t launch_clear_slots(double *p, size_t n, hipStream_t s);
 hipError_t launch_axpy_inplace(int t, void *x, const void *x0, long long L, hipStream_t s);
 
 // ---- NCP (ncp.hip) ------------------------------------------------------------------
@@ -171,9 +178,11 @@ int run_solver(const Geometry &g, int method, int kind, const void *b, const voi
 struct InstanceView {
     void *V, *Z, *cur, *q, *rb0, *tm, *tn, *fpws;
     double *H, *R, *cs, *sn, *g, *Y, *rho, *part, *mgs_part;
-    unsigned *bar, *count;
+    unsigned *count;
     long long L, ldv, mp, np;
-    int part_cap, mgs_part_cap;   // doubles in part / mgs_part
+    int part_cap;                 // doubles in part
+    int mgs_rows;                 // rows per MGS slot table
+    long long mgs_part_cap;       // doubles in mgs_part (two tables)
 };
 InstanceView instance_view(const Geometry &g, int method, int k_max, abg_precision p,
                            abg_stop st, void *ws);

@@ -61,8 +61,9 @@ struct BatchInst {
     long long L, ldv, mp, n, m;
     void *V, *Z, *cur, *q, *rb0, *tm, *tn, *xr, *xc;
     double *H, *R, *cs, *sn, *g, *Y, *rho, *part, *mgs_part;
-    unsigned *bar, *count;
+    unsigned *count;
     double bd_rel;
+    int mgs_rows;
     int need_res;
     int mgs_G, mgs_large;
     int chunk, n_chunks;
@@ -175,7 +176,23 @@ __global__ __launch_bounds__(256) void begin_kernel(const BatchInst *D, DevState
     }
 }
 
+// Problem and item of ticket `it` of list t (binary search over the segments). Every
+// thread of a block calls it with the same ticket, so the loads are uniform.
+__device__ inline void locate(const TabView &tv, int t, int it, int *slot, int *local)
+{
+    int lo = 0, hi = tv.nseg[t] - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tv.seg_first(t, mid) <= it) lo = mid;
+        else hi = mid - 1;
+    }
+    *slot = __builtin_amdgcn_readfirstlane(tv.seg_slot(t, lo));
+    *local = __builtin_amdgcn_readfirstlane(it - tv.seg_first(t, lo));
+}
+
 // Takes the next ticket of list t for the block: returns false when the list is used up.
+// Used where items must be taken in order by running blocks (the MGS block groups); the
+// other lists are dealt out statically (ticket = block + j * grid), which needs no atomic.
 __device__ inline bool next_item(const TabView &tv, int t, int *slot_out, int *local_out)
 {
     __shared__ int s_slot, s_local;
@@ -198,9 +215,10 @@ __device__ inline bool next_item(const TabView &tv, int t, int *slot_out, int *l
         s_local = local;
     }
     __syncthreads();
-    *slot_out = s_slot;
-    *local_out = s_local;
-    return s_slot >= 0;
+    // the same in every lane: keep it (and what is loaded through it) in scalar registers
+    *slot_out = __builtin_amdgcn_readfirstlane(s_slot);
+    *local_out = __builtin_amdgcn_readfirstlane(s_local);
+    return *slot_out >= 0;
 }
 
 template <typename T> __device__ inline T *zcol(const BatchInst &d, int k)
@@ -215,11 +233,14 @@ __global__ __launch_bounds__(256) void bpad_kernel(const BatchInst *D, const Dev
                                                    TabView tv, int t, int mode)
 {
     __shared__ PadLds<T> lds;
-    int slot, local;
-    while (next_item(tv, t, &slot, &local)) {
+    const int total = tv.total[t];
+    for (int it = blockIdx.x; it < total; it += gridDim.x) {
+        int slot, local;
+        locate(tv, t, it, &slot, &local);
         const BatchInst &d = D[slot];
         const DevState *st = S + slot;
         if (halted(st, st->kcur)) continue;
+        __syncthreads();   // the previous tile's LDS reads are done
         const int tpr = (d.N + 31) / 32;
         const T *src = static_cast<const T *>(mode == 0 ? d.cur : d.tn);
         pad_transpose_tile(src, static_cast<T *>(d.xr), static_cast<T *>(d.xc), d.N, d.S,
@@ -236,8 +257,10 @@ __global__ __launch_bounds__(256) void bfwd_kernel(const BatchInst *D, const Dev
     const int lane = threadIdx.x & 63;
     const int wpa = tl.rays / 64;       // waves per angle
     const int apb = 256 / tl.rays;      // angles per block
-    int slot, local;
-    while (next_item(tv, t, &slot, &local)) {
+    const int total = tv.total[t];
+    for (int it = blockIdx.x; it < total; it += gridDim.x) {
+        int slot, local;
+        locate(tv, t, it, &slot, &local);
         const BatchInst &d = D[slot];
         const DevState *st = S + slot;
         const int k = st->kcur;
@@ -259,8 +282,10 @@ __global__ __launch_bounds__(kBackThreads) void bback_kernel(const BatchInst *D,
                                                              int t, int mode)
 {
     __shared__ BackLds<T> lds;
-    int slot, local;
-    while (next_item(tv, t, &slot, &local)) {
+    const int total = tv.total[t];
+    for (int it = blockIdx.x; it < total; it += gridDim.x) {
+        int slot, local;
+        locate(tv, t, it, &slot, &local);
         const BatchInst &d = D[slot];
         const DevState *st = S + slot;
         const int k = st->kcur;
@@ -301,7 +326,7 @@ __global__ __launch_bounds__(kBlock) void bmgs_kernel(const BatchInst *D, DevSta
         a.vout = static_cast<TV *>(d.V) + (size_t)k * d.ldv;
         a.cur = d.cur;
         a.partials = d.mgs_part;
-        a.bar = d.bar + k;
+        a.rows = d.mgs_rows;
         a.st = st;
         a.bd_rel = d.bd_rel;
         a.step = k;
@@ -331,13 +356,16 @@ __global__ __launch_bounds__(kBlock) void bres_kernel(const BatchInst *D, DevSta
     __shared__ double cf[kMaxCoef];
     __shared__ double lds[kWaves];
     __shared__ int last;
-    int slot, c;
-    while (next_item(tv, kTRes, &slot, &c)) {
+    const int total = tv.total[kTRes];
+    for (int it = blockIdx.x; it < total; it += gridDim.x) {
+        int slot, c;
+        locate(tv, kTRes, it, &slot, &c);
         const BatchInst &d = D[slot];
         DevState *st = S + slot;
         const int k = st->kcur;
         if (halted(st, k)) continue;
         const bool ba = d.method == ABG_METHOD_BA;
+        __syncthreads();   // the previous item's use of cf and `last` is done
         const int kk = ba ? k : k + 1;
         const double *coef = ba ? d.Y + (size_t)(k - 1) * d.k_max : d.rho;
         for (int j = threadIdx.x; j < kk; j += kBlock) cf[j] = ba ? -coef[j] : coef[j];
@@ -648,7 +676,7 @@ struct Engine {
         d.rho = v.rho;
         d.part = v.part;
         d.mgs_part = v.mgs_part;
-        d.bar = v.bar;
+        d.mgs_rows = v.mgs_rows;
         d.count = v.count;
         d.bd_rel = (p.basis == ABG_F64 && p.proj == ABG_F64) ? 1e-14 : 1e-6;
         d.need_res = r.stop.kind == ABG_STOP_DP;
@@ -657,7 +685,7 @@ struct Engine {
         if (d.mgs_large)
             G = (v.L + (long long)kBlock * kMgsLargeE - 1) / ((long long)kBlock * kMgsLargeE);
         const int capG = d.mgs_large ? cap_mgs_l : cap_mgs_s;
-        if (G > capG / 2 || 4 * G > v.mgs_part_cap) return ABG_EINVAL;
+        if (G > capG / 2 || 2LL * v.mgs_rows * G > v.mgs_part_cap) return ABG_EINVAL;
         d.mgs_G = (int)std::max(1LL, G);
         long long chunk = 8192;
         while ((d.m + chunk - 1) / chunk > v.part_cap) chunk *= 2;

@@ -10,6 +10,7 @@
 // Every reduction runs in a fixed order, so results are identical run to run.
 #include <cmath>
 #include <cstdlib>
+#include <cstring>
 #include <mutex>
 #include <unordered_map>
 
@@ -283,7 +284,7 @@ hipError_t launch_mgs(const MgsLaunch &m, hipStream_t s)
     d.vout = m.vout;
     d.cur = m.cur;
     d.partials = m.partials;
-    d.bar = m.bar;
+    d.rows = m.rows;
     d.st = m.st;
     d.bd_rel = m.bd_rel;
     d.step = m.step;
@@ -363,6 +364,16 @@ hipError_t launch_fill_f64(double *p, size_t n, double v, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
     fill_f64_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_clear_slots(double *p, size_t n, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    double empty;
+    const unsigned long long bits = kSlotEmpty;
+    memcpy(&empty, &bits, sizeof empty);
+    fill_f64_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(p, n, empty);
     return hipGetLastError();
 }
 

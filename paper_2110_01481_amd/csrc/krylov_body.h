@@ -70,51 +70,72 @@ __device__ inline double agent_load(const double *p)
 }
 // Publishes a partial sum at device scope and waits until the write has been performed
 // (the exchange's returned value is consumed), so that a later counter increment
-// cannot overtake it. Partials are read back only with device-scope atomic loads, so
-// the barrier needs no release/acquire cache maintenance.
+// cannot overtake it. Partials are read back only with device-scope atomic loads.
 __device__ inline void agent_store(double *p, double v)
 {
     const double old = __hip_atomic_exchange(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     asm volatile("" ::"v"(old));
 }
 
-// Grid-wide barrier for a cooperative launch: each block adds one to the counter and
-// waits until it reaches `target`. The wait is bounded; on timeout the sticky error
-// flag is raised and every later barrier returns at once. Only values written with
-// agent_store and read with agent_load cross it.
-__device__ inline void grid_barrier(unsigned *bar, unsigned target, int *err)
+// ---- group reductions through value slots -----------------------------------------------
+// A block group reduces a scalar by writing one partial per block into a slot that holds
+// kSlotEmpty beforehand; readers poll the slots until none is empty. The value is its own
+// arrival signal, so a reduction costs one store and one round of polling, with no
+// counter and no ordering between different addresses. kSlotEmpty is a signalling NaN,
+// which arithmetic never produces (NaN partials are stored as the default quiet NaN).
+constexpr unsigned long long kSlotEmpty = 0x7ff4dead0000c0deull;
+
+__device__ inline void publish(double *slot, double v)
 {
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        unsigned spins = 0;
-        while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-            __builtin_amdgcn_s_sleep(1);
-            if (++spins > kSpinLimit) {
-                __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                break;
-            }
-            if ((spins & 255u) == 0 &&
-                __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-                break;
-        }
-    }
-    __syncthreads();
+    if (v != v) v = __longlong_as_double(0x7ff8000000000000ll);
+    __hip_atomic_store(slot, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Sum of the G per-block partials, the same in every block.
-__device__ inline double grid_total(const double *part, int G, double *lds)
+// Sum of the G published partials, the same in every block and every thread (thread t
+// adds slots t, t + kBlock, ... in order, then the fixed-order block sum). The wait is
+// bounded: on timeout the sticky error flag is raised; a raised flag ends every wait.
+__device__ inline double gather_total(const double *slots, int G, double *lds, int *err)
 {
     double s = 0.0;
-    for (int j = threadIdx.x; j < G; j += kBlock) s += agent_load(part + j);
+    unsigned spins = 0;
+    bool quit = false;
+    for (int j0 = 0; j0 < G && !quit; j0 += kBlock) {
+        const int j = j0 + (int)threadIdx.x;
+        double v = 0.0;
+        int have = j >= G;
+        for (;;) {
+            if (!have) {
+                v = agent_load(slots + j);
+                have = (unsigned long long)__double_as_longlong(v) != kSlotEmpty;
+            }
+            if (__syncthreads_and(have)) break;
+            ++spins;
+            if ((spins & 255u) == 0) {
+                const int e = __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (spins > kSpinLimit && threadIdx.x == 0 && !e)
+                    __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (__syncthreads_or(e != 0 || spins > kSpinLimit)) {
+                    quit = true;
+                    break;
+                }
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        if (j < G) s += v;
+    }
     return block_sum(s, lds);
 }
 
 // ---- modified Gram-Schmidt ------------------------------------------------------------
 // One Arnoldi step's orthogonalisation of q_k against w_1..w_k by G blocks (ranks
-// 0..G-1) that meet at grid barriers on `bar`: q_k stays in FP64 registers (E elements per
-// thread), each basis vector is read once, and every inner product is one reduction in a
-// fixed order. Writes h_{1,k}..h_{k+1,k}, w_{k+1} (basis dtype) and its copy in q's dtype.
+// 0..G-1): q_k stays in FP64 registers (E elements per thread), each basis vector is read
+// once, and every inner product is one group reduction in a fixed order. Writes
+// h_{1,k}..h_{k+1,k}, w_{k+1} (basis dtype) and its copy in q's dtype.
+//
+// Reduction slots: two tables (step parity) of `rows` rows x G doubles; step k uses
+// table k & 1, row i for <q, w_i>, row k for ||q||^2 after the sweep and row k + 1 for
+// ||q_k||^2 before it. Each rank clears its own column of the other table (rows up to
+// k + 2) for the next step; both tables start cleared.
 struct MgsDev {
     const void *q;
     const void *V;
@@ -125,64 +146,72 @@ struct MgsDev {
     void *vout;
     void *cur;
     double *partials;
-    unsigned *bar;
+    int rows;
     DevState *st;
     double bd_rel;
     int step;
 };
 
+// Rank r owns the E*kBlock consecutive elements from r*E*kBlock; register e of a lane
+// holds element base + e*kBlock, so every register is a coalesced wave access at a
+// compile-time offset from one per-lane address. The G ranks cover G*E*kBlock >= L
+// elements: the buffers are allocated that long and q is zero past L (the padding is
+// cleared once per solve), so there are no bounds tests and the padding of w_{k+1}
+// comes out zero.
 template <typename TX, typename TV, int E>
 __device__ inline void mgs_body(const MgsDev &a, int rank, int G, double *lds)
 {
-    const long long T = (long long)G * kBlock;
-    const long long gt = (long long)rank * kBlock + threadIdx.x;
-    const TX *q = static_cast<const TX *>(a.q);
-    const TV *V = static_cast<const TV *>(a.V);
+    const size_t base = (size_t)rank * (E * kBlock) + threadIdx.x;
+    const TX *q = static_cast<const TX *>(a.q) + base;
     int *err = &a.st->error;
-
+    // Large tiles read w_i again after the reduction (an L2 hit) instead of holding it
+    // across the barrier, which halves their register footprint.
+    constexpr bool kReload = E >= 32;
+    constexpr int EW = kReload ? 1 : E;
     double qv[E];
-    TV wv[E];
+    TV wv[EW];
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const long long l = gt + e * T;
-        qv[e] = l < a.L ? to_f64(q[l]) : 0.0;
+    for (int e = 0; e < E; ++e) qv[e] = to_f64(q[e * kBlock]);
+    double *tab = a.partials + (size_t)(a.step & 1) * a.rows * G;
+    double *next = a.partials + (size_t)((a.step + 1) & 1) * a.rows * G;
+    if (threadIdx.x == 0) {
+        const double empty = __longlong_as_double((long long)kSlotEmpty);
+        for (int r = 0; r <= a.k + 2 && r < a.rows; ++r)
+            __hip_atomic_store(next + (size_t)r * G + rank, empty, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
     }
-    unsigned nb = 0;
     double qq = 0.0;
     for (int i = 0; i < a.k; ++i) {
-        const TV *w = V + (size_t)i * a.ldv;
+        const TV *w = static_cast<const TV *>(a.V) + (size_t)i * a.ldv + base;
         double d = 0.0, s2 = 0.0;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-            const long long l = gt + e * T;
-            wv[e] = l < a.L ? w[l] : zero_of<TV>();
-            d = fma(qv[e], to_f64(wv[e]), d);
+            const TV we = w[e * kBlock];
+            if constexpr (!kReload) wv[e] = we;
+            d = fma(qv[e], to_f64(we), d);
             if (i == 0) s2 = fma(qv[e], qv[e], s2);
         }
-        double *slot = a.partials + (size_t)(nb & 1u) * 2 * G;
         d = block_sum(d, lds);
         if (i == 0) s2 = block_sum(s2, lds);
         if (threadIdx.x == 0) {
-            agent_store(slot + rank, d);
-            if (i == 0) agent_store(slot + G + rank, s2);
+            publish(tab + (size_t)i * G + rank, d);
+            if (i == 0) publish(tab + (size_t)(a.k + 1) * G + rank, s2);
         }
-        ++nb;
-        grid_barrier(a.bar, nb * (unsigned)G, err);
-        const double h = grid_total(slot, G, lds);
-        if (i == 0) qq = grid_total(slot + G, G, lds);
+        const double h = gather_total(tab + (size_t)i * G, G, lds, err);
+        if (i == 0) qq = gather_total(tab + (size_t)(a.k + 1) * G, G, lds, err);
         if (rank == 0 && threadIdx.x == 0) a.hcol[i] = h;
 #pragma unroll
-        for (int e = 0; e < E; ++e) qv[e] = fma(-h, to_f64(wv[e]), qv[e]);
+        for (int e = 0; e < E; ++e) {
+            if constexpr (kReload) qv[e] = fma(-h, to_f64(w[e * kBlock]), qv[e]);
+            else qv[e] = fma(-h, to_f64(wv[e]), qv[e]);
+        }
     }
     double s = 0.0;
 #pragma unroll
     for (int e = 0; e < E; ++e) s = fma(qv[e], qv[e], s);
-    double *slot = a.partials + (size_t)(nb & 1u) * 2 * G;
     s = block_sum(s, lds);
-    if (threadIdx.x == 0) agent_store(slot + rank, s);
-    ++nb;
-    grid_barrier(a.bar, nb * (unsigned)G, err);
-    const double hn2 = grid_total(slot, G, lds);
+    if (threadIdx.x == 0) publish(tab + (size_t)a.k * G + rank, s);
+    const double hn2 = gather_total(tab + (size_t)a.k * G, G, lds, err);
     if (a.k == 0) qq = hn2;
     const double hn = sqrt(hn2);
     const double q0 = sqrt(qq);
@@ -195,16 +224,13 @@ __device__ inline void mgs_body(const MgsDev &a, int rank, int G, double *lds)
         if (bd && a.step > 0) a.st->bd_k = a.step;
         if (!finite) a.st->error |= 2;
     }
-    TV *vo = static_cast<TV *>(a.vout);
-    TX *cu = static_cast<TX *>(a.cur);
+    TV *vo = static_cast<TV *>(a.vout) + base;
+    TX *cu = static_cast<TX *>(a.cur) + base;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-        const long long l = gt + e * T;
-        if (l < a.L) {
-            const TV w = (bd || !finite) ? zero_of<TV>() : from_f64<TV>(qv[e] / hn);
-            vo[l] = w;
-            cu[l] = (TX)to_f64(w);
-        }
+        const TV w = (bd || !finite) ? zero_of<TV>() : from_f64<TV>(qv[e] / hn);
+        vo[e * kBlock] = w;
+        cu[e * kBlock] = (TX)to_f64(w);
     }
 }
 

@@ -13,6 +13,7 @@
 // MGS (breakdown); the kernels of every later step then return at entry, so a step that
 // was enqueued past the stop costs only its launches. y_k is kept for every k, so the
 // iterate of any step can be formed afterwards.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 
@@ -23,8 +24,10 @@ namespace {
 
 struct Layout {
     size_t V, Z, cur, q, rb0, tm, tn, fpws, H, R, cs, sn, g, Y, rho;
-    size_t part, mgs_part, bar, count, st, ncp, total;
+    size_t part, mgs_part, count, st, ncp, total;
     long long L, ldv, mp, np;
+    int mgs_rows;
+    long long mgs_cap;
 };
 
 long long round_up(long long v, long long a) { return (v + a - 1) / a * a; }
@@ -33,8 +36,8 @@ Layout make_layout(const Geometry &g, int method, int k_max, abg_precision p, ab
 {
     Layout ly{};
     const size_t sX = dtype_size(p.proj), sV = dtype_size(p.basis);
-    ly.mp = round_up(g.m(), 128);
-    ly.np = round_up(g.n(), 128);
+    ly.mp = round_up(g.m(), kVecPad);
+    ly.np = round_up(g.n(), kVecPad);
     ly.L = method == ABG_METHOD_AB ? g.m() : g.n();
     ly.ldv = method == ABG_METHOD_AB ? ly.mp : ly.np;
     size_t off = 0;
@@ -61,8 +64,11 @@ Layout make_layout(const Geometry &g, int method, int k_max, abg_precision p, ab
     ly.Y = take((size_t)k_max * k_max * 8);
     ly.rho = take((ld + 1) * 8);
     ly.part = take(2048 * 8);
-    ly.mgs_part = take(4 * (size_t)kMaxGrid * 8);
-    ly.bar = take((ld + 2) * 4);
+    // MGS slot tables: two of (k_max + 3) rows, one column per block of the largest group
+    ly.mgs_rows = k_max + 3;
+    const long long gmax = std::min<long long>(kMaxGrid, (ly.L + 255) / 256);
+    ly.mgs_cap = 2LL * ly.mgs_rows * gmax;
+    ly.mgs_part = take((size_t)ly.mgs_cap * 8);
     ly.count = take(64);
     ly.st = take(sizeof(DevState));
     ly.ncp = st.kind == ABG_STOP_NCP ? take(ncp_scratch_bytes(g)) : 0;
@@ -134,7 +140,7 @@ struct Solve {
     char *W;
     void *V, *Z, *cur, *q, *rb0, *tm, *tn, *fpws;
     double *H, *R, *cs, *sn, *gv, *Y, *rho, *part, *mgs_part;
-    unsigned *bar, *count;
+    unsigned *count;
     DevState *dst;
     double *ncp;
     HostRes hr;
@@ -167,7 +173,6 @@ struct Solve {
         rho = reinterpret_cast<double *>(W + ly.rho);
         part = reinterpret_cast<double *>(W + ly.part);
         mgs_part = reinterpret_cast<double *>(W + ly.mgs_part);
-        bar = reinterpret_cast<unsigned *>(W + ly.bar);
         count = reinterpret_cast<unsigned *>(W + ly.count);
         dst = reinterpret_cast<DevState *>(W + ly.st);
         ncp = ly.ncp ? reinterpret_cast<double *>(W + ly.ncp) : nullptr;
@@ -209,7 +214,7 @@ struct Solve {
         M.hcol = k == 0 ? gv : H + (size_t)(k - 1) * ld;
         M.vout = vec(k);
         M.cur = cur;
-        M.bar = bar + k;
+        M.rows = ly.mgs_rows;
         return M;
     }
 
@@ -286,11 +291,16 @@ struct Solve {
     int init_async(const void *b, const void *x0)
     {
         const long long m = g.m();
-        CK(launch_fill_u32(bar, (size_t)ld + 2, 0u, s));
+        CK(launch_clear_slots(mgs_part, (size_t)ly.mgs_cap, s));
         CK(launch_fill_u32(count, 16, 0u, s));
         CK(launch_fill_f64(H, (size_t)ld * k_max, 0.0, s));
         CK(launch_fill_f64(gv, (size_t)ld, 0.0, s));
         CK(launch_fill_u32(reinterpret_cast<unsigned *>(fpws), fp_workspace_bytes(g, p.proj) / 4, 0u, s));
+        // padding of the MGS input vectors must read as zero; so must that of w_1, which
+        // a later step may read over a longer register tile than step 0 writes
+        CK(launch_fill_u32(reinterpret_cast<unsigned *>(q), ly.ldv * sX / 4, 0u, s));
+        CK(launch_fill_u32(reinterpret_cast<unsigned *>(rb0), ly.mp * sX / 4, 0u, s));
+        CK(launch_fill_u32(reinterpret_cast<unsigned *>(V), ly.ldv * dtype_size(p.basis) / 4, 0u, s));
         if (x0) {
             RC(fwd(x0, tm));
             int nb = 0;
@@ -344,14 +354,14 @@ InstanceView instance_view(const Geometry &g, int method, int k_max, abg_precisi
     v.rho = reinterpret_cast<double *>(W + ly.rho);
     v.part = reinterpret_cast<double *>(W + ly.part);
     v.mgs_part = reinterpret_cast<double *>(W + ly.mgs_part);
-    v.bar = reinterpret_cast<unsigned *>(W + ly.bar);
     v.count = reinterpret_cast<unsigned *>(W + ly.count);
     v.L = ly.L;
     v.ldv = ly.ldv;
     v.mp = ly.mp;
     v.np = ly.np;
     v.part_cap = 2048;
-    v.mgs_part_cap = 4 * kMaxGrid;
+    v.mgs_rows = ly.mgs_rows;
+    v.mgs_part_cap = ly.mgs_cap;
     return v;
 }
 

@@ -128,6 +128,35 @@ def test_continuous_admission_through_few_slots(gpu_lib, mix):
         assert torch.equal(done[i].x, ref[i].x), i
 
 
+@pytest.mark.parametrize("fill", [0x00, 0xFF, 0x7F])
+def test_workspace_contents_do_not_matter(gpu_lib, mix, fill):
+    """Workspaces handed over full of arbitrary bytes (NaN patterns included) give the
+    same results, bit for bit, in the engine and in single solves."""
+    import torch
+    abg = gpu_lib
+    eng = abg.Engine(proj="f32", basis="f32", max_slots=4)
+    for i in (1, 3):
+        c = mix[i]
+        p = c.problem(abg, torch.float32)
+        nb = abg.request_bytes(p.g, p.method, p.k_max, "f32", "f32", p.stop)
+        ws = torch.full((nb,), fill, dtype=torch.uint8, device="cuda")
+        ref = abg.Engine(proj="f32", basis="f32", max_slots=1).run([c.problem(abg, torch.float32)])[0]
+        tag = eng.submit(p, workspace=ws)
+        got = None
+        while got is None:
+            eng.step()
+            for t, r in eng.poll():
+                if t == tag:
+                    got = r
+        assert got.k_stop == ref.k_stop and torch.equal(got.x, ref.x), (i, fill)
+        ws.fill_(fill)
+        s1 = abg.gmres(c.method, p.g, p.b, c.k_max, stop=c.stop, tau=1.02, noise_norm=c.enorm,
+                       bp=c.kind, x0=p.x0, workspace=ws)
+        s2 = abg.gmres(c.method, p.g, p.b, c.k_max, stop=c.stop, tau=1.02, noise_norm=c.enorm,
+                       bp=c.kind, x0=p.x0)
+        assert s1.k_stop == s2.k_stop and torch.equal(s1.x, s2.x), (i, fill)
+
+
 @pytest.mark.parametrize("rays", [64, 128])
 def test_tile_shape_does_not_change_results(gpu_lib, mix, rays):
     import torch
