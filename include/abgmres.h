@@ -217,15 +217,24 @@ int abg_engine_step(abg_engine *e, int *n_active);
  * this, their x holds the result and their buffers are the caller's again. */
 int abg_engine_poll(abg_engine *e, long long *tags, int *status, int max, int *n);
 
-/* Tile shape of the forward projector's work items: rays per angle in one block (64,
- * 128 or 256; a block of 256 threads takes 256/rays angles). Takes effect next round. */
-int abg_engine_set_tiles(abg_engine *e, int rays);
-int abg_engine_get_tiles(const abg_engine *e, int *rays);
+/* Tile shapes of the projector work items, taking effect next round. rays: rays of one
+ * angle per forward-projector block (64, 128 or 256; a block of 256 threads takes
+ * 256/rays angles). ang_block: angles whose detector windows a back-projector block
+ * stages in LDS per round (64 or 128). Results do not depend on either. */
+int abg_engine_set_tiles(abg_engine *e, int rays, int ang_block);
+int abg_engine_get_tiles(const abg_engine *e, int *rays, int *ang_block);
+
+/* Autotuner: times the projector phases of one round for every tile shape on the
+ * problems the engine holds (after `reps` repetitions each, without advancing them),
+ * keeps the fastest and returns it with its time in ms. Synchronises the stream. With
+ * no running problem it keeps the current shape and returns ms = 0. */
+int abg_engine_autotune(abg_engine *e, int reps, int *rays, int *ang_block, double *ms);
 
 /* Convenience: solves n requests together on a new engine and returns when all are
  * finished (each request's status in its info, if given). Returns the first error, or
- * ABG_OK. `rays` <= 0 keeps the default tile shape. */
-int abg_batch_solve(const abg_request *r, int n, abg_precision p, int rays, void *stream);
+ * ABG_OK. rays / ang_block <= 0 keep the default tile shapes. */
+int abg_batch_solve(const abg_request *r, int n, abg_precision p, int rays, int ang_block,
+                    void *stream);
 
 /* ---- instrumentation -------------------------------------------------------------- */
 

@@ -26,7 +26,7 @@ EXPORTS = ["abg_create_geometry", "abg_destroy_geometry", "abg_geometry_sizes",
            "abg_ab_gmres", "abg_ba_gmres", "abg_status_string", "abg_profile_enable",
            "abg_profile_read", "abg_request_bytes", "abg_engine_create", "abg_engine_destroy",
            "abg_engine_submit", "abg_engine_step", "abg_engine_poll", "abg_engine_set_tiles",
-           "abg_engine_get_tiles", "abg_batch_solve"]
+           "abg_engine_get_tiles", "abg_engine_autotune", "abg_batch_solve"]
 
 
 class AbgError(RuntimeError):
@@ -100,9 +100,10 @@ def load_library(path: str | None = None):
     lib.abg_engine_step.argtypes = [vp, ctypes.POINTER(i)]
     lib.abg_engine_poll.argtypes = [vp, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(i), i,
                                     ctypes.POINTER(i)]
-    lib.abg_engine_set_tiles.argtypes = [vp, i]
-    lib.abg_engine_get_tiles.argtypes = [vp, ctypes.POINTER(i)]
-    lib.abg_batch_solve.argtypes = [ctypes.POINTER(Request), i, Precision, i, vp]
+    lib.abg_engine_set_tiles.argtypes = [vp, i, i]
+    lib.abg_engine_get_tiles.argtypes = [vp, ctypes.POINTER(i), ctypes.POINTER(i)]
+    lib.abg_engine_autotune.argtypes = [vp, i, ctypes.POINTER(i), ctypes.POINTER(i), _dp]
+    lib.abg_batch_solve.argtypes = [ctypes.POINTER(Request), i, Precision, i, i, vp]
     _lib = lib
     return lib
 
@@ -386,13 +387,49 @@ class Engine:
         except Exception:
             pass
 
-    def set_tiles(self, rays: int):
-        _check(self.lib.abg_engine_set_tiles(self._h, int(rays)), "abg_engine_set_tiles")
+    def set_tiles(self, rays: int, ang_block: int | None = None):
+        ab = ang_block if ang_block is not None else self.get_tiles()[1]
+        _check(self.lib.abg_engine_set_tiles(self._h, int(rays), int(ab)), "abg_engine_set_tiles")
 
-    def get_tiles(self) -> int:
-        r = ctypes.c_int()
-        _check(self.lib.abg_engine_get_tiles(self._h, ctypes.byref(r)), "abg_engine_get_tiles")
-        return r.value
+    def get_tiles(self) -> tuple:
+        r, a = ctypes.c_int(), ctypes.c_int()
+        _check(self.lib.abg_engine_get_tiles(self._h, ctypes.byref(r), ctypes.byref(a)),
+               "abg_engine_get_tiles")
+        return r.value, a.value
+
+    def signature(self) -> str:
+        """Key of the current mix for the tile cache: precision and the sorted shapes."""
+        shapes = sorted((p.prob.g.N, p.prob.g.n_ang, p.prob.g.n_det, p.prob.method)
+                        for p in self._pending.values())
+        return f"{self.proj}/{self.basis}:" + ";".join("%d,%d,%d,%s" % s for s in shapes)
+
+    def autotune(self, reps: int = 3, cache: str | None = None) -> dict:
+        """Picks the projector tile shapes for the problems held now (call after submit,
+        before the first step). With `cache` (a JSON file), a shape found before for the
+        same device and mix is reused without timing."""
+        import json
+        torch = _torch()
+        dev = torch.cuda.get_device_name(self.device)
+        key = dev + "|" + self.signature()
+        table = {}
+        if cache and os.path.exists(cache):
+            with open(cache) as fh:
+                table = json.load(fh)
+        if key in table:
+            rays, ab = table[key]["rays"], table[key]["ang_block"]
+            self.set_tiles(rays, ab)
+            return {"rays": rays, "ang_block": ab, "ms": table[key]["ms"], "cached": True}
+        r, a, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+        _check(self.lib.abg_engine_autotune(self._h, int(reps), ctypes.byref(r), ctypes.byref(a),
+                                            ctypes.byref(ms)), "abg_engine_autotune")
+        out = {"rays": r.value, "ang_block": a.value, "ms": ms.value, "cached": False}
+        if cache and ms.value > 0:
+            table[key] = {k: out[k] for k in ("rays", "ang_block", "ms")}
+            d = os.path.dirname(os.path.abspath(cache))
+            os.makedirs(d, exist_ok=True)
+            with open(cache, "w") as fh:
+                json.dump(table, fh, indent=1)
+        return out
 
     def submit(self, prob: Problem, x=None, workspace=None) -> int | None:
         """Adds a problem; returns its engine tag, or None when every slot is busy."""
@@ -462,7 +499,8 @@ class Engine:
         return [done[t] for t in tags]
 
 
-def batch_solve(problems, proj="f32", basis="f32", rays: int = 0, stream=None) -> list:
+def batch_solve(problems, proj="f32", basis="f32", rays: int = 0, ang_block: int = 0,
+                stream=None) -> list:
     """abg_batch_solve: all problems on a new engine; returns SolveResults in input order."""
     torch = _torch()
     lib = load_library()
@@ -485,6 +523,6 @@ def batch_solve(problems, proj="f32", basis="f32", rays: int = 0, stream=None) -
                           ctypes.c_void_p(prob.x0.data_ptr()) if prob.x0 is not None else None,
                           ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
                           ctypes.pointer(pend.info), i)
-    _check(lib.abg_batch_solve(reqs, len(problems), prec, int(rays), _stream_ptr(stream)),
-           "abg_batch_solve")
+    _check(lib.abg_batch_solve(reqs, len(problems), prec, int(rays), int(ang_block),
+                               _stream_ptr(stream)), "abg_batch_solve")
     return [p.result(p.info.status) for p in keep]

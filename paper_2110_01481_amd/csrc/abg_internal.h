@@ -124,6 +124,7 @@ struct MgsLaunch {
     void *cur;                   // out: w_{k+1} converted back to tx
     double *partials;            // reduction slot tables: 2 x rows x G doubles
     int rows;                    // rows per table (>= k + 3 for every step of the solve)
+    unsigned *ticket;            // zeroed counter of this step: hands out block ranks
     DevState *st;
     double bd_rel;               // breakdown: h_{k+1,k} <= bd_rel * ||q_k||
     int step;                    // Arnoldi step (0: the initial normalisation)
@@ -203,8 +204,9 @@ int engine_submit(Engine *e, const Geometry &g, const abg_request &r);
 int engine_step(Engine *e, int *n_running);
 int engine_poll(Engine *e, long long *tags, int *status, int max, int *n);
 int engine_pending(const Engine *e);
-int engine_set_tiles(Engine *e, int rays);
-int engine_get_tiles(const Engine *e, int *rays);
+int engine_set_tiles(Engine *e, int rays, int ang_block);
+int engine_get_tiles(const Engine *e, int *rays, int *ang_block);
+int engine_autotune(Engine *e, int reps, int *rays, int *ang_block, double *ms);
 int engine_device(const Engine *e);
 hipStream_t engine_stream(const Engine *e);
 int engine_precision(const Engine *e, abg_precision *p);

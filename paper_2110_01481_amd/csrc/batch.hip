@@ -81,7 +81,9 @@ struct TabView {
 };
 
 struct Tiles {
-    int rays;   // forward projector: rays per wave group (64, 128 or 256); 256/rays angles per block
+    int rays;        // forward projector: rays of one angle per block (64, 128 or 256);
+                     // a block of 256 threads takes 256/rays angles
+    int ang_block;   // back projectors: angles staged in LDS per round (64 or 128)
 };
 
 namespace {
@@ -276,12 +278,12 @@ __global__ __launch_bounds__(256) void bfwd_kernel(const BatchInst *D, const Dev
 }
 
 // mode 0: AB, t = B w_k;  mode 1: BA, q = B z
-template <typename T>
+template <typename T, int AB>
 __global__ __launch_bounds__(kBackThreads) void bback_kernel(const BatchInst *D,
                                                              const DevState *S, TabView tv,
                                                              int t, int mode)
 {
-    __shared__ BackLds<T> lds;
+    __shared__ BackLds<T, AB> lds;
     const int total = tv.total[t];
     for (int it = blockIdx.x; it < total; it += gridDim.x) {
         int slot, local;
@@ -295,9 +297,9 @@ __global__ __launch_bounds__(kBackThreads) void bback_kernel(const BatchInst *D,
         const T *y = mode == 0 ? static_cast<const T *>(d.cur) : zcol<T>(d, k);
         T *x = static_cast<T *>(mode == 0 ? d.tn : d.q);
         if (d.kind == ABG_BP_ADJ)
-            back_tile<T, true>(y, x, d.ang, d.N, d.n_ang, d.n_det, d.ds, d.s0, c0, r0, lds);
+            back_tile<T, true, AB>(y, x, d.ang, d.N, d.n_ang, d.n_det, d.ds, d.s0, c0, r0, lds);
         else
-            back_tile<T, false>(y, x, d.ang, d.N, d.n_ang, d.n_det, d.ds, d.s0, c0, r0, lds);
+            back_tile<T, false, AB>(y, x, d.ang, d.N, d.n_ang, d.n_det, d.ds, d.s0, c0, r0, lds);
     }
 }
 
@@ -527,8 +529,9 @@ struct Engine {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     bool dirty = true;
-    Tiles tiles{256};
-    int grid_proj = 0, grid_back = 0, grid_mgs_s = 0, grid_mgs_l = 0, grid_res = 0;
+    Tiles tiles{256, 128};
+    int grid_proj = 0, grid_back = 0, grid_back64 = 0, grid_mgs_s = 0, grid_mgs_l = 0, grid_res = 0;
+    hipEvent_t tev[2] = {};
     int cap_mgs_s = 0, cap_mgs_l = 0;
     int broken = 0;
     std::vector<Slot> slots;
@@ -549,6 +552,8 @@ struct Engine {
         if (graph) (void)hipGraphDestroy(graph);
         for (auto &e : ev)
             if (e) (void)hipEventDestroy(e);
+        for (auto &e : tev)
+            if (e) (void)hipEventDestroy(e);
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
         if (d_desc) (void)hipFree(d_desc);
         if (d_st) (void)hipFree(d_st);
@@ -562,7 +567,8 @@ struct Engine {
     {
         hipError_t e;
         if ((e = capacity_of(bfwd_kernel<TX>, 256, &grid_proj)) != hipSuccess) return e;
-        if ((e = capacity_of(bback_kernel<TX>, kBackThreads, &grid_back)) != hipSuccess) return e;
+        if ((e = capacity_of(bback_kernel<TX, 128>, kBackThreads, &grid_back)) != hipSuccess) return e;
+        if ((e = capacity_of(bback_kernel<TX, 64>, kBackThreads, &grid_back64)) != hipSuccess) return e;
         if ((e = capacity_of(bmgs_kernel<TX, TV, kMgsSmallE>, kBlock, &cap_mgs_s)) != hipSuccess) return e;
         if ((e = capacity_of(bmgs_kernel<TX, TV, kMgsLargeE>, kBlock, &cap_mgs_l)) != hipSuccess) return e;
         if ((e = capacity_of(bres_kernel<TX, TV>, kBlock, &grid_res)) != hipSuccess) return e;
@@ -579,15 +585,36 @@ struct Engine {
         return capacities<float, bf16>();
     }
 
+    template <typename TX> void enqueue_back(hipStream_t q, const Tiles &tl, int t, int mode)
+    {
+        if (tl.ang_block == 64)
+            bback_kernel<TX, 64><<<grid_back64, kBackThreads, 0, q>>>(d_desc, d_st, tv, t, mode);
+        else
+            bback_kernel<TX, 128><<<grid_back, kBackThreads, 0, q>>>(d_desc, d_st, tv, t, mode);
+    }
+
+    // begin + the three projector phases (idempotent between rounds: they recompute the
+    // round's z, t and q from w_k without advancing any problem)
+    template <typename TX> void enqueue_projectors_t(hipStream_t q, const Tiles &tl)
+    {
+        begin_kernel<<<kNumTab, 256, 0, q>>>(d_desc, d_st, tv, max_slots, tl);
+        bpad_kernel<TX><<<grid_proj, 256, 0, q>>>(d_desc, d_st, tv, kTPadBA, 0);
+        enqueue_back<TX>(q, tl, kTBackAB, 0);
+        bfwd_kernel<TX><<<grid_proj, 256, 0, q>>>(d_desc, d_st, tv, kTFwdBA, 0, tl);
+        bpad_kernel<TX><<<grid_proj, 256, 0, q>>>(d_desc, d_st, tv, kTPadAB, 1);
+        enqueue_back<TX>(q, tl, kTBackBA, 1);
+        bfwd_kernel<TX><<<grid_proj, 256, 0, q>>>(d_desc, d_st, tv, kTFwdAB, 1, tl);
+    }
+
+    void enqueue_projectors(hipStream_t q, const Tiles &tl)
+    {
+        if (p.proj == ABG_F64) enqueue_projectors_t<double>(q, tl);
+        else enqueue_projectors_t<float>(q, tl);
+    }
+
     template <typename TX, typename TV> void enqueue_round_t(hipStream_t q)
     {
-        begin_kernel<<<kNumTab, 256, 0, q>>>(d_desc, d_st, tv, max_slots, tiles);
-        bpad_kernel<TX><<<grid_proj, 256, 0, q>>>(d_desc, d_st, tv, kTPadBA, 0);
-        bback_kernel<TX><<<grid_back, kBackThreads, 0, q>>>(d_desc, d_st, tv, kTBackAB, 0);
-        bfwd_kernel<TX><<<grid_proj, 256, 0, q>>>(d_desc, d_st, tv, kTFwdBA, 0, tiles);
-        bpad_kernel<TX><<<grid_proj, 256, 0, q>>>(d_desc, d_st, tv, kTPadAB, 1);
-        bback_kernel<TX><<<grid_back, kBackThreads, 0, q>>>(d_desc, d_st, tv, kTBackBA, 1);
-        bfwd_kernel<TX><<<grid_proj, 256, 0, q>>>(d_desc, d_st, tv, kTFwdAB, 1, tiles);
+        enqueue_projectors_t<TX>(q, tiles);
         bmgs_kernel<TX, TV, kMgsSmallE><<<grid_mgs_s, kBlock, 0, q>>>(d_desc, d_st, tv, kTMgsS);
         bmgs_kernel<TX, TV, kMgsLargeE><<<grid_mgs_l, kBlock, 0, q>>>(d_desc, d_st, tv, kTMgsL);
         bgivens_kernel<<<max_slots, 64, 0, q>>>(d_desc, d_st, tv);
@@ -716,6 +743,57 @@ struct Engine {
             r.info->k_stop = r.info->k_done = r.info->n_literal = 0;
             r.info->status = ABG_OK;
         }
+        return ABG_OK;
+    }
+
+    // Average time of the projector phases of one round with tile shape tl, over `reps`
+    // repetitions on the current problems (0 when none is running).
+    int time_projectors(const Tiles &tl, int reps, double *ms)
+    {
+        *ms = 0.0;
+        if (n_in(kRunning) == 0) return ABG_OK;
+        for (auto &e : tev)
+            if (!e) BCK(hipEventCreate(&e));
+        enqueue_projectors(s, tl);   // warm-up
+        BCK(hipGetLastError());
+        BCK(hipEventRecord(tev[0], s));
+        for (int r = 0; r < reps; ++r) enqueue_projectors(s, tl);
+        BCK(hipGetLastError());
+        BCK(hipEventRecord(tev[1], s));
+        BCK(hipEventSynchronize(tev[1]));
+        float t = 0.f;
+        BCK(hipEventElapsedTime(&t, tev[0], tev[1]));
+        *ms = (double)t / std::max(1, reps);
+        return ABG_OK;
+    }
+
+    // Times every tile shape on the current problems and keeps the fastest.
+    int autotune(int reps, Tiles *best_out, double *best_ms)
+    {
+        if (broken) return broken;
+        if ((int)inflight.size() > 0) {
+            int rc = drain();
+            if (rc) return rc;
+        }
+        Tiles best = tiles;
+        double bms = INFINITY;
+        for (int rays : {64, 128, 256})
+            for (int ab : {64, 128}) {
+                const Tiles tl{rays, ab};
+                double ms = 0.0;
+                int rc = time_projectors(tl, reps, &ms);
+                if (rc) return rc;
+                if (ms > 0.0 && ms < bms) {
+                    bms = ms;
+                    best = tl;
+                }
+            }
+        if (best.rays != tiles.rays || best.ang_block != tiles.ang_block) {
+            tiles = best;
+            dirty = true;
+        }
+        *best_out = tiles;
+        *best_ms = std::isfinite(bms) ? bms : 0.0;
         return ABG_OK;
     }
 
@@ -935,20 +1013,31 @@ int engine_poll(Engine *e, long long *tags, int *status, int max, int *n)
 
 int engine_pending(const Engine *e) { return e->n_used() + (int)e->finished.size(); }
 
-int engine_set_tiles(Engine *e, int rays)
+int engine_set_tiles(Engine *e, int rays, int ang_block)
 {
     if (rays != 64 && rays != 128 && rays != 256) return ABG_EINVAL;
-    if (e->tiles.rays != rays) {
-        e->tiles.rays = rays;
+    if (ang_block != 64 && ang_block != 128) return ABG_EINVAL;
+    if (e->tiles.rays != rays || e->tiles.ang_block != ang_block) {
+        e->tiles = Tiles{rays, ang_block};
         e->dirty = true;
     }
     return ABG_OK;
 }
 
-int engine_get_tiles(const Engine *e, int *rays)
+int engine_get_tiles(const Engine *e, int *rays, int *ang_block)
 {
     *rays = e->tiles.rays;
+    *ang_block = e->tiles.ang_block;
     return ABG_OK;
+}
+
+int engine_autotune(Engine *e, int reps, int *rays, int *ang_block, double *ms)
+{
+    Tiles t{};
+    const int rc = e->autotune(reps, &t, ms);
+    *rays = t.rays;
+    *ang_block = t.ang_block;
+    return rc;
 }
 
 int engine_device(const Engine *e) { return e->device; }

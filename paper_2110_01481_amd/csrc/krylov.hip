@@ -1,8 +1,9 @@
 // Arnoldi machinery of AB-/BA-GMRES (Sec. 2) for gfx950:
 //   mgs     modified Gram-Schmidt of q_k against w_1..w_k, h_{k+1,k} = ||q_k||,
-//           w_{k+1} = q_k / h_{k+1,k}; one cooperative launch per Arnoldi step that keeps
-//           q_k in FP64 registers, reads each basis vector once, and takes one grid-wide
-//           reduction per inner product (the listing's sequential i loop is kept).
+//           w_{k+1} = q_k / h_{k+1,k}; one launch per Arnoldi step whose blocks all stay
+//           resident, keep q_k in FP64 registers, read each basis vector once, and take
+//           one group-wide reduction per inner product (the sequential loop over i of
+//           modified Gram-Schmidt is kept).
 //   givens  FP64 Givens update of the Hessenberg least squares problem, back
 //           substitution for y_k and the small residual vector ||r_0|| e_1 - H_k y_k.
 //   combine basis combinations base + sum_j c_j v_j (iterates and residual vectors)
@@ -21,26 +22,34 @@ namespace {
 
 constexpr int kCombU = 4;
 
+// Ranks are handed out in the order blocks start, so the blocks holding ranks are
+// running; a group no larger than the blocks the device holds at once always completes
+// (an ordinary launch then needs no co-scheduling guarantee).
 template <typename TX, typename TV, int E>
 __global__ __launch_bounds__(kBlock) void mgs_kernel(MgsDev a)
 {
     __shared__ double lds[kWaves];
+    __shared__ int s_rank;
     if (halted(a.st, a.step)) return;
-    mgs_body<TX, TV, E>(a, blockIdx.x, gridDim.x, lds);
+    if (threadIdx.x == 0)
+        s_rank = (int)__hip_atomic_fetch_add(a.ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const int rank = __builtin_amdgcn_readfirstlane(s_rank);
+    mgs_body<TX, TV, E>(a, rank, gridDim.x, lds);
 }
 
-// ---- cooperative launch bookkeeping --------------------------------------------------
-struct CoopInfo {
+// ---- resident-block bookkeeping -----------------------------------------------------
+struct CapInfo {
     int max_blocks = 0;
 };
-std::mutex g_coop_mu;
-std::unordered_map<const void *, CoopInfo> g_coop;
+std::mutex g_cap_mu;
+std::unordered_map<const void *, CapInfo> g_cap;
 
-hipError_t coop_capacity(const void *fn, int *max_blocks)
+hipError_t resident_capacity(const void *fn, int *max_blocks)
 {
-    std::lock_guard<std::mutex> lk(g_coop_mu);
-    auto it = g_coop.find(fn);
-    if (it != g_coop.end()) {
+    std::lock_guard<std::mutex> lk(g_cap_mu);
+    auto it = g_cap.find(fn);
+    if (it != g_cap.end()) {
         *max_blocks = it->second.max_blocks;
         return hipSuccess;
     }
@@ -52,14 +61,14 @@ hipError_t coop_capacity(const void *fn, int *max_blocks)
     if (e != hipSuccess) return e;
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kBlock, 0);
     if (e != hipSuccess) return e;
-    CoopInfo ci;
+    CapInfo ci;
     ci.max_blocks = per_cu * prop.multiProcessorCount;
-    g_coop[fn] = ci;
+    g_cap[fn] = ci;
     *max_blocks = ci.max_blocks;
     return hipSuccess;
 }
 
-// Blocks of the cooperative MGS launch when the vector is long enough (fewer blocks make
+// Blocks of the MGS launch when the vector is long enough (fewer blocks make
 // the grid-wide reductions cheaper, more blocks keep more loads in flight). The
 // environment variable ABG_MGS_BLOCKS overrides it.
 int default_target_blocks()
@@ -75,12 +84,11 @@ hipError_t mgs_go(const MgsDev &d, int G, hipStream_t s)
 {
     const void *fn = reinterpret_cast<const void *>(&mgs_kernel<TX, TV, E>);
     int cap = 0;
-    hipError_t e = coop_capacity(fn, &cap);
+    hipError_t e = resident_capacity(fn, &cap);
     if (e != hipSuccess) return e;
     if (G > cap || G > kMaxGrid) return hipErrorCooperativeLaunchTooLarge;
-    MgsDev arg = d;
-    void *args[] = {&arg};
-    return hipLaunchCooperativeKernel(fn, dim3(G), dim3(kBlock), args, 0, s);
+    mgs_kernel<TX, TV, E><<<G, kBlock, 0, s>>>(d);
+    return hipGetLastError();
 }
 
 template <typename TX, typename TV>
@@ -285,6 +293,7 @@ hipError_t launch_mgs(const MgsLaunch &m, hipStream_t s)
     d.cur = m.cur;
     d.partials = m.partials;
     d.rows = m.rows;
+    d.ticket = m.ticket;
     d.st = m.st;
     d.bd_rel = m.bd_rel;
     d.step = m.step;

@@ -147,6 +147,7 @@ struct MgsDev {
     void *cur;
     double *partials;
     int rows;
+    unsigned *ticket;
     DevState *st;
     double bd_rel;
     int step;

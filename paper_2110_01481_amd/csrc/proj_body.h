@@ -285,21 +285,22 @@ __device__ inline T back_tap(const BinPair<T> *wrow, T u, const BackStage<T> &P,
 }
 
 // LDS of one back-projection block (declared by the calling kernel, so that a kernel
-// serving both back projectors holds one copy).
-template <typename T> struct BackLds {
-    BinPair<T> win[kAngBlock][kWin];
-    BackStage<T> prm[kAngBlock];
+// serving both back projectors holds one copy). AB angles are staged per round.
+template <typename T, int AB = kAngBlock> struct BackLds {
+    BinPair<T> win[AB][kWin];
+    BackStage<T> prm[AB];
     T part[kBackWaves - 1][kTile * kTile];
 };
 
 // The 16 x 16 tile with first column c0 and first row r0, by one block of kBackThreads.
 // Starts and ends with a block-wide barrier, so consecutive calls may share the LDS.
-template <typename T, bool ADJ>
+template <typename T, bool ADJ, int AB = kAngBlock>
 __device__ inline void back_tile(const T *__restrict__ y, T *__restrict__ x,
                                  const AngleParams *__restrict__ ang, int N, int n_ang,
                                  int n_det, double ds, double s0, int c0, int r0,
-                                 BackLds<T> &L)
+                                 BackLds<T, AB> &L)
 {
+    static_assert(AB <= kBackThreads, "one thread stages one angle");
     auto &win = L.win;
     auto &prm = L.prm;
     auto &part = L.part;
@@ -312,8 +313,8 @@ __device__ inline void back_tile(const T *__restrict__ y, T *__restrict__ x,
     const T ftx = T(tx), fty = T(ty0);
     const T dsT = T(ds);
     T acc[kPixPerLane] = {};
-    for (int a0 = 0; a0 < n_ang; a0 += kAngBlock) {
-        const int na = min(kAngBlock, n_ang - a0);
+    for (int a0 = 0; a0 < n_ang; a0 += AB) {
+        const int na = min(AB, n_ang - a0);
         __syncthreads();
         if (threadIdx.x < na) {
             const AngleParams P = ang[a0 + threadIdx.x];

@@ -24,7 +24,7 @@ namespace {
 
 struct Layout {
     size_t V, Z, cur, q, rb0, tm, tn, fpws, H, R, cs, sn, g, Y, rho;
-    size_t part, mgs_part, count, st, ncp, total;
+    size_t part, mgs_part, tick, count, st, ncp, total;
     long long L, ldv, mp, np;
     int mgs_rows;
     long long mgs_cap;
@@ -69,6 +69,7 @@ Layout make_layout(const Geometry &g, int method, int k_max, abg_precision p, ab
     const long long gmax = std::min<long long>(kMaxGrid, (ly.L + 255) / 256);
     ly.mgs_cap = 2LL * ly.mgs_rows * gmax;
     ly.mgs_part = take((size_t)ly.mgs_cap * 8);
+    ly.tick = take((ld + 2) * 4);
     ly.count = take(64);
     ly.st = take(sizeof(DevState));
     ly.ncp = st.kind == ABG_STOP_NCP ? take(ncp_scratch_bytes(g)) : 0;
@@ -140,7 +141,7 @@ struct Solve {
     char *W;
     void *V, *Z, *cur, *q, *rb0, *tm, *tn, *fpws;
     double *H, *R, *cs, *sn, *gv, *Y, *rho, *part, *mgs_part;
-    unsigned *count;
+    unsigned *count, *tick;
     DevState *dst;
     double *ncp;
     HostRes hr;
@@ -174,6 +175,7 @@ struct Solve {
         part = reinterpret_cast<double *>(W + ly.part);
         mgs_part = reinterpret_cast<double *>(W + ly.mgs_part);
         count = reinterpret_cast<unsigned *>(W + ly.count);
+        tick = reinterpret_cast<unsigned *>(W + ly.tick);
         dst = reinterpret_cast<DevState *>(W + ly.st);
         ncp = ly.ncp ? reinterpret_cast<double *>(W + ly.ncp) : nullptr;
         sX = dtype_size(p.proj);
@@ -215,6 +217,7 @@ struct Solve {
         M.vout = vec(k);
         M.cur = cur;
         M.rows = ly.mgs_rows;
+        M.ticket = tick + k;
         return M;
     }
 
@@ -292,6 +295,7 @@ struct Solve {
     {
         const long long m = g.m();
         CK(launch_clear_slots(mgs_part, (size_t)ly.mgs_cap, s));
+        CK(launch_fill_u32(tick, (size_t)ld + 2, 0u, s));
         CK(launch_fill_u32(count, 16, 0u, s));
         CK(launch_fill_f64(H, (size_t)ld * k_max, 0.0, s));
         CK(launch_fill_f64(gv, (size_t)ld, 0.0, s));
