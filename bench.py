@@ -84,6 +84,119 @@ def cpu_oracle_baseline(w, b_np, enorm, budget_s=15.0, max_iters=10):
         k = min(max_iters, k * 2)
 
 
+def _dp_problem(abg, torch, gg, w, xt, dev, seed):
+    """b = A x + e for the workload's phantom x (device forward projector), e Gaussian
+    from a seeded device generator, scaled to ||e|| = eta ||A x||."""
+    bc = gg.fp(xt)
+    gg.release_workspace()
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(seed)
+    e = torch.randn(bc.numel(), generator=gen, device=dev, dtype=bc.dtype)
+    e *= w.eta * torch.linalg.vector_norm(bc) / torch.linalg.vector_norm(e)
+    b = bc + e
+    return abg.Problem(g=gg, method=w.method, b=b, k_max=w.k_max, stop="dp", tau=w.tau,
+                       noise_norm=float(torch.linalg.vector_norm(e.double())))
+
+
+def _single_solves(abg, torch, probs, dtype):
+    """Sequential single solves (the plain method) of the problems; returns (s, results)."""
+    bs = [p.b.to(dtype) for p in probs]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = [abg.gmres(p.method, p.g, b, p.k_max, stop=p.stop, tau=p.tau, noise_norm=p.noise_norm,
+                     bp=p.bp) for p, b in zip(probs, bs)]
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, out
+
+
+def bench_batched(abg, torch, dev, reps=3):
+    """The 64-problem batched workload (N in {128..1024}, 60..720 angles, half limited
+    angle, AB/BA alternating, per-problem DP): engine throughput after autotuning, next to
+    the same 64 solves run one by one (FP32 and plain FP64)."""
+    ws = W.batched_workloads()
+    probs = []
+    for w in ws:
+        gg = abg.Geometry(w.N, w.n_ang, w.n_det, ang_range=w.ang_range)
+        xt = torch.tensor(w.phantom().ravel(), dtype=torch.float32, device=dev)
+        probs.append(_dp_problem(abg, torch, gg, w, xt, dev, 4_000_000 + w.instance))
+    eng = abg.Engine(proj="f32", basis="f32", max_slots=len(probs))
+    xs = [torch.empty(p.g.n, dtype=torch.float32, device=dev) for p in probs]
+    wss = [torch.empty(abg.request_bytes(p.g, p.method, p.k_max, "f32", "f32", "dp"),
+                       dtype=torch.uint8, device=dev) for p in probs]
+
+    def run(tune=False):
+        tags = [eng.submit(p, x=x, workspace=w_) for p, x, w_ in zip(probs, xs, wss)]
+        tuned = eng.autotune(reps=3) if tune else None
+        done = {}
+        while len(done) < len(tags):
+            eng.step()
+            done.update(dict(eng.poll()))
+        return [done[t] for t in tags], tuned
+
+    run()                                   # warm-up (graph capture, allocations)
+    _, tuned = run(tune=True)
+    times = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res, _ = run()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    tb = float(np.median(times))
+    t32, s32 = _single_solves(abg, torch, probs, torch.float32)
+    t64, s64 = _single_solves(abg, torch, probs, torch.float64)
+    same_k = sum(int(a.k_stop == b.k_stop) for a, b in zip(res, s64))
+    err = max(float(torch.linalg.vector_norm(a.x.double() - b.x) / torch.linalg.vector_norm(b.x))
+              for a, b in zip(res, s64))
+    eng.close()
+    return {"workload": "64 problems: N in {128,256,512,1024}, angles in {60,180,360,720}, "
+                        "32 full-range [0,180) + 32 limited [0,120), eta U[0.005,0.03], AB/BA "
+                        "alternating, DP tau=1.02, k_max=100; FP32 projectors and basis",
+            "reconstructions_per_s": round(len(probs) / tb, 1), "ms_per_batch": round(1e3 * tb, 2),
+            "arnoldi_iterations": int(sum(r.k_done for r in res)),
+            "tiles": {"rays": tuned["rays"], "ang_block": tuned["ang_block"]},
+            "single_fp32_recon_per_s": round(len(probs) / t32, 1),
+            "single_fp64_recon_per_s": round(len(probs) / t64, 1),
+            "speedup_vs_single_fp64": round(t64 / tb, 2),
+            "same_k_stop_as_fp64": f"{same_k}/{len(probs)}",
+            "max_rel_diff_vs_fp64": float(f"{err:.3g}")}
+
+
+def bench_serving(abg, torch, dev, seconds, bases, tiles, single_sample=24):
+    """Poisson request stream (50/s; N in {256..2048}, 180-1800 angles, AB/BA, k_max in
+    [30,120], DP) through the continuous-batching server under a 200 GB workspace budget,
+    in real time and as a closed batch, per basis dtype; the plain FP64 single-solve rate
+    on the first requests for comparison."""
+    from paper_2110_01481_amd.serving import Request, Server
+    stream = W.serving_requests(rate=50.0, duration=seconds)
+    pool = {N: [torch.tensor(W.ellipse_phantom(N, 10, W.rng(5, 100000 + 10 * N + j, 0)).ravel(),
+                             dtype=torch.float32, device=dev) for j in range(2)]
+            for N in sorted({w.N for _, w in stream})}
+    reqs = []
+    for i, (t, w) in enumerate(stream):
+        gg = abg.Geometry(w.N, w.n_ang, w.n_det, ang_range=w.ang_range)
+        reqs.append(Request(t, _dp_problem(abg, torch, gg, w, pool[w.N][i % 2], dev, 5_000_000 + i)))
+    out = {"workload": f"Poisson arrivals 50/s for {seconds:g} s ({len(reqs)} requests): N in "
+                       "{256,512,1024,2048}, angles U{180..1800}, eta U[0.01,0.03], AB/BA 50/50, "
+                       "k_max U{30..120}, DP tau=1.02; admission by request workspace bytes "
+                       "against a 200 GB budget",
+           "runs": {}}
+    for basis in bases:
+        srv = Server(proj="f32", basis=basis, max_slots=256, budget_bytes=200e9, tiles=tiles)
+        live = srv.run(reqs, realtime=True)
+        closed = srv.run(reqs, realtime=False)
+        srv.close()
+        out["runs"][basis] = {"realtime": live.as_dict(),
+                              "closed_batch_reconstructions_per_s": round(closed.completed_per_s, 2)}
+    sample = [r.problem for r in reqs[:single_sample]]
+    t64, _ = _single_solves(abg, torch, sample, torch.float64)
+    t32, _ = _single_solves(abg, torch, sample, torch.float32)
+    out["single_fp64_recon_per_s"] = round(len(sample) / t64, 2)
+    out["single_fp32_recon_per_s"] = round(len(sample) / t32, 2)
+    out["single_sample"] = f"first {len(sample)} requests, solved one by one"
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -93,6 +206,10 @@ def main():
     ap.add_argument("--basis", default="f32", choices=["f32", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
+                    help="seconds of Poisson arrivals for the serving run (0: skip)")
+    ap.add_argument("--serve-basis", default="f32,bf16")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus N > 1 is not supported "
@@ -218,6 +335,14 @@ def main():
         extra["f32_vs_f64_iterate_rel"] = {
             m: float(torch.linalg.vector_norm(last[m].x.double() - r64[m].x) /
                      torch.linalg.vector_norm(r64[m].x)) for m in methods}
+
+    tiles = None
+    if not args.no_batch:
+        extra["batched"] = bench_batched(abg, torch, dev)
+        tiles = (extra["batched"]["tiles"]["rays"], extra["batched"]["tiles"]["ang_block"])
+    if args.serve_seconds > 0:
+        extra["serving"] = bench_serving(abg, torch, dev, args.serve_seconds,
+                                         [b for b in args.serve_basis.split(",") if b], tiles)
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -245,6 +245,13 @@ int abg_profile_enable(int on);
  * projector, 1 back projector, 2 Gram-Schmidt, 3 basis combination. */
 int abg_profile_read(long long counts[4], double ms[4], int reset);
 
+/* Single solves whose basis vectors are longer than 2^21 elements carry an FP64 scratch
+ * vector and switch to a streaming Gram-Schmidt variant (q_k in that scratch, one pass per
+ * inner product) when q_k does not fit the registers of the blocks the device holds at
+ * once. With on != 0 they always take the streaming variant (process-wide; for tests
+ * and measurements). */
+int abg_mgs_force_stream(int on);
+
 #ifdef __cplusplus
 }
 #endif

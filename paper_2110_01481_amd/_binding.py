@@ -26,7 +26,8 @@ EXPORTS = ["abg_create_geometry", "abg_destroy_geometry", "abg_geometry_sizes",
            "abg_ab_gmres", "abg_ba_gmres", "abg_status_string", "abg_profile_enable",
            "abg_profile_read", "abg_request_bytes", "abg_engine_create", "abg_engine_destroy",
            "abg_engine_submit", "abg_engine_step", "abg_engine_poll", "abg_engine_set_tiles",
-           "abg_engine_get_tiles", "abg_engine_autotune", "abg_batch_solve"]
+           "abg_engine_get_tiles", "abg_engine_autotune", "abg_batch_solve",
+           "abg_mgs_force_stream"]
 
 
 class AbgError(RuntimeError):
@@ -104,6 +105,7 @@ def load_library(path: str | None = None):
     lib.abg_engine_get_tiles.argtypes = [vp, ctypes.POINTER(i), ctypes.POINTER(i)]
     lib.abg_engine_autotune.argtypes = [vp, i, ctypes.POINTER(i), ctypes.POINTER(i), _dp]
     lib.abg_batch_solve.argtypes = [ctypes.POINTER(Request), i, Precision, i, i, vp]
+    lib.abg_mgs_force_stream.argtypes = [i]
     _lib = lib
     return lib
 
@@ -177,6 +179,10 @@ class Geometry:
     @property
     def handle(self):
         return self._h
+
+    def release_workspace(self):
+        """Drops the cached forward-projector scratch of fp()."""
+        self._fp_ws.clear()
 
     def fp_workspace(self, dtype_code: int, device):
         key = (dtype_code, str(device))
@@ -293,6 +299,12 @@ def ab_gmres(g, b, k_max, **kw) -> SolveResult:
 
 def ba_gmres(g, b, k_max, **kw) -> SolveResult:
     return gmres("ba", g, b, k_max, **kw)
+
+
+def mgs_force_stream(on: bool = True):
+    """Single solves of vectors longer than 2^21 elements always use the streaming
+    Gram-Schmidt variant (abg_mgs_force_stream)."""
+    load_library().abg_mgs_force_stream(1 if on else 0)
 
 
 def profile_enable(on: bool = True):

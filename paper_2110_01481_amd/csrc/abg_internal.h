@@ -98,6 +98,22 @@ struct DevState {
 enum { kStopNone = 0, kStopDP = 1, kStopNCP = 2, kStopError = 3, kStopZero = 4 };
 
 #ifdef __HIPCC__
+// A pointer read from memory (a descriptor field) is a generic pointer to the compiler,
+// which then emits flat loads through it. Reading the field as a global-address-space
+// pointer and converting that value to a generic one lets the compiler prove the target
+// is global memory and use global loads (cheaper addressing, and not counted against
+// LDS traffic).
+template <typename T, typename F> __device__ inline T *gfield(const F &field)
+{
+    static_assert(sizeof(F) == sizeof(void *), "pointer field");
+#if defined(__HIP_DEVICE_COMPILE__)
+    using GP = __attribute__((address_space(1))) T *;
+    return (T *)(*reinterpret_cast<const GP *>(&field));
+#else
+    return (T *)field;
+#endif
+}
+
 // True when per-step kernels of step k must not run.
 __device__ inline bool halted(const DevState *st, int k)
 {
@@ -111,6 +127,9 @@ __device__ inline bool halted(const DevState *st, int k)
 // allocated with a length rounded up to a multiple of kVecPad elements, zero past their
 // logical length, so that every register tile of the MGS kernels lies inside them.
 constexpr long long kVecPad = 16384;
+// Longer vectors may not fit the registers of one resident block group: their solves
+// carry an FP64 scratch copy of q_k for the streaming Gram-Schmidt variant.
+constexpr long long kRegMaxL = 2 * 1024 * 1024;
 
 struct MgsLaunch {
     int tx, tv;                  // dtypes of q / cur and of the basis
@@ -125,6 +144,7 @@ struct MgsLaunch {
     double *partials;            // reduction slot tables: 2 x rows x G doubles
     int rows;                    // rows per table (>= k + 3 for every step of the solve)
     unsigned *ticket;            // zeroed counter of this step: hands out block ranks
+    double *q64;                 // FP64 scratch of L elements (needed when L > kRegMaxL)
     DevState *st;
     double bd_rel;               // breakdown: h_{k+1,k} <= bd_rel * ||q_k||
     int step;                    // Arnoldi step (0: the initial normalisation)
@@ -154,6 +174,9 @@ hipError_t launch_givens(double *H, int ld, double *R, double *cs, double *sn, d
 // Clears the stop flag (after a DP candidate that the explicit residual rejected).
 hipError_t launch_clear_stop(DevState *st, hipStream_t s);
 void set_mgs_target_blocks(int blocks);
+// Single solves use the streaming Gram-Schmidt variant whenever their workspace has its
+// scratch (vectors longer than kRegMaxL), not only when the register tile does not fit.
+void set_mgs_force_stream(int on);
 hipError_t launch_fill_u32(unsigned *p, size_t n, unsigned v, hipStream_t s);
 hipError_t launch_fill_f64(double *p, size_t n, double v, hipStream_t s);
 // Marks MGS reduction slots empty (n doubles).
@@ -178,7 +201,7 @@ int run_solver(const Geometry &g, int method, int kind, const void *b, const voi
 // Buffers inside a solve's workspace (the same layout as a single solve).
 struct InstanceView {
     void *V, *Z, *cur, *q, *rb0, *tm, *tn, *fpws;
-    double *H, *R, *cs, *sn, *g, *Y, *rho, *part, *mgs_part;
+    double *H, *R, *cs, *sn, *g, *Y, *rho, *part, *mgs_part, *q64;
     unsigned *count;
     long long L, ldv, mp, np;
     int part_cap;                 // doubles in part

@@ -42,6 +42,7 @@ enum Tab {
     kTFwdAB,       // q = A t (AB)
     kTMgsS,        // MGS groups with the small register tile
     kTMgsL,        // MGS groups with the large register tile
+    kTMgsX,        // streaming MGS groups (vectors longer than kRegMaxL)
     kTRes,         // residual chunks
     kTGiv,         // one Givens block per problem
     kNumTab
@@ -50,6 +51,7 @@ enum Tab {
 constexpr int kMgsSmallE = 8;
 constexpr int kMgsLargeE = 32;
 constexpr int kMgsSmallMaxG = 128;
+constexpr int kMgsStreamG = 128;
 constexpr int kResU = 4;
 
 // Per-problem descriptor in device memory.
@@ -60,12 +62,12 @@ struct BatchInst {
     int method, kind, k_max, ld;
     long long L, ldv, mp, n, m;
     void *V, *Z, *cur, *q, *rb0, *tm, *tn, *xr, *xc;
-    double *H, *R, *cs, *sn, *g, *Y, *rho, *part, *mgs_part;
+    double *H, *R, *cs, *sn, *g, *Y, *rho, *part, *mgs_part, *q64;
     unsigned *count;
     double bd_rel;
     int mgs_rows;
     int need_res;
-    int mgs_G, mgs_large;
+    int mgs_G, mgs_class;   // class 0: small register tile, 1: large, 2: streaming
     int chunk, n_chunks;
 };
 
@@ -104,8 +106,9 @@ __device__ int items_of(int t, const BatchInst &d, const Tiles &tl)
         const int apb = 256 / tl.rays;
         return ceil_div(d.n_ang, apb) * ceil_div(d.n_det, tl.rays);
     }
-    case kTMgsS: return d.mgs_large ? 0 : d.mgs_G;
-    case kTMgsL: return d.mgs_large ? d.mgs_G : 0;
+    case kTMgsS: return d.mgs_class == 0 ? d.mgs_G : 0;
+    case kTMgsL: return d.mgs_class == 1 ? d.mgs_G : 0;
+    case kTMgsX: return d.mgs_class == 2 ? d.mgs_G : 0;
     case kTRes: return d.need_res ? d.n_chunks : 0;
     case kTGiv: return 1;
     }
@@ -114,7 +117,7 @@ __device__ int items_of(int t, const BatchInst &d, const Tiles &tl)
 
 // ---- begin ------------------------------------------------------------------------------
 // Block t builds list t; block 0 also publishes each problem's step for the round.
-__global__ __launch_bounds__(256) void begin_kernel(const BatchInst *D, DevState *S, TabView tv,
+__global__ __launch_bounds__(256) void begin_kernel(const BatchInst *__restrict__ D, DevState *S, TabView tv,
                                                     int n_slots, Tiles tl)
 {
     __shared__ int wsum_n[4], wsum_c[4];
@@ -225,13 +228,13 @@ __device__ inline bool next_item(const TabView &tv, int t, int *slot_out, int *l
 
 template <typename T> __device__ inline T *zcol(const BatchInst &d, int k)
 {
-    return d.Z ? static_cast<T *>(d.Z) + (size_t)(k - 1) * d.mp : static_cast<T *>(d.tm);
+    return d.Z ? gfield<T>(d.Z) + (size_t)(k - 1) * d.mp : gfield<T>(d.tm);
 }
 
 // ---- projector phases ---------------------------------------------------------------------
 // mode 0: BA, w_k;  mode 1: AB, t
 template <typename T>
-__global__ __launch_bounds__(256) void bpad_kernel(const BatchInst *D, const DevState *S,
+__global__ __launch_bounds__(256) void bpad_kernel(const BatchInst *__restrict__ D, const DevState *S,
                                                    TabView tv, int t, int mode)
 {
     __shared__ PadLds<T> lds;
@@ -244,15 +247,15 @@ __global__ __launch_bounds__(256) void bpad_kernel(const BatchInst *D, const Dev
         if (halted(st, st->kcur)) continue;
         __syncthreads();   // the previous tile's LDS reads are done
         const int tpr = (d.N + 31) / 32;
-        const T *src = static_cast<const T *>(mode == 0 ? d.cur : d.tn);
-        pad_transpose_tile(src, static_cast<T *>(d.xr), static_cast<T *>(d.xc), d.N, d.S,
+        const T *src = mode == 0 ? gfield<const T>(d.cur) : gfield<const T>(d.tn);
+        pad_transpose_tile(src, gfield<T>(d.xr), gfield<T>(d.xc), d.N, d.S,
                            (local % tpr) * 32, (local / tpr) * 32, lds);
     }
 }
 
 // mode 0: BA, z = A w_k (column k of Z);  mode 1: AB, q = A t
 template <typename T>
-__global__ __launch_bounds__(256) void bfwd_kernel(const BatchInst *D, const DevState *S,
+__global__ __launch_bounds__(256) void bfwd_kernel(const BatchInst *__restrict__ D, const DevState *S,
                                                    TabView tv, int t, int mode, Tiles tl)
 {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -271,15 +274,15 @@ __global__ __launch_bounds__(256) void bfwd_kernel(const BatchInst *D, const Dev
         const int a = (local / nrg) * apb + wave / wpa;
         const int i = (local % nrg) * tl.rays + (wave % wpa) * 64 + lane;
         if (a >= d.n_ang) continue;
-        T *y = mode == 0 ? zcol<T>(d, k) : static_cast<T *>(d.q);
-        forward_ray(static_cast<const T *>(d.xr), static_cast<const T *>(d.xc), y, d.ang, a, i,
-                    d.N, d.S, d.n_det, d.ds, d.s0);
+        T *y = mode == 0 ? zcol<T>(d, k) : gfield<T>(d.q);
+        forward_ray(gfield<const T>(d.xr), gfield<const T>(d.xc), y,
+                    gfield<const AngleParams>(d.ang), a, i, d.N, d.S, d.n_det, d.ds, d.s0);
     }
 }
 
 // mode 0: AB, t = B w_k;  mode 1: BA, q = B z
 template <typename T, int AB>
-__global__ __launch_bounds__(kBackThreads) void bback_kernel(const BatchInst *D,
+__global__ __launch_bounds__(kBackThreads) void bback_kernel(const BatchInst *__restrict__ D,
                                                              const DevState *S, TabView tv,
                                                              int t, int mode)
 {
@@ -294,12 +297,13 @@ __global__ __launch_bounds__(kBackThreads) void bback_kernel(const BatchInst *D,
         if (halted(st, k)) continue;
         const int tpr = (d.N + kTile - 1) / kTile;
         const int c0 = (local % tpr) * kTile, r0 = (local / tpr) * kTile;
-        const T *y = mode == 0 ? static_cast<const T *>(d.cur) : zcol<T>(d, k);
-        T *x = static_cast<T *>(mode == 0 ? d.tn : d.q);
+        const T *y = mode == 0 ? gfield<const T>(d.cur) : zcol<T>(d, k);
+        T *x = mode == 0 ? gfield<T>(d.tn) : gfield<T>(d.q);
+        const AngleParams *ang = gfield<const AngleParams>(d.ang);
         if (d.kind == ABG_BP_ADJ)
-            back_tile<T, true, AB>(y, x, d.ang, d.N, d.n_ang, d.n_det, d.ds, d.s0, c0, r0, lds);
+            back_tile<T, true, AB>(y, x, ang, d.N, d.n_ang, d.n_det, d.ds, d.s0, c0, r0, lds);
         else
-            back_tile<T, false, AB>(y, x, d.ang, d.N, d.n_ang, d.n_det, d.ds, d.s0, c0, r0, lds);
+            back_tile<T, false, AB>(y, x, ang, d.N, d.n_ang, d.n_det, d.ds, d.s0, c0, r0, lds);
     }
 }
 
@@ -308,7 +312,7 @@ __global__ __launch_bounds__(kBackThreads) void bback_kernel(const BatchInst *D,
 // every group whose first rank is taken is completed by blocks that are running (each
 // group is smaller than the grid).
 template <typename TX, typename TV, int E>
-__global__ __launch_bounds__(kBlock) void bmgs_kernel(const BatchInst *D, DevState *S,
+__global__ __launch_bounds__(kBlock) void bmgs_kernel(const BatchInst *__restrict__ D, DevState *S,
                                                       TabView tv, int t)
 {
     __shared__ double lds[kWaves];
@@ -319,24 +323,27 @@ __global__ __launch_bounds__(kBlock) void bmgs_kernel(const BatchInst *D, DevSta
         const int k = st->kcur;
         if (halted(st, k)) continue;
         MgsDev a;
-        a.q = d.q;
-        a.V = d.V;
+        a.q = gfield<const TX>(d.q);
+        a.V = gfield<const TV>(d.V);
         a.ldv = (size_t)d.ldv;
         a.k = k;
         a.L = d.L;
-        a.hcol = d.H + (size_t)(k - 1) * d.ld;
-        a.vout = static_cast<TV *>(d.V) + (size_t)k * d.ldv;
-        a.cur = d.cur;
-        a.partials = d.mgs_part;
+        a.hcol = gfield<double>(d.H) + (size_t)(k - 1) * d.ld;
+        a.vout = gfield<TV>(d.V) + (size_t)k * d.ldv;
+        a.cur = gfield<TX>(d.cur);
+        a.partials = gfield<double>(d.mgs_part);
         a.rows = d.mgs_rows;
         a.st = st;
         a.bd_rel = d.bd_rel;
         a.step = k;
-        mgs_body<TX, TV, E>(a, rank, d.mgs_G, lds);
+        a.ticket = nullptr;
+        a.q64 = gfield<double>(d.q64);
+        if constexpr (E == 0) mgs_stream_body<TX, TV>(a, rank, d.mgs_G, lds);
+        else mgs_body<TX, TV, E>(a, rank, d.mgs_G, lds);
     }
 }
 
-__global__ __launch_bounds__(64) void bgivens_kernel(const BatchInst *D, DevState *S, TabView tv)
+__global__ __launch_bounds__(64) void bgivens_kernel(const BatchInst *__restrict__ D, DevState *S, TabView tv)
 {
     if ((int)blockIdx.x >= tv.nseg[kTGiv]) return;
     const int slot = tv.seg_slot(kTGiv, blockIdx.x);
@@ -344,16 +351,17 @@ __global__ __launch_bounds__(64) void bgivens_kernel(const BatchInst *D, DevStat
     DevState *st = S + slot;
     const int k = st->kcur;
     if (halted(st, k)) return;
-    double *rho = (d.method == ABG_METHOD_AB && d.need_res) ? d.rho : nullptr;
-    givens_step(d.H, d.ld, d.R, d.cs, d.sn, d.g, d.Y + (size_t)(k - 1) * d.k_max, rho, st->beta,
-                k, st);
+    double *rho = (d.method == ABG_METHOD_AB && d.need_res) ? gfield<double>(d.rho) : nullptr;
+    givens_step(gfield<double>(d.H), d.ld, gfield<double>(d.R), gfield<double>(d.cs),
+                gfield<double>(d.sn), gfield<double>(d.g),
+                gfield<double>(d.Y) + (size_t)(k - 1) * d.k_max, rho, st->beta, k, st);
 }
 
 // ||r_k|| by chunks: BA r = (b - A x0) - Z y_k, AB r = W_{k+1} rho. Each chunk's sum of
 // squares is published; the last chunk to finish adds them in chunk order, writes the
 // norm and raises the DP candidate stop.
 template <typename TX, typename TV>
-__global__ __launch_bounds__(kBlock) void bres_kernel(const BatchInst *D, DevState *S, TabView tv)
+__global__ __launch_bounds__(kBlock) void bres_kernel(const BatchInst *__restrict__ D, DevState *S, TabView tv)
 {
     __shared__ double cf[kMaxCoef];
     __shared__ double lds[kWaves];
@@ -369,12 +377,13 @@ __global__ __launch_bounds__(kBlock) void bres_kernel(const BatchInst *D, DevSta
         const bool ba = d.method == ABG_METHOD_BA;
         __syncthreads();   // the previous item's use of cf and `last` is done
         const int kk = ba ? k : k + 1;
-        const double *coef = ba ? d.Y + (size_t)(k - 1) * d.k_max : d.rho;
+        const double *coef =
+            ba ? gfield<double>(d.Y) + (size_t)(k - 1) * d.k_max : gfield<double>(d.rho);
         for (int j = threadIdx.x; j < kk; j += kBlock) cf[j] = ba ? -coef[j] : coef[j];
         __syncthreads();
         const long long lo = (long long)c * d.chunk;
         const long long hi = min(lo + (long long)d.chunk, d.m);
-        const TX *base = ba ? static_cast<const TX *>(d.rb0) : nullptr;
+        const TX *base = ba ? gfield<const TX>(d.rb0) : nullptr;
         double ss = 0.0;
         for (long long l0 = lo + threadIdx.x; l0 < hi; l0 += kResU * kBlock) {
             double acc[kResU];
@@ -388,11 +397,11 @@ __global__ __launch_bounds__(kBlock) void bres_kernel(const BatchInst *D, DevSta
             for (int j = 0; j < kk; ++j) {
                 double x[kResU];
                 if (ba) {
-                    const TX *v = static_cast<const TX *>(d.Z) + (size_t)j * d.mp + l0;
+                    const TX *v = gfield<const TX>(d.Z) + (size_t)j * d.mp + l0;
 #pragma unroll
                     for (int u = 0; u < kResU; ++u) x[u] = in[u] ? to_f64(v[u * kBlock]) : 0.0;
                 } else {
-                    const TV *v = static_cast<const TV *>(d.V) + (size_t)j * d.ldv + l0;
+                    const TV *v = gfield<const TV>(d.V) + (size_t)j * d.ldv + l0;
 #pragma unroll
                     for (int u = 0; u < kResU; ++u) x[u] = in[u] ? to_f64(v[u * kBlock]) : 0.0;
                 }
@@ -532,7 +541,7 @@ struct Engine {
     Tiles tiles{256, 128};
     int grid_proj = 0, grid_back = 0, grid_back64 = 0, grid_mgs_s = 0, grid_mgs_l = 0, grid_res = 0;
     hipEvent_t tev[2] = {};
-    int cap_mgs_s = 0, cap_mgs_l = 0;
+    int cap_mgs_s = 0, cap_mgs_l = 0, cap_mgs_x = 0, grid_mgs_x = 0;
     int broken = 0;
     std::vector<Slot> slots;
     std::vector<std::pair<long long, int>> finished;
@@ -571,6 +580,8 @@ struct Engine {
         if ((e = capacity_of(bback_kernel<TX, 64>, kBackThreads, &grid_back64)) != hipSuccess) return e;
         if ((e = capacity_of(bmgs_kernel<TX, TV, kMgsSmallE>, kBlock, &cap_mgs_s)) != hipSuccess) return e;
         if ((e = capacity_of(bmgs_kernel<TX, TV, kMgsLargeE>, kBlock, &cap_mgs_l)) != hipSuccess) return e;
+        if ((e = capacity_of(bmgs_kernel<TX, TV, 0>, kBlock, &cap_mgs_x)) != hipSuccess) return e;
+        grid_mgs_x = cap_mgs_x;
         if ((e = capacity_of(bres_kernel<TX, TV>, kBlock, &grid_res)) != hipSuccess) return e;
         grid_mgs_s = cap_mgs_s;
         grid_mgs_l = cap_mgs_l;
@@ -617,6 +628,7 @@ struct Engine {
         enqueue_projectors_t<TX>(q, tiles);
         bmgs_kernel<TX, TV, kMgsSmallE><<<grid_mgs_s, kBlock, 0, q>>>(d_desc, d_st, tv, kTMgsS);
         bmgs_kernel<TX, TV, kMgsLargeE><<<grid_mgs_l, kBlock, 0, q>>>(d_desc, d_st, tv, kTMgsL);
+        bmgs_kernel<TX, TV, 0><<<grid_mgs_x, kBlock, 0, q>>>(d_desc, d_st, tv, kTMgsX);
         bgivens_kernel<<<max_slots, 64, 0, q>>>(d_desc, d_st, tv);
         bres_kernel<TX, TV><<<grid_res, kBlock, 0, q>>>(d_desc, d_st, tv);
     }
@@ -703,15 +715,26 @@ struct Engine {
         d.rho = v.rho;
         d.part = v.part;
         d.mgs_part = v.mgs_part;
+        d.q64 = v.q64;
         d.mgs_rows = v.mgs_rows;
         d.count = v.count;
         d.bd_rel = (p.basis == ABG_F64 && p.proj == ABG_F64) ? 1e-14 : 1e-6;
         d.need_res = r.stop.kind == ABG_STOP_DP;
+        // Gram-Schmidt class: small register tile while its group stays small, else the
+        // large tile, else (vectors longer than kRegMaxL) the streaming variant
         long long G = (v.L + (long long)kBlock * kMgsSmallE - 1) / ((long long)kBlock * kMgsSmallE);
-        d.mgs_large = G > kMgsSmallMaxG;
-        if (d.mgs_large)
+        d.mgs_class = 0;
+        int capG = cap_mgs_s;
+        if (v.L > kRegMaxL) {
+            d.mgs_class = 2;
+            G = kMgsStreamG;
+            capG = cap_mgs_x;
+            if (!v.q64) return ABG_EINVAL;
+        } else if (G > kMgsSmallMaxG) {
+            d.mgs_class = 1;
             G = (v.L + (long long)kBlock * kMgsLargeE - 1) / ((long long)kBlock * kMgsLargeE);
-        const int capG = d.mgs_large ? cap_mgs_l : cap_mgs_s;
+            capG = cap_mgs_l;
+        }
         if (G > capG / 2 || 2LL * v.mgs_rows * G > v.mgs_part_cap) return ABG_EINVAL;
         d.mgs_G = (int)std::max(1LL, G);
         long long chunk = 8192;

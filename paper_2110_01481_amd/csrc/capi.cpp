@@ -443,6 +443,12 @@ int abg_batch_solve(const abg_request *r, int n, abg_precision p, int rays, int 
     return first_err;
 }
 
+int abg_mgs_force_stream(int on)
+{
+    set_mgs_force_stream(on);
+    return ABG_OK;
+}
+
 const char *abg_status_string(int status)
 {
     switch (status) {

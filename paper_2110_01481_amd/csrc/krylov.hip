@@ -10,6 +10,7 @@
 //           with FP64 accumulation and a fixed-order norm reduction.
 // Every reduction runs in a fixed order, so results are identical run to run.
 #include <cmath>
+#include <algorithm>
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
@@ -36,6 +37,19 @@ __global__ __launch_bounds__(kBlock) void mgs_kernel(MgsDev a)
     __syncthreads();
     const int rank = __builtin_amdgcn_readfirstlane(s_rank);
     mgs_body<TX, TV, E>(a, rank, gridDim.x, lds);
+}
+
+template <typename TX, typename TV>
+__global__ __launch_bounds__(kBlock) void mgs_stream_kernel(MgsDev a)
+{
+    __shared__ double lds[kWaves];
+    __shared__ int s_rank;
+    if (halted(a.st, a.step)) return;
+    if (threadIdx.x == 0)
+        s_rank = (int)__hip_atomic_fetch_add(a.ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const int rank = __builtin_amdgcn_readfirstlane(s_rank);
+    mgs_stream_body<TX, TV>(a, rank, gridDim.x, lds);
 }
 
 // ---- resident-block bookkeeping -----------------------------------------------------
@@ -78,6 +92,23 @@ int default_target_blocks()
     return v > 0 ? v : 256;
 }
 int g_target_blocks = default_target_blocks();
+int g_force_stream = 0;
+
+// Streaming variant: a group of at most kStreamBlocks resident blocks.
+constexpr int kStreamBlocks = 256;
+
+template <typename TX, typename TV>
+hipError_t mgs_stream_go(const MgsDev &d, hipStream_t s)
+{
+    if (!d.q64) return hipErrorInvalidValue;
+    const void *fn = reinterpret_cast<const void *>(&mgs_stream_kernel<TX, TV>);
+    int cap = 0;
+    hipError_t e = resident_capacity(fn, &cap);
+    if (e != hipSuccess) return e;
+    const int G = std::min(kStreamBlocks, cap);
+    mgs_stream_kernel<TX, TV><<<G, kBlock, 0, s>>>(d);
+    return hipGetLastError();
+}
 
 template <typename TX, typename TV, int E>
 hipError_t mgs_go(const MgsDev &d, int G, hipStream_t s)
@@ -86,7 +117,11 @@ hipError_t mgs_go(const MgsDev &d, int G, hipStream_t s)
     int cap = 0;
     hipError_t e = resident_capacity(fn, &cap);
     if (e != hipSuccess) return e;
-    if (G > cap || G > kMaxGrid) return hipErrorCooperativeLaunchTooLarge;
+    if (G > cap || G > kMaxGrid || (g_force_stream && d.q64)) {
+        // q_k does not fit the registers of the blocks the device holds at once
+        if (d.q64) return mgs_stream_go<TX, TV>(d, s);
+        return hipErrorCooperativeLaunchTooLarge;
+    }
     mgs_kernel<TX, TV, E><<<G, kBlock, 0, s>>>(d);
     return hipGetLastError();
 }
@@ -275,6 +310,8 @@ hipError_t combine_go(const void *base, double bcoef, const void *V, size_t ldv,
 
 }  // namespace
 
+void set_mgs_force_stream(int on) { g_force_stream = on ? 1 : 0; }
+
 void set_mgs_target_blocks(int blocks)
 {
     g_target_blocks = blocks < 1 ? 1 : (blocks > kMaxGrid ? kMaxGrid : blocks);
@@ -294,6 +331,7 @@ hipError_t launch_mgs(const MgsLaunch &m, hipStream_t s)
     d.partials = m.partials;
     d.rows = m.rows;
     d.ticket = m.ticket;
+    d.q64 = m.q64;
     d.st = m.st;
     d.bd_rel = m.bd_rel;
     d.step = m.step;

@@ -151,6 +151,7 @@ struct MgsDev {
     DevState *st;
     double bd_rel;
     int step;
+    double *q64;       // FP64 scratch of the streaming variant (vectors longer than kRegMaxL)
 };
 
 // Rank r owns the E*kBlock consecutive elements from r*E*kBlock; register e of a lane
@@ -235,6 +236,97 @@ __device__ inline void mgs_body(const MgsDev &a, int rank, int G, double *lds)
     }
 }
 
+
+// The same orthogonalisation for vectors too long to keep in the registers of one
+// resident block group: q_k lives in an FP64 scratch vector (a.q64, zero-padded like the
+// other vectors) and every stage is one pass over it. Pass i updates q -= h_{i-1} w_{i-1}
+// and accumulates <q, w_i> (or ||q||^2 after the last basis vector), so a stage reads q,
+// w_{i-1} and w_i and writes q once. Block `rank` takes elements rank*kBlock + t +
+// j*G*kBlock; reductions are the same fixed-order group reductions as above.
+template <typename TX, typename TV>
+__device__ inline void mgs_stream_body(const MgsDev &a, int rank, int G, double *lds)
+{
+    double *q64 = a.q64;
+    const size_t T = (size_t)G * kBlock;
+    const size_t L = (size_t)a.L;
+    const TX *q = static_cast<const TX *>(a.q);
+    const TV *V = static_cast<const TV *>(a.V);
+    int *err = &a.st->error;
+    double *tab = a.partials + (size_t)(a.step & 1) * a.rows * G;
+    double *next = a.partials + (size_t)((a.step + 1) & 1) * a.rows * G;
+    if (threadIdx.x == 0) {
+        const double empty = __longlong_as_double((long long)kSlotEmpty);
+        for (int r = 0; r <= a.k + 2 && r < a.rows; ++r)
+            __hip_atomic_store(next + (size_t)r * G + rank, empty, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+    }
+    // pass 0: q64 = q, <q, w_1> and ||q||^2 (or only ||q||^2 when k = 0)
+    double d = 0.0, s2 = 0.0;
+    const TV *w0 = V;
+    for (size_t l = (size_t)rank * kBlock + threadIdx.x; l < L; l += T) {
+        const double v = to_f64(q[l]);
+        q64[l] = v;
+        s2 = fma(v, v, s2);
+        if (a.k > 0) d = fma(v, to_f64(w0[l]), d);
+    }
+    double qq;
+    double hprev = 0.0;
+    if (a.k > 0) {
+        d = block_sum(d, lds);
+        s2 = block_sum(s2, lds);
+        if (threadIdx.x == 0) {
+            publish(tab + rank, d);
+            publish(tab + (size_t)(a.k + 1) * G + rank, s2);
+        }
+        hprev = gather_total(tab, G, lds, err);
+        qq = gather_total(tab + (size_t)(a.k + 1) * G, G, lds, err);
+        if (rank == 0 && threadIdx.x == 0) a.hcol[0] = hprev;
+    } else {
+        s2 = block_sum(s2, lds);
+        if (threadIdx.x == 0) publish(tab + rank, s2);
+        qq = gather_total(tab, G, lds, err);
+    }
+    double hn2 = qq;
+    for (int i = 1; i <= a.k; ++i) {
+        // q -= h_{i-1} w_{i-1}, then <q, w_i> (i < k) or ||q||^2 (i = k)
+        const TV *wp = V + (size_t)(i - 1) * a.ldv;
+        const TV *wi = V + (size_t)i * a.ldv;
+        const bool last = i == a.k;
+        double acc = 0.0;
+        for (size_t l = (size_t)rank * kBlock + threadIdx.x; l < L; l += T) {
+            const double v = fma(-hprev, to_f64(wp[l]), q64[l]);
+            q64[l] = v;
+            acc = last ? fma(v, v, acc) : fma(v, to_f64(wi[l]), acc);
+        }
+        acc = block_sum(acc, lds);
+        if (threadIdx.x == 0) publish(tab + (size_t)i * G + rank, acc);
+        const double h = gather_total(tab + (size_t)i * G, G, lds, err);
+        if (last) {
+            hn2 = h;
+        } else {
+            hprev = h;
+            if (rank == 0 && threadIdx.x == 0) a.hcol[i] = h;
+        }
+    }
+    const double hn = sqrt(hn2);
+    const double q0 = sqrt(qq);
+    const bool finite = isfinite(hn) && isfinite(q0);
+    const bool bd = !(hn > a.bd_rel * q0);
+    if (rank == 0 && threadIdx.x == 0) {
+        a.hcol[a.k] = hn;
+        a.st->hnext = hn;
+        a.st->qnorm0 = q0;
+        if (bd && a.step > 0) a.st->bd_k = a.step;
+        if (!finite) a.st->error |= 2;
+    }
+    TV *vo = static_cast<TV *>(a.vout);
+    TX *cu = static_cast<TX *>(a.cur);
+    for (size_t l = (size_t)rank * kBlock + threadIdx.x; l < L; l += T) {
+        const TV w = (bd || !finite) ? zero_of<TV>() : from_f64<TV>(q64[l] / hn);
+        vo[l] = w;
+        cu[l] = (TX)to_f64(w);
+    }
+}
 
 // One wave. Column k-1 of H has just been written by mgs; R holds the rotated columns,
 // cs/sn the rotations, g the rotated right-hand side. Writes y_k (k entries) and, when

@@ -24,7 +24,7 @@ namespace {
 
 struct Layout {
     size_t V, Z, cur, q, rb0, tm, tn, fpws, H, R, cs, sn, g, Y, rho;
-    size_t part, mgs_part, tick, count, st, ncp, total;
+    size_t part, mgs_part, tick, count, st, ncp, q64, total;
     long long L, ldv, mp, np;
     int mgs_rows;
     long long mgs_cap;
@@ -70,6 +70,7 @@ Layout make_layout(const Geometry &g, int method, int k_max, abg_precision p, ab
     ly.mgs_cap = 2LL * ly.mgs_rows * gmax;
     ly.mgs_part = take((size_t)ly.mgs_cap * 8);
     ly.tick = take((ld + 2) * 4);
+    ly.q64 = ly.L > kRegMaxL ? take((size_t)ly.ldv * 8) : 0;
     ly.count = take(64);
     ly.st = take(sizeof(DevState));
     ly.ncp = st.kind == ABG_STOP_NCP ? take(ncp_scratch_bytes(g)) : 0;
@@ -140,7 +141,7 @@ struct Solve {
     Layout ly;
     char *W;
     void *V, *Z, *cur, *q, *rb0, *tm, *tn, *fpws;
-    double *H, *R, *cs, *sn, *gv, *Y, *rho, *part, *mgs_part;
+    double *H, *R, *cs, *sn, *gv, *Y, *rho, *part, *mgs_part, *q64;
     unsigned *count, *tick;
     DevState *dst;
     double *ncp;
@@ -176,6 +177,7 @@ struct Solve {
         mgs_part = reinterpret_cast<double *>(W + ly.mgs_part);
         count = reinterpret_cast<unsigned *>(W + ly.count);
         tick = reinterpret_cast<unsigned *>(W + ly.tick);
+        q64 = ly.q64 ? reinterpret_cast<double *>(W + ly.q64) : nullptr;
         dst = reinterpret_cast<DevState *>(W + ly.st);
         ncp = ly.ncp ? reinterpret_cast<double *>(W + ly.ncp) : nullptr;
         sX = dtype_size(p.proj);
@@ -218,6 +220,7 @@ struct Solve {
         M.cur = cur;
         M.rows = ly.mgs_rows;
         M.ticket = tick + k;
+        M.q64 = q64;
         return M;
     }
 
@@ -358,6 +361,7 @@ InstanceView instance_view(const Geometry &g, int method, int k_max, abg_precisi
     v.rho = reinterpret_cast<double *>(W + ly.rho);
     v.part = reinterpret_cast<double *>(W + ly.part);
     v.mgs_part = reinterpret_cast<double *>(W + ly.mgs_part);
+    v.q64 = ly.q64 ? reinterpret_cast<double *>(W + ly.q64) : nullptr;
     v.count = reinterpret_cast<unsigned *>(W + ly.count);
     v.L = ly.L;
     v.ldv = ly.ldv;
