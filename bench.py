@@ -154,7 +154,8 @@ def bench_batched(abg, torch, dev, reps=3):
                         "alternating, DP tau=1.02, k_max=100; FP32 projectors and basis",
             "reconstructions_per_s": round(len(probs) / tb, 1), "ms_per_batch": round(1e3 * tb, 2),
             "arnoldi_iterations": int(sum(r.k_done for r in res)),
-            "tiles": {"rays": tuned["rays"], "ang_block": tuned["ang_block"]},
+            "tiles": {"rays": tuned["rays"], "ang_block": tuned["ang_block"],
+                      "sched": tuned["sched"]},
             "single_fp32_recon_per_s": round(len(probs) / t32, 1),
             "single_fp64_recon_per_s": round(len(probs) / t64, 1),
             "speedup_vs_single_fp64": round(t64 / tb, 2),
@@ -182,12 +183,14 @@ def bench_serving(abg, torch, dev, seconds, bases, tiles, single_sample=24):
                        "against a 200 GB budget",
            "runs": {}}
     for basis in bases:
-        srv = Server(proj="f32", basis=basis, max_slots=256, budget_bytes=200e9, tiles=tiles)
+        srv = Server(proj="f32", basis=basis, max_slots=256, budget_bytes=200e9)
+        tuned = srv.tune([r.problem for r in reqs[:32]])
         live = srv.run(reqs, realtime=True)
         closed = srv.run(reqs, realtime=False)
         srv.close()
         out["runs"][basis] = {"realtime": live.as_dict(),
-                              "closed_batch_reconstructions_per_s": round(closed.completed_per_s, 2)}
+                              "closed_batch_reconstructions_per_s": round(closed.completed_per_s, 2),
+                              "tuned_on_first_32": {k: tuned[k] for k in ("rays", "ang_block", "sched")}}
     sample = [r.problem for r in reqs[:single_sample]]
     t64, _ = _single_solves(abg, torch, sample, torch.float64)
     t32, _ = _single_solves(abg, torch, sample, torch.float32)
@@ -339,7 +342,8 @@ def main():
     tiles = None
     if not args.no_batch:
         extra["batched"] = bench_batched(abg, torch, dev)
-        tiles = (extra["batched"]["tiles"]["rays"], extra["batched"]["tiles"]["ang_block"])
+        tiles = (extra["batched"]["tiles"]["rays"], extra["batched"]["tiles"]["ang_block"],
+                 extra["batched"]["tiles"]["sched"])
     if args.serve_seconds > 0:
         extra["serving"] = bench_serving(abg, torch, dev, args.serve_seconds,
                                          [b for b in args.serve_basis.split(",") if b], tiles)

@@ -217,24 +217,28 @@ int abg_engine_step(abg_engine *e, int *n_active);
  * this, their x holds the result and their buffers are the caller's again. */
 int abg_engine_poll(abg_engine *e, long long *tags, int *status, int max, int *n);
 
-/* Tile shapes of the projector work items, taking effect next round. rays: rays of one
- * angle per forward-projector block (64, 128 or 256; a block of 256 threads takes
- * 256/rays angles). ang_block: angles whose detector windows a back-projector block
- * stages in LDS per round (64 or 128). Results do not depend on either. */
-int abg_engine_set_tiles(abg_engine *e, int rays, int ang_block);
-int abg_engine_get_tiles(const abg_engine *e, int *rays, int *ang_block);
+/* Tile shapes and schedule of the projector work items, taking effect next round.
+ * rays: rays of one angle per forward-projector block (64, 128 or 256; a block of 256
+ * threads takes 256/rays angles). ang_block: angles whose detector windows a
+ * back-projector block stages in LDS per round (64 or 128). sched: 0 deals the items out
+ * round-robin over the resident blocks; 1 cuts each item list into 8 contiguous ranges,
+ * one per XCD, that blocks drain in chunks through per-range counters before helping
+ * with the others. Results do not depend on any of them. */
+int abg_engine_set_tiles(abg_engine *e, int rays, int ang_block, int sched);
+int abg_engine_get_tiles(const abg_engine *e, int *rays, int *ang_block, int *sched);
 
-/* Autotuner: times the projector phases of one round for every tile shape on the
- * problems the engine holds (after `reps` repetitions each, without advancing them),
- * keeps the fastest and returns it with its time in ms. Synchronises the stream. With
- * no running problem it keeps the current shape and returns ms = 0. */
-int abg_engine_autotune(abg_engine *e, int reps, int *rays, int *ang_block, double *ms);
+/* Autotuner: times the projector phases of one round for every tile shape and schedule
+ * on the problems the engine holds (after `reps` repetitions each, without advancing
+ * them), keeps the fastest and returns it with its time in ms. Synchronises the stream.
+ * With no running problem it keeps the current choice and returns ms = 0. */
+int abg_engine_autotune(abg_engine *e, int reps, int *rays, int *ang_block, int *sched,
+                        double *ms);
 
 /* Convenience: solves n requests together on a new engine and returns when all are
  * finished (each request's status in its info, if given). Returns the first error, or
- * ABG_OK. rays / ang_block <= 0 keep the default tile shapes. */
+ * ABG_OK. rays / ang_block <= 0 and sched < 0 keep the defaults. */
 int abg_batch_solve(const abg_request *r, int n, abg_precision p, int rays, int ang_block,
-                    void *stream);
+                    int sched, void *stream);
 
 /* ---- instrumentation -------------------------------------------------------------- */
 

@@ -101,10 +101,11 @@ def load_library(path: str | None = None):
     lib.abg_engine_step.argtypes = [vp, ctypes.POINTER(i)]
     lib.abg_engine_poll.argtypes = [vp, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(i), i,
                                     ctypes.POINTER(i)]
-    lib.abg_engine_set_tiles.argtypes = [vp, i, i]
-    lib.abg_engine_get_tiles.argtypes = [vp, ctypes.POINTER(i), ctypes.POINTER(i)]
-    lib.abg_engine_autotune.argtypes = [vp, i, ctypes.POINTER(i), ctypes.POINTER(i), _dp]
-    lib.abg_batch_solve.argtypes = [ctypes.POINTER(Request), i, Precision, i, i, vp]
+    lib.abg_engine_set_tiles.argtypes = [vp, i, i, i]
+    lib.abg_engine_get_tiles.argtypes = [vp, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i)]
+    lib.abg_engine_autotune.argtypes = [vp, i, ctypes.POINTER(i), ctypes.POINTER(i),
+                                        ctypes.POINTER(i), _dp]
+    lib.abg_batch_solve.argtypes = [ctypes.POINTER(Request), i, Precision, i, i, i, vp]
     lib.abg_mgs_force_stream.argtypes = [i]
     _lib = lib
     return lib
@@ -399,15 +400,18 @@ class Engine:
         except Exception:
             pass
 
-    def set_tiles(self, rays: int, ang_block: int | None = None):
-        ab = ang_block if ang_block is not None else self.get_tiles()[1]
-        _check(self.lib.abg_engine_set_tiles(self._h, int(rays), int(ab)), "abg_engine_set_tiles")
+    def set_tiles(self, rays: int, ang_block: int | None = None, sched: int | None = None):
+        cur = self.get_tiles()
+        ab = ang_block if ang_block is not None else cur[1]
+        sc = sched if sched is not None else cur[2]
+        _check(self.lib.abg_engine_set_tiles(self._h, int(rays), int(ab), int(sc)),
+               "abg_engine_set_tiles")
 
     def get_tiles(self) -> tuple:
-        r, a = ctypes.c_int(), ctypes.c_int()
-        _check(self.lib.abg_engine_get_tiles(self._h, ctypes.byref(r), ctypes.byref(a)),
-               "abg_engine_get_tiles")
-        return r.value, a.value
+        r, a, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(self.lib.abg_engine_get_tiles(self._h, ctypes.byref(r), ctypes.byref(a),
+                                             ctypes.byref(c)), "abg_engine_get_tiles")
+        return r.value, a.value, c.value
 
     def signature(self) -> str:
         """Key of the current mix for the tile cache: precision and the sorted shapes."""
@@ -428,15 +432,18 @@ class Engine:
             with open(cache) as fh:
                 table = json.load(fh)
         if key in table:
-            rays, ab = table[key]["rays"], table[key]["ang_block"]
-            self.set_tiles(rays, ab)
-            return {"rays": rays, "ang_block": ab, "ms": table[key]["ms"], "cached": True}
-        r, a, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+            e = table[key]
+            self.set_tiles(e["rays"], e["ang_block"], e["sched"])
+            return {"rays": e["rays"], "ang_block": e["ang_block"], "sched": e["sched"],
+                    "ms": e["ms"], "cached": True}
+        r, a, c, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
         _check(self.lib.abg_engine_autotune(self._h, int(reps), ctypes.byref(r), ctypes.byref(a),
-                                            ctypes.byref(ms)), "abg_engine_autotune")
-        out = {"rays": r.value, "ang_block": a.value, "ms": ms.value, "cached": False}
+                                            ctypes.byref(c), ctypes.byref(ms)),
+               "abg_engine_autotune")
+        out = {"rays": r.value, "ang_block": a.value, "sched": c.value, "ms": ms.value,
+               "cached": False}
         if cache and ms.value > 0:
-            table[key] = {k: out[k] for k in ("rays", "ang_block", "ms")}
+            table[key] = {k: out[k] for k in ("rays", "ang_block", "sched", "ms")}
             d = os.path.dirname(os.path.abspath(cache))
             os.makedirs(d, exist_ok=True)
             with open(cache, "w") as fh:
@@ -512,7 +519,7 @@ class Engine:
 
 
 def batch_solve(problems, proj="f32", basis="f32", rays: int = 0, ang_block: int = 0,
-                stream=None) -> list:
+                sched: int = -1, stream=None) -> list:
     """abg_batch_solve: all problems on a new engine; returns SolveResults in input order."""
     torch = _torch()
     lib = load_library()
@@ -535,6 +542,6 @@ def batch_solve(problems, proj="f32", basis="f32", rays: int = 0, ang_block: int
                           ctypes.c_void_p(prob.x0.data_ptr()) if prob.x0 is not None else None,
                           ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
                           ctypes.pointer(pend.info), i)
-    _check(lib.abg_batch_solve(reqs, len(problems), prec, int(rays), int(ang_block),
+    _check(lib.abg_batch_solve(reqs, len(problems), prec, int(rays), int(ang_block), int(sched),
                                _stream_ptr(stream)), "abg_batch_solve")
     return [p.result(p.info.status) for p in keep]

@@ -227,9 +227,9 @@ int engine_submit(Engine *e, const Geometry &g, const abg_request &r);
 int engine_step(Engine *e, int *n_running);
 int engine_poll(Engine *e, long long *tags, int *status, int max, int *n);
 int engine_pending(const Engine *e);
-int engine_set_tiles(Engine *e, int rays, int ang_block);
-int engine_get_tiles(const Engine *e, int *rays, int *ang_block);
-int engine_autotune(Engine *e, int reps, int *rays, int *ang_block, double *ms);
+int engine_set_tiles(Engine *e, int rays, int ang_block, int sched);
+int engine_get_tiles(const Engine *e, int *rays, int *ang_block, int *sched);
+int engine_autotune(Engine *e, int reps, int *rays, int *ang_block, int *sched, double *ms);
 int engine_device(const Engine *e);
 hipStream_t engine_stream(const Engine *e);
 int engine_precision(const Engine *e, abg_precision *p);

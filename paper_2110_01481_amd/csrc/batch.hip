@@ -33,6 +33,10 @@
 
 namespace abg {
 
+// Work lists are split into kRanges contiguous ranges with a counter each (see
+// for_each_item).
+constexpr int kRanges = 8;
+
 enum Tab {
     kTPadBA = 0,   // pad w_k (BA)
     kTBackAB,      // t = B w_k (AB)
@@ -42,7 +46,8 @@ enum Tab {
     kTFwdAB,       // q = A t (AB)
     kTMgsS,        // MGS groups with the small register tile
     kTMgsL,        // MGS groups with the large register tile
-    kTMgsX,        // streaming MGS groups (vectors longer than kRegMaxL)
+    kTMgsH,        // MGS groups with the largest register tile (FP32/BF16 basis)
+    kTMgsX,        // streaming MGS groups (vectors the register tiles cannot hold)
     kTRes,         // residual chunks
     kTGiv,         // one Givens block per problem
     kNumTab
@@ -50,8 +55,9 @@ enum Tab {
 
 constexpr int kMgsSmallE = 8;
 constexpr int kMgsLargeE = 32;
+constexpr int kMgsHugeE = 64;
 constexpr int kMgsSmallMaxG = 128;
-constexpr int kMgsStreamG = 128;
+constexpr int kMgsStreamG = 512;
 constexpr int kResU = 4;
 
 // Per-problem descriptor in device memory.
@@ -67,7 +73,7 @@ struct BatchInst {
     double bd_rel;
     int mgs_rows;
     int need_res;
-    int mgs_G, mgs_class;   // class 0: small register tile, 1: large, 2: streaming
+    int mgs_G, mgs_class;   // register tile class 0 small, 1 large, 3 huge; 2 streaming
     int chunk, n_chunks;
 };
 
@@ -75,7 +81,7 @@ struct BatchInst {
 // consecutive tickets.
 struct TabView {
     int *nseg, *total;
-    unsigned *ticket;
+    unsigned *ticket;    // [kNumTab][kRanges]
     int *slot, *first;   // [kNumTab][max_slots]
     int max_slots;
     __device__ int seg_slot(int t, int i) const { return slot[t * max_slots + i]; }
@@ -86,6 +92,7 @@ struct Tiles {
     int rays;        // forward projector: rays of one angle per block (64, 128 or 256);
                      // a block of 256 threads takes 256/rays angles
     int ang_block;   // back projectors: angles staged in LDS per round (64 or 128)
+    int sched;       // item schedule of the projector and residual lists (for_each_item)
 };
 
 namespace {
@@ -109,6 +116,7 @@ __device__ int items_of(int t, const BatchInst &d, const Tiles &tl)
     case kTMgsS: return d.mgs_class == 0 ? d.mgs_G : 0;
     case kTMgsL: return d.mgs_class == 1 ? d.mgs_G : 0;
     case kTMgsX: return d.mgs_class == 2 ? d.mgs_G : 0;
+    case kTMgsH: return d.mgs_class == 3 ? d.mgs_G : 0;
     case kTRes: return d.need_res ? d.n_chunks : 0;
     case kTGiv: return 1;
     }
@@ -177,8 +185,8 @@ __global__ __launch_bounds__(256) void begin_kernel(const BatchInst *__restrict_
     if (tid == 0) {
         tv.nseg[t] = tot_n;
         tv.total[t] = tot_c;
-        tv.ticket[t] = 0u;
     }
+    if (tid < kRanges) tv.ticket[t * kRanges + tid] = 0u;
 }
 
 // Problem and item of ticket `it` of list t (binary search over the segments). Every
@@ -195,16 +203,70 @@ __device__ inline void locate(const TabView &tv, int t, int it, int *slot, int *
     *local = __builtin_amdgcn_readfirstlane(it - tv.seg_first(t, lo));
 }
 
+// Runs body(slot, local) for the items of list t that this block takes, under one of two
+// schedules (a tunable):
+//  sched 0  static round-robin: block b takes items b, b + grid, b + 2 grid, ...
+//  sched 1  the list is cut into kRanges contiguous ranges with a counter each; block b
+//           starts on range b % kRanges (blocks are dispatched round-robin over the XCDs,
+//           so each XCD works mostly on its own contiguous part of the list and keeps it
+//           in its L2), takes chunks of items from it as it frees up, then helps with the
+//           other ranges: items of unequal cost are balanced dynamically.
+// A block's items come in increasing order, so the segment (problem) of an item is found
+// by moving a cursor forward. body must be called by the whole block (it may
+// synchronise).
+template <typename F>
+__device__ inline void for_each_item(const TabView &tv, int t, int sched, F &&body)
+{
+    __shared__ int s_c;
+    const int total = tv.total[t];
+    if ((int)blockIdx.x >= total) return;
+    const int nseg = tv.nseg[t];
+    int seg = 0;
+    auto visit = [&](int it) {
+        while (seg + 1 < nseg && tv.seg_first(t, seg + 1) <= it) ++seg;
+        body(__builtin_amdgcn_readfirstlane(tv.seg_slot(t, seg)),
+             __builtin_amdgcn_readfirstlane(it - tv.seg_first(t, seg)));
+    };
+    if (sched == 0) {
+        for (int it = blockIdx.x; it < total; it += gridDim.x) visit(it);
+        return;
+    }
+    const int G = min((int)gridDim.x, total);
+    const int C = max(1, total / (G * kRanges));
+    const int home = (int)(blockIdx.x % kRanges);
+    unsigned *tk = tv.ticket + t * kRanges;
+    for (int p = 0; p < kRanges; ++p) {
+        const int r = (home + p) % kRanges;
+        const int lo = (int)((long long)total * r / kRanges);
+        const int n = (int)((long long)total * (r + 1) / kRanges) - lo;
+        if (r < home) seg = 0;   // wrapped round to an earlier range
+        for (;;) {
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                int c = n;
+                if ((int)__hip_atomic_load(tk + r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < n)
+                    c = (int)__hip_atomic_fetch_add(tk + r, (unsigned)C, __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
+                s_c = c;
+            }
+            __syncthreads();
+            const int c = __builtin_amdgcn_readfirstlane(s_c);
+            if (c >= n) break;
+            const int e = min(n, c + C);
+            for (int it = lo + c; it < lo + e; ++it) visit(it);
+        }
+    }
+}
+
 // Takes the next ticket of list t for the block: returns false when the list is used up.
-// Used where items must be taken in order by running blocks (the MGS block groups); the
-// other lists are dealt out statically (ticket = block + j * grid), which needs no atomic.
+// Used where items must be taken in order by running blocks (the MGS block groups).
 __device__ inline bool next_item(const TabView &tv, int t, int *slot_out, int *local_out)
 {
     __shared__ int s_slot, s_local;
     __syncthreads();
     if (threadIdx.x == 0) {
-        const unsigned it = __hip_atomic_fetch_add(tv.ticket + t, 1u, __ATOMIC_RELAXED,
-                                                   __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned it = __hip_atomic_fetch_add(tv.ticket + t * kRanges, 1u,
+                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         int slot = -1, local = 0;
         if ((int)it < tv.total[t]) {
             int lo = 0, hi = tv.nseg[t] - 1;
@@ -235,22 +297,19 @@ template <typename T> __device__ inline T *zcol(const BatchInst &d, int k)
 // mode 0: BA, w_k;  mode 1: AB, t
 template <typename T>
 __global__ __launch_bounds__(256) void bpad_kernel(const BatchInst *__restrict__ D, const DevState *S,
-                                                   TabView tv, int t, int mode)
+                                                   TabView tv, int t, int mode, Tiles tl)
 {
     __shared__ PadLds<T> lds;
-    const int total = tv.total[t];
-    for (int it = blockIdx.x; it < total; it += gridDim.x) {
-        int slot, local;
-        locate(tv, t, it, &slot, &local);
+    for_each_item(tv, t, tl.sched, [&](int slot, int local) {
         const BatchInst &d = D[slot];
         const DevState *st = S + slot;
-        if (halted(st, st->kcur)) continue;
-        __syncthreads();   // the previous tile's LDS reads are done
+        if (halted(st, st->kcur)) return;
         const int tpr = (d.N + 31) / 32;
         const T *src = mode == 0 ? gfield<const T>(d.cur) : gfield<const T>(d.tn);
+        __syncthreads();   // the previous tile's LDS reads are done
         pad_transpose_tile(src, gfield<T>(d.xr), gfield<T>(d.xc), d.N, d.S,
                            (local % tpr) * 32, (local / tpr) * 32, lds);
-    }
+    });
 }
 
 // mode 0: BA, z = A w_k (column k of Z);  mode 1: AB, q = A t
@@ -262,39 +321,33 @@ __global__ __launch_bounds__(256) void bfwd_kernel(const BatchInst *__restrict__
     const int lane = threadIdx.x & 63;
     const int wpa = tl.rays / 64;       // waves per angle
     const int apb = 256 / tl.rays;      // angles per block
-    const int total = tv.total[t];
-    for (int it = blockIdx.x; it < total; it += gridDim.x) {
-        int slot, local;
-        locate(tv, t, it, &slot, &local);
+    for_each_item(tv, t, tl.sched, [&](int slot, int local) {
         const BatchInst &d = D[slot];
         const DevState *st = S + slot;
         const int k = st->kcur;
-        if (halted(st, k)) continue;
+        if (halted(st, k)) return;
         const int nrg = (d.n_det + tl.rays - 1) / tl.rays;
         const int a = (local / nrg) * apb + wave / wpa;
         const int i = (local % nrg) * tl.rays + (wave % wpa) * 64 + lane;
-        if (a >= d.n_ang) continue;
+        if (a >= d.n_ang) return;   // whole waves
         T *y = mode == 0 ? zcol<T>(d, k) : gfield<T>(d.q);
         forward_ray(gfield<const T>(d.xr), gfield<const T>(d.xc), y,
                     gfield<const AngleParams>(d.ang), a, i, d.N, d.S, d.n_det, d.ds, d.s0);
-    }
+    });
 }
 
 // mode 0: AB, t = B w_k;  mode 1: BA, q = B z
 template <typename T, int AB>
 __global__ __launch_bounds__(kBackThreads) void bback_kernel(const BatchInst *__restrict__ D,
                                                              const DevState *S, TabView tv,
-                                                             int t, int mode)
+                                                             int t, int mode, Tiles tl)
 {
     __shared__ BackLds<T, AB> lds;
-    const int total = tv.total[t];
-    for (int it = blockIdx.x; it < total; it += gridDim.x) {
-        int slot, local;
-        locate(tv, t, it, &slot, &local);
+    for_each_item(tv, t, tl.sched, [&](int slot, int local) {
         const BatchInst &d = D[slot];
         const DevState *st = S + slot;
         const int k = st->kcur;
-        if (halted(st, k)) continue;
+        if (halted(st, k)) return;
         const int tpr = (d.N + kTile - 1) / kTile;
         const int c0 = (local % tpr) * kTile, r0 = (local / tpr) * kTile;
         const T *y = mode == 0 ? gfield<const T>(d.cur) : zcol<T>(d, k);
@@ -304,7 +357,7 @@ __global__ __launch_bounds__(kBackThreads) void bback_kernel(const BatchInst *__
             back_tile<T, true, AB>(y, x, ang, d.N, d.n_ang, d.n_det, d.ds, d.s0, c0, r0, lds);
         else
             back_tile<T, false, AB>(y, x, ang, d.N, d.n_ang, d.n_det, d.ds, d.s0, c0, r0, lds);
-    }
+    });
 }
 
 // ---- Gram-Schmidt, Givens, residual -------------------------------------------------------
@@ -316,6 +369,9 @@ __global__ __launch_bounds__(kBlock) void bmgs_kernel(const BatchInst *__restric
                                                       TabView tv, int t)
 {
     __shared__ double lds[kWaves];
+    // at most `total` blocks can hold a ticket: the others leave without touching the
+    // counter (a large, mostly idle grid would otherwise queue on it)
+    if ((int)blockIdx.x >= tv.total[t]) return;
     int slot, rank;
     while (next_item(tv, t, &slot, &rank)) {
         const BatchInst &d = D[slot];
@@ -361,19 +417,17 @@ __global__ __launch_bounds__(64) void bgivens_kernel(const BatchInst *__restrict
 // squares is published; the last chunk to finish adds them in chunk order, writes the
 // norm and raises the DP candidate stop.
 template <typename TX, typename TV>
-__global__ __launch_bounds__(kBlock) void bres_kernel(const BatchInst *__restrict__ D, DevState *S, TabView tv)
+__global__ __launch_bounds__(kBlock) void bres_kernel(const BatchInst *__restrict__ D, DevState *S, TabView tv,
+                                                      Tiles tl)
 {
     __shared__ double cf[kMaxCoef];
     __shared__ double lds[kWaves];
     __shared__ int last;
-    const int total = tv.total[kTRes];
-    for (int it = blockIdx.x; it < total; it += gridDim.x) {
-        int slot, c;
-        locate(tv, kTRes, it, &slot, &c);
+    for_each_item(tv, kTRes, tl.sched, [&](int slot, int c) {
         const BatchInst &d = D[slot];
         DevState *st = S + slot;
         const int k = st->kcur;
-        if (halted(st, k)) continue;
+        if (halted(st, k)) return;
         const bool ba = d.method == ABG_METHOD_BA;
         __syncthreads();   // the previous item's use of cf and `last` is done
         const int kk = ba ? k : k + 1;
@@ -420,7 +474,7 @@ __global__ __launch_bounds__(kBlock) void bres_kernel(const BatchInst *__restric
             last = prev == (unsigned)d.n_chunks - 1;
         }
         __syncthreads();
-        if (!last) continue;
+        if (!last) return;
         double tsum = 0.0;
         for (int j = threadIdx.x; j < d.n_chunks; j += kBlock) tsum += agent_load(d.part + j);
         tsum = block_sum(tsum, lds);
@@ -436,7 +490,7 @@ __global__ __launch_bounds__(kBlock) void bres_kernel(const BatchInst *__restric
                 st->stop_reason = kStopDP;
             }
         }
-    }
+    });
 }
 
 // ---- per-problem control kernels (launched by the host between rounds) ------------------
@@ -538,10 +592,10 @@ struct Engine {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     bool dirty = true;
-    Tiles tiles{256, 128};
+    Tiles tiles{256, 128, 0};
     int grid_proj = 0, grid_back = 0, grid_back64 = 0, grid_mgs_s = 0, grid_mgs_l = 0, grid_res = 0;
     hipEvent_t tev[2] = {};
-    int cap_mgs_s = 0, cap_mgs_l = 0, cap_mgs_x = 0, grid_mgs_x = 0;
+    int cap_mgs_s = 0, cap_mgs_l = 0, cap_mgs_x = 0, grid_mgs_x = 0, cap_mgs_h = 0, grid_mgs_h = 0;
     int broken = 0;
     std::vector<Slot> slots;
     std::vector<std::pair<long long, int>> finished;
@@ -581,6 +635,13 @@ struct Engine {
         if ((e = capacity_of(bmgs_kernel<TX, TV, kMgsSmallE>, kBlock, &cap_mgs_s)) != hipSuccess) return e;
         if ((e = capacity_of(bmgs_kernel<TX, TV, kMgsLargeE>, kBlock, &cap_mgs_l)) != hipSuccess) return e;
         if ((e = capacity_of(bmgs_kernel<TX, TV, 0>, kBlock, &cap_mgs_x)) != hipSuccess) return e;
+        if constexpr (sizeof(TV) < 8) {
+            if ((e = capacity_of(bmgs_kernel<TX, TV, kMgsHugeE>, kBlock, &cap_mgs_h)) != hipSuccess)
+                return e;
+        } else {
+            cap_mgs_h = 0;
+        }
+        grid_mgs_h = std::max(1, cap_mgs_h);
         grid_mgs_x = cap_mgs_x;
         if ((e = capacity_of(bres_kernel<TX, TV>, kBlock, &grid_res)) != hipSuccess) return e;
         grid_mgs_s = cap_mgs_s;
@@ -599,9 +660,9 @@ struct Engine {
     template <typename TX> void enqueue_back(hipStream_t q, const Tiles &tl, int t, int mode)
     {
         if (tl.ang_block == 64)
-            bback_kernel<TX, 64><<<grid_back64, kBackThreads, 0, q>>>(d_desc, d_st, tv, t, mode);
+            bback_kernel<TX, 64><<<grid_back64, kBackThreads, 0, q>>>(d_desc, d_st, tv, t, mode, tl);
         else
-            bback_kernel<TX, 128><<<grid_back, kBackThreads, 0, q>>>(d_desc, d_st, tv, t, mode);
+            bback_kernel<TX, 128><<<grid_back, kBackThreads, 0, q>>>(d_desc, d_st, tv, t, mode, tl);
     }
 
     // begin + the three projector phases (idempotent between rounds: they recompute the
@@ -609,10 +670,10 @@ struct Engine {
     template <typename TX> void enqueue_projectors_t(hipStream_t q, const Tiles &tl)
     {
         begin_kernel<<<kNumTab, 256, 0, q>>>(d_desc, d_st, tv, max_slots, tl);
-        bpad_kernel<TX><<<grid_proj, 256, 0, q>>>(d_desc, d_st, tv, kTPadBA, 0);
+        bpad_kernel<TX><<<grid_proj, 256, 0, q>>>(d_desc, d_st, tv, kTPadBA, 0, tl);
         enqueue_back<TX>(q, tl, kTBackAB, 0);
         bfwd_kernel<TX><<<grid_proj, 256, 0, q>>>(d_desc, d_st, tv, kTFwdBA, 0, tl);
-        bpad_kernel<TX><<<grid_proj, 256, 0, q>>>(d_desc, d_st, tv, kTPadAB, 1);
+        bpad_kernel<TX><<<grid_proj, 256, 0, q>>>(d_desc, d_st, tv, kTPadAB, 1, tl);
         enqueue_back<TX>(q, tl, kTBackBA, 1);
         bfwd_kernel<TX><<<grid_proj, 256, 0, q>>>(d_desc, d_st, tv, kTFwdAB, 1, tl);
     }
@@ -628,9 +689,11 @@ struct Engine {
         enqueue_projectors_t<TX>(q, tiles);
         bmgs_kernel<TX, TV, kMgsSmallE><<<grid_mgs_s, kBlock, 0, q>>>(d_desc, d_st, tv, kTMgsS);
         bmgs_kernel<TX, TV, kMgsLargeE><<<grid_mgs_l, kBlock, 0, q>>>(d_desc, d_st, tv, kTMgsL);
+        if constexpr (sizeof(TV) < 8)
+            bmgs_kernel<TX, TV, kMgsHugeE><<<grid_mgs_h, kBlock, 0, q>>>(d_desc, d_st, tv, kTMgsH);
         bmgs_kernel<TX, TV, 0><<<grid_mgs_x, kBlock, 0, q>>>(d_desc, d_st, tv, kTMgsX);
         bgivens_kernel<<<max_slots, 64, 0, q>>>(d_desc, d_st, tv);
-        bres_kernel<TX, TV><<<grid_res, kBlock, 0, q>>>(d_desc, d_st, tv);
+        bres_kernel<TX, TV><<<grid_res, kBlock, 0, q>>>(d_desc, d_st, tv, tiles);
     }
 
     void enqueue_round(hipStream_t q)
@@ -720,22 +783,33 @@ struct Engine {
         d.count = v.count;
         d.bd_rel = (p.basis == ABG_F64 && p.proj == ABG_F64) ? 1e-14 : 1e-6;
         d.need_res = r.stop.kind == ABG_STOP_DP;
-        // Gram-Schmidt class: small register tile while its group stays small, else the
-        // large tile, else (vectors longer than kRegMaxL) the streaming variant
-        long long G = (v.L + (long long)kBlock * kMgsSmallE - 1) / ((long long)kBlock * kMgsSmallE);
+        // Gram-Schmidt class: the smallest register tile whose block group the device
+        // holds at once (the small tile while its group stays small), else the streaming
+        // variant. A group must be resident as a whole: its size stays within the
+        // kernel's resident-block capacity.
+        auto groups = [&](int E) {
+            return (v.L + (long long)kBlock * E - 1) / ((long long)kBlock * E);
+        };
+        long long G = groups(kMgsSmallE);
         d.mgs_class = 0;
         int capG = cap_mgs_s;
-        if (v.L > kRegMaxL) {
-            d.mgs_class = 2;
-            G = kMgsStreamG;
-            capG = cap_mgs_x;
-            if (!v.q64) return ABG_EINVAL;
-        } else if (G > kMgsSmallMaxG) {
+        if (G > kMgsSmallMaxG) {
+            G = groups(kMgsLargeE);
             d.mgs_class = 1;
-            G = (v.L + (long long)kBlock * kMgsLargeE - 1) / ((long long)kBlock * kMgsLargeE);
             capG = cap_mgs_l;
+            if (G > cap_mgs_l && cap_mgs_h > 0 && groups(kMgsHugeE) <= cap_mgs_h) {
+                G = groups(kMgsHugeE);
+                d.mgs_class = 3;
+                capG = cap_mgs_h;
+            }
+            if (G > capG) {
+                if (!v.q64) return ABG_EINVAL;
+                d.mgs_class = 2;
+                G = kMgsStreamG;
+                capG = cap_mgs_x;
+            }
         }
-        if (G > capG / 2 || 2LL * v.mgs_rows * G > v.mgs_part_cap) return ABG_EINVAL;
+        if (G > capG || 2LL * v.mgs_rows * G > v.mgs_part_cap) return ABG_EINVAL;
         d.mgs_G = (int)std::max(1LL, G);
         long long chunk = 8192;
         while ((d.m + chunk - 1) / chunk > v.part_cap) chunk *= 2;
@@ -801,8 +875,9 @@ struct Engine {
         Tiles best = tiles;
         double bms = INFINITY;
         for (int rays : {64, 128, 256})
-            for (int ab : {64, 128}) {
-                const Tiles tl{rays, ab};
+            for (int ab : {64, 128})
+            for (int sc : {0, 1}) {
+                const Tiles tl{rays, ab, sc};
                 double ms = 0.0;
                 int rc = time_projectors(tl, reps, &ms);
                 if (rc) return rc;
@@ -811,7 +886,8 @@ struct Engine {
                     best = tl;
                 }
             }
-        if (best.rays != tiles.rays || best.ang_block != tiles.ang_block) {
+        if (best.rays != tiles.rays || best.ang_block != tiles.ang_block ||
+            best.sched != tiles.sched) {
             tiles = best;
             dirty = true;
         }
@@ -986,7 +1062,7 @@ int engine_create(abg_precision p, int max_slots, hipStream_t s, Engine **out)
     };
     if (hipGetDevice(&e->device) != hipSuccess) return bad();
     if (hipStreamCreateWithFlags(&e->cap_stream, hipStreamNonBlocking) != hipSuccess) return bad();
-    const size_t tab_ints = 3 * kNumTab + 2 * (size_t)kNumTab * max_slots;
+    const size_t tab_ints = (2 + kRanges) * kNumTab + 2 * (size_t)kNumTab * max_slots;
     if (hipMalloc(&e->d_desc, sizeof(BatchInst) * max_slots) != hipSuccess) return bad();
     if (hipMalloc(&e->d_st, sizeof(DevState) * max_slots) != hipSuccess) return bad();
     if (hipMalloc(&e->d_tab, sizeof(int) * tab_ints) != hipSuccess) return bad();
@@ -998,7 +1074,7 @@ int engine_create(abg_precision p, int max_slots, hipStream_t s, Engine **out)
     e->tv.nseg = e->d_tab;
     e->tv.total = e->d_tab + kNumTab;
     e->tv.ticket = reinterpret_cast<unsigned *>(e->d_tab + 2 * kNumTab);
-    e->tv.slot = e->d_tab + 3 * kNumTab;
+    e->tv.slot = e->d_tab + (2 + kRanges) * kNumTab;
     e->tv.first = e->tv.slot + (size_t)kNumTab * max_slots;
     e->tv.max_slots = max_slots;
     // every slot starts idle: zero scalars and descriptors
@@ -1036,30 +1112,33 @@ int engine_poll(Engine *e, long long *tags, int *status, int max, int *n)
 
 int engine_pending(const Engine *e) { return e->n_used() + (int)e->finished.size(); }
 
-int engine_set_tiles(Engine *e, int rays, int ang_block)
+int engine_set_tiles(Engine *e, int rays, int ang_block, int sched)
 {
     if (rays != 64 && rays != 128 && rays != 256) return ABG_EINVAL;
     if (ang_block != 64 && ang_block != 128) return ABG_EINVAL;
-    if (e->tiles.rays != rays || e->tiles.ang_block != ang_block) {
-        e->tiles = Tiles{rays, ang_block};
+    if (sched != 0 && sched != 1) return ABG_EINVAL;
+    if (e->tiles.rays != rays || e->tiles.ang_block != ang_block || e->tiles.sched != sched) {
+        e->tiles = Tiles{rays, ang_block, sched};
         e->dirty = true;
     }
     return ABG_OK;
 }
 
-int engine_get_tiles(const Engine *e, int *rays, int *ang_block)
+int engine_get_tiles(const Engine *e, int *rays, int *ang_block, int *sched)
 {
     *rays = e->tiles.rays;
     *ang_block = e->tiles.ang_block;
+    *sched = e->tiles.sched;
     return ABG_OK;
 }
 
-int engine_autotune(Engine *e, int reps, int *rays, int *ang_block, double *ms)
+int engine_autotune(Engine *e, int reps, int *rays, int *ang_block, int *sched, double *ms)
 {
     Tiles t{};
     const int rc = e->autotune(reps, &t, ms);
     *rays = t.rays;
     *ang_block = t.ang_block;
+    *sched = t.sched;
     return rc;
 }
 

@@ -382,39 +382,42 @@ int abg_engine_poll(abg_engine *h, long long *tags, int *status, int max, int *n
     return engine_poll(h->e, tags, status, max, n);
 }
 
-int abg_engine_set_tiles(abg_engine *h, int rays, int ang_block)
+int abg_engine_set_tiles(abg_engine *h, int rays, int ang_block, int sched)
 {
     if (!h) return ABG_EINVAL;
-    return engine_set_tiles(h->e, rays, ang_block);
+    return engine_set_tiles(h->e, rays, ang_block, sched);
 }
 
-int abg_engine_get_tiles(const abg_engine *h, int *rays, int *ang_block)
+int abg_engine_get_tiles(const abg_engine *h, int *rays, int *ang_block, int *sched)
 {
-    if (!h || !rays || !ang_block) return ABG_EINVAL;
-    return engine_get_tiles(h->e, rays, ang_block);
+    if (!h || !rays || !ang_block || !sched) return ABG_EINVAL;
+    return engine_get_tiles(h->e, rays, ang_block, sched);
 }
 
-int abg_engine_autotune(abg_engine *h, int reps, int *rays, int *ang_block, double *ms)
+int abg_engine_autotune(abg_engine *h, int reps, int *rays, int *ang_block, int *sched,
+                        double *ms)
 {
-    if (!h || !rays || !ang_block || !ms || reps < 1 || reps > 1000) return ABG_EINVAL;
+    if (!h || !rays || !ang_block || !sched || !ms || reps < 1 || reps > 1000) return ABG_EINVAL;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return ABG_EHIP;
     if (dev != engine_device(h->e)) return ABG_EINVAL;
-    return engine_autotune(h->e, reps, rays, ang_block, ms);
+    return engine_autotune(h->e, reps, rays, ang_block, sched, ms);
 }
 
 int abg_batch_solve(const abg_request *r, int n, abg_precision p, int rays, int ang_block,
-                    void *stream)
+                    int sched, void *stream)
 {
     if (n < 0 || (n > 0 && !r)) return ABG_EINVAL;
     if (n == 0) return ABG_OK;
     abg_engine *h = nullptr;
     int rc = abg_engine_create(p, n, stream, &h);
     if (rc) return rc;
-    int cur_rays = 0, cur_ab = 0;
-    abg_engine_get_tiles(h, &cur_rays, &cur_ab);
-    if ((rays > 0 || ang_block > 0) &&
-        (rc = abg_engine_set_tiles(h, rays > 0 ? rays : cur_rays, ang_block > 0 ? ang_block : cur_ab))) {
+    int cur_rays = 0, cur_ab = 0, cur_sched = 0;
+    abg_engine_get_tiles(h, &cur_rays, &cur_ab, &cur_sched);
+    if ((rays > 0 || ang_block > 0 || sched >= 0) &&
+        (rc = abg_engine_set_tiles(h, rays > 0 ? rays : cur_rays,
+                                   ang_block > 0 ? ang_block : cur_ab,
+                                   sched >= 0 ? sched : cur_sched))) {
         abg_engine_destroy(h);
         return rc;
     }

@@ -95,7 +95,7 @@ int g_target_blocks = default_target_blocks();
 int g_force_stream = 0;
 
 // Streaming variant: a group of at most kStreamBlocks resident blocks.
-constexpr int kStreamBlocks = 256;
+constexpr int kStreamBlocks = 512;
 
 template <typename TX, typename TV>
 hipError_t mgs_stream_go(const MgsDev &d, hipStream_t s)

@@ -260,14 +260,26 @@ __device__ inline void mgs_stream_body(const MgsDev &a, int rank, int G, double 
             __hip_atomic_store(next + (size_t)r * G + rank, empty, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
     }
-    // pass 0: q64 = q, <q, w_1> and ||q||^2 (or only ||q||^2 when k = 0)
+    // pass 0: q64 = q, <q, w_1> and ||q||^2 (or only ||q||^2 when k = 0); every pass
+    // keeps kSU elements per thread in flight
+    constexpr int kSU = 4;
     double d = 0.0, s2 = 0.0;
     const TV *w0 = V;
-    for (size_t l = (size_t)rank * kBlock + threadIdx.x; l < L; l += T) {
-        const double v = to_f64(q[l]);
-        q64[l] = v;
-        s2 = fma(v, v, s2);
-        if (a.k > 0) d = fma(v, to_f64(w0[l]), d);
+    for (size_t l0 = (size_t)rank * kBlock + threadIdx.x; l0 < L; l0 += kSU * T) {
+        double v[kSU], w[kSU];
+#pragma unroll
+        for (int u = 0; u < kSU; ++u) {
+            const size_t l = l0 + u * T;
+            v[u] = l < L ? to_f64(q[l]) : 0.0;
+            w[u] = (l < L && a.k > 0) ? to_f64(w0[l]) : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kSU; ++u) {
+            const size_t l = l0 + u * T;
+            if (l < L) q64[l] = v[u];
+            s2 = fma(v[u], v[u], s2);
+            d = fma(v[u], w[u], d);
+        }
     }
     double qq;
     double hprev = 0.0;
@@ -293,10 +305,21 @@ __device__ inline void mgs_stream_body(const MgsDev &a, int rank, int G, double 
         const TV *wi = V + (size_t)i * a.ldv;
         const bool last = i == a.k;
         double acc = 0.0;
-        for (size_t l = (size_t)rank * kBlock + threadIdx.x; l < L; l += T) {
-            const double v = fma(-hprev, to_f64(wp[l]), q64[l]);
-            q64[l] = v;
-            acc = last ? fma(v, v, acc) : fma(v, to_f64(wi[l]), acc);
+        for (size_t l0 = (size_t)rank * kBlock + threadIdx.x; l0 < L; l0 += kSU * T) {
+            double v[kSU], w[kSU];
+#pragma unroll
+            for (int u = 0; u < kSU; ++u) {
+                const size_t l = l0 + u * T;
+                const bool in = l < L;
+                v[u] = in ? fma(-hprev, to_f64(wp[l]), q64[l]) : 0.0;
+                w[u] = (in && !last) ? to_f64(wi[l]) : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < kSU; ++u) {
+                const size_t l = l0 + u * T;
+                if (l < L) q64[l] = v[u];
+                acc = last ? fma(v[u], v[u], acc) : fma(v[u], w[u], acc);
+            }
         }
         acc = block_sum(acc, lds);
         if (threadIdx.x == 0) publish(tab + (size_t)i * G + rank, acc);
@@ -321,10 +344,22 @@ __device__ inline void mgs_stream_body(const MgsDev &a, int rank, int G, double 
     }
     TV *vo = static_cast<TV *>(a.vout);
     TX *cu = static_cast<TX *>(a.cur);
-    for (size_t l = (size_t)rank * kBlock + threadIdx.x; l < L; l += T) {
-        const TV w = (bd || !finite) ? zero_of<TV>() : from_f64<TV>(q64[l] / hn);
-        vo[l] = w;
-        cu[l] = (TX)to_f64(w);
+    for (size_t l0 = (size_t)rank * kBlock + threadIdx.x; l0 < L; l0 += kSU * T) {
+        double v[kSU];
+#pragma unroll
+        for (int u = 0; u < kSU; ++u) {
+            const size_t l = l0 + u * T;
+            v[u] = l < L ? q64[l] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kSU; ++u) {
+            const size_t l = l0 + u * T;
+            if (l < L) {
+                const TV w = (bd || !finite) ? zero_of<TV>() : from_f64<TV>(v[u] / hn);
+                vo[l] = w;
+                cu[l] = (TX)to_f64(w);
+            }
+        }
     }
 }
 

@@ -19,7 +19,7 @@ template <typename T> __device__ inline T edge_tie();
 template <> __device__ inline double edge_tie<double>() { return 1e-9; }
 template <> __device__ inline float edge_tie<float>() { return 2e-5f; }
 // back projector: a 16 x 16 pixel tile per block, 4 pixels per lane, the 4 waves
-// splitting the angles; the tile's detector footprint for 128 angles is staged per
+// splitting the angles; the tile's detector footprint for a block of angles (64 or 128) is staged per
 // round (at most 30 bins per angle for det_spacing >= 0.75, plus margins)
 constexpr int kTile = 16;
 constexpr int kBackWaves = 4;

@@ -44,7 +44,7 @@ class ServeReport:
     statuses: dict
     latencies: np.ndarray = field(repr=False, default=None)
     results: dict = field(repr=False, default_factory=dict)
-    tiles: tuple = (0, 0)
+    tiles: tuple = (0, 0, 0)
 
     def as_dict(self) -> dict:
         return {"requests": self.n, "duration_s": round(self.duration_s, 3),
@@ -87,6 +87,24 @@ class Server:
 
     def close(self):
         self.engine.close()
+
+    def tune(self, problems: list, reps: int = 2, cache: str | None = None) -> dict:
+        """Picks the engine's tile shapes and schedule on a closed batch of representative
+        problems (the autotuner times them without advancing them), then solves them to
+        completion. Call before run()."""
+        eng = self.engine
+        held = []
+        for p in problems:
+            ws, x = self._alloc(p, self.request_bytes(p))
+            if eng.submit(p, x=x, workspace=ws) is None:
+                break
+            held.append((ws, x))
+        out = eng.autotune(reps=reps, cache=cache)
+        left = len(held)
+        while left > 0:
+            eng.step()
+            left -= len(eng.poll())
+        return out
 
     def request_bytes(self, p: Problem) -> int:
         return request_bytes(p.g, p.method, p.k_max, self.proj, self.basis, p.stop)

@@ -157,13 +157,13 @@ def test_workspace_contents_do_not_matter(gpu_lib, mix, fill):
         assert s1.k_stop == s2.k_stop and torch.equal(s1.x, s2.x), (i, fill)
 
 
-@pytest.mark.parametrize("rays,ang_block", [(64, 128), (128, 64), (256, 64)])
-def test_tile_shape_does_not_change_results(gpu_lib, mix, rays, ang_block):
+@pytest.mark.parametrize("rays,ang_block,sched", [(64, 128, 0), (128, 64, 1), (256, 64, 1)])
+def test_tile_shape_does_not_change_results(gpu_lib, mix, rays, ang_block, sched):
     import torch
     abg = gpu_lib
     base = abg.batch_solve([c.problem(abg, torch.float32) for c in mix], proj="f32", basis="f32")
     other = abg.batch_solve([c.problem(abg, torch.float32) for c in mix], proj="f32", basis="f32",
-                            rays=rays, ang_block=ang_block)
+                            rays=rays, ang_block=ang_block, sched=sched)
     for a, b in zip(base, other):
         assert a.k_stop == b.k_stop and torch.equal(a.x, b.x)
 
@@ -179,7 +179,8 @@ def test_autotuner_picks_a_shape_and_caches_it(gpu_lib, mix, tmp_path):
     tags = [eng.submit(c.problem(abg, torch.float32)) for c in mix]
     t = eng.autotune(reps=2, cache=cache)
     assert t["rays"] in (64, 128, 256) and t["ang_block"] in (64, 128) and t["ms"] > 0
-    assert not t["cached"] and eng.get_tiles() == (t["rays"], t["ang_block"])
+    assert t["sched"] in (0, 1)
+    assert not t["cached"] and eng.get_tiles() == (t["rays"], t["ang_block"], t["sched"])
     done = {}
     while len(done) < len(tags):
         eng.step()
@@ -190,7 +191,7 @@ def test_autotuner_picks_a_shape_and_caches_it(gpu_lib, mix, tmp_path):
     for c in mix:
         eng2.submit(c.problem(abg, torch.float32))
     t2 = eng2.autotune(cache=cache)
-    assert t2["cached"] and (t2["rays"], t2["ang_block"]) == (t["rays"], t["ang_block"])
+    assert t2["cached"] and eng2.get_tiles() == (t["rays"], t["ang_block"], t["sched"])
 
 
 def test_fp32_and_bf16_basis_against_oracle(gpu_lib, mix, oracle_results):

@@ -62,7 +62,7 @@ class _FakeEngine:
         return out
 
     def get_tiles(self):
-        return (256, 128)
+        return (256, 128, 0)
 
     def set_tiles(self, *a):
         pass
