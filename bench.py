@@ -213,6 +213,9 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="seconds of Poisson arrivals for the serving run (0: skip)")
     ap.add_argument("--serve-basis", default="f32,bf16")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="only run device-to-device copies of this many MiB (a plain copy "
+                         "kernel whose HBM counters calibrate FETCH_SIZE / WRITE_SIZE)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus N > 1 is not supported "
@@ -223,6 +226,15 @@ def main():
     import paper_2110_01481_amd as abg
 
     torch.cuda.set_device(0)
+    if args.copy_calibration_mib > 0:
+        nb = args.copy_calibration_mib << 20
+        src = torch.ones(nb // 4, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": nb, "copies": 3}))
+        return
     abg.load_library()
     w = {1: W.CONFIG1, 2: W.CONFIG2, 3: W.CONFIG3}[args.config]
     k_max = w.k_max

@@ -167,10 +167,12 @@ hipError_t launch_sub_norm(int t, const void *a, const void *b, void *out, long 
 // dst = sqrt(sum partials[0..nb)) (fixed order, one block).
 hipError_t launch_reduce_sqrt(const double *partials, int nb, double *dst, hipStream_t s);
 // Givens update of column k of H, y_k into y (k entries), and rho = beta e_1 - H_k y_k
-// when rho is given.
+// when rho is given (beta read on the device).
 hipError_t launch_givens(double *H, int ld, double *R, double *cs, double *sn, double *g,
-                         double *y, double *rho, double beta, int k, DevState *st,
+                         double *y, double *rho, const double *beta, int k, DevState *st,
                          hipStream_t s);
+// st->beta = st->hnext after the initial normalisation, or the zero-right-hand-side stop.
+hipError_t launch_set_beta(DevState *st, hipStream_t s);
 // Clears the stop flag (after a DP candidate that the explicit residual rejected).
 hipError_t launch_clear_stop(DevState *st, hipStream_t s);
 void set_mgs_target_blocks(int blocks);

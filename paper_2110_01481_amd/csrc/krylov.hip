@@ -271,11 +271,25 @@ __global__ void fill_f64_kernel(double *p, size_t n, double v)
 
 __global__ __launch_bounds__(64) void givens_kernel(double *H, int ld, double *R, double *cs,
                                                     double *sn, double *g, double *y,
-                                                    double *rho, double beta, int k,
+                                                    double *rho, const double *beta, int k,
                                                     DevState *st)
 {
     if (halted(st, k)) return;
-    givens_step(H, ld, R, cs, sn, g, y, rho, beta, k, st);
+    givens_step(H, ld, R, cs, sn, g, y, rho, *beta, k, st);
+}
+
+// After the initial normalisation: beta = ||r_0|| for the later steps, or (r_0 = 0) the
+// zero-right-hand-side stop before step 1.
+__global__ void set_beta_kernel(DevState *st)
+{
+    if (threadIdx.x != 0 || st->error) return;
+    if (st->hnext == 0.0) {
+        st->stop = 1;
+        st->stop_k = 0;
+        st->stop_reason = kStopZero;
+    } else {
+        st->beta = st->hnext;
+    }
 }
 
 __global__ void clear_stop_kernel(DevState *st)
@@ -386,8 +400,15 @@ hipError_t launch_reduce_sqrt(const double *partials, int nb, double *dst, hipSt
     return hipGetLastError();
 }
 
+hipError_t launch_set_beta(DevState *st, hipStream_t s)
+{
+    set_beta_kernel<<<1, 64, 0, s>>>(st);
+    return hipGetLastError();
+}
+
 hipError_t launch_givens(double *H, int ld, double *R, double *cs, double *sn, double *g,
-                         double *y, double *rho, double beta, int k, DevState *st, hipStream_t s)
+                         double *y, double *rho, const double *beta, int k, DevState *st,
+                         hipStream_t s)
 {
     if (k + 1 > kMaxCoef) return hipErrorInvalidValue;
     givens_kernel<<<1, 64, 0, s>>>(H, ld, R, cs, sn, g, y, rho, beta, k, st);

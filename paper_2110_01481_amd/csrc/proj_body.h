@@ -81,9 +81,9 @@ __device__ inline void pad_zero_item(T *__restrict__ xr, T *__restrict__ xc, int
 
 // Position of a ray inside the current band of pixels: the band holds the minor-axis
 // interval [lo, lo + |m|] (pixels from the image edge) and the walk advances lo by m.
-// FP64 data: lo in FP64. FP32 data: lo in 24.40 fixed point biased by kPad, so a band
-// step is one 64-bit add, the pixel index is the integer part and the top 32 fraction
-// bits give the weight (position error ~1e-9 px after 32768 steps).
+// FP64 data: lo in FP64. FP32 data: lo biased by kPad as an integer column and a 32-bit
+// fraction, so a band step is an add with carry, the pixel index is the integer part and
+// the fraction gives the weight.
 template <typename T> struct Band;
 template <typename T> struct BandWeights {
     T invq, len;
@@ -106,19 +106,35 @@ template <> struct Band<double> {
 };
 
 template <> struct Band<float> {
-    long long fx, mfx;
+    // lo + kPad = c + f / 2^32: integer column and 32-bit fraction, stepped by the split
+    // slope (mi, mf) with one add and one add-with-carry; error < 1e-6 px after 2^12 steps
+    int c;
+    unsigned f;
+    int mi;
+    unsigned mf;
     __device__ Band(double lo0, double m)
-        : fx(__double2ll_rn((lo0 + kPad) * 0x1p40)), mfx(__double2ll_rn(m * 0x1p40)) {}
-    __device__ void next() { fx += mfx; }
+    {
+        const double p = lo0 + kPad;
+        const double pc = floor(p);
+        c = (int)pc;
+        f = (unsigned)min(__double2ull_rn((p - pc) * 0x1p32), 0xffffffffull);
+        const double mc = floor(m);
+        mi = (int)mc;
+        mf = (unsigned)min(__double2ull_rn((m - mc) * 0x1p32), 0xffffffffull);
+    }
+    __device__ void next()
+    {
+        const unsigned nf = f + mf;
+        c += mi + (nf < f ? 1 : 0);
+        f = nf;
+    }
     __device__ unsigned column(unsigned cmax) const
     {
-        // negative positions wrap to large values and clamp into the right-hand padding
-        return min((unsigned)(int)(fx >> 40), cmax);
+        return (unsigned)min(max(c, 0), (int)cmax);
     }
     __device__ float left_length(const BandWeights<float> &b) const
     {
-        const float frac = (float)(unsigned)(fx >> 8);      // top 32 fraction bits
-        const float w = fmaf(frac, -b.invq * 0x1p-32f, b.invq);
+        const float w = fmaf((float)f, -b.invq * 0x1p-32f, b.invq);
         return __builtin_amdgcn_fmed3f(w, b.len, -1e30f);   // min(w, len)
     }
 };

@@ -149,7 +149,6 @@ struct Solve {
     size_t sX;
     bool need_res;
     double bd_rel;
-    double beta = 0.0;   // ||r_0||, known after the initial normalisation
 
     Solve(const Geometry &g_, int method_, int kind_, int k_max_, abg_stop st_,
           abg_precision p_, hipStream_t s_, void *ws)
@@ -237,7 +236,8 @@ struct Solve {
         }
         CK(launch_mgs(mgs_args(q, k), s));
         CK(launch_givens(H, ld, R, cs, sn, gv, ycol(k),
-                         (method == ABG_METHOD_AB && need_res) ? rho : nullptr, beta, k, dst, s));
+                         (method == ABG_METHOD_AB && need_res) ? rho : nullptr, &dst->beta, k,
+                         dst, s));
         if (need_res) {
             if (method == ABG_METHOD_BA)
                 CK(launch_combine(p.proj, rb0, 1.0, p.proj, Z, ly.mp, k, ycol(k), -1.0, tm, g.m(),
@@ -425,28 +425,17 @@ int run_solver(const Geometry &g, int method, int kind, const void *b, const voi
     S.hr.slots[0] = init;
     CK(hipMemcpyAsync(S.dst, &S.hr.slots[0], sizeof(DevState), hipMemcpyHostToDevice, s));
 
-    // b - A x0, r0 = (B)(b - A x0), beta = ||r0|| into g[0], w_1
+    // b - A x0, r0 = (B)(b - A x0), beta = ||r0|| into g[0], w_1; the host learns beta
+    // (and a zero right-hand side or a NaN) from the scalars of step 1
     RC(S.init_async(b, x0));
+    CK(launch_set_beta(S.dst, s));
     DevState hs;
-    RC(S.sync_read(hs));
-    if (hs.error & 1) return ABG_EDEVICE;
-    const double beta = hs.hnext;
-    if (!std::isfinite(beta) || (hs.error & 2)) return ABG_ENAN;
-    if (info) info->beta = beta;
-    S.beta = beta;
-    if (beta == 0.0) {
-        if (x0) CK(hipMemcpyAsync(x, x0, (size_t)n * S.sX, hipMemcpyDeviceToDevice, s));
-        else CK(launch_combine(p.proj, nullptr, 0.0, p.basis, S.V, S.ly.ldv, 0, S.Y, 1.0, x, n,
-                               nullptr, nullptr, nullptr, nullptr, 0, s));
-        RC(S.literal_residual(b, x));
-        RC(S.sync_read(hs));
-        res_final = hs.res;
-        status = ABG_ZERO_RHS;
-    } else {
+    bool zero_rhs = false;
+    {
         double ncp_best = INFINITY, ncp_prev = 0.0;
         int best_k = 0;
         int k_sel = 0;        // step whose iterate is returned
-        bool x_built = false; // x already holds x_{k_sel}
+        bool x_built = false; // x already holds x_{k_sel}, and res_final its residual
         RC(S.enqueue_step(1));
         for (int k = 1; k <= k_max && k_sel == 0; ++k) {
             if (k < k_max) RC(S.enqueue_step(k + 1));
@@ -454,6 +443,13 @@ int run_solver(const Geometry &g, int method, int kind, const void *b, const voi
             RC(S.wait_step(k, sk));
             if (sk.error & 1) return ABG_EDEVICE;
             if (sk.error) return ABG_ENAN;
+            if (k == 1) {
+                if (info) info->beta = sk.beta;
+                if (sk.stop && sk.stop_reason == kStopZero) {
+                    zero_rhs = true;
+                    break;
+                }
+            }
             k_done = k;
             prof.last = k;
             hist(info ? info->ls_hist : nullptr, k, sk.ls);
@@ -471,6 +467,7 @@ int run_solver(const Geometry &g, int method, int kind, const void *b, const voi
                     if (rk <= thr) {
                         k_sel = k;
                         x_built = true;
+                        res_final = rk;
                     } else {
                         // rejected: resume; step k+1 was skipped, run it again
                         CK(launch_clear_stop(S.dst, s));
@@ -511,13 +508,28 @@ int run_solver(const Geometry &g, int method, int kind, const void *b, const voi
                 }
             }
         }
-        k_stop = k_sel;
-        if (!x_built) RC(S.build_x(S.ycol(k_sel), k_sel, x0, x));
-        // explicit residual of the returned iterate; a NaN/Inf anywhere in b shows here
-        RC(S.literal_residual(b, x));
-        RC(S.sync_read(hs));
-        res_final = hs.res;
-        if (!std::isfinite(res_final)) return ABG_ENAN;
+        if (zero_rhs) {
+            if (x0) CK(hipMemcpyAsync(x, x0, (size_t)n * S.sX, hipMemcpyDeviceToDevice, s));
+            else CK(launch_combine(p.proj, nullptr, 0.0, p.basis, S.V, S.ly.ldv, 0, S.Y, 1.0, x, n,
+                                   nullptr, nullptr, nullptr, nullptr, 0, s));
+            RC(S.literal_residual(b, x));
+            RC(S.sync_read(hs));
+            res_final = hs.res;
+            status = ABG_ZERO_RHS;
+            k_done = 0;
+            prof.last = 0;
+        } else {
+            k_stop = k_sel;
+            if (!x_built) {
+                RC(S.build_x(S.ycol(k_sel), k_sel, x0, x));
+                // explicit residual of the returned iterate (a DP-confirmed iterate has
+                // it already); a NaN/Inf anywhere in b shows here
+                RC(S.literal_residual(b, x));
+                RC(S.sync_read(hs));
+                res_final = hs.res;
+            }
+            if (!std::isfinite(res_final)) return ABG_ENAN;
+        }
     }
 
     if (info) {

@@ -257,3 +257,58 @@ def test_full_size_discrepancy_principle(gpu_lib, solve, dt):
     print(f"  iterate errors vs oracle: norm {e[0]:.2e} pixels {e[1]:.2e} probes {e[2]:.2e}")
     assert max(e) <= 1e-4, e
     assert abs(r.res_norm - ref["res_norms"][ref["k_stop"] - 1]) <= 1e-5 * ref["res_norms"][0]
+
+
+@pytest.fixture(scope="module")
+def config3_inputs():
+    """2048^2 image, 1800 angles, 2897 bins: b = A x_true + e with the oracle's A."""
+    import json
+    import os
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "oracle_config3.json")))
+    w = W.CONFIG3
+    go = O.Geometry(w.N, w.n_ang, w.n_det)
+    b, enorm = W.add_noise(go.A(w.phantom()), w.eta, w.noise_dir())
+    assert abs(enorm - gold["noise_norm"]) <= 1e-9 * enorm
+    return w, b, gold["solves"]["ba-hat"]
+
+
+def test_full_size_ncp_fp32_basis(gpu_lib, config3_inputs):
+    """2048^2 BA-GMRES with NCP stopping, FP32 projectors and basis: the GPU stops at the
+    FP64 oracle's iteration, with its NCP distances and iterate (stored fingerprint,
+    also at fixed k = 3 and 6) within 1e-4."""
+    import torch
+    import paper_2110_01481_amd as abg
+    w, b, ref = config3_inputs
+    gg = abg.Geometry(w.N, w.n_ang, w.n_det)
+    bt = torch.tensor(b, dtype=torch.float32, device="cuda")
+    r = abg.gmres("ba", gg, bt, w.k_max, stop="ncp", basis="f32")
+    print(f"FP32 basis: k_stop {r.k_stop} (oracle {ref['k_stop']}), k_done {r.k_done}")
+    assert r.status == "ok" and r.k_stop == ref["k_stop"]
+    d_ref = np.asarray(ref["ncp"][:r.k_done])
+    assert np.abs(r.ncp_hist - d_ref).max() <= 1e-4 * d_ref.max()
+    e = _fingerprint_errors(r.x.double().cpu().numpy(), ref["x"])
+    print(f"  x_{r.k_stop} errors vs oracle: norm {e[0]:.2e} pixels {e[1]:.2e} probes {e[2]:.2e}")
+    assert max(e) <= 1e-4, e
+    for k, fp in ref["fixed_k"].items():
+        rk = abg.gmres("ba", gg, bt, int(k), basis="f32")
+        ek = _fingerprint_errors(rk.x.double().cpu().numpy(), fp)
+        print(f"  x_{k} errors vs oracle: {max(ek):.2e}")
+        assert max(ek) <= 1e-4, (k, ek)
+
+
+def test_full_size_ncp_bf16_basis_reports_error(gpu_lib, config3_inputs):
+    """Same solve with the basis stored in BF16 (FP32 arithmetic, FP64 dots and
+    Hessenberg): its error against the FP64 oracle is reported; the run must complete with
+    a finite iterate and a stop the NCP rule chose."""
+    import torch
+    import paper_2110_01481_amd as abg
+    w, b, ref = config3_inputs
+    gg = abg.Geometry(w.N, w.n_ang, w.n_det)
+    bt = torch.tensor(b, dtype=torch.float32, device="cuda")
+    r = abg.gmres("ba", gg, bt, w.k_max, stop="ncp", basis="bf16")
+    x = r.x.double().cpu().numpy()
+    e = _fingerprint_errors(x, ref["x"])
+    print(f"BF16 basis: k_stop {r.k_stop} (oracle {ref['k_stop']}); x errors vs FP64 oracle: "
+          f"norm {e[0]:.2e} pixels {e[1]:.2e} probes {e[2]:.2e}")
+    assert r.status == "ok" and 1 <= r.k_stop <= w.k_max
+    assert np.all(np.isfinite(x))
