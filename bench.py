@@ -29,6 +29,91 @@ if ROOT not in sys.path:
 import workloads as W  # noqa: E402
 
 HBM_PEAK_GBPS = 8000.0
+COUNTERS_SUMMARY = os.path.join(ROOT, "profiles", "forward_kernel_512x512_720x725_counters.md")
+# sources whose change invalidates the stored counter readings of the forward projector
+FORWARD_SOURCES = ["paper_2110_01481_amd/csrc/proj_body.h", "paper_2110_01481_amd/csrc/projectors.hip",
+                   "paper_2110_01481_amd/csrc/abg_internal.h"]
+
+
+def forward_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in FORWARD_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _counter_means(csv_path: str, kernel_prefix: str) -> dict:
+    import csv
+    sums, counts = {}, {}
+    with open(csv_path) as fh:
+        for r in csv.DictReader(fh):
+            name = r["Kernel_Name"].replace("abg::(anonymous namespace)::", "").replace("void ", "")
+            if not name.startswith(kernel_prefix):
+                continue
+            c = r["Counter_Name"]
+            sums[c] = sums.get(c, 0.0) + float(r["Counter_Value"])
+            counts[c] = counts.get(c, 0) + 1
+    return {c: sums[c] / counts[c] for c in sums}
+
+
+def summarize_counters(d: str) -> str:
+    """Markdown summary of the FETCH_SIZE / WRITE_SIZE passes under directory d (sub-
+    directories fetch, write, cfetch, cwrite as written by the commands listed in it)."""
+    f = _counter_means(os.path.join(d, "fetch", "run_counter_collection.csv"), "forward_kernel<float>")
+    w = _counter_means(os.path.join(d, "write", "run_counter_collection.csv"), "forward_kernel<float>")
+    cf = _counter_means(os.path.join(d, "cfetch", "run_counter_collection.csv"), "__amd_rocclr_copyBuffer")
+    cw = _counter_means(os.path.join(d, "cwrite", "run_counter_collection.csv"), "__amd_rocclr_copyBuffer")
+    copy_kib = 1024 * 1024
+    data = {"kernel": "forward_kernel<float>", "workload": "512x512, 720 x 725, FP32",
+            "fetch_kib_per_dispatch": round(f["FETCH_SIZE"], 1),
+            "write_kib_per_dispatch": round(w["WRITE_SIZE"], 1),
+            "copy_kib": copy_kib,
+            "copy_fetch_kib": round(cf["FETCH_SIZE"], 1), "copy_write_kib": round(cw["WRITE_SIZE"], 1),
+            "fetch_scale": round(copy_kib / cf["FETCH_SIZE"], 4),
+            "write_scale": round(copy_kib / cw["WRITE_SIZE"], 4),
+            "source_hash": forward_source_hash()}
+    data["traffic_bytes_per_launch"] = int(1024 * (data["fetch_kib_per_dispatch"] * data["fetch_scale"] +
+                                                   data["write_kib_per_dispatch"] * data["write_scale"]))
+    b = ("python -u bench.py --steps 2 --warmup 1 --no-cpu-baseline --no-fp64 --no-batch "
+         "--serve-seconds 0")
+    c = "python -u bench.py --copy-calibration-mib 1024"
+    lines = [
+        "# HBM traffic of the forward projector (512x512 image, 720 x 725 sinogram, FP32)",
+        "",
+        "Counters per dispatch of `forward_kernel<float>`, averaged over the dispatches of the",
+        "run, and of the plain device copy of 1 GiB (`__amd_rocclr_copyBuffer`) that calibrates",
+        "them: the copy reads and writes exactly 1 GiB, so each counter is scaled by",
+        "1 GiB / (its reading on the copy).",
+        "",
+        "Commands (each a run of its own, from the repository root, `TMPDIR=/tmp`):",
+        "",
+        f"    rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir>/fetch -o run -- {b}",
+        f"    rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir>/write -o run -- {b}",
+        f"    rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir>/cfetch -o run -- {c}",
+        f"    rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir>/cwrite -o run -- {c}",
+        "    python bench.py --summarize-counters <dir>",
+        "",
+        "`source_hash` covers the forward projector's sources; bench.py reports `traffic` only",
+        "while it matches.",
+        "",
+        "```json",
+        json.dumps(data, indent=1),
+        "```",
+        ""]
+    return "\n".join(lines)
+
+
+def stored_traffic() -> dict | None:
+    """The stored counter summary, if it was taken on the current forward projector."""
+    try:
+        with open(COUNTERS_SUMMARY) as fh:
+            text = fh.read()
+        data = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+    except (OSError, IndexError, ValueError):
+        return None
+    return data if data.get("source_hash") == forward_source_hash() else None
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 
@@ -213,10 +298,15 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="seconds of Poisson arrivals for the serving run (0: skip)")
     ap.add_argument("--serve-basis", default="f32,bf16")
+    ap.add_argument("--summarize-counters", default="",
+                    help="print the counter summary of the rocprofv3 passes under this directory")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run device-to-device copies of this many MiB (a plain copy "
                          "kernel whose HBM counters calibrate FETCH_SIZE / WRITE_SIZE)")
     args = ap.parse_args()
+    if args.summarize_counters:
+        print(summarize_counters(args.summarize_counters))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus N > 1 is not supported "
                                    "(multi-GPU sharding is a design note, not built)"}))
@@ -319,11 +409,17 @@ def main():
                 "unit": "GB/s", "frac": None, "traffic": None,
                 "avg_launch_ms": round(mgs_ms / max(mgs_n, 1), 4)}
     else:
+        tr = stored_traffic() if args.config == 2 else None
         roof = {"bound": "alu", "kernel": "forward_kernel (ray-driven line model A, FP32)",
                 "achieved": round(fwd_tflops, 3), "peak": FP32_VECTOR_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(fwd_tflops / FP32_VECTOR_PEAK_TFLOPS, 4),
-                "traffic": None, "avg_launch_ms": round(fwd_avg_ms, 4),
+                "traffic": tr["traffic_bytes_per_launch"] if tr else None,
+                "avg_launch_ms": round(fwd_avg_ms, 4),
                 "work_per_launch": f"{nnz} ray-pixel intersections x 2 flop"}
+        if tr:
+            roof["traffic_note"] = (f"HBM bytes per launch from FETCH_SIZE x {tr['fetch_scale']} + "
+                                    f"WRITE_SIZE x {tr['write_scale']} (copy-calibrated); "
+                                    f"{tr['traffic_bytes_per_launch'] / (fwd_avg_ms * 1e-3) / 1e9:.0f} GB/s")
 
     extra = {
         "A_applies_per_s": round(1e3 / fwd_avg_ms, 1) if fwd_n else None,

@@ -243,11 +243,14 @@ bool profiling_on();
 // Brackets one launch with timing events when profiling is on. `step` tags launches
 // that belong to an Arnoldi step of the solve running on this thread; launches of
 // steps that a solve enqueued but never ran (past its stop) are dropped at its end.
+// With `ext`, the caller passes e0/e1 to hipExtLaunchKernelGGL, which stamps them at the
+// kernel's own start and end (when profiling is off both are null).
 struct ProfScope {
-    ProfScope(int kind, hipStream_t s, int step = 0);
+    ProfScope(int kind, hipStream_t s, int step = 0, bool ext = false);
     ~ProfScope();
     int kind, step;
     hipStream_t s;
+    bool ext;
     hipEvent_t e0 = nullptr, e1 = nullptr;
 };
 void profile_flush();

@@ -83,7 +83,8 @@ AngleParams make_angle(double theta_deg, double ds)
 
 bool profiling_on() { return g_prof_on; }
 
-ProfScope::ProfScope(int kind_, hipStream_t s_, int step_) : kind(kind_), step(step_), s(s_)
+ProfScope::ProfScope(int kind_, hipStream_t s_, int step_, bool ext_)
+    : kind(kind_), step(step_), s(s_), ext(ext_)
 {
     if (!g_prof_on) return;
     e0 = take_event();
@@ -92,13 +93,13 @@ ProfScope::ProfScope(int kind_, hipStream_t s_, int step_) : kind(kind_), step(s
         e0 = e1 = nullptr;
         return;
     }
-    (void)hipEventRecord(e0, s);
+    if (!ext) (void)hipEventRecord(e0, s);
 }
 
 ProfScope::~ProfScope()
 {
     if (!e0) return;
-    (void)hipEventRecord(e1, s);
+    if (!ext) (void)hipEventRecord(e1, s);
     std::lock_guard<std::mutex> lk(g_prof_mu);
     g_pending.push_back({kind, e0, e1, t_solve, step});
 }

@@ -14,6 +14,8 @@
 //           footprint (at most 32 bins per angle) is staged in LDS; every pixel then
 //           reads its two taps per angle from LDS, and the four wave partials are summed
 //           in a fixed order at the end.
+#include <hip/hip_ext.h>
+
 #include "proj_body.h"
 
 namespace abg {
@@ -80,9 +82,11 @@ hipError_t forward_t(const Geometry &g, const void *x, void *y, void *ws, hipStr
     dim3 grid((g.n_det + kFwdBlock - 1) / kFwdBlock, g.n_ang);
     const double s0 = -0.5 * (g.n_det - 1) * g.ds;
     {
-        ProfScope ps(kProfFwd, s, st ? k : 0);
-        forward_kernel<T><<<grid, kFwdBlock, 0, s>>>(xr, xc, static_cast<T *>(y), g.dev, N, S,
-                                                     g.n_det, g.ds, s0, st, k);
+        // timed at the kernel's own start and end when profiling is on
+        ProfScope ps(kProfFwd, s, st ? k : 0, true);
+        hipExtLaunchKernelGGL(forward_kernel<T>, grid, dim3(kFwdBlock), 0, s, ps.e0, ps.e1, 0,
+                              (const T *)xr, (const T *)xc, static_cast<T *>(y),
+                              (const AngleParams *)g.dev, N, S, g.n_det, g.ds, s0, st, k);
     }
     return hipGetLastError();
 }
@@ -93,15 +97,15 @@ hipError_t back_t(const Geometry &g, int kind, const void *y, void *x, hipStream
 {
     dim3 grid((g.N + kTile - 1) / kTile, (g.N + kTile - 1) / kTile);
     const double s0 = -0.5 * (g.n_det - 1) * g.ds;
-    ProfScope ps(kProfBack, s, st ? k : 0);
+    ProfScope ps(kProfBack, s, st ? k : 0, true);
     if (kind == ABG_BP_ADJ)
-        back_kernel<T, true><<<grid, kBackThreads, 0, s>>>(
-            static_cast<const T *>(y), static_cast<T *>(x), g.dev, g.N, g.n_ang, g.n_det, g.ds, s0,
-            st, k);
+        hipExtLaunchKernelGGL(back_kernel<T, true>, grid, dim3(kBackThreads), 0, s, ps.e0, ps.e1,
+                              0, static_cast<const T *>(y), static_cast<T *>(x),
+                              (const AngleParams *)g.dev, g.N, g.n_ang, g.n_det, g.ds, s0, st, k);
     else
-        back_kernel<T, false><<<grid, kBackThreads, 0, s>>>(
-            static_cast<const T *>(y), static_cast<T *>(x), g.dev, g.N, g.n_ang, g.n_det, g.ds, s0,
-            st, k);
+        hipExtLaunchKernelGGL(back_kernel<T, false>, grid, dim3(kBackThreads), 0, s, ps.e0, ps.e1,
+                              0, static_cast<const T *>(y), static_cast<T *>(x),
+                              (const AngleParams *)g.dev, g.N, g.n_ang, g.n_det, g.ds, s0, st, k);
     return hipGetLastError();
 }
 

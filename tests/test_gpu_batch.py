@@ -273,3 +273,28 @@ def test_config4_batched_equals_single_solves(gpu_lib):
             if r.k_stop > 1:
                 assert r.res_hist[r.k_stop - 2] > thr * (1 - 1e-3)
     print("config4 k_stop:", sorted(ks))
+
+
+@pytest.mark.parametrize("i", [0, 1])
+def test_dp_candidate_rejected_by_explicit_residual(gpu_lib, mix, i):
+    """A DP candidate whose residual-form norm lies within the candidate slack above the
+    threshold is rejected by the explicit ||b - A x_k|| and the solve resumes, in single
+    solves and in the engine alike: threshold set between ||r_5|| / (1 + slack) and
+    ||r_5||, so step 5 raises a candidate that the explicit residual turns down."""
+    import torch
+    abg = gpu_lib
+    c = mix[i]
+    p = c.problem(abg, torch.float32)
+    probe = abg.gmres(c.method, p.g, p.b, 12, stop="dp", tau=1.0, noise_norm=1e-30, bp=c.kind)
+    r5, r6 = probe.res_hist[4], probe.res_hist[5]
+    thr = r5 / (1.0 + 5e-4)          # FP32 candidate slack is 1e-3
+    assert r6 < thr * 0.999, "the residual must drop below the threshold at step 6"
+    s = abg.gmres(c.method, p.g, p.b, 12, stop="dp", tau=1.0, noise_norm=thr, bp=c.kind)
+    assert s.status == "ok" and s.k_stop == 6 and s.n_literal == 2, (s.k_stop, s.n_literal)
+    assert s.res_hist[4] > thr and s.res_norm <= thr
+    pe = c.problem(abg, torch.float32)
+    pe.tau, pe.noise_norm, pe.k_max = 1.0, thr, 12
+    e = abg.Engine(proj="f32", basis="f32", max_slots=2).run([pe])[0]
+    assert e.status == "ok" and e.k_stop == 6 and e.n_literal == 2, (e.k_stop, e.n_literal)
+    assert e.res_hist[4] > thr and e.res_norm <= thr
+    assert float(torch.linalg.vector_norm(e.x - s.x) / torch.linalg.vector_norm(s.x)) <= 1e-5
