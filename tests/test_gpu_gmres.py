@@ -312,3 +312,26 @@ def test_full_size_ncp_bf16_basis_reports_error(gpu_lib, config3_inputs):
           f"norm {e[0]:.2e} pixels {e[1]:.2e} probes {e[2]:.2e}")
     assert r.status == "ok" and 1 <= r.k_stop <= w.k_max
     assert np.all(np.isfinite(x))
+
+
+@pytest.mark.parametrize("N,n_ang,n_det", [(1, 1, 1), (2, 1, 3), (5, 3, 1), (3, 2, 2), (1, 4, 3)])
+def test_degenerate_geometries(gpu_lib, N, n_ang, n_det):
+    """Single pixel, single angle, single bin: the projectors match the oracle and both
+    solvers reach the same breakdown step and iterate (the Krylov space is exhausted
+    after one or two steps)."""
+    import torch
+    import paper_2110_01481_amd as abg
+    go = O.Geometry(N, n_ang, n_det)
+    gg = abg.Geometry(N, n_ang, n_det)
+    x = np.arange(1, N * N + 1, dtype=np.float64)
+    xt = torch.tensor(x, device="cuda")
+    y = go.A(x)
+    assert np.allclose(gg.fp(xt).cpu().numpy(), y, rtol=1e-12, atol=1e-12)
+    yt = torch.tensor(y, device="cuda")
+    for kind in ("hat", "adj"):
+        assert np.allclose(gg.bp(yt, kind).cpu().numpy(), go.back(kind)(y), rtol=1e-12, atol=1e-12)
+    for method, f in (("ab", O.ab_gmres), ("ba", O.ba_gmres)):
+        ref = f(go.A, go.B_hat, y, 4)
+        r = abg.gmres(method, gg, yt, 4)
+        assert r.status == ref.status == "breakdown" and r.k_stop == ref.k_stop, (method, r.status, r.k_stop)
+        assert np.allclose(r.x.cpu().numpy(), ref.x, rtol=1e-9, atol=1e-9)
