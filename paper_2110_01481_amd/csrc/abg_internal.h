@@ -156,21 +156,22 @@ hipError_t launch_mgs(const MgsLaunch &a, hipStream_t s);
 // set, ||out||_2 is reduced in a fixed order by the last block to finish and written to
 // *norm; when st is given the launch belongs to step k (halt check) and, if
 // st->dp_thr > 0 and ||out|| <= dp_thr, raises the DP stop for step k. `count` is a
-// zeroed counter that the last block resets.
+// zeroed counter that the last block resets. `snap` (norm and st given): a device-visible
+// copy of *st is written there once the launch is over (also when the step is halted).
 hipError_t launch_combine(int tout, const void *base, double base_coef, int tv, const void *V,
                           size_t ldv, int kk, const double *coef, double sgn, void *out,
                           long long L, double *partials, unsigned *count, double *norm,
-                          DevState *st, int k, hipStream_t s);
+                          DevState *st, int k, hipStream_t s, DevState *snap = nullptr);
 // out = a - b with partial sums of out^2.
 hipError_t launch_sub_norm(int t, const void *a, const void *b, void *out, long long L,
                            double *partials, int *nblocks, hipStream_t s);
 // dst = sqrt(sum partials[0..nb)) (fixed order, one block).
 hipError_t launch_reduce_sqrt(const double *partials, int nb, double *dst, hipStream_t s);
 // Givens update of column k of H, y_k into y (k entries), and rho = beta e_1 - H_k y_k
-// when rho is given (beta read on the device).
+// when rho is given (beta read on the device). `snap`: as for launch_combine.
 hipError_t launch_givens(double *H, int ld, double *R, double *cs, double *sn, double *g,
                          double *y, double *rho, const double *beta, int k, DevState *st,
-                         hipStream_t s);
+                         hipStream_t s, DevState *snap = nullptr);
 // st->beta = st->hnext after the initial normalisation, or the zero-right-hand-side stop.
 hipError_t launch_set_beta(DevState *st, hipStream_t s);
 // Clears the stop flag (after a DP candidate that the explicit residual rejected).
@@ -181,6 +182,21 @@ void set_mgs_target_blocks(int blocks);
 void set_mgs_force_stream(int on);
 hipError_t launch_fill_u32(unsigned *p, size_t n, unsigned v, hipStream_t s);
 hipError_t launch_fill_f64(double *p, size_t n, double v, hipStream_t s);
+// One range of a fused initialisation: n 32-bit words at p; the first n_src are copied
+// from src, the others set to the 64-bit pattern (lo, hi) (even words lo, odd words hi,
+// so p is 8-byte aligned when lo != hi). Ranges must not overlap.
+struct FillRange {
+    void *p;
+    const void *src;
+    unsigned long long n, n_src;
+    unsigned lo, hi;
+};
+constexpr int kMaxFill = 12;
+// All ranges in one launch; with init, *st = *init as well.
+hipError_t launch_init_fill(const FillRange *r, int n, const DevState *init, DevState *st,
+                            hipStream_t s);
+// Bit pattern of an empty MGS reduction slot.
+unsigned long long slot_empty_bits();
 // Marks MGS reduction slots empty (n doubles).
 hipError_t launch_clear_slots(double *p, size_t n, hipStream_t s);
 hipError_t launch_axpy_inplace(int t, void *x, const void *x0, long long L, hipStream_t s);
@@ -188,9 +204,9 @@ hipError_t launch_axpy_inplace(int t, void *x, const void *x0, long long L, hipS
 // ---- NCP (ncp.hip) ------------------------------------------------------------------
 size_t ncp_scratch_bytes(const Geometry &g);
 // d_k of the residual r into st->ncp; raises the NCP stop for step k when k >= 2 and
-// d_k > d_{k-1}.
+// d_k > d_{k-1}. `snap`: as for launch_combine.
 hipError_t launch_ncp(const Geometry &g, int t, const void *r, double *scratch, DevState *st,
-                      int k, hipStream_t s);
+                      int k, hipStream_t s, DevState *snap = nullptr);
 
 // ---- solvers (solver.hip) -----------------------------------------------------------
 size_t solver_workspace_bytes(const Geometry &g, int method, int k_max, abg_precision p,

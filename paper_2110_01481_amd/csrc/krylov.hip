@@ -159,12 +159,15 @@ __global__ __launch_bounds__(kBlock) void combine_kernel(const TB *__restrict__ 
                                                          double sgn, TO *__restrict__ out,
                                                          long long L, double *partials,
                                                          unsigned *count, double *norm,
-                                                         DevState *st, int k)
+                                                         DevState *st, int k, DevState *snap)
 {
     __shared__ double cf[kMaxCoef];
     __shared__ double lds[kWaves];
     __shared__ int last;
-    if (halted(st, k)) return;
+    if (halted(st, k)) {
+        if (snap && blockIdx.x == 0 && threadIdx.x == 0) *snap = *st;
+        return;
+    }
     for (int j = threadIdx.x; j < kk; j += kBlock) cf[j] = sgn * coef[j];
     __syncthreads();
     // each thread combines kCombU elements per trip, all of a column's loads in flight
@@ -221,6 +224,7 @@ __global__ __launch_bounds__(kBlock) void combine_kernel(const TB *__restrict__ 
                 st->stop_k = k;
                 st->stop_reason = kStopDP;
             }
+            if (snap) *snap = *st;
         }
     }
 }
@@ -269,13 +273,43 @@ __global__ void fill_f64_kernel(double *p, size_t n, double v)
     if (i < n) p[i] = v;
 }
 
+// The ranges of a fused initialisation, one after the other over the whole grid, and the
+// initial scalars (written by one thread).
+struct FillList {
+    FillRange r[kMaxFill];
+    int n;
+    int has_init;
+    DevState init;
+};
+
+__global__ __launch_bounds__(kBlock) void init_fill_kernel(const FillList L, DevState *st)
+{
+    const size_t T = (size_t)gridDim.x * kBlock;
+    const size_t i0 = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (L.has_init && i0 == 0) *st = L.init;
+    for (int r = 0; r < L.n; ++r) {
+        unsigned *p = static_cast<unsigned *>(L.r[r].p);
+        const unsigned *src = static_cast<const unsigned *>(L.r[r].src);
+        const size_t n = L.r[r].n, ns = L.r[r].n_src;
+        const unsigned lo = L.r[r].lo, hi = L.r[r].hi;
+        for (size_t i = i0; i < n; i += T) p[i] = i < ns ? src[i] : ((i & 1) ? hi : lo);
+    }
+}
+
 __global__ __launch_bounds__(64) void givens_kernel(double *H, int ld, double *R, double *cs,
                                                     double *sn, double *g, double *y,
                                                     double *rho, const double *beta, int k,
-                                                    DevState *st)
+                                                    DevState *st, DevState *snap)
 {
-    if (halted(st, k)) return;
+    if (halted(st, k)) {
+        if (snap && threadIdx.x == 0) *snap = *st;
+        return;
+    }
     givens_step(H, ld, R, cs, sn, g, y, rho, *beta, k, st);
+    if (snap) {
+        __syncthreads();
+        if (threadIdx.x == 0) *snap = *st;
+    }
 }
 
 // After the initial normalisation: beta = ||r_0|| for the later steps, or (r_0 = 0) the
@@ -312,13 +346,14 @@ int blocks_for(long long L, long long cap = 1024)
 template <typename TO, typename TB, typename TV>
 hipError_t combine_go(const void *base, double bcoef, const void *V, size_t ldv, int kk,
                       const double *coef, double sgn, void *out, long long L, double *partials,
-                      unsigned *count, double *norm, DevState *st, int k, hipStream_t s)
+                      unsigned *count, double *norm, DevState *st, int k, DevState *snap,
+                      hipStream_t s)
 {
     // with a norm, every block signals completion on one counter: keep the grid moderate
     const int nb = blocks_for((L + kCombU - 1) / kCombU, norm ? 512 : 1024);
     combine_kernel<TO, TB, TV><<<nb, kBlock, 0, s>>>(
         static_cast<const TB *>(base), bcoef, static_cast<const TV *>(V), ldv, kk, coef, sgn,
-        static_cast<TO *>(out), L, partials, count, norm, st, k);
+        static_cast<TO *>(out), L, partials, count, norm, st, k, snap);
     return hipGetLastError();
 }
 
@@ -363,12 +398,14 @@ hipError_t launch_mgs(const MgsLaunch &m, hipStream_t s)
 hipError_t launch_combine(int tout, const void *base, double base_coef, int tv, const void *V,
                           size_t ldv, int kk, const double *coef, double sgn, void *out,
                           long long L, double *partials, unsigned *count, double *norm,
-                          DevState *st, int k, hipStream_t s)
+                          DevState *st, int k, hipStream_t s, DevState *snap)
 {
     if (kk > kMaxCoef) return hipErrorInvalidValue;
+    if (snap && !(norm && st)) return hipErrorInvalidValue;
     ProfScope ps(kProfCombine, s, st ? k : 0);
 #define ABG_COMBINE(TO, TB, TV) \
-    combine_go<TO, TB, TV>(base, base_coef, V, ldv, kk, coef, sgn, out, L, partials, count, norm, st, k, s)
+    combine_go<TO, TB, TV>(base, base_coef, V, ldv, kk, coef, sgn, out, L, partials, count, norm, st, k, \
+                           snap, s)
     if (tout == ABG_F64) {
         if (tv == ABG_F64) return ABG_COMBINE(double, double, double);
         if (tv == ABG_F32) return ABG_COMBINE(double, double, float);
@@ -408,10 +445,10 @@ hipError_t launch_set_beta(DevState *st, hipStream_t s)
 
 hipError_t launch_givens(double *H, int ld, double *R, double *cs, double *sn, double *g,
                          double *y, double *rho, const double *beta, int k, DevState *st,
-                         hipStream_t s)
+                         hipStream_t s, DevState *snap)
 {
     if (k + 1 > kMaxCoef) return hipErrorInvalidValue;
-    givens_kernel<<<1, 64, 0, s>>>(H, ld, R, cs, sn, g, y, rho, beta, k, st);
+    givens_kernel<<<1, 64, 0, s>>>(H, ld, R, cs, sn, g, y, rho, beta, k, st, snap);
     return hipGetLastError();
 }
 
@@ -434,6 +471,28 @@ hipError_t launch_fill_f64(double *p, size_t n, double v, hipStream_t s)
     fill_f64_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(p, n, v);
     return hipGetLastError();
 }
+
+hipError_t launch_init_fill(const FillRange *r, int n, const DevState *init, DevState *st,
+                            hipStream_t s)
+{
+    if (n < 0 || n > kMaxFill || (init && !st)) return hipErrorInvalidValue;
+    FillList L{};
+    size_t most = 0;
+    for (int i = 0; i < n; ++i) {
+        L.r[i] = r[i];
+        if (r[i].n_src > r[i].n || (r[i].n && !r[i].p) || (r[i].n_src && !r[i].src))
+            return hipErrorInvalidValue;
+        most = std::max(most, (size_t)r[i].n);
+    }
+    L.n = n;
+    L.has_init = init != nullptr;
+    if (init) L.init = *init;
+    const int nb = (int)std::min<size_t>(std::max<size_t>((most + kBlock - 1) / kBlock, 1), 2048);
+    init_fill_kernel<<<nb, kBlock, 0, s>>>(L, st);
+    return hipGetLastError();
+}
+
+unsigned long long slot_empty_bits() { return kSlotEmpty; }
 
 hipError_t launch_clear_slots(double *p, size_t n, hipStream_t s)
 {

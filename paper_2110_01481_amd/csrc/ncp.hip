@@ -103,9 +103,13 @@ __global__ __launch_bounds__(kBlock) void ncp_mean_kernel(const double *__restri
 
 // d_k = sqrt(sum of partials); the NCP stop is raised at the first k >= 2 whose d_k
 // exceeds d_{k-1} (the iterate to return is then x_{k-1}).
-__global__ void ncp_final_kernel(const double *partials, int nb, DevState *st, int k)
+__global__ void ncp_final_kernel(const double *partials, int nb, DevState *st, int k,
+                                 DevState *snap)
 {
-    if (halted(st, k)) return;
+    if (halted(st, k)) {
+        if (snap && threadIdx.x == 0 && blockIdx.x == 0) *snap = *st;
+        return;
+    }
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         double t = 0.0;
         for (int b = 0; b < nb; ++b) t += partials[b];
@@ -119,6 +123,7 @@ __global__ void ncp_final_kernel(const double *partials, int nb, DevState *st, i
             st->stop_reason = kStopNCP;
         }
         st->ncp_prev = d;
+        if (snap) *snap = *st;
     }
 }
 
@@ -153,7 +158,7 @@ size_t ncp_scratch_bytes(const Geometry &g)
 }
 
 hipError_t launch_ncp(const Geometry &g, int t, const void *r, double *scratch, DevState *st,
-                      int k, hipStream_t s)
+                      int k, hipStream_t s, DevState *snap)
 {
     const int q = g.n_det / 2;
     if (q < 1) return hipErrorInvalidValue;
@@ -164,7 +169,7 @@ hipError_t launch_ncp(const Geometry &g, int t, const void *r, double *scratch, 
     if (e != hipSuccess) return e;
     const int nb = (q + kBlock - 1) / kBlock;
     ncp_mean_kernel<<<nb, kBlock, 0, s>>>(crow, g.n_ang, q, part, st, k);
-    ncp_final_kernel<<<1, 64, 0, s>>>(part, nb, st, k);
+    ncp_final_kernel<<<1, 64, 0, s>>>(part, nb, st, k, snap);
     return hipGetLastError();
 }
 

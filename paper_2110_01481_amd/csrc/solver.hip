@@ -85,6 +85,7 @@ constexpr int kRing = 4;
 // process ends.
 struct HostRes {
     DevState *slots = nullptr;
+    DevState *dslots = nullptr;   // the same slots as the device addresses them
     int capacity = 0;
     int device = -1;
     hipEvent_t ev[kRing] = {};
@@ -110,7 +111,10 @@ hipError_t host_resources(HostRes &h, int k_max)
         if (cache.slots) (void)hipHostFree(cache.slots);
         cache.slots = nullptr;
         e = hipHostMalloc((void **)&cache.slots, sizeof(DevState) * (k_max + 1), hipHostMallocDefault);
+        if (e == hipSuccess) e = hipHostGetDevicePointer((void **)&cache.dslots, cache.slots, 0);
         if (e != hipSuccess) {
+            if (cache.slots) (void)hipHostFree(cache.slots);
+            cache.slots = cache.dslots = nullptr;
             cache.capacity = 0;
             return e;
         }
@@ -235,19 +239,22 @@ struct Solve {
             RC(fwd(tn, q, dst, k));
         }
         CK(launch_mgs(mgs_args(q, k), s));
+        // the step's last kernel copies the scalars into host slot k
+        DevState *snap = hr.dslots + k;
+        const bool ncp_stop = st.kind == ABG_STOP_NCP;
         CK(launch_givens(H, ld, R, cs, sn, gv, ycol(k),
                          (method == ABG_METHOD_AB && need_res) ? rho : nullptr, &dst->beta, k,
-                         dst, s));
+                         dst, s, need_res ? nullptr : snap));
         if (need_res) {
+            DevState *csnap = ncp_stop ? nullptr : snap;
             if (method == ABG_METHOD_BA)
                 CK(launch_combine(p.proj, rb0, 1.0, p.proj, Z, ly.mp, k, ycol(k), -1.0, tm, g.m(),
-                                  part, count, &dst->res, dst, k, s));
+                                  part, count, &dst->res, dst, k, s, csnap));
             else
                 CK(launch_combine(p.proj, nullptr, 0.0, p.basis, V, ly.ldv, k + 1, rho, 1.0, tm,
-                                  g.m(), part, count, &dst->res, dst, k, s));
-            if (st.kind == ABG_STOP_NCP) CK(launch_ncp(g, p.proj, tm, ncp, dst, k, s));
+                                  g.m(), part, count, &dst->res, dst, k, s, csnap));
+            if (ncp_stop) CK(launch_ncp(g, p.proj, tm, ncp, dst, k, s, snap));
         }
-        CK(hipMemcpyAsync(&hr.slots[k], dst, sizeof(DevState), hipMemcpyDeviceToHost, s));
         CK(hipEventRecord(hr.ev[k % kRing], s));
         return ABG_OK;
     }
@@ -294,26 +301,32 @@ struct Solve {
 
     // Initialisation without a host synchronisation: scratch cleared, b - A x0,
     // r0 = (B)(b - A x0), and MGS step 0 (beta = ||r0|| into dst->hnext and g[0], w_1).
-    int init_async(const void *b, const void *x0)
+    // init: the solve's initial scalars (null: the caller owns *dst)
+    int init_async(const void *b, const void *x0, const DevState *init)
     {
         const long long m = g.m();
-        CK(launch_clear_slots(mgs_part, (size_t)ly.mgs_cap, s));
-        CK(launch_fill_u32(tick, (size_t)ld + 2, 0u, s));
-        CK(launch_fill_u32(count, 16, 0u, s));
-        CK(launch_fill_f64(H, (size_t)ld * k_max, 0.0, s));
-        CK(launch_fill_f64(gv, (size_t)ld, 0.0, s));
-        CK(launch_fill_u32(reinterpret_cast<unsigned *>(fpws), fp_workspace_bytes(g, p.proj) / 4, 0u, s));
-        // padding of the MGS input vectors must read as zero; so must that of w_1, which
-        // a later step may read over a longer register tile than step 0 writes
-        CK(launch_fill_u32(reinterpret_cast<unsigned *>(q), ly.ldv * sX / 4, 0u, s));
-        CK(launch_fill_u32(reinterpret_cast<unsigned *>(rb0), ly.mp * sX / 4, 0u, s));
-        CK(launch_fill_u32(reinterpret_cast<unsigned *>(V), ly.ldv * dtype_size(p.basis) / 4, 0u, s));
+        // one launch: the scalars, empty reduction slots, zeroed counters, H and g, the
+        // forward projector's scratch (its padding must read zero), and the padding of the
+        // MGS input vectors and of w_1 (a later step may read w_1 over a longer register
+        // tile than step 0 writes); with x0 = 0, rb0 = b (zero-padded)
+        const unsigned long long empty = slot_empty_bits();
+        auto words = [](size_t bytes) { return (unsigned long long)(bytes / 4); };
+        const FillRange fr[] = {
+            {mgs_part, nullptr, 2ull * ly.mgs_cap, 0, (unsigned)empty, (unsigned)(empty >> 32)},
+            {tick, nullptr, (unsigned long long)ld + 2, 0, 0u, 0u},
+            {count, nullptr, 16, 0, 0u, 0u},
+            {H, nullptr, 2ull * ld * k_max, 0, 0u, 0u},
+            {gv, nullptr, 2ull * ld, 0, 0u, 0u},
+            {fpws, nullptr, words(fp_workspace_bytes(g, p.proj)), 0, 0u, 0u},
+            {q, nullptr, words(ly.ldv * sX), 0, 0u, 0u},
+            {rb0, x0 ? nullptr : b, words(ly.mp * sX), x0 ? 0ull : words(m * sX), 0u, 0u},
+            {V, nullptr, words(ly.ldv * dtype_size(p.basis)), 0, 0u, 0u},
+        };
+        CK(launch_init_fill(fr, (int)(sizeof fr / sizeof fr[0]), init, dst, s));
         if (x0) {
             RC(fwd(x0, tm));
             int nb = 0;
             CK(launch_sub_norm(p.proj, b, tm, rb0, m, part, &nb, s));
-        } else {
-            CK(hipMemcpyAsync(rb0, b, (size_t)m * sX, hipMemcpyDeviceToDevice, s));
         }
         const void *r0 = rb0;
         if (method == ABG_METHOD_BA) {
@@ -379,7 +392,7 @@ int instance_init(const Geometry &g, int method, int kind, int k_max, abg_stop s
 {
     Solve S(g, method, kind, k_max, st, p, s, ws);
     S.dst = dst;
-    return S.init_async(b, x0);
+    return S.init_async(b, x0, nullptr);
 }
 
 int instance_form_x(const Geometry &g, int method, int kind, int k_max, abg_stop st,
@@ -411,7 +424,7 @@ int run_solver(const Geometry &g, int method, int kind, const void *b, const voi
         }
         ~ProfSolve() { finish(); }
     } prof;
-    const long long m = g.m(), n = g.n();
+    const long long n = g.n();
     const double thr = st.kind == ABG_STOP_DP ? st.tau * st.noise_norm : 0.0;
     int k_stop = 0, k_done = 0, status = ABG_OK, n_literal = 0;
     double res_final = 0.0, ncp_final = 0.0;
@@ -422,12 +435,10 @@ int run_solver(const Geometry &g, int method, int kind, const void *b, const voi
     // device scalars: zero, with the DP candidate threshold
     DevState init{};
     init.dp_thr = st.kind == ABG_STOP_DP ? thr * (1.0 + dp_slack(p.basis)) : 0.0;
-    S.hr.slots[0] = init;
-    CK(hipMemcpyAsync(S.dst, &S.hr.slots[0], sizeof(DevState), hipMemcpyHostToDevice, s));
 
     // b - A x0, r0 = (B)(b - A x0), beta = ||r0|| into g[0], w_1; the host learns beta
     // (and a zero right-hand side or a NaN) from the scalars of step 1
-    RC(S.init_async(b, x0));
+    RC(S.init_async(b, x0, &init));
     CK(launch_set_beta(S.dst, s));
     DevState hs;
     bool zero_rhs = false;
