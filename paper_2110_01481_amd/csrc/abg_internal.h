@@ -65,6 +65,13 @@ hipError_t launch_forward(const Geometry &g, int dtype, const void *x, void *y, 
                           bool pads_zero = false);
 hipError_t launch_back(const Geometry &g, int kind, int dtype, const void *y, void *x,
                        hipStream_t s, const DevState *st = nullptr, int k = 0);
+// The back projection written into the forward projector's scratch ws (its padded copies,
+// whose padding must already be zero), and the forward projection of what ws holds: an
+// A-after-B pair without the copy step.
+hipError_t launch_back_staged(const Geometry &g, int kind, int dtype, const void *y, void *ws,
+                              hipStream_t s, const DevState *st = nullptr, int k = 0);
+hipError_t launch_forward_staged(const Geometry &g, int dtype, void *y, void *ws, hipStream_t s,
+                                 const DevState *st = nullptr, int k = 0);
 
 // ---- Krylov kernels (krylov.hip) -----------------------------------------------------
 // Scalars of one solve, in device memory. Per-step kernels of step k return at entry
@@ -148,6 +155,13 @@ struct MgsLaunch {
     DevState *st;
     double bd_rel;               // breakdown: h_{k+1,k} <= bd_rel * ||q_k||
     int step;                    // Arnoldi step (0: the initial normalisation)
+    // single solves only (zero otherwise)
+    int set_beta;                // step 0: beta = h_{1,0}, or the zero-right-hand-side stop
+    // step k >= 1: the Givens update of column k follows in the same launch (giv_H null:
+    // none); arguments as for launch_givens, beta read from st; snap as for launch_combine
+    double *giv_H, *giv_R, *giv_cs, *giv_sn, *giv_g, *giv_y, *giv_rho;
+    int giv_ld;
+    DevState *snap;
 };
 constexpr int kMaxGrid = 2048;
 hipError_t launch_mgs(const MgsLaunch &a, hipStream_t s);

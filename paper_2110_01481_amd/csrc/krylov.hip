@@ -31,12 +31,16 @@ __global__ __launch_bounds__(kBlock) void mgs_kernel(MgsDev a)
 {
     __shared__ double lds[kWaves];
     __shared__ int s_rank;
-    if (halted(a.st, a.step)) return;
+    if (halted(a.st, a.step)) {
+        if (a.giv.snap && blockIdx.x == 0 && threadIdx.x == 0) *a.giv.snap = *a.st;
+        return;
+    }
     if (threadIdx.x == 0)
         s_rank = (int)__hip_atomic_fetch_add(a.ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
     const int rank = __builtin_amdgcn_readfirstlane(s_rank);
     mgs_body<TX, TV, E>(a, rank, gridDim.x, lds);
+    mgs_tail(a, rank);
 }
 
 template <typename TX, typename TV>
@@ -44,12 +48,16 @@ __global__ __launch_bounds__(kBlock) void mgs_stream_kernel(MgsDev a)
 {
     __shared__ double lds[kWaves];
     __shared__ int s_rank;
-    if (halted(a.st, a.step)) return;
+    if (halted(a.st, a.step)) {
+        if (a.giv.snap && blockIdx.x == 0 && threadIdx.x == 0) *a.giv.snap = *a.st;
+        return;
+    }
     if (threadIdx.x == 0)
         s_rank = (int)__hip_atomic_fetch_add(a.ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
     const int rank = __builtin_amdgcn_readfirstlane(s_rank);
     mgs_stream_body<TX, TV>(a, rank, gridDim.x, lds);
+    mgs_tail(a, rank);
 }
 
 // ---- resident-block bookkeeping -----------------------------------------------------
@@ -384,6 +392,11 @@ hipError_t launch_mgs(const MgsLaunch &m, hipStream_t s)
     d.st = m.st;
     d.bd_rel = m.bd_rel;
     d.step = m.step;
+    d.set_beta = m.set_beta;
+    d.giv = GivensDev{m.giv_H, m.giv_R, m.giv_cs, m.giv_sn, m.giv_g, m.giv_y, m.giv_rho,
+                      m.giv_ld, m.snap};
+    if (m.giv_H && (m.k < 1 || m.k + 1 > kMaxCoef)) return hipErrorInvalidValue;
+    if (m.snap && !m.giv_H) return hipErrorInvalidValue;
     ProfScope ps(kProfMgs, s, m.step);
     if (m.tx == ABG_F64) {
         if (m.tv == ABG_F64) return mgs_dispatch<double, double>(d, s);

@@ -136,6 +136,14 @@ __device__ inline double gather_total(const double *slots, int G, double *lds, i
 // table k & 1, row i for <q, w_i>, row k for ||q||^2 after the sweep and row k + 1 for
 // ||q_k||^2 before it. Each rank clears its own column of the other table (rows up to
 // k + 2) for the next step; both tables start cleared.
+// The Givens update that follows Gram-Schmidt step k, done by the block of rank 0 once
+// h_{1..k+1,k} are known (H null: none).
+struct GivensDev {
+    double *H, *R, *cs, *sn, *g, *y, *rho;
+    int ld;
+    DevState *snap;     // host-visible copy of the scalars after the update (or null)
+};
+
 struct MgsDev {
     const void *q;
     const void *V;
@@ -152,7 +160,98 @@ struct MgsDev {
     double bd_rel;
     int step;
     double *q64;       // FP64 scratch of the streaming variant (vectors longer than kRegMaxL)
+    int set_beta;      // step 0 of a single solve: beta = ||r_0||, or the zero-rhs stop
+    GivensDev giv;
 };
+
+// One block of NT threads. Column k-1 of H has just been written by mgs; R holds the
+// rotated columns,
+// cs/sn the rotations, g the rotated right-hand side. Writes y_k (k entries) and, when
+// rho is given, rho = beta e_1 - H_k y_k.
+template <int NT = 64>
+__device__ inline void givens_step(double *H, int ld, double *R, double *cs, double *sn,
+                                   double *g, double *y, double *rho, double beta, int k,
+                                   DevState *st)
+{
+    __shared__ double gg[kMaxCoef];
+    __shared__ double ys[kMaxCoef];
+    const int lane = threadIdx.x;
+    const int j = k - 1;
+    double *Hc = H + (size_t)j * ld;
+    double *Rc = R + (size_t)j * ld;
+    const bool bd = st->bd_k == k;
+    for (int i = lane; i <= k; i += NT) Rc[i] = (i == k && bd) ? 0.0 : Hc[i];
+    __syncthreads();
+    if (lane == 0) {
+        for (int i = 0; i < j; ++i) {
+            const double a = Rc[i], b = Rc[i + 1];
+            Rc[i] = cs[i] * a + sn[i] * b;
+            Rc[i + 1] = -sn[i] * a + cs[i] * b;
+        }
+        const double a = Rc[j], b = Rc[k];
+        const double r = hypot(a, b);
+        double c = 1.0, s = 0.0;
+        if (r > 0.0) {
+            c = a / r;
+            s = b / r;
+        } else {
+            st->error |= 4;
+        }
+        cs[j] = c;
+        sn[j] = s;
+        Rc[j] = r;
+        Rc[k] = 0.0;
+        const double gj = g[j];
+        g[j] = c * gj;
+        g[k] = -s * gj;
+        st->ls = fabs(g[k]);
+        st->k = k;
+    }
+    __syncthreads();
+    for (int i = lane; i < k; i += NT) gg[i] = g[i];
+    __syncthreads();
+    for (int jj = k - 1; jj >= 0; --jj) {
+        const double yj = gg[jj] / R[(size_t)jj * ld + jj];
+        if (lane == 0) ys[jj] = yj;
+        for (int i = lane; i < jj; i += NT) gg[i] -= R[(size_t)jj * ld + i] * yj;
+        __syncthreads();
+    }
+    for (int i = lane; i < k; i += NT) y[i] = ys[i];
+    if (rho) {
+        for (int i = lane; i <= k; i += NT) {
+            double acc = (i == 0) ? beta : 0.0;
+            for (int jj = (i > 0 ? i - 1 : 0); jj < k; ++jj) acc -= H[(size_t)jj * ld + i] * ys[jj];
+            rho[i] = acc;
+        }
+    }
+}
+
+// After the normalisation, by the block of rank 0 of a single solve's launch: step 0
+// sets beta = ||r_0|| (or raises the zero-right-hand-side stop), step k >= 1 runs the
+// Givens update of column k, then copies the scalars to the host slot.
+__device__ inline void mgs_tail(const MgsDev &a, int rank)
+{
+    if (rank != 0) return;
+    DevState *st = a.st;
+    if (a.set_beta && threadIdx.x == 0 && !st->error) {
+        if (st->hnext == 0.0) {
+            st->stop = 1;
+            st->stop_k = 0;
+            st->stop_reason = kStopZero;
+        } else {
+            st->beta = st->hnext;
+        }
+    }
+    if (a.giv.H) {
+        __syncthreads();   // h_{1..k+1,k} and the breakdown flag, written by thread 0
+        const GivensDev &g = a.giv;
+        givens_step<kBlock>(g.H, g.ld, g.R, g.cs, g.sn, g.g, g.y, g.rho, st->beta, a.step, st);
+        if (g.snap) {
+            __syncthreads();
+            if (threadIdx.x == 0) *g.snap = *st;
+        }
+    }
+}
 
 // Rank r owns the E*kBlock consecutive elements from r*E*kBlock; register e of a lane
 // holds element base + e*kBlock, so every register is a coalesced wave access at a
@@ -363,65 +462,6 @@ __device__ inline void mgs_stream_body(const MgsDev &a, int rank, int G, double 
     }
 }
 
-// One wave. Column k-1 of H has just been written by mgs; R holds the rotated columns,
-// cs/sn the rotations, g the rotated right-hand side. Writes y_k (k entries) and, when
-// rho is given, rho = beta e_1 - H_k y_k.
-__device__ inline void givens_step(double *H, int ld, double *R, double *cs, double *sn,
-                                   double *g, double *y, double *rho, double beta, int k,
-                                   DevState *st)
-{
-    __shared__ double gg[kMaxCoef];
-    __shared__ double ys[kMaxCoef];
-    const int lane = threadIdx.x;
-    const int j = k - 1;
-    double *Hc = H + (size_t)j * ld;
-    double *Rc = R + (size_t)j * ld;
-    const bool bd = st->bd_k == k;
-    for (int i = lane; i <= k; i += 64) Rc[i] = (i == k && bd) ? 0.0 : Hc[i];
-    __syncthreads();
-    if (lane == 0) {
-        for (int i = 0; i < j; ++i) {
-            const double a = Rc[i], b = Rc[i + 1];
-            Rc[i] = cs[i] * a + sn[i] * b;
-            Rc[i + 1] = -sn[i] * a + cs[i] * b;
-        }
-        const double a = Rc[j], b = Rc[k];
-        const double r = hypot(a, b);
-        double c = 1.0, s = 0.0;
-        if (r > 0.0) {
-            c = a / r;
-            s = b / r;
-        } else {
-            st->error |= 4;
-        }
-        cs[j] = c;
-        sn[j] = s;
-        Rc[j] = r;
-        Rc[k] = 0.0;
-        const double gj = g[j];
-        g[j] = c * gj;
-        g[k] = -s * gj;
-        st->ls = fabs(g[k]);
-        st->k = k;
-    }
-    __syncthreads();
-    for (int i = lane; i < k; i += 64) gg[i] = g[i];
-    __syncthreads();
-    for (int jj = k - 1; jj >= 0; --jj) {
-        const double yj = gg[jj] / R[(size_t)jj * ld + jj];
-        if (lane == 0) ys[jj] = yj;
-        for (int i = lane; i < jj; i += 64) gg[i] -= R[(size_t)jj * ld + i] * yj;
-        __syncthreads();
-    }
-    for (int i = lane; i < k; i += 64) y[i] = ys[i];
-    if (rho) {
-        for (int i = lane; i <= k; i += 64) {
-            double acc = (i == 0) ? beta : 0.0;
-            for (int jj = (i > 0 ? i - 1 : 0); jj < k; ++jj) acc -= H[(size_t)jj * ld + i] * ys[jj];
-            rho[i] = acc;
-        }
-    }
-}
 
 }  // namespace
 }  // namespace abg

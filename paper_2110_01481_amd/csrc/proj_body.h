@@ -322,11 +322,16 @@ template <typename T, int AB = kAngBlock> struct BackLds {
 // parameters are fetched one round before their set-up, so neither waits on the memory
 // latency in the barrier-separated phases. The loads are branch-free (clamped addresses,
 // out-of-range bins zeroed when stored).
-template <typename T, bool ADJ, int AB = kAngBlock>
+//
+// PAD: instead of x, the tile goes to the forward projector's zero-padded row-major and
+// transposed copies xr, xc (row stride S, image column c at c + kPad; the padding must
+// already be zero), through LDS so that both writes are coalesced.
+template <typename T, bool ADJ, int AB = kAngBlock, bool PAD = false>
 __device__ inline void back_tile(const T *__restrict__ y, T *__restrict__ x,
                                  const AngleParams *__restrict__ ang, int N, int n_ang,
                                  int n_det, double ds, double s0, int c0, int r0,
-                                 BackLds<T, AB> &L)
+                                 BackLds<T, AB> &L, T *__restrict__ xr = nullptr,
+                                 T *__restrict__ xc = nullptr, int S = 0)
 {
     static_assert(AB <= kBackThreads, "one thread sets up one angle");
     constexpr int kIt = AB * kWin / kBackThreads;      // window entries per thread and round
@@ -430,9 +435,19 @@ __device__ inline void back_tile(const T *__restrict__ y, T *__restrict__ x,
             T sum = acc[j];
 #pragma unroll
             for (int v = 0; v < kBackWaves - 1; ++v) sum += L.part[v][pix];
+            const T val = ADJ ? sum : sum * T(1.0 / ds);
             const int c = c0 + tx, r = r0 + ty0 + 4 * j;
-            if (r < N && c < N) x[(size_t)r * N + c] = ADJ ? sum : sum * T(1.0 / ds);
+            if constexpr (PAD) L.part[0][pix] = val;   // the lane's own entry
+            else if (r < N && c < N) x[(size_t)r * N + c] = val;
         }
+    }
+    if constexpr (PAD) {
+        static_assert(kBackThreads == kTile * kTile, "one thread per pixel of the tile");
+        __syncthreads();
+        const int t = threadIdx.x, hi = t / kTile, lo = t % kTile;
+        // xr: 16 lanes write 16 consecutive columns of a row; xc: of a column
+        if (r0 + hi < N && c0 + lo < N) xr[(size_t)(r0 + hi) * S + kPad + c0 + lo] = L.part[0][hi * kTile + lo];
+        if (c0 + hi < N && r0 + lo < N) xc[(size_t)(c0 + hi) * S + kPad + r0 + lo] = L.part[0][lo * kTile + hi];
     }
     __syncthreads();
 }

@@ -13,7 +13,8 @@
 //           four waves split the angles. For a round of 64 angles the tile's detector
 //           footprint (at most 32 bins per angle) is staged in LDS; every pixel then
 //           reads its two taps per angle from LDS, and the four wave partials are summed
-//           in a fixed order at the end.
+//           in a fixed order at the end. Its output can go straight into the forward
+//           projector's padded copies (AB-GMRES applies A right after B).
 #include <hip/hip_ext.h>
 
 #include "proj_body.h"
@@ -55,17 +56,21 @@ __global__ __launch_bounds__(kFwdBlock) void forward_kernel(
 // (measured faster than 128 on large images, equal on small ones).
 constexpr int kSingleAngBlock = 64;
 
-template <typename T, bool ADJ>
+// PAD: x is the forward projector's scratch (padded copies written directly).
+template <typename T, bool ADJ, bool PAD>
 __global__ __launch_bounds__(kBackThreads) void back_kernel(
     const T *__restrict__ y, T *__restrict__ x, const AngleParams *__restrict__ ang, int N,
     int n_ang, int n_det, double ds, double s0, const DevState *st, int k)
 {
     __shared__ BackLds<T, kSingleAngBlock> lds;
     if (halted(st, k)) return;
-    back_tile<T, ADJ, kSingleAngBlock>(y, x, ang, N, n_ang, n_det, ds, s0, blockIdx.x * kTile,
-                                       blockIdx.y * kTile, lds);
+    const int S = N + 2 * kPad;
+    back_tile<T, ADJ, kSingleAngBlock, PAD>(y, x, ang, N, n_ang, n_det, ds, s0,
+                                            blockIdx.x * kTile, blockIdx.y * kTile, lds, x,
+                                            x + (size_t)N * S, S);
 }
 
+// x == nullptr: the padded copies in ws already hold the input.
 template <typename T>
 hipError_t forward_t(const Geometry &g, const void *x, void *y, void *ws, hipStream_t s,
                      const DevState *st, int k, bool pads_zero)
@@ -73,11 +78,13 @@ hipError_t forward_t(const Geometry &g, const void *x, void *y, void *ws, hipStr
     const int N = g.N, S = g.padded_stride();
     T *xr = static_cast<T *>(ws);
     T *xc = xr + (size_t)N * S;
-    dim3 tgrid((N + 31) / 32, (N + 31) / 32);
-    pad_transpose_kernel<T><<<tgrid, 256, 0, s>>>(static_cast<const T *>(x), xr, xc, N, S, st, k);
-    if (!pads_zero) {
-        const int npad = 2 * N * 2 * kPad;
-        pad_zero_kernel<T><<<(npad + 255) / 256, 256, 0, s>>>(xr, xc, N, S, st, k);
+    if (x) {
+        dim3 tgrid((N + 31) / 32, (N + 31) / 32);
+        pad_transpose_kernel<T><<<tgrid, 256, 0, s>>>(static_cast<const T *>(x), xr, xc, N, S, st, k);
+        if (!pads_zero) {
+            const int npad = 2 * N * 2 * kPad;
+            pad_zero_kernel<T><<<(npad + 255) / 256, 256, 0, s>>>(xr, xc, N, S, st, k);
+        }
     }
     dim3 grid((g.n_det + kFwdBlock - 1) / kFwdBlock, g.n_ang);
     const double s0 = -0.5 * (g.n_det - 1) * g.ds;
@@ -91,7 +98,7 @@ hipError_t forward_t(const Geometry &g, const void *x, void *y, void *ws, hipStr
     return hipGetLastError();
 }
 
-template <typename T>
+template <typename T, bool PAD>
 hipError_t back_t(const Geometry &g, int kind, const void *y, void *x, hipStream_t s,
                   const DevState *st, int k)
 {
@@ -99,12 +106,12 @@ hipError_t back_t(const Geometry &g, int kind, const void *y, void *x, hipStream
     const double s0 = -0.5 * (g.n_det - 1) * g.ds;
     ProfScope ps(kProfBack, s, st ? k : 0, true);
     if (kind == ABG_BP_ADJ)
-        hipExtLaunchKernelGGL(back_kernel<T, true>, grid, dim3(kBackThreads), 0, s, ps.e0, ps.e1,
-                              0, static_cast<const T *>(y), static_cast<T *>(x),
+        hipExtLaunchKernelGGL(back_kernel<T, true, PAD>, grid, dim3(kBackThreads), 0, s, ps.e0,
+                              ps.e1, 0, static_cast<const T *>(y), static_cast<T *>(x),
                               (const AngleParams *)g.dev, g.N, g.n_ang, g.n_det, g.ds, s0, st, k);
     else
-        hipExtLaunchKernelGGL(back_kernel<T, false>, grid, dim3(kBackThreads), 0, s, ps.e0, ps.e1,
-                              0, static_cast<const T *>(y), static_cast<T *>(x),
+        hipExtLaunchKernelGGL(back_kernel<T, false, PAD>, grid, dim3(kBackThreads), 0, s, ps.e0,
+                              ps.e1, 0, static_cast<const T *>(y), static_cast<T *>(x),
                               (const AngleParams *)g.dev, g.N, g.n_ang, g.n_det, g.ds, s0, st, k);
     return hipGetLastError();
 }
@@ -126,8 +133,22 @@ hipError_t launch_forward(const Geometry &g, int dtype, const void *x, void *y, 
 hipError_t launch_back(const Geometry &g, int kind, int dtype, const void *y, void *x,
                        hipStream_t s, const DevState *st, int k)
 {
-    return dtype == ABG_F64 ? back_t<double>(g, kind, y, x, s, st, k)
-                            : back_t<float>(g, kind, y, x, s, st, k);
+    return dtype == ABG_F64 ? back_t<double, false>(g, kind, y, x, s, st, k)
+                            : back_t<float, false>(g, kind, y, x, s, st, k);
+}
+
+hipError_t launch_back_staged(const Geometry &g, int kind, int dtype, const void *y, void *ws,
+                              hipStream_t s, const DevState *st, int k)
+{
+    return dtype == ABG_F64 ? back_t<double, true>(g, kind, y, ws, s, st, k)
+                            : back_t<float, true>(g, kind, y, ws, s, st, k);
+}
+
+hipError_t launch_forward_staged(const Geometry &g, int dtype, void *y, void *ws, hipStream_t s,
+                                 const DevState *st, int k)
+{
+    return dtype == ABG_F64 ? forward_t<double>(g, nullptr, y, ws, s, st, k, true)
+                            : forward_t<float>(g, nullptr, y, ws, s, st, k, true);
 }
 
 }  // namespace abg

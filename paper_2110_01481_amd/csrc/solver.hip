@@ -227,6 +227,22 @@ struct Solve {
         return M;
     }
 
+    // Gram-Schmidt of step k followed by its Givens update in the same launch
+    MgsLaunch mgs_givens_args(const void *qin, int k, DevState *snap) const
+    {
+        MgsLaunch M = mgs_args(qin, k);
+        M.giv_H = H;
+        M.giv_R = R;
+        M.giv_cs = cs;
+        M.giv_sn = sn;
+        M.giv_g = gv;
+        M.giv_y = ycol(k);
+        M.giv_rho = (method == ABG_METHOD_AB && need_res) ? rho : nullptr;
+        M.giv_ld = ld;
+        M.snap = snap;
+        return M;
+    }
+
     // All kernels of Arnoldi step k, then a copy of the scalars into slot k.
     int enqueue_step(int k)
     {
@@ -235,16 +251,14 @@ struct Solve {
             RC(fwd(cur, z, dst, k));
             RC(back(z, q, dst, k));
         } else {
-            RC(back(cur, tn, dst, k));
-            RC(fwd(tn, q, dst, k));
+            // t = B w_k lands directly in the forward projector's padded copies
+            CK(launch_back_staged(g, kind, p.proj, cur, fpws, s, dst, k));
+            CK(launch_forward_staged(g, p.proj, q, fpws, s, dst, k));
         }
-        CK(launch_mgs(mgs_args(q, k), s));
         // the step's last kernel copies the scalars into host slot k
         DevState *snap = hr.dslots + k;
         const bool ncp_stop = st.kind == ABG_STOP_NCP;
-        CK(launch_givens(H, ld, R, cs, sn, gv, ycol(k),
-                         (method == ABG_METHOD_AB && need_res) ? rho : nullptr, &dst->beta, k,
-                         dst, s, need_res ? nullptr : snap));
+        CK(launch_mgs(mgs_givens_args(q, k, need_res ? nullptr : snap), s));
         if (need_res) {
             DevState *csnap = ncp_stop ? nullptr : snap;
             if (method == ABG_METHOD_BA)
@@ -333,7 +347,9 @@ struct Solve {
             RC(back(rb0, q));
             r0 = q;
         }
-        CK(launch_mgs(mgs_args(r0, 0), s));
+        MgsLaunch M0 = mgs_args(r0, 0);
+        M0.set_beta = init != nullptr;
+        CK(launch_mgs(M0, s));
         return ABG_OK;
     }
 };
@@ -439,7 +455,6 @@ int run_solver(const Geometry &g, int method, int kind, const void *b, const voi
     // b - A x0, r0 = (B)(b - A x0), beta = ||r0|| into g[0], w_1; the host learns beta
     // (and a zero right-hand side or a NaN) from the scalars of step 1
     RC(S.init_async(b, x0, &init));
-    CK(launch_set_beta(S.dst, s));
     DevState hs;
     bool zero_rhs = false;
     {
