@@ -18,11 +18,11 @@ constexpr double kEdgeTie = 1e-9;
 template <typename T> __device__ inline T edge_tie();
 template <> __device__ inline double edge_tie<double>() { return 1e-9; }
 template <> __device__ inline float edge_tie<float>() { return 2e-5f; }
-// back projector: a 16 x 16 pixel tile per block, 4 pixels per lane, the 4 waves
+// back projector: a 16 x 16 pixel tile per block, 4 pixels per lane, the 8 waves
 // splitting the angles; the tile's detector footprint for a block of angles (64 or 128) is staged per
 // round (at most 30 bins per angle for det_spacing >= 0.75, plus margins)
 constexpr int kTile = 16;
-constexpr int kBackWaves = 4;
+constexpr int kBackWaves = 8;
 constexpr int kBackThreads = 64 * kBackWaves;
 constexpr int kPixPerLane = kTile * kTile / 64;
 constexpr int kAngBlock = 128;
@@ -420,7 +420,7 @@ __device__ inline void back_tile(const T *__restrict__ y, T *__restrict__ x,
                 acc[j] += back_tap<T, ADJ>(L.win[t], fma(T(j), P.su4, u0), P, dsT);
         }
     }
-    // fixed-order sum of the four waves' partials
+    // fixed-order sum of the waves' partials
     __syncthreads();                                   // the window space becomes part
 #pragma unroll
     for (int j = 0; j < kPixPerLane; ++j) {
@@ -442,12 +442,14 @@ __device__ inline void back_tile(const T *__restrict__ y, T *__restrict__ x,
         }
     }
     if constexpr (PAD) {
-        static_assert(kBackThreads == kTile * kTile, "one thread per pixel of the tile");
+        static_assert(kBackThreads >= kTile * kTile, "one thread per pixel of the tile");
         __syncthreads();
         const int t = threadIdx.x, hi = t / kTile, lo = t % kTile;
         // xr: 16 lanes write 16 consecutive columns of a row; xc: of a column
-        if (r0 + hi < N && c0 + lo < N) xr[(size_t)(r0 + hi) * S + kPad + c0 + lo] = L.part[0][hi * kTile + lo];
-        if (c0 + hi < N && r0 + lo < N) xc[(size_t)(c0 + hi) * S + kPad + r0 + lo] = L.part[0][lo * kTile + hi];
+        if (t < kTile * kTile) {
+            if (r0 + hi < N && c0 + lo < N) xr[(size_t)(r0 + hi) * S + kPad + c0 + lo] = L.part[0][hi * kTile + lo];
+            if (c0 + hi < N && r0 + lo < N) xc[(size_t)(c0 + hi) * S + kPad + r0 + lo] = L.part[0][lo * kTile + hi];
+        }
     }
     __syncthreads();
 }

@@ -10,9 +10,9 @@
 //           copy, both zero-padded so that no per-tap bounds test is needed.
 //  back     x = B y (unmatched, linear interpolation on the detector) or x = A^T y,
 //           pixel-driven: a block owns a 16 x 16 tile, each lane 4 of its pixels, and the
-//           four waves split the angles. For a round of 64 angles the tile's detector
+//           eight waves split the angles. For a round of 64 angles the tile's detector
 //           footprint (at most 32 bins per angle) is staged in LDS; every pixel then
-//           reads its two taps per angle from LDS, and the four wave partials are summed
+//           reads its two taps per angle from LDS, and the eight wave partials are summed
 //           in a fixed order at the end. Its output can go straight into the forward
 //           projector's padded copies (AB-GMRES applies A right after B).
 #include <hip/hip_ext.h>
@@ -57,8 +57,12 @@ __global__ __launch_bounds__(kFwdBlock) void forward_kernel(
 constexpr int kSingleAngBlock = 64;
 
 // PAD: x is the forward projector's scratch (padded copies written directly).
+// FP32: at most 64 VGPRs, so that four blocks (eight waves per SIMD) share a CU
+template <typename T> constexpr int kBackMinWaves = 1;
+template <> constexpr int kBackMinWaves<float> = 8;
+
 template <typename T, bool ADJ, bool PAD>
-__global__ __launch_bounds__(kBackThreads) void back_kernel(
+__global__ __launch_bounds__(kBackThreads, kBackMinWaves<T>) void back_kernel(
     const T *__restrict__ y, T *__restrict__ x, const AngleParams *__restrict__ ang, int N,
     int n_ang, int n_det, double ds, double s0, const DevState *st, int k)
 {
