@@ -31,8 +31,8 @@ import workloads as W  # noqa: E402
 HBM_PEAK_GBPS = 8000.0
 COUNTERS_SUMMARY = os.path.join(ROOT, "profiles", "forward_kernel_512x512_720x725_counters.md")
 # sources whose change invalidates the stored counter readings of the forward projector
-FORWARD_SOURCES = ["paper_2110_01481_amd/csrc/proj_body.h", "paper_2110_01481_amd/csrc/projectors.hip",
-                   "paper_2110_01481_amd/csrc/abg_internal.h"]
+FORWARD_SOURCES = ["paper_2110_01481_amd/csrc/fwd_body.h", "paper_2110_01481_amd/csrc/geometry.h",
+                   "paper_2110_01481_amd/csrc/projectors.hip"]
 
 
 def forward_source_hash() -> str:
@@ -146,12 +146,44 @@ def line_model_nnz(N: int, theta_deg: np.ndarray, n_det: int, ds: float = 1.0) -
     return int(round(total))
 
 
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _stream_kernel_stats(ms_total, launches, bytes_total, reductions=None):
+    """Achieved HBM rate of a bandwidth-bound kernel from its algorithmic bytes."""
+    if not launches or ms_total <= 0:
+        return None
+    out = {"launches": launches, "avg_us": round(1e3 * ms_total / launches, 2),
+           "alg_bytes_per_launch": int(bytes_total / launches),
+           "GBps": round(bytes_total / (ms_total * 1e-3) / 1e9, 1)}
+    out["frac_hbm"] = round(out["GBps"] / HBM_PEAK_GBPS, 4)
+    if reductions:
+        out["grid_reductions"] = reductions
+        out["us_per_reduction_upper"] = round(1e3 * ms_total / reductions, 2)
+    return out
+
+
 def cpu_oracle_baseline(w, b_np, enorm, budget_s=15.0, max_iters=10):
     """Times the FP64 oracle's AB-GMRES (unmatched pair) on the same workload for as
     many Arnoldi iterations as fit in ~budget_s seconds."""
     import oracle as O
     from oracle.core import num_threads
     g = O.Geometry(w.N, w.n_ang, w.n_det)
+    # one A and one B apply of the oracle's C projectors, for the per-apply figures
+    t0 = time.perf_counter()
+    ya = g.A(np.ones(g.n))
+    t_a = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    g.B_hat(ya)
+    t_b = time.perf_counter() - t0
     k = 1
     t_used = 0.0
     # grow the iteration count until the budget is used (each run starts from scratch)
@@ -162,7 +194,8 @@ def cpu_oracle_baseline(w, b_np, enorm, budget_s=15.0, max_iters=10):
         t_used += dt
         if dt * 2.2 > budget_s or k >= max_iters:
             return {"value": k / dt, "unit": "GMRES iters/s", "cores": num_threads(),
-                    "kind": "oracle",
+                    "kind": "oracle", "A_apply_s": round(t_a, 4), "B_apply_s": round(t_b, 4),
+                    "host_cpu": _cpu_model(),
                     "sample": f"FP64 oracle AB-GMRES, {k} Arnoldi iterations from x0=0 on the "
                               f"{w.N}^2 / {w.n_ang}x{w.n_det} workload (literal x_k and b-Ax_k "
                               f"each step), {dt:.2f} s; host {os.cpu_count()} logical CPUs"}
@@ -432,6 +465,27 @@ def main():
         "k_done": {m: last[m].k_done for m in methods},
         "n_literal": {m: last[m].n_literal for m in methods},
     }
+    # Gram-Schmidt and basis GEMVs: algorithmic HBM bytes of the counted launches. Step j
+    # (0..k_done) of a solve reads q and w_1..w_j, writes w_{j+1} and its copy; the DP
+    # residual of step j reads j (BA: Z, plus rb0) or j+1 (AB: W) vectors of m and writes
+    # one; forming the iterate reads k_done basis vectors. Counted launches are those of
+    # steps up to each solve's last (k_done).
+    sv = {"f64": 8, "f32": 4, "bf16": 2}[args.basis]
+    mgs_bytes = comb_bytes = 0
+    red = 0
+    for m in methods:
+        L = w.m if m == "ab" else w.n
+        kd = last[m].k_done
+        for j in range(kd + 1):
+            mgs_bytes += j * L * sv + L * sv + 2 * L * 4
+            red += j + 1
+        for j in range(1, kd + 1):
+            comb_bytes += ((j + 1) * w.m * 4 + w.m * 4) if m == "ba" else ((j + 1) * w.m * sv + w.m * 4)
+        # forming the returned iterate: x = W y (BA) or t = W y (AB, before B)
+        comb_bytes += kd * L * sv + L * 4
+    extra["mgs"] = _stream_kernel_stats(mgs_ms, mgs_n, mgs_bytes * args.steps, red * args.steps)
+    comb_n, comb_ms = prof["combine"]
+    extra["combine"] = _stream_kernel_stats(comb_ms, comb_n, comb_bytes * args.steps)
 
     if not args.no_fp64:
         b64bufs = {m: make(m, b64, "f64") for m in methods}

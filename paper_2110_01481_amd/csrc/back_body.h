@@ -1,0 +1,228 @@
+// Device code of the pixel-driven back projectors (linear interpolation B, and the
+// line-model transpose A^T), shared by the single-problem kernels (projectors.hip) and the
+// batched kernels (batch.hip), so that both run the same arithmetic.
+#pragma once
+
+#include <cmath>
+
+#include "abg_internal.h"
+
+namespace abg {
+namespace {
+
+// An axis-aligned ray lies on a pixel edge when its offset from the edge is below this
+// (in pixels); FP32 back projection evaluates offsets with ~4e-6 error.
+template <typename T> __device__ inline T edge_tie();
+template <> __device__ inline double edge_tie<double>() { return 1e-9; }
+template <> __device__ inline float edge_tie<float>() { return 2e-5f; }
+
+// back projector: a 16 x 16 pixel tile per block, 4 pixels per lane, the 8 waves
+// splitting the angles; the tile's detector footprint for a block of angles (64 or 128)
+// is staged per round (at most 30 bins per angle for det_spacing >= 0.75, plus margins)
+constexpr int kTile = 16;
+constexpr int kBackWaves = 8;
+constexpr int kBackThreads = 64 * kBackWaves;
+constexpr int kPixPerLane = kTile * kTile / 64;
+constexpr int kAngBlock = 128;
+constexpr int kWin = 32;
+
+// Per staged angle: position of the tile's reference pixel in the window (f), the
+// change of u per pixel step (cu, su), the window's first bin, and the line-model
+// trapezoid of the matched back projector.
+template <typename T>
+struct alignas(16) BackStage {
+    T f, cu, su, su4;   // su4 = 4 su, the step between a lane's pixel rows
+    T invp, half, invpq;
+    int axis;
+};
+
+// Length of a ray at offset |t| from a unit pixel's centre projection (the trapezoid of
+// the line model); on an axis-aligned ray at exactly |t| = 1/2 the two pixels share it.
+template <typename T>
+__device__ inline T trapezoid(T at, const BackStage<T> &P)
+{
+    if (P.axis) {
+        if (fabs(at - T(0.5)) <= edge_tie<T>()) return T(0.5) * P.invp;
+        return at < T(0.5) ? P.invp : T(0);
+    }
+    return fmin(P.invp, fmax(T(0), (P.half - at) * P.invpq));
+}
+
+template <typename T> __device__ inline T fract_of(T u);
+template <> __device__ inline float fract_of<float>(float u) { return __builtin_amdgcn_fractf(u); }
+template <> __device__ inline double fract_of<double>(double u) { return __builtin_amdgcn_fract(u); }
+
+// Staged window entry: the bin's value and the difference to the next bin.
+template <typename T> struct alignas(2 * sizeof(T)) BinPair {
+    T v, d;
+};
+
+// One pixel's contribution at detector coordinate u (window-relative). The window starts
+// at least one bin below the tile's smallest u, and a 16 x 16 tile spans at most
+// 15 sqrt(2) / ds < 28.3 bins for ds >= 0.75 (the smallest spacing a geometry accepts),
+// so 1 <= u < 30.3 up to rounding: truncation is floor and k <= kWin - 2.
+template <typename T, bool ADJ>
+__device__ inline T back_tap(const BinPair<T> *wrow, T u, const BackStage<T> &P, T dsT)
+{
+    const T w = fract_of(u);
+    const int k = (int)u;
+    const BinPair<T> b = wrow[k];
+    if (!ADJ) return fma(w, b.d, b.v);
+    return trapezoid(w * dsT, P) * b.v + trapezoid((T(1) - w) * dsT, P) * (b.v + b.d);
+}
+
+// LDS of one back-projection block (declared by the calling kernel, so that a kernel
+// serving both back projectors holds one copy). AB angles are staged per round; the
+// per-angle set-up is double-buffered (round r is computed while round r + 1's is
+// written); the waves' partial sums reuse the window's space at the end of a tile.
+template <typename T, int AB = kAngBlock> struct BackLds {
+    union {
+        BinPair<T> win[AB][kWin];
+        T part[kBackWaves - 1][kTile * kTile];
+    };
+    BackStage<T> prm[2][AB];
+    int ib[2][AB];      // first bin of each angle's window
+};
+
+// The 16 x 16 tile with first column c0 and first row r0, by one block of kBackThreads.
+// Starts and ends with a block-wide barrier, so consecutive calls may share the LDS.
+//
+// Software pipeline over rounds of AB angles: the sinogram loads of round r + 1's windows
+// are issued before round r is computed and land in LDS after it, and the angle
+// parameters are fetched one round before their set-up, so neither waits on the memory
+// latency in the barrier-separated phases. The loads are branch-free (clamped addresses,
+// out-of-range bins zeroed when stored).
+//
+// PAD: instead of x, the tile goes to the forward projector's zero-padded row-major and
+// transposed copies xr, xc (row stride S, image column c at c + kPad; the padding must
+// already be zero), through LDS so that both writes are coalesced.
+template <typename T, bool ADJ, int AB = kAngBlock, bool PAD = false>
+__device__ inline void back_tile(const T *__restrict__ y, T *__restrict__ x,
+                                 const AngleParams *__restrict__ ang, int N, int n_ang,
+                                 int n_det, double ds, double s0, int c0, int r0,
+                                 BackLds<T, AB> &L, T *__restrict__ xr = nullptr,
+                                 T *__restrict__ xc = nullptr, int S = 0)
+{
+    static_assert(AB <= kBackThreads, "one thread sets up one angle");
+    constexpr int kIt = AB * kWin / kBackThreads;      // window entries per thread and round
+    constexpr int kRowsPer = kBackThreads / kWin;      // angles covered by one pass
+    static_assert(kIt * kBackThreads == AB * kWin && 2 * kIt <= 32, "window split");
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    // lane owns pixels (tx, ty0 + 4j), j = 0..3, of the 16 x 16 tile
+    const int tx = lane & 15, ty0 = lane >> 4;
+    const double xref = c0 - 0.5 * N + 0.5, yref = r0 - 0.5 * N + 0.5;
+    const double s0u = s0 / ds;
+    const T ftx = T(tx), fty = T(ty0);
+    const T dsT = T(ds);
+    const int n_rounds = (n_ang + AB - 1) / AB;
+    const int kk = threadIdx.x % kWin;                 // this thread's window column
+
+    AngleParams Pn;                                    // parameters of the next set-up
+    auto fetch = [&](int r) { Pn = ang[min(r * AB + (int)threadIdx.x, n_ang - 1)]; };
+    auto setup = [&](int r) {
+        if ((int)threadIdx.x < min(AB, n_ang - r * AB)) {
+            const double uref = fma(xref, Pn.cu, fma(yref, Pn.su, -s0u));
+            const double umin = uref + (kTile - 1) * (fmin(Pn.cu, 0.0) + fmin(Pn.su, 0.0));
+            const double ib = floor(umin) - 1.0;
+            BackStage<T> st;
+            st.f = T(uref - ib);
+            st.cu = T(Pn.cu);
+            st.su = T(Pn.su);
+            st.su4 = T(4.0 * Pn.su);
+            st.invp = T(Pn.len);
+            st.half = T(Pn.half);
+            st.invpq = T(Pn.invpq);
+            st.axis = Pn.axis;
+            L.prm[r & 1][threadIdx.x] = st;
+            L.ib[r & 1][threadIdx.x] = (int)ib;
+        }
+    };
+    T w0[kIt], w1[kIt];
+    unsigned live = 0;                                 // in-range bits of w0 / w1
+    auto load = [&](int r) {
+        const int a0 = r * AB, last = min(AB, n_ang - a0) - 1;
+        live = 0;
+#pragma unroll
+        for (int j = 0; j < kIt; ++j) {
+            const int t = min((int)threadIdx.x / kWin + j * kRowsPer, last);
+            const int bin = L.ib[r & 1][t] + kk;
+            const T *row = y + (size_t)(a0 + t) * n_det;
+            w0[j] = row[min(max(bin, 0), n_det - 1)];
+            w1[j] = row[min(max(bin + 1, 0), n_det - 1)];
+            live |= (unsigned)(bin >= 0 && bin < n_det) << (2 * j);
+            live |= (unsigned)(bin + 1 >= 0 && bin + 1 < n_det) << (2 * j + 1);
+        }
+    };
+    auto store = [&]() {
+#pragma unroll
+        for (int j = 0; j < kIt; ++j) {
+            const T v0 = (live >> (2 * j)) & 1u ? w0[j] : T(0);
+            const T v1 = (live >> (2 * j + 1)) & 1u ? w1[j] : T(0);
+            L.win[(int)threadIdx.x / kWin + j * kRowsPer][kk] = BinPair<T>{v0, v1 - v0};
+        }
+    };
+
+    T acc[kPixPerLane] = {};
+    __syncthreads();                                   // the previous tile is done with the LDS
+    fetch(0);
+    setup(0);
+    if (n_rounds > 1) fetch(1);
+    __syncthreads();
+    load(0);
+    for (int r = 0; r < n_rounds; ++r) {
+        const int na = min(AB, n_ang - r * AB);
+        __syncthreads();                               // round r - 1 is done with win, prm
+        store();
+        if (r + 1 < n_rounds) {
+            setup(r + 1);
+            if (r + 2 < n_rounds) fetch(r + 2);
+        }
+        __syncthreads();                               // window r, set-up r + 1 visible
+        if (r + 1 < n_rounds) load(r + 1);
+        // the block's waves take interleaved angles of the round
+        for (int t = wave; t < na; t += kBackWaves) {
+            const BackStage<T> P = L.prm[r & 1][t];
+            const T u0 = fma(ftx, P.cu, fma(fty, P.su, P.f));
+            acc[0] += back_tap<T, ADJ>(L.win[t], u0, P, dsT);
+#pragma unroll
+            for (int j = 1; j < kPixPerLane; ++j)
+                acc[j] += back_tap<T, ADJ>(L.win[t], fma(T(j), P.su4, u0), P, dsT);
+        }
+    }
+    // fixed-order sum of the waves' partials
+    __syncthreads();                                   // the window space becomes part
+#pragma unroll
+    for (int j = 0; j < kPixPerLane; ++j) {
+        const int pix = (ty0 + 4 * j) * kTile + tx;
+        if (wave > 0) L.part[wave - 1][pix] = acc[j];
+    }
+    __syncthreads();
+    if (wave == 0) {
+#pragma unroll
+        for (int j = 0; j < kPixPerLane; ++j) {
+            const int pix = (ty0 + 4 * j) * kTile + tx;
+            T sum = acc[j];
+#pragma unroll
+            for (int v = 0; v < kBackWaves - 1; ++v) sum += L.part[v][pix];
+            const T val = ADJ ? sum : sum * T(1.0 / ds);
+            const int c = c0 + tx, r = r0 + ty0 + 4 * j;
+            if constexpr (PAD) L.part[0][pix] = val;   // the lane's own entry
+            else if (r < N && c < N) x[(size_t)r * N + c] = val;
+        }
+    }
+    if constexpr (PAD) {
+        static_assert(kBackThreads >= kTile * kTile, "one thread per pixel of the tile");
+        __syncthreads();
+        const int t = threadIdx.x, hi = t / kTile, lo = t % kTile;
+        // xr: 16 lanes write 16 consecutive columns of a row; xc: of a column
+        if (t < kTile * kTile) {
+            if (r0 + hi < N && c0 + lo < N) xr[(size_t)(r0 + hi) * S + kPad + c0 + lo] = L.part[0][hi * kTile + lo];
+            if (c0 + hi < N && r0 + lo < N) xc[(size_t)(c0 + hi) * S + kPad + r0 + lo] = L.part[0][lo * kTile + hi];
+        }
+    }
+    __syncthreads();
+}
+
+}  // namespace
+}  // namespace abg

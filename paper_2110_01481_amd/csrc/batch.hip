@@ -410,9 +410,14 @@ __global__ __launch_bounds__(64) void bgivens_kernel(const BatchInst *__restrict
     const int k = st->kcur;
     if (halted(st, k)) return;
     double *rho = (d.method == ABG_METHOD_AB && d.need_res) ? gfield<double>(d.rho) : nullptr;
-    givens_step(gfield<double>(d.H), d.ld, gfield<double>(d.R), gfield<double>(d.cs),
-                gfield<double>(d.sn), gfield<double>(d.g),
-                gfield<double>(d.Y) + (size_t)(k - 1) * d.k_max, rho, st->beta, k, st);
+    if (k <= kWaveGivensMax)
+        givens_wave(gfield<double>(d.H), d.ld, gfield<double>(d.R), gfield<double>(d.cs),
+                    gfield<double>(d.sn), gfield<double>(d.g),
+                    gfield<double>(d.Y) + (size_t)(k - 1) * d.k_max, rho, st->beta, k, st);
+    else
+        givens_step(gfield<double>(d.H), d.ld, gfield<double>(d.R), gfield<double>(d.cs),
+                    gfield<double>(d.sn), gfield<double>(d.g),
+                    gfield<double>(d.Y) + (size_t)(k - 1) * d.k_max, rho, st->beta, k, st);
 }
 
 // ||r_k|| by chunks: BA r = (b - A x0) - Z y_k, AB r = W_{k+1} rho. Each chunk's sum of

@@ -313,11 +313,13 @@ __global__ __launch_bounds__(64) void givens_kernel(double *H, int ld, double *R
         if (snap && threadIdx.x == 0) *snap = *st;
         return;
     }
-    givens_step(H, ld, R, cs, sn, g, y, rho, *beta, k, st);
-    if (snap) {
+    if (k <= kWaveGivensMax) {
+        givens_wave(H, ld, R, cs, sn, g, y, rho, *beta, k, st);
+    } else {
+        givens_step(H, ld, R, cs, sn, g, y, rho, *beta, k, st);
         __syncthreads();
-        if (threadIdx.x == 0) *snap = *st;
     }
+    if (snap && threadIdx.x == 0) *snap = *st;
 }
 
 // After the initial normalisation: beta = ||r_0|| for the later steps, or (r_0 = 0) the

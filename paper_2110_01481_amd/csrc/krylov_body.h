@@ -226,6 +226,97 @@ __device__ inline void givens_step(double *H, int ld, double *R, double *cs, dou
     }
 }
 
+// Value of a double held by lane l of the wave (l uniform).
+__device__ inline double readlane_d(double v, int l)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Largest step that givens_wave takes (rows 0..k of the new column, one per lane).
+constexpr int kWaveGivensMax = 63;
+
+// givens_step for k <= kWaveGivensMax by the first wave of the block (lanes 0..63): the
+// new column, the previous rotations and g are held one entry per lane and scalars move
+// between lanes by readlane, so the sequential parts (applying the rotations, the back
+// substitution) run from registers; the columns of R are fetched eight at a time. Same
+// arithmetic, in the same order, as givens_step. Lane 0 writes the scalars.
+__device__ inline void givens_wave(double *H, int ld, double *R, double *cs, double *sn,
+                                   double *g, double *y, double *rho, double beta, int k,
+                                   DevState *st)
+{
+    const int lane = threadIdx.x & 63;
+    const int j = k - 1;
+    const double *Hc = H + (size_t)j * ld;
+    double *Rc = R + (size_t)j * ld;
+    const bool bd = st->bd_k == k;
+    const double hv = lane <= k ? ((lane == k && bd) ? 0.0 : Hc[lane]) : 0.0;
+    const double cv = lane < j ? cs[lane] : 0.0;
+    const double sv = lane < j ? sn[lane] : 0.0;
+    double gl = lane < k ? g[lane] : 0.0;
+    // rotations 0..j-1 applied to the column: t carries entry i+1 down the column
+    double t = readlane_d(hv, 0);
+    double rv = 0.0;   // this lane's entry of the rotated column
+    for (int i = 0; i < j; ++i) {
+        const double a = t, b = readlane_d(hv, i + 1);
+        const double ci = readlane_d(cv, i), si = readlane_d(sv, i);
+        const double o = ci * a + si * b;
+        t = -si * a + ci * b;
+        if (lane == i) rv = o;
+    }
+    const double a = t, b = readlane_d(hv, k);
+    const double r = hypot(a, b);
+    double c = 1.0, s = 0.0;
+    if (r > 0.0) {
+        c = a / r;
+        s = b / r;
+    } else if (lane == 0) {
+        st->error |= 4;
+    }
+    if (lane == j) rv = r;
+    if (lane < k) Rc[lane] = rv;
+    if (lane == k) Rc[k] = 0.0;
+    const double gj = readlane_d(gl, j);
+    if (lane == 0) {
+        cs[j] = c;
+        sn[j] = s;
+        g[j] = c * gj;
+        g[k] = -s * gj;
+        st->ls = fabs(-s * gj);
+        st->k = k;
+    }
+    if (lane == j) gl = c * gj;
+    // back substitution R_k y = g[0..k), column by column from the last
+    double yv = 0.0;   // y[lane]
+    for (int jb = j; jb >= 0; jb -= 8) {
+        double col[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int jj = jb - u;
+            col[u] = jj < 0 ? 0.0 : (jj == j ? rv : (lane <= jj ? R[(size_t)jj * ld + lane] : 0.0));
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int jj = jb - u;
+            if (jj < 0) break;
+            const double yj = readlane_d(gl, jj) / readlane_d(col[u], jj);
+            if (lane == jj) yv = yj;
+            if (lane < jj) gl -= col[u] * yj;
+        }
+    }
+    if (lane < k) y[lane] = yv;
+    if (rho) {
+        double acc = lane == 0 ? beta : 0.0;
+        for (int jj = 0; jj < k; ++jj) {
+            const double yj = readlane_d(yv, jj);
+            if (lane <= k && jj >= lane - 1) acc -= H[(size_t)jj * ld + lane] * yj;
+        }
+        if (lane <= k) rho[lane] = acc;
+    }
+}
+
 // After the normalisation, by the block of rank 0 of a single solve's launch: step 0
 // sets beta = ||r_0|| (or raises the zero-right-hand-side stop), step k >= 1 runs the
 // Givens update of column k, then copies the scalars to the host slot.
@@ -245,11 +336,15 @@ __device__ inline void mgs_tail(const MgsDev &a, int rank)
     if (a.giv.H) {
         __syncthreads();   // h_{1..k+1,k} and the breakdown flag, written by thread 0
         const GivensDev &g = a.giv;
-        givens_step<kBlock>(g.H, g.ld, g.R, g.cs, g.sn, g.g, g.y, g.rho, st->beta, a.step, st);
-        if (g.snap) {
+        if (a.step <= kWaveGivensMax) {
+            if (threadIdx.x < 64)
+                givens_wave(g.H, g.ld, g.R, g.cs, g.sn, g.g, g.y, g.rho, st->beta, a.step, st);
+        } else {
+            givens_step<kBlock>(g.H, g.ld, g.R, g.cs, g.sn, g.g, g.y, g.rho, st->beta, a.step,
+                                st);
             __syncthreads();
-            if (threadIdx.x == 0) *g.snap = *st;
         }
+        if (g.snap && threadIdx.x == 0) *g.snap = *st;
     }
 }
 
