@@ -1,10 +1,17 @@
-"""Brute-force ray/pixel intersection lengths (test infrastructure only).
+"""Brute-force projector matrices of tiny geometries (test infrastructure only).
 
-Clips every ray of a tiny geometry against every pixel square with the Liang-Barsky
-parametric slab test. This is independent of the closed-form trapezoid used by the
-oracle projectors and serves to pin them. A ray lying exactly on a pixel edge (only
-possible for axis-aligned rays) is credited with half its clipped length, the mean of
-the two one-sided limits.
+* Line model: every ray is clipped against every pixel square with the Liang-Barsky
+  parametric slab test. A ray lying exactly on a pixel edge (only possible for
+  axis-aligned rays) is credited with half its clipped length, the mean of the two
+  one-sided limits.
+* Strip model: every pixel square is clipped (Sutherland-Hodgman) against the two
+  half-planes bounding the strip of width ds around the ray, and the area of the
+  remaining polygon is taken by the shoelace formula.
+* Joseph's model: the ray's crossing of each row (or column) centre line, the two
+  pixels of that row bracketing it, linear interpolation weights times the ray's
+  length per row.
+
+None of these uses the closed forms of the oracle projectors; they serve to pin them.
 """
 from __future__ import annotations
 
@@ -70,3 +77,79 @@ def chord_length_in_square(g: Geometry, a: int, i: int) -> float:
     t1 = min(tx1[0], ty1[0])
     L = t1 - t0 if (t1 > t0 and np.isfinite(t1 - t0)) else 0.0
     return 0.5 * L if (ex[0] or ey[0]) else L
+
+
+def _clip_halfplane(poly, nx, ny, c):
+    """Part of polygon `poly` (list of (x, y)) with nx*x + ny*y <= c."""
+    out = []
+    n = len(poly)
+    for k in range(n):
+        P, Q = poly[k], poly[(k + 1) % n]
+        fp = nx * P[0] + ny * P[1] - c
+        fq = nx * Q[0] + ny * Q[1] - c
+        if fp <= 0.0:
+            out.append(P)
+        if (fp < 0.0 < fq) or (fq < 0.0 < fp):
+            r = fp / (fp - fq)
+            out.append((P[0] + r * (Q[0] - P[0]), P[1] + r * (Q[1] - P[1])))
+    return out
+
+
+def _area(poly):
+    if len(poly) < 3:
+        return 0.0
+    a = 0.0
+    for k in range(len(poly)):
+        x0, y0 = poly[k]
+        x1, y1 = poly[(k + 1) % len(poly)]
+        a += x0 * y1 - x1 * y0
+    return 0.5 * abs(a)
+
+
+def strip_area_matrix(g: Geometry) -> np.ndarray:
+    """Dense m x n strip-model matrix: area of (pixel square) and (strip of width ds
+    centred on the ray), divided by ds."""
+    N = g.N
+    A = np.zeros((g.m, g.n))
+    for a in range(g.n_ang):
+        c, s = g.cos[a], g.sin[a]
+        for i in range(g.n_det):
+            lo, hi = g.s[i] - 0.5 * g.ds, g.s[i] + 0.5 * g.ds
+            for j in range(g.n):
+                r, cc = divmod(j, N)
+                x0, y0 = cc - N / 2, r - N / 2
+                sq = [(x0, y0), (x0 + 1, y0), (x0 + 1, y0 + 1), (x0, y0 + 1)]
+                poly = _clip_halfplane(sq, c, s, hi)            # <p, omega> <= hi
+                poly = _clip_halfplane(poly, -c, -s, -lo)       # <p, omega> >= lo
+                A[a * g.n_det + i, j] = _area(poly) / g.ds
+    return A
+
+
+def joseph_matrix(g: Geometry) -> np.ndarray:
+    """Dense m x n matrix of Joseph's method: for a ray with |cos| >= |sin| (closer to
+    the y axis) the image rows are sampled where the ray crosses their centre lines,
+    else the columns; each sample interpolates linearly between the two pixel centres
+    around the crossing (pixels outside the image are zero) and is weighted by the
+    ray's length per row (or column), 1/max(|cos|, |sin|)."""
+    N = g.N
+    A = np.zeros((g.m, g.n))
+    centres = np.arange(N) - N / 2 + 0.5
+    for a in range(g.n_ang):
+        c, s = g.cos[a], g.sin[a]
+        rows = abs(c) >= abs(s)
+        step = 1.0 / max(abs(c), abs(s))
+        for i in range(g.n_det):
+            row = a * g.n_det + i
+            for b in range(N):
+                if rows:
+                    xs = (g.s[i] - centres[b] * s) / c       # crossing of row b's centre line
+                else:
+                    xs = (g.s[i] - centres[b] * c) / s       # crossing of column b's centre line
+                k = int(np.floor(xs - centres[0]))           # centres[k] <= xs < centres[k+1]
+                f = xs - centres[0] - k
+                for kk, w in ((k, 1.0 - f), (k + 1, f)):
+                    if 0 <= kk < N and w > 0.0:
+                        j = b * N + kk if rows else kk * N + b
+                        A[row, j] += w * step
+    return A
+

@@ -3,7 +3,9 @@
 The paper's operators are ASTRA's explicit matrices (Sec. 6.1); here the forward
 projector A is the line model (exact ray/pixel intersection lengths), A^T its exact
 transpose, and B the unmatched back projector that interpolates linearly on the
-detector at each pixel centre. Conventions are spelled out in ``projectors.c``.
+detector at each pixel centre. The strip and interpolation (Joseph) models of Sec. 6.1
+and their transposes complete the paper's three discretisations (their norm-wise
+differences reproduce Table 6.2). Conventions are spelled out in ``projectors.c``.
 """
 from __future__ import annotations
 
@@ -32,6 +34,14 @@ def _load():
             f = getattr(lib, name)
             f.restype = None
             f.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, ctypes.c_int, ctypes.c_double, dp, dp]
+        for name in ("orc_forward_model", "orc_transpose_model"):
+            f = getattr(lib, name)
+            f.restype = None
+            f.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, dp, ctypes.c_int,
+                          ctypes.c_double, dp, dp]
+        lib.orc_model_gram.restype = None
+        lib.orc_model_gram.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, ctypes.c_int,
+                                       ctypes.c_double, dp]
         lib.orc_num_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -61,6 +71,10 @@ def angle_table(n_ang: int, ang_range: float = 180.0, ang_start: float = 0.0, an
     return th, c, s
 
 
+# Discretisation models of the forward projector (Sec. 6.1): codes of projectors.c.
+MODELS = {"line": 0, "strip": 1, "joseph": 2}
+
+
 class Geometry:
     """2-D parallel-beam scan of an N x N unit-pixel image: n = N^2, m = n_ang*n_det."""
 
@@ -86,6 +100,30 @@ class Geometry:
                                self.ds, _ptr(src), _ptr(out))
         return out
 
+    def _call_model(self, name, model, src, n_out):
+        src = np.ascontiguousarray(src, dtype=np.float64)
+        out = np.empty(n_out, dtype=np.float64)
+        getattr(_load(), name)(MODELS[model], self.N, self.n_ang, _ptr(self.cos), _ptr(self.sin),
+                               self.n_det, self.ds, _ptr(src), _ptr(out))
+        return out
+
+    def A_model(self, model: str, x: np.ndarray) -> np.ndarray:
+        """y = A x for the line, strip or Joseph (interpolation) model (Sec. 6.1)."""
+        assert x.size == self.n
+        return self._call_model("orc_forward_model", model, x, self.m)
+
+    def AT_model(self, model: str, y: np.ndarray) -> np.ndarray:
+        """x = A^T y for the line, strip or Joseph model."""
+        assert y.size == self.m
+        return self._call_model("orc_transpose_model", model, y, self.n)
+
+    def model_gram(self) -> np.ndarray:
+        """3 x 3 Frobenius inner products <A_a, A_b> of the line, strip and Joseph models."""
+        G = np.empty(9)
+        _load().orc_model_gram(self.N, self.n_ang, _ptr(self.cos), _ptr(self.sin), self.n_det,
+                               self.ds, _ptr(G))
+        return G.reshape(3, 3)
+
     def A(self, x: np.ndarray) -> np.ndarray:
         """Forward projection y = A x (line model)."""
         assert x.size == self.n
@@ -102,7 +140,17 @@ class Geometry:
         return self._call("orc_backproject_hat", y, self.n)
 
     def back(self, kind: str):
+        """Back projector by name: "hat" (unmatched interpolation B), "adj" (A_line^T),
+        "strip_t" (A_strip^T), "joseph_t" (A_Joseph^T)."""
+        if kind == "strip_t":
+            return lambda y: self.AT_model("strip", y)
+        if kind == "joseph_t":
+            return lambda y: self.AT_model("joseph", y)
         return {"hat": self.B_hat, "adj": self.AT}[kind]
+
+    def fwd(self, model: str):
+        """Forward projector by model name ("line", "strip", "joseph")."""
+        return self.A if model == "line" else (lambda x: self.A_model(model, x))
 
     def back_pixels(self, kind: str, y: np.ndarray, pixels) -> np.ndarray:
         """(B y)_j or (A^T y)_j for the listed pixel indices only (NumPy, vectorised over

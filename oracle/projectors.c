@@ -24,8 +24,25 @@
  * u = (<c_j, omega_a> - s_0)/ds: linear interpolation of the sinogram row at the
  * detector position of the pixel centre, scaled so that B approximates A^T.
  *
- * The three operators are evaluated pixel-driven from these closed forms, with an
- * explicit loop over the detector bins each pixel can reach.
+ * Two further discretisation models of A (Sec. 6.1 names the line, strip and
+ * interpolation (Joseph) models), with t = s_i - t0 as above:
+ *
+ * A_s (strip model): ray (a,i) is the strip of width ds centred on s_i, and the weight is
+ * the area of strip and pixel divided by ds. By Cavalieri the area is the integral of
+ * the line-model trapezoid over the strip, so
+ *     A_s[(a,i), j] = (G(t + ds/2) - G(t - ds/2)) / ds,
+ * G the antiderivative of the trapezoid (G(-inf) = 0, G(+inf) = 1: the pixel's area).
+ *
+ * A_i (Joseph's interpolation model): along the major axis of the ray (rows when
+ * |cos| >= |sin|), the image row is interpolated linearly at the point where the ray
+ * crosses the row's centre line, and the sample is weighted by the ray's length in the
+ * row, 1/p. A pixel whose centre lies a distance d from that crossing point (in pixels
+ * along the row) gets (1/p)(1 - d) for d < 1; since d = |t|/p, in detector coordinates
+ *     A_i[(a,i), j] = max(0, 1 - |t|/p) / p,
+ * a triangle of half-width p (pixels beyond the image edge count as zero).
+ *
+ * The operators are evaluated pixel-driven from these closed forms, with an explicit
+ * loop over the detector bins each pixel can reach.
  */
 #include <math.h>
 #include <stddef.h>
@@ -48,6 +65,40 @@ static double trap(double t, double p, double q)
     if (at <= flat) return 1.0 / p;
     if (at >= outer) return 0.0;
     return (outer - at) / (p * q);
+}
+
+/* Antiderivative of the trapezoid trap(., p, q) (unit area), from -inf to x. */
+static double trap_int(double x, double p, double q)
+{
+    double a = fabs(x);
+    double h0 = 0.5 * (p - q), h1 = 0.5 * (p + q);
+    double below;   /* integral from -inf to -a */
+    if (a >= h1)
+        below = 0.0;
+    else if (a >= h0)
+        below = (h1 - a) * (h1 - a) / (2.0 * p * q);
+    else
+        below = (q > 0.0 ? 0.5 * q / p : 0.0) + (h0 - a) / p;
+    return x < 0.0 ? below : 1.0 - below;
+}
+
+/* Weight of ray (a,i) at pixel j for model 0 (line), 1 (strip), 2 (Joseph); t = s_i - t0. */
+static double model_w(int model, double t, double p, double q, double ds)
+{
+    if (model == 1) return (trap_int(t + 0.5 * ds, p, q) - trap_int(t - 0.5 * ds, p, q)) / ds;
+    if (model == 2) {
+        double a = 1.0 - fabs(t) / p;
+        return a > 0.0 ? a / p : 0.0;
+    }
+    return trap(t, p, q);
+}
+
+/* Half-width (in t) of the support of model_w. */
+static double model_reach(int model, double p, double q, double ds)
+{
+    if (model == 1) return 0.5 * (p + q) + 0.5 * ds;
+    if (model == 2) return p;
+    return 0.5 * (p + q);
 }
 
 static double hat(double v)
@@ -145,6 +196,86 @@ void orc_backproject_hat(int N, int n_ang, const double *cs, const double *sn, i
         }
         x[j] = acc / ds;
     }
+}
+
+/* y = A_model x (model 0 line, 1 strip, 2 Joseph); rows owned by threads as above. */
+void orc_forward_model(int model, int N, int n_ang, const double *cs, const double *sn,
+                       int n_det, double ds, const double *x, double *y)
+{
+    const double s0 = -0.5 * (n_det - 1) * ds;
+    #pragma omp parallel for schedule(dynamic, 1)
+    for (int a = 0; a < n_ang; ++a) {
+        double c = cs[a], s = sn[a];
+        double p = fmax(fabs(c), fabs(s)), q = fmin(fabs(c), fabs(s));
+        double *row = y + (size_t)a * n_det;
+        for (int i = 0; i < n_det; ++i) row[i] = 0.0;
+        for (int j = 0; j < N * N; ++j) {
+            if (x[j] == 0.0) continue;
+            double xc, yc;
+            pixel_centre(N, j, &xc, &yc);
+            double t0 = xc * c + yc * s;
+            int lo, hi;
+            bin_range(t0, model_reach(model, p, q, ds), s0, ds, n_det, &lo, &hi);
+            for (int i = lo; i <= hi; ++i)
+                row[i] += model_w(model, s0 + i * ds - t0, p, q, ds) * x[j];
+        }
+    }
+}
+
+/* x = A_model^T y, one pixel per loop iteration. */
+void orc_transpose_model(int model, int N, int n_ang, const double *cs, const double *sn,
+                         int n_det, double ds, const double *y, double *x)
+{
+    const double s0 = -0.5 * (n_det - 1) * ds;
+    #pragma omp parallel for schedule(static)
+    for (int j = 0; j < N * N; ++j) {
+        double xc, yc, acc = 0.0;
+        pixel_centre(N, j, &xc, &yc);
+        for (int a = 0; a < n_ang; ++a) {
+            double c = cs[a], s = sn[a];
+            double p = fmax(fabs(c), fabs(s)), q = fmin(fabs(c), fabs(s));
+            double t0 = xc * c + yc * s;
+            int lo, hi;
+            bin_range(t0, model_reach(model, p, q, ds), s0, ds, n_det, &lo, &hi);
+            for (int i = lo; i <= hi; ++i)
+                acc += model_w(model, s0 + i * ds - t0, p, q, ds) * y[(size_t)a * n_det + i];
+        }
+        x[j] = acc;
+    }
+}
+
+/* Frobenius inner products <A_a, A_b>_F of the three models (3 x 3, row-major into G),
+ * for the norm-wise model differences of Table 6.2. */
+void orc_model_gram(int N, int n_ang, const double *cs, const double *sn, int n_det,
+                    double ds, double *G)
+{
+    const double s0 = -0.5 * (n_det - 1) * ds;
+    double acc[9] = {0};
+    #pragma omp parallel
+    {
+        double loc[9] = {0};
+        #pragma omp for schedule(static)
+        for (int j = 0; j < N * N; ++j) {
+            double xc, yc;
+            pixel_centre(N, j, &xc, &yc);
+            for (int a = 0; a < n_ang; ++a) {
+                double c = cs[a], s = sn[a];
+                double p = fmax(fabs(c), fabs(s)), q = fmin(fabs(c), fabs(s));
+                double t0 = xc * c + yc * s;
+                int lo, hi;
+                bin_range(t0, model_reach(1, p, q, ds), s0, ds, n_det, &lo, &hi);
+                for (int i = lo; i <= hi; ++i) {
+                    double t = s0 + i * ds - t0, w[3];
+                    for (int m = 0; m < 3; ++m) w[m] = model_w(m, t, p, q, ds);
+                    for (int m = 0; m < 3; ++m)
+                        for (int k = 0; k < 3; ++k) loc[3 * m + k] += w[m] * w[k];
+                }
+            }
+        }
+        #pragma omp critical
+        for (int m = 0; m < 9; ++m) acc[m] += loc[m];
+    }
+    for (int m = 0; m < 9; ++m) G[m] = acc[m];
 }
 
 /* Number of threads OpenMP will use (reported with CPU timings). */

@@ -298,3 +298,23 @@ def test_dp_candidate_rejected_by_explicit_residual(gpu_lib, mix, i):
     assert e.status == "ok" and e.k_stop == 6 and e.n_literal == 2, (e.k_stop, e.n_literal)
     assert e.res_hist[4] > thr and e.res_norm <= thr
     assert float(torch.linalg.vector_norm(e.x - s.x) / torch.linalg.vector_norm(s.x)) <= 1e-5
+
+
+def test_long_runs_past_the_one_wave_givens(gpu_lib):
+    """Engine, FP64, 80 steps without a stopping rule (from k = 64 the Givens update
+    takes the general path): the GMRES residual history of an AB and a BA problem follows
+    the oracle's over all steps, and the explicit residual of x_80 matches."""
+    import torch
+    import paper_2110_01481_amd as abg
+    spec = (48, 60, 69, 180.0, "ab", "hat", "none", 0.02, 80, 1.0, False)
+    cases = [_Case(20, spec), _Case(21, spec[:4] + ("ba",) + spec[5:])]
+    probs = [c.problem(abg, torch.float64, tag=i) for i, c in enumerate(cases)]
+    out = abg.batch_solve(probs, proj="f64", basis="f64")
+    for c, r in zip(cases, out):
+        ref = c.oracle()
+        assert r.status == "ok" and r.k_done == 80
+        ls = np.asarray(r.ls_hist)
+        assert np.allclose(ls, ref.ls_res, rtol=2e-3, atol=0), (c.method, np.max(np.abs(ls / ref.ls_res - 1)))
+        assert np.all(np.diff(ls) <= 1e-12 * ls[:-1])
+        assert abs(r.res_norm - ref.res_norms[-1]) <= 2e-3 * ref.res_norms[-1]
+

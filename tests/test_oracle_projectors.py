@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 
 import oracle as O
+from oracle import brute
 from oracle.core import assemble_dense
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -203,3 +204,119 @@ def test_angle_table_snaps_axis_angles():
     assert th[900] == 90.0 and c[900] == 0.0
     th, c, s = O.angle_table(60, 120.0)
     assert th[45] == 90.0 and c[45] == 0.0 and s[45] == 1.0
+
+
+# ---- strip and Joseph (interpolation) models -------------------------------------------
+
+MODEL_GEOMS = [
+    dict(N=4, n_ang=7, n_det=7),                                   # 0 deg included
+    dict(N=5, n_ang=6, n_det=9, det_spacing=0.8),
+    dict(N=3, n_ang=8, n_det=5, det_spacing=1.3),                  # 0, 45, 90, 135 deg
+    dict(N=6, n_ang=0, n_det=8, angles_deg=[0.0, 90.0, 45.0, 13.7, 101.3, 179.9, 33.3333]),
+]
+
+
+def _dense(g, f, n_in):
+    return np.stack([f(e) for e in np.eye(n_in)], axis=1)
+
+
+@pytest.mark.parametrize("kw", MODEL_GEOMS)
+def test_strip_model_equals_polygon_clipping(kw):
+    """Strip model (Sec. 6.1): the oracle's closed form (trapezoid integrated over the
+    detector cell) equals the area of strip and pixel by polygon clipping, divided by
+    ds; its transpose is the exact transpose."""
+    g = O.Geometry(**kw)
+    ref = brute.strip_area_matrix(g)
+    A = _dense(g, lambda e: g.A_model("strip", e), g.n)
+    AT = _dense(g, lambda e: g.AT_model("strip", e), g.m)
+    assert np.abs(A - ref).max() <= 1e-13 * max(1.0, np.abs(ref).max())
+    assert np.abs(AT - ref.T).max() <= 1e-13 * max(1.0, np.abs(ref).max())
+
+
+@pytest.mark.parametrize("kw", MODEL_GEOMS)
+def test_joseph_model_equals_row_interpolation(kw):
+    """Joseph's model (Sec. 6.1): the oracle's closed form (a triangle of half-width
+    max(|cos|,|sin|) in detector coordinates) equals sampling the rows (or columns) at
+    the ray's crossings with linear interpolation, weighted by the length per row."""
+    g = O.Geometry(**kw)
+    ref = brute.joseph_matrix(g)
+    A = _dense(g, lambda e: g.A_model("joseph", e), g.n)
+    AT = _dense(g, lambda e: g.AT_model("joseph", e), g.m)
+    assert np.abs(A - ref).max() <= 1e-13 * max(1.0, np.abs(ref).max())
+    assert np.abs(AT - ref.T).max() <= 1e-13 * max(1.0, np.abs(ref).max())
+
+
+@pytest.mark.parametrize("row", [0, 1])
+def test_model_differences_match_table_6_2(row):
+    """||As - Al||/||As||, ||As - Ai||/||As||, ||Al - Ai||/||Al|| (Frobenius) at the
+    scan parameters of Table 6.1 reproduce Table 6.2 to the four printed digits."""
+    with open(os.path.join(GOLDEN, "table_6_2_model_differences.json")) as f:
+        gold = json.load(f)["rows"][row]
+    g = O.Geometry(gold["N"], gold["n_ang"], gold["n_det"])
+    G = g.model_gram()        # order: line, strip, Joseph
+    d = lambda a, b: math.sqrt(G[a, a] + G[b, b] - 2.0 * G[a, b])
+    got = {"s_l": d(1, 0) / math.sqrt(G[1, 1]), "s_i": d(1, 2) / math.sqrt(G[1, 1]),
+           "l_i": d(0, 2) / math.sqrt(G[0, 0])}
+    for k in ("s_l", "s_i", "l_i"):
+        assert abs(got[k] - gold[k]) <= 0.5e-4, (gold["size"], k, got[k], gold[k])
+
+
+def test_strip_columns_sum_to_the_pixel_area():
+    """Summed over the bins of one angle, a strip-model column is the pixel's area over
+    ds (every strip of the detector tiles the plane), for pixels whose footprint lies
+    on the detector."""
+    for ds in (1.0, 0.8, 1.25):
+        g = O.Geometry(12, 17, 31, det_spacing=ds)
+        A = _dense(g, lambda e: g.A_model("strip", e), g.n).reshape(g.n_ang, g.n_det, g.n)
+        sums = A.sum(axis=1)                      # n_ang x n
+        assert np.abs(sums - 1.0 / ds).max() <= 1e-13, ds
+
+
+def test_joseph_is_exact_on_linear_images():
+    """Linear interpolation reproduces a linear image, so for rays that stay inside the
+    pixel centres' hull Joseph's ray sum is the exact line integral of the linear
+    function across the image: the length of the segment times its midpoint value."""
+    N = 24
+    g = O.Geometry(N, 0, 9, angles_deg=[0.0, 10.0, 30.0, 44.0, 60.0, 80.0, 90.0, 125.0, 170.0],
+                   det_spacing=1.0)
+    al, be, ga = 0.37, -0.21, 1.5
+    cen = np.arange(N) - N / 2 + 0.5
+    X, Y = np.meshgrid(cen, cen)                      # X: column coordinate, Y: row
+    x = (al * X + be * Y + ga).ravel()
+    y = g.A_model("joseph", x).reshape(g.n_ang, g.n_det)
+    checked = 0
+    for a in range(g.n_ang):
+        c, s = g.cos[a], g.sin[a]
+        for i, si in enumerate(g.s):
+            p0 = np.array([si * c, si * s])           # foot of the ray, its midpoint
+            d = np.array([-s, c])
+            if abs(c) >= abs(s):                      # rows: y from -N/2 to N/2
+                tt = np.array([-N / 2, N / 2]) - p0[1]
+                ends = [p0 + (t / d[1]) * d for t in tt]
+                inner = all(abs(e[0]) <= N / 2 - 1.0 for e in ends)
+            else:
+                tt = np.array([-N / 2, N / 2]) - p0[0]
+                ends = [p0 + (t / d[0]) * d for t in tt]
+                inner = all(abs(e[1]) <= N / 2 - 1.0 for e in ends)
+            if not inner:
+                continue
+            length = np.linalg.norm(ends[1] - ends[0])
+            mid = 0.5 * (ends[0] + ends[1])
+            exact = length * (al * mid[0] + be * mid[1] + ga)
+            assert abs(y[a, i] - exact) <= 1e-12 * abs(exact), (a, i)
+            checked += 1
+    assert checked >= 30
+
+
+def test_narrow_strips_tend_to_the_line_model():
+    """As the strip width goes to zero the strip model becomes the line model (away
+    from the axis-aligned edge case): one ray through the centre, error O(ds)."""
+    angles = [7.0, 23.0, 45.0, 61.0, 118.0]
+    x = np.random.default_rng(3).random(10 * 10)
+    line = O.Geometry(10, 0, 1, angles_deg=angles, det_spacing=1.0).A(x)
+    errs = []
+    for ds in (1e-2, 1e-3):
+        g = O.Geometry(10, 0, 1, angles_deg=angles, det_spacing=ds)
+        errs.append(np.abs(g.A_model("strip", x) - line).max() / np.abs(line).max())
+    assert errs[1] < 1e-2 and errs[1] < 0.2 * errs[0], errs
+
