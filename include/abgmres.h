@@ -24,6 +24,12 @@
  *            u = (<c_j, omega_a> - s_0)/det_spacing, c_j the pixel centre (linear
  *            interpolation on the detector, pixel-driven; zero beyond the detector).
  *   B (ADJ)  the matched back projector A^T, for matched runs (Sec. 5).
+ *   A_s      strip model (Sec. 6.1, abg_geometry_set_model): ray (a,i) is the strip of
+ *            width det_spacing around s_i; weight = area of strip and pixel / det_spacing.
+ *   A_i      interpolation (Joseph) model: along the ray's major axis (rows when
+ *            |cos| >= |sin|) each row is interpolated linearly at the ray's crossing of
+ *            its centre line, weight 1/max(|cos|,|sin|) per row.
+ *   STRIP_T, JOSEPH_T  the transposes A_s^T, A_i^T (pixel-driven).
  *
  * Conventions of every entry point:
  *   - Device buffers (x, y, b, workspaces) are caller-owned device pointers on the
@@ -58,7 +64,12 @@ extern "C" {
 #define ABG_ZERO_RHS 3         /* ||r_0|| = 0: x = x_0 returned with k = 0               */
 
 typedef enum { ABG_F64 = 0, ABG_F32 = 1, ABG_BF16 = 2 } abg_dtype;
-typedef enum { ABG_BP_HAT = 0, ABG_BP_ADJ = 1 } abg_bp_kind;
+/* Back projectors: HAT the unmatched interpolating B; ADJ = A_line^T; STRIP_T and
+ * JOSEPH_T the transposes of the strip and interpolation models (unmatched pairs of
+ * Sec. 6: B = A'^T with A' another model than the forward projector's). */
+typedef enum { ABG_BP_HAT = 0, ABG_BP_ADJ = 1, ABG_BP_STRIP_T = 2, ABG_BP_JOSEPH_T = 3 } abg_bp_kind;
+/* Discretisation models of the forward projector A (Sec. 6.1). */
+typedef enum { ABG_FP_LINE = 0, ABG_FP_STRIP = 1, ABG_FP_JOSEPH = 2 } abg_fp_model;
 typedef enum { ABG_STOP_NONE = 0, ABG_STOP_DP = 1, ABG_STOP_NCP = 2 } abg_stop_kind;
 typedef enum { ABG_METHOD_AB = 0, ABG_METHOD_BA = 1 } abg_method;
 
@@ -118,20 +129,29 @@ int abg_destroy_geometry(abg_geometry *g);
 /* n = N*N (image length) and m = n_ang*n_det (sinogram length). */
 int abg_geometry_sizes(const abg_geometry *g, long long *n, long long *m);
 
+/* Forward projector model of the geometry (abg_fp_model), used by abg_fp_apply and by the
+ * solvers; ABG_FP_LINE when created. The strip model needs det_spacing <= 1.4 (at most
+ * four pixels per row and ray): ABG_EINVAL otherwise. Not to be changed while a solve or
+ * an engine request uses the geometry. The batched engine takes line-model geometries
+ * only. */
+int abg_geometry_set_model(abg_geometry *g, int fp_model);
+int abg_geometry_get_model(const abg_geometry *g, int *fp_model);
+
 /* ---- operators -------------------------------------------------------------------- */
 
 /* Device scratch (bytes) abg_fp_apply needs for dtype t: two zero-padded copies of the
  * image, one row-major and one transposed. */
 size_t abg_fp_workspace_bytes(const abg_geometry *g, int dtype);
 
-/* y = A x (line model, ray-driven). x: n elements, y: m elements, both of `dtype`
+/* y = A x (the geometry's model, ray-driven). x: n elements, y: m elements, both of `dtype`
  * (ABG_F64 or ABG_F32); ws: abg_fp_workspace_bytes(g, dtype) bytes, 256-byte aligned.
  * Asynchronous on `stream`. */
 int abg_fp_apply(const abg_geometry *g, int dtype, const void *x, void *y,
                  void *ws, size_t ws_bytes, void *stream);
 
-/* x = B y for kind ABG_BP_HAT (unmatched) or x = A^T y for ABG_BP_ADJ (matched), pixel
- * driven. y: m elements, x: n elements of `dtype`. Asynchronous on `stream`. */
+/* x = B y for kind ABG_BP_HAT (unmatched), x = A_line^T y for ABG_BP_ADJ, A_strip^T y for
+ * ABG_BP_STRIP_T, A_Joseph^T y for ABG_BP_JOSEPH_T; pixel driven. y: m elements, x: n
+ * elements of `dtype`. Asynchronous on `stream`. */
 int abg_bp_apply(const abg_geometry *g, int kind, int dtype, const void *y, void *x,
                  void *stream);
 
@@ -176,7 +196,7 @@ typedef struct abg_engine abg_engine;
 typedef struct {
     const abg_geometry *g;   /* geometry on the engine's device; must outlive the request */
     int method;              /* ABG_METHOD_AB or ABG_METHOD_BA                             */
-    int bp_kind;             /* ABG_BP_HAT or ABG_BP_ADJ                                   */
+    int bp_kind;             /* ABG_BP_HAT or ABG_BP_ADJ (line-model geometries only)      */
     int k_max;               /* 1..500                                                     */
     abg_stop stop;           /* ABG_STOP_NONE or ABG_STOP_DP                               */
     const void *b;           /* m elements of the engine's proj dtype (device)             */

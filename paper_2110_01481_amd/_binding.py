@@ -15,7 +15,12 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libabgmres.so")
 
 F64, F32, BF16 = 0, 1, 2
-BP_HAT, BP_ADJ = 0, 1
+BP_HAT, BP_ADJ, BP_STRIP_T, BP_JOSEPH_T = 0, 1, 2, 3
+# back projectors by name: the unmatched interpolating B, and the transposes of the line,
+# strip and interpolation (Joseph) models
+BP_KINDS = {"hat": BP_HAT, "adj": BP_ADJ, "strip_t": BP_STRIP_T, "joseph_t": BP_JOSEPH_T}
+# forward projector models (Sec. 6.1)
+FP_MODELS = {"line": 0, "strip": 1, "joseph": 2}
 STOP_NONE, STOP_DP, STOP_NCP = 0, 1, 2
 METHOD_AB, METHOD_BA = 0, 1
 
@@ -27,7 +32,7 @@ EXPORTS = ["abg_create_geometry", "abg_destroy_geometry", "abg_geometry_sizes",
            "abg_profile_read", "abg_request_bytes", "abg_engine_create", "abg_engine_destroy",
            "abg_engine_submit", "abg_engine_step", "abg_engine_poll", "abg_engine_set_tiles",
            "abg_engine_get_tiles", "abg_engine_autotune", "abg_batch_solve",
-           "abg_mgs_force_stream"]
+           "abg_mgs_force_stream", "abg_geometry_set_model", "abg_geometry_get_model"]
 
 
 class AbgError(RuntimeError):
@@ -107,6 +112,8 @@ def load_library(path: str | None = None):
                                         ctypes.POINTER(i), _dp]
     lib.abg_batch_solve.argtypes = [ctypes.POINTER(Request), i, Precision, i, i, i, vp]
     lib.abg_mgs_force_stream.argtypes = [i]
+    lib.abg_geometry_set_model.argtypes = [vp, i]
+    lib.abg_geometry_get_model.argtypes = [vp, ctypes.POINTER(i)]
     _lib = lib
     return lib
 
@@ -149,7 +156,8 @@ class Geometry:
     """2-D parallel-beam geometry owned by the library (abg_create_geometry)."""
 
     def __init__(self, N: int, n_ang: int, n_det: int, ang_range: float = 180.0,
-                 ang_start: float = 0.0, angles_deg=None, det_spacing: float = 1.0):
+                 ang_start: float = 0.0, angles_deg=None, det_spacing: float = 1.0,
+                 model: str = "line"):
         lib = load_library()
         h = ctypes.c_void_p()
         arr = None
@@ -165,6 +173,15 @@ class Geometry:
         self.n = self.N * self.N
         self.m = self.n_ang * self.n_det
         self._fp_ws = {}
+        self.model = "line"
+        if model != "line":
+            self.set_model(model)
+
+    def set_model(self, model: str):
+        """Forward projector model: "line", "strip" or "joseph" (abg_geometry_set_model)."""
+        _check(load_library().abg_geometry_set_model(self._h, FP_MODELS[model]),
+               "abg_geometry_set_model")
+        self.model = model
 
     def close(self):
         if getattr(self, "_h", None):
@@ -195,7 +212,7 @@ class Geometry:
         return ws
 
     def fp(self, x, out=None, stream=None):
-        """y = A x (line model) for a contiguous CUDA tensor x of n elements."""
+        """y = A x (the geometry's model) for a contiguous CUDA tensor x of n elements."""
         torch = _torch()
         assert x.is_cuda and x.is_contiguous() and x.numel() == self.n
         t = _dtype_code(x.dtype)
@@ -208,12 +225,13 @@ class Geometry:
         return y
 
     def bp(self, y, kind: str = "hat", out=None, stream=None):
-        """x = B y (kind "hat", unmatched) or x = A^T y (kind "adj")."""
+        """x = B y (kind "hat", unmatched), A_line^T y ("adj"), A_strip^T y ("strip_t") or
+        A_Joseph^T y ("joseph_t")."""
         torch = _torch()
         assert y.is_cuda and y.is_contiguous() and y.numel() == self.m
         t = _dtype_code(y.dtype)
         x = out if out is not None else torch.empty(self.n, dtype=y.dtype, device=y.device)
-        _check(load_library().abg_bp_apply(self._h, BP_ADJ if kind == "adj" else BP_HAT, t,
+        _check(load_library().abg_bp_apply(self._h, BP_KINDS[kind], t,
                                            ctypes.c_void_p(y.data_ptr()),
                                            ctypes.c_void_p(x.data_ptr()), _stream_ptr(stream)),
                "abg_bp_apply")
@@ -253,7 +271,8 @@ def gmres(method: str, g: Geometry, b, k_max: int, stop: str = "none", tau: floa
     """AB-GMRES (method "ab") or BA-GMRES ("ba") through the C ABI.
 
     b: CUDA tensor of m elements (float64 or float32: the projector dtype);
-    basis: "f64", "f32" or "bf16" storage of the Krylov basis (default: b's dtype).
+    basis: "f64", "f32" or "bf16" storage of the Krylov basis (default: b's dtype);
+    bp: back projector "hat", "adj", "strip_t" or "joseph_t" (A is the geometry's model).
     """
     torch = _torch()
     lib = load_library()
@@ -280,7 +299,7 @@ def gmres(method: str, g: Geometry, b, k_max: int, stop: str = "none", tau: floa
     info.H = H.ctypes.data_as(_dp) if H is not None else None
     fn = lib.abg_ab_gmres if meth == METHOD_AB else lib.abg_ba_gmres
     x0p = ctypes.c_void_p(x0.data_ptr()) if x0 is not None else None
-    rc = fn(g.handle, BP_ADJ if bp == "adj" else BP_HAT, ctypes.c_void_p(b.data_ptr()), x0p,
+    rc = fn(g.handle, BP_KINDS[bp], ctypes.c_void_p(b.data_ptr()), x0p,
             ctypes.c_void_p(x.data_ptr()), int(k_max), st, prec, ctypes.c_void_p(ws.data_ptr()),
             ws.numel(), ctypes.byref(info), _stream_ptr(stream))
     _check(rc, "abg_%s_gmres" % method, ok=(0, 1, 2, 3))
@@ -467,7 +486,7 @@ class Engine:
         tag = self._next_tag
         self._next_tag += 1
         pend = _Pending(prob, x, ws, int(prob.k_max))
-        r = Request(g.handle, meth, BP_ADJ if prob.bp == "adj" else BP_HAT, int(prob.k_max), st,
+        r = Request(g.handle, meth, BP_KINDS[prob.bp], int(prob.k_max), st,
                     ctypes.c_void_p(b.data_ptr()),
                     ctypes.c_void_p(prob.x0.data_ptr()) if prob.x0 is not None else None,
                     ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
@@ -537,7 +556,7 @@ def batch_solve(problems, proj="f32", basis="f32", rays: int = 0, ang_block: int
         x = torch.empty(g.n, dtype=b.dtype, device=b.device)
         pend = _Pending(prob, x, ws, int(prob.k_max))
         keep.append(pend)
-        reqs[i] = Request(g.handle, meth, BP_ADJ if prob.bp == "adj" else BP_HAT, int(prob.k_max),
+        reqs[i] = Request(g.handle, meth, BP_KINDS[prob.bp], int(prob.k_max),
                           st, ctypes.c_void_p(b.data_ptr()),
                           ctypes.c_void_p(prob.x0.data_ptr()) if prob.x0 is not None else None,
                           ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(ws.data_ptr()), ws.numel(),

@@ -6,6 +6,7 @@
 #include <cmath>
 
 #include "abg_internal.h"
+#include "footprint.h"
 
 namespace abg {
 namespace {
@@ -83,6 +84,50 @@ template <typename T, int AB = kAngBlock> struct BackLds {
     BackStage<T> prm[2][AB];
     int ib[2][AB];      // first bin of each angle's window
 };
+
+// Fixed-order sum of the waves' partials of a tile (the window space of the LDS becomes
+// `part`), scaled, into x or (PAD) into the forward projector's padded copies xr / xc;
+// ends with a block-wide barrier.
+template <typename T, bool PAD>
+__device__ inline void tile_store(const T (&acc)[kPixPerLane], T (*part)[kTile * kTile], T scale,
+                                  T *__restrict__ x, int N, int c0, int r0, T *__restrict__ xr,
+                                  T *__restrict__ xc, int S)
+{
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int tx = lane & 15, ty0 = lane >> 4;
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kPixPerLane; ++j) {
+        const int pix = (ty0 + 4 * j) * kTile + tx;
+        if (wave > 0) part[wave - 1][pix] = acc[j];
+    }
+    __syncthreads();
+    if (wave == 0) {
+#pragma unroll
+        for (int j = 0; j < kPixPerLane; ++j) {
+            const int pix = (ty0 + 4 * j) * kTile + tx;
+            T sum = acc[j];
+#pragma unroll
+            for (int v = 0; v < kBackWaves - 1; ++v) sum += part[v][pix];
+            const T val = sum * scale;
+            const int c = c0 + tx, r = r0 + ty0 + 4 * j;
+            if constexpr (PAD) part[0][pix] = val;   // the lane's own entry
+            else if (r < N && c < N) x[(size_t)r * N + c] = val;
+        }
+    }
+    if constexpr (PAD) {
+        static_assert(kBackThreads >= kTile * kTile, "one thread per pixel of the tile");
+        __syncthreads();
+        const int t = threadIdx.x, hi = t / kTile, lo = t % kTile;
+        // xr: 16 lanes write 16 consecutive columns of a row; xc: of a column
+        if (t < kTile * kTile) {
+            if (r0 + hi < N && c0 + lo < N) xr[(size_t)(r0 + hi) * S + kPad + c0 + lo] = part[0][hi * kTile + lo];
+            if (c0 + hi < N && r0 + lo < N) xc[(size_t)(c0 + hi) * S + kPad + r0 + lo] = part[0][lo * kTile + hi];
+        }
+    }
+    __syncthreads();
+}
 
 // The 16 x 16 tile with first column c0 and first row r0, by one block of kBackThreads.
 // Starts and ends with a block-wide barrier, so consecutive calls may share the LDS.
@@ -190,38 +235,142 @@ __device__ inline void back_tile(const T *__restrict__ y, T *__restrict__ x,
                 acc[j] += back_tap<T, ADJ>(L.win[t], fma(T(j), P.su4, u0), P, dsT);
         }
     }
-    // fixed-order sum of the waves' partials
-    __syncthreads();                                   // the window space becomes part
-#pragma unroll
-    for (int j = 0; j < kPixPerLane; ++j) {
-        const int pix = (ty0 + 4 * j) * kTile + tx;
-        if (wave > 0) L.part[wave - 1][pix] = acc[j];
-    }
-    __syncthreads();
-    if (wave == 0) {
-#pragma unroll
-        for (int j = 0; j < kPixPerLane; ++j) {
-            const int pix = (ty0 + 4 * j) * kTile + tx;
-            T sum = acc[j];
-#pragma unroll
-            for (int v = 0; v < kBackWaves - 1; ++v) sum += L.part[v][pix];
-            const T val = ADJ ? sum : sum * T(1.0 / ds);
-            const int c = c0 + tx, r = r0 + ty0 + 4 * j;
-            if constexpr (PAD) L.part[0][pix] = val;   // the lane's own entry
-            else if (r < N && c < N) x[(size_t)r * N + c] = val;
+    tile_store<T, PAD>(acc, L.part, ADJ ? T(1) : T(1.0 / ds), x, N, c0, r0, xr, xc, S);
+}
+
+// ---- transposes of the strip and interpolation (Joseph) models ------------------------
+// Pixel driven like back_tile, over windows of plain sinogram values (kWinV bins per
+// angle: a tile spans at most 28.3 bins for ds >= 0.75, plus two bins of margin on each
+// side for the footprints). A pixel at window coordinate u (bins) takes the bins k with
+// |k - u| below the footprint's reach, at most three:
+//   Joseph^T:  (1/p) max(0, 1 - |k - u| ds / p)           (triangle of half-width p)
+//   strip^T:   (G(e + ds/2) - G(e - ds/2)) / ds, e = |k - u| ds   (see Trapezoid)
+constexpr int kWinV = 40;
+
+template <typename T> struct alignas(16) BackStageV {
+    T f, cu, su, su4;     // as BackStage
+    T reach;              // footprint half-width in bins
+    T js;                 // Joseph: ds / p^2;  strip: ds
+    Trapezoid<T> tz;      // strip: footprint constants; Joseph: invp only
+};
+
+template <typename T, int AB = kAngBlock> struct BackLdsV {
+    union {
+        T win[AB][kWinV];
+        T part[kBackWaves - 1][kTile * kTile];
+    };
+    BackStageV<T> prm[2][AB];
+    int ib[2][AB];
+};
+
+template <typename T, int KIND, int AB = kAngBlock, bool PAD = false>
+__device__ inline void back_tile_v(const T *__restrict__ y, T *__restrict__ x,
+                                   const AngleParams *__restrict__ ang, int N, int n_ang,
+                                   int n_det, double ds, double s0, int c0, int r0,
+                                   BackLdsV<T, AB> &L, T *__restrict__ xr = nullptr,
+                                   T *__restrict__ xc = nullptr, int S = 0)
+{
+    static_assert(KIND == ABG_BP_STRIP_T || KIND == ABG_BP_JOSEPH_T, "strip or Joseph");
+    static_assert(AB <= kBackThreads, "one thread sets up one angle");
+    constexpr int kIt = AB * kWinV / kBackThreads;     // window entries per thread and round
+    static_assert(kIt * kBackThreads == AB * kWinV && kIt <= 32, "window split");
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int tx = lane & 15, ty0 = lane >> 4;
+    const double xref = c0 - 0.5 * N + 0.5, yref = r0 - 0.5 * N + 0.5;
+    const double s0u = s0 / ds;
+    const T ftx = T(tx), fty = T(ty0);
+    const int n_rounds = (n_ang + AB - 1) / AB;
+
+    AngleParams Pn;
+    auto fetch = [&](int r) { Pn = ang[min(r * AB + (int)threadIdx.x, n_ang - 1)]; };
+    auto setup = [&](int r) {
+        if ((int)threadIdx.x < min(AB, n_ang - r * AB)) {
+            const double uref = fma(xref, Pn.cu, fma(yref, Pn.su, -s0u));
+            const double umin = uref + (kTile - 1) * (fmin(Pn.cu, 0.0) + fmin(Pn.su, 0.0));
+            const double ib = floor(umin) - 2.0;
+            BackStageV<T> st;
+            st.f = T(uref - ib);
+            st.cu = T(Pn.cu);
+            st.su = T(Pn.su);
+            st.su4 = T(4.0 * Pn.su);
+            st.tz = Trapezoid<T>(Pn, ds);
+            if (KIND == ABG_BP_JOSEPH_T) {
+                st.reach = T(Pn.p / ds);
+                st.js = T(ds * Pn.len * Pn.len);
+            } else {
+                st.reach = T((Pn.half + 0.5 * ds) / ds);
+                st.js = T(ds);
+            }
+            L.prm[r & 1][threadIdx.x] = st;
+            L.ib[r & 1][threadIdx.x] = (int)ib;
         }
-    }
-    if constexpr (PAD) {
-        static_assert(kBackThreads >= kTile * kTile, "one thread per pixel of the tile");
+    };
+    T w0[kIt];
+    unsigned live = 0;
+    // entry e = threadIdx.x + j kBackThreads of a round is bin e % kWinV of angle e / kWinV
+    auto load = [&](int r) {
+        const int a0 = r * AB, last = min(AB, n_ang - a0) - 1;
+        live = 0;
+#pragma unroll
+        for (int j = 0; j < kIt; ++j) {
+            const int e = (int)threadIdx.x + j * kBackThreads;
+            const int t = min(e / kWinV, last);
+            const int bin = L.ib[r & 1][t] + e % kWinV;
+            w0[j] = y[(size_t)(a0 + t) * n_det + min(max(bin, 0), n_det - 1)];
+            live |= (unsigned)(bin >= 0 && bin < n_det) << j;
+        }
+    };
+    auto store = [&]() {
+#pragma unroll
+        for (int j = 0; j < kIt; ++j) {
+            const int e = (int)threadIdx.x + j * kBackThreads;
+            L.win[e / kWinV][e % kWinV] = (live >> j) & 1u ? w0[j] : T(0);
+        }
+    };
+    auto tap = [&](const T *win, T u, const BackStageV<T> &P) {
+        // window coordinates keep u - reach >= 0.5, so truncation is floor
+        const int k0 = (int)(u - P.reach) + 1;
+        const T e0 = fabs(T(k0) - u), e1 = fabs(T(k0 + 1) - u), e2 = fabs(T(k0 + 2) - u);
+        T w[3];
+        if constexpr (KIND == ABG_BP_JOSEPH_T) {
+            w[0] = fmax(fma(-e0, P.js, P.tz.invp), T(0));
+            w[1] = fmax(fma(-e1, P.js, P.tz.invp), T(0));
+            w[2] = fmax(fma(-e2, P.js, P.tz.invp), T(0));
+        } else {
+            w[0] = P.tz.strip(e0 * P.js);
+            w[1] = P.tz.strip(e1 * P.js);
+            w[2] = P.tz.strip(e2 * P.js);
+        }
+        return fma(w[0], win[k0], fma(w[1], win[k0 + 1], w[2] * win[k0 + 2]));
+    };
+
+    T acc[kPixPerLane] = {};
+    __syncthreads();
+    fetch(0);
+    setup(0);
+    if (n_rounds > 1) fetch(1);
+    __syncthreads();
+    load(0);
+    for (int r = 0; r < n_rounds; ++r) {
+        const int na = min(AB, n_ang - r * AB);
         __syncthreads();
-        const int t = threadIdx.x, hi = t / kTile, lo = t % kTile;
-        // xr: 16 lanes write 16 consecutive columns of a row; xc: of a column
-        if (t < kTile * kTile) {
-            if (r0 + hi < N && c0 + lo < N) xr[(size_t)(r0 + hi) * S + kPad + c0 + lo] = L.part[0][hi * kTile + lo];
-            if (c0 + hi < N && r0 + lo < N) xc[(size_t)(c0 + hi) * S + kPad + r0 + lo] = L.part[0][lo * kTile + hi];
+        store();
+        if (r + 1 < n_rounds) {
+            setup(r + 1);
+            if (r + 2 < n_rounds) fetch(r + 2);
+        }
+        __syncthreads();
+        if (r + 1 < n_rounds) load(r + 1);
+        for (int t = wave; t < na; t += kBackWaves) {
+            const BackStageV<T> P = L.prm[r & 1][t];
+            const T u0 = fma(ftx, P.cu, fma(fty, P.su, P.f));
+            acc[0] += tap(L.win[t], u0, P);
+#pragma unroll
+            for (int j = 1; j < kPixPerLane; ++j) acc[j] += tap(L.win[t], fma(T(j), P.su4, u0), P);
         }
     }
-    __syncthreads();
+    tile_store<T, PAD>(acc, L.part, T(1), x, N, c0, r0, xr, xc, S);
 }
 
 }  // namespace

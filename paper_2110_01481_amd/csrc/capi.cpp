@@ -221,6 +221,21 @@ int abg_destroy_geometry(abg_geometry *h)
     return rc;
 }
 
+int abg_geometry_set_model(abg_geometry *h, int fp_model)
+{
+    if (!h || fp_model < ABG_FP_LINE || fp_model > ABG_FP_JOSEPH) return ABG_EINVAL;
+    if (fp_model == ABG_FP_STRIP && !(h->g.ds <= 1.4)) return ABG_EINVAL;
+    h->g.model = fp_model;
+    return ABG_OK;
+}
+
+int abg_geometry_get_model(const abg_geometry *h, int *fp_model)
+{
+    if (!h || !fp_model) return ABG_EINVAL;
+    *fp_model = h->g.model;
+    return ABG_OK;
+}
+
 int abg_geometry_sizes(const abg_geometry *h, long long *n, long long *m)
 {
     if (!h) return ABG_EINVAL;
@@ -252,7 +267,7 @@ int abg_bp_apply(const abg_geometry *h, int kind, int dtype, const void *y, void
                  void *stream)
 {
     if (!h || !x || !y || !valid_dtype_proj(dtype)) return ABG_EINVAL;
-    if (kind != ABG_BP_HAT && kind != ABG_BP_ADJ) return ABG_EINVAL;
+    if (kind < ABG_BP_HAT || kind > ABG_BP_JOSEPH_T) return ABG_EINVAL;
     int rc = current_device_matches(h->g);
     if (rc) return rc;
     return launch_back(h->g, kind, dtype, y, x, static_cast<hipStream_t>(stream)) == hipSuccess
@@ -293,7 +308,7 @@ static int solve_entry(int method, const abg_geometry *h, int bp_kind, const voi
 {
     int rc = check_solver_args(h, method, k_max, p, st);
     if (rc) return rc;
-    if (bp_kind != ABG_BP_HAT && bp_kind != ABG_BP_ADJ) return ABG_EINVAL;
+    if (bp_kind < ABG_BP_HAT || bp_kind > ABG_BP_JOSEPH_T) return ABG_EINVAL;
     if (!b || !x || !ws || x == b || (x0 && x == x0)) return ABG_EINVAL;
     if (reinterpret_cast<uintptr_t>(ws) % 256) return ABG_EINVAL;
     if ((rc = current_device_matches(h->g))) return rc;
@@ -359,6 +374,7 @@ int abg_engine_submit(abg_engine *h, const abg_request *r)
     int rc = check_solver_args(r->g, r->method, r->k_max, p, r->stop);
     if (rc) return rc;
     if (r->bp_kind != ABG_BP_HAT && r->bp_kind != ABG_BP_ADJ) return ABG_EINVAL;
+    if (r->g->g.model != ABG_FP_LINE) return ABG_EINVAL;
     if (!r->b || !r->x || !r->ws || r->x == r->b || (r->x0 && r->x == r->x0)) return ABG_EINVAL;
     if (reinterpret_cast<uintptr_t>(r->ws) % 256) return ABG_EINVAL;
     if (r->g->g.device != engine_device(h->e)) return ABG_EINVAL;

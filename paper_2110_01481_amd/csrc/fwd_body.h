@@ -6,6 +6,7 @@
 #include <cmath>
 
 #include "abg_internal.h"
+#include "footprint.h"
 
 namespace abg {
 namespace {
@@ -91,6 +92,8 @@ template <> struct Band<double> {
     {
         return fmin(b.len, fma(floor(lo) - lo, b.invq, b.invq));
     }
+    // (lo - floor(lo)) * s
+    __device__ double frac_scaled(double s) const { return (lo - floor(lo)) * s; }
 };
 
 template <> struct Band<float> {
@@ -125,6 +128,8 @@ template <> struct Band<float> {
         const float w = fmaf((float)f, -b.invq * 0x1p-32f, b.invq);
         return __builtin_amdgcn_fmed3f(w, b.len, -1e30f);   // min(w, len)
     }
+    // fractional part times s * 2^32 (the caller folds 2^-32 into s)
+    __device__ float frac_scaled(float s) const { return (float)f * s; }
 };
 
 // The two adjacent pixels a band segment can touch, fetched with one load from a
@@ -239,6 +244,192 @@ __device__ inline void forward_ray(const T *__restrict__ xr, const T *__restrict
             acc = fma(w, t.a, acc);
             acc = fma(bw.len - w, t.b, acc);
             row += S;
+        }
+    }
+    if (i < n_det) y[(size_t)a * n_det + i] = acc;
+}
+
+// ---- strip and interpolation (Joseph) models -----------------------------------------
+// Both walk the bands of the line model. Joseph samples each band on its centre line:
+// the ray crosses it at minor coordinate u* = u0 + (r + 1/2) m, and with b = u* - 1/2
+// (pixel-centre coordinates) the pixels floor(b) and floor(b) + 1 get (1 - frac b)/p and
+// (frac b)/p. The strip model (a strip of width ds around the ray; area of strip and
+// pixel over ds) weighs every pixel of the band whose centre lies within R pixels of b,
+// R = ((p + q)/2 + ds/2)/p, by the line-model trapezoid integrated over the strip: with
+// e = |b - c| p the centre's distance from the ray in detector units,
+//     w = (G(e + ds/2) - G(e - ds/2)) / ds,   G = antiderivative of the trapezoid.
+// For ds <= 1.4 that is at most four consecutive pixels, fetched with one 16-byte load.
+
+// Bands [r0, r1) whose minor-axis interval, widened by `extra` pixels on both sides, can
+// meet [-1, N + 1]; empty for rays that store nothing.
+__device__ inline void band_range(double lo0, double m, int N, double extra, bool live, int &r0,
+                                  int &r1)
+{
+    const double am = fabs(m);
+    double ra, rb;
+    if (m > 0.0) {
+        ra = (-1.0 - am - extra - lo0) / am;
+        rb = (N + 1.0 + extra - lo0) / am;
+    } else {
+        ra = (lo0 - extra - (N + 1.0)) / am;
+        rb = (lo0 + 1.0 + am + extra) / am;
+    }
+    ra = fmin(fmax(ra, 0.0), (double)N);
+    rb = fmin(fmax(rb, 0.0), (double)N);
+    r0 = live ? (int)floor(ra) : N;
+    r1 = live ? min((int)ceil(rb) + 1, N) : 0;
+}
+
+template <typename T> struct alignas(sizeof(T)) Quad {
+    T v[4];
+};
+
+// Joseph's model, ray i of angle a (called by whole waves of consecutive rays).
+template <typename T>
+__device__ inline void forward_ray_joseph(const T *__restrict__ xr, const T *__restrict__ xc,
+                                          T *__restrict__ y, const AngleParams *__restrict__ ang,
+                                          int a, int i, int N, int S, int n_det, double ds,
+                                          double s0)
+{
+    const AngleParams P = ang[a];
+    const T *img = (P.steep ? xr : xc) + kPad;
+    const double half = 0.5 * N;
+    const double si = s0 + (double)i * ds;
+    const double u0 = fma(si, P.inv, fma(-half, P.m, half));
+    T acc = T(0);
+    if (P.axis) {
+        // u* is the same in every band; out of reach, both taps read zero padding
+        const double b = fmin(fmax(u0 - 0.5, -(double)kPad), (double)(N + kPad - 2));
+        const int c0 = (int)floor(b);
+        const T w1 = T((b - c0) * P.len), w0 = T(P.len) - w1;
+        const T *p = img + c0;
+        for (int r = 0; r < N; ++r) {
+            acc = fma(w0, p[0], acc);
+            acc = fma(w1, p[1], acc);
+            p += S;
+        }
+    } else {
+        const double lo0 = u0 + fmin(P.m, 0.0);
+        int r0, r1;
+        band_range(lo0, P.m, N, 0.0, i < n_det, r0, r1);
+        const int wr0 = __builtin_amdgcn_readfirstlane(wave_min_i(r0));
+        const int wr1 = __builtin_amdgcn_readfirstlane(wave_max_i(r1));
+        // b at band wr0
+        Band<T> band(fma((double)wr0 + 0.5, P.m, u0) - 0.5, P.m);
+        const T *row = img - kPad + (size_t)wr0 * S;
+        const T len = T(P.len);
+        const T fs = sizeof(T) == 4 ? T(P.len * 0x1p-32) : len;
+        const unsigned cmax = (unsigned)(N + 2 * kPad - 2);
+        int r = wr0;
+        for (; r + 4 <= wr1; r += 4) {
+            unsigned c[4];
+            T w[4], v0[4], v1[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                c[j] = band.column(cmax);
+                w[j] = band.frac_scaled(fs);
+                band.next();
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const Taps<T> t = load_taps(row + (size_t)j * S, c[j]);
+                v0[j] = t.a;
+                v1[j] = t.b;
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                acc = fma(len - w[j], v0[j], acc);
+                acc = fma(w[j], v1[j], acc);
+            }
+            row += 4 * (size_t)S;
+        }
+        for (; r < wr1; ++r) {
+            const unsigned c = band.column(cmax);
+            const T w = band.frac_scaled(fs);
+            band.next();
+            const Taps<T> t = load_taps(row, c);
+            acc = fma(len - w, t.a, acc);
+            acc = fma(w, t.b, acc);
+            row += S;
+        }
+    }
+    if (i < n_det) y[(size_t)a * n_det + i] = acc;
+}
+
+// Strip model, ray i of angle a (called by whole waves of consecutive rays; ds <= 1.4).
+template <typename T>
+__device__ inline void forward_ray_strip(const T *__restrict__ xr, const T *__restrict__ xc,
+                                         T *__restrict__ y, const AngleParams *__restrict__ ang,
+                                         int a, int i, int N, int S, int n_det, double ds,
+                                         double s0)
+{
+    const AngleParams P = ang[a];
+    const T *img = P.steep ? xr : xc;   // row starts, padding included
+    const double half = 0.5 * N;
+    const double si = s0 + (double)i * ds;
+    const double u0 = fma(si, P.inv, fma(-half, P.m, half));
+    const double R = (P.half + 0.5 * ds) * P.len;     // reach in pixels
+    const Trapezoid<T> tz(P, ds);
+    const T pT = T(P.p);
+    // pixel c0 + k of a band, with c0 = floor(b - R) + 1 and f = frac(b - R + 1), lies
+    // b - c0 - k = f + (R - 1 - k) from the crossing point
+    const T d0 = T(R - 1.0);
+    const unsigned cmax = (unsigned)(S - 4);           // the four pixels stay in the row
+    T acc = T(0);
+    auto band4 = [&](T f, const Quad<T> &v) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const T e = fabs(f + (d0 - T(k))) * pT;
+            acc = fma(tz.strip(e), v.v[k], acc);
+        }
+    };
+    if (P.axis) {
+        // first pixel (padded index) and f, clamped into the row: out of reach only
+        // padding is read
+        const double pb = fmin(fmax(u0 - 0.5 - R + 1.0 + kPad, 0.0), (double)(N + 2 * kPad - 4));
+        const int c0 = (int)floor(pb);
+        const T f = T(pb - c0);
+        const T *p = img + c0;
+        for (int r = 0; r < N; ++r) {
+            const Quad<T> v = *reinterpret_cast<const Quad<T> *>(p);
+            band4(f, v);
+            p += S;
+        }
+    } else {
+        const double lo0 = u0 + fmin(P.m, 0.0);
+        int r0, r1;
+        band_range(lo0, P.m, N, R, i < n_det, r0, r1);
+        const int wr0 = __builtin_amdgcn_readfirstlane(wave_min_i(r0));
+        const int wr1 = __builtin_amdgcn_readfirstlane(wave_max_i(r1));
+        // b - R + 1 at band wr0
+        Band<T> band(fma((double)wr0 + 0.5, P.m, u0) - 0.5 - R + 1.0, P.m);
+        const T *row = img + (size_t)wr0 * S;
+        const T fs = sizeof(T) == 4 ? T(0x1p-32) : T(1);
+        int r = wr0;
+        for (; r + 2 <= wr1; r += 2) {
+            unsigned c[2];
+            T f[2];
+            Quad<T> v[2];
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                c[j] = band.column(cmax);
+                f[j] = band.frac_scaled(fs);
+                band.next();
+            }
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                v[j] = *reinterpret_cast<const Quad<T> *>(reinterpret_cast<const char *>(
+                    row + (size_t)j * S) + c[j] * (unsigned)sizeof(T));
+#pragma unroll
+            for (int j = 0; j < 2; ++j) band4(f[j], v[j]);
+            row += 2 * (size_t)S;
+        }
+        if (r < wr1) {
+            const unsigned c = band.column(cmax);
+            const T f = band.frac_scaled(fs);
+            const Quad<T> v = *reinterpret_cast<const Quad<T> *>(
+                reinterpret_cast<const char *>(row) + c * (unsigned)sizeof(T));
+            band4(f, v);
         }
     }
     if (i < n_det) y[(size_t)a * n_det + i] = acc;

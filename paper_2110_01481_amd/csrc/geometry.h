@@ -31,6 +31,7 @@ struct AngleParams {
 struct Geometry {
     int N = 0, n_ang = 0, n_det = 0;
     double ds = 1.0;
+    int model = 0;      // forward projector: ABG_FP_LINE, ABG_FP_STRIP or ABG_FP_JOSEPH
     int device = 0;
     std::vector<double> theta;
     std::vector<AngleParams> host;

@@ -1,6 +1,7 @@
 // Matrix-free 2-D parallel-beam projectors for gfx950.
 //
-//  forward  y = A x : line model (Sec. 6.1), one thread per ray. A ray crosses each
+//  forward  y = A x : line model (Sec. 6.1), one thread per ray; the strip and
+//           interpolation (Joseph) models of Sec. 6.1 walk the same bands. A ray crosses each
 //           band of pixels along its major axis (rows when |cos| >= |sin|, else columns)
 //           in a segment of length 1/p that spans at most two pixels; the kernel walks
 //           the bands and splits the segment at the pixel edge it crosses, i.e. it
@@ -52,6 +53,21 @@ __global__ __launch_bounds__(kFwdBlock) void forward_kernel(
                 ds, s0);
 }
 
+// Strip (MODEL = ABG_FP_STRIP) and interpolation (ABG_FP_JOSEPH) models.
+template <typename T, int MODEL>
+__global__ __launch_bounds__(kFwdBlock) void forward_model_kernel(
+    const T *__restrict__ xr, const T *__restrict__ xc, T *__restrict__ y,
+    const AngleParams *__restrict__ ang, int N, int S, int n_det, double ds, double s0,
+    const DevState *st, int k)
+{
+    if (halted(st, k)) return;
+    const int i = blockIdx.x * kFwdBlock + threadIdx.x;
+    if constexpr (MODEL == ABG_FP_STRIP)
+        forward_ray_strip(xr, xc, y, ang, blockIdx.y, i, N, S, n_det, ds, s0);
+    else
+        forward_ray_joseph(xr, xc, y, ang, blockIdx.y, i, N, S, n_det, ds, s0);
+}
+
 // 64 angles staged per round: the smaller LDS footprint lets more blocks share a CU
 // (measured faster than 128 on large images, equal on small ones).
 constexpr int kSingleAngBlock = 64;
@@ -60,6 +76,20 @@ constexpr int kSingleAngBlock = 64;
 // FP32: at most 64 VGPRs, so that four blocks (eight waves per SIMD) share a CU
 template <typename T> constexpr int kBackMinWaves = 1;
 template <> constexpr int kBackMinWaves<float> = 8;
+
+// Transposes of the strip and interpolation models (KIND ABG_BP_STRIP_T / _JOSEPH_T).
+template <typename T, int KIND, bool PAD>
+__global__ __launch_bounds__(kBackThreads) void back_model_kernel(
+    const T *__restrict__ y, T *__restrict__ x, const AngleParams *__restrict__ ang, int N,
+    int n_ang, int n_det, double ds, double s0, const DevState *st, int k)
+{
+    __shared__ BackLdsV<T, kSingleAngBlock> lds;
+    if (halted(st, k)) return;
+    const int S = N + 2 * kPad;
+    back_tile_v<T, KIND, kSingleAngBlock, PAD>(y, x, ang, N, n_ang, n_det, ds, s0,
+                                               blockIdx.x * kTile, blockIdx.y * kTile, lds, x,
+                                               x + (size_t)N * S, S);
+}
 
 template <typename T, bool ADJ, bool PAD>
 __global__ __launch_bounds__(kBackThreads, kBackMinWaves<T>) void back_kernel(
@@ -95,7 +125,10 @@ hipError_t forward_t(const Geometry &g, const void *x, void *y, void *ws, hipStr
     {
         // timed at the kernel's own start and end when profiling is on
         ProfScope ps(kProfFwd, s, st ? k : 0, true);
-        hipExtLaunchKernelGGL(forward_kernel<T>, grid, dim3(kFwdBlock), 0, s, ps.e0, ps.e1, 0,
+        auto fn = g.model == ABG_FP_STRIP    ? forward_model_kernel<T, ABG_FP_STRIP>
+                  : g.model == ABG_FP_JOSEPH ? forward_model_kernel<T, ABG_FP_JOSEPH>
+                                             : forward_kernel<T>;
+        hipExtLaunchKernelGGL(fn, grid, dim3(kFwdBlock), 0, s, ps.e0, ps.e1, 0,
                               (const T *)xr, (const T *)xc, static_cast<T *>(y),
                               (const AngleParams *)g.dev, N, S, g.n_det, g.ds, s0, st, k);
     }
@@ -109,6 +142,14 @@ hipError_t back_t(const Geometry &g, int kind, const void *y, void *x, hipStream
     dim3 grid((g.N + kTile - 1) / kTile, (g.N + kTile - 1) / kTile);
     const double s0 = -0.5 * (g.n_det - 1) * g.ds;
     ProfScope ps(kProfBack, s, st ? k : 0, true);
+    if (kind == ABG_BP_STRIP_T || kind == ABG_BP_JOSEPH_T) {
+        auto fn = kind == ABG_BP_STRIP_T ? back_model_kernel<T, ABG_BP_STRIP_T, PAD>
+                                         : back_model_kernel<T, ABG_BP_JOSEPH_T, PAD>;
+        hipExtLaunchKernelGGL(fn, grid, dim3(kBackThreads), 0, s, ps.e0, ps.e1, 0,
+                              static_cast<const T *>(y), static_cast<T *>(x),
+                              (const AngleParams *)g.dev, g.N, g.n_ang, g.n_det, g.ds, s0, st, k);
+        return hipGetLastError();
+    }
     if (kind == ABG_BP_ADJ)
         hipExtLaunchKernelGGL(back_kernel<T, true, PAD>, grid, dim3(kBackThreads), 0, s, ps.e0,
                               ps.e1, 0, static_cast<const T *>(y), static_cast<T *>(x),

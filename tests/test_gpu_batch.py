@@ -300,10 +300,21 @@ def test_dp_candidate_rejected_by_explicit_residual(gpu_lib, mix, i):
     assert float(torch.linalg.vector_norm(e.x - s.x) / torch.linalg.vector_norm(s.x)) <= 1e-5
 
 
+def _ls_bound(f, A, B, b, k, ref):
+    """Per-step bound on the relative deviation of the GMRES residual history from the
+    oracle's: 1000x the change a 1e-13 relative perturbation of b causes in the oracle
+    itself (steps near k = 25 of these problems are ill-conditioned), at least 1e-7."""
+    d = np.random.default_rng(1).standard_normal(b.size)
+    pert = f(A, B, b + 1e-13 * np.linalg.norm(b) * d / np.linalg.norm(d), k)
+    dev = np.abs(np.asarray(pert.ls_res) / np.asarray(ref.ls_res) - 1.0)
+    return np.maximum(1e-7, 1e3 * dev)
+
+
 def test_long_runs_past_the_one_wave_givens(gpu_lib):
     """Engine, FP64, 80 steps without a stopping rule (from k = 64 the Givens update
     takes the general path): the GMRES residual history of an AB and a BA problem follows
-    the oracle's over all steps, and the explicit residual of x_80 matches."""
+    the oracle's within the sensitivity bound at every step and never increases; the
+    explicit residual of x_80 matches."""
     import torch
     import paper_2110_01481_amd as abg
     spec = (48, 60, 69, 180.0, "ab", "hat", "none", 0.02, 80, 1.0, False)
@@ -312,9 +323,11 @@ def test_long_runs_past_the_one_wave_givens(gpu_lib):
     out = abg.batch_solve(probs, proj="f64", basis="f64")
     for c, r in zip(cases, out):
         ref = c.oracle()
+        f = O.ab_gmres if c.method == "ab" else O.ba_gmres
+        bound = _ls_bound(f, c.go.A, c.go.back(c.kind), c.b, 80, ref)
         assert r.status == "ok" and r.k_done == 80
         ls = np.asarray(r.ls_hist)
-        assert np.allclose(ls, ref.ls_res, rtol=2e-3, atol=0), (c.method, np.max(np.abs(ls / ref.ls_res - 1)))
+        dev = np.abs(ls / np.asarray(ref.ls_res) - 1.0)
+        assert np.all(dev <= bound), (c.method, int(np.argmax(dev / bound)) + 1)
         assert np.all(np.diff(ls) <= 1e-12 * ls[:-1])
-        assert abs(r.res_norm - ref.res_norms[-1]) <= 2e-3 * ref.res_norms[-1]
-
+        assert abs(r.res_norm - ref.res_norms[-1]) <= max(1e-7, bound[-1]) * ref.res_norms[-1]

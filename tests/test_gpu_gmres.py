@@ -85,18 +85,23 @@ def test_plain_fp64_thirty_iterations(gpu_lib, cfg1, method, kind):
 @pytest.mark.parametrize("method", ["ab", "ba"])
 def test_long_run_past_the_one_wave_givens(gpu_lib, cfg1, method):
     """80 steps: from k = 64 on, the Givens update leaves the one-wave register path for
-    the general block path. The GMRES residual history (well conditioned, unlike the
-    iterates around k = 24 on this problem) follows the oracle's over all 80 steps and
-    never increases; the explicit residual of x_80 matches."""
+    the general block path. The GMRES residual history follows the oracle's at every step
+    within 1000x the change a 1e-13 perturbation of b causes in the oracle itself (steps
+    near k = 24 are ill-conditioned on this problem), at least 1e-7, and never increases;
+    the explicit residual of x_80 matches."""
     go, gg, _, b, _ = cfg1
     f = O.ab_gmres if method == "ab" else O.ba_gmres
     ref = f(go.A, go.B_hat, b, 80)
+    d = np.random.default_rng(1).standard_normal(b.size)
+    pert = f(go.A, go.B_hat, b + 1e-13 * np.linalg.norm(b) * d / np.linalg.norm(d), 80)
+    bound = np.maximum(1e-7, 1e3 * np.abs(np.asarray(pert.ls_res) / np.asarray(ref.ls_res) - 1.0))
     r = _solve(method, gg, b, 80)
     assert r.status == "ok" and r.k_done == 80
     ls = np.asarray(r.ls_hist)
-    assert np.allclose(ls, ref.ls_res, rtol=2e-3, atol=0), np.max(np.abs(ls / ref.ls_res - 1))
+    dev = np.abs(ls / np.asarray(ref.ls_res) - 1.0)
+    assert np.all(dev <= bound), int(np.argmax(dev / bound)) + 1
     assert np.all(np.diff(ls) <= 1e-12 * ls[:-1])
-    assert abs(r.res_norm - ref.res_norms[-1]) <= 2e-3 * ref.res_norms[-1]
+    assert abs(r.res_norm - ref.res_norms[-1]) <= max(1e-7, bound[-1]) * ref.res_norms[-1]
 
 
 @pytest.mark.parametrize("method", ["ab", "ba"])
