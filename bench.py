@@ -227,6 +227,64 @@ def _single_solves(abg, torch, probs, dtype):
     return time.perf_counter() - t0, out
 
 
+PAIRS = [("strip", "adj"), ("strip", "joseph_t"), ("line", "strip_t"), ("line", "joseph_t"),
+         ("joseph", "adj"), ("joseph", "strip_t")]
+
+
+def bench_models(abg, torch, dev, w, xb, reps=20):
+    """The three forward models and four back projectors of the workload (time per apply,
+    FP32), and the six unmatched pairs (A, B = A'^T) of the paper's Table 6.3 solved with
+    AB- and BA-GMRES under the DP rule on this workload: stopping iteration, solve time
+    and relative reconstruction error ||x - x_true|| / ||x_true||."""
+    geo = {m: abg.Geometry(w.N, w.n_ang, w.n_det, ang_range=w.ang_range, model=m)
+           for m in ("line", "strip", "joseph")}
+    x = torch.tensor(xb, dtype=torch.float32, device=dev)
+    xt = torch.tensor(xb, dtype=torch.float64, device=dev)
+
+    def timed(fn):
+        for _ in range(2):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    out = {"apply_ms": {}}
+    y = geo["line"].fp(x)
+    for m, g in geo.items():
+        out["apply_ms"]["A_" + m] = round(timed(lambda: g.fp(x)), 4)
+    for k in ("hat", "adj", "strip_t", "joseph_t"):
+        out["apply_ms"]["B_" + k] = round(timed(lambda: geo["line"].bp(y, k)), 4)
+    pairs = {}
+    for m, k in PAIRS:
+        g = geo[m]
+        bc = g.fp(xt)
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(7)
+        e = torch.randn(bc.numel(), generator=gen, device=dev, dtype=bc.dtype)
+        e *= w.eta * torch.linalg.vector_norm(bc) / torch.linalg.vector_norm(e)
+        b = (bc + e).float()
+        enorm = float(torch.linalg.vector_norm(e))
+        for meth in ("ab", "ba"):
+            abg.gmres(meth, g, b, w.k_max, stop="dp", tau=w.tau, noise_norm=enorm, bp=k)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = abg.gmres(meth, g, b, w.k_max, stop="dp", tau=w.tau, noise_norm=enorm, bp=k)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            err = float(torch.linalg.vector_norm(r.x.double() - xt) / torch.linalg.vector_norm(xt))
+            pairs[f"{meth}:A_{m},B_{k}"] = {"k_stop": r.k_stop, "ms": round(1e3 * dt, 3),
+                                           "iters_per_s": round(r.k_done / dt, 1),
+                                           "rel_error": round(err, 4)}
+    out["pairs_dp"] = pairs
+    for g in geo.values():
+        g.release_workspace()
+    return out
+
+
 def bench_batched(abg, torch, dev, reps=3):
     """The 64-problem batched workload (N in {128..1024}, 60..720 angles, half limited
     angle, AB/BA alternating, per-problem DP): engine throughput after autotuning, next to
@@ -331,6 +389,8 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="seconds of Poisson arrivals for the serving run (0: skip)")
     ap.add_argument("--serve-basis", default="f32,bf16")
+    ap.add_argument("--no-models", action="store_true",
+                    help="skip the strip / Joseph models and the six unmatched pairs")
     ap.add_argument("--summarize-counters", default="",
                     help="print the counter summary of the rocprofv3 passes under this directory")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -500,6 +560,9 @@ def main():
         extra["f32_vs_f64_iterate_rel"] = {
             m: float(torch.linalg.vector_norm(last[m].x.double() - r64[m].x) /
                      torch.linalg.vector_norm(r64[m].x)) for m in methods}
+
+    if not args.no_models:
+        extra["models"] = bench_models(abg, torch, dev, w, xb)
 
     tiles = None
     if not args.no_batch:
