@@ -42,6 +42,16 @@ def _load():
         lib.orc_model_gram.restype = None
         lib.orc_model_gram.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, ctypes.c_int,
                                        ctypes.c_double, dp]
+        lib.orc_strip_max.restype = ctypes.c_double
+        lib.orc_strip_max.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, ctypes.c_int,
+                                      ctypes.c_double]
+        lib.orc_transpose_strip_tau.restype = None
+        lib.orc_transpose_strip_tau.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, ctypes.c_int,
+                                                ctypes.c_double, ctypes.c_double,
+                                                ctypes.c_double, dp, dp]
+        lib.orc_strip_tau_sums.restype = None
+        lib.orc_strip_tau_sums.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, ctypes.c_int,
+                                           ctypes.c_double, ctypes.c_double, ctypes.c_double, dp]
         lib.orc_num_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -123,6 +133,35 @@ class Geometry:
         _load().orc_model_gram(self.N, self.n_ang, _ptr(self.cos), _ptr(self.sin), self.n_det,
                                self.ds, _ptr(G))
         return G.reshape(3, 3)
+
+    def strip_max(self) -> float:
+        """Largest entry of the strip-model matrix A_s."""
+        if getattr(self, "_strip_max", None) is None:
+            self._strip_max = float(_load().orc_strip_max(self.N, self.n_ang, _ptr(self.cos),
+                                                          _ptr(self.sin), self.n_det, self.ds))
+        return self._strip_max
+
+    def B_tau(self, tau: float):
+        """x = B_tau y (Sec. 6.5): A_s^T without its entries below tau * max A_s (entries
+        within 1e-6 * max of that threshold are kept)."""
+        mx = self.strip_max()
+
+        def apply(y):
+            y = np.ascontiguousarray(y, dtype=np.float64)
+            assert y.size == self.m
+            out = np.empty(self.n)
+            _load().orc_transpose_strip_tau(self.N, self.n_ang, _ptr(self.cos), _ptr(self.sin),
+                                            self.n_det, self.ds, tau * mx, mx, _ptr(y), _ptr(out))
+            return out
+        return apply
+
+    def strip_tau_unmatchedness(self, tau: float) -> float:
+        """||B_tau - A_s^T||_F / ||A_s||_F (Table 6.4)."""
+        mx = self.strip_max()
+        out = np.empty(2)
+        _load().orc_strip_tau_sums(self.N, self.n_ang, _ptr(self.cos), _ptr(self.sin), self.n_det,
+                                   self.ds, tau * mx, mx, _ptr(out))
+        return float(np.sqrt(out[1] / out[0]))
 
     def A(self, x: np.ndarray) -> np.ndarray:
         """Forward projection y = A x (line model)."""

@@ -278,6 +278,89 @@ void orc_model_gram(int N, int n_ang, const double *cs, const double *sn, int n_
     for (int m = 0; m < 9; ++m) G[m] = acc[m];
 }
 
+#define TAU_TIE 1e-6
+
+/* Largest entry of the strip-model matrix (max over rays and pixels). */
+double orc_strip_max(int N, int n_ang, const double *cs, const double *sn, int n_det, double ds)
+{
+    const double s0 = -0.5 * (n_det - 1) * ds;
+    double best = 0.0;
+    #pragma omp parallel for schedule(static) reduction(max : best)
+    for (int j = 0; j < N * N; ++j) {
+        double xc, yc;
+        pixel_centre(N, j, &xc, &yc);
+        for (int a = 0; a < n_ang; ++a) {
+            double c = cs[a], s = sn[a];
+            double p = fmax(fabs(c), fabs(s)), q = fmin(fabs(c), fabs(s));
+            double t0 = xc * c + yc * s;
+            int lo, hi;
+            bin_range(t0, model_reach(1, p, q, ds), s0, ds, n_det, &lo, &hi);
+            for (int i = lo; i <= hi; ++i) {
+                double w = model_w(1, s0 + i * ds - t0, p, q, ds);
+                if (w > best) best = w;
+            }
+        }
+    }
+    return best;
+}
+
+/* x = B_tau y: the strip-model transpose without its entries below thr (Sec. 6.5, eq. for
+ * B_tau with thr = tau * max A_s). Entries within TAU_TIE * max of the threshold count as
+ * on it and are kept: ties such as a strip covering half a pixel at 0 degrees (weight
+ * exactly 1/2) must be decided the same way by implementations that round differently. */
+void orc_transpose_strip_tau(int N, int n_ang, const double *cs, const double *sn, int n_det,
+                             double ds, double thr, double max_entry, const double *y, double *x)
+{
+    const double s0 = -0.5 * (n_det - 1) * ds;
+    const double tie = TAU_TIE * max_entry;
+    #pragma omp parallel for schedule(static)
+    for (int j = 0; j < N * N; ++j) {
+        double xc, yc, acc = 0.0;
+        pixel_centre(N, j, &xc, &yc);
+        for (int a = 0; a < n_ang; ++a) {
+            double c = cs[a], s = sn[a];
+            double p = fmax(fabs(c), fabs(s)), q = fmin(fabs(c), fabs(s));
+            double t0 = xc * c + yc * s;
+            int lo, hi;
+            bin_range(t0, model_reach(1, p, q, ds), s0, ds, n_det, &lo, &hi);
+            for (int i = lo; i <= hi; ++i) {
+                double w = model_w(1, s0 + i * ds - t0, p, q, ds);
+                if (w >= thr - tie) acc += w * y[(size_t)a * n_det + i];
+            }
+        }
+        x[j] = acc;
+    }
+}
+
+/* Sums of squares of the strip-model entries: all of them (out[0]) and those B_tau drops
+ * (out[1]), so that ||B_tau - A_s^T||_F / ||A_s||_F = sqrt(out[1] / out[0]). */
+void orc_strip_tau_sums(int N, int n_ang, const double *cs, const double *sn, int n_det,
+                        double ds, double thr, double max_entry, double *out)
+{
+    const double s0 = -0.5 * (n_det - 1) * ds;
+    const double tie = TAU_TIE * max_entry;
+    double all = 0.0, low = 0.0;
+    #pragma omp parallel for schedule(static) reduction(+ : all, low)
+    for (int j = 0; j < N * N; ++j) {
+        double xc, yc;
+        pixel_centre(N, j, &xc, &yc);
+        for (int a = 0; a < n_ang; ++a) {
+            double c = cs[a], s = sn[a];
+            double p = fmax(fabs(c), fabs(s)), q = fmin(fabs(c), fabs(s));
+            double t0 = xc * c + yc * s;
+            int lo, hi;
+            bin_range(t0, model_reach(1, p, q, ds), s0, ds, n_det, &lo, &hi);
+            for (int i = lo; i <= hi; ++i) {
+                double w = model_w(1, s0 + i * ds - t0, p, q, ds);
+                all += w * w;
+                if (w < thr - tie) low += w * w;
+            }
+        }
+    }
+    out[0] = all;
+    out[1] = low;
+}
+
 /* Number of threads OpenMP will use (reported with CPU timings). */
 int orc_num_threads(void)
 {

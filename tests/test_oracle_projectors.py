@@ -320,3 +320,37 @@ def test_narrow_strips_tend_to_the_line_model():
         errs.append(np.abs(g.A_model("strip", x) - line).max() / np.abs(line).max())
     assert errs[1] < 1e-2 and errs[1] < 0.2 * errs[0], errs
 
+
+# ---- thresholded back projector B_tau (Sec. 6.5) ----------------------------------------
+
+@pytest.mark.parametrize("row", [0, 1])
+def test_b_tau_unmatchedness_matches_table_6_4(row):
+    """||B_tau - As^T||_F / ||As||_F at the scan parameters of Table 6.1 reproduces Table 6.4
+    for tau = 0.01, 0.1, 0.3, 0.5 to the four printed digits (max As = 1 there: at 0
+    degrees a strip covers a pixel column exactly)."""
+    with open(os.path.join(GOLDEN, "table_6_4_b_tau_unmatchedness.json")) as f:
+        gold = json.load(f)
+    r = gold["rows"][row]
+    g = O.Geometry(r["N"], r["n_ang"], r["n_det"])
+    assert g.strip_max() == pytest.approx(1.0, abs=1e-14)
+    for tau, want in zip(gold["tau"], r["values"]):
+        assert abs(g.strip_tau_unmatchedness(tau) - want) <= 0.5e-4, (r["size"], tau)
+
+
+@pytest.mark.parametrize("kw", MODEL_GEOMS[:3])
+def test_b_tau_equals_thresholded_clipping_matrix(kw):
+    """B_tau is the transpose of the polygon-clipping strip matrix with the entries below
+    tau * max dropped (entries within 1e-6 * max of the threshold kept), for several tau,
+    including 0.5 where axis angles put entries exactly on the threshold."""
+    g = O.Geometry(**kw)
+    ref = brute.strip_area_matrix(g)
+    mx = ref.max()
+    assert abs(g.strip_max() - mx) <= 1e-13
+    for tau in (0.0, 0.1, 0.3, 0.5, 0.9):
+        want = np.where(ref >= tau * mx - 1e-6 * mx, ref, 0.0).T
+        got = _dense(g, g.B_tau(tau), g.m)
+        assert np.abs(got - want).max() <= 1e-13, tau
+    # tau = 0 is the strip transpose itself
+    y = np.random.default_rng(4).standard_normal(g.m)
+    assert np.abs(g.B_tau(0.0)(y) - g.AT_model("strip", y)).max() <= 1e-13
+
