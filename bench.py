@@ -233,9 +233,10 @@ PAIRS = [("strip", "adj"), ("strip", "joseph_t"), ("line", "strip_t"), ("line", 
 
 def bench_models(abg, torch, dev, w, xb, reps=20):
     """The three forward models and four back projectors of the workload (time per apply,
-    FP32), and the six unmatched pairs (A, B = A'^T) of the paper's Table 6.3 solved with
-    AB- and BA-GMRES under the DP rule on this workload: stopping iteration, solve time
-    and relative reconstruction error ||x - x_true|| / ||x_true||."""
+    FP32), the six unmatched pairs (A, B = A'^T) of the paper's Table 6.3 and the pairs
+    (A_s, B_tau) of Sec. 6.5 for the thresholds of Table 6.4, solved with AB- and BA-GMRES
+    under the DP rule on this workload: stopping iteration, solve time and relative
+    reconstruction error ||x - x_true|| / ||x_true||."""
     geo = {m: abg.Geometry(w.N, w.n_ang, w.n_det, ang_range=w.ang_range, model=m)
            for m in ("line", "strip", "joseph")}
     x = torch.tensor(xb, dtype=torch.float32, device=dev)
@@ -280,6 +281,29 @@ def bench_models(abg, torch, dev, w, xb, reps=20):
                                            "iters_per_s": round(r.k_done / dt, 1),
                                            "rel_error": round(err, 4)}
     out["pairs_dp"] = pairs
+    # Sec. 6.5: (A_s, B_tau) for the thresholds of Table 6.4
+    sweep = {}
+    g = geo["strip"]
+    bc = g.fp(xt)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(8)
+    e = torch.randn(bc.numel(), generator=gen, device=dev, dtype=bc.dtype)
+    e *= w.eta * torch.linalg.vector_norm(bc) / torch.linalg.vector_norm(e)
+    b = (bc + e).float()
+    enorm = float(torch.linalg.vector_norm(e))
+    for tau in (0.0, 0.01, 0.1, 0.3, 0.5):
+        mx = g.set_strip_threshold(tau)
+        for meth in ("ab", "ba"):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = abg.gmres(meth, g, b, w.k_max, stop="dp", tau=w.tau, noise_norm=enorm, bp="strip_tau")
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            err = float(torch.linalg.vector_norm(r.x.double() - xt) / torch.linalg.vector_norm(xt))
+            sweep[f"{meth}:tau={tau:g}"] = {"k_stop": r.k_stop, "ms": round(1e3 * dt, 3),
+                                           "rel_error": round(err, 4)}
+    out["strip_b_tau_dp"] = sweep
+    out["strip_max_entry"] = mx
     for g in geo.values():
         g.release_workspace()
     return out

@@ -66,8 +66,15 @@ extern "C" {
 typedef enum { ABG_F64 = 0, ABG_F32 = 1, ABG_BF16 = 2 } abg_dtype;
 /* Back projectors: HAT the unmatched interpolating B; ADJ = A_line^T; STRIP_T and
  * JOSEPH_T the transposes of the strip and interpolation models (unmatched pairs of
- * Sec. 6: B = A'^T with A' another model than the forward projector's). */
-typedef enum { ABG_BP_HAT = 0, ABG_BP_ADJ = 1, ABG_BP_STRIP_T = 2, ABG_BP_JOSEPH_T = 3 } abg_bp_kind;
+ * Sec. 6: B = A'^T with A' another model than the forward projector's); STRIP_TAU the
+ * thresholded strip transpose B_tau of Sec. 6.5 (abg_geometry_set_strip_threshold). */
+typedef enum {
+    ABG_BP_HAT = 0,
+    ABG_BP_ADJ = 1,
+    ABG_BP_STRIP_T = 2,
+    ABG_BP_JOSEPH_T = 3,
+    ABG_BP_STRIP_TAU = 4
+} abg_bp_kind;
 /* Discretisation models of the forward projector A (Sec. 6.1). */
 typedef enum { ABG_FP_LINE = 0, ABG_FP_STRIP = 1, ABG_FP_JOSEPH = 2 } abg_fp_model;
 typedef enum { ABG_STOP_NONE = 0, ABG_STOP_DP = 1, ABG_STOP_NCP = 2 } abg_stop_kind;
@@ -137,6 +144,16 @@ int abg_geometry_sizes(const abg_geometry *g, long long *n, long long *m);
 int abg_geometry_set_model(abg_geometry *g, int fp_model);
 int abg_geometry_get_model(const abg_geometry *g, int *fp_model);
 
+/* Threshold of the back projector ABG_BP_STRIP_TAU (Sec. 6.5): B_tau keeps the entries of
+ * A_s^T that are >= tau * max(A_s), 0 <= tau <= 1; entries within 1e-6 * max(A_s) of the
+ * threshold count as on it (kept), so that ties are decided the same way whatever the
+ * rounding. The first call computes max(A_s), the largest strip-model entry of the
+ * geometry, on the host (a scan of the pixel-bin pairs of the angles that can hold it)
+ * and writes it to *max_entry (may be NULL). tau = 0 (the default) gives A_s^T. The
+ * strip model needs det_spacing <= 1.4 (ABG_EINVAL otherwise). Not to be changed while a
+ * solve uses the geometry. */
+int abg_geometry_set_strip_threshold(abg_geometry *g, double tau, double *max_entry);
+
 /* ---- operators -------------------------------------------------------------------- */
 
 /* Device scratch (bytes) abg_fp_apply needs for dtype t: two zero-padded copies of the
@@ -150,8 +167,8 @@ int abg_fp_apply(const abg_geometry *g, int dtype, const void *x, void *y,
                  void *ws, size_t ws_bytes, void *stream);
 
 /* x = B y for kind ABG_BP_HAT (unmatched), x = A_line^T y for ABG_BP_ADJ, A_strip^T y for
- * ABG_BP_STRIP_T, A_Joseph^T y for ABG_BP_JOSEPH_T; pixel driven. y: m elements, x: n
- * elements of `dtype`. Asynchronous on `stream`. */
+ * ABG_BP_STRIP_T, A_Joseph^T y for ABG_BP_JOSEPH_T, B_tau y for ABG_BP_STRIP_TAU; pixel
+ * driven. y: m elements, x: n elements of `dtype`. Asynchronous on `stream`. */
 int abg_bp_apply(const abg_geometry *g, int kind, int dtype, const void *y, void *x,
                  void *stream);
 

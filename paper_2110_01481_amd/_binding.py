@@ -15,10 +15,11 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libabgmres.so")
 
 F64, F32, BF16 = 0, 1, 2
-BP_HAT, BP_ADJ, BP_STRIP_T, BP_JOSEPH_T = 0, 1, 2, 3
-# back projectors by name: the unmatched interpolating B, and the transposes of the line,
-# strip and interpolation (Joseph) models
-BP_KINDS = {"hat": BP_HAT, "adj": BP_ADJ, "strip_t": BP_STRIP_T, "joseph_t": BP_JOSEPH_T}
+BP_HAT, BP_ADJ, BP_STRIP_T, BP_JOSEPH_T, BP_STRIP_TAU = 0, 1, 2, 3, 4
+# back projectors by name: the unmatched interpolating B, the transposes of the line,
+# strip and interpolation (Joseph) models, and the thresholded strip transpose B_tau
+BP_KINDS = {"hat": BP_HAT, "adj": BP_ADJ, "strip_t": BP_STRIP_T, "joseph_t": BP_JOSEPH_T,
+            "strip_tau": BP_STRIP_TAU}
 # forward projector models (Sec. 6.1)
 FP_MODELS = {"line": 0, "strip": 1, "joseph": 2}
 STOP_NONE, STOP_DP, STOP_NCP = 0, 1, 2
@@ -32,7 +33,8 @@ EXPORTS = ["abg_create_geometry", "abg_destroy_geometry", "abg_geometry_sizes",
            "abg_profile_read", "abg_request_bytes", "abg_engine_create", "abg_engine_destroy",
            "abg_engine_submit", "abg_engine_step", "abg_engine_poll", "abg_engine_set_tiles",
            "abg_engine_get_tiles", "abg_engine_autotune", "abg_batch_solve",
-           "abg_mgs_force_stream", "abg_geometry_set_model", "abg_geometry_get_model"]
+           "abg_mgs_force_stream", "abg_geometry_set_model", "abg_geometry_get_model",
+           "abg_geometry_set_strip_threshold"]
 
 
 class AbgError(RuntimeError):
@@ -114,6 +116,7 @@ def load_library(path: str | None = None):
     lib.abg_mgs_force_stream.argtypes = [i]
     lib.abg_geometry_set_model.argtypes = [vp, i]
     lib.abg_geometry_get_model.argtypes = [vp, ctypes.POINTER(i)]
+    lib.abg_geometry_set_strip_threshold.argtypes = [vp, ctypes.c_double, _dp]
     _lib = lib
     return lib
 
@@ -177,6 +180,14 @@ class Geometry:
         if model != "line":
             self.set_model(model)
 
+    def set_strip_threshold(self, tau: float) -> float:
+        """Threshold tau of the "strip_tau" back projector B_tau (Sec. 6.5); returns the
+        largest strip-model entry (abg_geometry_set_strip_threshold)."""
+        mx = ctypes.c_double()
+        _check(load_library().abg_geometry_set_strip_threshold(self._h, float(tau), ctypes.byref(mx)),
+               "abg_geometry_set_strip_threshold")
+        return mx.value
+
     def set_model(self, model: str):
         """Forward projector model: "line", "strip" or "joseph" (abg_geometry_set_model)."""
         _check(load_library().abg_geometry_set_model(self._h, FP_MODELS[model]),
@@ -225,8 +236,8 @@ class Geometry:
         return y
 
     def bp(self, y, kind: str = "hat", out=None, stream=None):
-        """x = B y (kind "hat", unmatched), A_line^T y ("adj"), A_strip^T y ("strip_t") or
-        A_Joseph^T y ("joseph_t")."""
+        """x = B y (kind "hat", unmatched), A_line^T y ("adj"), A_strip^T y ("strip_t"),
+        A_Joseph^T y ("joseph_t") or B_tau y ("strip_tau", set_strip_threshold)."""
         torch = _torch()
         assert y.is_cuda and y.is_contiguous() and y.numel() == self.m
         t = _dtype_code(y.dtype)
@@ -272,7 +283,8 @@ def gmres(method: str, g: Geometry, b, k_max: int, stop: str = "none", tau: floa
 
     b: CUDA tensor of m elements (float64 or float32: the projector dtype);
     basis: "f64", "f32" or "bf16" storage of the Krylov basis (default: b's dtype);
-    bp: back projector "hat", "adj", "strip_t" or "joseph_t" (A is the geometry's model).
+    bp: back projector "hat", "adj", "strip_t", "joseph_t" or "strip_tau" (A is the
+    geometry's model).
     """
     torch = _torch()
     lib = load_library()

@@ -252,6 +252,7 @@ template <typename T> struct alignas(16) BackStageV {
     T reach;              // footprint half-width in bins
     T js;                 // Joseph: ds / p^2;  strip: ds
     Trapezoid<T> tz;      // strip: footprint constants; Joseph: invp only
+    T thr;                // B_tau: smallest entry kept
 };
 
 template <typename T, int AB = kAngBlock> struct BackLdsV {
@@ -263,14 +264,16 @@ template <typename T, int AB = kAngBlock> struct BackLdsV {
     int ib[2][AB];
 };
 
+// KIND ABG_BP_STRIP_TAU: the strip transpose without the entries below tau_thr (B_tau).
 template <typename T, int KIND, int AB = kAngBlock, bool PAD = false>
 __device__ inline void back_tile_v(const T *__restrict__ y, T *__restrict__ x,
                                    const AngleParams *__restrict__ ang, int N, int n_ang,
                                    int n_det, double ds, double s0, int c0, int r0,
                                    BackLdsV<T, AB> &L, T *__restrict__ xr = nullptr,
-                                   T *__restrict__ xc = nullptr, int S = 0)
+                                   T *__restrict__ xc = nullptr, int S = 0, double tau_thr = -1.0)
 {
-    static_assert(KIND == ABG_BP_STRIP_T || KIND == ABG_BP_JOSEPH_T, "strip or Joseph");
+    static_assert(KIND == ABG_BP_STRIP_T || KIND == ABG_BP_JOSEPH_T || KIND == ABG_BP_STRIP_TAU,
+                  "strip, Joseph or thresholded strip");
     static_assert(AB <= kBackThreads, "one thread sets up one angle");
     constexpr int kIt = AB * kWinV / kBackThreads;     // window entries per thread and round
     static_assert(kIt * kBackThreads == AB * kWinV && kIt <= 32, "window split");
@@ -295,6 +298,7 @@ __device__ inline void back_tile_v(const T *__restrict__ y, T *__restrict__ x,
             st.su = T(Pn.su);
             st.su4 = T(4.0 * Pn.su);
             st.tz = Trapezoid<T>(Pn, ds);
+            st.thr = T(tau_thr);
             if (KIND == ABG_BP_JOSEPH_T) {
                 st.reach = T(Pn.p / ds);
                 st.js = T(ds * Pn.len * Pn.len);
@@ -341,6 +345,11 @@ __device__ inline void back_tile_v(const T *__restrict__ y, T *__restrict__ x,
             w[0] = P.tz.strip(e0 * P.js);
             w[1] = P.tz.strip(e1 * P.js);
             w[2] = P.tz.strip(e2 * P.js);
+            if constexpr (KIND == ABG_BP_STRIP_TAU) {
+                w[0] = w[0] >= P.thr ? w[0] : T(0);
+                w[1] = w[1] >= P.thr ? w[1] : T(0);
+                w[2] = w[2] >= P.thr ? w[2] : T(0);
+            }
         }
         return fma(w[0], win[k0], fma(w[1], win[k0 + 1], w[2] * win[k0 + 2]));
     };

@@ -1,5 +1,6 @@
 // extern "C" entry points of libabgmres: argument checking, geometry set-up (angle
 // table, Table 6.1 parameters), dispatch to the HIP launchers, and launch timing.
+#include <algorithm>
 #include <atomic>
 #include <cmath>
 #include <mutex>
@@ -221,6 +222,64 @@ int abg_destroy_geometry(abg_geometry *h)
     return rc;
 }
 
+namespace {
+
+// Strip-model weight (area of pixel and strip over ds) of a pixel whose centre lies e >= 0
+// from the ray (detector units), for an angle with p = max(|cos|,|sin|), q = min(...):
+// the integral of the line-model trapezoid over the strip.
+double trapezoid_below(double a, const AngleParams &P)
+{
+    const double h0 = P.p - P.half, h1 = P.half;
+    if (a >= h1) return 0.0;
+    if (a >= h0) return (h1 - a) * (h1 - a) * 0.5 * P.invpq;
+    return 0.5 * P.q * P.len + (h0 - a) * P.len;
+}
+
+double strip_weight(double e, const AngleParams &P, double ds)
+{
+    const double lo = e - 0.5 * ds, hi = e + 0.5 * ds;
+    const double glo = lo >= 0.0 ? trapezoid_below(lo, P) : 1.0 - trapezoid_below(-lo, P);
+    return (glo - trapezoid_below(hi, P)) / ds;
+}
+
+// Largest strip-model entry. An angle's entries are at most its weight at e = 0 (the weight
+// falls with e), so angles are visited in decreasing order of that bound and the scan
+// stops once no remaining angle can exceed the maximum found; each visited angle takes
+// every pixel at its nearest bin.
+double strip_max_entry(const Geometry &g)
+{
+    std::vector<std::pair<double, int>> order(g.n_ang);
+    for (int a = 0; a < g.n_ang; ++a) order[a] = {strip_weight(0.0, g.host[a], g.ds), a};
+    std::sort(order.begin(), order.end(), [](const auto &u, const auto &v) { return u.first > v.first; });
+    const double s0 = -0.5 * (g.n_det - 1) * g.ds;
+    double best = 0.0;
+    for (const auto &oa : order) {
+        if (oa.first <= best) break;
+        const AngleParams &P = g.host[oa.second];
+        for (int r = 0; r < g.N; ++r) {
+            const double yc = r - 0.5 * g.N + 0.5;
+            for (int c = 0; c < g.N; ++c) {
+                const double t0 = (c - 0.5 * g.N + 0.5) * P.c + yc * P.s;
+                long long i = std::llround((t0 - s0) / g.ds);
+                i = std::min<long long>(std::max<long long>(i, 0), g.n_det - 1);
+                best = std::max(best, strip_weight(std::fabs(s0 + i * g.ds - t0), P, g.ds));
+            }
+        }
+    }
+    return best;
+}
+
+}  // namespace
+
+int abg_geometry_set_strip_threshold(abg_geometry *h, double tau, double *max_entry)
+{
+    if (!h || !(tau >= 0.0 && tau <= 1.0) || !(h->g.ds <= 1.4)) return ABG_EINVAL;
+    if (h->g.strip_max <= 0.0) h->g.strip_max = strip_max_entry(h->g);
+    h->g.tau_thr = (tau - 1e-6) * h->g.strip_max;
+    if (max_entry) *max_entry = h->g.strip_max;
+    return ABG_OK;
+}
+
 int abg_geometry_set_model(abg_geometry *h, int fp_model)
 {
     if (!h || fp_model < ABG_FP_LINE || fp_model > ABG_FP_JOSEPH) return ABG_EINVAL;
@@ -267,7 +326,8 @@ int abg_bp_apply(const abg_geometry *h, int kind, int dtype, const void *y, void
                  void *stream)
 {
     if (!h || !x || !y || !valid_dtype_proj(dtype)) return ABG_EINVAL;
-    if (kind < ABG_BP_HAT || kind > ABG_BP_JOSEPH_T) return ABG_EINVAL;
+    if (kind < ABG_BP_HAT || kind > ABG_BP_STRIP_TAU) return ABG_EINVAL;
+    if (kind == ABG_BP_STRIP_TAU && !(h->g.ds <= 1.4)) return ABG_EINVAL;
     int rc = current_device_matches(h->g);
     if (rc) return rc;
     return launch_back(h->g, kind, dtype, y, x, static_cast<hipStream_t>(stream)) == hipSuccess
@@ -308,7 +368,8 @@ static int solve_entry(int method, const abg_geometry *h, int bp_kind, const voi
 {
     int rc = check_solver_args(h, method, k_max, p, st);
     if (rc) return rc;
-    if (bp_kind < ABG_BP_HAT || bp_kind > ABG_BP_JOSEPH_T) return ABG_EINVAL;
+    if (bp_kind < ABG_BP_HAT || bp_kind > ABG_BP_STRIP_TAU) return ABG_EINVAL;
+    if (bp_kind == ABG_BP_STRIP_TAU && !(h->g.ds <= 1.4)) return ABG_EINVAL;
     if (!b || !x || !ws || x == b || (x0 && x == x0)) return ABG_EINVAL;
     if (reinterpret_cast<uintptr_t>(ws) % 256) return ABG_EINVAL;
     if ((rc = current_device_matches(h->g))) return rc;

@@ -32,6 +32,9 @@ struct Geometry {
     int N = 0, n_ang = 0, n_det = 0;
     double ds = 1.0;
     int model = 0;      // forward projector: ABG_FP_LINE, ABG_FP_STRIP or ABG_FP_JOSEPH
+    // thresholded strip back projector B_tau: entries below tau_thr are dropped
+    double strip_max = 0.0;   // largest strip-model entry (0: not computed yet)
+    double tau_thr = -1.0;    // tau * strip_max - tie band (tau = 0: keep every entry)
     int device = 0;
     std::vector<double> theta;
     std::vector<AngleParams> host;

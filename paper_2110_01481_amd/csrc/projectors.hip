@@ -77,18 +77,19 @@ constexpr int kSingleAngBlock = 64;
 template <typename T> constexpr int kBackMinWaves = 1;
 template <> constexpr int kBackMinWaves<float> = 8;
 
-// Transposes of the strip and interpolation models (KIND ABG_BP_STRIP_T / _JOSEPH_T).
+// Transposes of the strip and interpolation models (KIND ABG_BP_STRIP_T / _JOSEPH_T) and
+// the thresholded strip transpose (ABG_BP_STRIP_TAU, entries below tau_thr dropped).
 template <typename T, int KIND, bool PAD>
 __global__ __launch_bounds__(kBackThreads) void back_model_kernel(
     const T *__restrict__ y, T *__restrict__ x, const AngleParams *__restrict__ ang, int N,
-    int n_ang, int n_det, double ds, double s0, const DevState *st, int k)
+    int n_ang, int n_det, double ds, double s0, double tau_thr, const DevState *st, int k)
 {
     __shared__ BackLdsV<T, kSingleAngBlock> lds;
     if (halted(st, k)) return;
     const int S = N + 2 * kPad;
     back_tile_v<T, KIND, kSingleAngBlock, PAD>(y, x, ang, N, n_ang, n_det, ds, s0,
                                                blockIdx.x * kTile, blockIdx.y * kTile, lds, x,
-                                               x + (size_t)N * S, S);
+                                               x + (size_t)N * S, S, tau_thr);
 }
 
 template <typename T, bool ADJ, bool PAD>
@@ -142,12 +143,14 @@ hipError_t back_t(const Geometry &g, int kind, const void *y, void *x, hipStream
     dim3 grid((g.N + kTile - 1) / kTile, (g.N + kTile - 1) / kTile);
     const double s0 = -0.5 * (g.n_det - 1) * g.ds;
     ProfScope ps(kProfBack, s, st ? k : 0, true);
-    if (kind == ABG_BP_STRIP_T || kind == ABG_BP_JOSEPH_T) {
-        auto fn = kind == ABG_BP_STRIP_T ? back_model_kernel<T, ABG_BP_STRIP_T, PAD>
-                                         : back_model_kernel<T, ABG_BP_JOSEPH_T, PAD>;
+    if (kind == ABG_BP_STRIP_T || kind == ABG_BP_JOSEPH_T || kind == ABG_BP_STRIP_TAU) {
+        auto fn = kind == ABG_BP_STRIP_T    ? back_model_kernel<T, ABG_BP_STRIP_T, PAD>
+                  : kind == ABG_BP_JOSEPH_T ? back_model_kernel<T, ABG_BP_JOSEPH_T, PAD>
+                                            : back_model_kernel<T, ABG_BP_STRIP_TAU, PAD>;
         hipExtLaunchKernelGGL(fn, grid, dim3(kBackThreads), 0, s, ps.e0, ps.e1, 0,
                               static_cast<const T *>(y), static_cast<T *>(x),
-                              (const AngleParams *)g.dev, g.N, g.n_ang, g.n_det, g.ds, s0, st, k);
+                              (const AngleParams *)g.dev, g.N, g.n_ang, g.n_det, g.ds, s0,
+                              g.tau_thr, st, k);
         return hipGetLastError();
     }
     if (kind == ABG_BP_ADJ)

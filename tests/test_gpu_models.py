@@ -143,3 +143,46 @@ def test_strip_model_needs_narrow_bins_and_engine_takes_line_model_only(gpu_lib)
     b = torch.ones(gg.m, dtype=torch.float32, device="cuda")
     with pytest.raises(abg.AbgError):
         abg.batch_solve([abg.Problem(g=gg, method="ab", b=b, k_max=5, stop="none")])
+
+
+# ---- thresholded strip back projector B_tau (Sec. 6.5) ----------------------------------
+
+@pytest.mark.parametrize("kw", [GEOMS[0], GEOMS[1], GEOMS[3], GEOMS[5], GEOMS[6]], ids=_ids)
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("tau", [0.0, 0.1, 0.3, 0.5])
+def test_b_tau_matches_oracle(gpu_lib, kw, dt, tau):
+    """B_tau on the GPU (threshold from the library's own max(A_s)) against the oracle's;
+    tau = 0.5 puts axis-angle entries exactly on the threshold."""
+    import torch
+    go, gg = _pair(kw)
+    mx = gg.set_strip_threshold(tau)
+    assert abs(mx - go.strip_max()) <= 1e-12 * go.strip_max()
+    tdt = torch.float64 if dt == "f64" else torch.float32
+    tol = 1e-12 if dt == "f64" else 1e-5
+    rng = np.random.default_rng(14)
+    for y in (rng.uniform(size=go.m), go.A_model("strip", rng.uniform(size=go.n))):
+        want = go.B_tau(tau)(y)
+        got = gg.bp(torch.tensor(y, dtype=tdt, device="cuda"), "strip_tau").double().cpu().numpy()
+        assert _rel(got, want) <= tol, (_rel(got, want), np.abs(got - want).max())
+
+
+@pytest.mark.parametrize("tau", [0.1, 0.5])
+@pytest.mark.parametrize("method", ["ab", "ba"])
+def test_strip_b_tau_pairs(gpu_lib, tau, method):
+    """The pair (A_s, B_tau) of Sec. 6.5, FP64 at k = 12 and FP32 with the DP stop,
+    against the oracle."""
+    import torch
+    import paper_2110_01481_amd as abg
+    go, _, b, enorm = _problem("strip")
+    gg = abg.Geometry(go.N, go.n_ang, go.n_det, model="strip")
+    gg.set_strip_threshold(tau)
+    f = O.ab_gmres if method == "ab" else O.ba_gmres
+    ref = f(go.fwd("strip"), go.B_tau(tau), b, 12)
+    r = abg.gmres(method, gg, torch.tensor(b, device="cuda"), 12, bp="strip_tau")
+    assert r.k_done == 12 and _rel(r.x.cpu().numpy(), ref.x) <= 1e-6
+    ref = f(go.fwd("strip"), go.B_tau(tau), b, 100, stop="dp", tau=1.02, noise_norm=enorm)
+    r = abg.gmres(method, gg, torch.tensor(b, dtype=torch.float32, device="cuda"), 100,
+                  stop="dp", tau=1.02, noise_norm=enorm, bp="strip_tau")
+    assert r.k_stop == ref.k_stop, (r.k_stop, ref.k_stop)
+    assert _rel(r.x.double().cpu().numpy(), ref.x) <= 1e-4
+
