@@ -309,6 +309,38 @@ def bench_models(abg, torch, dev, w, xb, reps=20):
     return out
 
 
+def bench_few_view(abg, torch, dev):
+    """Under-determined few-view scan (512^2, 180 angles: m = 0.5 n), AB- and BA-GMRES
+    with the DP rule in FP32: stopping iteration, time, Krylov-basis bytes (k+1 vectors of
+    length m for AB, n for BA) and relative reconstruction error."""
+    w = W.CONFIG_FEW_VIEW
+    g = abg.Geometry(w.N, w.n_ang, w.n_det, ang_range=w.ang_range)
+    xt = torch.tensor(w.phantom(), dtype=torch.float64, device=dev)
+    bc = g.fp(xt)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(9)
+    e = torch.randn(bc.numel(), generator=gen, device=dev, dtype=bc.dtype)
+    e *= w.eta * torch.linalg.vector_norm(bc) / torch.linalg.vector_norm(e)
+    b = (bc + e).float()
+    enorm = float(torch.linalg.vector_norm(e))
+    out = {"workload": f"{w.N}x{w.N}, {w.n_ang} angles, {w.n_det} bins (m = {w.m}, n = {w.n}), "
+                       f"{100 * w.eta:g}% noise, DP tau={w.tau}"}
+    for meth in ("ab", "ba"):
+        abg.gmres(meth, g, b, w.k_max, stop="dp", tau=w.tau, noise_norm=enorm)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = abg.gmres(meth, g, b, w.k_max, stop="dp", tau=w.tau, noise_norm=enorm)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        L = w.m if meth == "ab" else w.n
+        err = float(torch.linalg.vector_norm(r.x.double() - xt) / torch.linalg.vector_norm(xt))
+        out[meth] = {"k_stop": r.k_stop, "ms": round(1e3 * dt, 3),
+                     "iters_per_s": round(r.k_done / dt, 1),
+                     "basis_bytes": (r.k_done + 1) * L * 4, "rel_error": round(err, 4)}
+    g.release_workspace()
+    return out
+
+
 def bench_batched(abg, torch, dev, reps=3):
     """The 64-problem batched workload (N in {128..1024}, 60..720 angles, half limited
     angle, AB/BA alternating, per-problem DP): engine throughput after autotuning, next to
@@ -587,6 +619,7 @@ def main():
 
     if not args.no_models:
         extra["models"] = bench_models(abg, torch, dev, w, xb)
+        extra["few_view"] = bench_few_view(abg, torch, dev)
 
     tiles = None
     if not args.no_batch:

@@ -362,3 +362,28 @@ def test_degenerate_geometries(gpu_lib, N, n_ang, n_det):
         r = abg.gmres(method, gg, yt, 4)
         assert r.status == ref.status == "breakdown" and r.k_stop == ref.k_stop, (method, r.status, r.k_stop)
         assert np.allclose(r.x.cpu().numpy(), ref.x, rtol=1e-9, atol=1e-9)
+
+
+@pytest.mark.parametrize("size", ["small", "full"])
+@pytest.mark.parametrize("method", ["ab", "ba"])
+def test_few_view_underdetermined_discrepancy_principle(gpu_lib, size, method):
+    """Under-determined few-view scans (m < n; Sec. 6.2 reports the same conclusions there):
+    FP32 projectors and basis with the DP stop stop at the FP64 oracle's iteration with
+    the iterate within 1e-4 of the oracle's. Small: 64^2, 24 angles (m = 0.53 n); full:
+    512^2, 180 angles (m = 0.50 n)."""
+    import torch
+    import paper_2110_01481_amd as abg
+    w = W.CONFIG_FEW_VIEW if size == "full" else W.Workload(cfg=6, instance=1, N=64, n_ang=24,
+                                                            n_det=91, n_ellipses=5, eta=0.02,
+                                                            k_max=100, stop="dp", tau=1.02)
+    assert w.m < w.n
+    go = O.Geometry(w.N, w.n_ang, w.n_det)
+    xb = w.phantom()
+    b, enorm = W.add_noise(go.A(xb), w.eta, w.noise_dir())
+    f = O.ab_gmres if method == "ab" else O.ba_gmres
+    ref = f(go.A, go.B_hat, b, w.k_max, stop="dp", tau=w.tau, noise_norm=enorm)
+    gg = abg.Geometry(w.N, w.n_ang, w.n_det)
+    r = _solve(method, gg, b, w.k_max, dt="f32", stop="dp", tau=w.tau, noise_norm=enorm)
+    assert r.status == "ok" and r.k_stop == ref.k_stop, (r.k_stop, ref.k_stop)
+    assert _rel(r.x.double().cpu().numpy(), ref.x) <= 1e-4
+

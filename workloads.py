@@ -111,6 +111,10 @@ CONFIG2 = Workload(cfg=2, instance=0, N=512, n_ang=720, n_det=725, n_ellipses=20
                    k_max=100, stop="dp", tau=1.02)
 CONFIG3 = Workload(cfg=3, instance=0, N=2048, n_ang=1800, n_det=2897, n_ellipses=50,
                    eta=0.01, k_max=60, stop="ncp", method="ba")
+# Under-determined few-view scan (m < n), the regime Sec. 6.2 mentions beside the
+# over-determined one: a 512^2 ellipse phantom seen from 180 angles (m = 0.5 n).
+CONFIG_FEW_VIEW = Workload(cfg=6, instance=0, N=512, n_ang=180, n_det=725, n_ellipses=20,
+                           eta=0.02, k_max=100, stop="dp", tau=1.02)
 
 
 def batched_workloads(count: int = 64, cfg: int = 4):
