@@ -309,6 +309,40 @@ def bench_models(abg, torch, dev, w, xb, reps=20):
     return out
 
 
+def bench_histories(abg, torch, dev, w, xb, eta=0.003, K=150):
+    """Error histories of Sec. 6.2 with the markers of Sec. 6.3 on the workload's geometry
+    with the strip model A_s and noise ||e|| / ||A_s x|| = eta (the paper's histories use
+    0.3%): AB- and BA-GMRES for (A_s, A_l^T) and (A_s, A_i^T), LSQR and LSMR on A_s, FP32.
+    Per run: the minimum of ||x_k - x|| / ||x|| over k <= K and its k, k_DP (tau = 1) and
+    k_NCP with the errors there, the curve every 5 steps, and the time of its three solves
+    (the full history, DP, NCP)."""
+    from paper_2110_01481_amd import history as Hh
+    g = abg.Geometry(w.N, w.n_ang, w.n_det, ang_range=w.ang_range, model="strip")
+    bc = g.fp(torch.tensor(xb, dtype=torch.float64, device=dev)).cpu().numpy()
+    b, enorm = W.add_noise(bc, eta, W.rng(w.cfg, w.instance, 11).standard_normal(bc.size))
+    out = {"workload": f"{w.N}x{w.N}, {w.n_ang} angles, {w.n_det} bins, A_s (strip model), "
+                       f"{100 * eta:g}% noise, K = {K}, FP32 projectors and basis"}
+    runs = [("ab", "adj"), ("ba", "adj"), ("ab", "joseph_t"), ("ba", "joseph_t"),
+            ("lsqr", None), ("lsmr", None)]
+    for meth, bp in runs:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h = Hh.error_history(meth, g, b, xb, K, enorm, tau=1.0, bp=bp or "adj", dtype="f32")
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        name = f"{meth}:A_s,B_{bp}" if bp else f"{meth}:A_s"
+
+        def r4(v):
+            return None if v is None else round(v, 4)
+
+        out[name] = {"k_min": h.k_min, "err_min": r4(h.err_min), "k_dp": h.k_dp,
+                     "err_dp": r4(h.err_dp), "k_ncp": h.k_ncp, "err_ncp": r4(h.err_ncp),
+                     "curve_every_5": [r4(float(v)) for v in h.rel_err[4::5]],
+                     "s": round(dt, 3)}
+    g.release_workspace()
+    return out
+
+
 def bench_few_view(abg, torch, dev):
     """Under-determined few-view scan (512^2, 180 angles: m = 0.5 n), AB- and BA-GMRES
     with the DP rule in FP32: stopping iteration, time, Krylov-basis bytes (k+1 vectors of
@@ -620,6 +654,7 @@ def main():
     if not args.no_models:
         extra["models"] = bench_models(abg, torch, dev, w, xb)
         extra["few_view"] = bench_few_view(abg, torch, dev)
+        extra["histories"] = bench_histories(abg, torch, dev, w, xb)
 
     tiles = None
     if not args.no_batch:

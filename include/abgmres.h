@@ -78,7 +78,7 @@ typedef enum {
 /* Discretisation models of the forward projector A (Sec. 6.1). */
 typedef enum { ABG_FP_LINE = 0, ABG_FP_STRIP = 1, ABG_FP_JOSEPH = 2 } abg_fp_model;
 typedef enum { ABG_STOP_NONE = 0, ABG_STOP_DP = 1, ABG_STOP_NCP = 2 } abg_stop_kind;
-typedef enum { ABG_METHOD_AB = 0, ABG_METHOD_BA = 1 } abg_method;
+typedef enum { ABG_METHOD_AB = 0, ABG_METHOD_BA = 1, ABG_METHOD_LSQR = 2, ABG_METHOD_LSMR = 3 } abg_method;
 
 typedef struct abg_geometry abg_geometry;
 
@@ -190,6 +190,51 @@ int abg_ab_gmres(const abg_geometry *g, int bp_kind, const void *b, const void *
 int abg_ba_gmres(const abg_geometry *g, int bp_kind, const void *b, const void *x0, void *x,
                  int k_max, abg_stop st, abg_precision p, void *ws, size_t ws_bytes,
                  abg_info *info, void *stream);
+
+/* Error history of a finished solve (the semi-convergence curves of Sec. 6.2: the error
+ * of each iterate against a known image falls, reaches a minimum, then grows as noise
+ * is fitted). Called after abg_ab_gmres (method 0) or abg_ba_gmres (method 1) returned
+ * on `ws` with the same g, bp_kind, k_max, st, p and x0, before ws is used again:
+ * err[k-1] = ||x_k - x_ref||_2 for k = 1..k_done (host array of k_done doubles), where
+ * x_k is rebuilt from the basis and the k-step small-problem solution that the solve
+ * left in ws, so k_done may not exceed the steps the solve completed (info->k_done).
+ * x_ref: n elements of p.proj (device). Overwrites the solve's scratch vectors (not x).
+ * Synchronises `stream`. Returns ABG_EINVAL when ws holds fewer than k_done completed
+ * steps or an argument is invalid. */
+int abg_gmres_error_history(const abg_geometry *g, int method, int bp_kind, int k_max,
+                            abg_stop st, abg_precision p, const void *x0, const void *x_ref,
+                            void *ws, size_t ws_bytes, int k_done, double *err,
+                            void *stream);
+
+/* ---- matched comparators (Sec. 5, 6.2) ----------------------------------------------- */
+/*
+ * LSQR (Paige & Saunders) and LSMR (Fong & Saunders): the methods AB-GMRES and BA-GMRES
+ * become with B = A^T (Sec. 5), run by the paper as comparators (Table 6.3). A is the
+ * geometry's forward model and the back projector its exact transpose. Golub-Kahan
+ * bidiagonalisation with short recurrences (no basis is stored; no reorthogonalisation),
+ * FP64 scalars. LSQR minimises ||b - A x|| over K_k(A^T A, A^T r_0), LSMR ||A^T (b - A x)||.
+ * Stopping rules ABG_STOP_NONE, ABG_STOP_DP (the residual estimate -- LSQR's phibar,
+ * LSMR's recurred residual -- raises a candidate, confirmed with ||b - A x_k||) and
+ * ABG_STOP_NCP (Sec. 6.3: every step forms the explicit residual b - A x_k, one extra
+ * forward projection, and its periodogram distance d_k; the first k >= 2 with
+ * d_k > d_{k-1} returns x_{k-1}, kept by the step; without such a k, x_{k_max}, the
+ * iterate of smallest d). info->res_hist receives the residual estimates (explicit
+ * residual norms in NCP runs), info->ls_hist the estimates of ||A^T r_k||, ncp_hist d_k
+ * (NCP runs); info->H is not filled. Returns as abg_ab_gmres; ABG_BREAKDOWN when the
+ * bidiagonalisation ends (alpha or beta = 0: x_k solves the least squares problem).
+ * b: m elements, x0 (or NULL) and x: n elements, all of `dtype` (ABG_F64 or ABG_F32,
+ * device); ws: abg_lsq_workspace_bytes(g, method, dtype) bytes, 256-byte aligned; k_max
+ * in 1..500. Error history (Sec. 6.2): with x_ref (n elements of dtype, device) and
+ * err_hist (host, k_max doubles) both given, err_hist[k-1] = ||x_k - x_ref||_2 for every
+ * step performed; both NULL otherwise. Synchronises `stream` before returning.
+ */
+size_t abg_lsq_workspace_bytes(const abg_geometry *g, int method, int dtype);
+int abg_lsqr(const abg_geometry *g, const void *b, const void *x0, void *x, int k_max,
+             abg_stop st, int dtype, void *ws, size_t ws_bytes, abg_info *info,
+             const void *x_ref, double *err_hist, void *stream);
+int abg_lsmr(const abg_geometry *g, const void *b, const void *x0, void *x, int k_max,
+             abg_stop st, int dtype, void *ws, size_t ws_bytes, abg_info *info,
+             const void *x_ref, double *err_hist, void *stream);
 
 /* Static description of a status code. */
 const char *abg_status_string(int status);

@@ -23,7 +23,7 @@ BP_KINDS = {"hat": BP_HAT, "adj": BP_ADJ, "strip_t": BP_STRIP_T, "joseph_t": BP_
 # forward projector models (Sec. 6.1)
 FP_MODELS = {"line": 0, "strip": 1, "joseph": 2}
 STOP_NONE, STOP_DP, STOP_NCP = 0, 1, 2
-METHOD_AB, METHOD_BA = 0, 1
+METHOD_AB, METHOD_BA, METHOD_LSQR, METHOD_LSMR = 0, 1, 2, 3
 
 STATUS = {0: "ok", -1: "einval", -2: "enomem", -3: "ehip", -4: "enan", -5: "edevice",
           -6: "efull", 1: "not_converged", 2: "breakdown", 3: "zero_rhs"}
@@ -34,7 +34,8 @@ EXPORTS = ["abg_create_geometry", "abg_destroy_geometry", "abg_geometry_sizes",
            "abg_engine_submit", "abg_engine_step", "abg_engine_poll", "abg_engine_set_tiles",
            "abg_engine_get_tiles", "abg_engine_autotune", "abg_batch_solve",
            "abg_mgs_force_stream", "abg_geometry_set_model", "abg_geometry_get_model",
-           "abg_geometry_set_strip_threshold"]
+           "abg_geometry_set_strip_threshold", "abg_lsq_workspace_bytes", "abg_lsqr", "abg_lsmr",
+           "abg_gmres_error_history"]
 
 
 class AbgError(RuntimeError):
@@ -117,6 +118,14 @@ def load_library(path: str | None = None):
     lib.abg_geometry_set_model.argtypes = [vp, i]
     lib.abg_geometry_get_model.argtypes = [vp, ctypes.POINTER(i)]
     lib.abg_geometry_set_strip_threshold.argtypes = [vp, ctypes.c_double, _dp]
+    lib.abg_lsq_workspace_bytes.restype = ctypes.c_size_t
+    lib.abg_lsq_workspace_bytes.argtypes = [vp, i, i]
+    for name in ("abg_lsqr", "abg_lsmr"):
+        f = getattr(lib, name)
+        f.argtypes = [vp, vp, vp, vp, i, Stop, i, vp, ctypes.c_size_t, ctypes.POINTER(Info), vp,
+                      _dp, vp]
+    lib.abg_gmres_error_history.argtypes = [vp, i, i, i, Stop, Precision, vp, vp, vp, sz, i, _dp,
+                                            vp]
     _lib = lib
     return lib
 
@@ -264,6 +273,7 @@ class SolveResult:
     ncp_hist: np.ndarray
     H: np.ndarray | None = None
     extra: dict = field(default_factory=dict)
+    err_hist: np.ndarray | None = None   # ||x_k - x_ref|| per k (runs given x_ref)
 
 
 _DTYPES = {"f64": F64, "f32": F32, "bf16": BF16}
@@ -278,13 +288,16 @@ def workspace_bytes(g: Geometry, method: str, k_max: int, proj="f32", basis="f32
 
 def gmres(method: str, g: Geometry, b, k_max: int, stop: str = "none", tau: float = 1.0,
           noise_norm: float = 0.0, bp: str = "hat", basis: str | None = None, x0=None,
-          out=None, workspace=None, want_H: bool = False, stream=None) -> SolveResult:
+          out=None, workspace=None, want_H: bool = False, x_ref=None,
+          stream=None) -> SolveResult:
     """AB-GMRES (method "ab") or BA-GMRES ("ba") through the C ABI.
 
     b: CUDA tensor of m elements (float64 or float32: the projector dtype);
     basis: "f64", "f32" or "bf16" storage of the Krylov basis (default: b's dtype);
     bp: back projector "hat", "adj", "strip_t", "joseph_t" or "strip_tau" (A is the
-    geometry's model).
+    geometry's model);
+    x_ref: optional CUDA tensor of n elements (b's dtype): the result's err_hist then holds
+    ||x_k - x_ref|| for k = 1..k_done (abg_gmres_error_history on the solve's workspace).
     """
     torch = _torch()
     lib = load_library()
@@ -316,13 +329,79 @@ def gmres(method: str, g: Geometry, b, k_max: int, stop: str = "none", tau: floa
             ws.numel(), ctypes.byref(info), _stream_ptr(stream))
     _check(rc, "abg_%s_gmres" % method, ok=(0, 1, 2, 3))
     kd = info.k_done
+    err = None
+    if x_ref is not None:
+        assert x_ref.is_cuda and x_ref.dtype == b.dtype and x_ref.numel() == g.n
+        x_ref = x_ref.contiguous()
+        err = np.zeros(max(kd, 1))
+        rc2 = lib.abg_gmres_error_history(g.handle, meth, BP_KINDS[bp], int(k_max), st, prec,
+                                          x0p, ctypes.c_void_p(x_ref.data_ptr()),
+                                          ctypes.c_void_p(ws.data_ptr()), ws.numel(), kd,
+                                          err.ctypes.data_as(_dp), _stream_ptr(stream))
+        _check(rc2, "abg_gmres_error_history")
+        err = err[:kd].copy()
     Hm = None
     if H is not None:
         Hm = H.T[:kd + 1, :kd].copy()   # column-major (k_max+1) x k_max in memory
     return SolveResult(x=x, status=STATUS[rc], k_stop=info.k_stop, k_done=kd,
                        res_norm=info.res_norm, ncp_dist=info.ncp_dist, beta=info.beta,
                        n_literal=info.n_literal, res_hist=res[:kd].copy(),
-                       ls_hist=ls[:kd].copy(), ncp_hist=ncp[:kd].copy(), H=Hm)
+                       ls_hist=ls[:kd].copy(), ncp_hist=ncp[:kd].copy(), H=Hm, err_hist=err)
+
+
+def lsq_workspace_bytes(g: Geometry, method: str, dtype="f64") -> int:
+    """Workspace bytes of LSQR ("lsqr") or LSMR ("lsmr") (abg_lsq_workspace_bytes)."""
+    meth = METHOD_LSQR if method == "lsqr" else METHOD_LSMR
+    return int(load_library().abg_lsq_workspace_bytes(g.handle, meth, _DTYPES[dtype]))
+
+
+def lsq(method: str, g: Geometry, b, k_max: int, stop: str = "none", tau: float = 1.0,
+        noise_norm: float = 0.0, x0=None, out=None, workspace=None, x_ref=None,
+        stream=None) -> SolveResult:
+    """LSQR (method "lsqr") or LSMR ("lsmr") with the geometry's model A and its exact
+    transpose, through the C ABI (abg_lsqr / abg_lsmr). b: CUDA tensor of m elements
+    (float64 or float32); x_ref: optional CUDA tensor of n elements (b's dtype): the
+    result's err_hist then holds ||x_k - x_ref|| per step."""
+    torch = _torch()
+    lib = load_library()
+    assert b.is_cuda and b.is_contiguous() and b.numel() == g.m
+    t = _dtype_code(b.dtype)
+    meth = METHOD_LSQR if method == "lsqr" else METHOD_LSMR
+    st = Stop({"none": STOP_NONE, "dp": STOP_DP, "ncp": STOP_NCP}[stop], float(tau),
+              float(noise_norm))
+    nb = lib.abg_lsq_workspace_bytes(g.handle, meth, t)
+    if nb == 0:
+        raise AbgError(-1, "abg_lsq_workspace_bytes")
+    ws = workspace if workspace is not None else _dev_empty(nb, b.device)
+    x = out if out is not None else torch.empty(g.n, dtype=b.dtype, device=b.device)
+    res = np.zeros(k_max)
+    ls = np.zeros(k_max)
+    ncp = np.zeros(k_max)
+    info = Info()
+    info.res_hist = res.ctypes.data_as(_dp)
+    info.ls_hist = ls.ctypes.data_as(_dp)
+    info.ncp_hist = ncp.ctypes.data_as(_dp)
+    info.hist_len = k_max
+    info.H = None
+    fn = lib.abg_lsqr if meth == METHOD_LSQR else lib.abg_lsmr
+    x0p = ctypes.c_void_p(x0.data_ptr()) if x0 is not None else None
+    err = None
+    xr = None
+    if x_ref is not None:
+        assert x_ref.is_cuda and x_ref.dtype == b.dtype and x_ref.numel() == g.n
+        x_ref = x_ref.contiguous()
+        xr = ctypes.c_void_p(x_ref.data_ptr())
+        err = np.zeros(k_max)
+    rc = fn(g.handle, ctypes.c_void_p(b.data_ptr()), x0p, ctypes.c_void_p(x.data_ptr()), int(k_max),
+            st, t, ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.byref(info), xr,
+            err.ctypes.data_as(_dp) if err is not None else None, _stream_ptr(stream))
+    _check(rc, "abg_" + method, ok=(0, 1, 2, 3))
+    kd = info.k_done
+    return SolveResult(x=x, status=STATUS[rc], k_stop=info.k_stop, k_done=kd,
+                       res_norm=info.res_norm, ncp_dist=info.ncp_dist, beta=info.beta,
+                       n_literal=info.n_literal, res_hist=res[:kd].copy(), ls_hist=ls[:kd].copy(),
+                       ncp_hist=ncp[:kd].copy() if stop == "ncp" else np.zeros(0), H=None,
+                       err_hist=err[:kd].copy() if err is not None else None)
 
 
 def ab_gmres(g, b, k_max, **kw) -> SolveResult:

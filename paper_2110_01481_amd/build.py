@@ -16,7 +16,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libabgmres.so")
-SOURCES = ["capi.cpp", "projectors.hip", "krylov.hip", "ncp.hip", "solver.hip", "batch.hip"]
+SOURCES = ["capi.cpp", "projectors.hip", "krylov.hip", "ncp.hip", "solver.hip", "batch.hip",
+           "lsq.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall",

@@ -53,6 +53,7 @@ struct DevState {
     double ncp;          // d_k
     double ncp_prev;     // d_{k-1}
     double dp_thr;       // DP candidate threshold tau*||e||*(1+slack); 0 without DP
+    double err;          // ||x_k - x_ref|| (error-history runs only)
     int k;               // step that last completed its Givens update
     int bd_k;            // step at which h_{k+1,k} fell below the breakdown bound (0: none)
     int error;           // sticky: 1 grid-barrier timeout, 2 non-finite norm, 4 singular R
@@ -189,12 +190,52 @@ size_t ncp_scratch_bytes(const Geometry &g);
 hipError_t launch_ncp(const Geometry &g, int t, const void *r, double *scratch, DevState *st,
                       int k, hipStream_t s, DevState *snap = nullptr);
 
+// ---- LSQR / LSMR (lsq.hip) -------------------------------------------------------------
+// FP64 scalars of the recurrences (device memory). alpha, beta: alpha_k, beta_k of the
+// current step; alpha_n, beta_n: alpha_{k+1}, beta_{k+1} once computed.
+struct LsqScalars {
+    double alpha, beta, alpha_n, beta_n;
+    double rhobar, phibar;                                          // LSQR
+    double alphabar, zetabar, rho_prev, rhobar_prev, cbar, sbar;    // LSMR
+    double theta, hcoef, xcoef;                                     // LSMR
+};
+// u <- t - (alpha/beta) u, beta_n = ||u||; with ah: ah <- t - (theta/rho_prev) ah.
+hipError_t launch_lsq_u(int t, void *u, const void *tv, void *ah, long long m, LsqScalars *S,
+                        double *partials, unsigned *count, DevState *st, int k, hipStream_t s);
+// v <- s/beta_n - beta_n v, alpha_n = ||v||.
+hipError_t launch_lsq_v(int t, void *v, const void *sv, long long n, LsqScalars *S,
+                        double *partials, unsigned *count, DevState *st, int k, hipStream_t s);
+// xprev (optional): receives the previous iterate
+hipError_t launch_lsqr_x(int t, void *x, void *xprev, void *w, void *v, long long n,
+                         LsqScalars *S, unsigned *count, DevState *st, int k, DevState *snap,
+                         hipStream_t s);
+hipError_t launch_lsmr_x(int t, void *x, void *xprev, void *h, void *hbar, void *v, long long n,
+                         LsqScalars *S, unsigned *count, DevState *st, int k, hipStream_t s);
+hipError_t launch_lsmr_r(int t, const void *ah, void *ahbar, void *r, long long m, LsqScalars *S,
+                         double *partials, unsigned *count, DevState *st, int k, DevState *snap,
+                         hipStream_t s);
+hipError_t launch_lsq_start(int t, void *v, void *w, void *hbar, long long n, LsqScalars *S,
+                            unsigned *count, DevState *st, int lsmr, hipStream_t s);
+
 // ---- solvers (solver.hip) -----------------------------------------------------------
 size_t solver_workspace_bytes(const Geometry &g, int method, int k_max, abg_precision p,
                               abg_stop st);
+// LSQR (method ABG_METHOD_LSQR) or LSMR (ABG_METHOD_LSMR) with A the geometry's model and
+// its exact transpose.
+size_t lsq_workspace_bytes(const Geometry &g, int method, int dtype);
+// x_ref (device, n elements) and err_hist (host, k_max entries), both optional together:
+// err_hist[k-1] = ||x_k - x_ref|| for every step k performed.
+int run_lsq(const Geometry &g, int method, const void *b, const void *x0, void *x, int k_max,
+            abg_stop st, int dtype, void *ws, size_t ws_bytes, abg_info *info,
+            const void *x_ref, double *err_hist, hipStream_t s);
 int run_solver(const Geometry &g, int method, int kind, const void *b, const void *x0,
                void *x, int k_max, abg_stop st, abg_precision p, void *ws, size_t ws_bytes,
                abg_info *info, hipStream_t s);
+// After run_solver on ws with the same arguments: err[k-1] = ||x_k - x_ref|| for
+// k = 1..k_done, each iterate rebuilt from the stored basis and small-problem solutions.
+int gmres_error_history(const Geometry &g, int method, int kind, int k_max, abg_stop st,
+                        abg_precision p, void *ws, size_t ws_bytes, const void *x0,
+                        const void *x_ref, int k_done, double *err, hipStream_t s);
 
 // ---- one problem of the batched engine (solver.hip) ------------------------------------
 // Buffers inside a solve's workspace (the same layout as a single solve).

@@ -395,6 +395,20 @@ int abg_ba_gmres(const abg_geometry *h, int bp_kind, const void *b, const void *
                        stream);
 }
 
+int abg_gmres_error_history(const abg_geometry *h, int method, int bp_kind, int k_max,
+                            abg_stop st, abg_precision p, const void *x0, const void *x_ref,
+                            void *ws, size_t ws_bytes, int k_done, double *err, void *stream)
+{
+    int rc = check_solver_args(h, method, k_max, p, st);
+    if (rc) return rc;
+    if (bp_kind < ABG_BP_HAT || bp_kind > ABG_BP_STRIP_TAU) return ABG_EINVAL;
+    if (!x_ref || !ws || (k_done > 0 && !err)) return ABG_EINVAL;
+    if (reinterpret_cast<uintptr_t>(ws) % 256) return ABG_EINVAL;
+    if ((rc = current_device_matches(h->g))) return rc;
+    return gmres_error_history(h->g, method, bp_kind, k_max, st, p, ws, ws_bytes, x0, x_ref,
+                               k_done, err, static_cast<hipStream_t>(stream));
+}
+
 // ---- batched engine ------------------------------------------------------------------
 
 size_t abg_request_bytes(const abg_geometry *h, int method, int k_max, abg_precision p,
@@ -528,6 +542,53 @@ int abg_mgs_force_stream(int on)
 {
     set_mgs_force_stream(on);
     return ABG_OK;
+}
+
+size_t abg_lsq_workspace_bytes(const abg_geometry *h, int method, int dtype)
+{
+    if (!h || (method != ABG_METHOD_LSQR && method != ABG_METHOD_LSMR) || !valid_dtype_proj(dtype))
+        return 0;
+    return lsq_workspace_bytes(h->g, method, dtype);
+}
+
+static int lsq_entry(int method, const abg_geometry *h, const void *b, const void *x0, void *x,
+                     int k_max, abg_stop st, int dtype, void *ws, size_t ws_bytes, abg_info *info,
+                     const void *x_ref, double *err_hist, void *stream)
+{
+    if (!h || !valid_dtype_proj(dtype) || k_max < 1 || k_max > 500) return ABG_EINVAL;
+    if (st.kind == ABG_STOP_DP) {
+        if (!(st.tau >= 1.0) || !(st.noise_norm > 0.0) || !std::isfinite(st.tau * st.noise_norm))
+            return ABG_EINVAL;
+    } else if (st.kind == ABG_STOP_NCP) {
+        if (h->g.n_det < 2 || h->g.n_det / 2 > 2048) return ABG_EINVAL;
+    } else if (st.kind != ABG_STOP_NONE) {
+        return ABG_EINVAL;
+    }
+    if (!b || !x || !ws || x == b || (x0 && x == x0)) return ABG_EINVAL;
+    if ((x_ref == nullptr) != (err_hist == nullptr) || (x_ref && x_ref == x)) return ABG_EINVAL;
+    if (reinterpret_cast<uintptr_t>(ws) % 256) return ABG_EINVAL;
+    int rc = current_device_matches(h->g);
+    if (rc) return rc;
+    rc = run_lsq(h->g, method, b, x0, x, k_max, st, dtype, ws, ws_bytes, info, x_ref, err_hist,
+                 static_cast<hipStream_t>(stream));
+    if (info) info->status = rc;
+    return rc;
+}
+
+int abg_lsqr(const abg_geometry *h, const void *b, const void *x0, void *x, int k_max, abg_stop st,
+             int dtype, void *ws, size_t ws_bytes, abg_info *info, const void *x_ref,
+             double *err_hist, void *stream)
+{
+    return lsq_entry(ABG_METHOD_LSQR, h, b, x0, x, k_max, st, dtype, ws, ws_bytes, info, x_ref,
+                     err_hist, stream);
+}
+
+int abg_lsmr(const abg_geometry *h, const void *b, const void *x0, void *x, int k_max, abg_stop st,
+             int dtype, void *ws, size_t ws_bytes, abg_info *info, const void *x_ref,
+             double *err_hist, void *stream)
+{
+    return lsq_entry(ABG_METHOD_LSMR, h, b, x0, x, k_max, st, dtype, ws, ws_bytes, info, x_ref,
+                     err_hist, stream);
 }
 
 const char *abg_status_string(int status)

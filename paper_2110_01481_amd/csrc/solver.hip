@@ -575,4 +575,297 @@ int run_solver(const Geometry &g, int method, int kind, const void *b, const voi
     return status;
 }
 
+int gmres_error_history(const Geometry &g, int method, int kind, int k_max, abg_stop st,
+                        abg_precision p, void *ws, size_t ws_bytes, const void *x0,
+                        const void *x_ref, int k_done, double *err, hipStream_t s)
+{
+    Solve S(g, method, kind, k_max, st, p, s, ws);
+    if (ws_bytes < S.ly.total) return ABG_ENOMEM;
+    if (k_done < 0 || k_done > k_max) return ABG_EINVAL;
+    CK(host_resources(S.hr, k_max));
+    // the workspace must hold k_done completed steps (their small-problem solutions)
+    DevState h;
+    RC(S.sync_read(h));
+    if (h.k < k_done) return ABG_EINVAL;
+    const long long n = g.n();
+    for (int k = 1; k <= k_done; ++k) {
+        // x_k into tn, then ||x_k - x_ref|| into host slot k
+        RC(S.build_x(S.ycol(k), k, x0, S.tn));
+        int nb = 0;
+        CK(launch_sub_norm(p.proj, x_ref, S.tn, S.tn, n, S.part, &nb, s));
+        CK(launch_reduce_sqrt(S.part, nb, &S.hr.dslots[k].err, s));
+    }
+    CK(hipStreamSynchronize(s));
+    for (int k = 1; k <= k_done; ++k) err[k - 1] = S.hr.slots[k].err;
+    return ABG_OK;
+}
+
+// ---- LSQR / LSMR -----------------------------------------------------------------------
+
+namespace {
+
+struct LsqLayout {
+    size_t u, t, tres, ah, ahbar, r, v, sv, w, hbar, xprev, fpws, ncp, part, count, S, st, total;
+};
+
+LsqLayout make_lsq_layout(const Geometry &g, int method, int dtype)
+{
+    LsqLayout ly{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += align256(std::max<size_t>(bytes, 1));
+        return o;
+    };
+    const size_t sx = dtype_size(dtype);
+    const size_t m = (size_t)g.m(), n = (size_t)g.n();
+    const bool lsmr = method == ABG_METHOD_LSMR;
+    ly.u = take(m * sx);
+    ly.t = take(m * sx);
+    ly.tres = take(m * sx);
+    ly.ah = lsmr ? take(m * sx) : 0;
+    ly.ahbar = lsmr ? take(m * sx) : 0;
+    ly.r = lsmr ? take(m * sx) : 0;
+    ly.v = take(n * sx);
+    ly.sv = take(n * sx);
+    ly.w = take(n * sx);               // LSQR w, LSMR h
+    ly.hbar = lsmr ? take(n * sx) : 0;
+    ly.xprev = take(n * sx);           // NCP runs: x_{k-1}
+    ly.fpws = take(fp_workspace_bytes(g, dtype));
+    ly.ncp = g.n_det >= 2 ? take(ncp_scratch_bytes(g)) : 0;
+    ly.part = take(2048 * 8);
+    ly.count = take(64);
+    ly.S = take(sizeof(LsqScalars));
+    ly.st = take(sizeof(DevState));
+    ly.total = off;
+    return ly;
+}
+
+}  // namespace
+
+size_t lsq_workspace_bytes(const Geometry &g, int method, int dtype)
+{
+    return make_lsq_layout(g, method, dtype).total;
+}
+
+int run_lsq(const Geometry &g, int method, const void *b, const void *x0, void *x, int k_max,
+            abg_stop st, int dtype, void *ws, size_t ws_bytes, abg_info *info,
+            const void *x_ref, double *err_hist, hipStream_t s)
+{
+    const LsqLayout ly = make_lsq_layout(g, method, dtype);
+    if (ws_bytes < ly.total) return ABG_ENOMEM;
+    const bool lsmr = method == ABG_METHOD_LSMR;
+    char *W = static_cast<char *>(ws);
+    void *u = W + ly.u, *t = W + ly.t, *tres = W + ly.tres, *v = W + ly.v, *sv = W + ly.sv,
+         *w = W + ly.w, *fpws = W + ly.fpws;
+    void *ah = lsmr ? W + ly.ah : nullptr, *ahbar = lsmr ? W + ly.ahbar : nullptr;
+    void *r = lsmr ? W + ly.r : nullptr, *hbar = lsmr ? W + ly.hbar : nullptr;
+    const bool ncp_stop = st.kind == ABG_STOP_NCP;
+    if (ncp_stop && !ly.ncp) return ABG_EINVAL;
+    void *xprev = ncp_stop ? W + ly.xprev : nullptr;
+    double *ncp = ncp_stop ? reinterpret_cast<double *>(W + ly.ncp) : nullptr;
+    double *part = reinterpret_cast<double *>(W + ly.part);
+    unsigned *count = reinterpret_cast<unsigned *>(W + ly.count);
+    LsqScalars *S = reinterpret_cast<LsqScalars *>(W + ly.S);
+    DevState *dst = reinterpret_cast<DevState *>(W + ly.st);
+    const long long m = g.m(), n = g.n();
+    const size_t sx = dtype_size(dtype);
+    // the forward projector's exact transpose
+    const int bkind = g.model == ABG_FP_STRIP    ? ABG_BP_STRIP_T
+                      : g.model == ABG_FP_JOSEPH ? ABG_BP_JOSEPH_T
+                                                 : ABG_BP_ADJ;
+    HostRes hr;
+    CK(host_resources(hr, k_max));
+    struct ProfSolve {
+        int last = 0;
+        bool done = false;
+        ProfSolve() { profile_solve_begin(); }
+        void finish()
+        {
+            if (!done) profile_solve_end(last);
+            done = true;
+        }
+        ~ProfSolve() { finish(); }
+    } prof;
+    const double thr = st.kind == ABG_STOP_DP ? st.tau * st.noise_norm : 0.0;
+    DevState init{};
+    init.dp_thr = st.kind == ABG_STOP_DP ? thr * (1.0 + dp_slack(dtype)) : 0.0;
+
+    // scalars: alpha_0 = 0, beta_0 = 1 (the first u step copies t), rho_0 = 1
+    auto words = [](size_t bytes) { return (unsigned long long)(bytes / 4); };
+    const unsigned one_hi = 0x3ff00000u;
+    const size_t xb = (size_t)n * sx;
+    std::vector<FillRange> fr = {
+        {count, nullptr, 16, 0, 0u, 0u},
+        {S, nullptr, words(sizeof(LsqScalars)), 0, 0u, 0u},
+        {u, nullptr, words((size_t)m * sx), 0, 0u, 0u},  // the first step reads 0 * u
+        {v, nullptr, words(xb), 0, 0u, 0u},
+        {fpws, nullptr, words(fp_workspace_bytes(g, dtype)), 0, 0u, 0u},
+        {x, x0, words(xb), x0 ? words(xb) : 0, 0u, 0u},
+    };
+    if (!x0) fr.push_back({t, b, words((size_t)m * sx), words((size_t)m * sx), 0u, 0u});
+    if (lsmr) {
+        fr.push_back({ah, nullptr, words((size_t)m * sx), 0, 0u, 0u});
+        fr.push_back({ahbar, nullptr, words((size_t)m * sx), 0, 0u, 0u});
+        if (!x0) fr.push_back({r, b, words((size_t)m * sx), words((size_t)m * sx), 0u, 0u});
+    }
+    CK(launch_init_fill(fr.data(), (int)fr.size(), &init, dst, s));
+    {
+        // beta_0 = 1 and rho_0 = 1 (after the zero fill of the scalars)
+        const FillRange ones[] = {
+            {&S->beta, nullptr, 2, 0, 0u, one_hi},
+            {&S->rho_prev, nullptr, 2, 0, 0u, one_hi},
+            {&S->rhobar_prev, nullptr, 2, 0, 0u, one_hi},
+            {&S->cbar, nullptr, 2, 0, 0u, one_hi},
+        };
+        CK(launch_init_fill(ones, 4, nullptr, nullptr, s));
+    }
+    if (x0) {
+        CK(launch_forward(g, dtype, x0, t, fpws, s, nullptr, 0, true));
+        int nb = 0;
+        CK(launch_sub_norm(dtype, b, t, t, m, part, &nb, s));
+        if (lsmr) CK(hipMemcpyAsync(r, t, (size_t)m * sx, hipMemcpyDeviceToDevice, s));
+    }
+    // beta_1 u_1 = b - A x0, alpha_1 v_1 = A^T u_1, v_1, w_1 / h_1 and the scalars
+    CK(launch_lsq_u(dtype, u, t, ah, m, S, part, count, nullptr, 0, s));
+    CK(launch_back(g, bkind, dtype, u, sv, s));
+    CK(launch_lsq_v(dtype, v, sv, n, S, part, count, nullptr, 0, s));
+    CK(launch_lsq_start(dtype, v, w, hbar, n, S, count, dst, lsmr ? 1 : 0, s));
+
+    auto enqueue_step = [&](int k) -> int {
+        CK(launch_forward(g, dtype, v, t, fpws, s, dst, k, true));
+        CK(launch_lsq_u(dtype, u, t, ah, m, S, part, count, dst, k, s));
+        CK(launch_back(g, bkind, dtype, u, sv, s, dst, k));
+        CK(launch_lsq_v(dtype, v, sv, n, S, part, count, dst, k, s));
+        // the scalars go to host slot k from the step's last kernel
+        DevState *snap = ncp_stop ? nullptr : hr.dslots + k;
+        if (lsmr) {
+            CK(launch_lsmr_x(dtype, x, xprev, w, hbar, v, n, S, count, dst, k, s));
+            CK(launch_lsmr_r(dtype, ah, ahbar, r, m, S, part, count, dst, k, snap, s));
+        } else {
+            CK(launch_lsqr_x(dtype, x, xprev, w, v, n, S, count, dst, k, snap, s));
+        }
+        if (ncp_stop) {
+            // the NCP distance of the explicit residual b - A x_k (its norm into res)
+            CK(launch_forward(g, dtype, x, tres, fpws, s, dst, k, true));
+            int nb = 0;
+            CK(launch_sub_norm(dtype, b, tres, tres, m, part, &nb, s));
+            CK(launch_reduce_sqrt(part, nb, &dst->res, s));
+            CK(launch_ncp(g, dtype, tres, ncp, dst, k, s, hr.dslots + k));
+        }
+        if (x_ref) {
+            // ||x_k - x_ref|| into slot k, after the step's copy of the scalars (sv is
+            // free until the next step's back projection)
+            int nb = 0;
+            CK(launch_sub_norm(dtype, x_ref, x, sv, n, part, &nb, s));
+            CK(launch_reduce_sqrt(part, nb, &hr.dslots[k].err, s));
+        }
+        CK(hipEventRecord(hr.ev[k % kRing], s));
+        return ABG_OK;
+    };
+    auto sync_read = [&](DevState &out) -> int {
+        CK(hipMemcpyAsync(&hr.slots[0], dst, sizeof(DevState), hipMemcpyDeviceToHost, s));
+        CK(hipStreamSynchronize(s));
+        out = hr.slots[0];
+        return ABG_OK;
+    };
+    // ||b - A x|| into dst->res
+    auto literal_residual = [&]() -> int {
+        CK(launch_forward(g, dtype, x, tres, fpws, s, nullptr, 0, true));
+        int nb = 0;
+        CK(launch_sub_norm(dtype, b, tres, tres, m, part, &nb, s));
+        CK(launch_reduce_sqrt(part, nb, &dst->res, s));
+        return ABG_OK;
+    };
+    auto hist = [&](double *arr, int k, double val) {
+        if (info && arr && k - 1 < info->hist_len) arr[k - 1] = val;
+    };
+
+    int k_sel = -1, k_done = 0, status = ABG_OK, n_literal = 0;
+    double res_final = 0.0, ncp_prev = 0.0, ncp_final = 0.0;
+    bool res_known = false, from_prev = false;
+    RC(enqueue_step(1));
+    for (int k = 1; k <= k_max && k_sel < 0; ++k) {
+        if (k < k_max) RC(enqueue_step(k + 1));
+        CK(hipEventSynchronize(hr.ev[k % kRing]));
+        const DevState sk = hr.slots[k];
+        if (sk.error & 1) return ABG_EDEVICE;
+        if (sk.error) return ABG_ENAN;
+        if (k == 1) {
+            if (info) info->beta = sk.beta;
+            if (sk.stop && sk.stop_reason == kStopZero) {
+                // b - A x0 = 0, or A^T (b - A x0) = 0: x0 is returned
+                status = sk.beta == 0.0 ? ABG_ZERO_RHS : ABG_BREAKDOWN;
+                k_sel = 0;
+                break;
+            }
+        }
+        k_done = k;
+        prof.last = k;
+        hist(info ? info->res_hist : nullptr, k, sk.res);
+        hist(info ? info->ls_hist : nullptr, k, sk.ls);
+        if (x_ref) err_hist[k - 1] = sk.err;
+        if (ncp_stop) {
+            hist(info ? info->ncp_hist : nullptr, k, sk.ncp);
+            if (sk.stop && sk.stop_k == k) {
+                // d_k > d_{k-1}: x_{k-1} (kept by the step's x kernel) is returned
+                k_sel = k - 1;
+                ncp_final = ncp_prev;
+                from_prev = true;
+                break;
+            }
+            ncp_prev = sk.ncp;
+            ncp_final = sk.ncp;
+        }
+        if (st.kind == ABG_STOP_DP && sk.stop && sk.stop_k == k) {
+            // candidate: confirm with the explicit residual of x_k (later steps are halted)
+            RC(literal_residual());
+            DevState h2;
+            RC(sync_read(h2));
+            ++n_literal;
+            if (h2.res <= thr) {
+                k_sel = k;
+                res_final = h2.res;
+                res_known = true;
+                break;
+            }
+            CK(launch_clear_stop(dst, s));
+            if (k < k_max) {
+                profile_drop_step(k + 1);
+                RC(enqueue_step(k + 1));
+            }
+        }
+        if (sk.bd_k == k) {
+            k_sel = k;
+            status = ABG_BREAKDOWN;
+            break;
+        }
+        if (k == k_max) {
+            k_sel = k;
+            status = st.kind == ABG_STOP_DP ? ABG_NOT_CONVERGED : ABG_OK;
+        }
+    }
+    if (k_sel < 0) k_sel = k_done;
+    if (from_prev) CK(hipMemcpyAsync(x, xprev, (size_t)n * sx, hipMemcpyDeviceToDevice, s));
+    if (!res_known) {
+        RC(literal_residual());
+        DevState hs;
+        RC(sync_read(hs));
+        res_final = hs.res;
+    }
+    if (!std::isfinite(res_final)) return ABG_ENAN;
+    if (status == ABG_ZERO_RHS || (k_sel == 0 && status == ABG_BREAKDOWN)) k_done = 0;
+    if (info) {
+        info->k_stop = k_sel;
+        info->k_done = k_done;
+        info->status = status;
+        info->n_literal = n_literal;
+        info->res_norm = res_final;
+        info->ncp_dist = ncp_stop ? ncp_final : 0.0;
+    }
+    prof.finish();
+    if (profiling_on()) profile_flush();
+    return status;
+}
+
 }  // namespace abg
