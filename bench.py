@@ -77,7 +77,7 @@ def summarize_counters(d: str) -> str:
     data["traffic_bytes_per_launch"] = int(1024 * (data["fetch_kib_per_dispatch"] * data["fetch_scale"] +
                                                    data["write_kib_per_dispatch"] * data["write_scale"]))
     b = ("python -u bench.py --steps 2 --warmup 1 --no-cpu-baseline --no-fp64 --no-batch "
-         "--serve-seconds 0")
+         "--serve-seconds 0 --no-models")
     c = "python -u bench.py --copy-calibration-mib 1024"
     lines = [
         "# HBM traffic of the forward projector (512x512 image, 720 x 725 sinogram, FP32)",
