@@ -325,7 +325,10 @@ int abg_batch_solve(const abg_request *r, int n, abg_precision p, int rays, int 
 /* ---- instrumentation -------------------------------------------------------------- */
 
 /* When enabled, solver calls bracket every forward- and back-projector launch with HIP
- * events on the solver's stream and accumulate their durations (process-wide). */
+ * events on the solver's stream and accumulate their durations (process-wide). Enabling
+ * creates the events it will need (about 8k, on the current device); the durations are
+ * read by abg_profile_read (or once 4096 launches are pending), so solves do not wait
+ * for them. */
 int abg_profile_enable(int on);
 /* Reads and (if reset) clears the accumulated counts and milliseconds: index 0 forward
  * projector, 1 back projector, 2 Gram-Schmidt, 3 basis combination. */

@@ -97,12 +97,20 @@ ProfScope::ProfScope(int kind_, hipStream_t s_, int step_, bool ext_)
     if (!ext) (void)hipEventRecord(e0, s);
 }
 
+namespace {
+// Launches whose events are read only when the counters are (or when this many wait):
+// reading them at the end of every solve would stall the host between solves.
+constexpr size_t kMaxPending = 4096;
+void flush_locked();
+}  // namespace
+
 ProfScope::~ProfScope()
 {
     if (!e0) return;
     if (!ext) (void)hipEventRecord(e1, s);
     std::lock_guard<std::mutex> lk(g_prof_mu);
     g_pending.push_back({kind, e0, e1, t_solve, step});
+    if (g_pending.size() >= kMaxPending) flush_locked();
 }
 
 void profile_solve_begin()
@@ -147,9 +155,10 @@ void profile_drop_step(int step)
     drop_pending(t_solve, [&](int st) { return st == step; });
 }
 
-void profile_flush()
+namespace {
+// Accumulates the durations of all pending launches (caller holds the lock).
+void flush_locked()
 {
-    std::lock_guard<std::mutex> lk(g_prof_mu);
     for (auto &p : g_pending) {
         float ms = 0.f;
         (void)hipEventSynchronize(p.e1);
@@ -161,6 +170,13 @@ void profile_flush()
         g_event_pool.push_back(p.e1);
     }
     g_pending.clear();
+}
+}  // namespace
+
+void profile_flush()
+{
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    flush_locked();
 }
 
 }  // namespace abg
@@ -612,6 +628,12 @@ int abg_profile_enable(int on)
 {
     std::lock_guard<std::mutex> lk(g_prof_mu);
     g_prof_on = on != 0;
+    // events for every launch that can be pending, created now rather than in the solves
+    while (g_prof_on && g_event_pool.size() < 2 * kMaxPending + 64) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return ABG_EHIP;
+        g_event_pool.push_back(e);
+    }
     return ABG_OK;
 }
 

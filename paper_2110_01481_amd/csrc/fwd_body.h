@@ -87,6 +87,12 @@ template <> struct Band<double> {
     {
         return min((unsigned)((int)floor(lo) + kPad), cmax);
     }
+    // padded column, unclamped; far outside the image it is clamped to +-2^30 so that the
+    // byte offset cannot wrap back into the row
+    __device__ int column_raw() const
+    {
+        return (int)fmin(fmax(floor(lo) + kPad, -0x1p30), 0x1p30);
+    }
     // length of the band segment left of the pixel edge at floor(lo) + 1
     __device__ double left_length(const BandWeights<double> &b) const
     {
@@ -123,6 +129,7 @@ template <> struct Band<float> {
     {
         return (unsigned)min(max(c, 0), (int)cmax);
     }
+    __device__ int column_raw() const { return c; }
     __device__ float left_length(const BandWeights<float> &b) const
     {
         const float w = fmaf((float)f, -b.invq * 0x1p-32f, b.invq);
@@ -143,6 +150,24 @@ __device__ inline Taps<T> load_taps(const T *row, unsigned col)
 {
     const unsigned boff = col * (unsigned)sizeof(T);
     return *reinterpret_cast<const Taps<T> *>(reinterpret_cast<const char *>(row) + boff);
+}
+
+// The same two taps through a buffer resource spanning exactly one padded row of S
+// elements: the hardware range check returns zero for a column outside the row (a lane
+// walking bands outside its own chord, negative columns included, as their unsigned byte
+// offset is huge), so the walk needs no clamp. Data format word of a raw gfx9 buffer.
+constexpr int kRawBufferFlags = 0x00020000;
+template <typename T>
+__device__ inline Taps<T> load_taps_row(const T *row, int S, int col)
+{
+    __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<T *>(row), (short)0, S * (int)sizeof(T), kRawBufferFlags);
+    const int boff = col * (int)sizeof(T);
+    if constexpr (sizeof(T) == 4) {
+        return __builtin_bit_cast(Taps<T>, __builtin_amdgcn_raw_buffer_load_b64(r, boff, 0, 0));
+    } else {
+        return __builtin_bit_cast(Taps<T>, __builtin_amdgcn_raw_buffer_load_b128(r, boff, 0, 0));
+    }
 }
 
 // Ray i of angle a (i may exceed n_det: such lanes only take part in the wave's band
@@ -208,24 +233,23 @@ __device__ inline void forward_ray(const T *__restrict__ xr, const T *__restrict
         const int wr0 = __builtin_amdgcn_readfirstlane(wave_min_i(r0));
         const int wr1 = __builtin_amdgcn_readfirstlane(wave_max_i(r1));
         Band<T> band(fma((double)wr0, P.m, lo0), P.m);
-        // row-start pointer (padding included): column offsets are unsigned
+        // row-start pointer (padding included); taps outside the padded row read zero
         const T *row = img - kPad + (size_t)wr0 * S;
         const BandWeights<T> bw(P.invq, P.len);
-        const unsigned cmax = (unsigned)(N + 2 * kPad - 2);
         int r = wr0;
         // four bands per trip, all loads issued before their use
         for (; r + 4 <= wr1; r += 4) {
-            unsigned c[4];
+            int c[4];
             T w[4], v0[4], v1[4];
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                c[j] = band.column(cmax);
+                c[j] = band.column_raw();
                 w[j] = band.left_length(bw);
                 band.next();
             }
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                const Taps<T> t = load_taps(row + (size_t)j * S, c[j]);
+                const Taps<T> t = load_taps_row(row + (size_t)j * S, S, c[j]);
                 v0[j] = t.a;
                 v1[j] = t.b;
             }
@@ -237,10 +261,10 @@ __device__ inline void forward_ray(const T *__restrict__ xr, const T *__restrict
             row += 4 * (size_t)S;
         }
         for (; r < wr1; ++r) {
-            const unsigned c = band.column(cmax);
+            const int c = band.column_raw();
             const T w = band.left_length(bw);
             band.next();
-            const Taps<T> t = load_taps(row, c);
+            const Taps<T> t = load_taps_row(row, S, c);
             acc = fma(w, t.a, acc);
             acc = fma(bw.len - w, t.b, acc);
             row += S;

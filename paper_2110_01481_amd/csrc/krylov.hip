@@ -16,12 +16,15 @@
 #include <mutex>
 #include <unordered_map>
 
+#include <hip/hip_ext.h>
+
 #include "krylov_body.h"
 
 namespace abg {
 namespace {
 
 constexpr int kCombU = 4;
+constexpr int kCombJ = 4;   // basis columns per trip of the combination
 
 // Ranks are handed out in the order blocks start, so the blocks holding ranks are
 // running; a group no larger than the blocks the device holds at once always completes
@@ -105,8 +108,9 @@ int g_force_stream = 0;
 // Streaming variant: a group of at most kStreamBlocks resident blocks.
 constexpr int kStreamBlocks = 512;
 
+// e0, e1: events stamped with the kernel's start and end (timing), or null
 template <typename TX, typename TV>
-hipError_t mgs_stream_go(const MgsDev &d, hipStream_t s)
+hipError_t mgs_stream_go(const MgsDev &d, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
     if (!d.q64) return hipErrorInvalidValue;
     const void *fn = reinterpret_cast<const void *>(&mgs_stream_kernel<TX, TV>);
@@ -114,12 +118,12 @@ hipError_t mgs_stream_go(const MgsDev &d, hipStream_t s)
     hipError_t e = resident_capacity(fn, &cap);
     if (e != hipSuccess) return e;
     const int G = std::min(kStreamBlocks, cap);
-    mgs_stream_kernel<TX, TV><<<G, kBlock, 0, s>>>(d);
+    hipExtLaunchKernelGGL(mgs_stream_kernel<TX, TV>, dim3(G), dim3(kBlock), 0, s, e0, e1, 0, d);
     return hipGetLastError();
 }
 
 template <typename TX, typename TV, int E>
-hipError_t mgs_go(const MgsDev &d, int G, hipStream_t s)
+hipError_t mgs_go(const MgsDev &d, int G, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
     const void *fn = reinterpret_cast<const void *>(&mgs_kernel<TX, TV, E>);
     int cap = 0;
@@ -127,15 +131,15 @@ hipError_t mgs_go(const MgsDev &d, int G, hipStream_t s)
     if (e != hipSuccess) return e;
     if (G > cap || G > kMaxGrid || (g_force_stream && d.q64)) {
         // q_k does not fit the registers of the blocks the device holds at once
-        if (d.q64) return mgs_stream_go<TX, TV>(d, s);
+        if (d.q64) return mgs_stream_go<TX, TV>(d, s, e0, e1);
         return hipErrorCooperativeLaunchTooLarge;
     }
-    mgs_kernel<TX, TV, E><<<G, kBlock, 0, s>>>(d);
+    hipExtLaunchKernelGGL(mgs_kernel<TX, TV, E>, dim3(G), dim3(kBlock), 0, s, e0, e1, 0, d);
     return hipGetLastError();
 }
 
 template <typename TX, typename TV>
-hipError_t mgs_dispatch(const MgsDev &d, hipStream_t s)
+hipError_t mgs_dispatch(const MgsDev &d, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
     // Smallest register tile E per thread such that target blocks cover L; beyond the
     // largest tile the grid grows instead.
@@ -147,14 +151,14 @@ hipError_t mgs_dispatch(const MgsDev &d, hipStream_t s)
     if (G < 1) G = 1;
     const int Gi = (int)G;
     switch (E) {
-    case 1: return mgs_go<TX, TV, 1>(d, Gi, s);
-    case 2: return mgs_go<TX, TV, 2>(d, Gi, s);
-    case 4: return mgs_go<TX, TV, 4>(d, Gi, s);
-    case 8: return mgs_go<TX, TV, 8>(d, Gi, s);
-    case 16: return mgs_go<TX, TV, 16>(d, Gi, s);
-    case 32: return mgs_go<TX, TV, 32>(d, Gi, s);
+    case 1: return mgs_go<TX, TV, 1>(d, Gi, s, e0, e1);
+    case 2: return mgs_go<TX, TV, 2>(d, Gi, s, e0, e1);
+    case 4: return mgs_go<TX, TV, 4>(d, Gi, s, e0, e1);
+    case 8: return mgs_go<TX, TV, 8>(d, Gi, s, e0, e1);
+    case 16: return mgs_go<TX, TV, 16>(d, Gi, s, e0, e1);
+    case 32: return mgs_go<TX, TV, 32>(d, Gi, s, e0, e1);
     default:
-        if constexpr (sizeof(TV) < 8) return mgs_go<TX, TV, 64>(d, Gi, s);
+        if constexpr (sizeof(TV) < 8) return mgs_go<TX, TV, 64>(d, Gi, s, e0, e1);
         return hipErrorInvalidValue;
     }
 }
@@ -190,7 +194,23 @@ __global__ __launch_bounds__(kBlock) void combine_kernel(const TB *__restrict__ 
             in[u] = l < L;
             acc[u] = (in[u] && base) ? bcoef * to_f64(base[l]) : 0.0;
         }
-        for (int j = 0; j < kk; ++j) {
+        // four columns' loads in flight at once; each element still sums over j in order
+        int j = 0;
+        for (; j + kCombJ <= kk; j += kCombJ) {
+            double x[kCombJ][kCombU];
+#pragma unroll
+            for (int jj = 0; jj < kCombJ; ++jj) {
+                const TV *v = V + (size_t)(j + jj) * ldv + l0;
+#pragma unroll
+                for (int u = 0; u < kCombU; ++u) x[jj][u] = in[u] ? to_f64(v[u * T]) : 0.0;
+            }
+#pragma unroll
+            for (int jj = 0; jj < kCombJ; ++jj) {
+#pragma unroll
+                for (int u = 0; u < kCombU; ++u) acc[u] = fma(cf[j + jj], x[jj][u], acc[u]);
+            }
+        }
+        for (; j < kk; ++j) {
             const TV *v = V + (size_t)j * ldv + l0;
             double x[kCombU];
 #pragma unroll
@@ -357,13 +377,14 @@ template <typename TO, typename TB, typename TV>
 hipError_t combine_go(const void *base, double bcoef, const void *V, size_t ldv, int kk,
                       const double *coef, double sgn, void *out, long long L, double *partials,
                       unsigned *count, double *norm, DevState *st, int k, DevState *snap,
-                      hipStream_t s)
+                      hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
     // with a norm, every block signals completion on one counter: keep the grid moderate
     const int nb = blocks_for((L + kCombU - 1) / kCombU, norm ? 512 : 1024);
-    combine_kernel<TO, TB, TV><<<nb, kBlock, 0, s>>>(
-        static_cast<const TB *>(base), bcoef, static_cast<const TV *>(V), ldv, kk, coef, sgn,
-        static_cast<TO *>(out), L, partials, count, norm, st, k, snap);
+    hipExtLaunchKernelGGL(combine_kernel<TO, TB, TV>, dim3(nb), dim3(kBlock), 0, s, e0, e1, 0,
+                          static_cast<const TB *>(base), bcoef, static_cast<const TV *>(V), ldv,
+                          kk, coef, sgn, static_cast<TO *>(out), L, partials, count, norm, st, k,
+                          snap);
     return hipGetLastError();
 }
 
@@ -399,14 +420,15 @@ hipError_t launch_mgs(const MgsLaunch &m, hipStream_t s)
                       m.giv_ld, m.snap};
     if (m.giv_H && (m.k < 1 || m.k + 1 > kMaxCoef)) return hipErrorInvalidValue;
     if (m.snap && !m.giv_H) return hipErrorInvalidValue;
-    ProfScope ps(kProfMgs, s, m.step);
+    // timed at the kernel's own start and end when profiling is on
+    ProfScope ps(kProfMgs, s, m.step, true);
     if (m.tx == ABG_F64) {
-        if (m.tv == ABG_F64) return mgs_dispatch<double, double>(d, s);
-        if (m.tv == ABG_F32) return mgs_dispatch<double, float>(d, s);
-        return mgs_dispatch<double, bf16>(d, s);
+        if (m.tv == ABG_F64) return mgs_dispatch<double, double>(d, s, ps.e0, ps.e1);
+        if (m.tv == ABG_F32) return mgs_dispatch<double, float>(d, s, ps.e0, ps.e1);
+        return mgs_dispatch<double, bf16>(d, s, ps.e0, ps.e1);
     }
-    if (m.tv == ABG_F32) return mgs_dispatch<float, float>(d, s);
-    if (m.tv == ABG_BF16) return mgs_dispatch<float, bf16>(d, s);
+    if (m.tv == ABG_F32) return mgs_dispatch<float, float>(d, s, ps.e0, ps.e1);
+    if (m.tv == ABG_BF16) return mgs_dispatch<float, bf16>(d, s, ps.e0, ps.e1);
     return hipErrorInvalidValue;
 }
 
@@ -417,10 +439,10 @@ hipError_t launch_combine(int tout, const void *base, double base_coef, int tv, 
 {
     if (kk > kMaxCoef) return hipErrorInvalidValue;
     if (snap && !(norm && st)) return hipErrorInvalidValue;
-    ProfScope ps(kProfCombine, s, st ? k : 0);
+    ProfScope ps(kProfCombine, s, st ? k : 0, true);
 #define ABG_COMBINE(TO, TB, TV) \
     combine_go<TO, TB, TV>(base, base_coef, V, ldv, kk, coef, sgn, out, L, partials, count, norm, st, k, \
-                           snap, s)
+                           snap, s, ps.e0, ps.e1)
     if (tout == ABG_F64) {
         if (tv == ABG_F64) return ABG_COMBINE(double, double, double);
         if (tv == ABG_F32) return ABG_COMBINE(double, double, float);

@@ -571,7 +571,6 @@ int run_solver(const Geometry &g, int method, int kind, const void *b, const voi
         }
     }
     prof.finish();
-    if (profiling_on()) profile_flush();
     return status;
 }
 
@@ -864,7 +863,6 @@ int run_lsq(const Geometry &g, int method, const void *b, const void *x0, void *
         info->ncp_dist = ncp_stop ? ncp_final : 0.0;
     }
     prof.finish();
-    if (profiling_on()) profile_flush();
     return status;
 }
 
