@@ -5,8 +5,9 @@ Calls only the oracle and the seeded input generators. Usage:
     python tests/golden/make_oracle_golden.py 3     # 2048^2, 1800 x 2897, NCP (an hour)
 
 Output: tests/golden/oracle_config<N>.json with, per solve, the stopping iteration, the
-residual / NCP histories and a fingerprint of the returned iterate (norm, inner
-products with seeded vectors, values at seeded pixels) that GPU tests compare with.
+residual / NCP histories, the error history against the phantom (config 2) and a
+fingerprint of the returned iterate (norm, inner products with seeded vectors, values at
+seeded pixels) that GPU tests compare with.
 """
 from __future__ import annotations
 
@@ -48,11 +49,15 @@ def run_config2(out_path: str):
     for method, f in (("ab", O.ab_gmres), ("ba", O.ba_gmres)):
         for kind in ("hat", "adj"):
             t0 = time.time()
-            r = f(g.A, g.back(kind), b, w.k_max, stop="dp", tau=w.tau, noise_norm=enorm)
+            r = f(g.A, g.back(kind), b, w.k_max, stop="dp", tau=w.tau, noise_norm=enorm,
+                  keep_iterates=True)
             res["solves"][f"{method}-{kind}"] = {
                 "k_stop": r.k_stop, "status": r.status, "res_norms": r.res_norms,
                 "dp_margin": r.dp_margin, "ls_res": r.ls_res,
                 "error_vs_truth": float(np.linalg.norm(r.x - xb) / np.linalg.norm(xb)),
+                # error history (Sec. 6.2): ||x_k - x_bar|| and ||x_k|| for k = 1..k_stop
+                "err_norms": [float(np.linalg.norm(x - xb)) for x in r.iterates],
+                "x_norms": [float(np.linalg.norm(x)) for x in r.iterates],
                 "x": fingerprint(r.x), "seconds": time.time() - t0}
             print(method, kind, r.k_stop, r.status, f"{time.time() - t0:.1f}s", flush=True)
     with open(out_path, "w") as fh:

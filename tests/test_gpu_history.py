@@ -203,3 +203,71 @@ def test_history_harness_markers(gpu_lib, cfg1, method):
     assert abs(ref_rel[h.k_min - 1] - ref_rel.min()) <= tol[h.k_min - 1] * xn[h.k_min - 1] + 1e-12
     if h.k_dp is not None:
         assert h.err_dp == h.rel_err[h.k_dp - 1]
+
+
+@pytest.fixture(scope="module")
+def config2():
+    """512^2 image, 720 x 725 sinogram, 2% noise: b = A x_true + e with the oracle's A, and
+    the oracle's DP solves (tests/golden/make_oracle_golden.py)."""
+    import json
+    import os
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "oracle_config2.json")))
+    w = W.CONFIG2
+    go = O.Geometry(w.N, w.n_ang, w.n_det)
+    xb = w.phantom()
+    b, enorm = W.add_noise(go.A(xb), w.eta, w.noise_dir())
+    assert abs(enorm - gold["noise_norm"]) <= 1e-9 * enorm
+    return w, xb, b, enorm, gold
+
+
+def _fingerprint_errors(x, fp):
+    rng = np.random.default_rng(99)
+    pix = np.asarray(fp["pixels"])
+    rng.choice(x.size, size=min(len(pix), x.size), replace=False)   # same stream as the writer
+    probes = [rng.standard_normal(x.size) for _ in range(len(fp["probe_dots"]))]
+    e_norm = abs(np.linalg.norm(x) - fp["norm"]) / fp["norm"]
+    e_pix = np.linalg.norm(x[pix] - np.asarray(fp["values"])) / np.linalg.norm(fp["values"])
+    e_dot = max(abs(v @ x - d) / (np.linalg.norm(v) * fp["norm"]) for v, d in zip(probes, fp["probe_dots"]))
+    return max(e_norm, e_pix, e_dot)
+
+
+@pytest.mark.parametrize("method", ["ab", "ba"])
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_full_size_gmres_error_history(gpu_lib, config2, method, dt):
+    """The bench's workload: DP solve with the unmatched B; the error history of every
+    iterate up to the stop against the oracle's, within the iterate bound (FP64 1e-6, FP32
+    1e-4) times ||x_k||."""
+    import paper_2110_01481_amd as abg
+    w, xb, b, enorm, gold = config2
+    ref = gold["solves"][f"{method}-hat"]
+    gg = abg.Geometry(w.N, w.n_ang, w.n_det)
+    r = abg.gmres(method, gg, _t(b, dt), w.k_max, stop="dp", tau=w.tau, noise_norm=enorm,
+                  bp="hat", x_ref=_t(xb, dt))
+    assert r.status == "ok" and r.k_stop == ref["k_stop"] and r.err_hist.shape == (r.k_stop,)
+    tol = 1e-6 if dt == "f64" else 1e-4
+    slack = 0.0 if dt == "f64" else np.linalg.norm(xb - xb.astype(np.float32))
+    dev = np.abs(r.err_hist - np.asarray(ref["err_norms"])) / np.asarray(ref["x_norms"])
+    print(f"{method} {dt}: max |err_k - err_k(oracle)| / ||x_k|| = {dev.max():.2e}")
+    assert np.all(np.abs(r.err_hist - np.asarray(ref["err_norms"]))
+                  <= tol * np.asarray(ref["x_norms"]) + slack), dev
+
+
+@pytest.mark.parametrize("method", ["lsqr", "lsmr"])
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_full_size_lsq_discrepancy_principle(gpu_lib, config2, method, dt):
+    """LSQR / LSMR at full size under DP (tau = 1.02): Sec. 5 makes them the oracle's matched
+    AB-/BA-GMRES, which stop at k = 7; the GPU stops there too, with the returned iterate
+    and the error history matching the oracle's."""
+    import paper_2110_01481_amd as abg
+    w, xb, b, enorm, gold = config2
+    ref = gold["solves"]["ab-adj" if method == "lsqr" else "ba-adj"]
+    gg = abg.Geometry(w.N, w.n_ang, w.n_det)
+    r = abg.lsq(method, gg, _t(b, dt), w.k_max, stop="dp", tau=w.tau, noise_norm=enorm,
+                x_ref=_t(xb, dt))
+    assert r.status == "ok" and r.k_stop == ref["k_stop"], (r.k_stop, ref["k_stop"])
+    e = _fingerprint_errors(r.x.double().cpu().numpy(), ref["x"])
+    dev = np.abs(r.err_hist - np.asarray(ref["err_norms"])) / np.asarray(ref["x_norms"])
+    print(f"{method} {dt}: iterate vs oracle {e:.2e}; error history {dev.max():.2e}")
+    tol = 1e-6 if dt == "f64" else 1e-4
+    assert e <= tol and dev.max() <= tol
+    assert abs(r.res_norm - ref["res_norms"][ref["k_stop"] - 1]) <= 1e-5 * ref["res_norms"][0]
