@@ -491,8 +491,9 @@ def main():
         print(summarize_counters(args.summarize_counters))
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus N > 1 is not supported "
-                                   "(multi-GPU sharding is a design note, not built)"}))
+        print(json.dumps({"error": "the solver library runs on one GPU; --gpus N > 1 is not "
+                                   "supported (how the path would shard is described, not "
+                                   "implemented)"}))
         sys.exit(2)
 
     import torch
