@@ -343,6 +343,34 @@ def bench_histories(abg, torch, dev, w, xb, eta=0.003, K=150):
     return out
 
 
+def bench_lsq(abg, torch, dev, w, xb, b32, enorm, reps=5):
+    """The matched comparators (Sec. 5, 6.2) on the timed workload's input: LSQR and LSMR
+    with A and its exact transpose, FP32, under the same DP rule: stopping iteration,
+    solve time (median of reps), iterations per second and ||x - x_true|| / ||x_true||.
+    Each step is one forward and one transposed projection with short recurrences."""
+    g = abg.Geometry(w.N, w.n_ang, w.n_det, ang_range=w.ang_range)
+    xt = torch.tensor(xb, dtype=torch.float64, device=dev)
+    out = {}
+    for meth in ("lsqr", "lsmr"):
+        nb = abg.lsq_workspace_bytes(g, meth, "f32")
+        ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+        x = torch.empty(g.n, dtype=torch.float32, device=dev)
+        times = []
+        for _ in range(reps + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = abg.lsq(meth, g, b32, w.k_max, stop="dp", tau=w.tau, noise_norm=enorm,
+                        workspace=ws, out=x)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        dt = float(np.median(times[1:]))
+        err = float(torch.linalg.vector_norm(r.x.double() - xt) / torch.linalg.vector_norm(xt))
+        out[meth] = {"k_stop": r.k_stop, "ms": round(1e3 * dt, 3),
+                     "iters_per_s": round(r.k_done / dt, 1), "n_literal": r.n_literal,
+                     "rel_error": round(err, 4)}
+    return out
+
+
 def bench_few_view(abg, torch, dev):
     """Under-determined few-view scan (512^2, 180 angles: m = 0.5 n), AB- and BA-GMRES
     with the DP rule in FP32: stopping iteration, time, Krylov-basis bytes (k+1 vectors of
@@ -669,6 +697,7 @@ def main():
         extra["models"] = bench_models(abg, torch, dev, w, xb)
         extra["few_view"] = bench_few_view(abg, torch, dev)
         extra["histories"] = bench_histories(abg, torch, dev, w, xb)
+        extra["lsq"] = bench_lsq(abg, torch, dev, w, xb, b32, enorm)
 
     tiles = None
     if not args.no_batch:
