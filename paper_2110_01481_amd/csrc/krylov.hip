@@ -141,12 +141,18 @@ hipError_t mgs_go(const MgsDev &d, int G, hipStream_t s, hipEvent_t e0, hipEvent
 template <typename TX, typename TV>
 hipError_t mgs_dispatch(const MgsDev &d, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
-    // Smallest register tile E per thread such that target blocks cover L; beyond the
-    // largest tile the grid grows instead.
+    // A vector one block can hold in its registers gets one block: its reductions stay
+    // inside the CU, where a reduction across the XCDs costs several microseconds. Longer
+    // vectors: the smallest register tile E per thread such that target blocks cover L;
+    // beyond the largest tile the grid grows instead.
     const long long L = d.L;
     const int maxE = sizeof(TV) == 8 ? 32 : 64;
     int E = 1;
-    while (E < maxE && (long long)g_target_blocks * kBlock * E < L) E *= 2;
+    if (L <= (long long)kBlock * maxE) {
+        while ((long long)kBlock * E < L) E *= 2;
+    } else {
+        while (E < maxE && (long long)g_target_blocks * kBlock * E < L) E *= 2;
+    }
     long long G = (L + (long long)kBlock * E - 1) / ((long long)kBlock * E);
     if (G < 1) G = 1;
     const int Gi = (int)G;

@@ -376,7 +376,9 @@ __device__ inline void mgs_body(const MgsDev &a, int rank, int G, double *lds)
             __hip_atomic_store(next + (size_t)r * G + rank, empty, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
     }
-    double qq = 0.0;
+    // a group of one block: its block sums are the totals, no exchange through memory
+    const bool solo = G == 1;
+    double qq = 0.0, h = 0.0;
     for (int i = 0; i < a.k; ++i) {
         const TV *w = static_cast<const TV *>(a.V) + (size_t)i * a.ldv + base;
         double d = 0.0, s2 = 0.0;
@@ -389,12 +391,17 @@ __device__ inline void mgs_body(const MgsDev &a, int rank, int G, double *lds)
         }
         d = block_sum(d, lds);
         if (i == 0) s2 = block_sum(s2, lds);
-        if (threadIdx.x == 0) {
-            publish(tab + (size_t)i * G + rank, d);
-            if (i == 0) publish(tab + (size_t)(a.k + 1) * G + rank, s2);
+        if (solo) {
+            h = d;
+            if (i == 0) qq = s2;
+        } else {
+            if (threadIdx.x == 0) {
+                publish(tab + (size_t)i * G + rank, d);
+                if (i == 0) publish(tab + (size_t)(a.k + 1) * G + rank, s2);
+            }
+            h = gather_total(tab + (size_t)i * G, G, lds, err);
+            if (i == 0) qq = gather_total(tab + (size_t)(a.k + 1) * G, G, lds, err);
         }
-        const double h = gather_total(tab + (size_t)i * G, G, lds, err);
-        if (i == 0) qq = gather_total(tab + (size_t)(a.k + 1) * G, G, lds, err);
         if (rank == 0 && threadIdx.x == 0) a.hcol[i] = h;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
@@ -406,8 +413,11 @@ __device__ inline void mgs_body(const MgsDev &a, int rank, int G, double *lds)
 #pragma unroll
     for (int e = 0; e < E; ++e) s = fma(qv[e], qv[e], s);
     s = block_sum(s, lds);
-    if (threadIdx.x == 0) publish(tab + (size_t)a.k * G + rank, s);
-    const double hn2 = gather_total(tab + (size_t)a.k * G, G, lds, err);
+    double hn2 = s;
+    if (!solo) {
+        if (threadIdx.x == 0) publish(tab + (size_t)a.k * G + rank, s);
+        hn2 = gather_total(tab + (size_t)a.k * G, G, lds, err);
+    }
     if (a.k == 0) qq = hn2;
     const double hn = sqrt(hn2);
     const double q0 = sqrt(qq);
