@@ -379,15 +379,34 @@ __device__ inline void mgs_body(const MgsDev &a, int rank, int G, double *lds)
     // a group of one block: its block sums are the totals, no exchange through memory
     const bool solo = G == 1;
     double qq = 0.0, h = 0.0;
+    // small tiles: w_{i+1} is loaded while the partial sums of <q, w_i> are exchanged
+    TV wn[EW];
+    if constexpr (!kReload) {
+        if (a.k > 0) {
+#pragma unroll
+            for (int e = 0; e < E; ++e) wn[e] = static_cast<const TV *>(a.V)[base + e * kBlock];
+        }
+    }
     for (int i = 0; i < a.k; ++i) {
         const TV *w = static_cast<const TV *>(a.V) + (size_t)i * a.ldv + base;
         double d = 0.0, s2 = 0.0;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-            const TV we = w[e * kBlock];
-            if constexpr (!kReload) wv[e] = we;
+            TV we;
+            if constexpr (kReload) {
+                we = w[e * kBlock];
+            } else {
+                we = wn[e];
+                wv[e] = we;
+            }
             d = fma(qv[e], to_f64(we), d);
             if (i == 0) s2 = fma(qv[e], qv[e], s2);
+        }
+        if constexpr (!kReload) {
+            if (i + 1 < a.k) {
+#pragma unroll
+                for (int e = 0; e < E; ++e) wn[e] = w[a.ldv + e * kBlock];
+            }
         }
         d = block_sum(d, lds);
         if (i == 0) s2 = block_sum(s2, lds);
