@@ -40,7 +40,12 @@
  *   - Return value: ABG_OK (0), a negative error or a positive informational status.
  *     No exception crosses the ABI and the library never aborts the process.
  *   - Calls are thread-safe as long as concurrent calls use distinct workspaces and
- *     output buffers.
+ *     output buffers. A solve's Gram-Schmidt launch needs its whole block group (256
+ *     blocks for vectors of up to 2^22 elements, more for longer ones, never more than
+ *     the device holds of that kernel) resident at once:
+ *     solves run concurrently on several streams whose groups together exceed what the
+ *     device holds can end with ABG_EDEVICE (the bounded wait) instead of completing.
+ *     Many problems at once belong on one engine (below), which has no such limit.
  */
 #ifndef ABGMRES_H
 #define ABGMRES_H
