@@ -33,20 +33,30 @@ constexpr int kWin = 32;
 template <typename T>
 struct alignas(16) BackStage {
     T f, cu, su, su4;   // su4 = 4 su, the step between a lane's pixel rows
-    T invp, half, invpq;
+    // matched back projector: with w = frac(u), the trapezoid's values at the two bins
+    // around u are clamp(t1 - w c, 0, 1/p) (distance w ds) and clamp(t2 + w c, 0, 1/p)
+    // (distance (1 - w) ds), where t1 = h/(pq), t2 = (h - ds)/(pq), c = ds/(pq), h = (p+q)/2
+    T invp, t1, t2, c;
     int axis;
 };
 
-// Length of a ray at offset |t| from a unit pixel's centre projection (the trapezoid of
-// the line model); on an axis-aligned ray at exactly |t| = 1/2 the two pixels share it.
+// Length of an axis-aligned ray at offset |t| from a unit pixel's centre projection (the
+// line model's trapezoid is then a box); at exactly |t| = 1/2 the two pixels share it.
 template <typename T>
-__device__ inline T trapezoid(T at, const BackStage<T> &P)
+__device__ inline T box(T at, const BackStage<T> &P)
 {
-    if (P.axis) {
-        if (fabs(at - T(0.5)) <= edge_tie<T>()) return T(0.5) * P.invp;
-        return at < T(0.5) ? P.invp : T(0);
-    }
-    return fmin(P.invp, fmax(T(0), (P.half - at) * P.invpq));
+    if (fabs(at - T(0.5)) <= edge_tie<T>()) return T(0.5) * P.invp;
+    return at < T(0.5) ? P.invp : T(0);
+}
+
+template <typename T> __device__ inline T clamp_to(T v, T hi);
+template <> __device__ inline float clamp_to<float>(float v, float hi)
+{
+    return __builtin_amdgcn_fmed3f(v, 0.f, hi);
+}
+template <> __device__ inline double clamp_to<double>(double v, double hi)
+{
+    return fmin(hi, fmax(0.0, v));
 }
 
 template <typename T> __device__ inline T fract_of(T u);
@@ -62,14 +72,27 @@ template <typename T> struct alignas(2 * sizeof(T)) BinPair {
 // at least one bin below the tile's smallest u, and a 16 x 16 tile spans at most
 // 15 sqrt(2) / ds < 28.3 bins for ds >= 0.75 (the smallest spacing a geometry accepts),
 // so 1 <= u < 30.3 up to rounding: truncation is floor and k <= kWin - 2.
+// Adds the pixel's contribution to acc.
 template <typename T, bool ADJ>
-__device__ inline T back_tap(const BinPair<T> *wrow, T u, const BackStage<T> &P, T dsT)
+__device__ inline void back_tap(T &acc, const BinPair<T> *wrow, T u, const BackStage<T> &P, T dsT)
 {
     const T w = fract_of(u);
     const int k = (int)u;
     const BinPair<T> b = wrow[k];
-    if (!ADJ) return fma(w, b.d, b.v);
-    return trapezoid(w * dsT, P) * b.v + trapezoid((T(1) - w) * dsT, P) * (b.v + b.d);
+    if (!ADJ) {
+        acc += fma(w, b.d, b.v);
+        return;
+    }
+    T a0, a1;
+    if (P.axis) {
+        a0 = box(w * dsT, P);
+        a1 = box((T(1) - w) * dsT, P);
+    } else {
+        a0 = clamp_to(fma(-w, P.c, P.t1), P.invp);
+        a1 = clamp_to(fma(w, P.c, P.t2), P.invp);
+    }
+    acc = fma(a0, b.v, acc);
+    acc = fma(a1, b.v + b.d, acc);
 }
 
 // LDS of one back-projection block (declared by the calling kernel, so that a kernel
@@ -176,8 +199,9 @@ __device__ inline void back_tile(const T *__restrict__ y, T *__restrict__ x,
             st.su = T(Pn.su);
             st.su4 = T(4.0 * Pn.su);
             st.invp = T(Pn.len);
-            st.half = T(Pn.half);
-            st.invpq = T(Pn.invpq);
+            st.t1 = T(Pn.half * Pn.invpq);
+            st.t2 = T((Pn.half - ds) * Pn.invpq);
+            st.c = T(ds * Pn.invpq);
             st.axis = Pn.axis;
             L.prm[r & 1][threadIdx.x] = st;
             L.ib[r & 1][threadIdx.x] = (int)ib;
@@ -229,10 +253,10 @@ __device__ inline void back_tile(const T *__restrict__ y, T *__restrict__ x,
         for (int t = wave; t < na; t += kBackWaves) {
             const BackStage<T> P = L.prm[r & 1][t];
             const T u0 = fma(ftx, P.cu, fma(fty, P.su, P.f));
-            acc[0] += back_tap<T, ADJ>(L.win[t], u0, P, dsT);
+            back_tap<T, ADJ>(acc[0], L.win[t], u0, P, dsT);
 #pragma unroll
             for (int j = 1; j < kPixPerLane; ++j)
-                acc[j] += back_tap<T, ADJ>(L.win[t], fma(T(j), P.su4, u0), P, dsT);
+                back_tap<T, ADJ>(acc[j], L.win[t], fma(T(j), P.su4, u0), P, dsT);
         }
     }
     tile_store<T, PAD>(acc, L.part, ADJ ? T(1) : T(1.0 / ds), x, N, c0, r0, xr, xc, S);

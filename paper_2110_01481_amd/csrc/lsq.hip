@@ -13,6 +13,8 @@
 namespace abg {
 namespace {
 
+constexpr int kLU = 4;   // elements per thread and trip of the vector kernels
+
 // Reduction of a per-block double to its fixed-order total in the last block to finish
 // (true in that block only).
 __device__ inline bool last_block_total(double v, double *partials, unsigned *count, double *lds,
@@ -63,12 +65,25 @@ __global__ __launch_bounds__(kBlock) void lsq_u_kernel(T *__restrict__ u, const 
     const double ch = safe_div(S->theta, S->rho_prev);
     double ss = 0.0;
     const long long T_ = (long long)gridDim.x * kBlock;
-    for (long long l = (long long)blockIdx.x * kBlock + threadIdx.x; l < m; l += T_) {
-        const double tv = to_f64(t[l]);
-        const double un = fma(-cu, to_f64(u[l]), tv);
-        u[l] = (T)un;
-        ss = fma(un, un, ss);
-        if (ah) ah[l] = (T)fma(-ch, to_f64(ah[l]), tv);
+    for (long long l0 = (long long)blockIdx.x * kBlock + threadIdx.x; l0 < m; l0 += kLU * T_) {
+        double tv[kLU], uv[kLU], hv[kLU];
+#pragma unroll
+        for (int j = 0; j < kLU; ++j) {
+            const long long l = l0 + j * T_;
+            const bool in = l < m;
+            tv[j] = in ? to_f64(t[l]) : 0.0;
+            uv[j] = in ? to_f64(u[l]) : 0.0;
+            hv[j] = (in && ah) ? to_f64(ah[l]) : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < kLU; ++j) {
+            const long long l = l0 + j * T_;
+            if (l >= m) continue;
+            const double un = fma(-cu, uv[j], tv[j]);
+            u[l] = (T)un;
+            ss = fma(un, un, ss);
+            if (ah) ah[l] = (T)fma(-ch, hv[j], tv[j]);
+        }
     }
     double tot;
     if (last_block_total(ss, partials, count, lds, &tot, &last) && threadIdx.x == 0)
@@ -88,10 +103,23 @@ __global__ __launch_bounds__(kBlock) void lsq_v_kernel(T *__restrict__ v, const 
     const double ib = safe_div(1.0, bn);
     double ss = 0.0;
     const long long T_ = (long long)gridDim.x * kBlock;
-    for (long long l = (long long)blockIdx.x * kBlock + threadIdx.x; l < n; l += T_) {
-        const double vn = fma(to_f64(s[l]), ib, -bn * to_f64(v[l]));
-        v[l] = (T)vn;
-        ss = fma(vn, vn, ss);
+    for (long long l0 = (long long)blockIdx.x * kBlock + threadIdx.x; l0 < n; l0 += kLU * T_) {
+        double sv[kLU], vv[kLU];
+#pragma unroll
+        for (int j = 0; j < kLU; ++j) {
+            const long long l = l0 + j * T_;
+            const bool in = l < n;
+            sv[j] = in ? to_f64(s[l]) : 0.0;
+            vv[j] = in ? to_f64(v[l]) : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < kLU; ++j) {
+            const long long l = l0 + j * T_;
+            if (l >= n) continue;
+            const double vn = fma(sv[j], ib, -bn * vv[j]);
+            v[l] = (T)vn;
+            ss = fma(vn, vn, ss);
+        }
     }
     double tot;
     if (last_block_total(ss, partials, count, lds, &tot, &last) && threadIdx.x == 0)
@@ -120,14 +148,27 @@ __global__ __launch_bounds__(kBlock) void lsqr_x_kernel(T *__restrict__ x, T *__
     const double theta = sn * an, phi = c * phibar;
     const double fx = safe_div(phi, rho), fw = safe_div(theta, rho), ia = safe_div(1.0, an);
     const long long T_ = (long long)gridDim.x * kBlock;
-    for (long long l = (long long)blockIdx.x * kBlock + threadIdx.x; l < n; l += T_) {
-        const double wl = to_f64(w[l]);
-        const double vn = to_f64(v[l]) * ia;
-        const T xl = x[l];
-        if (xprev) xprev[l] = xl;
-        x[l] = (T)fma(fx, wl, to_f64(xl));
-        w[l] = (T)fma(-fw, wl, vn);
-        v[l] = (T)vn;
+    for (long long l0 = (long long)blockIdx.x * kBlock + threadIdx.x; l0 < n; l0 += kLU * T_) {
+        double wv[kLU], vv[kLU];
+        T xv[kLU];
+#pragma unroll
+        for (int j = 0; j < kLU; ++j) {
+            const long long l = l0 + j * T_;
+            const bool in = l < n;
+            wv[j] = in ? to_f64(w[l]) : 0.0;
+            vv[j] = in ? to_f64(v[l]) : 0.0;
+            xv[j] = in ? x[l] : T(0);
+        }
+#pragma unroll
+        for (int j = 0; j < kLU; ++j) {
+            const long long l = l0 + j * T_;
+            if (l >= n) continue;
+            const double vn = vv[j] * ia;
+            if (xprev) xprev[l] = xv[j];
+            x[l] = (T)fma(fx, wv[j], to_f64(xv[j]));
+            w[l] = (T)fma(-fw, wv[j], vn);
+            v[l] = (T)vn;
+        }
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -178,16 +219,30 @@ __global__ __launch_bounds__(kBlock) void lsmr_x_kernel(T *__restrict__ x, T *__
     const double xcoef = safe_div(zeta, rho * rhobar);
     const double fh = safe_div(theta_n, rho), ia = safe_div(1.0, an);
     const long long T_ = (long long)gridDim.x * kBlock;
-    for (long long l = (long long)blockIdx.x * kBlock + threadIdx.x; l < n; l += T_) {
-        const double hl = to_f64(h[l]);
-        const double hb = fma(-hcoef, to_f64(hbar[l]), hl);
-        const double vn = to_f64(v[l]) * ia;
-        hbar[l] = (T)hb;
-        const T xl = x[l];
-        if (xprev) xprev[l] = xl;
-        x[l] = (T)fma(xcoef, hb, to_f64(xl));
-        h[l] = (T)fma(-fh, hl, vn);
-        v[l] = (T)vn;
+    for (long long l0 = (long long)blockIdx.x * kBlock + threadIdx.x; l0 < n; l0 += kLU * T_) {
+        double hv[kLU], bv[kLU], vv[kLU];
+        T xv[kLU];
+#pragma unroll
+        for (int j = 0; j < kLU; ++j) {
+            const long long l = l0 + j * T_;
+            const bool in = l < n;
+            hv[j] = in ? to_f64(h[l]) : 0.0;
+            bv[j] = in ? to_f64(hbar[l]) : 0.0;
+            vv[j] = in ? to_f64(v[l]) : 0.0;
+            xv[j] = in ? x[l] : T(0);
+        }
+#pragma unroll
+        for (int j = 0; j < kLU; ++j) {
+            const long long l = l0 + j * T_;
+            if (l >= n) continue;
+            const double hb = fma(-hcoef, bv[j], hv[j]);
+            const double vn = vv[j] * ia;
+            hbar[l] = (T)hb;
+            if (xprev) xprev[l] = xv[j];
+            x[l] = (T)fma(xcoef, hb, to_f64(xv[j]));
+            h[l] = (T)fma(-fh, hv[j], vn);
+            v[l] = (T)vn;
+        }
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -230,12 +285,26 @@ __global__ __launch_bounds__(kBlock) void lsmr_r_kernel(const T *__restrict__ ah
     const double hcoef = S->hcoef, xcoef = S->xcoef;
     double ss = 0.0;
     const long long T_ = (long long)gridDim.x * kBlock;
-    for (long long l = (long long)blockIdx.x * kBlock + threadIdx.x; l < m; l += T_) {
-        const double hb = fma(-hcoef, to_f64(ahbar[l]), to_f64(ah[l]));
-        const double rn = fma(-xcoef, hb, to_f64(r[l]));
-        ahbar[l] = (T)hb;
-        r[l] = (T)rn;
-        ss = fma(rn, rn, ss);
+    for (long long l0 = (long long)blockIdx.x * kBlock + threadIdx.x; l0 < m; l0 += kLU * T_) {
+        double av[kLU], bv[kLU], rv[kLU];
+#pragma unroll
+        for (int j = 0; j < kLU; ++j) {
+            const long long l = l0 + j * T_;
+            const bool in = l < m;
+            av[j] = in ? to_f64(ah[l]) : 0.0;
+            bv[j] = in ? to_f64(ahbar[l]) : 0.0;
+            rv[j] = in ? to_f64(r[l]) : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < kLU; ++j) {
+            const long long l = l0 + j * T_;
+            if (l >= m) continue;
+            const double hb = fma(-hcoef, bv[j], av[j]);
+            const double rn = fma(-xcoef, hb, rv[j]);
+            ahbar[l] = (T)hb;
+            r[l] = (T)rn;
+            ss = fma(rn, rn, ss);
+        }
     }
     double tot;
     if (last_block_total(ss, partials, count, lds, &tot, &last) && threadIdx.x == 0) {
@@ -296,10 +365,12 @@ __global__ __launch_bounds__(kBlock) void lsq_start_kernel(T *__restrict__ v, T 
     (void)lsmr;
 }
 
+// At most 256 blocks of kLU elements per thread and trip: the last block's final sum then
+// reads one partial per thread.
 unsigned blocks_of(long long L)
 {
-    long long b = (L + kBlock - 1) / kBlock;
-    return (unsigned)std::min<long long>(std::max<long long>(b, 1), 1024);
+    long long b = (L + (long long)kBlock * kLU - 1) / ((long long)kBlock * kLU);
+    return (unsigned)std::min<long long>(std::max<long long>(b, 1), 256);
 }
 
 }  // namespace
