@@ -497,8 +497,11 @@ def bench_serving(abg, torch, dev, seconds, bases, tiles, single_sample=24):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
+    # 200 warm-up steps (~0.7 s at 512^2): after idle the device needs that long under load
+    # before a timed region runs at its steady rate (with 5, the first region after start
+    # ran up to 15% slower than later ones)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3])
     ap.add_argument("--basis", default="f32", choices=["f32", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
