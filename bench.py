@@ -343,6 +343,61 @@ def bench_histories(abg, torch, dev, w, xb, eta=0.003, K=150):
     return out
 
 
+def bench_concurrent_pair(abg, torch, dev, gg, w, b32, enorm, basis, steps, warmup=50):
+    """The timed step's two solves (AB and BA, same input and rule) run at the same time
+    from two host threads, each on its own stream with its own workspace: Arnoldi
+    iterations per second of the pair. The solves are the same as in the sequential
+    step; only their overlap on the device differs."""
+    import threading
+    jobs = []
+    for m in ("ab", "ba"):
+        nb = abg.workspace_bytes(gg, m, w.k_max, proj="f32", basis=basis, stop="dp")
+        jobs.append((m, torch.empty(nb, dtype=torch.uint8, device=dev),
+                     torch.empty(gg.n, dtype=torch.float32, device=dev), torch.cuda.Stream()))
+    n_steps = warmup + steps
+    start = threading.Barrier(3)
+    done = threading.Barrier(3)
+    iters = [0, 0]
+    errors = []
+
+    def worker(j):
+        m, ws, x, st = jobs[j]
+        try:
+            with torch.cuda.stream(st):
+                for step in range(n_steps):
+                    start.wait()
+                    r = abg.gmres(m, gg, b32, w.k_max, stop="dp", tau=w.tau, noise_norm=enorm,
+                                  basis=basis, workspace=ws, out=x, stream=st)
+                    if step >= warmup:
+                        iters[j] += r.k_done
+                    done.wait()
+        except Exception as e:   # reported below
+            errors.append(repr(e))
+            start.abort()
+            done.abort()
+
+    torch.cuda.synchronize()
+    ths = [threading.Thread(target=worker, args=(j,)) for j in range(2)]
+    for t in ths:
+        t.start()
+    t0 = None
+    try:
+        for step in range(n_steps):
+            if step == warmup:
+                t0 = time.perf_counter()
+            start.wait()
+            done.wait()
+        t1 = time.perf_counter()
+    except threading.BrokenBarrierError:
+        pass
+    for t in ths:
+        t.join()
+    if errors or t0 is None:
+        return {"error": errors}
+    return {"iters_per_s": round(sum(iters) / (t1 - t0), 1),
+            "ms_per_step": round(1e3 * (t1 - t0) / steps, 3), "steps": steps}
+
+
 def bench_lsq(abg, torch, dev, w, xb, b32, enorm, reps=5):
     """The matched comparators (Sec. 5, 6.2) on the timed workload's input: LSQR and LSMR
     with A and its exact transpose, FP32, under the same DP rule: stopping iteration,
@@ -696,6 +751,9 @@ def main():
             m: float(torch.linalg.vector_norm(last[m].x.double() - r64[m].x) /
                      torch.linalg.vector_norm(r64[m].x)) for m in methods}
 
+    if args.config == 2:
+        extra["concurrent_ab_ba"] = bench_concurrent_pair(abg, torch, dev, gg, w, b32, enorm,
+                                                          args.basis, args.steps)
     if not args.no_models:
         extra["models"] = bench_models(abg, torch, dev, w, xb)
         extra["few_view"] = bench_few_view(abg, torch, dev)
