@@ -147,3 +147,38 @@ def test_workspace_contents_do_not_matter(gpu_lib, method, dt, stop):
     assert outs[0][0] == outs[1][0] and outs[0][1] == outs[1][1]
     assert np.array_equal(outs[0][2], outs[1][2]) and np.array_equal(outs[0][3], outs[1][3])
     assert np.all(np.isfinite(outs[1][2]))
+
+
+def test_lsq_one_pixel_and_invalid_rules(gpu_lib):
+    """A 1 x 1 image: the Krylov space has dimension one, so after the first step the
+    iterate is the least-squares solution, and later steps keep it (FP64). The NCP rule
+    needs at least two bins per projection; x_ref and err_hist come together."""
+    import ctypes
+    import torch
+    import paper_2110_01481_amd as abg
+    from paper_2110_01481_amd import _binding as B
+    go = O.Geometry(1, 7, 3)
+    A = np.stack([go.A(e) for e in np.eye(go.n)], axis=1)
+    b = np.random.default_rng(3).uniform(size=go.m)
+    xs = np.linalg.lstsq(A, b, rcond=None)[0]
+    gg = abg.Geometry(1, 7, 3)
+    for method in ("lsqr", "lsmr"):
+        for k in (1, 3):
+            r = abg.lsq(method, gg, torch.tensor(b, device="cuda"), k)
+            assert r.status in ("ok", "breakdown")
+            assert abs(float(r.x.cpu()[0]) - xs[0]) <= 1e-12 * abs(xs[0]), (method, k)
+    g1 = abg.Geometry(8, 6, 1)
+    with pytest.raises(abg.AbgError):
+        abg.lsq("lsqr", g1, torch.ones(g1.m, device="cuda"), 5, stop="ncp")
+    lib = B.load_library()
+    bt = torch.ones(gg.m, dtype=torch.float64, device="cuda")
+    x = torch.empty(gg.n, dtype=torch.float64, device="cuda")
+    nb = abg.lsq_workspace_bytes(gg, "lsqr", "f64")
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    xr = torch.zeros(gg.n, dtype=torch.float64, device="cuda")
+    err = np.zeros(5)
+    for xref, eh in ((ctypes.c_void_p(xr.data_ptr()), None), (None, err.ctypes.data_as(B._dp))):
+        rc = lib.abg_lsqr(gg.handle, ctypes.c_void_p(bt.data_ptr()), None,
+                          ctypes.c_void_p(x.data_ptr()), 5, B.Stop(B.STOP_NONE, 1.0, 0.0), B.F64,
+                          ctypes.c_void_p(ws.data_ptr()), nb, None, xref, eh, None)
+        assert rc == -1
