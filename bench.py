@@ -76,9 +76,15 @@ def summarize_counters(d: str) -> str:
             "source_hash": forward_source_hash()}
     data["traffic_bytes_per_launch"] = int(1024 * (data["fetch_kib_per_dispatch"] * data["fetch_scale"] +
                                                    data["write_kib_per_dispatch"] * data["write_scale"]))
+    sq_csv = os.path.join(d, "sq", "run_counter_collection.csv")
+    if os.path.exists(sq_csv):
+        sq = _counter_means(sq_csv, "forward_kernel<float>")
+        data["valu_wave_insts_per_dispatch"] = round(sq["SQ_INSTS_VALU"], 1)
     b = ("python -u bench.py --steps 2 --warmup 1 --no-cpu-baseline --no-fp64 --no-batch "
          "--serve-seconds 0 --no-models")
     c = "python -u bench.py --copy-calibration-mib 1024"
+    sqc = ("SQ_WAVES SQ_BUSY_CYCLES SQ_WAVE_CYCLES SQ_INSTS_VALU SQ_INSTS_VMEM_RD "
+           "SQ_ACTIVE_INST_VALU SQ_WAIT_ANY GRBM_GUI_ACTIVE")
     lines = [
         "# HBM traffic of the forward projector (512x512 image, 720 x 725 sinogram, FP32)",
         "",
@@ -93,7 +99,11 @@ def summarize_counters(d: str) -> str:
         f"    rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir>/write -o run -- {b}",
         f"    rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir>/cfetch -o run -- {c}",
         f"    rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir>/cwrite -o run -- {c}",
+        f"    rocprofv3 --pmc {sqc} --output-format csv -d <dir>/sq -o run -- {b}",
         "    python bench.py --summarize-counters <dir>",
+        "",
+        "The last pass gives the VALU instructions per dispatch (wave level; x 64 lanes for",
+        "the lane operations that bench.py sets against the VALU issue rate).",
         "",
         "`source_hash` covers the forward projector's sources; bench.py reports `traffic` only",
         "while it matches.",
@@ -115,6 +125,7 @@ def stored_traffic() -> dict | None:
         return None
     return data if data.get("source_hash") == forward_source_hash() else None
 FP32_VECTOR_PEAK_TFLOPS = 157.3
+VALU_ISSUE_PEAK = 256 * 4 * 16 * 2.4e9   # lane operations per second
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 
 
@@ -697,6 +708,13 @@ def main():
                 "traffic": tr["traffic_bytes_per_launch"] if tr else None,
                 "avg_launch_ms": round(fwd_avg_ms, 4),
                 "work_per_launch": f"{nnz} ray-pixel intersections x 2 flop"}
+        if tr and "valu_wave_insts_per_dispatch" in tr:
+            # the survey's primary reading: VALU lane operations against the issue rate
+            lane_ops = 64.0 * tr["valu_wave_insts_per_dispatch"]
+            roof["valu_issue_frac"] = round(lane_ops / (fwd_avg_ms * 1e-3) / VALU_ISSUE_PEAK, 4)
+            roof["valu_note"] = (f"{lane_ops:.3g} VALU lane operations per launch (SQ_INSTS_VALU x 64) "
+                                 f"against {VALU_ISSUE_PEAK:.3g} lane-ops/s (256 CUs x 4 SIMDs x 16 "
+                                 "lanes x 2.4 GHz)")
         if tr:
             roof["traffic_note"] = (f"HBM bytes per launch from FETCH_SIZE x {tr['fetch_scale']} + "
                                     f"WRITE_SIZE x {tr['write_scale']} (copy-calibrated); "

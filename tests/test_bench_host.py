@@ -41,3 +41,8 @@ def test_counter_summary_scales_by_the_copy_calibration(tmp_path):
     assert data["fetch_scale"] == 2.0 and data["write_scale"] == 1.0
     assert data["traffic_bytes_per_launch"] == 1024 * (1000 * 2 + 300)
     assert data["source_hash"] == bench.forward_source_hash()
+    assert "valu_wave_insts_per_dispatch" not in data
+    write("sq", fwd, "SQ_INSTS_VALU", 5000.0)
+    text = bench.summarize_counters(str(tmp_path))
+    data = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+    assert data["valu_wave_insts_per_dispatch"] == 5000.0
