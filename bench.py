@@ -35,6 +35,11 @@ FORWARD_SOURCES = ["paper_2110_01481_amd/csrc/fwd_body.h", "paper_2110_01481_amd
                    "paper_2110_01481_amd/csrc/projectors.hip"]
 
 
+def progress(msg: str):
+    """One progress line on stderr (stdout carries only the result line)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def forward_source_hash() -> str:
     import hashlib
     h = hashlib.sha256()
@@ -584,8 +589,11 @@ def bench_serving(abg, torch, dev, seconds, bases, tiles, single_sample=24):
     for basis in bases:
         srv = Server(proj="f32", basis=basis, max_slots=256, budget_bytes=200e9)
         tuned = srv.tune([r.problem for r in reqs[:32]])
+        progress(f"serving {basis}: tuned, {len(reqs)} requests in real time")
         live = srv.run(reqs, realtime=True)
+        progress(f"serving {basis}: real-time run done, closed batch")
         closed = srv.run(reqs, realtime=False)
+        progress(f"serving {basis}: closed batch done")
         srv.close()
         out["runs"][basis] = {"realtime": live.as_dict(),
                               "closed_batch_reconstructions_per_s": round(closed.completed_per_s, 2),
@@ -696,6 +704,7 @@ def main():
     elapsed = t1 - t0
     value = iters / elapsed
     ms_per_step = 1e3 * elapsed / args.steps
+    progress(f"timed region: {value:.1f} iters/s")
     # the same steps again with every projector, Gram-Schmidt and combination launch
     # stamped with HIP events at its own start and end (on the solver's stream): the
     # kernels' durations for the roofline and the breakdown
@@ -813,13 +822,17 @@ def main():
                                                           args.basis, args.steps)
     if not args.no_models:
         extra["models"] = bench_models(abg, torch, dev, w, xb)
+        progress("models done")
         extra["few_view"] = bench_few_view(abg, torch, dev)
         extra["histories"] = bench_histories(abg, torch, dev, w, xb)
+        progress("few-view and histories done")
         extra["lsq"] = bench_lsq(abg, torch, dev, w, xb, b32, enorm)
 
     tiles = None
     if not args.no_batch:
+        progress("batched mix")
         extra["batched"] = bench_batched(abg, torch, dev)
+        progress("batched mix done")
         tiles = (extra["batched"]["tiles"]["rays"], extra["batched"]["tiles"]["ang_block"],
                  extra["batched"]["tiles"]["sched"])
     if args.serve_seconds > 0:
