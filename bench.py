@@ -85,6 +85,15 @@ def summarize_counters(d: str) -> str:
     if os.path.exists(sq_csv):
         sq = _counter_means(sq_csv, "forward_kernel<float>")
         data["valu_wave_insts_per_dispatch"] = round(sq["SQ_INSTS_VALU"], 1)
+    l2_csv = os.path.join(d, "l2", "run_counter_collection.csv")
+    if os.path.exists(l2_csv):
+        # L2 (TCC) hit rate = hits / (hits + misses) per kernel of the solve
+        data["l2_hit_rate"] = {}
+        for k in L2_KERNELS:
+            m = _counter_means(l2_csv, k)
+            hit, miss = m.get("TCC_HIT_sum", 0.0), m.get("TCC_MISS_sum", 0.0)
+            if hit + miss > 0:
+                data["l2_hit_rate"][k] = round(hit / (hit + miss), 4)
     b = ("python -u bench.py --steps 2 --warmup 1 --no-cpu-baseline --no-fp64 --no-batch "
          "--serve-seconds 0 --no-models")
     c = "python -u bench.py --copy-calibration-mib 1024"
@@ -105,10 +114,12 @@ def summarize_counters(d: str) -> str:
         f"    rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir>/cfetch -o run -- {c}",
         f"    rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir>/cwrite -o run -- {c}",
         f"    rocprofv3 --pmc {sqc} --output-format csv -d <dir>/sq -o run -- {b}",
+        f"    rocprofv3 --pmc TCC_HIT_sum TCC_MISS_sum --output-format csv -d <dir>/l2 -o run -- {b}",
         "    python bench.py --summarize-counters <dir>",
         "",
-        "The last pass gives the VALU instructions per dispatch (wave level; x 64 lanes for",
-        "the lane operations that bench.py sets against the VALU issue rate).",
+        "The SQ pass gives the VALU instructions per dispatch (wave level; x 64 lanes for",
+        "the lane operations that bench.py sets against the VALU issue rate); the TCC pass",
+        "the L2 hit rate, hits / (hits + misses), of each kernel of the solve.",
         "",
         "`source_hash` covers the forward projector's sources; bench.py reports `traffic` only",
         "while it matches.",
@@ -118,6 +129,10 @@ def summarize_counters(d: str) -> str:
         "```",
         ""]
     return "\n".join(lines)
+
+
+L2_KERNELS = ("forward_kernel<float>", "back_kernel<float, false, false>",
+              "back_kernel<float, false, true>", "mgs_kernel", "combine_kernel")
 
 
 def stored_traffic() -> dict | None:
@@ -767,6 +782,8 @@ def main():
             roof["traffic_note"] = (f"HBM bytes per launch from FETCH_SIZE x {tr['fetch_scale']} + "
                                     f"WRITE_SIZE x {tr['write_scale']} (copy-calibrated); "
                                     f"{tr['traffic_bytes_per_launch'] / (fwd_avg_ms * 1e-3) / 1e9:.0f} GB/s")
+        if tr and tr.get("l2_hit_rate"):
+            roof["l2_hit_rate"] = tr["l2_hit_rate"].get("forward_kernel<float>")
 
     extra = {
         "A_applies_per_s": round(1e3 / fwd_avg_ms, 1) if fwd_n else None,
@@ -781,6 +798,9 @@ def main():
         "k_done": {m: last[m].k_done for m in methods},
         "n_literal": {m: last[m].n_literal for m in methods},
     }
+    l2 = (stored_traffic() or {}).get("l2_hit_rate") if args.config == 2 else None
+    if l2:
+        extra["l2_hit_rate"] = l2   # per kernel, from the stored TCC counter pass
     # Gram-Schmidt and basis GEMVs: algorithmic HBM bytes of the counted launches. Step j
     # (0..k_done) of a solve reads q and w_1..w_j, writes w_{j+1} and its copy; the DP
     # residual of step j reads j (BA: Z, plus rb0) or j+1 (AB: W) vectors of m and writes
