@@ -130,8 +130,20 @@ struct MgsLaunch {
     double *giv_H, *giv_R, *giv_cs, *giv_sn, *giv_g, *giv_y, *giv_rho;
     int giv_ld;
     DevState *snap;
+    // strictly lower triangle of the basis Gram matrix (gram_entries(k_max) doubles),
+    // kept across the steps of one solve; set: steps 2..64 run the low-synchronisation
+    // form (rows >= 2 k_max + 3); null: plain MGS
+    double *gram;
 };
 constexpr int kMaxGrid = 2048;
+// Largest Arnoldi step that runs the low-synchronisation form of Gram-Schmidt, and the
+// size of the packed Gram triangle it keeps (rows 0..min(k_max, kIcwyMaxK) - 1).
+constexpr int kIcwyMaxK = 64;
+constexpr size_t gram_entries(int k_max)
+{
+    const size_t r = (size_t)(k_max < kIcwyMaxK ? k_max : kIcwyMaxK);
+    return r * (r - 1) / 2 + 1;
+}
 hipError_t launch_mgs(const MgsLaunch &a, hipStream_t s);
 
 // out = base_coef*base + sum_{j<kk} sgn*coef[j]*V_j  (FP64 accumulation). With `norm`

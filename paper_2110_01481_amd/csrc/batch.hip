@@ -396,6 +396,7 @@ __global__ __launch_bounds__(kBlock) void bmgs_kernel(const BatchInst *__restric
         a.q64 = gfield<double>(d.q64);
         a.set_beta = 0;
         a.giv = GivensDev{};
+        a.gram = nullptr;   // the engine runs the plain sweep
         if constexpr (E == 0) mgs_stream_body<TX, TV>(a, rank, d.mgs_G, lds);
         else mgs_body<TX, TV, E>(a, rank, d.mgs_G, lds);
     }

@@ -33,6 +33,7 @@ template <typename TX, typename TV, int E>
 __global__ __launch_bounds__(kBlock) void mgs_kernel(MgsDev a)
 {
     __shared__ double lds[kWaves];
+    __shared__ IcwyLds il;
     __shared__ int s_rank;
     if (halted(a.st, a.step)) {
         if (a.giv.snap && blockIdx.x == 0 && threadIdx.x == 0) *a.giv.snap = *a.st;
@@ -42,7 +43,7 @@ __global__ __launch_bounds__(kBlock) void mgs_kernel(MgsDev a)
         s_rank = (int)__hip_atomic_fetch_add(a.ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
     const int rank = __builtin_amdgcn_readfirstlane(s_rank);
-    mgs_body<TX, TV, E>(a, rank, gridDim.x, lds);
+    mgs_body<TX, TV, E>(a, rank, gridDim.x, lds, &il);
     mgs_tail(a, rank);
 }
 
@@ -422,9 +423,12 @@ hipError_t launch_mgs(const MgsLaunch &m, hipStream_t s)
     d.bd_rel = m.bd_rel;
     d.step = m.step;
     d.set_beta = m.set_beta;
+    d.gram = m.gram;
     d.giv = GivensDev{m.giv_H, m.giv_R, m.giv_cs, m.giv_sn, m.giv_g, m.giv_y, m.giv_rho,
                       m.giv_ld, m.snap};
     if (m.giv_H && (m.k < 1 || m.k + 1 > kMaxCoef)) return hipErrorInvalidValue;
+    // the low-synchronisation form publishes rows 0..2k and clears up to 2k + 2
+    if (m.gram && m.rows < 2 * std::min(m.k, kIcwyMaxK) + 3) return hipErrorInvalidValue;
     if (m.snap && !m.giv_H) return hipErrorInvalidValue;
     // timed at the kernel's own start and end when profiling is on
     ProfScope ps(kProfMgs, s, m.step, true);

@@ -13,6 +13,7 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
 constexpr unsigned kSpinLimit = 1u << 22;
+constexpr int kGatherRows = 8;    // slot rows polled together by gather_rows
 constexpr int kMaxCoef = 512;
 
 // ---- element access ------------------------------------------------------------------
@@ -126,6 +127,79 @@ __device__ inline double gather_total(const double *slots, int G, double *lds, i
     return block_sum(s, lds);
 }
 
+// Totals of slot rows 0..R-1 (each over the G published partials) into tot[0..R-1], the
+// same in every block. Groups of at most kBlock blocks: thread t reads column t of
+// kGatherRows rows at once, so the rows of one exchange cost one round of polling
+// together; the waves' sums are added in wave order. Larger groups: gather_total row by
+// row. Bounded wait as gather_total.
+__device__ inline void gather_rows(const double *tab, int G, int R, double (*red)[kGatherRows],
+                                   double *tot, double *lds, int *err)
+{
+    if (G > kBlock) {
+        for (int r = 0; r < R; ++r) {
+            const double t = gather_total(tab + (size_t)r * G, G, lds, err);
+            if (threadIdx.x == 0) tot[r] = t;
+        }
+        __syncthreads();
+        return;
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int j = threadIdx.x;
+    const int jc = min(j, G - 1);
+    unsigned spins = 0;
+    bool quit = false;
+    for (int c0 = 0; c0 < R; c0 += kGatherRows) {
+        const int nr = min(kGatherRows, R - c0);
+        const double *col = tab + (size_t)c0 * G + jc;
+        double v[kGatherRows];
+        // every load issued before any is tested (rows past nr re-read row nr - 1)
+#pragma unroll
+        for (int r = 0; r < kGatherRows; ++r) v[r] = agent_load(col + (size_t)min(r, nr - 1) * G);
+        unsigned need = 0;
+#pragma unroll
+        for (int r = 0; r < kGatherRows; ++r)
+            if ((unsigned long long)__double_as_longlong(v[r]) == kSlotEmpty) need |= 1u << r;
+        if (j >= G) need = 0;
+        while (!quit && !__syncthreads_and(need == 0)) {
+            ++spins;
+            if ((spins & 255u) == 0) {
+                const int e = __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (spins > kSpinLimit && threadIdx.x == 0 && !e)
+                    __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (__syncthreads_or(e != 0 || spins > kSpinLimit)) {
+                    quit = true;
+                    break;
+                }
+            }
+            __builtin_amdgcn_s_sleep(1);
+            if (need) {
+#pragma unroll
+                for (int r = 0; r < kGatherRows; ++r) {
+                    v[r] = agent_load(col + (size_t)min(r, nr - 1) * G);
+                    if ((unsigned long long)__double_as_longlong(v[r]) != kSlotEmpty)
+                        need &= ~(1u << r);
+                }
+            }
+        }
+        // all kGatherRows wave sums in one straight-line block (rows past nr dropped)
+#pragma unroll
+        for (int r = 0; r < kGatherRows; ++r) v[r] = wave_sum(j < G ? v[r] : 0.0);
+        if (lane == 0) {
+#pragma unroll
+            for (int r = 0; r < kGatherRows; ++r)
+                if (r < nr) red[wave][r] = v[r];
+        }
+        __syncthreads();
+        if ((int)threadIdx.x < nr) {
+            double t = red[0][threadIdx.x];
+#pragma unroll
+            for (int w = 1; w < kWaves; ++w) t += red[w][threadIdx.x];
+            tot[c0 + threadIdx.x] = t;
+        }
+        __syncthreads();
+    }
+}
+
 // ---- modified Gram-Schmidt ------------------------------------------------------------
 // One Arnoldi step's orthogonalisation of q_k against w_1..w_k by G blocks (ranks
 // 0..G-1): q_k stays in FP64 registers (E elements per thread), each basis vector is read
@@ -162,6 +236,25 @@ struct MgsDev {
     double *q64;       // FP64 scratch of the streaming variant (vectors longer than kRegMaxL)
     int set_beta;      // step 0 of a single solve: beta = ||r_0||, or the zero-rhs stop
     GivensDev giv;
+    // strictly lower triangle of the basis Gram matrix, row i (<w_i, w_j>, j < i) packed
+    // from i(i-1)/2; null: every step runs the plain sweep
+    double *gram;
+};
+
+// ---- low-synchronisation Gram-Schmidt (inverse compact WY form of MGS) ------------------
+// MGS's coefficients h_i = <q - sum_{j<i} h_j w_j, w_i> equal, in exact arithmetic, the
+// forward substitution h_i = <q, w_i> - sum_{j<i} <w_i, w_j> h_j. Steps 2 <= k <=
+// kIcwyMaxK therefore exchange the k inner products <q, w_i>, ||q_k||^2 and the new Gram
+// row <w_k, w_j> (j < k) in one group reduction, solve for h in FP64 (every block alike),
+// subtract sum_i h_i w_i in MGS's order and exchange ||q||^2 in a second reduction: two
+// reductions per step instead of k + 1. Slot rows of step k: <q, w_i> in 0..k-1,
+// ||q_k||^2 in k, the Gram row in k+1..2k-1, ||q||^2 after the update in 2k.
+struct IcwyLds {
+    double part[kWaves][2 * kIcwyMaxK];                   // wave partials of rows 0..2k-1
+    double tot[2 * kIcwyMaxK];                            // group totals of rows 0..2k-1
+    double red[kWaves][kGatherRows];
+    double tri[kIcwyMaxK * (kIcwyMaxK - 1) / 2];          // Gram rows 0..k-2, packed
+    double h[kIcwyMaxK];
 };
 
 // One block of NT threads. Column k-1 of H has just been written by mgs; R holds the
@@ -354,8 +447,132 @@ __device__ inline void mgs_tail(const MgsDev &a, int rank)
 // elements: the buffers are allocated that long and q is zero past L (the padding is
 // cleared once per solve), so there are no bounds tests and the padding of w_{k+1}
 // comes out zero.
+// Low-synchronisation sweep of step k (2 <= k <= kIcwyMaxK) for mgs_body: leaves q_k
+// minus its projections in qv, sets qq = ||q_k||^2, writes h_{1..k,k} and the new Gram row
+// (rank 0). Same element ownership as mgs_body.
 template <typename TX, typename TV, int E>
-__device__ inline void mgs_body(const MgsDev &a, int rank, int G, double *lds)
+__device__ inline void mgs_icwy_sweep(const MgsDev &a, int rank, int G, double (&qv)[E],
+                                      double *tab, IcwyLds &il, double *lds, double &qq)
+{
+    const int k = a.k;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const size_t base = (size_t)rank * (E * kBlock) + threadIdx.x;
+    const TV *V = static_cast<const TV *>(a.V) + base;
+    const TV *wk = V + (size_t)(k - 1) * a.ldv;
+    int *err = &a.st->error;
+    // Gram rows 0..k-2 (earlier steps) into LDS while the sweep runs
+    const int ntri = (k - 1) * (k - 2) / 2;
+    for (int t = threadIdx.x; t < ntri; t += kBlock) il.tri[t] = a.gram[t];
+    constexpr bool kHold = E < 32;
+    TV wkv[kHold ? E : 1];
+    if constexpr (kHold) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) wkv[e] = wk[e * kBlock];
+    }
+    double s2 = 0.0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) s2 = fma(qv[e], qv[e], s2);
+    // D basis vectors per trip, all their loads issued before any is used (a trip then
+    // costs one memory latency); past the last vector the loads repeat it, unused
+    constexpr int D = E >= 32 ? 1 : (32 / E < 8 ? 32 / E : 8);
+    for (int i0 = 0; i0 < k; i0 += D) {
+        TV wb[D][E];
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            const TV *w = V + (size_t)min(i0 + d, k - 1) * a.ldv;
+#pragma unroll
+            for (int e = 0; e < E; ++e) wb[d][e] = w[e * kBlock];
+        }
+        // the trip's 2D wave sums form one straight-line block, so that their lane
+        // exchanges overlap; sums past the last vector are computed and dropped
+        double ds[D], dl[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            ds[d] = 0.0;
+            dl[d] = 0.0;
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const double we = to_f64(wb[d][e]);
+                ds[d] = fma(qv[e], we, ds[d]);
+                if constexpr (kHold) dl[d] = fma(to_f64(wkv[e]), we, dl[d]);
+                else dl[d] = fma(to_f64(wk[e * kBlock]), we, dl[d]);
+            }
+        }
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            ds[d] = wave_sum(ds[d]);
+            dl[d] = wave_sum(dl[d]);
+        }
+        if (lane == 0) {
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                const int i = i0 + d;
+                if (i < k) il.part[wave][i] = ds[d];
+                if (i < k - 1) il.part[wave][k + 1 + i] = dl[d];
+            }
+        }
+    }
+    s2 = wave_sum(s2);
+    if (lane == 0) il.part[wave][k] = s2;
+    __syncthreads();
+    const int R = 2 * k;
+    double mine = 0.0;
+    if ((int)threadIdx.x < R) {
+        mine = il.part[0][threadIdx.x];
+#pragma unroll
+        for (int w = 1; w < kWaves; ++w) mine += il.part[w][threadIdx.x];
+    }
+    if (G == 1) {
+        if ((int)threadIdx.x < R) il.tot[threadIdx.x] = mine;
+        __syncthreads();
+    } else {
+        if ((int)threadIdx.x < R) publish(tab + (size_t)threadIdx.x * G + rank, mine);
+        gather_rows(tab, G, R, il.red, il.tot, lds, err);
+    }
+    qq = il.tot[k];
+    // forward substitution by one thread (four accumulators per row, added in a fixed
+    // order); the same arithmetic in every block
+    if (threadIdx.x == 0) {
+        for (int i = 0; i < k; ++i) {
+            const double *row = i < k - 1 ? il.tri + i * (i - 1) / 2 : il.tot + k + 1;
+            double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;
+            int j = 0;
+            for (; j + 4 <= i; j += 4) {
+                t0 = fma(row[j], il.h[j], t0);
+                t1 = fma(row[j + 1], il.h[j + 1], t1);
+                t2 = fma(row[j + 2], il.h[j + 2], t2);
+                t3 = fma(row[j + 3], il.h[j + 3], t3);
+            }
+            for (; j < i; ++j) t0 = fma(row[j], il.h[j], t0);
+            il.h[i] = il.tot[i] - ((t0 + t1) + (t2 + t3));
+        }
+    }
+    __syncthreads();
+    if (rank == 0) {
+        if ((int)threadIdx.x < k) a.hcol[threadIdx.x] = il.h[threadIdx.x];
+        if ((int)threadIdx.x < k - 1) a.gram[ntri + threadIdx.x] = il.tot[k + 1 + threadIdx.x];
+    }
+    for (int i0 = 0; i0 < k; i0 += D) {
+        TV wb[D][E];
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            const TV *w = V + (size_t)min(i0 + d, k - 1) * a.ldv;
+#pragma unroll
+            for (int e = 0; e < E; ++e) wb[d][e] = w[e * kBlock];
+        }
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            if (i0 + d >= k) break;
+            const double h = il.h[i0 + d];
+#pragma unroll
+            for (int e = 0; e < E; ++e) qv[e] = fma(-h, to_f64(wb[d][e]), qv[e]);
+        }
+    }
+}
+
+template <typename TX, typename TV, int E>
+__device__ inline void mgs_body(const MgsDev &a, int rank, int G, double *lds,
+                                IcwyLds *il = nullptr)
 {
     const size_t base = (size_t)rank * (E * kBlock) + threadIdx.x;
     const TX *q = static_cast<const TX *>(a.q) + base;
@@ -370,15 +587,22 @@ __device__ inline void mgs_body(const MgsDev &a, int rank, int G, double *lds)
     for (int e = 0; e < E; ++e) qv[e] = to_f64(q[e * kBlock]);
     double *tab = a.partials + (size_t)(a.step & 1) * a.rows * G;
     double *next = a.partials + (size_t)((a.step + 1) & 1) * a.rows * G;
+    // rows the next step uses: up to 2(k+1) in the low-synchronisation form
+    const bool icwy = a.gram && il && a.k >= 2 && a.k <= kIcwyMaxK;
+    const int clear_to = a.gram ? 2 * a.k + 2 : a.k + 2;
     if (threadIdx.x == 0) {
         const double empty = __longlong_as_double((long long)kSlotEmpty);
-        for (int r = 0; r <= a.k + 2 && r < a.rows; ++r)
+        for (int r = 0; r <= clear_to && r < a.rows; ++r)
             __hip_atomic_store(next + (size_t)r * G + rank, empty, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
     }
     // a group of one block: its block sums are the totals, no exchange through memory
     const bool solo = G == 1;
     double qq = 0.0, h = 0.0;
+    const int norm_row = icwy ? 2 * a.k : a.k;
+    if (icwy) {
+        mgs_icwy_sweep<TX, TV, E>(a, rank, G, qv, tab, *il, lds, qq);
+    } else {
     // small tiles: w_{i+1} is loaded while the partial sums of <q, w_i> are exchanged
     TV wn[EW];
     if constexpr (!kReload) {
@@ -428,14 +652,15 @@ __device__ inline void mgs_body(const MgsDev &a, int rank, int G, double *lds)
             else qv[e] = fma(-h, to_f64(wv[e]), qv[e]);
         }
     }
+    }
     double s = 0.0;
 #pragma unroll
     for (int e = 0; e < E; ++e) s = fma(qv[e], qv[e], s);
     s = block_sum(s, lds);
     double hn2 = s;
     if (!solo) {
-        if (threadIdx.x == 0) publish(tab + (size_t)a.k * G + rank, s);
-        hn2 = gather_total(tab + (size_t)a.k * G, G, lds, err);
+        if (threadIdx.x == 0) publish(tab + (size_t)norm_row * G + rank, s);
+        hn2 = gather_total(tab + (size_t)norm_row * G, G, lds, err);
     }
     if (a.k == 0) qq = hn2;
     const double hn = sqrt(hn2);

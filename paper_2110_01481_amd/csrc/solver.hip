@@ -24,7 +24,7 @@ namespace {
 
 struct Layout {
     size_t V, Z, cur, q, rb0, tm, tn, fpws, H, R, cs, sn, g, Y, rho;
-    size_t part, mgs_part, tick, count, st, ncp, q64, total;
+    size_t part, mgs_part, tick, count, st, ncp, q64, gram, total;
     long long L, ldv, mp, np;
     int mgs_rows;
     long long mgs_cap;
@@ -64,13 +64,15 @@ Layout make_layout(const Geometry &g, int method, int k_max, abg_precision p, ab
     ly.Y = take((size_t)k_max * k_max * 8);
     ly.rho = take((ld + 1) * 8);
     ly.part = take(2048 * 8);
-    // MGS slot tables: two of (k_max + 3) rows, one column per block of the largest group
-    ly.mgs_rows = k_max + 3;
+    // MGS slot tables: two of (2 k_max + 3) rows (the low-synchronisation form uses rows
+    // 0..2k), one column per block of the largest group
+    ly.mgs_rows = 2 * k_max + 3;
     const long long gmax = std::min<long long>(kMaxGrid, (ly.L + 255) / 256);
     ly.mgs_cap = 2LL * ly.mgs_rows * gmax;
     ly.mgs_part = take((size_t)ly.mgs_cap * 8);
     ly.tick = take((ld + 2) * 4);
     ly.q64 = ly.L > kRegMaxL ? take((size_t)ly.ldv * 8) : 0;
+    ly.gram = take(gram_entries(k_max) * 8);
     ly.count = take(64);
     ly.st = take(sizeof(DevState));
     ly.ncp = st.kind == ABG_STOP_NCP ? take(ncp_scratch_bytes(g)) : 0;
@@ -145,7 +147,7 @@ struct Solve {
     Layout ly;
     char *W;
     void *V, *Z, *cur, *q, *rb0, *tm, *tn, *fpws;
-    double *H, *R, *cs, *sn, *gv, *Y, *rho, *part, *mgs_part, *q64;
+    double *H, *R, *cs, *sn, *gv, *Y, *rho, *part, *mgs_part, *q64, *gram;
     unsigned *count, *tick;
     DevState *dst;
     double *ncp;
@@ -181,6 +183,7 @@ struct Solve {
         count = reinterpret_cast<unsigned *>(W + ly.count);
         tick = reinterpret_cast<unsigned *>(W + ly.tick);
         q64 = ly.q64 ? reinterpret_cast<double *>(W + ly.q64) : nullptr;
+        gram = reinterpret_cast<double *>(W + ly.gram);
         dst = reinterpret_cast<DevState *>(W + ly.st);
         ncp = ly.ncp ? reinterpret_cast<double *>(W + ly.ncp) : nullptr;
         sX = dtype_size(p.proj);
@@ -224,6 +227,7 @@ struct Solve {
         M.rows = ly.mgs_rows;
         M.ticket = tick + k;
         M.q64 = q64;
+        M.gram = gram;
         return M;
     }
 
