@@ -9,7 +9,9 @@
  *   BA-GMRES: min_x || B b - B A x ||_2                  (Sec. 2, B left preconditioner)
  * following the algorithm listed in Sec. 2 (Arnoldi with modified Gram-Schmidt, the
  * (k+1) x k Hessenberg least squares problem, iterate and residual), and stops with
- * the discrepancy principle or the NCP criterion (Sec. 6.3).
+ * the discrepancy principle or the NCP criterion (Sec. 6.3). Steps 2..64 of a single
+ * solve obtain MGS's coefficients in the inverse compact WY form (equal in exact
+ * arithmetic; two grid reductions per step instead of k + 1).
  *
  * Operators (matrix-free, 2-D parallel beam; conventions, since the paper fixes none):
  *   image    N x N unit pixels centred on the origin, row-major: pixel (r, c) has
