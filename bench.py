@@ -638,6 +638,9 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="seconds of Poisson arrivals for the serving run (0: skip)")
     ap.add_argument("--serve-basis", default="f32,bf16")
+    ap.add_argument("--no-concurrent", action="store_true",
+                    help="skip the AB || BA run on two streams (its overlapped launches last "
+                         "longer, which a kernel-time profile of the run would average in)")
     ap.add_argument("--no-models", action="store_true",
                     help="skip the strip / Joseph models and the six unmatched pairs")
     ap.add_argument("--summarize-counters", default="",
@@ -837,7 +840,7 @@ def main():
             m: float(torch.linalg.vector_norm(last[m].x.double() - r64[m].x) /
                      torch.linalg.vector_norm(r64[m].x)) for m in methods}
 
-    if args.config == 2:
+    if args.config == 2 and not args.no_concurrent:
         extra["concurrent_ab_ba"] = bench_concurrent_pair(abg, torch, dev, gg, w, b32, enorm,
                                                           args.basis, args.steps)
     if not args.no_models:
