@@ -462,7 +462,17 @@ __device__ inline void mgs_icwy_sweep(const MgsDev &a, int rank, int G, double (
     int *err = &a.st->error;
     // Gram rows 0..k-2 (earlier steps) into LDS while the sweep runs
     const int ntri = (k - 1) * (k - 2) / 2;
-    for (int t = threadIdx.x; t < ntri; t += kBlock) il.tri[t] = a.gram[t];
+    {
+        // all loads issued at once (clamped into the rows written so far)
+        constexpr int kTriPer = (kIcwyMaxK * (kIcwyMaxK - 1) / 2 + kBlock - 1) / kBlock;
+        double tv[kTriPer];
+#pragma unroll
+        for (int u = 0; u < kTriPer; ++u)
+            tv[u] = a.gram[min((int)threadIdx.x + u * kBlock, max(ntri - 1, 0))];
+#pragma unroll
+        for (int u = 0; u < kTriPer; ++u)
+            if ((int)threadIdx.x + u * kBlock < ntri) il.tri[threadIdx.x + u * kBlock] = tv[u];
+    }
     constexpr bool kHold = E < 32;
     TV wkv[kHold ? E : 1];
     if constexpr (kHold) {
@@ -530,22 +540,17 @@ __device__ inline void mgs_icwy_sweep(const MgsDev &a, int rank, int G, double (
         gather_rows(tab, G, R, il.red, il.tot, lds, err);
     }
     qq = il.tot[k];
-    // forward substitution by one thread (four accumulators per row, added in a fixed
-    // order); the same arithmetic in every block
-    if (threadIdx.x == 0) {
-        for (int i = 0; i < k; ++i) {
-            const double *row = i < k - 1 ? il.tri + i * (i - 1) / 2 : il.tot + k + 1;
-            double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;
-            int j = 0;
-            for (; j + 4 <= i; j += 4) {
-                t0 = fma(row[j], il.h[j], t0);
-                t1 = fma(row[j + 1], il.h[j + 1], t1);
-                t2 = fma(row[j + 2], il.h[j + 2], t2);
-                t3 = fma(row[j + 3], il.h[j + 3], t3);
-            }
-            for (; j < i; ++j) t0 = fma(row[j], il.h[j], t0);
-            il.h[i] = il.tot[i] - ((t0 + t1) + (t2 + t3));
+    // forward substitution by the first wave, column by column: lane j holds h_j and
+    // subtracts <w_j, w_i> h_i once h_i is final (h_i broadcast by readlane); the same
+    // arithmetic, in the same order, in every block
+    if (wave == 0) {
+        double hj = lane < k ? il.tot[lane] : 0.0;
+        const double *lrow = lane < k - 1 ? il.tri + lane * (lane - 1) / 2 : il.tot + k + 1;
+        for (int i = 0; i < k - 1; ++i) {
+            const double hi = readlane_d(hj, i);
+            if (lane > i && lane < k) hj = fma(-lrow[i], hi, hj);
         }
+        if (lane < k) il.h[lane] = hj;
     }
     __syncthreads();
     if (rank == 0) {
