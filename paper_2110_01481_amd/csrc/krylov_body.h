@@ -410,6 +410,131 @@ __device__ inline void givens_wave(double *H, int ld, double *R, double *cs, dou
     }
 }
 
+// Entry idx (uniform) of a vector held NE entries per lane (entry e*64 + lane in v[e]).
+template <int NE>
+__device__ inline double readlane_n(const double (&v)[NE], int idx)
+{
+    double x = 0.0;
+#pragma unroll
+    for (int e = 0; e < NE; ++e)
+        if ((idx >> 6) == e) x = readlane_d(v[e], idx & 63);
+    return x;
+}
+
+// Largest step that givens_wave2 takes (rows 0..k of the new column, two per lane).
+constexpr int kWave2GivensMax = 127;
+
+// givens_wave for kWaveGivensMax < k <= kWave2GivensMax: every per-lane quantity is held
+// as two entries (lane and lane + 64). Same arithmetic, in the same order, as
+// givens_step.
+template <int NE>
+__device__ inline void givens_wave_n(double *H, int ld, double *R, double *cs, double *sn,
+                                     double *g, double *y, double *rho, double beta, int k,
+                                     DevState *st)
+{
+    const int lane = threadIdx.x & 63;
+    const int j = k - 1;
+    const double *Hc = H + (size_t)j * ld;
+    double *Rc = R + (size_t)j * ld;
+    const bool bd = st->bd_k == k;
+    double hv[NE], cv[NE], sv[NE], gl[NE], rv[NE], yv[NE];
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+        const int r = e * 64 + lane;
+        hv[e] = r <= k ? ((r == k && bd) ? 0.0 : Hc[r]) : 0.0;
+        cv[e] = r < j ? cs[r] : 0.0;
+        sv[e] = r < j ? sn[r] : 0.0;
+        gl[e] = r < k ? g[r] : 0.0;
+        rv[e] = 0.0;
+        yv[e] = 0.0;
+    }
+    // rotations 0..j-1 applied to the column: t carries entry i+1 down the column
+    double t = readlane_n(hv, 0);
+    for (int i = 0; i < j; ++i) {
+        const double a = t, b = readlane_n(hv, i + 1);
+        const double ci = readlane_n(cv, i), si = readlane_n(sv, i);
+        const double o = ci * a + si * b;
+        t = -si * a + ci * b;
+#pragma unroll
+        for (int e = 0; e < NE; ++e)
+            if (e * 64 + lane == i) rv[e] = o;
+    }
+    const double a = t, b = readlane_n(hv, k);
+    const double r = hypot(a, b);
+    double c = 1.0, s = 0.0;
+    if (r > 0.0) {
+        c = a / r;
+        s = b / r;
+    } else if (lane == 0) {
+        st->error |= 4;
+    }
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+        const int ri = e * 64 + lane;
+        if (ri == j) rv[e] = r;
+        if (ri < k) Rc[ri] = rv[e];
+        if (ri == k) Rc[k] = 0.0;
+    }
+    const double gj = readlane_n(gl, j);
+    if (lane == 0) {
+        cs[j] = c;
+        sn[j] = s;
+        g[j] = c * gj;
+        g[k] = -s * gj;
+        st->ls = fabs(-s * gj);
+        st->k = k;
+    }
+#pragma unroll
+    for (int e = 0; e < NE; ++e)
+        if (e * 64 + lane == j) gl[e] = c * gj;
+    // back substitution R_k y = g[0..k), column by column from the last
+    for (int jb = j; jb >= 0; jb -= 8) {
+        double col[8][NE];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int jj = jb - u;
+#pragma unroll
+            for (int e = 0; e < NE; ++e) {
+                const int ri = e * 64 + lane;
+                col[u][e] = jj < 0 ? 0.0
+                                   : (jj == j ? rv[e]
+                                              : (ri <= jj ? R[(size_t)jj * ld + ri] : 0.0));
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int jj = jb - u;
+            if (jj < 0) break;
+            const double yj = readlane_n(gl, jj) / readlane_n(col[u], jj);
+#pragma unroll
+            for (int e = 0; e < NE; ++e) {
+                const int ri = e * 64 + lane;
+                if (ri == jj) yv[e] = yj;
+                if (ri < jj) gl[e] -= col[u][e] * yj;
+            }
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < NE; ++e)
+        if (e * 64 + lane < k) y[e * 64 + lane] = yv[e];
+    if (rho) {
+        double acc[NE];
+#pragma unroll
+        for (int e = 0; e < NE; ++e) acc[e] = e * 64 + lane == 0 ? beta : 0.0;
+        for (int jj = 0; jj < k; ++jj) {
+            const double yj = readlane_n(yv, jj);
+#pragma unroll
+            for (int e = 0; e < NE; ++e) {
+                const int ri = e * 64 + lane;
+                if (ri <= k && jj >= ri - 1) acc[e] -= H[(size_t)jj * ld + ri] * yj;
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < NE; ++e)
+            if (e * 64 + lane <= k) rho[e * 64 + lane] = acc[e];
+    }
+}
+
 // After the normalisation, by the block of rank 0 of a single solve's launch: step 0
 // sets beta = ||r_0|| (or raises the zero-right-hand-side stop), step k >= 1 runs the
 // Givens update of column k, then copies the scalars to the host slot.
@@ -432,6 +557,10 @@ __device__ inline void mgs_tail(const MgsDev &a, int rank)
         if (a.step <= kWaveGivensMax) {
             if (threadIdx.x < 64)
                 givens_wave(g.H, g.ld, g.R, g.cs, g.sn, g.g, g.y, g.rho, st->beta, a.step, st);
+        } else if (a.step <= kWave2GivensMax) {
+            if (threadIdx.x < 64)
+                givens_wave_n<2>(g.H, g.ld, g.R, g.cs, g.sn, g.g, g.y, g.rho, st->beta, a.step,
+                                 st);
         } else {
             givens_step<kBlock>(g.H, g.ld, g.R, g.cs, g.sn, g.g, g.y, g.rho, st->beta, a.step,
                                 st);
