@@ -43,12 +43,42 @@ template <> __device__ inline float zero_of<float>() { return 0.0f; }
 template <> __device__ inline bf16 zero_of<bf16>() { return bf16{0}; }
 
 // ---- reductions ----------------------------------------------------------------------
+// Value of a double held by lane l (a compile-time lane) of the wave.
+__device__ inline double readlane_first(double v, int l)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
 // Butterfly sum: lanes l and l^d add the same two operands, so every lane ends with the
 // same value regardless of position.
 __device__ inline double wave_sum(double v)
 {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;
+}
+
+// Wave sum through DPP moves only (no LDS permutes), the same value in every lane: within
+// each row of 16 lanes x += ror(x, 8), x += ror(x, 4), then the quad swaps of 2 and 1
+// (each add takes the same two operands in the lanes it pairs, so the row's lanes agree);
+// the four row totals are then added in row order from lanes 0, 16, 32, 48.
+template <int CTRL> __device__ inline double dpp_move(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, true);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ inline double wave_sum_dpp(double v)
+{
+    v += dpp_move<0x128>(v);   // row_ror:8
+    v += dpp_move<0x124>(v);   // row_ror:4
+    v += dpp_move<0x4e>(v);    // quad_perm [2,3,0,1]
+    v += dpp_move<0xb1>(v);    // quad_perm [1,0,3,2]
+    return ((readlane_first(v, 0) + readlane_first(v, 16)) + readlane_first(v, 32)) +
+           readlane_first(v, 48);
 }
 
 // Block sum returned to every thread, fixed order.
@@ -183,7 +213,7 @@ __device__ inline void gather_rows(const double *tab, int G, int R, double (*red
         }
         // all kGatherRows wave sums in one straight-line block (rows past nr dropped)
 #pragma unroll
-        for (int r = 0; r < kGatherRows; ++r) v[r] = wave_sum(j < G ? v[r] : 0.0);
+        for (int r = 0; r < kGatherRows; ++r) v[r] = wave_sum_dpp(j < G ? v[r] : 0.0);
         if (lane == 0) {
 #pragma unroll
             for (int r = 0; r < kGatherRows; ++r)
@@ -639,8 +669,8 @@ __device__ inline void mgs_icwy_sweep(const MgsDev &a, int rank, int G, double (
         }
 #pragma unroll
         for (int d = 0; d < D; ++d) {
-            ds[d] = wave_sum(ds[d]);
-            dl[d] = wave_sum(dl[d]);
+            ds[d] = wave_sum_dpp(ds[d]);
+            dl[d] = wave_sum_dpp(dl[d]);
         }
         if (lane == 0) {
 #pragma unroll
@@ -651,7 +681,7 @@ __device__ inline void mgs_icwy_sweep(const MgsDev &a, int rank, int G, double (
             }
         }
     }
-    s2 = wave_sum(s2);
+    s2 = wave_sum_dpp(s2);
     if (lane == 0) il.part[wave][k] = s2;
     __syncthreads();
     const int R = 2 * k;
