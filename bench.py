@@ -29,10 +29,24 @@ if ROOT not in sys.path:
 import workloads as W  # noqa: E402
 
 HBM_PEAK_GBPS = 8000.0
-COUNTERS_SUMMARY = os.path.join(ROOT, "profiles", "forward_kernel_512x512_720x725_counters.md")
-# sources whose change invalidates the stored counter readings of the forward projector
-FORWARD_SOURCES = ["paper_2110_01481_amd/csrc/fwd_body.h", "paper_2110_01481_amd/csrc/geometry.h",
-                   "paper_2110_01481_amd/csrc/projectors.hip"]
+PROFILES = os.path.join(ROOT, "profiles")
+_CSRC = "paper_2110_01481_amd/csrc/"
+# kernels whose stored counter summaries (profiles/<kernel>_<workload>_counters.md) bench.py
+# reads: the kernel-name prefix in rocprofv3's CSV and the sources whose change makes the
+# stored readings stale
+COUNTER_KERNELS = {
+    "forward_kernel_f32": ("forward_kernel<float>",
+                           [_CSRC + "fwd_body.h", _CSRC + "geometry.h", _CSRC + "projectors.hip"]),
+    "forward_kernel_f64": ("forward_kernel<double>",
+                           [_CSRC + "fwd_body.h", _CSRC + "geometry.h", _CSRC + "projectors.hip"]),
+    "back_kernel_f64": ("back_kernel<double, false, false>",
+                        [_CSRC + "back_body.h", _CSRC + "geometry.h", _CSRC + "projectors.hip"]),
+    "back_kernel_f32": ("back_kernel<float, false, false>",
+                        [_CSRC + "back_body.h", _CSRC + "geometry.h", _CSRC + "projectors.hip"]),
+}
+# kernels of a solve whose L2 hit rate the TCC pass reports
+L2_KERNELS = ("forward_kernel", "back_kernel", "mgs_kernel", "mgs_icwy_kernel",
+              "mgs_stream_kernel", "combine_kernel", "ncp_rows_kernel")
 
 
 def progress(msg: str):
@@ -40,13 +54,17 @@ def progress(msg: str):
     print(f"bench: {msg}", file=sys.stderr, flush=True)
 
 
-def forward_source_hash() -> str:
+def source_hash(kernel_key: str) -> str:
     import hashlib
     h = hashlib.sha256()
-    for f in FORWARD_SOURCES:
+    for f in COUNTER_KERNELS[kernel_key][1]:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+def forward_source_hash() -> str:
+    return source_hash("forward_kernel_f32")
 
 
 def _counter_means(csv_path: str, kernel_prefix: str) -> dict:
@@ -63,27 +81,30 @@ def _counter_means(csv_path: str, kernel_prefix: str) -> dict:
     return {c: sums[c] / counts[c] for c in sums}
 
 
-def summarize_counters(d: str) -> str:
+def summarize_counters(d: str, kernel_key: str = "forward_kernel_f32",
+                       workload: str = "512x512, 720 x 725, FP32", bench_args: str = "") -> str:
     """Markdown summary of the FETCH_SIZE / WRITE_SIZE passes under directory d (sub-
-    directories fetch, write, cfetch, cwrite as written by the commands listed in it)."""
-    f = _counter_means(os.path.join(d, "fetch", "run_counter_collection.csv"), "forward_kernel<float>")
-    w = _counter_means(os.path.join(d, "write", "run_counter_collection.csv"), "forward_kernel<float>")
+    directories fetch, write, cfetch, cwrite, and optionally sq and l2, as written by the
+    commands listed in it) for the kernel `kernel_key` of COUNTER_KERNELS."""
+    kname = COUNTER_KERNELS[kernel_key][0]
+    f = _counter_means(os.path.join(d, "fetch", "run_counter_collection.csv"), kname)
+    w = _counter_means(os.path.join(d, "write", "run_counter_collection.csv"), kname)
     cf = _counter_means(os.path.join(d, "cfetch", "run_counter_collection.csv"), "__amd_rocclr_copyBuffer")
     cw = _counter_means(os.path.join(d, "cwrite", "run_counter_collection.csv"), "__amd_rocclr_copyBuffer")
     copy_kib = 1024 * 1024
-    data = {"kernel": "forward_kernel<float>", "workload": "512x512, 720 x 725, FP32",
+    data = {"kernel": kname, "workload": workload,
             "fetch_kib_per_dispatch": round(f["FETCH_SIZE"], 1),
             "write_kib_per_dispatch": round(w["WRITE_SIZE"], 1),
             "copy_kib": copy_kib,
             "copy_fetch_kib": round(cf["FETCH_SIZE"], 1), "copy_write_kib": round(cw["WRITE_SIZE"], 1),
             "fetch_scale": round(copy_kib / cf["FETCH_SIZE"], 4),
             "write_scale": round(copy_kib / cw["WRITE_SIZE"], 4),
-            "source_hash": forward_source_hash()}
+            "source_hash": source_hash(kernel_key)}
     data["traffic_bytes_per_launch"] = int(1024 * (data["fetch_kib_per_dispatch"] * data["fetch_scale"] +
                                                    data["write_kib_per_dispatch"] * data["write_scale"]))
     sq_csv = os.path.join(d, "sq", "run_counter_collection.csv")
     if os.path.exists(sq_csv):
-        sq = _counter_means(sq_csv, "forward_kernel<float>")
+        sq = _counter_means(sq_csv, kname)
         data["valu_wave_insts_per_dispatch"] = round(sq["SQ_INSTS_VALU"], 1)
     l2_csv = os.path.join(d, "l2", "run_counter_collection.csv")
     if os.path.exists(l2_csv):
@@ -94,15 +115,14 @@ def summarize_counters(d: str) -> str:
             hit, miss = m.get("TCC_HIT_sum", 0.0), m.get("TCC_MISS_sum", 0.0)
             if hit + miss > 0:
                 data["l2_hit_rate"][k] = round(hit / (hit + miss), 4)
-    b = ("python -u bench.py --steps 2 --warmup 1 --no-cpu-baseline --no-fp64 --no-batch "
-         "--serve-seconds 0 --no-models")
+    b = "python -u bench.py " + (bench_args or "--config 2 --steps 2 --warmup 1 --quick")
     c = "python -u bench.py --copy-calibration-mib 1024"
     sqc = ("SQ_WAVES SQ_BUSY_CYCLES SQ_WAVE_CYCLES SQ_INSTS_VALU SQ_INSTS_VMEM_RD "
            "SQ_ACTIVE_INST_VALU SQ_WAIT_ANY GRBM_GUI_ACTIVE")
     lines = [
-        "# HBM traffic of the forward projector (512x512 image, 720 x 725 sinogram, FP32)",
+        f"# HBM traffic of {kname} ({workload})",
         "",
-        "Counters per dispatch of `forward_kernel<float>`, averaged over the dispatches of the",
+        f"Counters per dispatch of `{kname}`, averaged over the dispatches of the",
         "run, and of the plain device copy of 1 GiB (`__amd_rocclr_copyBuffer`) that calibrates",
         "them: the copy reads and writes exactly 1 GiB, so each counter is scaled by",
         "1 GiB / (its reading on the copy).",
@@ -115,14 +135,14 @@ def summarize_counters(d: str) -> str:
         f"    rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir>/cwrite -o run -- {c}",
         f"    rocprofv3 --pmc {sqc} --output-format csv -d <dir>/sq -o run -- {b}",
         f"    rocprofv3 --pmc TCC_HIT_sum TCC_MISS_sum --output-format csv -d <dir>/l2 -o run -- {b}",
-        "    python bench.py --summarize-counters <dir>",
+        f"    python bench.py --summarize-counters <dir> --counter-kernel {kernel_key}",
         "",
         "The SQ pass gives the VALU instructions per dispatch (wave level; x 64 lanes for",
         "the lane operations that bench.py sets against the VALU issue rate); the TCC pass",
         "the L2 hit rate, hits / (hits + misses), of each kernel of the solve.",
         "",
-        "`source_hash` covers the forward projector's sources; bench.py reports `traffic` only",
-        "while it matches.",
+        "`source_hash` covers the kernel's sources; bench.py reports `traffic` only while it",
+        "matches.",
         "",
         "```json",
         json.dumps(data, indent=1),
@@ -131,19 +151,19 @@ def summarize_counters(d: str) -> str:
     return "\n".join(lines)
 
 
-L2_KERNELS = ("forward_kernel<float>", "back_kernel<float, false, false>",
-              "back_kernel<float, false, true>", "mgs_kernel", "combine_kernel")
-
-
-def stored_traffic() -> dict | None:
-    """The stored counter summary, if it was taken on the current forward projector."""
+def stored_counters(kernel_key: str, workload_tag: str) -> dict | None:
+    """The stored counter summary of a kernel on a workload, if it was taken on the
+    kernel's current sources."""
+    path = os.path.join(PROFILES, f"{kernel_key}_{workload_tag}_counters.md")
     try:
-        with open(COUNTERS_SUMMARY) as fh:
+        with open(path) as fh:
             text = fh.read()
         data = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
     except (OSError, IndexError, ValueError):
         return None
-    return data if data.get("source_hash") == forward_source_hash() else None
+    return data if data.get("source_hash") == source_hash(kernel_key) else None
+
+
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 VALU_ISSUE_PEAK = 256 * 4 * 16 * 2.4e9   # lane operations per second
 FP64_VECTOR_PEAK_TFLOPS = 78.6
@@ -203,34 +223,77 @@ def _stream_kernel_stats(ms_total, launches, bytes_total, reductions=None):
 
 
 def cpu_oracle_baseline(w, b_np, enorm, budget_s=15.0, max_iters=10):
-    """Times the FP64 oracle's AB-GMRES (unmatched pair) on the same workload for as
-    many Arnoldi iterations as fit in ~budget_s seconds."""
+    """Times the FP64 oracle's AB-GMRES (unmatched pair) on the 512^2 workload for as many
+    Arnoldi iterations as fit in ~budget_s seconds (each run from scratch)."""
     import oracle as O
     from oracle.core import num_threads
     g = O.Geometry(w.N, w.n_ang, w.n_det)
-    # one A and one B apply of the oracle's C projectors, for the per-apply figures
-    t0 = time.perf_counter()
-    ya = g.A(np.ones(g.n))
-    t_a = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    g.B_hat(ya)
-    t_b = time.perf_counter() - t0
     k = 1
-    t_used = 0.0
-    # grow the iteration count until the budget is used (each run starts from scratch)
     while True:
         t0 = time.perf_counter()
         O.ab_gmres(g.A, g.B_hat, b_np, k)
         dt = time.perf_counter() - t0
-        t_used += dt
         if dt * 2.2 > budget_s or k >= max_iters:
-            return {"value": k / dt, "unit": "GMRES iters/s", "cores": num_threads(),
-                    "kind": "oracle", "A_apply_s": round(t_a, 4), "B_apply_s": round(t_b, 4),
-                    "host_cpu": _cpu_model(),
+            return {"value": round(k / dt, 4), "unit": "GMRES iters/s", "cores": num_threads(),
+                    "kind": "oracle", "host_cpu": _cpu_model(),
                     "sample": f"FP64 oracle AB-GMRES, {k} Arnoldi iterations from x0=0 on the "
                               f"{w.N}^2 / {w.n_ang}x{w.n_det} workload (literal x_k and b-Ax_k "
                               f"each step), {dt:.2f} s; host {os.cpu_count()} logical CPUs"}
         k = min(max_iters, k * 2)
+
+
+def cpu_oracle_baseline_ncp(w, b_np, xb, arnoldi_steps=0):
+    """The FP64 oracle on the 2048^2 NCP workload, on the host cores. A BA-GMRES
+    iteration with the NCP rule applies A and B once (q = B A w_k), forms x_k = W_k y_k,
+    applies A once more for the literal residual b - A x_k and evaluates its periodogram
+    distance; its Gram-Schmidt and least squares cost O(k L) and O(k^3). The bounded
+    sample times one oracle A apply (on the phantom), one B apply (on b) and one NCP
+    distance (of b - A x_bar) and gives value = 1 / (2 t_A + t_B + t_NCP) iterations per
+    second, an upper bound on the oracle's rate (its Gram-Schmidt is left out).
+    arnoldi_steps > 0 also runs the oracle's BA-GMRES for that many iterations with its
+    operators wrapped in timers, and reports the time per iteration after the set-up
+    applies (B of a zero vector for the size, A x_0, B r_0)."""
+    import oracle as O
+    from oracle.core import num_threads
+    g = O.Geometry(w.N, w.n_ang, w.n_det)
+    t0 = time.perf_counter()
+    ax = g.A(xb)
+    t_a = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    g.B_hat(b_np)
+    t_b = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    O.ncp_distance(b_np - ax, g.n_ang, g.n_det)
+    t_ncp = time.perf_counter() - t0
+    it = 2 * t_a + t_b + t_ncp
+    out = {"value": round(1.0 / it, 5), "unit": "GMRES iters/s", "cores": num_threads(),
+           "kind": "oracle", "host_cpu": _cpu_model(),
+           "A_apply_s": round(t_a, 3), "B_apply_s": round(t_b, 3), "ncp_s": round(t_ncp, 3),
+           "sample": f"FP64 oracle on the {w.N}^2 / {w.n_ang}x{w.n_det} workload: one A apply "
+                     f"({t_a:.1f} s), one B apply ({t_b:.1f} s) and one NCP distance "
+                     f"({t_ncp:.2f} s); value = 1/(2 t_A + t_B + t_NCP), the operator and "
+                     f"stopping-rule cost of one BA-GMRES iteration; host {os.cpu_count()} "
+                     "logical CPUs"}
+    if arnoldi_steps > 0:
+        calls = []
+
+        def timed(name, f):
+            def run(v):
+                t1 = time.perf_counter()
+                r = f(v)
+                calls.append((name, time.perf_counter() - t1))
+                return r
+            return run
+
+        t0 = time.perf_counter()
+        O.ba_gmres(timed("A", g.A), timed("B", g.B_hat), b_np, arnoldi_steps, stop="ncp",
+                   ncp_shape=(g.n_ang, g.n_det))
+        total = time.perf_counter() - t0
+        setup = sum(dt for _, dt in calls[:3])    # B(0) for the size, A x_0, B r_0
+        out["arnoldi"] = {"steps": arnoldi_steps, "s": round(total, 2),
+                          "s_per_iteration": round((total - setup) / arnoldi_steps, 2),
+                          "iters_per_s": round(arnoldi_steps / (total - setup), 5)}
+    return out
 
 
 def _dp_problem(abg, torch, gg, w, xt, dev, seed):
@@ -622,35 +685,198 @@ def bench_serving(abg, torch, dev, seconds, bases, tiles, single_sample=24):
     return out
 
 
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+
+
+def oracle_iterate(cfg: int):
+    """The oracle's returned iterate of the workload, stored whole by
+    tests/golden/make_oracle_golden.py (config 3: x_{k_NCP}, rounded to FP32), and its
+    stopping iteration; None when absent."""
+    try:
+        with open(os.path.join(GOLDEN, f"oracle_config{cfg}.json")) as fh:
+            meta = json.load(fh)
+        if cfg == 3:
+            return np.load(os.path.join(GOLDEN, "oracle_config3_x.npy")).astype(np.float64), meta
+        z = np.load(os.path.join(GOLDEN, "oracle_config2_x.npz"))
+        return {k: z[k] for k in z.files}, meta
+    except (OSError, ValueError, KeyError):
+        return None, None
+
+
+class SingleRun:
+    """Repeated single solves of one workload through the C ABI: untimed warm-up steps,
+    a timed region without instrumentation, then (optionally) the same steps with every
+    projector, Gram-Schmidt, basis-combination and NCP launch stamped with HIP events on
+    the solver's stream (abg_profile_enable): the kernels' durations."""
+
+    def __init__(self, abg, torch, gg, w, methods, b, basis, stop, tau, enorm):
+        self.abg, self.torch, self.gg, self.w = abg, torch, gg, w
+        self.methods, self.b, self.basis = methods, b, basis
+        self.stop, self.tau, self.enorm = stop, tau, enorm
+        proj = "f64" if b.dtype == torch.float64 else "f32"
+        self.bufs = {}
+        for m in methods:
+            nb = abg.workspace_bytes(gg, m, w.k_max, proj=proj, basis=basis, stop=stop)
+            self.bufs[m] = (torch.empty(nb, dtype=torch.uint8, device=b.device),
+                            torch.empty(gg.n, dtype=b.dtype, device=b.device))
+
+    def step(self):
+        iters, res = 0, {}
+        for m in self.methods:
+            ws, out = self.bufs[m]
+            r = self.abg.gmres(m, self.gg, self.b, self.w.k_max, stop=self.stop, tau=self.tau,
+                               noise_norm=self.enorm, basis=self.basis, workspace=ws, out=out)
+            iters += r.k_done
+            res[m] = r
+        return iters, res
+
+    def run(self, steps, warmup, instrument=True):
+        torch, abg = self.torch, self.abg
+        for _ in range(warmup):
+            self.step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        iters, last = 0, None
+        for _ in range(steps):
+            n, last = self.step()
+            iters += n
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out = {"iters_per_s": iters / dt, "ms_per_step": 1e3 * dt / steps, "iters": iters,
+               "last": last, "prof": None}
+        if instrument:
+            abg.profile_enable(True)
+            abg.profile_read(reset=True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            n_i = 0
+            for _ in range(steps):
+                n_i += self.step()[0]
+            torch.cuda.synchronize()
+            out["instrumented"] = {"ms_per_step": round(1e3 * (time.perf_counter() - t0) / steps, 3),
+                                   "iters": n_i}
+            out["prof"] = abg.profile_read(reset=True)
+            abg.profile_enable(False)
+        return out
+
+
+def _rel(a, b) -> float:
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _work_per_launch(w, proj: str):
+    """Algorithmic work of one launch of each compute-bound kernel on workload w: 2 flop per
+    nonzero of A (forward), 4 flop per pixel-angle pair (back: two taps), 3 flop per
+    Goertzel step (NCP: N_det steps for each of floor(N_det/2) frequencies of every row)."""
+    th = (np.arange(w.n_ang) * w.ang_range) / w.n_ang
+    nnz = line_model_nnz(w.N, th, w.n_det)
+    q = w.n_det // 2
+    return {"forward": (2.0 * nnz, f"{nnz} ray-pixel intersections x 2 flop"),
+            "back": (4.0 * w.n * w.n_ang, f"{w.n * w.n_ang} pixel-angle pairs x 4 flop"),
+            "ncp": (3.0 * w.n_ang * q * w.n_det,
+                    f"{w.n_ang} rows x {q} frequencies x {w.n_det} Goertzel steps x 3 flop")}, nnz
+
+
+def roofline_of(prof, w, proj: str, tag: str):
+    """Roofline object of the kernel class with the largest share of the instrumented pass."""
+    share = {k: v[1] for k, v in prof.items() if v[0] > 0}
+    dominant = max(share, key=share.get)
+    n, ms = prof[dominant]
+    avg_ms = ms / n
+    peak = FP64_VECTOR_PEAK_TFLOPS if proj == "f64" else FP32_VECTOR_PEAK_TFLOPS
+    work, _ = _work_per_launch(w, proj)
+    names = {"forward": f"forward_kernel<{'double' if proj == 'f64' else 'float'}> (ray-driven "
+                        f"line model A, {proj.upper()})",
+             "back": f"back_kernel (pixel-driven unmatched B, {proj.upper()})",
+             "ncp": "ncp_rows/mean/final kernels (periodogram of every sinogram row, FP64)",
+             "mgs": "mgs kernels (Gram-Schmidt + Givens)", "combine": "combine_kernel"}
+    roof = {"kernel": names[dominant], "avg_launch_ms": round(avg_ms, 4),
+            "share_of_kernel_time": round(ms / sum(share.values()), 4)}
+    if dominant in work:
+        flops, desc = work[dominant]
+        pk = FP64_VECTOR_PEAK_TFLOPS if dominant == "ncp" else peak
+        ach = flops / (avg_ms * 1e-3) / 1e12
+        roof.update({"bound": "alu", "achieved": round(ach, 3), "peak": pk, "unit": "TFLOP/s",
+                     "frac": round(ach / pk, 4), "traffic": None, "work_per_launch": desc})
+        key = f"{dominant}_kernel_{proj}"
+        tr = stored_counters(key, tag) if key in COUNTER_KERNELS else None
+        if tr:
+            roof["traffic"] = tr["traffic_bytes_per_launch"]
+            roof["traffic_note"] = (f"HBM bytes per launch from FETCH_SIZE x {tr['fetch_scale']} + "
+                                    f"WRITE_SIZE x {tr['write_scale']} (copy-calibrated, "
+                                    f"profiles/{key}_{tag}_counters.md); "
+                                    f"{tr['traffic_bytes_per_launch'] / (avg_ms * 1e-3) / 1e9:.0f} GB/s")
+            if "valu_wave_insts_per_dispatch" in tr:
+                lane_ops = 64.0 * tr["valu_wave_insts_per_dispatch"]
+                roof["valu_issue_frac"] = round(lane_ops / (avg_ms * 1e-3) / VALU_ISSUE_PEAK, 4)
+            if tr.get("l2_hit_rate"):
+                roof["l2_hit_rate"] = tr["l2_hit_rate"].get(dominant + "_kernel")
+    else:
+        roof.update({"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": None, "traffic": None})
+    return roof
+
+
+def krylov_bytes(methods, w, last, sv: int, sx: int):
+    """Algorithmic HBM bytes of the Gram-Schmidt and basis-combination launches of one
+    step. Step j (0..k_done) of a solve reads q and w_1..w_j and writes w_{j+1} and its
+    copy; the residual form of step j reads j (BA: Z, plus b - A x_0) or j+1 (AB: W)
+    vectors of m and writes one; forming the iterate reads k_done basis vectors."""
+    mgs = comb = red = 0
+    for m in methods:
+        L = w.m if m == "ab" else w.n
+        kd = last[m].k_done
+        for j in range(kd + 1):
+            mgs += j * L * sv + L * sv + 2 * L * sx
+            red += j + 1
+        for j in range(1, kd + 1):
+            comb += ((j + 1) * w.m * sx + w.m * sx) if m == "ba" else ((j + 1) * w.m * sv + w.m * sx)
+        comb += kd * L * sv + L * sx
+    return mgs, comb, red
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    # 200 warm-up steps (~0.7 s at 512^2): after idle the device needs that long under load
-    # before a timed region runs at its steady rate (with 5, the first region after start
-    # ran up to 15% slower than later ones)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3])
-    ap.add_argument("--basis", default="f32", choices=["f32", "bf16"])
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default 30 at 2048^2, 50 otherwise)")
+    # after idle the device needs ~0.7 s under load before a timed region runs at its
+    # steady rate (with too short a warm-up the first region ran up to 15% slower)
+    ap.add_argument("--warmup", type=int, default=None,
+                    help="warm-up steps (default 8 at 2048^2, 200 otherwise)")
+    ap.add_argument("--config", type=int, default=3, choices=[1, 2, 3],
+                    help="3: 2048^2 BA-GMRES NCP (default); 2: 512^2 AB+BA DP; 1: 64^2")
+    ap.add_argument("--proj", default=None, choices=["f64", "f32"],
+                    help="projector dtype of the timed solves (default f64 at 2048^2, else f32)")
+    ap.add_argument("--basis", default=None, choices=["f64", "f32", "bf16"],
+                    help="basis storage dtype (default: the projector dtype)")
+    ap.add_argument("--quick", action="store_true",
+                    help="only the timed workload (no variants, 512^2 extras, batched mix, "
+                         "serving or CPU baseline): for profiler runs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--cpu-arnoldi-steps", type=int, default=0,
+                    help="also time this many iterations of the oracle's BA-GMRES at 2048^2")
     ap.add_argument("--no-batch", action="store_true")
-    ap.add_argument("--serve-seconds", type=float, default=10.0,
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="seconds of Poisson arrivals for the serving run (0: skip)")
     ap.add_argument("--serve-basis", default="f32,bf16")
     ap.add_argument("--no-concurrent", action="store_true",
-                    help="skip the AB || BA run on two streams (its overlapped launches last "
-                         "longer, which a kernel-time profile of the run would average in)")
+                    help="skip the 512^2 AB || BA run on two streams")
     ap.add_argument("--no-models", action="store_true",
-                    help="skip the strip / Joseph models and the six unmatched pairs")
+                    help="skip the strip / Joseph models, the six unmatched pairs, few-view, "
+                         "error histories and LSQR/LSMR")
     ap.add_argument("--summarize-counters", default="",
                     help="print the counter summary of the rocprofv3 passes under this directory")
+    ap.add_argument("--counter-kernel", default="forward_kernel_f32", choices=sorted(COUNTER_KERNELS))
+    ap.add_argument("--counter-workload", default="512x512, 720 x 725, FP32")
+    ap.add_argument("--counter-bench-args", default="")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run device-to-device copies of this many MiB (a plain copy "
                          "kernel whose HBM counters calibrate FETCH_SIZE / WRITE_SIZE)")
     args = ap.parse_args()
     if args.summarize_counters:
-        print(summarize_counters(args.summarize_counters))
+        print(summarize_counters(args.summarize_counters, args.counter_kernel,
+                                 args.counter_workload, args.counter_bench_args))
         return
     if args.gpus != 1:
         print(json.dumps({"error": "the solver library runs on one GPU; --gpus N > 1 is not "
@@ -672,216 +898,191 @@ def main():
         print(json.dumps({"copy_calibration_bytes": nb, "copies": 3}))
         return
     abg.load_library()
+    try:
+        out = run_bench(args, abg, torch)
+    finally:
+        # release the library's process-wide resources before the interpreter and the
+        # HIP runtime shut down
+        abg.shutdown()
+    print(json.dumps(out), flush=True)
+
+
+def run_bench(args, abg, torch):
+    big = args.config == 3
+    steps = args.steps if args.steps is not None else (30 if big else 50)
+    warmup = args.warmup if args.warmup is not None else (8 if big else 200)
+    proj = args.proj or ("f64" if big else "f32")
+    basis = args.basis or proj
     w = {1: W.CONFIG1, 2: W.CONFIG2, 3: W.CONFIG3}[args.config]
-    k_max = w.k_max
-    gg = abg.Geometry(w.N, w.n_ang, w.n_det, ang_range=w.ang_range)
+    tag = f"{w.N}x{w.N}_{w.n_ang}x{w.n_det}"
     dev = torch.device("cuda:0")
+    gg = abg.Geometry(w.N, w.n_ang, w.n_det, ang_range=w.ang_range)
     xb = w.phantom()
+    # b = A x_bar + e: A x_bar by the library's FP64 forward projector (the oracle's FP64
+    # A gives the same vector to rounding), e the seeded noise direction scaled to eta
     bbar = gg.fp(torch.tensor(xb, dtype=torch.float64, device=dev)).cpu().numpy()
+    gg.release_workspace()
     b_np, enorm = W.add_noise(bbar, w.eta, w.noise_dir())
-    b32 = torch.tensor(b_np, dtype=torch.float32, device=dev)
-    b64 = torch.tensor(b_np, dtype=torch.float64, device=dev)
-    stop = "dp" if w.stop == "dp" else w.stop
+    bt = {"f64": torch.tensor(b_np, dtype=torch.float64, device=dev),
+          "f32": torch.tensor(b_np, dtype=torch.float32, device=dev)}
+    stop = w.stop if w.stop != "none" else "dp"
     tau = w.tau if stop == "dp" else 1.0
-    if args.config == 1:
-        stop, tau = "dp", 1.0
-
-    def make(method, b, basis):
-        nb = abg.workspace_bytes(gg, method, k_max, proj="f64" if b.dtype == torch.float64 else "f32",
-                                 basis=basis, stop=stop)
-        return (torch.empty(nb, dtype=torch.uint8, device=dev),
-                torch.empty(gg.n, dtype=b.dtype, device=dev))
-
-    methods = ["ab", "ba"] if args.config != 3 else ["ba"]
-    bufs = {m: make(m, b32, args.basis) for m in methods}
-
-    def step(b, basis, bset):
-        iters = 0
-        res = {}
-        for m in methods:
-            ws, out = bset[m]
-            r = abg.gmres(m, gg, b, k_max, stop=stop, tau=tau, noise_norm=enorm, basis=basis,
-                          workspace=ws, out=out)
-            iters += r.k_done
-            res[m] = r
-        return iters, res
-
-    for _ in range(args.warmup):
-        step(b32, args.basis, bufs)
-    torch.cuda.synchronize()
-    # the timed region runs without instrumentation: launches that carry timing events
-    # dispatch more slowly (~30 us of gaps per iteration at this size)
-    t0 = time.perf_counter()
-    iters = 0
-    last = None
-    for _ in range(args.steps):
-        n, last = step(b32, args.basis, bufs)
-        iters += n
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    elapsed = t1 - t0
-    value = iters / elapsed
-    ms_per_step = 1e3 * elapsed / args.steps
-    progress(f"timed region: {value:.1f} iters/s")
-    # the same steps again with every projector, Gram-Schmidt and combination launch
-    # stamped with HIP events at its own start and end (on the solver's stream): the
-    # kernels' durations for the roofline and the breakdown
-    abg.profile_enable(True)
-    abg.profile_read(reset=True)
-    torch.cuda.synchronize()
-    ti0 = time.perf_counter()
-    iters_i = 0
-    for _ in range(args.steps):
-        iters_i += step(b32, args.basis, bufs)[0]
-    torch.cuda.synchronize()
-    ti1 = time.perf_counter()
-    prof = abg.profile_read(reset=True)
-    abg.profile_enable(False)
-
-    # kernel shares of the timed region
-    share = {k: v[1] for k, v in prof.items()}
-    dominant = max(share, key=share.get)
+    methods = ["ba"] if big else ["ab", "ba"]
+    progress(f"timed workload {tag}, {'+'.join(methods)}, {stop}, proj {proj}, basis {basis}")
+    main_run = SingleRun(abg, torch, gg, w, methods, bt[proj], basis, stop, tau, enorm)
+    r = main_run.run(steps, warmup)
+    value, last, prof = r["iters_per_s"], r["last"], r["prof"]
+    progress(f"timed region: {value:.2f} iters/s ({r['ms_per_step']:.2f} ms per step)")
+    roof = roofline_of(prof, w, proj, tag)
+    work, nnz = _work_per_launch(w, proj)
     fwd_n, fwd_ms = prof["forward"]
     bck_n, bck_ms = prof["back"]
-    mgs_n, mgs_ms = prof["mgs"]
-    fwd_avg_ms = fwd_ms / max(fwd_n, 1)
-    bck_avg_ms = bck_ms / max(bck_n, 1)
-    th = (np.arange(w.n_ang) * w.ang_range) / w.n_ang
-    nnz = line_model_nnz(w.N, th, w.n_det)
-    n_pix_ang = w.n * w.n_ang
-    # algorithmic work per apply: one multiply-add per nonzero of A (forward) and two
-    # interpolation taps per pixel-angle pair (back); bytes of the equivalent explicit
-    # sparse matrix-vector product (4-byte index + 4-byte value per nonzero + vectors)
-    spmv_bytes = nnz * 8 + (w.n + w.m) * 4
-    fwd_tflops = 2.0 * nnz / (fwd_avg_ms * 1e-3) / 1e12
-    bck_tflops = 4.0 * n_pix_ang / (bck_avg_ms * 1e-3) / 1e12
-    if dominant == "back":
-        roof = {"bound": "alu", "kernel": "back_kernel (pixel-driven B, FP32)",
-                "achieved": round(bck_tflops, 3), "peak": FP32_VECTOR_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(bck_tflops / FP32_VECTOR_PEAK_TFLOPS, 4),
-                "traffic": None, "avg_launch_ms": round(bck_avg_ms, 4),
-                "work_per_launch": f"{n_pix_ang} pixel-angle pairs x 4 flop"}
-    elif dominant == "mgs":
-        L_avg = (w.m + w.n) / 2
-        roof = {"bound": "hbm", "kernel": "mgs_kernel", "achieved": None, "peak": HBM_PEAK_GBPS,
-                "unit": "GB/s", "frac": None, "traffic": None,
-                "avg_launch_ms": round(mgs_ms / max(mgs_n, 1), 4)}
-    else:
-        tr = stored_traffic() if args.config == 2 else None
-        roof = {"bound": "alu", "kernel": "forward_kernel (ray-driven line model A, FP32)",
-                "achieved": round(fwd_tflops, 3), "peak": FP32_VECTOR_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(fwd_tflops / FP32_VECTOR_PEAK_TFLOPS, 4),
-                "traffic": tr["traffic_bytes_per_launch"] if tr else None,
-                "avg_launch_ms": round(fwd_avg_ms, 4),
-                "work_per_launch": f"{nnz} ray-pixel intersections x 2 flop"}
-        if tr and "valu_wave_insts_per_dispatch" in tr:
-            # the survey's primary reading: VALU lane operations against the issue rate
-            lane_ops = 64.0 * tr["valu_wave_insts_per_dispatch"]
-            roof["valu_issue_frac"] = round(lane_ops / (fwd_avg_ms * 1e-3) / VALU_ISSUE_PEAK, 4)
-            roof["valu_note"] = (f"{lane_ops:.3g} VALU lane operations per launch (SQ_INSTS_VALU x 64) "
-                                 f"against {VALU_ISSUE_PEAK:.3g} lane-ops/s (256 CUs x 4 SIMDs x 16 "
-                                 "lanes x 2.4 GHz)")
-        if tr:
-            roof["traffic_note"] = (f"HBM bytes per launch from FETCH_SIZE x {tr['fetch_scale']} + "
-                                    f"WRITE_SIZE x {tr['write_scale']} (copy-calibrated); "
-                                    f"{tr['traffic_bytes_per_launch'] / (fwd_avg_ms * 1e-3) / 1e9:.0f} GB/s")
-        if tr and tr.get("l2_hit_rate"):
-            roof["l2_hit_rate"] = tr["l2_hit_rate"].get("forward_kernel<float>")
-
+    fwd_avg, bck_avg = fwd_ms / max(fwd_n, 1), bck_ms / max(bck_n, 1)
+    sx = 8 if proj == "f64" else 4
+    sv = {"f64": 8, "f32": 4, "bf16": 2}[basis]
+    spmv_bytes = nnz * (sx + 4) + (w.n + w.m) * sx
     extra = {
-        "A_applies_per_s": round(1e3 / fwd_avg_ms, 1) if fwd_n else None,
-        "B_applies_per_s": round(1e3 / bck_avg_ms, 1) if bck_n else None,
-        "A_spmv_equiv_GBps": round(spmv_bytes / (fwd_avg_ms * 1e-3) / 1e9, 1) if fwd_n else None,
-        "B_spmv_equiv_GBps": round(spmv_bytes / (bck_avg_ms * 1e-3) / 1e9, 1) if bck_n else None,
+        "A_applies_per_s": round(1e3 / fwd_avg, 2) if fwd_n else None,
+        "B_applies_per_s": round(1e3 / bck_avg, 2) if bck_n else None,
+        "A_spmv_equiv_GBps": round(spmv_bytes / (fwd_avg * 1e-3) / 1e9, 1) if fwd_n else None,
+        "B_spmv_equiv_GBps": round(spmv_bytes / (bck_avg * 1e-3) / 1e9, 1) if bck_n else None,
+        "spmv_equiv_note": "bytes an explicit CSR product would stream: nnz x (value + 4-byte "
+                           "index) + the two vectors",
         "nnz_A": nnz,
         "kernel_ms": {k: [v[0], round(v[1], 3)] for k, v in prof.items()},
-        "instrumented_pass": {"ms_per_step": round(1e3 * (ti1 - ti0) / args.steps, 3),
-                              "iters": iters_i, "iters_timed": iters},
+        "instrumented_pass": r["instrumented"],
         "k_stop": {m: last[m].k_stop for m in methods},
         "k_done": {m: last[m].k_done for m in methods},
-        "n_literal": {m: last[m].n_literal for m in methods},
     }
-    l2 = (stored_traffic() or {}).get("l2_hit_rate") if args.config == 2 else None
-    if l2:
-        extra["l2_hit_rate"] = l2   # per kernel, from the stored TCC counter pass
-    # Gram-Schmidt and basis GEMVs: algorithmic HBM bytes of the counted launches. Step j
-    # (0..k_done) of a solve reads q and w_1..w_j, writes w_{j+1} and its copy; the DP
-    # residual of step j reads j (BA: Z, plus rb0) or j+1 (AB: W) vectors of m and writes
-    # one; forming the iterate reads k_done basis vectors. Counted launches are those of
-    # steps up to each solve's last (k_done).
-    sv = {"f64": 8, "f32": 4, "bf16": 2}[args.basis]
-    mgs_bytes = comb_bytes = 0
-    red = 0
-    for m in methods:
-        L = w.m if m == "ab" else w.n
-        kd = last[m].k_done
-        for j in range(kd + 1):
-            mgs_bytes += j * L * sv + L * sv + 2 * L * 4
-            red += j + 1
-        for j in range(1, kd + 1):
-            comb_bytes += ((j + 1) * w.m * 4 + w.m * 4) if m == "ba" else ((j + 1) * w.m * sv + w.m * 4)
-        # forming the returned iterate: x = W y (BA) or t = W y (AB, before B)
-        comb_bytes += kd * L * sv + L * 4
-    extra["mgs"] = _stream_kernel_stats(mgs_ms, mgs_n, mgs_bytes * args.steps, red * args.steps)
-    comb_n, comb_ms = prof["combine"]
-    extra["combine"] = _stream_kernel_stats(comb_ms, comb_n, comb_bytes * args.steps)
+    if fwd_n:
+        extra["A_tflops"] = round(work["forward"][0] / (fwd_avg * 1e-3) / 1e12, 3)
+    if bck_n:
+        extra["B_tflops"] = round(work["back"][0] / (bck_avg * 1e-3) / 1e12, 3)
+    if prof["ncp"][0]:
+        extra["ncp_avg_ms"] = round(prof["ncp"][1] / prof["ncp"][0], 4)
+    mgs_b, comb_b, red = krylov_bytes(methods, w, last, sv, sx)
+    extra["mgs"] = _stream_kernel_stats(prof["mgs"][1], prof["mgs"][0], mgs_b * steps, red * steps)
+    extra["combine"] = _stream_kernel_stats(prof["combine"][1], prof["combine"][0], comb_b * steps)
 
-    if not args.no_fp64:
-        b64bufs = {m: make(m, b64, "f64") for m in methods}
-        step(b64, "f64", b64bufs)
-        torch.cuda.synchronize()
-        t2 = time.perf_counter()
-        n64, r64 = step(b64, "f64", b64bufs)
-        torch.cuda.synchronize()
-        t3 = time.perf_counter()
-        extra["fp64_plain_iters_per_s"] = round(n64 / (t3 - t2), 2)
-        extra["fp64_plain_k_stop"] = {m: r64[m].k_stop for m in methods}
-        extra["f32_vs_f64_iterate_rel"] = {
-            m: float(torch.linalg.vector_norm(last[m].x.double() - r64[m].x) /
-                     torch.linalg.vector_norm(r64[m].x)) for m in methods}
+    if big:
+        x_orc, meta = oracle_iterate(3)
+        if meta is not None:
+            sol = meta["solves"]["ba-hat"]
+            extra["oracle"] = {"k_stop": sol["k_stop"], "ncp": sol["ncp"],
+                               "stored": "tests/golden/oracle_config3_x.npy (x_kNCP, FP32-rounded)"}
+        if x_orc is not None:
+            extra["rel_error_vs_oracle"] = round(_rel(last["ba"].x.double().cpu().numpy(), x_orc), 9)
+        extra["ncp_hist"] = [round(float(v), 6) for v in last["ba"].ncp_hist]
+        extra["rel_error_vs_phantom"] = round(_rel(last["ba"].x.double().cpu().numpy(), xb), 5)
+        if not args.quick:
+            variants = {}
+            for p_, b_ in (("f32", "f32"), ("f32", "bf16")):
+                if (p_, b_) == (proj, basis):
+                    continue
+                progress(f"variant proj {p_} basis {b_}")
+                vr = SingleRun(abg, torch, gg, w, methods, bt[p_], b_, stop, tau, enorm).run(
+                    max(steps // 3, 3), 2, instrument=False)
+                xv = vr["last"]["ba"].x.double().cpu().numpy()
+                d = {"iters_per_s": round(vr["iters_per_s"], 2),
+                     "ms_per_solve": round(vr["ms_per_step"], 2),
+                     "k_stop": vr["last"]["ba"].k_stop, "k_done": vr["last"]["ba"].k_done,
+                     "rel_error_vs_fp64_gpu": round(_rel(xv, last["ba"].x.double().cpu().numpy()), 7)}
+                if x_orc is not None:
+                    d["rel_error_vs_oracle"] = round(_rel(xv, x_orc), 7)
+                variants[f"proj_{p_}_basis_{b_}"] = d
+                torch.cuda.empty_cache()
+            extra["variants"] = variants
+    gg.release_workspace()
 
-    if args.config == 2 and not args.no_concurrent:
-        extra["concurrent_ab_ba"] = bench_concurrent_pair(abg, torch, dev, gg, w, b32, enorm,
-                                                          args.basis, args.steps)
-    if not args.no_models:
-        extra["models"] = bench_models(abg, torch, dev, w, xb)
-        progress("models done")
-        extra["few_view"] = bench_few_view(abg, torch, dev)
-        extra["histories"] = bench_histories(abg, torch, dev, w, xb)
-        progress("few-view and histories done")
-        extra["lsq"] = bench_lsq(abg, torch, dev, w, xb, b32, enorm)
+    if not args.quick and args.config != 1:
+        extra["workload_512"] = bench_512(args, abg, torch, dev)
 
     tiles = None
-    if not args.no_batch:
+    if not args.quick and not args.no_batch:
         progress("batched mix")
         extra["batched"] = bench_batched(abg, torch, dev)
         progress("batched mix done")
         tiles = (extra["batched"]["tiles"]["rays"], extra["batched"]["tiles"]["ang_block"],
                  extra["batched"]["tiles"]["sched"])
-    if args.serve_seconds > 0:
+    if not args.quick and args.serve_seconds > 0:
         extra["serving"] = bench_serving(abg, torch, dev, args.serve_seconds,
                                          [b for b in args.serve_basis.split(",") if b], tiles)
 
     cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_oracle_baseline(w, b_np, enorm)
+    if not args.quick and not args.no_cpu_baseline:
+        progress("CPU oracle baseline")
+        if big:
+            cpu = cpu_oracle_baseline_ncp(w, b_np, xb, args.cpu_arnoldi_steps)
+        else:
+            cpu = cpu_oracle_baseline(w, b_np, enorm)
+        progress("CPU oracle baseline done")
 
-    out = {
-        "metric": "GMRES iters/s", "value": round(value, 2), "unit": "iters/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+    stop_desc = {"dp": f"DP stop (tau={tau})", "ncp": "NCP stop"}[stop]
+    return {
+        "metric": "GMRES iters/s", "value": round(value, 3), "unit": "iters/s",
+        "n_gpus": 1, "steps": steps, "warmup": warmup,
+        "ms_per_step": round(r["ms_per_step"], 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": proj if basis == proj else f"{proj}+{basis} basis",
+        "data": "synthetic",
         "config": {"workload": f"{w.N}x{w.N} image, {w.n_ang} angles in [0,{w.ang_range:g}), "
                                f"{w.n_det} bins, {w.n_ellipses}-ellipse phantom, "
                                f"{100 * w.eta:g}% noise; " + "+".join(m.upper() for m in methods) +
-                               f"-GMRES {stop.upper()} stop, k_max={k_max}, FP32 projectors, "
-                               f"{args.basis.upper()} basis, FP64 Hessenberg/Givens, unmatched pair",
+                               f"-GMRES, {stop_desc}, k_max={w.k_max}, {proj.upper()} projectors, "
+                               f"{basis.upper()} basis, FP64 Hessenberg/Givens, unmatched pair "
+                               "(line-model A, interpolating B)",
                    "global_batch": len(methods), "parallelism": "single GPU"},
         "roofline": roof,
         "cpu_baseline": cpu,
         "extra": extra,
     }
-    print(json.dumps(out), flush=True)
+
+
+def bench_512(args, abg, torch, dev):
+    """The 512^2 single-solve workload (AB- and BA-GMRES, DP tau = 1.02, k_max = 100):
+    FP32 projectors and basis timed as in the main region, the plain FP64 solves, the two
+    solves on two streams, and the strip / Joseph models, few-view, error histories and
+    LSQR / LSMR on the same geometry."""
+    w = W.CONFIG2
+    gg = abg.Geometry(w.N, w.n_ang, w.n_det, ang_range=w.ang_range)
+    xb = w.phantom()
+    bbar = gg.fp(torch.tensor(xb, dtype=torch.float64, device=dev)).cpu().numpy()
+    gg.release_workspace()
+    b_np, enorm = W.add_noise(bbar, w.eta, w.noise_dir())
+    b32 = torch.tensor(b_np, dtype=torch.float32, device=dev)
+    b64 = torch.tensor(b_np, dtype=torch.float64, device=dev)
+    progress("512^2 workload")
+    r32 = SingleRun(abg, torch, gg, w, ["ab", "ba"], b32, "f32", "dp", w.tau, enorm).run(50, 200)
+    r64 = SingleRun(abg, torch, gg, w, ["ab", "ba"], b64, "f64", "dp", w.tau, enorm).run(10, 5,
+                                                                                      instrument=False)
+    prof = r32["prof"]
+    out = {"workload": "512x512, 720 angles, 725 bins, 20 ellipses, 2% noise; AB+BA-GMRES, DP "
+                       "tau=1.02, k_max=100, unmatched pair",
+           "fp32_iters_per_s": round(r32["iters_per_s"], 2),
+           "fp32_ms_per_step": round(r32["ms_per_step"], 3),
+           "fp64_iters_per_s": round(r64["iters_per_s"], 2),
+           "k_stop_fp32": {m: r32["last"][m].k_stop for m in ("ab", "ba")},
+           "k_stop_fp64": {m: r64["last"][m].k_stop for m in ("ab", "ba")},
+           "kernel_ms_fp32": {k: [v[0], round(v[1], 3)] for k, v in prof.items()},
+           "roofline_fp32": roofline_of(prof, w, "f32", f"{w.N}x{w.N}_{w.n_ang}x{w.n_det}"),
+           "f32_vs_f64_iterate_rel": {
+               m: _rel(r32["last"][m].x.double().cpu().numpy(), r64["last"][m].x.cpu().numpy())
+               for m in ("ab", "ba")}}
+    x_orc, _ = oracle_iterate(2)
+    if x_orc is not None:
+        out["rel_error_vs_oracle"] = {
+            f"{m}_{dt}": round(_rel(rr["last"][m].x.double().cpu().numpy(), x_orc[f"{m}_hat"]), 9)
+            for m in ("ab", "ba") for dt, rr in (("fp32", r32), ("fp64", r64))}
+    if not args.no_concurrent:
+        out["concurrent_ab_ba"] = bench_concurrent_pair(abg, torch, dev, gg, w, b32, enorm, "f32", 50)
+    if not args.no_models:
+        out["models"] = bench_models(abg, torch, dev, w, xb)
+        progress("models done")
+        out["few_view"] = bench_few_view(abg, torch, dev)
+        out["histories"] = bench_histories(abg, torch, dev, w, xb)
+        progress("few-view and histories done")
+        out["lsq"] = bench_lsq(abg, torch, dev, w, xb, b32, enorm)
+    gg.release_workspace()
+    return out
 
 
 if __name__ == "__main__":

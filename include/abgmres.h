@@ -337,9 +337,19 @@ int abg_batch_solve(const abg_request *r, int n, abg_precision p, int rays, int 
  * read by abg_profile_read (or once 4096 launches are pending), so solves do not wait
  * for them. */
 int abg_profile_enable(int on);
-/* Reads and (if reset) clears the accumulated counts and milliseconds: index 0 forward
- * projector, 1 back projector, 2 Gram-Schmidt, 3 basis combination. */
-int abg_profile_read(long long counts[4], double ms[4], int reset);
+/* Reads and (if reset) clears the accumulated counts and milliseconds (arrays of
+ * ABG_PROF_KINDS entries, caller-owned): index 0 forward projector, 1 back projector,
+ * 2 Gram-Schmidt, 3 basis combination, 4 NCP evaluation (its three kernels). */
+#define ABG_PROF_KINDS 5
+int abg_profile_read(long long counts[ABG_PROF_KINDS], double ms[ABG_PROF_KINDS], int reset);
+
+/* Releases what the library holds process-wide beyond geometries and engines: the
+ * profiling events (profiling is switched off; accumulated counts are kept) and the idle
+ * pooled pinned scalar slots and events of single solves (a solve leases one set for its
+ * duration). Call it with no library call in flight on any thread, before the HIP
+ * runtime shuts down (e.g. at the end of a program), so that nothing is left to static
+ * destructors at process exit; later calls re-create what they need. Returns ABG_OK. */
+int abg_release_process_resources(void);
 
 /* Single solves whose basis vectors are longer than 2^21 elements carry an FP64 scratch
  * vector and switch to a streaming Gram-Schmidt variant (q_k in that scratch, one pass per

@@ -26,16 +26,18 @@ def krylov_basis(M, v0: np.ndarray, k: int) -> np.ndarray:
     return Q
 
 
-def min_residual_iterate(method: str, A, B, b: np.ndarray, k: int) -> np.ndarray:
-    """x_k of AB-/BA-GMRES from x_0 = 0 by direct minimisation over K_k(BA, B b)."""
-    Q = krylov_basis(lambda v: B(A(v)), B(b), k)
+def min_residual_iterate(method: str, A, B, b: np.ndarray, k: int, x0=None) -> np.ndarray:
+    """x_k of AB-/BA-GMRES by direct minimisation over x_0 + K_k(BA, B r_0), r_0 = b - A x_0
+    (x_0 = 0 if not given): AB minimises ||b - A x||, BA ||B(b - A x)|| (Sec. 2)."""
+    r0 = b if x0 is None else b - A(x0)
+    Q = krylov_basis(lambda v: B(A(v)), B(r0), k)
     AQ = np.stack([A(Q[:, j]) for j in range(k)], axis=1)
     if method == "ab":
-        c = np.linalg.lstsq(AQ, b, rcond=None)[0]
+        c = np.linalg.lstsq(AQ, r0, rcond=None)[0]
     else:
         BAQ = np.stack([B(AQ[:, j]) for j in range(k)], axis=1)
-        c = np.linalg.lstsq(BAQ, B(b), rcond=None)[0]
-    return Q @ c
+        c = np.linalg.lstsq(BAQ, B(r0), rcond=None)[0]
+    return Q @ c if x0 is None else x0 + Q @ c
 
 
 def _golub_kahan(A, AT, b, k):

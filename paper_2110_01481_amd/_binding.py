@@ -5,8 +5,11 @@ in the library's kernels. The module fails loudly when the library is missing.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import sys
+import weakref
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -35,7 +38,7 @@ EXPORTS = ["abg_create_geometry", "abg_destroy_geometry", "abg_geometry_sizes",
            "abg_engine_get_tiles", "abg_engine_autotune", "abg_batch_solve",
            "abg_mgs_force_stream", "abg_geometry_set_model", "abg_geometry_get_model",
            "abg_geometry_set_strip_threshold", "abg_lsq_workspace_bytes", "abg_lsqr", "abg_lsmr",
-           "abg_gmres_error_history"]
+           "abg_gmres_error_history", "abg_release_process_resources"]
 
 
 class AbgError(RuntimeError):
@@ -72,6 +75,29 @@ class Request(ctypes.Structure):
 
 
 _lib = None
+# geometries and engines alive in this process: shutdown() releases them in order
+_live: "weakref.WeakSet" = weakref.WeakSet()
+_shut = False
+
+
+def shutdown():
+    """Releases every live engine and geometry, then the library's process-wide resources
+    (abg_release_process_resources), while the HIP runtime is still up. Registered with
+    atexit when the library is loaded; bench.py and the test session also call it at
+    their end. Objects released here are closed; the library stays usable."""
+    global _shut
+    if _lib is None:
+        return
+    for o in sorted(list(_live), key=lambda o: 0 if isinstance(o, Engine) else 1):
+        o.close()
+    _lib.abg_release_process_resources()
+    _shut = True
+
+
+def _finalizing() -> bool:
+    # during interpreter shutdown the HIP runtime may already be gone: objects collected
+    # then leave their memory to the process exit instead of calling into the library
+    return sys.is_finalizing()
 
 
 def load_library(path: str | None = None):
@@ -126,7 +152,9 @@ def load_library(path: str | None = None):
                       _dp, vp]
     lib.abg_gmres_error_history.argtypes = [vp, i, i, i, Stop, Precision, vp, vp, vp, sz, i, _dp,
                                             vp]
+    lib.abg_release_process_resources.argtypes = []
     _lib = lib
+    atexit.register(shutdown)
     return lib
 
 
@@ -181,6 +209,7 @@ class Geometry:
                                        int(n_det), float(det_spacing), ctypes.byref(h)),
                "abg_create_geometry")
         self._h = h
+        _live.add(self)
         self.N, self.n_ang, self.n_det = int(N), int(n_ang), int(n_det)
         self.n = self.N * self.N
         self.m = self.n_ang * self.n_det
@@ -205,10 +234,13 @@ class Geometry:
 
     def close(self):
         if getattr(self, "_h", None):
+            self._fp_ws.clear()
             load_library().abg_destroy_geometry(self._h)
             self._h = None
 
     def __del__(self):
+        if _finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -418,15 +450,19 @@ def mgs_force_stream(on: bool = True):
     load_library().abg_mgs_force_stream(1 if on else 0)
 
 
+# the launch classes abg_profile_read reports, in its order (ABG_PROF_KINDS of them)
+PROF_KINDS = ["forward", "back", "mgs", "combine", "ncp"]
+
+
 def profile_enable(on: bool = True):
     load_library().abg_profile_enable(1 if on else 0)
 
 
 def profile_read(reset: bool = True):
-    counts = (ctypes.c_longlong * 4)()
-    ms = (ctypes.c_double * 4)()
+    counts = (ctypes.c_longlong * len(PROF_KINDS))()
+    ms = (ctypes.c_double * len(PROF_KINDS))()
     load_library().abg_profile_read(counts, ms, 1 if reset else 0)
-    names = ["forward", "back", "mgs", "combine"]
+    names = PROF_KINDS
     return {nm: (int(counts[i]), float(ms[i])) for i, nm in enumerate(names)}
 
 
@@ -494,6 +530,7 @@ class Engine:
         _check(self.lib.abg_engine_create(self.prec, int(max_slots), _stream_ptr(stream),
                                           ctypes.byref(h)), "abg_engine_create")
         self._h = h
+        _live.add(self)
         self.max_slots = int(max_slots)
         self._pending: dict[int, _Pending] = {}
         self._next_tag = 1
@@ -505,6 +542,8 @@ class Engine:
             self._pending.clear()
 
     def __del__(self):
+        if _finalizing():
+            return
         try:
             self.close()
         except Exception:

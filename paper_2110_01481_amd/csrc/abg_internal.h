@@ -288,7 +288,9 @@ int engine_precision(const Engine *e, abg_precision *p);
 long long engine_rounds(const Engine *e);
 
 // ---- profiling (capi.cpp) -----------------------------------------------------------
-enum ProfKind { kProfFwd = 0, kProfBack = 1, kProfMgs = 2, kProfCombine = 3 };
+// Frees the idle pooled pinned scalar slots and step events of single solves.
+int host_release_all();
+enum ProfKind { kProfFwd = 0, kProfBack = 1, kProfMgs = 2, kProfCombine = 3, kProfNcp = 4, kProfKinds = 5 };
 bool profiling_on();
 // Brackets one launch with timing events when profiling is on. `step` tags launches
 // that belong to an Arnoldi step of the solve running on this thread; launches of

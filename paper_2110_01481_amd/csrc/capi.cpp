@@ -14,8 +14,8 @@ namespace {
 
 std::mutex g_prof_mu;
 bool g_prof_on = false;
-long long g_prof_count[4] = {0, 0, 0, 0};
-double g_prof_ms[4] = {0, 0, 0, 0};
+long long g_prof_count[kProfKinds] = {};
+double g_prof_ms[kProfKinds] = {};
 struct Pending {
     int kind;
     hipEvent_t e0, e1;
@@ -637,11 +637,25 @@ int abg_profile_enable(int on)
     return ABG_OK;
 }
 
-int abg_profile_read(long long counts[4], double ms[4], int reset)
+int abg_release_process_resources(void)
 {
+    {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        flush_locked();
+        g_prof_on = false;
+        for (hipEvent_t e : g_event_pool) (void)hipEventDestroy(e);
+        g_event_pool.clear();
+        g_event_pool.shrink_to_fit();
+    }
+    return host_release_all();
+}
+
+int abg_profile_read(long long counts[ABG_PROF_KINDS], double ms[ABG_PROF_KINDS], int reset)
+{
+    static_assert(ABG_PROF_KINDS == kProfKinds, "profile kinds");
     profile_flush();
     std::lock_guard<std::mutex> lk(g_prof_mu);
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < kProfKinds; ++i) {
         if (counts) counts[i] = g_prof_count[i];
         if (ms) ms[i] = g_prof_ms[i];
         if (reset) {

@@ -164,6 +164,8 @@ hipError_t launch_ncp(const Geometry &g, int t, const void *r, double *scratch, 
     if (q < 1) return hipErrorInvalidValue;
     double *crow = scratch;
     double *part = scratch + align256((size_t)g.n_ang * q * sizeof(double)) / sizeof(double);
+    // timed from before the row kernel to after the final one when profiling is on
+    ProfScope ps(kProfNcp, s, st ? k : 0, false);
     hipError_t e = t == ABG_F64 ? rows_dispatch<double>(g, r, crow, q, st, k, s)
                                 : rows_dispatch<float>(g, r, crow, q, st, k, s);
     if (e != hipSuccess) return e;

@@ -16,6 +16,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
+#include <vector>
 
 #include "abg_internal.h"
 
@@ -82,9 +84,10 @@ Layout make_layout(const Geometry &g, int method, int k_max, abg_precision p, ab
 
 constexpr int kRing = 4;
 
-// Pinned scalar slots and step events, cached per host thread (allocating pinned memory
-// and events on every call costs more than a short solve). They are kept until the
-// process ends.
+// Pinned scalar slots and step events of a solve. They are pooled process-wide
+// (allocating pinned memory and events on every call costs more than a short solve): a
+// solve leases one set for its duration and returns it when it ends; host_release_all
+// frees the idle sets (abg_release_process_resources).
 struct HostRes {
     DevState *slots = nullptr;
     DevState *dslots = nullptr;   // the same slots as the device addresses them
@@ -93,38 +96,100 @@ struct HostRes {
     hipEvent_t ev[kRing] = {};
 };
 
-hipError_t host_resources(HostRes &h, int k_max)
+std::mutex g_host_mu;
+std::vector<HostRes> g_host_idle;
+
+void host_free(HostRes &h)
 {
-    thread_local HostRes cache;
-    int dev = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess) return e;
-    if (cache.device != dev) {
-        for (auto &ev : cache.ev) ev = nullptr;   // events of another device are left alone
-        for (auto &ev : cache.ev) {
-            e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
-            if (e != hipSuccess) return e;
-        }
-        cache.slots = nullptr;
-        cache.capacity = 0;
-        cache.device = dev;
-    }
-    if (cache.capacity < k_max + 1) {
-        if (cache.slots) (void)hipHostFree(cache.slots);
-        cache.slots = nullptr;
-        e = hipHostMalloc((void **)&cache.slots, sizeof(DevState) * (k_max + 1), hipHostMallocDefault);
-        if (e == hipSuccess) e = hipHostGetDevicePointer((void **)&cache.dslots, cache.slots, 0);
-        if (e != hipSuccess) {
-            if (cache.slots) (void)hipHostFree(cache.slots);
-            cache.slots = cache.dslots = nullptr;
-            cache.capacity = 0;
-            return e;
-        }
-        cache.capacity = k_max + 1;
-    }
-    h = cache;
-    return hipSuccess;
+    if (h.slots) (void)hipHostFree(h.slots);
+    for (auto &ev : h.ev)
+        if (ev) (void)hipEventDestroy(ev);
+    h = HostRes{};
 }
+
+}  // namespace
+
+int host_release_all()
+{
+    std::lock_guard<std::mutex> lk(g_host_mu);
+    int prev = -1;
+    (void)hipGetDevice(&prev);
+    for (auto &h : g_host_idle) {
+        // events and pinned memory are released with their device current
+        if (h.device >= 0) (void)hipSetDevice(h.device);
+        host_free(h);
+    }
+    g_host_idle.clear();
+    if (prev >= 0) (void)hipSetDevice(prev);
+    return ABG_OK;
+}
+
+namespace {
+
+struct HostLease {
+    HostRes r;
+    hipStream_t s = nullptr;
+    bool held = false;
+
+    // an idle set of the current device (the smallest that holds k_max + 1 slots, else
+    // any, grown), or a new one
+    hipError_t acquire(int k_max, hipStream_t s_)
+    {
+        s = s_;
+        int dev = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e != hipSuccess) return e;
+        {
+            std::lock_guard<std::mutex> lk(g_host_mu);
+            int pick = -1;
+            for (int i = 0; i < (int)g_host_idle.size(); ++i) {
+                const HostRes &h = g_host_idle[i];
+                if (h.device != dev) continue;
+                if (pick < 0) pick = i;
+                const int cp = g_host_idle[pick].capacity;
+                const bool fits = h.capacity >= k_max + 1, pfits = cp >= k_max + 1;
+                if ((fits && (!pfits || h.capacity < cp)) || (!fits && !pfits && h.capacity > cp))
+                    pick = i;
+            }
+            if (pick >= 0) {
+                r = g_host_idle[pick];
+                g_host_idle.erase(g_host_idle.begin() + pick);
+            }
+        }
+        held = true;
+        if (r.device != dev) {
+            r.device = dev;
+            for (auto &ev : r.ev) {
+                e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+                if (e != hipSuccess) return e;
+            }
+        }
+        if (r.capacity < k_max + 1) {
+            if (r.slots) (void)hipHostFree(r.slots);
+            r.slots = r.dslots = nullptr;
+            r.capacity = 0;
+            e = hipHostMalloc((void **)&r.slots, sizeof(DevState) * (k_max + 1), hipHostMallocDefault);
+            if (e == hipSuccess) e = hipHostGetDevicePointer((void **)&r.dslots, r.slots, 0);
+            if (e != hipSuccess) return e;
+            r.capacity = k_max + 1;
+        }
+        return hipSuccess;
+    }
+
+    // Back to the pool once the stream is idle (an error return may leave the solve's
+    // kernels in flight, and they write these slots).
+    ~HostLease()
+    {
+        if (!held) return;
+        (void)hipStreamSynchronize(s);
+        if (r.slots && r.dslots && r.ev[kRing - 1]) {
+            std::lock_guard<std::mutex> lk(g_host_mu);
+            g_host_idle.push_back(r);
+        } else {
+            host_free(r);
+        }
+    }
+};
 
 #define CK(expr)                                   \
     do {                                           \
@@ -151,7 +216,8 @@ struct Solve {
     unsigned *count, *tick;
     DevState *dst;
     double *ncp;
-    HostRes hr;
+    HostLease lease;
+    HostRes &hr = lease.r;
     size_t sX;
     bool need_res;
     double bd_rel;
@@ -431,7 +497,7 @@ int run_solver(const Geometry &g, int method, int kind, const void *b, const voi
 {
     Solve S(g, method, kind, k_max, st, p, s, ws);
     if (ws_bytes < S.ly.total) return ABG_ENOMEM;
-    CK(host_resources(S.hr, k_max));
+    CK(S.lease.acquire(k_max, s));
     // launches of steps enqueued past the stop are left out of the launch timing
     struct ProfSolve {
         int last = 0;
@@ -585,7 +651,7 @@ int gmres_error_history(const Geometry &g, int method, int kind, int k_max, abg_
     Solve S(g, method, kind, k_max, st, p, s, ws);
     if (ws_bytes < S.ly.total) return ABG_ENOMEM;
     if (k_done < 0 || k_done > k_max) return ABG_EINVAL;
-    CK(host_resources(S.hr, k_max));
+    CK(S.lease.acquire(k_max, s));
     // the workspace must hold k_done completed steps (their small-problem solutions)
     DevState h;
     RC(S.sync_read(h));
@@ -677,8 +743,9 @@ int run_lsq(const Geometry &g, int method, const void *b, const void *x0, void *
     const int bkind = g.model == ABG_FP_STRIP    ? ABG_BP_STRIP_T
                       : g.model == ABG_FP_JOSEPH ? ABG_BP_JOSEPH_T
                                                  : ABG_BP_ADJ;
-    HostRes hr;
-    CK(host_resources(hr, k_max));
+    HostLease lease;
+    CK(lease.acquire(k_max, s));
+    HostRes &hr = lease.r;
     struct ProfSolve {
         int last = 0;
         bool done = false;

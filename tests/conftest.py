@@ -21,3 +21,11 @@ def gpu_lib():
     import paper_2110_01481_amd as abg
     abg.load_library()
     return abg
+
+
+def pytest_sessionfinish(session, exitstatus):
+    """Releases the library's engines, geometries and process-wide resources while the
+    HIP runtime is still up (only if a test loaded the library)."""
+    mod = sys.modules.get("paper_2110_01481_amd._binding")
+    if mod is not None and mod._lib is not None:
+        mod.shutdown()

@@ -39,6 +39,27 @@ def test_iterates_minimise_over_krylov_space(cfg1, method, kind):
 
 
 @pytest.mark.parametrize("method", ["ab", "ba"])
+@pytest.mark.parametrize("kind", ["hat", "adj"])
+def test_iterates_from_nonzero_x0_are_krylov_minimisers(cfg1, method, kind):
+    """Sec. 2 with a starting guess: x_k lies in x_0 + K_k(BA, B r_0), r_0 = b - A x_0, and
+    minimises ||b - A x|| (AB) or ||B(b - A x)|| (BA) there. The minimiser is recomputed
+    from a QR of the power sequence; the starting guess is a seeded smooth image, and the
+    iterates differ from those of x_0 = 0 (the start matters)."""
+    g, xb, b, _ = cfg1
+    f = O.ab_gmres if method == "ab" else O.ba_gmres
+    x0 = 0.5 * xb + 0.05 * np.random.default_rng(31).uniform(size=g.n)
+    r = f(g.A, g.back(kind), b, 6, x0=x0, keep_iterates=True)
+    r0 = f(g.A, g.back(kind), b, 6, keep_iterates=True)
+    for k in range(1, 7):
+        xr = O.min_residual_iterate(method, g.A, g.back(kind), b, k, x0=x0)
+        assert np.linalg.norm(xr - r.iterates[k - 1]) <= 1e-9 * np.linalg.norm(xr), k
+        assert np.linalg.norm(r0.iterates[k - 1] - r.iterates[k - 1]) > 1e-3 * np.linalg.norm(xr)
+    # the same minimiser with x_0 = 0 reproduces the zero-start run
+    assert np.allclose(O.min_residual_iterate(method, g.A, g.back(kind), b, 4, x0=np.zeros(g.n)),
+                       r0.iterates[3], rtol=0, atol=1e-9 * np.linalg.norm(r0.iterates[3]))
+
+
+@pytest.mark.parametrize("method", ["ab", "ba"])
 def test_matched_case_equals_lsqr_lsmr_full_reorth(cfg1, method):
     """Sec. 5: with B = A^T, AB-GMRES equals LSQR and BA-GMRES equals LSMR; in finite
     precision they agree with the full-reorthogonalisation variants."""
