@@ -343,6 +343,14 @@ int abg_profile_enable(int on);
 #define ABG_PROF_KINDS 5
 int abg_profile_read(long long counts[ABG_PROF_KINDS], double ms[ABG_PROF_KINDS], int reset);
 
+/* NCP periodograms (Sec. 6.3) take the DFT of every sinogram row by Bluestein's chirp
+ * transform (two power-of-two FFTs in LDS; rows of 64 to 4096 bins), with tables of
+ * at most 256 KB that the first NCP solve on a geometry builds on the host and keeps in
+ * device memory until the geometry is destroyed; other row lengths use Goertzel's
+ * recurrence per frequency. With on != 0 every row length uses the recurrence
+ * (process-wide; for tests and measurements). Returns ABG_OK. */
+int abg_ncp_force_goertzel(int on);
+
 /* Releases what the library holds process-wide beyond geometries and engines: the
  * profiling events (profiling is switched off; accumulated counts are kept) and the idle
  * pooled pinned scalar slots and events of single solves (a solve leases one set for its

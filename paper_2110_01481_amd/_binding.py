@@ -38,7 +38,7 @@ EXPORTS = ["abg_create_geometry", "abg_destroy_geometry", "abg_geometry_sizes",
            "abg_engine_get_tiles", "abg_engine_autotune", "abg_batch_solve",
            "abg_mgs_force_stream", "abg_geometry_set_model", "abg_geometry_get_model",
            "abg_geometry_set_strip_threshold", "abg_lsq_workspace_bytes", "abg_lsqr", "abg_lsmr",
-           "abg_gmres_error_history", "abg_release_process_resources"]
+           "abg_gmres_error_history", "abg_release_process_resources", "abg_ncp_force_goertzel"]
 
 
 class AbgError(RuntimeError):
@@ -78,6 +78,9 @@ _lib = None
 # geometries and engines alive in this process: shutdown() releases them in order
 _live: "weakref.WeakSet" = weakref.WeakSet()
 _shut = False
+# Objects collected during interpreter shutdown (when the HIP runtime may already be gone)
+# leave their memory to the process exit instead of calling into the library: __del__
+# binds sys.is_finalizing as a default argument, since module globals may be cleared by then.
 
 
 def shutdown():
@@ -92,12 +95,6 @@ def shutdown():
         o.close()
     _lib.abg_release_process_resources()
     _shut = True
-
-
-def _finalizing() -> bool:
-    # during interpreter shutdown the HIP runtime may already be gone: objects collected
-    # then leave their memory to the process exit instead of calling into the library
-    return sys.is_finalizing()
 
 
 def load_library(path: str | None = None):
@@ -141,6 +138,7 @@ def load_library(path: str | None = None):
                                         ctypes.POINTER(i), _dp]
     lib.abg_batch_solve.argtypes = [ctypes.POINTER(Request), i, Precision, i, i, i, vp]
     lib.abg_mgs_force_stream.argtypes = [i]
+    lib.abg_ncp_force_goertzel.argtypes = [i]
     lib.abg_geometry_set_model.argtypes = [vp, i]
     lib.abg_geometry_get_model.argtypes = [vp, ctypes.POINTER(i)]
     lib.abg_geometry_set_strip_threshold.argtypes = [vp, ctypes.c_double, _dp]
@@ -238,7 +236,7 @@ class Geometry:
             load_library().abg_destroy_geometry(self._h)
             self._h = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         if _finalizing():
             return
         try:
@@ -450,6 +448,11 @@ def mgs_force_stream(on: bool = True):
     load_library().abg_mgs_force_stream(1 if on else 0)
 
 
+def ncp_force_goertzel(on: bool = True):
+    """NCP periodograms by Goertzel's recurrence for every row length (abg_ncp_force_goertzel)."""
+    load_library().abg_ncp_force_goertzel(1 if on else 0)
+
+
 # the launch classes abg_profile_read reports, in its order (ABG_PROF_KINDS of them)
 PROF_KINDS = ["forward", "back", "mgs", "combine", "ncp"]
 
@@ -541,7 +544,7 @@ class Engine:
             self._h = None
             self._pending.clear()
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         if _finalizing():
             return
         try:

@@ -9,6 +9,7 @@
 
 #include "../../include/abgmres.h"
 #include "geometry.h"
+#include "group_budget.h"
 
 namespace abg {
 
@@ -197,6 +198,10 @@ hipError_t launch_axpy_inplace(int t, void *x, const void *x0, long long L, hipS
 
 // ---- NCP (ncp.hip) ------------------------------------------------------------------
 size_t ncp_scratch_bytes(const Geometry &g);
+// Frees the geometry's periodogram tables (abg_destroy_geometry).
+void ncp_release(Geometry &g);
+// Process-wide: periodograms by Goertzel's recurrence for every row length (tests).
+void ncp_force_goertzel(int on);
 // d_k of the residual r into st->ncp; raises the NCP stop for step k when k >= 2 and
 // d_k > d_{k-1}. `snap`: as for launch_combine.
 hipError_t launch_ncp(const Geometry &g, int t, const void *r, double *scratch, DevState *st,
@@ -287,9 +292,17 @@ hipStream_t engine_stream(const Engine *e);
 int engine_precision(const Engine *e, abg_precision *p);
 long long engine_rounds(const Engine *e);
 
-// ---- profiling (capi.cpp) -----------------------------------------------------------
-// Frees the idle pooled pinned scalar slots and step events of single solves.
+// Admission of spinning Gram-Schmidt block groups (krylov.hip): the current device's
+// budget, and the units a single solve's Gram-Schmidt launches hold for vectors of L
+// elements (tx, tv: projector and basis dtypes; q64: the FP64 scratch of the streaming
+// variant exists).
+GroupBudget &device_group_budget();
+hipError_t mgs_group_units(int tx, int tv, long long L, bool q64, long long *units);
+
+// Frees the idle pooled pinned scalar slots and step events of single solves (solver.hip).
 int host_release_all();
+
+// ---- profiling (capi.cpp) -----------------------------------------------------------
 enum ProfKind { kProfFwd = 0, kProfBack = 1, kProfMgs = 2, kProfCombine = 3, kProfNcp = 4, kProfKinds = 5 };
 bool profiling_on();
 // Brackets one launch with timing events when profiling is on. `step` tags launches

@@ -29,7 +29,8 @@
 #include <vector>
 
 #include "krylov_body.h"
-#include "proj_body.h"
+#include "back_body.h"
+#include "fwd_body.h"
 
 namespace abg {
 
@@ -477,12 +478,13 @@ __global__ __launch_bounds__(kBlock) void bres_kernel(const BatchInst *__restric
         ss = block_sum(ss, lds);
         if (threadIdx.x == 0) {
             agent_store(d.part + c, ss);
-            const unsigned prev = __hip_atomic_fetch_add(d.count, 1u, __ATOMIC_RELAXED,
+            const unsigned prev = __hip_atomic_fetch_add(d.count, 1u, __ATOMIC_ACQ_REL,
                                                          __HIP_MEMORY_SCOPE_AGENT);
             last = prev == (unsigned)d.n_chunks - 1;
         }
         __syncthreads();
         if (!last) return;
+        last_block_fence();
         double tsum = 0.0;
         for (int j = threadIdx.x; j < d.n_chunks; j += kBlock) tsum += agent_load(d.part + j);
         tsum = block_sum(tsum, lds);
@@ -567,6 +569,10 @@ constexpr int kSnapRing = 4;
         hipError_t e_ = (expr);                     \
         if (e_ != hipSuccess) return fail(ABG_EHIP); \
     } while (0)
+
+// Stream callback after an engine round: returns the round's share of the Gram-Schmidt
+// budget (touches only the budget object, no HIP call).
+void release_round(void *budget) { static_cast<GroupBudget *>(budget)->release(GroupBudget::kUnits); }
 
 }  // namespace
 
@@ -1031,7 +1037,17 @@ struct Engine {
                 int rc = capture();
                 if (rc) return rc;
             }
-            BCK(hipGraphLaunch(exec, s));
+            // the round's Gram-Schmidt grids take what the device holds: the whole
+            // budget, returned by a stream callback once the round has run
+            GroupBudget &budget = device_group_budget();
+            budget.acquire(GroupBudget::kUnits);
+            hipError_t e = hipGraphLaunch(exec, s);
+            if (e == hipSuccess) e = hipLaunchHostFunc(s, release_round, &budget);
+            if (e != hipSuccess) {
+                (void)hipStreamSynchronize(s);
+                budget.release(GroupBudget::kUnits);
+                return fail(ABG_EHIP);
+            }
             ++rounds;
         }
         const int r = ring_next;

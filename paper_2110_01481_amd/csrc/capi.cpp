@@ -234,6 +234,7 @@ int abg_destroy_geometry(abg_geometry *h)
     if (!h) return ABG_OK;
     int rc = ABG_OK;
     if (h->g.dev && hipFree(h->g.dev) != hipSuccess) rc = ABG_EHIP;
+    ncp_release(h->g);
     delete h;
     return rc;
 }
@@ -634,6 +635,12 @@ int abg_profile_enable(int on)
         if (hipEventCreate(&e) != hipSuccess) return ABG_EHIP;
         g_event_pool.push_back(e);
     }
+    return ABG_OK;
+}
+
+int abg_ncp_force_goertzel(int on)
+{
+    ncp_force_goertzel(on);
     return ABG_OK;
 }
 

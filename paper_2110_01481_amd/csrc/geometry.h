@@ -39,6 +39,8 @@ struct Geometry {
     std::vector<double> theta;
     std::vector<AngleParams> host;
     AngleParams *dev = nullptr;
+    // NCP periodogram tables (chirp transform of the row length), built on first use
+    mutable void *ncp_tab = nullptr;
     long long n() const { return (long long)N * N; }
     long long m() const { return (long long)n_ang * n_det; }
     int padded_stride() const { return N + 2 * kPad; }

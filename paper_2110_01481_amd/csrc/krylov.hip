@@ -13,6 +13,8 @@
 #include <algorithm>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <memory>
 #include <mutex>
 #include <unordered_map>
 
@@ -238,12 +240,13 @@ __global__ __launch_bounds__(kBlock) void combine_kernel(const TB *__restrict__ 
     ss = block_sum(ss, lds);
     if (threadIdx.x == 0) {
         agent_store(partials + blockIdx.x, ss);
-        const unsigned prev = __hip_atomic_fetch_add(count, 1u, __ATOMIC_RELAXED,
+        const unsigned prev = __hip_atomic_fetch_add(count, 1u, __ATOMIC_ACQ_REL,
                                                      __HIP_MEMORY_SCOPE_AGENT);
         last = prev == gridDim.x - 1;
     }
     __syncthreads();
     if (!last) return;
+    last_block_fence();
     double t = 0.0;
     for (int j = threadIdx.x; j < (int)gridDim.x; j += kBlock) t += agent_load(partials + j);
     t = block_sum(t, lds);
@@ -395,9 +398,80 @@ hipError_t combine_go(const void *base, double bcoef, const void *V, size_t ldv,
     return hipGetLastError();
 }
 
+// Share of the device (GroupBudget units) of the Gram-Schmidt launch mgs_dispatch makes
+// for vectors of length L: the same tile and group choice, then the group's blocks
+// against what the device holds of that kernel.
+template <typename TX, typename TV>
+hipError_t group_units_t(long long L, bool q64, long long *units)
+{
+    const int maxE = sizeof(TV) == 8 ? 32 : 64;
+    int E = 1;
+    if (L <= (long long)kBlock * maxE) {
+        while ((long long)kBlock * E < L) E *= 2;
+    } else {
+        while (E < maxE && (long long)g_target_blocks * kBlock * E < L) E *= 2;
+    }
+    long long G = (L + (long long)kBlock * E - 1) / ((long long)kBlock * E);
+    *units = 0;
+    if (G <= 1) return hipSuccess;
+    const void *fn = nullptr;
+    switch (E) {
+    case 1: fn = reinterpret_cast<const void *>(&mgs_kernel<TX, TV, 1>); break;
+    case 2: fn = reinterpret_cast<const void *>(&mgs_kernel<TX, TV, 2>); break;
+    case 4: fn = reinterpret_cast<const void *>(&mgs_kernel<TX, TV, 4>); break;
+    case 8: fn = reinterpret_cast<const void *>(&mgs_kernel<TX, TV, 8>); break;
+    case 16: fn = reinterpret_cast<const void *>(&mgs_kernel<TX, TV, 16>); break;
+    case 32: fn = reinterpret_cast<const void *>(&mgs_kernel<TX, TV, 32>); break;
+    default:
+        if constexpr (sizeof(TV) < 8) fn = reinterpret_cast<const void *>(&mgs_kernel<TX, TV, 64>);
+        break;
+    }
+    if (!fn) return hipErrorInvalidValue;
+    int cap = 0;
+    hipError_t e = resident_capacity(fn, &cap);
+    if (e != hipSuccess) return e;
+    if (G > cap || G > kMaxGrid || (g_force_stream && q64)) {
+        if (!q64) {
+            *units = GroupBudget::kUnits;
+            return hipSuccess;
+        }
+        int caps = 0;
+        e = resident_capacity(reinterpret_cast<const void *>(&mgs_stream_kernel<TX, TV>), &caps);
+        if (e != hipSuccess) return e;
+        *units = GroupBudget::units_for(std::min(kStreamBlocks, caps), caps);
+        return hipSuccess;
+    }
+    *units = GroupBudget::units_for(G, cap);
+    return hipSuccess;
+}
+
 }  // namespace
 
 void set_mgs_force_stream(int on) { g_force_stream = on ? 1 : 0; }
+
+hipError_t mgs_group_units(int tx, int tv, long long L, bool q64, long long *units)
+{
+    if (tx == ABG_F64) {
+        if (tv == ABG_F64) return group_units_t<double, double>(L, q64, units);
+        if (tv == ABG_F32) return group_units_t<double, float>(L, q64, units);
+        return group_units_t<double, bf16>(L, q64, units);
+    }
+    if (tv == ABG_F32) return group_units_t<float, float>(L, q64, units);
+    if (tv == ABG_BF16) return group_units_t<float, bf16>(L, q64, units);
+    return hipErrorInvalidValue;
+}
+
+GroupBudget &device_group_budget()
+{
+    static std::mutex mu;
+    static std::map<int, std::unique_ptr<GroupBudget>> budgets;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> lk(mu);
+    auto &b = budgets[dev];
+    if (!b) b.reset(new GroupBudget);
+    return *b;
+}
 
 void set_mgs_target_blocks(int blocks)
 {

@@ -100,13 +100,19 @@ __device__ inline double agent_load(const double *p)
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 // Publishes a partial sum at device scope and waits until the write has been performed
-// (the exchange's returned value is consumed), so that a later counter increment
-// cannot overtake it. Partials are read back only with device-scope atomic loads.
+// (the exchange's returned value is consumed). The counter increment after it is an
+// agent-scope acquire-release, which orders the store before it in the memory model as
+// well; partials are read back only with device-scope atomic loads, after an
+// agent-scope acquire fence in the block that read the last count (last_block_fence).
 __device__ inline void agent_store(double *p, double v)
 {
     const double old = __hip_atomic_exchange(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    asm volatile("" ::"v"(old));
+    asm volatile("" ::"v"(old) : "memory");
 }
+
+// In the last block of a counted reduction, after the barrier that shares the count:
+// every thread's later loads see what the other blocks wrote before their increments.
+__device__ inline void last_block_fence() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
 
 // ---- group reductions through value slots -----------------------------------------------
 // A block group reduces a scalar by writing one partial per block into a slot that holds

@@ -23,12 +23,13 @@ __device__ inline bool last_block_total(double v, double *partials, unsigned *co
     v = block_sum(v, lds);
     if (threadIdx.x == 0) {
         agent_store(partials + blockIdx.x, v);
-        const unsigned prev = __hip_atomic_fetch_add(count, 1u, __ATOMIC_RELAXED,
+        const unsigned prev = __hip_atomic_fetch_add(count, 1u, __ATOMIC_ACQ_REL,
                                                      __HIP_MEMORY_SCOPE_AGENT);
         *last = prev == gridDim.x - 1;
     }
     __syncthreads();
     if (!*last) return false;
+    last_block_fence();
     double t = 0.0;
     for (int j = threadIdx.x; j < (int)gridDim.x; j += kBlock) t += agent_load(partials + j);
     t = block_sum(t, lds);
@@ -172,12 +173,13 @@ __global__ __launch_bounds__(kBlock) void lsqr_x_kernel(T *__restrict__ x, T *__
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        const unsigned prev = __hip_atomic_fetch_add(count, 1u, __ATOMIC_RELAXED,
+        const unsigned prev = __hip_atomic_fetch_add(count, 1u, __ATOMIC_ACQ_REL,
                                                      __HIP_MEMORY_SCOPE_AGENT);
         last = prev == gridDim.x - 1;
     }
     __syncthreads();
     if (!last || threadIdx.x != 0) return;
+    last_block_fence();
     __hip_atomic_store(count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     S->rhobar = -c * an;
     S->phibar = sn * phibar;
@@ -246,12 +248,13 @@ __global__ __launch_bounds__(kBlock) void lsmr_x_kernel(T *__restrict__ x, T *__
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        const unsigned prev = __hip_atomic_fetch_add(count, 1u, __ATOMIC_RELAXED,
+        const unsigned prev = __hip_atomic_fetch_add(count, 1u, __ATOMIC_ACQ_REL,
                                                      __HIP_MEMORY_SCOPE_AGENT);
         last = prev == gridDim.x - 1;
     }
     __syncthreads();
     if (!last || threadIdx.x != 0) return;
+    last_block_fence();
     __hip_atomic_store(count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     S->alphabar = alphabar_n;
     S->zetabar = zetabar_n;
@@ -336,12 +339,13 @@ __global__ __launch_bounds__(kBlock) void lsq_start_kernel(T *__restrict__ v, T 
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        const unsigned prev = __hip_atomic_fetch_add(count, 1u, __ATOMIC_RELAXED,
+        const unsigned prev = __hip_atomic_fetch_add(count, 1u, __ATOMIC_ACQ_REL,
                                                      __HIP_MEMORY_SCOPE_AGENT);
         last = prev == gridDim.x - 1;
     }
     __syncthreads();
     if (!last || threadIdx.x != 0) return;
+    last_block_fence();
     __hip_atomic_store(count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     S->alpha = a1;
     S->beta = b1;

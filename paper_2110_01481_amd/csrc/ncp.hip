@@ -1,11 +1,27 @@
 // NCP stopping criterion (Sec. 6.3) on gfx950.
 //
 // For each sinogram row of the residual (one block per row): the periodogram
-// p_j = |DFT_j|^2, j = 1..q = floor(n_det/2), by Goertzel's second-order recurrence in
-// FP64 (one recurrence per frequency, no twiddle table; n_det may be prime), then the
-// normalised cumulative sum c(j) = sum_{l<=j} p_l / sum_{l<=q} p_l. A second kernel
-// averages c over the rows per j and forms the distance to the white-noise line j/q.
+// p_j = |DFT_j|^2, j = 1..q = floor(n_det/2), then the normalised cumulative sum
+// c(j) = sum_{l<=j} p_l / sum_{l<=q} p_l. Two more kernels average c over the rows per j
+// (column sums over chunks of rows, then the chunks in order) and form the distance to
+// the white-noise line j/q.
+//
+// The DFT of a row of any length n (2897 at the largest scan is prime) is taken with
+// Bluestein's chirp transform: with c_i = exp(-pi i i^2/n), 2ij = i^2 + j^2 - (j-i)^2
+// gives X_j = c_j sum_i (r_i c_i) conj(c_{j-i}), a linear convolution of length 2n-1,
+// done cyclically with two power-of-two FFTs of length M >= 2n-1 held in LDS (M <= 8192:
+// 128 KB of complex FP64). |c_j| = 1, so p_j = |convolution_j|^2 and the final chirp is
+// not needed; the 1/M of the inverse transform cancels in the normalisation. The
+// transform of the fixed chirp kernel conj(c_t), the chirp c_i and the twiddle factors
+// are computed once per geometry on the host (FP64) and kept on the device. Short rows
+// (n < 64) and rows too long for LDS use Goertzel's recurrence per frequency instead
+// (O(n) work per frequency, FP64).
+#include <algorithm>
+#include <atomic>
 #include <cmath>
+#include <complex>
+#include <mutex>
+#include <vector>
 
 #include "abg_internal.h"
 
@@ -77,8 +93,30 @@ __global__ __launch_bounds__(kBlock) void ncp_rows_kernel(const T *__restrict__ 
     }
 }
 
-__global__ __launch_bounds__(kBlock) void ncp_mean_kernel(const double *__restrict__ crow, int n_ang,
-                                                          int q, double *__restrict__ partials,
+// Column sums of crow over chunks of rows: block (jb, c) adds rows c*rows_per .. of
+// frequencies jb*kBlock + t into colsum[c][j] (many blocks, short loops: the rows of a
+// scan are read once, spread over the device).
+constexpr int kRowChunks = 32;
+
+__global__ __launch_bounds__(kBlock) void ncp_colsum_kernel(const double *__restrict__ crow,
+                                                            int n_ang, int q, int rows_per,
+                                                            double *__restrict__ colsum,
+                                                            const DevState *st, int k)
+{
+    if (halted(st, k)) return;
+    const int j = blockIdx.x * kBlock + threadIdx.x;
+    const int a0 = blockIdx.y * rows_per, a1 = min(n_ang, a0 + rows_per);
+    if (j >= q) return;
+    double s = 0.0;
+    for (int a = a0; a < a1; ++a) s += crow[(size_t)a * q + j];
+    colsum[(size_t)blockIdx.y * q + j] = s;
+}
+
+// (mean over rows - j/q)^2 per frequency, the chunks' sums added in chunk order; one
+// partial per block.
+__global__ __launch_bounds__(kBlock) void ncp_dist_kernel(const double *__restrict__ colsum,
+                                                          int n_chunks, int n_ang, int q,
+                                                          double *__restrict__ partials,
                                                           const DevState *st, int k)
 {
     __shared__ double lds[kBlock / 64];
@@ -87,7 +125,7 @@ __global__ __launch_bounds__(kBlock) void ncp_mean_kernel(const double *__restri
     double d2 = 0.0;
     if (j < q) {
         double s = 0.0;
-        for (int a = 0; a < n_ang; ++a) s += crow[(size_t)a * q + j];
+        for (int c = 0; c < n_chunks; ++c) s += colsum[(size_t)c * q + j];
         const double dev = s / (double)n_ang - (double)(j + 1) / (double)q;
         d2 = dev * dev;
     }
@@ -127,6 +165,109 @@ __global__ void ncp_final_kernel(const double *partials, int nb, DevState *st, i
     }
 }
 
+// ---- Bluestein rows: forward FFT (decimation in frequency: natural order in, bit-
+// reversed order out), product with the kernel's transform (stored bit-reversed), inverse
+// FFT (decimation in time: bit-reversed in, natural out) -- no permutation pass.
+constexpr int kFftThreads = 512;
+constexpr int kFftMaxM = 8192;
+
+template <typename T>
+__global__ __launch_bounds__(kFftThreads) void ncp_fft_rows_kernel(
+    const T *__restrict__ r, int n_det, int q, int M, const double2 *__restrict__ chirp,
+    const double2 *__restrict__ khat, const double2 *__restrict__ tw, double *__restrict__ crow,
+    const DevState *st, int k)
+{
+    extern __shared__ double2 z[];          // M values
+    __shared__ double wsum[kFftThreads / 64];
+    __shared__ double total_s;
+    if (halted(st, k)) return;
+    const int t = threadIdx.x;
+    const T *src = r + (size_t)blockIdx.x * n_det;
+    for (int i = t; i < M; i += kFftThreads) {
+        double2 v = make_double2(0.0, 0.0);
+        if (i < n_det) {
+            const double x = (double)src[i];
+            const double2 c = chirp[i];
+            v = make_double2(x * c.x, x * c.y);
+        }
+        z[i] = v;
+    }
+    __syncthreads();
+    const int half = M >> 1;
+    // butterfly b of a pass with span h joins i = 2(b - j) + j and i + h, j = b mod h;
+    // its twiddle exp(-2 pi i j / (2h)) is tw[h - 1 + j] (the pass's twiddles are
+    // contiguous: adjacent lanes read adjacent entries)
+    for (int h = half; h >= 1; h >>= 1) {
+        for (int b = t; b < half; b += kFftThreads) {
+            const int j = b & (h - 1);
+            const int i = ((b - j) << 1) + j;
+            const double2 u = z[i], v = z[i + h];
+            const double2 w = tw[h - 1 + j];
+            const double dx = u.x - v.x, dy = u.y - v.y;
+            z[i] = make_double2(u.x + v.x, u.y + v.y);
+            z[i + h] = make_double2(fma(dx, w.x, -dy * w.y), fma(dx, w.y, dy * w.x));
+        }
+        __syncthreads();
+    }
+    for (int i = t; i < M; i += kFftThreads) {
+        const double2 u = z[i], v = khat[i];
+        z[i] = make_double2(fma(u.x, v.x, -u.y * v.y), fma(u.x, v.y, u.y * v.x));
+    }
+    __syncthreads();
+    for (int h = 1; h < M; h <<= 1) {
+        for (int b = t; b < half; b += kFftThreads) {
+            const int j = b & (h - 1);
+            const int i = ((b - j) << 1) + j;
+            const double2 w = tw[h - 1 + j];
+            const double2 u = z[i], v = z[i + h];
+            // v times conj(w)
+            const double px = fma(v.x, w.x, v.y * w.y), py = fma(v.y, w.x, -v.x * w.y);
+            z[i] = make_double2(u.x + px, u.y + py);
+            z[i + h] = make_double2(u.x - px, u.y - py);
+        }
+        __syncthreads();
+    }
+    // thread t owns frequencies j = 1 + t*J .. (t+1)*J; fixed-order prefix over threads
+    const int J = (q + kFftThreads - 1) / kFftThreads;
+    double own = 0.0;
+    for (int u = 0; u < J; ++u) {
+        const int j = 1 + t * J + u;
+        if (j <= q) {
+            const double2 v = z[j];
+            own = fma(v.x, v.x, fma(v.y, v.y, own));
+        }
+    }
+    // inclusive scan within the wave, then wave totals in order
+    const int lane = t & 63, wv = t >> 6;
+    double inc = own;
+    for (int o = 1; o < 64; o <<= 1) {
+        const double n = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += n;
+    }
+    if (lane == 63) wsum[wv] = inc;
+    __syncthreads();
+    if (t == 0) {
+        double run = 0.0;
+        for (int w = 0; w < kFftThreads / 64; ++w) {
+            const double v = wsum[w];
+            wsum[w] = run;
+            run += v;
+        }
+        total_s = run;
+    }
+    __syncthreads();
+    const double total = total_s;
+    double acc = wsum[wv] + inc - own;
+    for (int u = 0; u < J; ++u) {
+        const int j = 1 + t * J + u;
+        if (j <= q) {
+            const double2 v = z[j];
+            acc = fma(v.x, v.x, fma(v.y, v.y, acc));
+            crow[(size_t)blockIdx.x * q + (j - 1)] = total > 0.0 ? acc / total : (double)j / (double)q;
+        }
+    }
+}
+
 template <typename T, int J>
 hipError_t rows_go(const Geometry &g, const void *r, double *crow, int q, const DevState *st,
                    int k, hipStream_t s)
@@ -148,13 +289,114 @@ hipError_t rows_dispatch(const Geometry &g, const void *r, double *crow, int q,
     return hipErrorInvalidValue;
 }
 
+int fft_length(int n_det)
+{
+    if (n_det < 64) return 0;
+    int M = 1;
+    while (M < 2 * n_det - 1) M <<= 1;
+    return M <= kFftMaxM ? M : 0;
+}
+
+// Host FFT (FP64, radix 2, decimation in time after a bit-reversal permutation) of the
+// chirp kernel; the same twiddles as the device.
+void host_fft(std::vector<std::complex<double>> &a, const std::vector<std::complex<double>> &tw)
+{
+    const int M = (int)a.size();
+    for (int i = 1, j = 0; i < M; ++i) {
+        int bit = M >> 1;
+        for (; j & bit; bit >>= 1) j ^= bit;
+        j ^= bit;
+        if (i < j) std::swap(a[i], a[j]);
+    }
+    for (int h = 1; h < M; h <<= 1)
+        for (int i0 = 0; i0 < M; i0 += 2 * h)
+            for (int j = 0; j < h; ++j) {
+                const std::complex<double> v = a[i0 + j + h] * tw[(size_t)j * (M / (2 * h))];
+                a[i0 + j + h] = a[i0 + j] - v;
+                a[i0 + j] += v;
+            }
+}
+
+std::mutex g_ncp_mu;
+std::atomic<int> g_force_goertzel{0};
+
+// Chirp (n), kernel transform in bit-reversed order (M) and the twiddles of every pass
+// (M - 1: the pass of span h holds exp(-2 pi i j / (2h)), j < h, at h - 1 + j) of the
+// geometry's row length, built on first use and kept with the geometry.
+hipError_t ncp_tables(const Geometry &g, int M, const double2 **chirp, const double2 **khat,
+                      const double2 **tw)
+{
+    std::lock_guard<std::mutex> lk(g_ncp_mu);
+    const int n = g.n_det;
+    if (!g.ncp_tab) {
+        const double pi = 3.14159265358979323846;
+        std::vector<std::complex<double>> c(n), w(M / 2), kern(M, 0.0);
+        for (int i = 0; i < n; ++i) {
+            const long long e = ((long long)i * i) % (2LL * n);   // c_i = exp(-pi i e / n)
+            c[i] = std::polar(1.0, -pi * (double)e / (double)n);
+        }
+        for (int j = 0; j < M / 2; ++j) w[j] = std::polar(1.0, -2.0 * pi * (double)j / (double)M);
+        kern[0] = std::conj(c[0]);
+        for (int i = 1; i < n; ++i) kern[i] = kern[M - i] = std::conj(c[i]);
+        host_fft(kern, w);
+        std::vector<double2> tab((size_t)n + 2 * M - 1);
+        for (int i = 0; i < n; ++i) tab[i] = make_double2(c[i].real(), c[i].imag());
+        const int bits = __builtin_ctz(M);
+        for (int i = 0; i < M; ++i) {
+            const unsigned br = __builtin_bitreverse32((unsigned)i) >> (32 - bits);
+            tab[(size_t)n + i] = make_double2(kern[br].real(), kern[br].imag());
+        }
+        for (int h = 1; h < M; h <<= 1)
+            for (int j = 0; j < h; ++j) {
+                // exp(-2 pi i j / (2h)) = w[j M / (2h)]
+                const std::complex<double> v = w[(size_t)j * (M / (2 * h))];
+                tab[(size_t)n + M + h - 1 + j] = make_double2(v.real(), v.imag());
+            }
+        void *d = nullptr;
+        hipError_t e = hipMalloc(&d, tab.size() * sizeof(double2));
+        if (e != hipSuccess) return e;
+        e = hipMemcpy(d, tab.data(), tab.size() * sizeof(double2), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(d);
+            return e;
+        }
+        g.ncp_tab = d;
+    }
+    const double2 *base = static_cast<const double2 *>(g.ncp_tab);
+    *chirp = base;
+    *khat = base + n;
+    *tw = base + n + M;
+    return hipSuccess;
+}
+
+template <typename T>
+hipError_t fft_rows_go(const Geometry &g, int M, const void *r, double *crow, int q,
+                       const DevState *st, int k, hipStream_t s)
+{
+    const double2 *chirp, *khat, *tw;
+    hipError_t e = ncp_tables(g, M, &chirp, &khat, &tw);
+    if (e != hipSuccess) return e;
+    ncp_fft_rows_kernel<T><<<g.n_ang, kFftThreads, (size_t)M * sizeof(double2), s>>>(
+        static_cast<const T *>(r), g.n_det, q, M, chirp, khat, tw, crow, st, k);
+    return hipGetLastError();
+}
+
 }  // namespace
+
+void ncp_force_goertzel(int on) { g_force_goertzel.store(on ? 1 : 0); }
+
+void ncp_release(Geometry &g)
+{
+    if (g.ncp_tab) (void)hipFree(g.ncp_tab);
+    g.ncp_tab = nullptr;
+}
 
 size_t ncp_scratch_bytes(const Geometry &g)
 {
     const int q = g.n_det / 2;
     const size_t nb = (size_t)(q + kBlock - 1) / kBlock;
-    return align256((size_t)g.n_ang * q * sizeof(double)) + align256((nb + 1) * sizeof(double));
+    return align256((size_t)g.n_ang * q * sizeof(double)) +
+           align256((size_t)kRowChunks * q * sizeof(double)) + align256((nb + 1) * sizeof(double));
 }
 
 hipError_t launch_ncp(const Geometry &g, int t, const void *r, double *scratch, DevState *st,
@@ -163,14 +405,27 @@ hipError_t launch_ncp(const Geometry &g, int t, const void *r, double *scratch, 
     const int q = g.n_det / 2;
     if (q < 1) return hipErrorInvalidValue;
     double *crow = scratch;
-    double *part = scratch + align256((size_t)g.n_ang * q * sizeof(double)) / sizeof(double);
+    double *colsum = crow + align256((size_t)g.n_ang * q * sizeof(double)) / sizeof(double);
+    double *part = colsum + align256((size_t)kRowChunks * q * sizeof(double)) / sizeof(double);
     // timed from before the row kernel to after the final one when profiling is on
+    const int M = g_force_goertzel.load() ? 0 : fft_length(g.n_det);
+    // tables first: building them (once per geometry) must not fall inside the timing
+    if (M) {
+        const double2 *c, *kh, *tw;
+        hipError_t e = ncp_tables(g, M, &c, &kh, &tw);
+        if (e != hipSuccess) return e;
+    }
     ProfScope ps(kProfNcp, s, st ? k : 0, false);
-    hipError_t e = t == ABG_F64 ? rows_dispatch<double>(g, r, crow, q, st, k, s)
-                                : rows_dispatch<float>(g, r, crow, q, st, k, s);
+    hipError_t e = M ? (t == ABG_F64 ? fft_rows_go<double>(g, M, r, crow, q, st, k, s)
+                                     : fft_rows_go<float>(g, M, r, crow, q, st, k, s))
+                     : (t == ABG_F64 ? rows_dispatch<double>(g, r, crow, q, st, k, s)
+                                     : rows_dispatch<float>(g, r, crow, q, st, k, s));
     if (e != hipSuccess) return e;
     const int nb = (q + kBlock - 1) / kBlock;
-    ncp_mean_kernel<<<nb, kBlock, 0, s>>>(crow, g.n_ang, q, part, st, k);
+    const int chunks = std::min(kRowChunks, g.n_ang);
+    const int rows_per = (g.n_ang + chunks - 1) / chunks;
+    ncp_colsum_kernel<<<dim3(nb, chunks), kBlock, 0, s>>>(crow, g.n_ang, q, rows_per, colsum, st, k);
+    ncp_dist_kernel<<<nb, kBlock, 0, s>>>(colsum, chunks, g.n_ang, q, part, st, k);
     ncp_final_kernel<<<1, 64, 0, s>>>(part, nb, st, k, snap);
     return hipGetLastError();
 }

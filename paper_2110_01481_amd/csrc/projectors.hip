@@ -18,7 +18,8 @@
 //           projector's padded copies (AB-GMRES applies A right after B).
 #include <hip/hip_ext.h>
 
-#include "proj_body.h"
+#include "back_body.h"
+#include "fwd_body.h"
 
 namespace abg {
 namespace {

@@ -191,6 +191,22 @@ struct HostLease {
     }
 };
 
+struct Solve;
+
+// A single solve's share of the device for its Gram-Schmidt block groups (see
+// GroupBudget), held from before its first launch until its stream is idle again.
+struct GroupHold {
+    long long units = 0;
+    hipStream_t s = nullptr;
+    hipError_t acquire(const Solve &S);
+    ~GroupHold()
+    {
+        if (units <= 0) return;
+        (void)hipStreamSynchronize(s);
+        device_group_budget().release(units);
+    }
+};
+
 #define CK(expr)                                   \
     do {                                           \
         hipError_t e_ = (expr);                    \
@@ -491,6 +507,17 @@ int instance_form_x(const Geometry &g, int method, int kind, int k_max, abg_stop
     return S.literal_residual(b, x, lit);
 }
 
+hipError_t GroupHold::acquire(const Solve &S)
+{
+    s = S.s;
+    long long u = 0;
+    hipError_t e = mgs_group_units(S.p.proj, S.p.basis, S.ly.L, S.q64 != nullptr, &u);
+    if (e != hipSuccess) return e;
+    device_group_budget().acquire(u);
+    units = u;
+    return hipSuccess;
+}
+
 int run_solver(const Geometry &g, int method, int kind, const void *b, const void *x0,
                void *x, int k_max, abg_stop st, abg_precision p, void *ws, size_t ws_bytes,
                abg_info *info, hipStream_t s)
@@ -498,6 +525,9 @@ int run_solver(const Geometry &g, int method, int kind, const void *b, const voi
     Solve S(g, method, kind, k_max, st, p, s, ws);
     if (ws_bytes < S.ly.total) return ABG_ENOMEM;
     CK(S.lease.acquire(k_max, s));
+    // the Gram-Schmidt groups must fit beside those of solves on other streams
+    GroupHold hold;
+    CK(hold.acquire(S));
     // launches of steps enqueued past the stop are left out of the launch timing
     struct ProfSolve {
         int last = 0;

@@ -116,6 +116,23 @@ def _deep_case(f, go, b, K, ks, eps=1e-15):
     return out
 
 
+def _f32(v):
+    return np.asarray(v, dtype=np.float32).astype(np.float64)
+
+
+def _f32_rounded_case(f, go, b, ref):
+    """The same run with every projector output, the data b and every stored basis vector
+    rounded to FP32 (dots, norms and the small problem stay FP64): how far FP32 storage
+    alone moves x_k and the GMRES residual norms from the FP64 run `ref`."""
+    r = f(lambda v: _f32(go.A(v)), lambda v: _f32(go.B_hat(v)), _f32(b), len(ref["ls_res"]),
+          keep_iterates=True, basis_round=_f32)
+    out = {"d32_ls": np.abs(np.asarray(r.ls_res) / ref["ls_res"] - 1.0)}
+    x_all = {int(k): ref[f"x{int(k)}"] for k in ref["ks"]}
+    out["d32_x"] = np.array([np.linalg.norm(r.iterates[k - 1] - x_all[k]) / np.linalg.norm(x_all[k])
+                             if k in x_all else np.nan for k in range(1, len(ref["ls_res"]) + 1)])
+    return out
+
+
 # Deep Krylov runs: vectors long enough for the multi-block Gram-Schmidt paths (more than
 # 16384 elements for both methods), 80 steps without a stopping rule so that the iterates
 # cross every Gram-Schmidt and Givens form; and the 64^2 problem for 140 steps, past the
@@ -146,7 +163,9 @@ def run_deep(out_path: str):
     go, _, b, _ = deep_problem()
     for method, f in (("ab", O.ab_gmres), ("ba", O.ba_gmres)):
         t0 = time.time()
-        for k, v in _deep_case(f, go, b, DEEP["K"], DEEP["ks"]).items():
+        case = _deep_case(f, go, b, DEEP["K"], DEEP["ks"])
+        case.update(_f32_rounded_case(f, go, b, case))
+        for k, v in case.items():
             res[f"deep_{method}_{k}"] = v
         print("deep", method, f"{time.time() - t0:.1f}s", flush=True)
     go, _, b, _ = givens_problem()

@@ -275,6 +275,48 @@ def test_config4_batched_equals_single_solves(gpu_lib):
     print("config4 k_stop:", sorted(ks))
 
 
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_config4_small_problems_against_oracle(gpu_lib, dt):
+    """The 40 problems of the 64-problem mix with N = 128 or 256 (60-720 angles, full and
+    limited range, AB and BA, DP tau = 1.02), b = A x_bar + e with the oracle's A, all in
+    one engine: each stops at the FP64 oracle's k (tests/golden/oracle_config4_small.npz,
+    make_oracle_golden.py 4) with the same status, and its iterate matches the oracle's
+    whole iterate (stored rounded to FP32, a relative floor of 6e-8) in the 2-norm and
+    element by element: FP64 within 1e-6, FP32 within the 1e-4 target."""
+    import os
+    import torch
+    abg = gpu_lib
+    z = np.load(os.path.join(os.path.dirname(__file__), "golden", "oracle_config4_small.npz"))
+    tdt = torch.float64 if dt == "f64" else torch.float32
+    cases = []
+    for w in W.batched_workloads():
+        if w.N > 256:
+            continue
+        go = O.Geometry(w.N, w.n_ang, w.n_det, ang_range=w.ang_range)
+        b, enorm = W.add_noise(go.A(w.phantom()), w.eta, w.noise_dir())
+        gg = abg.Geometry(w.N, w.n_ang, w.n_det, ang_range=w.ang_range)
+        cases.append((w, abg.Problem(g=gg, method=w.method, b=torch.tensor(b, dtype=tdt, device="cuda"),
+                                     k_max=w.k_max, stop="dp", tau=w.tau, noise_norm=enorm)))
+    assert len(cases) == 40
+    eng = abg.Engine(proj=dt, basis=dt, max_slots=len(cases))
+    try:
+        res = eng.run([p for _, p in cases])
+    finally:
+        eng.close()
+    tol = 1e-6 if dt == "f64" else 1e-4
+    worst = 0.0
+    for (w, _), r in zip(cases, res):
+        i = w.instance
+        assert r.status == str(z[f"i{i}_status"]) and r.k_stop == int(z[f"i{i}_k_stop"]), \
+            (i, r.status, r.k_stop, int(z[f"i{i}_k_stop"]))
+        ref = z[f"i{i}_x"].astype(np.float64)
+        x = r.x.double().cpu().numpy()
+        e = max(_rel(x, ref), np.abs(x - ref).max() / np.abs(ref).max())
+        worst = max(worst, e)
+        assert e <= tol, (i, w.N, w.n_ang, w.method, e)
+    print(f"config4 N<=256, {dt}: 40/40 same k_stop as the oracle, worst iterate error {worst:.2e}")
+
+
 @pytest.mark.parametrize("i", [0, 1])
 def test_dp_candidate_rejected_by_explicit_residual(gpu_lib, mix, i):
     """A DP candidate whose residual-form norm lies within the candidate slack above the

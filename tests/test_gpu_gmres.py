@@ -156,6 +156,33 @@ def test_bf16_basis_matches_rounded_oracle(gpu_lib, cfg1, method):
 
 
 @pytest.mark.parametrize("method", ["ab", "ba"])
+def test_bf16_basis_discrepancy_principle(gpu_lib, cfg1, method):
+    """DP (eq. 6.1, tau = 1.02) with the basis stored in BF16, against the oracle run whose
+    stored basis vectors are rounded to bf16 (everything else FP64). AB-GMRES: the oracle
+    stops at k = 10 (margins +4.4% at k = 9 and -3.7% at k = 10, far beyond FP32 effects)
+    and the GPU stops there too; the iterate one step earlier, formed explicitly by a
+    9-step solve, has ||b - A x_9|| above tau ||e||, so no earlier k was skipped by the
+    device's candidate gate. BA-GMRES: with bf16 storage the oracle's residual grows after
+    the first steps and never meets the rule (NOT_CONVERGED at k_max = 60, margin ~ +6.5);
+    the GPU returns NOT_CONVERGED as well and its explicit residual stays above the
+    threshold at every step."""
+    go, gg, _, b, enorm = cfg1
+    f = O.ab_gmres if method == "ab" else O.ba_gmres
+    ref = f(go.A, go.B_hat, b, 60, stop="dp", tau=1.02, noise_norm=enorm, basis_round=O.bf16_round)
+    r = _solve(method, gg, b, 60, dt="f32", basis="bf16", stop="dp", tau=1.02, noise_norm=enorm)
+    thr = 1.02 * enorm
+    print(f"{method} bf16 DP: GPU k_stop {r.k_stop} {r.status}, bf16-rounded oracle {ref.k_stop} "
+          f"{ref.status}; GPU res_norm / thr = {r.res_norm / thr:.4f}")
+    assert r.status == ref.status and r.k_stop == ref.k_stop
+    if method == "ab":
+        assert r.res_norm <= thr
+        prev = _solve(method, gg, b, r.k_stop - 1, dt="f32", basis="bf16")
+        assert prev.k_done == r.k_stop - 1 and prev.res_norm > thr, (prev.res_norm, thr)
+    else:
+        assert r.res_norm > thr and r.k_done == 60
+
+
+@pytest.mark.parametrize("method", ["ab", "ba"])
 @pytest.mark.parametrize("kind", ["hat", "adj"])
 def test_discrepancy_principle_same_k(gpu_lib, cfg1, method, kind):
     go, gg, _, b, enorm = cfg1
@@ -169,16 +196,25 @@ def test_discrepancy_principle_same_k(gpu_lib, cfg1, method, kind):
         assert abs(r.res_norm - ref.res_norms[ref.k_stop - 1]) <= 1e-5 * enorm
 
 
+@pytest.mark.parametrize("path", ["chirp_fft", "goertzel"])
 @pytest.mark.parametrize("method", ["ab", "ba"])
-def test_ncp_same_k(gpu_lib, cfg1, method):
+def test_ncp_same_k(gpu_lib, cfg1, method, path):
+    """NCP stop (Sec. 6.3) with the periodograms by the chirp transform (rows of 91 bins:
+    FFTs of length 256) and by Goertzel's recurrence: the oracle's k_NCP, d_k within 1e-5
+    (1e-9 in FP64) and its iterate."""
     go, gg, _, b, _ = cfg1
     f = O.ab_gmres if method == "ab" else O.ba_gmres
     ref = f(go.A, go.B_hat, b, 30, stop="ncp", ncp_shape=(go.n_ang, go.n_det))
+    gpu_lib.ncp_force_goertzel(path == "goertzel")
+    try:
+        runs = {dt: _solve(method, gg, b, 30, dt=dt, stop="ncp") for dt in ("f64", "f32")}
+    finally:
+        gpu_lib.ncp_force_goertzel(False)
     for dt in ("f64", "f32"):
-        r = _solve(method, gg, b, 30, dt=dt, stop="ncp")
+        r = runs[dt]
         assert r.k_stop == ref.k_stop, (dt, r.k_stop, ref.k_stop)
         n = min(len(ref.ncp), len(r.ncp_hist))
-        assert np.allclose(r.ncp_hist[:n], ref.ncp[:n], rtol=1e-5, atol=1e-9)
+        assert np.allclose(r.ncp_hist[:n], ref.ncp[:n], rtol=1e-9 if dt == "f64" else 1e-5, atol=1e-12)
         tol = _f64_tol(f, go, "hat", b, ref.k_stop) if dt == "f64" else 1e-4
         assert _rel(r.x.double().cpu().numpy(), ref.x) <= tol
 
@@ -256,17 +292,31 @@ def _fingerprint_errors(x, fp):
     return e_norm, e_pix, e_dot
 
 
+def _whole_errors(x, ref):
+    """Relative errors of a GPU iterate against the oracle's whole iterate: in the 2-norm
+    and element by element (largest difference over the largest entry)."""
+    x = np.asarray(x, dtype=np.float64)
+    return (float(np.linalg.norm(x - ref) / np.linalg.norm(ref)),
+            float(np.abs(x - ref).max() / np.abs(ref).max()))
+
+
+def _golden(name):
+    import os
+    return os.path.join(os.path.dirname(__file__), "golden", name)
+
+
 @pytest.mark.parametrize("solve", ["ab-hat", "ab-adj", "ba-hat", "ba-adj"])
 @pytest.mark.parametrize("dt", ["f32", "f64"])
 def test_full_size_discrepancy_principle(gpu_lib, solve, dt):
     """512^2 image, 720 x 725 sinogram, DP with tau = 1.02: the GPU stops at the oracle's
-    k and its iterate matches the oracle's (stored fingerprint written by
-    tests/golden/make_oracle_golden.py) within 1e-4."""
+    k and its iterate matches the oracle's whole iterate (tests/golden/oracle_config2_x.npz,
+    written by tests/golden/make_oracle_golden.py) element by element: FP64 within 1e-9
+    (the iterate at k = 7 is well conditioned), FP32 within the 1e-4 target."""
     import json
-    import os
     import torch
     import paper_2110_01481_amd as abg
-    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "oracle_config2.json")))
+    gold = json.load(open(_golden("oracle_config2.json")))
+    xs = np.load(_golden("oracle_config2_x.npz"))
     ref = gold["solves"][solve]
     w = W.CONFIG2
     go = O.Geometry(w.N, w.n_ang, w.n_det)
@@ -280,32 +330,57 @@ def test_full_size_discrepancy_principle(gpu_lib, solve, dt):
     assert r.status == "ok" and r.k_stop == ref["k_stop"], (r.k_stop, ref["k_stop"])
     margin = ref["dp_margin"][ref["k_stop"] - 1]
     print(f"{solve} {dt}: k={r.k_stop}, DP margin at stop {margin:.2e}, n_literal={r.n_literal}")
-    e = _fingerprint_errors(r.x.double().cpu().numpy(), ref["x"])
-    print(f"  iterate errors vs oracle: norm {e[0]:.2e} pixels {e[1]:.2e} probes {e[2]:.2e}")
-    assert max(e) <= 1e-4, e
-    assert abs(r.res_norm - ref["res_norms"][ref["k_stop"] - 1]) <= 1e-5 * ref["res_norms"][0]
+    e = _whole_errors(r.x.double().cpu().numpy(), xs[f"{method}_{kind}"])
+    print(f"  iterate vs oracle: 2-norm {e[0]:.2e}, element-wise {e[1]:.2e}")
+    assert max(e) <= (1e-9 if dt == "f64" else 1e-4), e
+    assert abs(r.res_norm - ref["res_norms"][ref["k_stop"] - 1]) <= \
+        (1e-11 if dt == "f64" else 1e-5) * ref["res_norms"][0]
 
 
 @pytest.fixture(scope="module")
 def config3_inputs():
-    """2048^2 image, 1800 angles, 2897 bins: b = A x_true + e with the oracle's A."""
+    """2048^2 image, 1800 angles, 2897 bins: b = A x_true + e with the oracle's A; the
+    oracle's NCP solve (stopping iteration, d_k, fingerprints) and its returned iterate,
+    stored whole rounded to FP32 (a relative floor of 6e-8 per element)."""
     import json
-    import os
-    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "oracle_config3.json")))
+    gold = json.load(open(_golden("oracle_config3.json")))
     w = W.CONFIG3
     go = O.Geometry(w.N, w.n_ang, w.n_det)
     b, enorm = W.add_noise(go.A(w.phantom()), w.eta, w.noise_dir())
     assert abs(enorm - gold["noise_norm"]) <= 1e-9 * enorm
-    return w, b, gold["solves"]["ba-hat"]
+    x_orc = np.load(_golden("oracle_config3_x.npy")).astype(np.float64)
+    return w, b, gold["solves"]["ba-hat"], x_orc
+
+
+def test_full_size_ncp_fp64(gpu_lib, config3_inputs):
+    """2048^2 BA-GMRES with NCP stopping in FP64 (projectors, basis and small problem): the
+    GPU stops at the oracle's iteration; d_k agree to 1e-9 relative; the iterate matches
+    the oracle's FP64 fingerprint (2000 pixels, 4 Gaussian probes, the norm) within 1e-9
+    and its whole FP32-rounded iterate element by element within 1e-6."""
+    import torch
+    import paper_2110_01481_amd as abg
+    w, b, ref, x_orc = config3_inputs
+    gg = abg.Geometry(w.N, w.n_ang, w.n_det)
+    bt = torch.tensor(b, dtype=torch.float64, device="cuda")
+    r = abg.gmres("ba", gg, bt, w.k_max, stop="ncp")
+    print(f"FP64: k_stop {r.k_stop} (oracle {ref['k_stop']}), k_done {r.k_done}")
+    assert r.status == "ok" and r.k_stop == ref["k_stop"]
+    d_ref = np.asarray(ref["ncp"][:r.k_done])
+    dd = np.abs(r.ncp_hist - d_ref).max() / d_ref.max()
+    x = r.x.cpu().numpy()
+    fp = max(_fingerprint_errors(x, ref["x"]))
+    e = _whole_errors(x, x_orc)
+    print(f"  d_k {dd:.2e}; fingerprint {fp:.2e}; whole iterate 2-norm {e[0]:.2e}, element-wise {e[1]:.2e}")
+    assert dd <= 1e-9 and fp <= 1e-9 and max(e) <= 1e-6
 
 
 def test_full_size_ncp_fp32_basis(gpu_lib, config3_inputs):
     """2048^2 BA-GMRES with NCP stopping, FP32 projectors and basis: the GPU stops at the
-    FP64 oracle's iteration, with its NCP distances and iterate (stored fingerprint,
-    also at fixed k = 3 and 6) within 1e-4."""
+    FP64 oracle's iteration, with its NCP distances and its whole iterate within 1e-4 (and
+    the stored fingerprints at fixed k = 3 and 6)."""
     import torch
     import paper_2110_01481_amd as abg
-    w, b, ref = config3_inputs
+    w, b, ref, x_orc = config3_inputs
     gg = abg.Geometry(w.N, w.n_ang, w.n_det)
     bt = torch.tensor(b, dtype=torch.float32, device="cuda")
     r = abg.gmres("ba", gg, bt, w.k_max, stop="ncp", basis="f32")
@@ -313,8 +388,8 @@ def test_full_size_ncp_fp32_basis(gpu_lib, config3_inputs):
     assert r.status == "ok" and r.k_stop == ref["k_stop"]
     d_ref = np.asarray(ref["ncp"][:r.k_done])
     assert np.abs(r.ncp_hist - d_ref).max() <= 1e-4 * d_ref.max()
-    e = _fingerprint_errors(r.x.double().cpu().numpy(), ref["x"])
-    print(f"  x_{r.k_stop} errors vs oracle: norm {e[0]:.2e} pixels {e[1]:.2e} probes {e[2]:.2e}")
+    e = _whole_errors(r.x.double().cpu().numpy(), x_orc)
+    print(f"  x_{r.k_stop} vs oracle: 2-norm {e[0]:.2e}, element-wise {e[1]:.2e}")
     assert max(e) <= 1e-4, e
     for k, fp in ref["fixed_k"].items():
         rk = abg.gmres("ba", gg, bt, int(k), basis="f32")
@@ -325,20 +400,30 @@ def test_full_size_ncp_fp32_basis(gpu_lib, config3_inputs):
 
 def test_full_size_ncp_bf16_basis_reports_error(gpu_lib, config3_inputs):
     """Same solve with the basis stored in BF16 (FP32 arithmetic, FP64 dots and
-    Hessenberg): its error against the FP64 oracle is reported; the run must complete with
-    a finite iterate and a stop the NCP rule chose."""
+    Hessenberg). BF16 storage perturbs every basis vector by ~4e-3 relative; BA-GMRES
+    amplifies it (the oracle with the same storage rounding shows it on the 64^2 problem),
+    the NCP distances separate from the FP64 ones after a few steps and the rule stops
+    early. Measured: k_stop = 9 against the oracle's 14, iterate error ~0.11. Asserted:
+    the stop is not later than the oracle's, the d_k of the first three steps agree with
+    the oracle's within 1e-2 (the rule sees the same early curve), the error against the
+    FP64 oracle stays below 0.2, and the returned iterate is the one a k_stop-step BF16
+    solve returns."""
     import torch
     import paper_2110_01481_amd as abg
-    w, b, ref = config3_inputs
+    w, b, ref, x_orc = config3_inputs
     gg = abg.Geometry(w.N, w.n_ang, w.n_det)
     bt = torch.tensor(b, dtype=torch.float32, device="cuda")
     r = abg.gmres("ba", gg, bt, w.k_max, stop="ncp", basis="bf16")
     x = r.x.double().cpu().numpy()
-    e = _fingerprint_errors(x, ref["x"])
-    print(f"BF16 basis: k_stop {r.k_stop} (oracle {ref['k_stop']}); x errors vs FP64 oracle: "
-          f"norm {e[0]:.2e} pixels {e[1]:.2e} probes {e[2]:.2e}")
-    assert r.status == "ok" and 1 <= r.k_stop <= w.k_max
-    assert np.all(np.isfinite(x))
+    e = _whole_errors(x, x_orc)
+    print(f"BF16 basis: k_stop {r.k_stop} (oracle {ref['k_stop']}); x vs FP64 oracle: "
+          f"2-norm {e[0]:.2e}, element-wise {e[1]:.2e}; d_k {np.round(r.ncp_hist, 4).tolist()}")
+    assert r.status == "ok" and 1 <= r.k_stop <= ref["k_stop"]
+    d_ref = np.asarray(ref["ncp"][:3])
+    assert np.abs(r.ncp_hist[:3] - d_ref).max() <= 1e-2 * d_ref.max()
+    assert e[0] <= 0.2
+    rk = abg.gmres("ba", gg, bt, r.k_stop, basis="bf16")
+    assert np.array_equal(rk.x.cpu().numpy(), r.x.cpu().numpy())
 
 
 @pytest.mark.parametrize("N,n_ang,n_det", [(1, 1, 1), (2, 1, 3), (5, 3, 1), (3, 2, 2), (1, 4, 3)])
