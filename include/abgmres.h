@@ -173,6 +173,19 @@ size_t abg_fp_workspace_bytes(const abg_geometry *g, int dtype);
 int abg_fp_apply(const abg_geometry *g, int dtype, const void *x, void *y,
                  void *ws, size_t ws_bytes, void *stream);
 
+/* y = A x like abg_fp_apply, for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the two padded
+ * copies of the image live in a static device array of the library (72 MiB per device,
+ * held from the library's load until the process ends) instead of a caller workspace.
+ * The call allocates nothing (no hipMalloc, no events, no library routine that
+ * allocates); the caller still owns x and y. Limit: abg_fp_workspace_bytes(g, dtype) must
+ * not exceed 72 MiB (N <= 2168 in FP64, N <= 3068 in FP32); larger geometries return
+ * ABG_ENOMEM and launch nothing. Every call on a device shares that device's array and
+ * clears what must start at zero itself; calls that overlap in time on one device (other
+ * streams, other threads) race on the array and must not be issued. Asynchronous on
+ * `stream`; results are bit-for-bit those of abg_fp_apply. */
+int abg_fp_apply_noalloc(const abg_geometry *g, int dtype, const void *x, void *y, void *stream);
+
 /* x = B y for kind ABG_BP_HAT (unmatched), x = A_line^T y for ABG_BP_ADJ, A_strip^T y for
  * ABG_BP_STRIP_T, A_Joseph^T y for ABG_BP_JOSEPH_T, B_tau y for ABG_BP_STRIP_TAU; pixel
  * driven. y: m elements, x: n elements of `dtype`. Asynchronous on `stream`. */

@@ -38,7 +38,8 @@ EXPORTS = ["abg_create_geometry", "abg_destroy_geometry", "abg_geometry_sizes",
            "abg_engine_get_tiles", "abg_engine_autotune", "abg_batch_solve",
            "abg_mgs_force_stream", "abg_geometry_set_model", "abg_geometry_get_model",
            "abg_geometry_set_strip_threshold", "abg_lsq_workspace_bytes", "abg_lsqr", "abg_lsmr",
-           "abg_gmres_error_history", "abg_release_process_resources", "abg_ncp_force_goertzel"]
+           "abg_gmres_error_history", "abg_release_process_resources", "abg_fp_apply_noalloc",
+           "abg_ncp_force_goertzel"]
 
 
 class AbgError(RuntimeError):
@@ -115,6 +116,7 @@ def load_library(path: str | None = None):
     lib.abg_fp_workspace_bytes.restype = sz
     lib.abg_fp_apply.argtypes = [vp, i, vp, vp, vp, sz, vp]
     lib.abg_bp_apply.argtypes = [vp, i, i, vp, vp, vp]
+    lib.abg_fp_apply_noalloc.argtypes = [vp, i, vp, vp, vp]
     lib.abg_workspace_bytes.argtypes = [vp, i, i, Precision, Stop]
     lib.abg_workspace_bytes.restype = sz
     for name in ("abg_ab_gmres", "abg_ba_gmres"):
@@ -273,6 +275,17 @@ class Geometry:
                                            ctypes.c_void_p(ws.data_ptr()), ws.numel(),
                                            _stream_ptr(stream)), "abg_fp_apply")
         return y
+
+    def fp_noalloc(self, x, out, stream=None):
+        """y = A x through abg_fp_apply_noalloc (the library's static device scratch; no
+        allocation by the library): x and the output `out` are caller-owned CUDA tensors."""
+        assert x.is_cuda and x.is_contiguous() and x.numel() == self.n
+        assert out.is_cuda and out.is_contiguous() and out.numel() == self.m and out.dtype == x.dtype
+        _check(load_library().abg_fp_apply_noalloc(self._h, _dtype_code(x.dtype),
+                                                   ctypes.c_void_p(x.data_ptr()),
+                                                   ctypes.c_void_p(out.data_ptr()),
+                                                   _stream_ptr(stream)), "abg_fp_apply_noalloc")
+        return out
 
     def bp(self, y, kind: str = "hat", out=None, stream=None):
         """x = B y (kind "hat", unmatched), A_line^T y ("adj"), A_strip^T y ("strip_t"),

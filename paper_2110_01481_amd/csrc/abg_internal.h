@@ -302,6 +302,11 @@ hipError_t mgs_group_units(int tx, int tv, long long L, bool q64, long long *uni
 // Frees the idle pooled pinned scalar slots and step events of single solves (solver.hip).
 int host_release_all();
 
+// Forward projection through the library's static device scratch instead of a caller
+// workspace (projectors.hip); ABG_ENOMEM when the padded copies do not fit it.
+size_t fp_static_scratch_bytes();
+int fp_apply_static(const Geometry &g, int dtype, const void *x, void *y, hipStream_t s);
+
 // ---- profiling (capi.cpp) -----------------------------------------------------------
 enum ProfKind { kProfFwd = 0, kProfBack = 1, kProfMgs = 2, kProfCombine = 3, kProfNcp = 4, kProfKinds = 5 };
 bool profiling_on();
@@ -317,6 +322,13 @@ struct ProfScope {
     hipStream_t s;
     bool ext;
     hipEvent_t e0 = nullptr, e1 = nullptr;
+};
+// While one of these lives, launches of the current thread are not timed (their
+// ProfScope takes no events): entry points that must not create any.
+struct ProfSuppress {
+    ProfSuppress();
+    ~ProfSuppress();
+    bool prev;
 };
 void profile_flush();
 void profile_solve_begin();

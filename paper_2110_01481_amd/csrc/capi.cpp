@@ -24,6 +24,7 @@ struct Pending {
 };
 std::atomic<long long> g_solve_ids{0};
 thread_local long long t_solve = 0;
+thread_local bool t_prof_suppressed = false;
 std::vector<Pending> g_pending;
 std::vector<hipEvent_t> g_event_pool;   // recycled so timing adds no event creation
 
@@ -87,7 +88,7 @@ bool profiling_on() { return g_prof_on; }
 ProfScope::ProfScope(int kind_, hipStream_t s_, int step_, bool ext_)
     : kind(kind_), step(step_), s(s_), ext(ext_)
 {
-    if (!g_prof_on) return;
+    if (!g_prof_on || t_prof_suppressed) return;
     e0 = take_event();
     e1 = take_event();
     if (!e0 || !e1) {
@@ -112,6 +113,9 @@ ProfScope::~ProfScope()
     g_pending.push_back({kind, e0, e1, t_solve, step});
     if (g_pending.size() >= kMaxPending) flush_locked();
 }
+
+ProfSuppress::ProfSuppress() : prev(t_prof_suppressed) { t_prof_suppressed = true; }
+ProfSuppress::~ProfSuppress() { t_prof_suppressed = prev; }
 
 void profile_solve_begin()
 {
@@ -337,6 +341,14 @@ int abg_fp_apply(const abg_geometry *h, int dtype, const void *x, void *y, void 
     return launch_forward(h->g, dtype, x, y, ws, static_cast<hipStream_t>(stream)) == hipSuccess
                ? ABG_OK
                : ABG_EHIP;
+}
+
+int abg_fp_apply_noalloc(const abg_geometry *h, int dtype, const void *x, void *y, void *stream)
+{
+    if (!h || !x || !y || !valid_dtype_proj(dtype)) return ABG_EINVAL;
+    int rc = current_device_matches(h->g);
+    if (rc) return rc;
+    return fp_apply_static(h->g, dtype, x, y, static_cast<hipStream_t>(stream));
 }
 
 int abg_bp_apply(const abg_geometry *h, int kind, int dtype, const void *y, void *x,

@@ -18,6 +18,8 @@
 //           projector's padded copies (AB-GMRES applies A right after B).
 #include <hip/hip_ext.h>
 
+#include <mutex>
+
 #include "back_body.h"
 #include "fwd_body.h"
 
@@ -198,6 +200,51 @@ hipError_t launch_forward_staged(const Geometry &g, int dtype, void *y, void *ws
 {
     return dtype == ABG_F64 ? forward_t<double>(g, nullptr, y, ws, s, st, k, true)
                             : forward_t<float>(g, nullptr, y, ws, s, st, k, true);
+}
+
+// ---- forward projection without a caller workspace ------------------------------------
+// The two padded copies live in a file-scope device array instead. In host code the
+// array's name is only a host-side stand-in: every use goes through the device address
+// that hipGetSymbolAddress returns, looked up once per device (each device holds its own
+// copy of the array) on the first call there.
+namespace {
+constexpr size_t kStaticScratchBytes = size_t(72) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+hipError_t scratch_address(void **out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+}  // namespace
+
+size_t fp_static_scratch_bytes() { return kStaticScratchBytes; }
+
+int fp_apply_static(const Geometry &g, int dtype, const void *x, void *y, hipStream_t s)
+{
+    if (fp_workspace_bytes(g, dtype) > kStaticScratchBytes) return ABG_ENOMEM;
+    void *ptr = nullptr;
+    if (scratch_address(&ptr) != hipSuccess) return ABG_EHIP;
+    ProfSuppress no_events;
+    // pads_zero = false: the padding is cleared by a kernel on every call, whatever an
+    // earlier call left in the array
+    return launch_forward(g, dtype, x, y, ptr, s, nullptr, 0, false) == hipSuccess ? ABG_OK
+                                                                                 : ABG_EHIP;
 }
 
 }  // namespace abg
