@@ -45,8 +45,8 @@ COUNTER_KERNELS = {
                         [_CSRC + "back_body.h", _CSRC + "geometry.h", _CSRC + "projectors.hip"]),
 }
 # kernels of a solve whose L2 hit rate the TCC pass reports
-L2_KERNELS = ("forward_kernel", "back_kernel", "mgs_kernel", "mgs_icwy_kernel",
-              "mgs_stream_kernel", "combine_kernel", "ncp_rows_kernel")
+L2_KERNELS = ("forward_kernel", "back_kernel", "mgs_kernel", "mgs_stream_kernel",
+              "combine_kernel", "ncp_fft_rows_kernel", "ncp_colsum_kernel")
 
 
 def progress(msg: str):
@@ -149,6 +149,52 @@ def summarize_counters(d: str, kernel_key: str = "forward_kernel_f32",
         "```",
         ""]
     return "\n".join(lines)
+
+
+def summarize_kernel_stats(d: str, title: str, command: str) -> str:
+    """Text summary of a `rocprofv3 --kernel-trace --stats --output-format csv` run under
+    directory d: calls, average and total time and share per kernel (run_kernel_stats.csv),
+    and the average over launches longer than 20 us per kernel (run_kernel_trace.csv:
+    launches of steps enqueued past a stop return at entry in a few microseconds)."""
+    import csv
+    import glob
+
+    def find(name):
+        hits = glob.glob(os.path.join(d, "**", name), recursive=True)
+        if not hits:
+            raise FileNotFoundError(f"{name} under {d}")
+        return hits[0]
+
+    def short(n):
+        n = n.replace("abg::(anonymous namespace)::", "").replace("void ", "")
+        return n.split("(")[0] if "(" in n else n
+
+    rows = []
+    with open(find("run_kernel_stats.csv")) as fh:
+        for r in csv.DictReader(fh):
+            rows.append((short(r["Name"]), int(r["Calls"]), float(r["AverageNs"]) / 1e3,
+                         float(r["TotalDurationNs"]) / 1e6, float(r["Percentage"])))
+    long_runs = {}
+    with open(find("run_kernel_trace.csv")) as fh:
+        for r in csv.DictReader(fh):
+            us = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+            if us > 20.0:
+                k = short(r["Kernel_Name"])
+                n, t = long_runs.get(k, (0, 0.0))
+                long_runs[k] = (n + 1, t + us)
+    out = [f"# {title}", "", "Command (from the repository root, TMPDIR=/tmp):", "",
+           f"    {command}", "",
+           "Whole run (set-up, warm-up and the timed steps). Launches of steps enqueued past a",
+           "stop return at entry (a few microseconds) and are counted in calls/avg of the table;",
+           "the averages over launches longer than 20 us are listed below it.", "",
+           f"{'kernel':<64s} {'calls':>7s} {'avg us':>9s} {'total ms':>9s} {'share':>6s}"]
+    for name, calls, avg, tot, pct in sorted(rows, key=lambda r: -r[3]):
+        out.append(f"{name[:64]:<64s} {calls:7d} {avg:9.1f} {tot:9.2f} {pct:5.1f}%")
+    out.append("")
+    for name, (n, t) in sorted(long_runs.items(), key=lambda kv: -kv[1][1]):
+        out.append(f"{name}: {n} launches > 20 us, average {t / n:.1f} us")
+    out.append("")
+    return "\n".join(out)
 
 
 def stored_counters(kernel_key: str, workload_tag: str) -> dict | None:
@@ -870,6 +916,11 @@ def main():
     ap.add_argument("--counter-kernel", default="forward_kernel_f32", choices=sorted(COUNTER_KERNELS))
     ap.add_argument("--counter-workload", default="512x512, 720 x 725, FP32")
     ap.add_argument("--counter-bench-args", default="")
+    ap.add_argument("--summarize-kernel-stats", default="",
+                    help="print the kernel-time summary of a rocprofv3 --kernel-trace --stats "
+                         "csv run under this directory (with --stats-title, --stats-command)")
+    ap.add_argument("--stats-title", default="")
+    ap.add_argument("--stats-command", default="")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run device-to-device copies of this many MiB (a plain copy "
                          "kernel whose HBM counters calibrate FETCH_SIZE / WRITE_SIZE)")
@@ -877,6 +928,10 @@ def main():
     if args.summarize_counters:
         print(summarize_counters(args.summarize_counters, args.counter_kernel,
                                  args.counter_workload, args.counter_bench_args))
+        return
+    if args.summarize_kernel_stats:
+        print(summarize_kernel_stats(args.summarize_kernel_stats, args.stats_title,
+                                     args.stats_command))
         return
     if args.gpus != 1:
         print(json.dumps({"error": "the solver library runs on one GPU; --gpus N > 1 is not "

@@ -46,3 +46,27 @@ def test_counter_summary_scales_by_the_copy_calibration(tmp_path):
     text = bench.summarize_counters(str(tmp_path))
     data = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
     assert data["valu_wave_insts_per_dispatch"] == 5000.0
+
+
+def test_kernel_stats_summary(tmp_path):
+    sys.path.insert(0, ROOT)
+    import bench
+    with open(tmp_path / "run_kernel_stats.csv", "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=["Name", "Calls", "TotalDurationNs", "AverageNs", "Percentage"])
+        w.writeheader()
+        w.writerow({"Name": "void abg::(anonymous namespace)::forward_kernel<double>(double const*)",
+                    "Calls": 3, "TotalDurationNs": 15000000, "AverageNs": 5000000, "Percentage": 75.0})
+        w.writerow({"Name": "abg::(anonymous namespace)::ncp_dist_kernel(double const*)",
+                    "Calls": 2, "TotalDurationNs": 5000000, "AverageNs": 2500000, "Percentage": 25.0})
+    with open(tmp_path / "run_kernel_trace.csv", "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=["Kernel_Name", "Start_Timestamp", "End_Timestamp"])
+        w.writeheader()
+        for start, end in ((0, 4000000), (10, 6000010), (20, 3020)):   # the last one < 20 us
+            w.writerow({"Kernel_Name": "void abg::(anonymous namespace)::forward_kernel<double>(x)",
+                        "Start_Timestamp": start, "End_Timestamp": end})
+    text = bench.summarize_kernel_stats(str(tmp_path), "t", "cmd")
+    lines = text.splitlines()
+    assert lines[0] == "# t" and "    cmd" in lines
+    row = [ln for ln in lines if ln.startswith("forward_kernel<double>") and "%" in ln][0]
+    assert row.split()[1:] == ["3", "5000.0", "15.00", "75.0%"]
+    assert "forward_kernel<double>: 2 launches > 20 us, average 5000.0 us" in lines

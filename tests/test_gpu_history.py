@@ -2,7 +2,8 @@
 
 * abg_gmres_error_history: ||x_k - x_bar|| for every k of a finished AB-/BA-GMRES solve,
   each iterate rebuilt from the stored basis, against the oracle's iterates (FP64: the
-  sensitivity-based bound of the fixed-k tests; FP32: the 1e-4 iterate target), and the
+  sensitivity-based bound of the fixed-k tests; FP32: the 1e-4 iterate target, or 100
+  times what FP32 storage alone changes in the oracle's iterate where that is larger), and the
   rebuilt iterate at the DP stop against the iterate the DP solve returned.
 * LSQR / LSMR x_ref histories: equal to the error of the iterate a k-step solve returns,
   and to the oracle's matched GMRES iterates at early k (Sec. 5).
@@ -41,19 +42,29 @@ def _t(a, dt):
 
 
 def _iterate_bounds(f, go, back, b, K, dt, eps=1e-13, seed=17):
-    """Per-k bound on ||x_k(GPU) - x_k(oracle)|| / ||x_k(oracle)||. s_k: the relative change
-    a 1e-13 perturbation of b causes in the oracle's own x_k, the largest over k-3..k+3
-    (isolated steps of this problem are ill-conditioned: near k = 24 a 1e-15 change of b
-    moves x_k by ~3e-4, and one perturbation direction samples the spike). FP64:
-    max(1e-6, 1e3 s_k); FP32 (rounding ~1e6 times larger): max(1e-4, 1e7 s_k)."""
+    """Per-k bound on ||x_k(GPU) - x_k(oracle)|| / ||x_k(oracle)||, from two probes of the
+    oracle, each taken as the largest over k-3..k+3 (isolated steps of this problem are
+    ill-conditioned: near k = 24 a 1e-15 change of b moves x_k by ~3e-4, and one
+    perturbation samples the spike).
+      FP64: s_k, the relative change a 1e-13 perturbation of b causes in the oracle's own
+            x_k; bound max(1e-6, 1e3 s_k).
+      FP32: d_k, the relative change when every projector output, b and every stored
+            basis vector are rounded to FP32 (dots, norms and the small problem in FP64):
+            what FP32 storage alone does to the method; bound max(1e-4, 100 d_k) (the GPU
+            also rounds inside each projector sum of ~100 terms)."""
     ref = f(go.A, back, b, K, keep_iterates=True)
-    d = np.random.default_rng(seed).standard_normal(b.size)
-    bp = b + eps * np.linalg.norm(b) * d / np.linalg.norm(d)
-    per = f(go.A, back, bp, K, keep_iterates=True)
-    sens = np.array([_rel(per.iterates[k], ref.iterates[k]) for k in range(K)])
-    near = np.array([sens[max(0, k - 3):k + 4].max() for k in range(K)])
     if dt == "f32":
-        return ref, np.maximum(1e-4, 1e7 * near)
+        f32 = lambda v: np.asarray(v, dtype=np.float32).astype(np.float64)  # noqa: E731
+        per = f(lambda v: f32(go.A(v)), lambda v: f32(back(v)), f32(b), K,
+                keep_iterates=True, basis_round=f32)
+    else:
+        d = np.random.default_rng(seed).standard_normal(b.size)
+        per = f(go.A, back, b + eps * np.linalg.norm(b) * d / np.linalg.norm(d), K,
+                keep_iterates=True)
+    probe = np.array([_rel(per.iterates[k], ref.iterates[k]) for k in range(K)])
+    near = np.array([probe[max(0, k - 3):k + 4].max() for k in range(K)])
+    if dt == "f32":
+        return ref, np.maximum(1e-4, 100.0 * near)
     return ref, np.maximum(1e-6, 1e3 * near)
 
 
@@ -72,8 +83,12 @@ def test_gmres_error_history_vs_oracle(gpu_lib, cfg1, method, dt):
     # | ||x_k - x_bar|| - ||x_k^ref - x_bar|| | <= ||x_k - x_k^ref|| (plus x_bar's rounding
     # to FP32 in the FP32 run)
     slack = 0.0 if dt == "f64" else np.linalg.norm(xb - xb.astype(np.float32))
-    assert np.all(np.abs(r.err_hist - ref_err) <= tol * xn + slack + 1e-12), \
-        np.max(np.abs(r.err_hist - ref_err) / xn)
+    dev = np.abs(r.err_hist - ref_err)
+    lim = tol * xn + slack + 1e-12
+    k = int(np.argmax(dev / lim))
+    print(f"{method} {dt}: worst step {k + 1}: deviation {dev[k] / xn[k]:.2e} of ||x_k|| "
+          f"(bound {lim[k] / xn[k]:.2e}); largest {np.max(dev / xn):.2e}")
+    assert np.all(dev <= lim), (k + 1, dev[k] / xn[k], lim[k] / xn[k])
     # the last entry is the error of the iterate the solve returned
     xg = r.x.double().cpu().numpy()
     xr = _t(xb, dt).double().cpu().numpy()
