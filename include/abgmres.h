@@ -321,11 +321,16 @@ int abg_engine_poll(abg_engine *e, long long *tags, int *status, int max, int *n
 
 /* Tile shapes and schedule of the projector work items, taking effect next round.
  * rays: rays of one angle per forward-projector block (64, 128 or 256; a block of 256
- * threads takes 256/rays angles). ang_block: angles whose detector windows a
- * back-projector block stages in LDS per round (64 or 128). sched: 0 deals the items out
- * round-robin over the resident blocks; 1 cuts each item list into 8 contiguous ranges,
- * one per XCD, that blocks drain in chunks through per-range counters before helping
- * with the others. Results do not depend on any of them. */
+ * threads takes 256/rays angles), or 0 (the default): per problem, the shape single
+ * solves of its geometry use (abg_fp_force_block_shape). ang_block: angles whose detector
+ * windows a back-projector block stages in LDS per round (64, the default, or 128). sched:
+ * 0 deals the items out round-robin over the resident blocks; 1 cuts each
+ * item list into 8 contiguous ranges, one per XCD, that blocks drain through per-range
+ * counters in shrinking chunks (half of what is left over the blocks of the range) before
+ * helping with the others; 2 (the default) hands the whole list out in order through one
+ * counter, in shrinking chunks, so that all blocks work on the same one or two problems
+ * at a time.
+ * Results do not depend on any of them. */
 int abg_engine_set_tiles(abg_engine *e, int rays, int ang_block, int sched);
 int abg_engine_get_tiles(const abg_engine *e, int *rays, int *ang_block, int *sched);
 
@@ -363,6 +368,16 @@ int abg_profile_read(long long counts[ABG_PROF_KINDS], double ms[ABG_PROF_KINDS]
  * recurrence per frequency. With on != 0 every row length uses the recurrence
  * (process-wide; for tests and measurements). Returns ABG_OK. */
 int abg_ncp_force_goertzel(int on);
+
+/* Block shape of the forward projectors (line, strip and Joseph models): each block of
+ * 256 threads takes 2^lg_angles consecutive angles and 256 / 2^lg_angles consecutive rays
+ * of each (0: one angle, 1: two, 2: four). -1 (the default) chooses by image size: four
+ * angles for N > 640, else one, or two where that leaves fewer lanes of the last block of
+ * each angle idle. The shape changes only
+ * which rays run together, never a ray's arithmetic: results are bit-identical for every
+ * shape. Process-wide; for tests and measurements. Returns ABG_OK, or ABG_EINVAL for
+ * lg_angles outside -1..2. */
+int abg_fp_force_block_shape(int lg_angles);
 
 /* Releases what the library holds process-wide beyond geometries and engines: the
  * profiling events (profiling is switched off; accumulated counts are kept) and the idle

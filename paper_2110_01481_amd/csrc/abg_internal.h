@@ -202,6 +202,12 @@ size_t ncp_scratch_bytes(const Geometry &g);
 void ncp_release(Geometry &g);
 // Process-wide: periodograms by Goertzel's recurrence for every row length (tests).
 void ncp_force_goertzel(int on);
+// Process-wide: forward projector block shape, 2^lg_apb angles per block (0..2), or -1 for
+// the automatic choice (tests and measurements).
+void fwd_force_block_shape(int lg_apb);
+// Forward projector block shape (log2 of the angles per block of 256 threads) for a
+// geometry: the choice single solves make, or the forced one.
+int fwd_lg_angles_per_block(const Geometry &g);
 // d_k of the residual r into st->ncp; raises the NCP stop for step k when k >= 2 and
 // d_k > d_{k-1}. `snap`: as for launch_combine.
 hipError_t launch_ncp(const Geometry &g, int t, const void *r, double *scratch, DevState *st,

@@ -23,6 +23,10 @@ template <> __device__ inline float edge_tie<float>() { return 2e-5f; }
 constexpr int kTile = 16;
 constexpr int kBackWaves = 8;
 constexpr int kBackThreads = 64 * kBackWaves;
+// Launch bound (waves per SIMD) of the back projector kernels: in FP32 at most 64 VGPRs,
+// so that four blocks (eight waves per SIMD) share a CU.
+template <typename T> constexpr int kBackMinWaves = 1;
+template <> constexpr int kBackMinWaves<float> = 8;
 constexpr int kPixPerLane = kTile * kTile / 64;
 constexpr int kAngBlock = 128;
 constexpr int kWin = 32;

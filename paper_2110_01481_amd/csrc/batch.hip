@@ -35,15 +35,18 @@
 namespace abg {
 
 // Work lists are split into kRanges contiguous ranges with a counter each (see
-// for_each_item).
+// for_each_item); the list-order schedule claims at most kMaxListChunk items at a time.
 constexpr int kRanges = 8;
+constexpr int kMaxListChunk = 8;
 
 enum Tab {
     kTPadBA = 0,   // pad w_k (BA)
-    kTBackAB,      // t = B w_k (AB)
+    kTBackAB,      // t = B w_k (AB), interpolating back projector
+    kTBackABAdj,   // t = A^T w_k (AB), matched pair
     kTFwdBA,       // z = A w_k (BA)
     kTPadAB,       // pad t (AB)
-    kTBackBA,      // q = B z (BA)
+    kTBackBA,      // q = B z (BA), interpolating back projector
+    kTBackBAAdj,   // q = A^T z (BA), matched pair
     kTFwdAB,       // q = A t (AB)
     kTMgsS,        // MGS groups with the small register tile
     kTMgsL,        // MGS groups with the large register tile
@@ -76,6 +79,7 @@ struct BatchInst {
     int need_res;
     int mgs_G, mgs_class;   // register tile class 0 small, 1 large, 3 huge; 2 streaming
     int chunk, n_chunks;
+    int fwd_rays;           // forward block shape of the single-solve rule (tiles.rays = 0)
 };
 
 // Work lists: list t holds segments (problem, first ticket); items of a segment are
@@ -91,7 +95,8 @@ struct TabView {
 
 struct Tiles {
     int rays;        // forward projector: rays of one angle per block (64, 128 or 256);
-                     // a block of 256 threads takes 256/rays angles
+                     // a block of 256 threads takes 256/rays angles; 0: per problem, the
+                     // shape single solves of its geometry use
     int ang_block;   // back projectors: angles staged in LDS per round (64 or 128)
     int sched;       // item schedule of the projector and residual lists (for_each_item)
 };
@@ -106,13 +111,20 @@ __device__ int items_of(int t, const BatchInst &d, const Tiles &tl)
     switch (t) {
     case kTPadBA: return ba ? ceil_div(d.N, 32) * ceil_div(d.N, 32) : 0;
     case kTPadAB: return ba ? 0 : ceil_div(d.N, 32) * ceil_div(d.N, 32);
-    case kTBackAB: return ba ? 0 : ceil_div(d.N, kTile) * ceil_div(d.N, kTile);
-    case kTBackBA: return ba ? ceil_div(d.N, kTile) * ceil_div(d.N, kTile) : 0;
+    case kTBackAB:
+    case kTBackABAdj:
+    case kTBackBA:
+    case kTBackBAAdj: {
+        const bool want_ba = t == kTBackBA || t == kTBackBAAdj;
+        const bool want_adj = t == kTBackABAdj || t == kTBackBAAdj;
+        if (ba != want_ba || (d.kind == ABG_BP_ADJ) != want_adj) return 0;
+        return ceil_div(d.N, kTile) * ceil_div(d.N, kTile);
+    }
     case kTFwdBA:
     case kTFwdAB: {
         if ((t == kTFwdBA) != ba) return 0;
-        const int apb = 256 / tl.rays;
-        return ceil_div(d.n_ang, apb) * ceil_div(d.n_det, tl.rays);
+        const int rays = tl.rays ? tl.rays : d.fwd_rays;
+        return ceil_div(d.n_ang, 256 / rays) * ceil_div(d.n_det, rays);
     }
     case kTMgsS: return d.mgs_class == 0 ? d.mgs_G : 0;
     case kTMgsL: return d.mgs_class == 1 ? d.mgs_G : 0;
@@ -204,21 +216,33 @@ __device__ inline void locate(const TabView &tv, int t, int it, int *slot, int *
     *local = __builtin_amdgcn_readfirstlane(it - tv.seg_first(t, lo));
 }
 
-// Runs body(slot, local) for the items of list t that this block takes, under one of two
+// Runs body(slot, local) for the items of list t that this block takes, under one of three
 // schedules (a tunable):
 //  sched 0  static round-robin: block b takes items b, b + grid, b + 2 grid, ...
 //  sched 1  the list is cut into kRanges contiguous ranges with a counter each; block b
 //           starts on range b % kRanges (blocks are dispatched round-robin over the XCDs,
 //           so each XCD works mostly on its own contiguous part of the list and keeps it
 //           in its L2), takes chunks of items from it as it frees up, then helps with the
-//           other ranges: items of unequal cost are balanced dynamically.
+//           other ranges: items of unequal cost are balanced dynamically. Chunks are
+//           guided: a claim takes half of what is left of the range divided by the blocks
+//           that start on it, so the last items go one at a time and a phase does not
+//           wait on one block's large final chunk (an item of a 2048^2 problem is ~0.1 ms).
+//  sched 2  list order: block b takes item b, then the blocks claim the items after the
+//           first `grid` through one counter in guided chunks (what is left over twice
+//           the grid, between 1 and kMaxListChunk items). The running blocks all work on
+//           the same one or two problems, as the blocks of a single solve's launch do, so
+//           only those problems' images and sinograms compete for the caches (with one
+//           range per XCD, or with chunks of ~100 items, eight or more large problems are
+//           in flight at once, more than the Infinity Cache holds, and a served batch ran
+//           15% slower); a list no longer than the grid takes no claim at all.
+// The pad and residual lists (uniform, cheap items) always run sched 0.
 // A block's items come in increasing order, so the segment (problem) of an item is found
 // by moving a cursor forward. body must be called by the whole block (it may
 // synchronise).
 template <typename F>
 __device__ inline void for_each_item(const TabView &tv, int t, int sched, F &&body)
 {
-    __shared__ int s_c;
+    __shared__ int s_c, s_len;
     const int total = tv.total[t];
     if ((int)blockIdx.x >= total) return;
     const int nseg = tv.nseg[t];
@@ -233,7 +257,33 @@ __device__ inline void for_each_item(const TabView &tv, int t, int sched, F &&bo
         return;
     }
     const int G = min((int)gridDim.x, total);
-    const int C = max(1, total / (G * kRanges));
+    if (sched == 2) {
+        visit(blockIdx.x);
+        const int rest = total - G;
+        if (rest <= 0) return;
+        unsigned *tk = tv.ticket + t * kRanges;
+        for (;;) {
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                int c = rest, len = 0;
+                const int seen =
+                    (int)__hip_atomic_load(tk, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (seen < rest) {
+                    len = min(kMaxListChunk, max(1, (rest - seen) / (2 * G)));
+                    c = (int)__hip_atomic_fetch_add(tk, (unsigned)len, __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
+                }
+                s_c = c;
+                s_len = len;
+            }
+            __syncthreads();
+            const int c = __builtin_amdgcn_readfirstlane(s_c);
+            if (c >= rest) return;
+            const int e = min(rest, c + __builtin_amdgcn_readfirstlane(s_len));
+            for (int it = G + c; it < G + e; ++it) visit(it);
+        }
+    }
+    const int per_range = max(1, G / kRanges);
     const int home = (int)(blockIdx.x % kRanges);
     unsigned *tk = tv.ticket + t * kRanges;
     for (int p = 0; p < kRanges; ++p) {
@@ -244,16 +294,21 @@ __device__ inline void for_each_item(const TabView &tv, int t, int sched, F &&bo
         for (;;) {
             __syncthreads();
             if (threadIdx.x == 0) {
-                int c = n;
-                if ((int)__hip_atomic_load(tk + r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < n)
-                    c = (int)__hip_atomic_fetch_add(tk + r, (unsigned)C, __ATOMIC_RELAXED,
+                int c = n, len = 0;
+                const int seen =
+                    (int)__hip_atomic_load(tk + r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (seen < n) {
+                    len = max(1, (n - seen) / (2 * per_range));
+                    c = (int)__hip_atomic_fetch_add(tk + r, (unsigned)len, __ATOMIC_RELAXED,
                                                     __HIP_MEMORY_SCOPE_AGENT);
+                }
                 s_c = c;
+                s_len = len;
             }
             __syncthreads();
             const int c = __builtin_amdgcn_readfirstlane(s_c);
             if (c >= n) break;
-            const int e = min(n, c + C);
+            const int e = min(n, c + __builtin_amdgcn_readfirstlane(s_len));
             for (int it = lo + c; it < lo + e; ++it) visit(it);
         }
     }
@@ -301,7 +356,8 @@ __global__ __launch_bounds__(256) void bpad_kernel(const BatchInst *__restrict__
                                                    TabView tv, int t, int mode, Tiles tl)
 {
     __shared__ PadLds<T> lds;
-    for_each_item(tv, t, tl.sched, [&](int slot, int local) {
+    // uniform, cheap items: static round-robin
+    for_each_item(tv, t, 0, [&](int slot, int local) {
         const BatchInst &d = D[slot];
         const DevState *st = S + slot;
         if (halted(st, st->kcur)) return;
@@ -320,16 +376,17 @@ __global__ __launch_bounds__(256) void bfwd_kernel(const BatchInst *__restrict__
 {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    const int wpa = tl.rays / 64;       // waves per angle
-    const int apb = 256 / tl.rays;      // angles per block
     for_each_item(tv, t, tl.sched, [&](int slot, int local) {
         const BatchInst &d = D[slot];
         const DevState *st = S + slot;
         const int k = st->kcur;
         if (halted(st, k)) return;
-        const int nrg = (d.n_det + tl.rays - 1) / tl.rays;
+        const int rays = tl.rays ? tl.rays : d.fwd_rays;
+        const int wpa = rays / 64;       // waves per angle
+        const int apb = 256 / rays;      // angles per block
+        const int nrg = (d.n_det + rays - 1) / rays;
         const int a = (local / nrg) * apb + wave / wpa;
-        const int i = (local % nrg) * tl.rays + (wave % wpa) * 64 + lane;
+        const int i = (local % nrg) * rays + (wave % wpa) * 64 + lane;
         if (a >= d.n_ang) return;   // whole waves
         T *y = mode == 0 ? zcol<T>(d, k) : gfield<T>(d.q);
         forward_ray(gfield<const T>(d.xr), gfield<const T>(d.xc), y,
@@ -337,11 +394,17 @@ __global__ __launch_bounds__(256) void bfwd_kernel(const BatchInst *__restrict__
     });
 }
 
-// mode 0: AB, t = B w_k;  mode 1: BA, q = B z
-template <typename T, int AB>
-__global__ __launch_bounds__(kBackThreads) void bback_kernel(const BatchInst *__restrict__ D,
-                                                             const DevState *S, TabView tv,
-                                                             int t, int mode, Tiles tl)
+// mode 0: AB, t = B w_k;  mode 1: BA, q = B z. One kernel per back projector kind (their
+// lists are separate): with both kinds in one kernel it took 102-144 VGPRs and ran at
+// half the occupancy of the single-solve kernel. Launch bounds (waves per SIMD) at the
+// single-solve kernel's occupancy where the item loop still fits without spilling, for
+// 64 staged angles: the interpolating kind 8 (FP32, 64 VGPRs) and 6 (FP64, 80 VGPRs),
+// the matched pair 6 and 4. With 128 staged angles the LDS stage limits the occupancy.
+template <typename T, int AB, bool ADJ>
+constexpr int kBBackMinWaves = AB != 64 ? 1 : sizeof(T) == 4 ? (ADJ ? 6 : 8) : (ADJ ? 4 : 6);
+template <typename T, int AB, bool ADJ>
+__global__ __launch_bounds__(kBackThreads, (kBBackMinWaves<T, AB, ADJ>)) void bback_kernel(
+    const BatchInst *__restrict__ D, const DevState *S, TabView tv, int t, int mode, Tiles tl)
 {
     __shared__ BackLds<T, AB> lds;
     for_each_item(tv, t, tl.sched, [&](int slot, int local) {
@@ -354,10 +417,7 @@ __global__ __launch_bounds__(kBackThreads) void bback_kernel(const BatchInst *__
         const T *y = mode == 0 ? gfield<const T>(d.cur) : zcol<T>(d, k);
         T *x = mode == 0 ? gfield<T>(d.tn) : gfield<T>(d.q);
         const AngleParams *ang = gfield<const AngleParams>(d.ang);
-        if (d.kind == ABG_BP_ADJ)
-            back_tile<T, true, AB>(y, x, ang, d.N, d.n_ang, d.n_det, d.ds, d.s0, c0, r0, lds);
-        else
-            back_tile<T, false, AB>(y, x, ang, d.N, d.n_ang, d.n_det, d.ds, d.s0, c0, r0, lds);
+        back_tile<T, ADJ, AB>(y, x, ang, d.N, d.n_ang, d.n_det, d.ds, d.s0, c0, r0, lds);
     });
 }
 
@@ -432,7 +492,8 @@ __global__ __launch_bounds__(kBlock) void bres_kernel(const BatchInst *__restric
     __shared__ double cf[kMaxCoef];
     __shared__ double lds[kWaves];
     __shared__ int last;
-    for_each_item(tv, kTRes, tl.sched, [&](int slot, int c) {
+    // uniform chunks: static round-robin
+    for_each_item(tv, kTRes, 0, [&](int slot, int c) {
         const BatchInst &d = D[slot];
         DevState *st = S + slot;
         const int k = st->kcur;
@@ -606,8 +667,9 @@ struct Engine {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     bool dirty = true;
-    Tiles tiles{256, 128, 0};
-    int grid_proj = 0, grid_back = 0, grid_back64 = 0, grid_mgs_s = 0, grid_mgs_l = 0, grid_res = 0;
+    Tiles tiles{0, 64, 2};
+    int grid_proj = 0, grid_back = 0, grid_back64 = 0, grid_back_adj = 0, grid_back64_adj = 0;
+    int grid_mgs_s = 0, grid_mgs_l = 0, grid_res = 0;
     hipEvent_t tev[2] = {};
     int cap_mgs_s = 0, cap_mgs_l = 0, cap_mgs_x = 0, grid_mgs_x = 0, cap_mgs_h = 0, grid_mgs_h = 0;
     int broken = 0;
@@ -644,8 +706,14 @@ struct Engine {
     {
         hipError_t e;
         if ((e = capacity_of(bfwd_kernel<TX>, 256, &grid_proj)) != hipSuccess) return e;
-        if ((e = capacity_of(bback_kernel<TX, 128>, kBackThreads, &grid_back)) != hipSuccess) return e;
-        if ((e = capacity_of(bback_kernel<TX, 64>, kBackThreads, &grid_back64)) != hipSuccess) return e;
+        if ((e = capacity_of(bback_kernel<TX, 128, false>, kBackThreads, &grid_back)) != hipSuccess)
+            return e;
+        if ((e = capacity_of(bback_kernel<TX, 64, false>, kBackThreads, &grid_back64)) != hipSuccess)
+            return e;
+        if ((e = capacity_of(bback_kernel<TX, 128, true>, kBackThreads, &grid_back_adj)) != hipSuccess)
+            return e;
+        if ((e = capacity_of(bback_kernel<TX, 64, true>, kBackThreads, &grid_back64_adj)) != hipSuccess)
+            return e;
         if ((e = capacity_of(bmgs_kernel<TX, TV, kMgsSmallE>, kBlock, &cap_mgs_s)) != hipSuccess) return e;
         if ((e = capacity_of(bmgs_kernel<TX, TV, kMgsLargeE>, kBlock, &cap_mgs_l)) != hipSuccess) return e;
         if ((e = capacity_of(bmgs_kernel<TX, TV, 0>, kBlock, &cap_mgs_x)) != hipSuccess) return e;
@@ -671,12 +739,18 @@ struct Engine {
         return capacities<float, bf16>();
     }
 
+    // list t (interpolating back projector) and list t + 1 (its matched-pair twin)
     template <typename TX> void enqueue_back(hipStream_t q, const Tiles &tl, int t, int mode)
     {
-        if (tl.ang_block == 64)
-            bback_kernel<TX, 64><<<grid_back64, kBackThreads, 0, q>>>(d_desc, d_st, tv, t, mode, tl);
-        else
-            bback_kernel<TX, 128><<<grid_back, kBackThreads, 0, q>>>(d_desc, d_st, tv, t, mode, tl);
+        if (tl.ang_block == 64) {
+            bback_kernel<TX, 64, false><<<grid_back64, kBackThreads, 0, q>>>(d_desc, d_st, tv, t, mode, tl);
+            bback_kernel<TX, 64, true><<<grid_back64_adj, kBackThreads, 0, q>>>(d_desc, d_st, tv, t + 1,
+                                                                                mode, tl);
+        } else {
+            bback_kernel<TX, 128, false><<<grid_back, kBackThreads, 0, q>>>(d_desc, d_st, tv, t, mode, tl);
+            bback_kernel<TX, 128, true><<<grid_back_adj, kBackThreads, 0, q>>>(d_desc, d_st, tv, t + 1,
+                                                                               mode, tl);
+        }
     }
 
     // begin + the three projector phases (idempotent between rounds: they recompute the
@@ -797,6 +871,7 @@ struct Engine {
         d.count = v.count;
         d.bd_rel = (p.basis == ABG_F64 && p.proj == ABG_F64) ? 1e-14 : 1e-6;
         d.need_res = r.stop.kind == ABG_STOP_DP;
+        d.fwd_rays = 256 >> fwd_lg_angles_per_block(g);
         // Gram-Schmidt class: the smallest register tile whose block group the device
         // holds at once (the small tile while its group stays small), else the streaming
         // variant. A group must be resident as a whole: its size stays within the
@@ -888,9 +963,9 @@ struct Engine {
         }
         Tiles best = tiles;
         double bms = INFINITY;
-        for (int rays : {64, 128, 256})
+        for (int rays : {0, 64, 128, 256})
             for (int ab : {64, 128})
-            for (int sc : {0, 1}) {
+            for (int sc : {0, 1, 2}) {
                 const Tiles tl{rays, ab, sc};
                 double ms = 0.0;
                 int rc = time_projectors(tl, reps, &ms);
@@ -1138,9 +1213,9 @@ int engine_pending(const Engine *e) { return e->n_used() + (int)e->finished.size
 
 int engine_set_tiles(Engine *e, int rays, int ang_block, int sched)
 {
-    if (rays != 64 && rays != 128 && rays != 256) return ABG_EINVAL;
+    if (rays != 0 && rays != 64 && rays != 128 && rays != 256) return ABG_EINVAL;
     if (ang_block != 64 && ang_block != 128) return ABG_EINVAL;
-    if (sched != 0 && sched != 1) return ABG_EINVAL;
+    if (sched < 0 || sched > 2) return ABG_EINVAL;
     if (e->tiles.rays != rays || e->tiles.ang_block != ang_block || e->tiles.sched != sched) {
         e->tiles = Tiles{rays, ang_block, sched};
         e->dirty = true;

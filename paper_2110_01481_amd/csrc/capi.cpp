@@ -656,6 +656,13 @@ int abg_ncp_force_goertzel(int on)
     return ABG_OK;
 }
 
+int abg_fp_force_block_shape(int lg_angles)
+{
+    if (lg_angles < -1 || lg_angles > 2) return ABG_EINVAL;
+    fwd_force_block_shape(lg_angles);
+    return ABG_OK;
+}
+
 int abg_release_process_resources(void)
 {
     {

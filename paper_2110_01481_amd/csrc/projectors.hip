@@ -18,6 +18,7 @@
 //           projector's padded copies (AB-GMRES applies A right after B).
 #include <hip/hip_ext.h>
 
+#include <atomic>
 #include <mutex>
 
 #include "back_body.h"
@@ -45,30 +46,51 @@ __global__ void pad_zero_kernel(T *__restrict__ xr, T *__restrict__ xc, int N, i
     pad_zero_item(xr, xc, N, S, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
+// Block shape of the forward projectors: a block's four waves take 2^lg_apb consecutive
+// angles and 64 * 4 / 2^lg_apb consecutive rays of each (block (x, y): angles from
+// y * 2^lg_apb, rays from x times that width). Every wave walks its own rays; with several
+// angles per block the waves of a block walk nearly the same image rows at nearly the
+// same time (adjacent angles cross the same pixels), which keeps those rows in L2 while
+// they are reused. Waves past the last angle leave at once.
+struct FwdShape {
+    int lg_apb;
+    __device__ int wave_angle(int wave) const { return blockIdx.y * (1 << lg_apb) + (wave >> (2 - lg_apb)); }
+    __device__ int lane_ray(int wave) const
+    {
+        const int rays = kFwdBlock >> lg_apb;
+        return blockIdx.x * rays + (wave & ((4 >> lg_apb) - 1)) * 64 + ((int)threadIdx.x & 63);
+    }
+};
+
 template <typename T>
 __global__ __launch_bounds__(kFwdBlock) void forward_kernel(
     const T *__restrict__ xr, const T *__restrict__ xc, T *__restrict__ y,
-    const AngleParams *__restrict__ ang, int N, int S, int n_det, double ds, double s0,
-    const DevState *st, int k)
+    const AngleParams *__restrict__ ang, int N, int S, int n_ang, int n_det, double ds,
+    double s0, const DevState *st, int k, FwdShape sh)
 {
     if (halted(st, k)) return;
-    forward_ray(xr, xc, y, ang, blockIdx.y, blockIdx.x * kFwdBlock + threadIdx.x, N, S, n_det,
-                ds, s0);
+    const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+    const int a = sh.wave_angle(wave);
+    if (a >= n_ang) return;
+    forward_ray(xr, xc, y, ang, a, sh.lane_ray(wave), N, S, n_det, ds, s0);
 }
 
 // Strip (MODEL = ABG_FP_STRIP) and interpolation (ABG_FP_JOSEPH) models.
 template <typename T, int MODEL>
 __global__ __launch_bounds__(kFwdBlock) void forward_model_kernel(
     const T *__restrict__ xr, const T *__restrict__ xc, T *__restrict__ y,
-    const AngleParams *__restrict__ ang, int N, int S, int n_det, double ds, double s0,
-    const DevState *st, int k)
+    const AngleParams *__restrict__ ang, int N, int S, int n_ang, int n_det, double ds,
+    double s0, const DevState *st, int k, FwdShape sh)
 {
     if (halted(st, k)) return;
-    const int i = blockIdx.x * kFwdBlock + threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+    const int a = sh.wave_angle(wave);
+    if (a >= n_ang) return;
+    const int i = sh.lane_ray(wave);
     if constexpr (MODEL == ABG_FP_STRIP)
-        forward_ray_strip(xr, xc, y, ang, blockIdx.y, i, N, S, n_det, ds, s0);
+        forward_ray_strip(xr, xc, y, ang, a, i, N, S, n_det, ds, s0);
     else
-        forward_ray_joseph(xr, xc, y, ang, blockIdx.y, i, N, S, n_det, ds, s0);
+        forward_ray_joseph(xr, xc, y, ang, a, i, N, S, n_det, ds, s0);
 }
 
 // 64 angles staged per round: the smaller LDS footprint lets more blocks share a CU
@@ -76,9 +98,6 @@ __global__ __launch_bounds__(kFwdBlock) void forward_model_kernel(
 constexpr int kSingleAngBlock = 64;
 
 // PAD: x is the forward projector's scratch (padded copies written directly).
-// FP32: at most 64 VGPRs, so that four blocks (eight waves per SIMD) share a CU
-template <typename T> constexpr int kBackMinWaves = 1;
-template <> constexpr int kBackMinWaves<float> = 8;
 
 // Transposes of the strip and interpolation models (KIND ABG_BP_STRIP_T / _JOSEPH_T) and
 // the thresholded strip transpose (ABG_BP_STRIP_TAU, entries below tau_thr dropped).
@@ -124,7 +143,9 @@ hipError_t forward_t(const Geometry &g, const void *x, void *y, void *ws, hipStr
             pad_zero_kernel<T><<<(npad + 255) / 256, 256, 0, s>>>(xr, xc, N, S, st, k);
         }
     }
-    dim3 grid((g.n_det + kFwdBlock - 1) / kFwdBlock, g.n_ang);
+    const FwdShape sh{fwd_lg_angles_per_block(g)};
+    const int apb = 1 << sh.lg_apb, rays = kFwdBlock >> sh.lg_apb;
+    dim3 grid((g.n_det + rays - 1) / rays, (g.n_ang + apb - 1) / apb);
     const double s0 = -0.5 * (g.n_det - 1) * g.ds;
     {
         // timed at the kernel's own start and end when profiling is on
@@ -134,7 +155,8 @@ hipError_t forward_t(const Geometry &g, const void *x, void *y, void *ws, hipStr
                                              : forward_kernel<T>;
         hipExtLaunchKernelGGL(fn, grid, dim3(kFwdBlock), 0, s, ps.e0, ps.e1, 0,
                               (const T *)xr, (const T *)xc, static_cast<T *>(y),
-                              (const AngleParams *)g.dev, N, S, g.n_det, g.ds, s0, st, k);
+                              (const AngleParams *)g.dev, N, S, g.n_ang, g.n_det, g.ds, s0, st,
+                              k, sh);
     }
     return hipGetLastError();
 }
@@ -168,6 +190,31 @@ hipError_t back_t(const Geometry &g, int kind, const void *y, void *x, hipStream
 }
 
 }  // namespace
+
+namespace {
+std::atomic<int> g_fwd_force_lg{-1};
+}  // namespace
+
+
+// Angles per block of the forward projectors (log2), from measurements on gfx950 (all
+// shapes give the same bits). Four angles per block pay from N = 768 up: the 4 MB L2 of
+// an XCD holds only about three band steps of the rows its resident waves read, so rows
+// are reused only by waves walking nearly the same rows at nearly the same time -- the
+// waves of one block at adjacent angles (FP64: 9% faster at 768^2, 27% at 2048^2, 42% at
+// 1536^2; FP32 1-3%). Smaller images stay in L2 anyway; there one angle per block is
+// faster (its rays share each band's cache lines within a wave) unless the last block of
+// each angle leaves more lanes idle than blocks of two angles would (n_det = 363: 512
+// lanes against 384, two angles 6-8% faster).
+int fwd_lg_angles_per_block(const Geometry &g)
+{
+    const int forced = g_fwd_force_lg.load(std::memory_order_relaxed);
+    if (forced >= 0) return forced;
+    if (g.N > 640) return 2;
+    const long long lanes1 = (g.n_det + 255LL) / 256 * 256, lanes2 = (g.n_det + 127LL) / 128 * 128;
+    return lanes2 < lanes1 ? 1 : 0;
+}
+
+void fwd_force_block_shape(int lg_apb) { g_fwd_force_lg.store(lg_apb >= 0 && lg_apb <= 2 ? lg_apb : -1); }
 
 size_t fp_workspace_bytes(const Geometry &g, int dtype)
 {

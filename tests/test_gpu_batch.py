@@ -157,7 +157,8 @@ def test_workspace_contents_do_not_matter(gpu_lib, mix, fill):
         assert s1.k_stop == s2.k_stop and torch.equal(s1.x, s2.x), (i, fill)
 
 
-@pytest.mark.parametrize("rays,ang_block,sched", [(64, 128, 0), (128, 64, 1), (256, 64, 1)])
+@pytest.mark.parametrize("rays,ang_block,sched", [(64, 128, 0), (128, 64, 1), (256, 64, 1),
+                                                  (0, 64, 0), (64, 128, 2), (256, 64, 2)])
 def test_tile_shape_does_not_change_results(gpu_lib, mix, rays, ang_block, sched):
     import torch
     abg = gpu_lib
@@ -178,8 +179,8 @@ def test_autotuner_picks_a_shape_and_caches_it(gpu_lib, mix, tmp_path):
     eng = abg.Engine(proj="f32", basis="f32", max_slots=len(mix))
     tags = [eng.submit(c.problem(abg, torch.float32)) for c in mix]
     t = eng.autotune(reps=2, cache=cache)
-    assert t["rays"] in (64, 128, 256) and t["ang_block"] in (64, 128) and t["ms"] > 0
-    assert t["sched"] in (0, 1)
+    assert t["rays"] in (0, 64, 128, 256) and t["ang_block"] in (64, 128) and t["ms"] > 0
+    assert t["sched"] in (0, 1, 2)
     assert not t["cached"] and eng.get_tiles() == (t["rays"], t["ang_block"], t["sched"])
     done = {}
     while len(done) < len(tags):

@@ -82,6 +82,35 @@ def test_gpu_adjoint_identity(gpu_lib, kw):
     assert abs(lhs - rhs) <= 1e-12 * (abs(lhs) + abs(rhs))
 
 
+@pytest.mark.parametrize("kw", GEOMS + [dict(N=512, n_ang=7, n_det=725), dict(N=1030, n_ang=6, n_det=1459)],
+                         ids=_ids)
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_forward_block_shapes_bit_identical(gpu_lib, kw, dt):
+    """The forward projectors' block shapes (one, two or four angles per block) change
+    only which rays run together: every model gives bit-identical sinograms for every
+    shape, on ragged angle counts (waves past the last angle) and ragged detector rows.
+    The automatic shape is four angles per block for the 1030^2 geometry, two for
+    n_det = 91, 183 or 300, one for the others."""
+    import torch
+    import paper_2110_01481_amd as abg
+    tdt = torch.float64 if dt == "f64" else torch.float32
+    rng = np.random.default_rng(5)
+    x = torch.tensor(rng.uniform(size=kw["N"] ** 2), dtype=tdt, device="cuda")
+    try:
+        for model in ("line", "strip", "joseph"):
+            if model == "strip" and kw.get("det_spacing", 1.0) > 1.4:
+                continue
+            gg = abg.Geometry(**kw, model=model)
+            abg.fp_force_block_shape(-1)
+            auto = gg.fp(x)
+            for lg in (0, 1, 2):
+                abg.fp_force_block_shape(lg)
+                assert torch.equal(gg.fp(x), auto), (model, lg)
+            gg.close()
+    finally:
+        abg.fp_force_block_shape(-1)
+
+
 def test_forward_deterministic_and_stream_ordered(gpu_lib):
     import torch
     _, gg = _pair(dict(N=128, n_ang=64, n_det=183))
