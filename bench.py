@@ -691,11 +691,12 @@ def bench_batched(abg, torch, dev, reps=3):
             "max_rel_diff_vs_fp64": float(f"{err:.3g}")}
 
 
-def bench_serving(abg, torch, dev, seconds, bases, tiles, single_sample=24):
+def bench_serving(abg, torch, dev, seconds, bases, single_sample=160):
     """Poisson request stream (50/s; N in {256..2048}, 180-1800 angles, AB/BA, k_max in
     [30,120], DP) through the continuous-batching server under a 200 GB workspace budget,
-    in real time and as a closed batch, per basis dtype; the plain FP64 single-solve rate
-    on the first requests for comparison."""
+    in real time and as a closed batch, per basis dtype; for comparison, the first
+    `single_sample` requests as a closed batch and solved one by one (plain FP64 and FP32
+    single solves)."""
     from paper_2110_01481_amd.serving import Request, Server
     stream = W.serving_requests(rate=50.0, duration=seconds)
     pool = {N: [torch.tensor(W.ellipse_phantom(N, 10, W.rng(5, 100000 + 10 * N + j, 0)).ravel(),
@@ -723,11 +724,18 @@ def bench_serving(abg, torch, dev, seconds, bases, tiles, single_sample=24):
                               "closed_batch_reconstructions_per_s": round(closed.completed_per_s, 2),
                               "tuned_on_first_32": {k: tuned[k] for k in ("rays", "ang_block", "sched")}}
     sample = [r.problem for r in reqs[:single_sample]]
+    srv = Server(proj="f32", basis="f32", max_slots=256, budget_bytes=200e9)
+    srv.tune(sample[:32])
+    srv.run(reqs[:single_sample], realtime=False)   # warm-up
+    eng = srv.run(reqs[:single_sample], realtime=False)
+    srv.close()
+    _single_solves(abg, torch, sample[:8], torch.float32)   # warm-up
     t64, _ = _single_solves(abg, torch, sample, torch.float64)
     t32, _ = _single_solves(abg, torch, sample, torch.float32)
-    out["single_fp64_recon_per_s"] = round(len(sample) / t64, 2)
-    out["single_fp32_recon_per_s"] = round(len(sample) / t32, 2)
-    out["single_sample"] = f"first {len(sample)} requests, solved one by one"
+    out["sample"] = {"requests": f"the first {len(sample)} requests",
+                     "engine_fp32_closed_batch_recon_per_s": round(eng.completed_per_s, 2),
+                     "single_fp32_recon_per_s": round(len(sample) / t32, 2),
+                     "single_fp64_recon_per_s": round(len(sample) / t64, 2)}
     return out
 
 
@@ -834,7 +842,7 @@ def roofline_of(prof, w, proj: str, tag: str):
     names = {"forward": f"forward_kernel<{'double' if proj == 'f64' else 'float'}> (ray-driven "
                         f"line model A, {proj.upper()})",
              "back": f"back_kernel (pixel-driven unmatched B, {proj.upper()})",
-             "ncp": "ncp_rows/mean/final kernels (periodogram of every sinogram row, FP64)",
+             "ncp": "ncp_fft_rows/colsum/dist/final kernels (periodogram of every sinogram row, FP64)",
              "mgs": "mgs kernels (Gram-Schmidt + Givens)", "combine": "combine_kernel"}
     roof = {"kernel": names[dominant], "avg_launch_ms": round(avg_ms, 4),
             "share_of_kernel_time": round(ms / sum(share.values()), 4)}
@@ -1052,16 +1060,13 @@ def run_bench(args, abg, torch):
     if not args.quick and args.config != 1:
         extra["workload_512"] = bench_512(args, abg, torch, dev)
 
-    tiles = None
     if not args.quick and not args.no_batch:
         progress("batched mix")
         extra["batched"] = bench_batched(abg, torch, dev)
         progress("batched mix done")
-        tiles = (extra["batched"]["tiles"]["rays"], extra["batched"]["tiles"]["ang_block"],
-                 extra["batched"]["tiles"]["sched"])
     if not args.quick and args.serve_seconds > 0:
         extra["serving"] = bench_serving(abg, torch, dev, args.serve_seconds,
-                                         [b for b in args.serve_basis.split(",") if b], tiles)
+                                         [b for b in args.serve_basis.split(",") if b])
 
     cpu = None
     if not args.quick and not args.no_cpu_baseline:
