@@ -80,19 +80,21 @@ template <typename T> struct BandWeights {
 };
 
 template <> struct Band<double> {
+    // lo: the band's lower minor-axis edge in padded column coordinates (+ kPad), so that
+    // floor(lo) is the padded column itself
     double lo, m;
-    __device__ Band(double lo0, double m_) : lo(lo0), m(m_) {}
+    __device__ Band(double lo0, double m_) : lo(lo0 + kPad), m(m_) {}
     __device__ void next() { lo += m; }
     __device__ unsigned column(unsigned cmax) const
     {
-        return min((unsigned)((int)floor(lo) + kPad), cmax);
+        return min((unsigned)(int)floor(lo), cmax);
     }
-    // padded column, unclamped; far outside the image it is clamped to +-2^30 so that the
-    // byte offset cannot wrap back into the row
-    __device__ int column_raw() const
-    {
-        return (int)fmin(fmax(floor(lo) + kPad, -0x1p30), 0x1p30);
-    }
+    // padded column, unclamped. A wave walks only the bands some lane's ray crosses
+    // (at most N of them, |m| <= 1), and the lanes of a wave lie within 63 bins of each
+    // other (63 * 64 * sqrt(2) < 5702 px for the spacings a geometry accepts), so every
+    // column a walking lane reaches is below 2N + 5710 < 2^17 in magnitude (N <= 32768):
+    // the conversion is exact and the byte offset cannot wrap back into the row.
+    __device__ int column_raw() const { return (int)floor(lo); }
     // length of the band segment left of the pixel edge at floor(lo) + 1
     __device__ double left_length(const BandWeights<double> &b) const
     {
