@@ -103,6 +103,9 @@ __device__ inline bool halted(const DevState *st, int k)
 // allocated with a length rounded up to a multiple of kVecPad elements, zero past their
 // logical length, so that every register tile of the MGS kernels lies inside them.
 constexpr long long kVecPad = 16384;
+// Data format word of a raw gfx9 buffer resource (projector loads through
+// __builtin_amdgcn_make_buffer_rsrc: offsets past the resource's size read zero).
+constexpr int kRawBufferFlags = 0x00020000;
 // Longer vectors may not fit the registers of one resident block group: their solves
 // carry an FP64 scratch copy of q_k for the streaming Gram-Schmidt variant.
 constexpr long long kRegMaxL = 2 * 1024 * 1024;

@@ -67,6 +67,15 @@ template <typename T> __device__ inline T fract_of(T u);
 template <> __device__ inline float fract_of<float>(float u) { return __builtin_amdgcn_fractf(u); }
 template <> __device__ inline double fract_of<double>(double u) { return __builtin_amdgcn_fract(u); }
 
+// One element at byte offset `off` of a raw buffer resource (zero past its size).
+template <typename T> __device__ inline T buffer_elem(__amdgpu_buffer_rsrc_t r, unsigned off)
+{
+    if constexpr (sizeof(T) == 4)
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+    else
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+}
+
 // Staged window entry: the bin's value and the difference to the next bin.
 template <typename T> struct alignas(2 * sizeof(T)) BinPair {
     T v, d;
@@ -213,6 +222,17 @@ __device__ inline void back_tile(const T *__restrict__ y, T *__restrict__ x,
     };
     T w0[kIt], w1[kIt];
     unsigned live = 0;                                 // in-range bits of w0 / w1
+    // While the sinogram's bytes fit a 31-bit offset, one buffer resource spans it: the
+    // window loads take 32-bit element offsets instead of clamped 64-bit addresses. An
+    // element index is clamped below at 0 (only row 0's bins left of the detector are
+    // negative) and reads past the sinogram's end return zero; offsets never wrap (the
+    // range check would see a wrapped offset as out of range once the compiler moves a
+    // constant part into the instruction's offset field). Bins outside their row are
+    // zeroed through `live` like every out-of-range bin.
+    const size_t ybytes = (size_t)n_ang * (size_t)n_det * sizeof(T);
+    const bool whole_y = ybytes < 0x80000000ull;
+    const __amdgpu_buffer_rsrc_t ry = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<T *>(y), (short)0, whole_y ? (int)ybytes : 0, kRawBufferFlags);
     auto load = [&](int r) {
         const int a0 = r * AB, last = min(AB, n_ang - a0) - 1;
         live = 0;
@@ -220,11 +240,17 @@ __device__ inline void back_tile(const T *__restrict__ y, T *__restrict__ x,
         for (int j = 0; j < kIt; ++j) {
             const int t = min((int)threadIdx.x / kWin + j * kRowsPer, last);
             const int bin = L.ib[r & 1][t] + kk;
-            const T *row = y + (size_t)(a0 + t) * n_det;
-            w0[j] = row[min(max(bin, 0), n_det - 1)];
-            w1[j] = row[min(max(bin + 1, 0), n_det - 1)];
-            live |= (unsigned)(bin >= 0 && bin < n_det) << (2 * j);
-            live |= (unsigned)(bin + 1 >= 0 && bin + 1 < n_det) << (2 * j + 1);
+            if (whole_y) {
+                const int e = (a0 + t) * n_det + bin;
+                w0[j] = buffer_elem<T>(ry, (unsigned)max(e, 0) * (unsigned)sizeof(T));
+                w1[j] = buffer_elem<T>(ry, (unsigned)max(e + 1, 0) * (unsigned)sizeof(T));
+            } else {
+                const T *row = y + (size_t)(a0 + t) * n_det;
+                w0[j] = row[min(max(bin, 0), n_det - 1)];
+                w1[j] = row[min(max(bin + 1, 0), n_det - 1)];
+            }
+            live |= (unsigned)((unsigned)bin < (unsigned)n_det) << (2 * j);
+            live |= (unsigned)((unsigned)(bin + 1) < (unsigned)n_det) << (2 * j + 1);
         }
     };
     auto store = [&]() {

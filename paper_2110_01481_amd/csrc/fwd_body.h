@@ -157,8 +157,7 @@ __device__ inline Taps<T> load_taps(const T *row, unsigned col)
 // The same two taps through a buffer resource spanning exactly one padded row of S
 // elements: the hardware range check returns zero for a column outside the row (a lane
 // walking bands outside its own chord, negative columns included, as their unsigned byte
-// offset is huge), so the walk needs no clamp. Data format word of a raw gfx9 buffer.
-constexpr int kRawBufferFlags = 0x00020000;
+// offset is huge), so the walk needs no clamp.
 template <typename T>
 __device__ inline Taps<T> load_taps_row(const T *row, int S, int col)
 {
