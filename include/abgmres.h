@@ -306,7 +306,8 @@ int abg_engine_destroy(abg_engine *e);
 /* Adds a problem. Its buffers (b, x0, x, ws) belong to the engine until abg_engine_poll
  * has returned its tag. Enqueues the initialisation (r_0, beta, w_1) without waiting.
  * Returns ABG_EFULL when no slot is free, ABG_EINVAL on bad arguments (including a basis
- * vector too long for one block group). */
+ * vector too long for one block group, or a sinogram of 2 GiB or more in the projector
+ * dtype: the engine's back projector addresses it with 31-bit offsets). */
 int abg_engine_submit(abg_engine *e, const abg_request *r);
 
 /* Runs one round: enqueues one Arnoldi step of every running problem and processes the

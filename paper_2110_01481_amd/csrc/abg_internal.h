@@ -106,6 +106,9 @@ constexpr long long kVecPad = 16384;
 // Data format word of a raw gfx9 buffer resource (projector loads through
 // __builtin_amdgcn_make_buffer_rsrc: offsets past the resource's size read zero).
 constexpr int kRawBufferFlags = 0x00020000;
+// The back projectors read the sinogram through one buffer resource when its bytes fit a
+// 31-bit offset (batched problems must; single applies fall back to clamped addresses).
+inline bool sinogram_fits_offset(long long m, size_t elem) { return (size_t)m * elem < 0x80000000ull; }
 // Longer vectors may not fit the registers of one resident block group: their solves
 // carry an FP64 scratch copy of q_k for the streaming Gram-Schmidt variant.
 constexpr long long kRegMaxL = 2 * 1024 * 1024;

@@ -23,10 +23,13 @@ template <> __device__ inline float edge_tie<float>() { return 2e-5f; }
 constexpr int kTile = 16;
 constexpr int kBackWaves = 8;
 constexpr int kBackThreads = 64 * kBackWaves;
-// Launch bound (waves per SIMD) of the back projector kernels: in FP32 at most 64 VGPRs,
-// so that four blocks (eight waves per SIMD) share a CU.
-template <typename T> constexpr int kBackMinWaves = 1;
-template <> constexpr int kBackMinWaves<float> = 8;
+// Launch bound (waves per SIMD) of the back projector kernels: the interpolating kind in
+// FP32 at most 64 VGPRs (four blocks, eight waves per SIMD, share a CU), in FP64 at most
+// 80 (six waves); the matched kind's FP64 trapezoid needs more registers than that
+// without spilling.
+template <typename T, bool ADJ = false> constexpr int kBackMinWaves = ADJ ? 1 : 6;
+template <> constexpr int kBackMinWaves<float, false> = 8;
+template <> constexpr int kBackMinWaves<float, true> = 8;
 constexpr int kPixPerLane = kTile * kTile / 64;
 constexpr int kAngBlock = 128;
 constexpr int kWin = 32;
@@ -177,7 +180,11 @@ __device__ inline void tile_store(const T (&acc)[kPixPerLane], T (*part)[kTile *
 // PAD: instead of x, the tile goes to the forward projector's zero-padded row-major and
 // transposed copies xr, xc (row stride S, image column c at c + kPad; the padding must
 // already be zero), through LDS so that both writes are coalesced.
-template <typename T, bool ADJ, int AB = kAngBlock, bool PAD = false>
+//
+// WY: the sinogram's bytes fit a 31-bit offset (the caller checks), so that the window
+// loads go through one buffer resource over the whole sinogram (below); otherwise they
+// clamp 64-bit addresses into the row.
+template <typename T, bool ADJ, int AB = kAngBlock, bool PAD = false, bool WY = true>
 __device__ inline void back_tile(const T *__restrict__ y, T *__restrict__ x,
                                  const AngleParams *__restrict__ ang, int N, int n_ang,
                                  int n_det, double ds, double s0, int c0, int r0,
@@ -194,7 +201,7 @@ __device__ inline void back_tile(const T *__restrict__ y, T *__restrict__ x,
     const int tx = lane & 15, ty0 = lane >> 4;
     const double xref = c0 - 0.5 * N + 0.5, yref = r0 - 0.5 * N + 0.5;
     const double s0u = s0 / ds;
-    const T ftx = T(tx), fty = T(ty0);
+    T ftx = T(tx), fty = T(ty0);
     const T dsT = T(ds);
     const int n_rounds = (n_ang + AB - 1) / AB;
     const int kk = threadIdx.x % kWin;                 // this thread's window column
@@ -222,17 +229,16 @@ __device__ inline void back_tile(const T *__restrict__ y, T *__restrict__ x,
     };
     T w0[kIt], w1[kIt];
     unsigned live = 0;                                 // in-range bits of w0 / w1
-    // While the sinogram's bytes fit a 31-bit offset, one buffer resource spans it: the
-    // window loads take 32-bit element offsets instead of clamped 64-bit addresses. An
-    // element index is clamped below at 0 (only row 0's bins left of the detector are
-    // negative) and reads past the sinogram's end return zero; offsets never wrap (the
-    // range check would see a wrapped offset as out of range once the compiler moves a
-    // constant part into the instruction's offset field). Bins outside their row are
-    // zeroed through `live` like every out-of-range bin.
-    const size_t ybytes = (size_t)n_ang * (size_t)n_det * sizeof(T);
-    const bool whole_y = ybytes < 0x80000000ull;
+    // WY: one buffer resource spans the sinogram, and the window loads take 32-bit
+    // element offsets instead of clamped 64-bit addresses. An element index is clamped
+    // below at 0 (only row 0's bins left of the detector are negative) and reads past the
+    // sinogram's end return zero; offsets never wrap (the range check would see a wrapped
+    // offset as out of range once the compiler moves a constant part into the
+    // instruction's offset field). Bins outside their row are zeroed through `live` like
+    // every out-of-range bin.
     const __amdgpu_buffer_rsrc_t ry = __builtin_amdgcn_make_buffer_rsrc(
-        const_cast<T *>(y), (short)0, whole_y ? (int)ybytes : 0, kRawBufferFlags);
+        const_cast<T *>(y), (short)0, WY ? (int)((size_t)n_ang * (size_t)n_det * sizeof(T)) : 0,
+        kRawBufferFlags);
     auto load = [&](int r) {
         const int a0 = r * AB, last = min(AB, n_ang - a0) - 1;
         live = 0;
@@ -240,7 +246,7 @@ __device__ inline void back_tile(const T *__restrict__ y, T *__restrict__ x,
         for (int j = 0; j < kIt; ++j) {
             const int t = min((int)threadIdx.x / kWin + j * kRowsPer, last);
             const int bin = L.ib[r & 1][t] + kk;
-            if (whole_y) {
+            if constexpr (WY) {
                 const int e = (a0 + t) * n_det + bin;
                 w0[j] = buffer_elem<T>(ry, (unsigned)max(e, 0) * (unsigned)sizeof(T));
                 w1[j] = buffer_elem<T>(ry, (unsigned)max(e + 1, 0) * (unsigned)sizeof(T));
@@ -281,6 +287,9 @@ __device__ inline void back_tile(const T *__restrict__ y, T *__restrict__ x,
         if (r + 1 < n_rounds) load(r + 1);
         // the block's waves take interleaved angles of the round
         for (int t = wave; t < na; t += kBackWaves) {
+            // FP64: keep the lane's pixel coordinates in registers (rematerialising them
+            // costs two FP64 conversions per angle)
+            if constexpr (sizeof(T) == 8) asm volatile("" : "+v"(ftx), "+v"(fty));
             const BackStage<T> P = L.prm[r & 1][t];
             const T u0 = fma(ftx, P.cu, fma(fty, P.su, P.f));
             back_tap<T, ADJ>(acc[0], L.win[t], u0, P, dsT);

@@ -830,6 +830,8 @@ struct Engine {
                 break;
             }
         if (sidx < 0) return ABG_EFULL;
+        // the back projector's window loads address the sinogram with 31-bit offsets
+        if (!sinogram_fits_offset(g.m(), dtype_size(p.proj))) return ABG_EINVAL;
         const InstanceView v = instance_view(g, r.method, r.k_max, p, r.stop, r.ws);
         BatchInst d{};
         d.ang = g.dev;

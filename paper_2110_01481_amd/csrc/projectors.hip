@@ -114,17 +114,18 @@ __global__ __launch_bounds__(kBackThreads) void back_model_kernel(
                                                x + (size_t)N * S, S, tau_thr);
 }
 
-template <typename T, bool ADJ, bool PAD>
-__global__ __launch_bounds__(kBackThreads, kBackMinWaves<T>) void back_kernel(
+// WY: the sinogram's bytes fit a 31-bit offset (window loads through one buffer resource).
+template <typename T, bool ADJ, bool PAD, bool WY>
+__global__ __launch_bounds__(kBackThreads, (kBackMinWaves<T, ADJ>)) void back_kernel(
     const T *__restrict__ y, T *__restrict__ x, const AngleParams *__restrict__ ang, int N,
     int n_ang, int n_det, double ds, double s0, const DevState *st, int k)
 {
     __shared__ BackLds<T, kSingleAngBlock> lds;
     if (halted(st, k)) return;
     const int S = N + 2 * kPad;
-    back_tile<T, ADJ, kSingleAngBlock, PAD>(y, x, ang, N, n_ang, n_det, ds, s0,
-                                            blockIdx.x * kTile, blockIdx.y * kTile, lds, x,
-                                            x + (size_t)N * S, S);
+    back_tile<T, ADJ, kSingleAngBlock, PAD, WY>(y, x, ang, N, n_ang, n_det, ds, s0,
+                                                blockIdx.x * kTile, blockIdx.y * kTile, lds, x,
+                                                x + (size_t)N * S, S);
 }
 
 // x == nullptr: the padded copies in ws already hold the input.
@@ -178,14 +179,12 @@ hipError_t back_t(const Geometry &g, int kind, const void *y, void *x, hipStream
                               g.tau_thr, st, k);
         return hipGetLastError();
     }
-    if (kind == ABG_BP_ADJ)
-        hipExtLaunchKernelGGL(back_kernel<T, true, PAD>, grid, dim3(kBackThreads), 0, s, ps.e0,
-                              ps.e1, 0, static_cast<const T *>(y), static_cast<T *>(x),
-                              (const AngleParams *)g.dev, g.N, g.n_ang, g.n_det, g.ds, s0, st, k);
-    else
-        hipExtLaunchKernelGGL(back_kernel<T, false, PAD>, grid, dim3(kBackThreads), 0, s, ps.e0,
-                              ps.e1, 0, static_cast<const T *>(y), static_cast<T *>(x),
-                              (const AngleParams *)g.dev, g.N, g.n_ang, g.n_det, g.ds, s0, st, k);
+    const bool wy = sinogram_fits_offset(g.m(), sizeof(T));
+    auto fn = kind == ABG_BP_ADJ ? (wy ? back_kernel<T, true, PAD, true> : back_kernel<T, true, PAD, false>)
+                                 : (wy ? back_kernel<T, false, PAD, true> : back_kernel<T, false, PAD, false>);
+    hipExtLaunchKernelGGL(fn, grid, dim3(kBackThreads), 0, s, ps.e0, ps.e1, 0,
+                          static_cast<const T *>(y), static_cast<T *>(x),
+                          (const AngleParams *)g.dev, g.N, g.n_ang, g.n_det, g.ds, s0, st, k);
     return hipGetLastError();
 }
 
