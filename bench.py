@@ -39,9 +39,9 @@ COUNTER_KERNELS = {
                            [_CSRC + "fwd_body.h", _CSRC + "geometry.h", _CSRC + "projectors.hip"]),
     "forward_kernel_f64": ("forward_kernel<double>",
                            [_CSRC + "fwd_body.h", _CSRC + "geometry.h", _CSRC + "projectors.hip"]),
-    "back_kernel_f64": ("back_kernel<double, false, false>",
+    "back_kernel_f64": ("back_kernel<double, false, false, true>",
                         [_CSRC + "back_body.h", _CSRC + "geometry.h", _CSRC + "projectors.hip"]),
-    "back_kernel_f32": ("back_kernel<float, false, false>",
+    "back_kernel_f32": ("back_kernel<float, false, false, true>",
                         [_CSRC + "back_body.h", _CSRC + "geometry.h", _CSRC + "projectors.hip"]),
 }
 # kernels of a solve whose L2 hit rate the TCC pass reports

@@ -70,15 +70,31 @@ def test_plain_fp64_thirty_iterations(gpu_lib, cfg1, method, kind):
     err = _rel(x, ref.x)
     print(f"{method}-{kind} k=30 FP64 rel err {err:.2e} (bound {tol:.1e})")
     assert err <= tol
-    # Late Hessenberg columns are ill-conditioned functions of the data (a 1e-13
-    # perturbation of b moves column 25 by O(100) in the oracle itself), so H is
-    # compared on its first 15 columns; the GMRES residual history on all 30.
-    dH = np.abs(r.H[:, :15] - ref.H[:, :15])
-    assert dH.max() <= 1e-8 * np.abs(ref.H).max(), np.unravel_index(np.argmax(dH), dH.shape)
-    # Around k = 24 this problem is ill-conditioned: in the oracle itself a 1e-15
-    # relative change of b moves the residual at k = 24 by ~2e-4 (and x_24 by ~3e-4)
-    # before x recovers by k = 29, so the residual history is compared up to k = 20.
-    assert np.allclose(r.ls_hist[:20], ref.ls_res[:20], rtol=1e-7, atol=0)
+    # Every column of H and every step of the GMRES residual history, each against a
+    # bound from a probe of the oracle itself: the change a 1e-13 relative perturbation
+    # of b causes there (largest over +-3 neighbouring columns / steps, since one
+    # direction samples a spike), times 1e3, at least 1e-8 (H, relative to max |H|) and
+    # 1e-7 (history, relative). Late columns are ill-conditioned functions of the data
+    # (the probe moves column 25 by O(100) and the residual at k = 24 by ~2e-4), and
+    # their bounds say so; the early ones are held at the rounding level.
+    d = np.random.default_rng(3).standard_normal(b.size)
+    pert = f(go.A, go.back(kind), b + 1e-13 * np.linalg.norm(b) * d / np.linalg.norm(d), 30,
+             keep_iterates=True)
+    hmax = np.abs(ref.H).max()
+    near = lambda v: np.array([v[max(0, j - 3):j + 4].max() for j in range(v.size)])  # noqa: E731
+    sH = near(np.abs(pert.H - ref.H).max(axis=0) / hmax)
+    dH = np.abs(r.H - ref.H).max(axis=0) / hmax
+    bH = np.maximum(1e-8, 1e3 * sH)
+    j = int(np.argmax(dH / bH))
+    print(f"H: worst column {j + 1}: {dH[j]:.2e} of max|H| (bound {bH[j]:.1e})")
+    assert np.all(dH <= bH), (j + 1, dH[j], bH[j])
+    ls_ref = np.asarray(ref.ls_res)
+    sL = near(np.abs(np.asarray(pert.ls_res) / ls_ref - 1.0))
+    dL = np.abs(np.asarray(r.ls_hist) / ls_ref - 1.0)
+    bL = np.maximum(1e-7, 1e3 * sL)
+    k = int(np.argmax(dL / bL))
+    print(f"residual history: worst step {k + 1}: {dL[k]:.2e} (bound {bL[k]:.1e})")
+    assert np.all(dL <= bL), (k + 1, dL[k], bL[k])
     assert abs(r.res_norm - ref.res_norms[-1]) <= 1e-8 * ref.res_norms[-1]
 
 
