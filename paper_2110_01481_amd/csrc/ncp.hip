@@ -1,6 +1,6 @@
 // NCP stopping criterion (Sec. 6.3) on gfx950.
 //
-// For each sinogram row of the residual (one block per row): the periodogram
+// For each sinogram row of the residual: the periodogram
 // p_j = |DFT_j|^2, j = 1..q = floor(n_det/2), then the normalised cumulative sum
 // c(j) = sum_{l<=j} p_l / sum_{l<=q} p_l. Two more kernels average c over the rows per j
 // (column sums over chunks of rows, then the chunks in order) and form the distance to
@@ -10,8 +10,10 @@
 // Bluestein's chirp transform: with c_i = exp(-pi i i^2/n), 2ij = i^2 + j^2 - (j-i)^2
 // gives X_j = c_j sum_i (r_i c_i) conj(c_{j-i}), a linear convolution of length 2n-1,
 // done cyclically with two power-of-two FFTs of length M >= 2n-1 held in LDS (M <= 8192:
-// 128 KB of complex FP64). |c_j| = 1, so p_j = |convolution_j|^2 and the final chirp is
-// not needed; the 1/M of the inverse transform cancels in the normalisation. The
+// 128 KB of complex FP64). One block transforms two rows at once, packed as the real and
+// imaginary part of one complex row (the rows are real; their spectra are separated by
+// conjugate symmetry after the final chirp); the 1/M of the inverse transform cancels in
+// the normalisation. The
 // transform of the fixed chirp kernel conj(c_t), the chirp c_i and the twiddle factors
 // are computed once per geometry on the host (FP64) and kept on the device. Short rows
 // (n < 64) and rows too long for LDS use Goertzel's recurrence per frequency instead
@@ -171,28 +173,47 @@ __global__ void ncp_final_kernel(const double *partials, int nb, DevState *st, i
 constexpr int kFftThreads = 512;
 constexpr int kFftMaxM = 8192;
 
+__device__ inline double2 cmul(double2 a, double2 b)
+{
+    return make_double2(fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x));
+}
+
+// Rows 2b and 2b + 1 of the sinogram share one complex transform: z = (x_a + i x_b) c,
+// and the DFT Z = c * conv of that packed row gives both rows' spectra by conjugate
+// symmetry (the rows are real): X_a[j] = (Z[j] + conj(Z[n-j])) / 2 and
+// X_b[j] = (Z[j] - conj(Z[n-j])) / 2i. Adjacent angles are paired, so the two rows have
+// similar magnitudes and each row's share of the rounding stays at its own level. A row
+// that is zero everywhere takes the white-noise line j/q, as in the one-row definition
+// (its packed spectrum would be the other row's rounding).
 template <typename T>
 __global__ __launch_bounds__(kFftThreads) void ncp_fft_rows_kernel(
-    const T *__restrict__ r, int n_det, int q, int M, const double2 *__restrict__ chirp,
+    const T *__restrict__ r, int n_ang, int n_det, int q, int M, const double2 *__restrict__ chirp,
     const double2 *__restrict__ khat, const double2 *__restrict__ tw, double *__restrict__ crow,
     const DevState *st, int k)
 {
     extern __shared__ double2 z[];          // M values
-    __shared__ double wsum[kFftThreads / 64];
-    __shared__ double total_s;
+    __shared__ double wsum[2][kFftThreads / 64];
+    __shared__ double total_s[2];
     if (halted(st, k)) return;
     const int t = threadIdx.x;
-    const T *src = r + (size_t)blockIdx.x * n_det;
+    const int ra = 2 * (int)blockIdx.x, rb = ra + 1;
+    const bool has_b = rb < n_ang;
+    const T *src_a = r + (size_t)ra * n_det;
+    const T *src_b = r + (size_t)(has_b ? rb : ra) * n_det;
+    int nz_a = 0, nz_b = 0;
     for (int i = t; i < M; i += kFftThreads) {
         double2 v = make_double2(0.0, 0.0);
         if (i < n_det) {
-            const double x = (double)src[i];
-            const double2 c = chirp[i];
-            v = make_double2(x * c.x, x * c.y);
+            const double xa = (double)src_a[i];
+            const double xb = has_b ? (double)src_b[i] : 0.0;
+            nz_a |= xa != 0.0;
+            nz_b |= xb != 0.0;
+            v = cmul(make_double2(xa, xb), chirp[i]);
         }
         z[i] = v;
     }
-    __syncthreads();
+    const bool live_a = __syncthreads_or(nz_a) != 0;
+    const bool live_b = __syncthreads_or(nz_b) != 0;
     const int half = M >> 1;
     // butterfly b of a pass with span h joins i = 2(b - j) + j and i + h, j = b mod h;
     // its twiddle exp(-2 pi i j / (2h)) is tw[h - 1 + j] (the pass's twiddles are
@@ -209,10 +230,7 @@ __global__ __launch_bounds__(kFftThreads) void ncp_fft_rows_kernel(
         }
         __syncthreads();
     }
-    for (int i = t; i < M; i += kFftThreads) {
-        const double2 u = z[i], v = khat[i];
-        z[i] = make_double2(fma(u.x, v.x, -u.y * v.y), fma(u.x, v.y, u.y * v.x));
-    }
+    for (int i = t; i < M; i += kFftThreads) z[i] = cmul(z[i], khat[i]);
     __syncthreads();
     for (int h = 1; h < M; h <<= 1) {
         for (int b = t; b < half; b += kFftThreads) {
@@ -227,43 +245,64 @@ __global__ __launch_bounds__(kFftThreads) void ncp_fft_rows_kernel(
         }
         __syncthreads();
     }
+    // both rows' periodograms at frequency j (up to the common factor M^2 / 4)
+    auto power = [&](int j, double &pa, double &pb) {
+        const double2 zj = cmul(z[j], chirp[j]);
+        const double2 zn = cmul(z[n_det - j], chirp[n_det - j]);
+        const double ax = zj.x + zn.x, ay = zj.y - zn.y;    // 2 X_a
+        const double bx = zj.y + zn.y, by = zn.x - zj.x;    // 2 X_b
+        pa = fma(ax, ax, ay * ay);
+        pb = fma(bx, bx, by * by);
+    };
     // thread t owns frequencies j = 1 + t*J .. (t+1)*J; fixed-order prefix over threads
     const int J = (q + kFftThreads - 1) / kFftThreads;
-    double own = 0.0;
+    double own_a = 0.0, own_b = 0.0;
     for (int u = 0; u < J; ++u) {
         const int j = 1 + t * J + u;
         if (j <= q) {
-            const double2 v = z[j];
-            own = fma(v.x, v.x, fma(v.y, v.y, own));
+            double pa, pb;
+            power(j, pa, pb);
+            own_a += pa;
+            own_b += pb;
         }
     }
-    // inclusive scan within the wave, then wave totals in order
+    // inclusive scans within the wave, then wave totals in order
     const int lane = t & 63, wv = t >> 6;
-    double inc = own;
+    double inc_a = own_a, inc_b = own_b;
     for (int o = 1; o < 64; o <<= 1) {
-        const double n = __shfl_up(inc, o, 64);
-        if (lane >= o) inc += n;
+        const double na = __shfl_up(inc_a, o, 64), nb = __shfl_up(inc_b, o, 64);
+        if (lane >= o) {
+            inc_a += na;
+            inc_b += nb;
+        }
     }
-    if (lane == 63) wsum[wv] = inc;
+    if (lane == 63) {
+        wsum[0][wv] = inc_a;
+        wsum[1][wv] = inc_b;
+    }
     __syncthreads();
-    if (t == 0) {
+    if (t < 2) {
         double run = 0.0;
         for (int w = 0; w < kFftThreads / 64; ++w) {
-            const double v = wsum[w];
-            wsum[w] = run;
+            const double v = wsum[t][w];
+            wsum[t][w] = run;
             run += v;
         }
-        total_s = run;
+        total_s[t] = run;
     }
     __syncthreads();
-    const double total = total_s;
-    double acc = wsum[wv] + inc - own;
+    const double total_a = live_a ? total_s[0] : 0.0, total_b = live_b ? total_s[1] : 0.0;
+    double acc_a = wsum[0][wv] + inc_a - own_a, acc_b = wsum[1][wv] + inc_b - own_b;
     for (int u = 0; u < J; ++u) {
         const int j = 1 + t * J + u;
         if (j <= q) {
-            const double2 v = z[j];
-            acc = fma(v.x, v.x, fma(v.y, v.y, acc));
-            crow[(size_t)blockIdx.x * q + (j - 1)] = total > 0.0 ? acc / total : (double)j / (double)q;
+            double pa, pb;
+            power(j, pa, pb);
+            acc_a += pa;
+            acc_b += pb;
+            const double white = (double)j / (double)q;
+            crow[(size_t)ra * q + (j - 1)] = total_a > 0.0 ? acc_a / total_a : white;
+            if (has_b) crow[(size_t)rb * q + (j - 1)] = total_b > 0.0 ? acc_b / total_b : white;
         }
     }
 }
@@ -376,8 +415,8 @@ hipError_t fft_rows_go(const Geometry &g, int M, const void *r, double *crow, in
     const double2 *chirp, *khat, *tw;
     hipError_t e = ncp_tables(g, M, &chirp, &khat, &tw);
     if (e != hipSuccess) return e;
-    ncp_fft_rows_kernel<T><<<g.n_ang, kFftThreads, (size_t)M * sizeof(double2), s>>>(
-        static_cast<const T *>(r), g.n_det, q, M, chirp, khat, tw, crow, st, k);
+    ncp_fft_rows_kernel<T><<<(g.n_ang + 1) / 2, kFftThreads, (size_t)M * sizeof(double2), s>>>(
+        static_cast<const T *>(r), g.n_ang, g.n_det, q, M, chirp, khat, tw, crow, st, k);
     return hipGetLastError();
 }
 
