@@ -235,6 +235,35 @@ def test_ncp_same_k(gpu_lib, cfg1, method, path):
         assert _rel(r.x.double().cpu().numpy(), ref.x) <= tol
 
 
+@pytest.mark.parametrize("n_ang,n_det", [(37, 69), (45, 100)])
+@pytest.mark.parametrize("method", ["ab", "ba"])
+def test_ncp_odd_angle_counts_and_even_rows(gpu_lib, method, n_ang, n_det):
+    """The chirp transform takes two sinogram rows per transform: with an odd number of
+    angles the last row is transformed alone, and with an even row length the frequency
+    n/2 is its own mirror. Both against the oracle: same k_NCP, d_k within 1e-9 (FP64) /
+    1e-4 (FP32: the FP32 iterate target; FP32 projectors and basis move d_k by ~1e-5 here),
+    iterate as in the other NCP tests."""
+    import torch
+    import paper_2110_01481_amd as abg
+    N = 48
+    go = O.Geometry(N, n_ang, n_det)
+    gg = abg.Geometry(N, n_ang, n_det)
+    xb = W.ellipse_phantom(N, 5, W.rng(95, n_ang, W.STREAM_PHANTOM))
+    b, _ = W.add_noise(go.A(xb), 0.02, W.rng(95, n_ang, W.STREAM_NOISE).standard_normal(go.m))
+    f = O.ab_gmres if method == "ab" else O.ba_gmres
+    ref = f(go.A, go.B_hat, b, 30, stop="ncp", ncp_shape=(go.n_ang, go.n_det))
+    for dt in ("f64", "f32"):
+        tdt = torch.float64 if dt == "f64" else torch.float32
+        r = abg.gmres(method, gg, torch.tensor(b, dtype=tdt, device="cuda"), 30, stop="ncp",
+                      basis=dt)
+        assert r.k_stop == ref.k_stop, (dt, r.k_stop, ref.k_stop)
+        n = min(len(ref.ncp), len(r.ncp_hist))
+        assert np.allclose(r.ncp_hist[:n], ref.ncp[:n], rtol=1e-9 if dt == "f64" else 1e-4,
+                           atol=1e-12), (dt, np.abs(r.ncp_hist[:n] / np.asarray(ref.ncp[:n]) - 1).max())
+        tol = _f64_tol(f, go, "hat", b, ref.k_stop) if dt == "f64" else 1e-4
+        assert _rel(r.x.double().cpu().numpy(), ref.x) <= tol
+
+
 def test_ragged_geometry_and_initial_guess(gpu_lib):
     import torch
     import paper_2110_01481_amd as abg
