@@ -174,7 +174,8 @@ __device__ inline void tile_store(const T (&acc)[kPixPerLane], T (*part)[kTile *
 // Software pipeline over rounds of AB angles: the sinogram loads of round r + 1's windows
 // are issued before round r is computed and land in LDS after it, and the angle
 // parameters are fetched one round before their set-up, so neither waits on the memory
-// latency in the barrier-separated phases. The loads are branch-free (clamped addresses,
+// latency in the barrier-separated phases. The loads are branch-free (WY: out-of-range
+// bins read as zero through the buffer's range check; otherwise clamped addresses, and
 // out-of-range bins zeroed when stored).
 //
 // PAD: instead of x, the tile goes to the forward projector's zero-padded row-major and
@@ -228,42 +229,54 @@ __device__ inline void back_tile(const T *__restrict__ y, T *__restrict__ x,
         }
     };
     T w0[kIt], w1[kIt];
-    unsigned live = 0;                                 // in-range bits of w0 / w1
-    // WY: one buffer resource spans the sinogram, and the window loads take 32-bit
-    // element offsets instead of clamped 64-bit addresses. An element index is clamped
-    // below at 0 (only row 0's bins left of the detector are negative) and reads past the
-    // sinogram's end return zero; offsets never wrap (the range check would see a wrapped
-    // offset as out of range once the compiler moves a constant part into the
-    // instruction's offset field). Bins outside their row are zeroed through `live` like
-    // every out-of-range bin.
+    unsigned live = 0;                                 // !WY: in-range bits of w0 / w1
+    // WY: one buffer resource spans the sinogram (its bytes fit 31 bits), and the window
+    // loads take 32-bit byte offsets instead of clamped 64-bit addresses. A bin outside
+    // its detector row is read at offset 2^31, past the sinogram, which the range check
+    // returns as zero: the loaded values need no mask. A bin inside its row has a
+    // nonnegative element index below m, and 2^31 stays out of range if the compiler
+    // moves a small constant between the offset and the instruction's offset field.
     const __amdgpu_buffer_rsrc_t ry = __builtin_amdgcn_make_buffer_rsrc(
         const_cast<T *>(y), (short)0, WY ? (int)((size_t)n_ang * (size_t)n_det * sizeof(T)) : 0,
         kRawBufferFlags);
+    constexpr unsigned kOutside = 0x80000000u;
     auto load = [&](int r) {
         const int a0 = r * AB, last = min(AB, n_ang - a0) - 1;
         live = 0;
+        // WY: angles of the last round past n_ang are not clamped. Their window entries
+        // are never read, and their loads, whatever first bin their stale (or never
+        // written) LDS entries hold, go through the buffer's range check. Element index
+        // of (angle a0 + t, bin 0), modulo 2^32:
+        const unsigned row0 = (unsigned)(a0 + (int)threadIdx.x / kWin) * (unsigned)n_det;
 #pragma unroll
         for (int j = 0; j < kIt; ++j) {
-            const int t = min((int)threadIdx.x / kWin + j * kRowsPer, last);
-            const int bin = L.ib[r & 1][t] + kk;
+            const int t = (int)threadIdx.x / kWin + j * kRowsPer;
             if constexpr (WY) {
-                const int e = (a0 + t) * n_det + bin;
-                w0[j] = buffer_elem<T>(ry, (unsigned)max(e, 0) * (unsigned)sizeof(T));
-                w1[j] = buffer_elem<T>(ry, (unsigned)max(e + 1, 0) * (unsigned)sizeof(T));
+                const int bin = L.ib[r & 1][t] + kk;
+                const unsigned o = (row0 + (unsigned)(j * kRowsPer) * (unsigned)n_det +
+                                    (unsigned)bin) * (unsigned)sizeof(T);
+                w0[j] = buffer_elem<T>(ry, (unsigned)bin < (unsigned)n_det ? o : kOutside);
+                w1[j] = buffer_elem<T>(ry, ((unsigned)(bin + 1) < (unsigned)n_det ? o : kOutside) +
+                                               (unsigned)sizeof(T));
             } else {
-                const T *row = y + (size_t)(a0 + t) * n_det;
+                const int tc = min(t, last);
+                const int bin = L.ib[r & 1][tc] + kk;
+                const T *row = y + (size_t)(a0 + tc) * n_det;
                 w0[j] = row[min(max(bin, 0), n_det - 1)];
                 w1[j] = row[min(max(bin + 1, 0), n_det - 1)];
+                live |= (unsigned)((unsigned)bin < (unsigned)n_det) << (2 * j);
+                live |= (unsigned)((unsigned)(bin + 1) < (unsigned)n_det) << (2 * j + 1);
             }
-            live |= (unsigned)((unsigned)bin < (unsigned)n_det) << (2 * j);
-            live |= (unsigned)((unsigned)(bin + 1) < (unsigned)n_det) << (2 * j + 1);
         }
     };
     auto store = [&]() {
 #pragma unroll
         for (int j = 0; j < kIt; ++j) {
-            const T v0 = (live >> (2 * j)) & 1u ? w0[j] : T(0);
-            const T v1 = (live >> (2 * j + 1)) & 1u ? w1[j] : T(0);
+            T v0 = w0[j], v1 = w1[j];
+            if constexpr (!WY) {
+                v0 = (live >> (2 * j)) & 1u ? v0 : T(0);
+                v1 = (live >> (2 * j + 1)) & 1u ? v1 : T(0);
+            }
             L.win[(int)threadIdx.x / kWin + j * kRowsPer][kk] = BinPair<T>{v0, v1 - v0};
         }
     };
@@ -292,10 +305,24 @@ __device__ inline void back_tile(const T *__restrict__ y, T *__restrict__ x,
             if constexpr (sizeof(T) == 8) asm volatile("" : "+v"(ftx), "+v"(fty));
             const BackStage<T> P = L.prm[r & 1][t];
             const T u0 = fma(ftx, P.cu, fma(fty, P.su, P.f));
-            back_tap<T, ADJ>(acc[0], L.win[t], u0, P, dsT);
+            if constexpr (!ADJ) {
+                // the four window reads issued before their use
+                BinPair<T> b[kPixPerLane];
+                T w[kPixPerLane];
 #pragma unroll
-            for (int j = 1; j < kPixPerLane; ++j)
-                back_tap<T, ADJ>(acc[j], L.win[t], fma(T(j), P.su4, u0), P, dsT);
+                for (int j = 0; j < kPixPerLane; ++j) {
+                    const T u = j == 0 ? u0 : fma(T(j), P.su4, u0);
+                    w[j] = fract_of(u);
+                    b[j] = L.win[t][(int)u];
+                }
+#pragma unroll
+                for (int j = 0; j < kPixPerLane; ++j) acc[j] += fma(w[j], b[j].d, b[j].v);
+            } else {
+                back_tap<T, ADJ>(acc[0], L.win[t], u0, P, dsT);
+#pragma unroll
+                for (int j = 1; j < kPixPerLane; ++j)
+                    back_tap<T, ADJ>(acc[j], L.win[t], fma(T(j), P.su4, u0), P, dsT);
+            }
         }
     }
     tile_store<T, PAD>(acc, L.part, ADJ ? T(1) : T(1.0 / ds), x, N, c0, r0, xr, xc, S);

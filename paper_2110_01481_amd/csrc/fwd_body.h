@@ -89,16 +89,25 @@ template <> struct Band<double> {
     {
         return min((unsigned)(int)floor(lo), cmax);
     }
-    // padded column, unclamped. A wave walks only the bands some lane's ray crosses
-    // (at most N of them, |m| <= 1), and the lanes of a wave lie within 63 bins of each
-    // other (63 * 64 * sqrt(2) < 5702 px for the spacings a geometry accepts), so every
-    // column a walking lane reaches is below 2N + 5710 < 2^17 in magnitude (N <= 32768):
-    // the conversion is exact and the byte offset cannot wrap back into the row.
-    __device__ int column_raw() const { return (int)floor(lo); }
-    // length of the band segment left of the pixel edge at floor(lo) + 1
+    // padded column, unclamped, by truncation. A wave walks only the bands some lane's
+    // ray crosses (at most N of them, |m| <= 1), and the lanes of a wave lie within 63
+    // bins of each other (63 * 64 * sqrt(2) < 5702 px for the spacings a geometry
+    // accepts), so every column a walking lane reaches is below 2N + 5710 < 2^17 in
+    // magnitude (N <= 32768): the conversion is exact and the byte offset cannot wrap back
+    // into the row. A tap can meet a nonzero pixel only for lo >= kPad - 1 > 0, where
+    // truncation is floor; below, truncation lands in the zero padding (lo > -1) or before
+    // the row (out of range, read as zero) as floor would.
+    __device__ int column_raw() const { return (int)lo; }
+    // length of the band segment left of the pixel edge at floor(lo) + 1, from the
+    // fractional part of lo (exactly lo - floor(lo) for lo >= 0)
     __device__ double left_length(const BandWeights<double> &b) const
     {
-        return fmin(b.len, fma(floor(lo) - lo, b.invq, b.invq));
+        const double t = fma(-__builtin_amdgcn_fract(lo), b.invq, b.invq);
+        // min of two finite values: the plain instruction (fmin would quieten the
+        // loop-invariant operand on every step)
+        double w;
+        asm("v_min_f64 %0, %1, %2" : "=v"(w) : "s"(b.len), "v"(t));
+        return w;
     }
     // (lo - floor(lo)) * s
     __device__ double frac_scaled(double s) const { return (lo - floor(lo)) * s; }
