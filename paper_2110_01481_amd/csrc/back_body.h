@@ -252,11 +252,12 @@ __device__ inline void back_tile(const T *__restrict__ y, T *__restrict__ x,
         for (int j = 0; j < kIt; ++j) {
             const int t = (int)threadIdx.x / kWin + j * kRowsPer;
             if constexpr (WY) {
-                const int bin = L.ib[r & 1][t] + kk;
-                const unsigned o = (row0 + (unsigned)(j * kRowsPer) * (unsigned)n_det +
-                                    (unsigned)bin) * (unsigned)sizeof(T);
-                w0[j] = buffer_elem<T>(ry, (unsigned)bin < (unsigned)n_det ? o : kOutside);
-                w1[j] = buffer_elem<T>(ry, ((unsigned)(bin + 1) < (unsigned)n_det ? o : kOutside) +
+                // unsigned: a stale first bin must not overflow a signed sum
+                const unsigned bin = (unsigned)L.ib[r & 1][t] + (unsigned)kk;
+                const unsigned o = (row0 + (unsigned)(j * kRowsPer) * (unsigned)n_det + bin) *
+                                   (unsigned)sizeof(T);
+                w0[j] = buffer_elem<T>(ry, bin < (unsigned)n_det ? o : kOutside);
+                w1[j] = buffer_elem<T>(ry, (bin + 1u < (unsigned)n_det ? o : kOutside) +
                                                (unsigned)sizeof(T));
             } else {
                 const int tc = min(t, last);
