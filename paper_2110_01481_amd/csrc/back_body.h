@@ -200,8 +200,6 @@ __device__ inline void back_tile(const T *__restrict__ y, T *__restrict__ x,
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     // lane owns pixels (tx, ty0 + 4j), j = 0..3, of the 16 x 16 tile
     const int tx = lane & 15, ty0 = lane >> 4;
-    const double xref = c0 - 0.5 * N + 0.5, yref = r0 - 0.5 * N + 0.5;
-    const double s0u = s0 / ds;
     T ftx = T(tx), fty = T(ty0);
     const T dsT = T(ds);
     const int n_rounds = (n_ang + AB - 1) / AB;
@@ -211,6 +209,15 @@ __device__ inline void back_tile(const T *__restrict__ y, T *__restrict__ x,
     auto fetch = [&](int r) { Pn = ang[min(r * AB + (int)threadIdx.x, n_ang - 1)]; };
     auto setup = [&](int r) {
         if ((int)threadIdx.x < min(AB, n_ang - r * AB)) {
+            // the tile's reference pixel and the first bin's offset, formed here from the
+            // scalar arguments (opaque to hoisting: kept live across the rounds as FP64
+            // vector registers, they would be spilled by the FP64 kernel at its six-wave
+            // bound)
+            int cx = c0, cy = r0;
+            double s0v = s0;
+            asm volatile("" : "+s"(cx), "+s"(cy), "+s"(s0v));
+            const double xref = cx - 0.5 * N + 0.5, yref = cy - 0.5 * N + 0.5;
+            const double s0u = s0v / ds;
             const double uref = fma(xref, Pn.cu, fma(yref, Pn.su, -s0u));
             const double umin = uref + (kTile - 1) * (fmin(Pn.cu, 0.0) + fmin(Pn.su, 0.0));
             const double ib = floor(umin) - 1.0;
