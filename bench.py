@@ -106,6 +106,7 @@ def summarize_counters(d: str, kernel_key: str = "forward_kernel_f32",
     if os.path.exists(sq_csv):
         sq = _counter_means(sq_csv, kname)
         data["valu_wave_insts_per_dispatch"] = round(sq["SQ_INSTS_VALU"], 1)
+        data["vmem_read_wave_insts_per_dispatch"] = round(sq["SQ_INSTS_VMEM_RD"], 1)
     l2_csv = os.path.join(d, "l2", "run_counter_collection.csv")
     if os.path.exists(l2_csv):
         # L2 (TCC) hit rate = hits / (hits + misses) per kernel of the solve
@@ -865,6 +866,16 @@ def roofline_of(prof, w, proj: str, tag: str):
                 roof["valu_issue_frac"] = round(lane_ops / (avg_ms * 1e-3) / VALU_ISSUE_PEAK, 4)
             if tr.get("l2_hit_rate"):
                 roof["l2_hit_rate"] = tr["l2_hit_rate"].get(dominant + "_kernel")
+            if dominant == "forward" and "vmem_read_wave_insts_per_dispatch" in tr:
+                # the forward walk issues one 64-lane gather per band and wave: its issue
+                # rate per CU, in cycles of the 2.4 GHz peak clock (a texture path taking
+                # four lane addresses per cycle needs 16)
+                g = tr["vmem_read_wave_insts_per_dispatch"]
+                roof["gathers"] = {
+                    "wave_gathers_per_launch": int(g),
+                    "cycles_per_gather_per_cu_at_2_4_ghz": round(avg_ms * 1e-3 * 2.4e9 / (g / 256), 1),
+                    "note": "one 64-lane gather per band and wave; 16 cycles each at four lane "
+                            "addresses per cycle"}
     else:
         roof.update({"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": None, "traffic": None})
