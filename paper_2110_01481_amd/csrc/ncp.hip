@@ -170,7 +170,7 @@ __global__ void ncp_final_kernel(const double *partials, int nb, DevState *st, i
 // ---- Bluestein rows: forward FFT (decimation in frequency: natural order in, bit-
 // reversed order out), product with the kernel's transform (stored bit-reversed), inverse
 // FFT (decimation in time: bit-reversed in, natural out) -- no permutation pass.
-constexpr int kFftThreads = 512;
+constexpr int kFftThreads = 1024;
 constexpr int kFftMaxM = 8192;
 
 __device__ inline double2 cmul(double2 a, double2 b)
@@ -214,34 +214,81 @@ __global__ __launch_bounds__(kFftThreads) void ncp_fft_rows_kernel(
     }
     const bool live_a = __syncthreads_or(nz_a) != 0;
     const bool live_b = __syncthreads_or(nz_b) != 0;
-    const int half = M >> 1;
-    // butterfly b of a pass with span h joins i = 2(b - j) + j and i + h, j = b mod h;
-    // its twiddle exp(-2 pi i j / (2h)) is tw[h - 1 + j] (the pass's twiddles are
-    // contiguous: adjacent lanes read adjacent entries)
-    for (int h = half; h >= 1; h >>= 1) {
+    const int half = M >> 1, quarter = M >> 2;
+    // Radix-2 butterflies. Decimation in frequency, span h: (u, v) -> (u + v, (u - v) w);
+    // decimation in time: (u, v) -> (u + v conj(w), u - v conj(w)); w = exp(-2 pi i j /
+    // (2h)) = tw[h - 1 + j] for the pair's offset j < h in its block of 2h (a pass's
+    // twiddles are contiguous: adjacent lanes read adjacent entries).
+    auto dif = [](double2 &u, double2 &v, double2 w) {
+        const double dx = u.x - v.x, dy = u.y - v.y;
+        u = make_double2(u.x + v.x, u.y + v.y);
+        v = make_double2(fma(dx, w.x, -dy * w.y), fma(dx, w.y, dy * w.x));
+    };
+    auto dit = [](double2 &u, double2 &v, double2 w) {
+        const double px = fma(v.x, w.x, v.y * w.y), py = fma(v.y, w.x, -v.x * w.y);
+        v = make_double2(u.x - px, u.y - py);
+        u = make_double2(u.x + px, u.y + py);
+    };
+    // Two consecutive passes run as one: a thread takes the four elements that the two
+    // spans join (offsets j, j + g, j + 2g, j + 3g of a block of 4g) through both passes
+    // in registers -- the same operations on every element as two radix-2 passes, with
+    // half the LDS traffic and barriers.
+    int lg = 0;
+    while ((1 << lg) < M) ++lg;
+    int h = half;
+    if (lg & 1) {                                       // odd number of passes: one alone
         for (int b = t; b < half; b += kFftThreads) {
-            const int j = b & (h - 1);
-            const int i = ((b - j) << 1) + j;
-            const double2 u = z[i], v = z[i + h];
-            const double2 w = tw[h - 1 + j];
-            const double dx = u.x - v.x, dy = u.y - v.y;
-            z[i] = make_double2(u.x + v.x, u.y + v.y);
-            z[i + h] = make_double2(fma(dx, w.x, -dy * w.y), fma(dx, w.y, dy * w.x));
+            const int j = b & (h - 1), i = ((b - j) << 1) + j;
+            double2 u = z[i], v = z[i + h];
+            dif(u, v, tw[h - 1 + j]);
+            z[i] = u;
+            z[i + h] = v;
+        }
+        __syncthreads();
+        h >>= 1;
+    }
+    for (; h >= 2; h >>= 2) {                           // spans h and h / 2
+        const int g = h >> 1;
+        for (int b = t; b < quarter; b += kFftThreads) {
+            const int j = b & (g - 1), i = ((b - j) << 2) + j;
+            double2 a0 = z[i], a1 = z[i + g], a2 = z[i + 2 * g], a3 = z[i + 3 * g];
+            dif(a0, a2, tw[h - 1 + j]);
+            dif(a1, a3, tw[h - 1 + j + g]);
+            const double2 w2 = tw[g - 1 + j];
+            dif(a0, a1, w2);
+            dif(a2, a3, w2);
+            z[i] = a0;
+            z[i + g] = a1;
+            z[i + 2 * g] = a2;
+            z[i + 3 * g] = a3;
         }
         __syncthreads();
     }
     for (int i = t; i < M; i += kFftThreads) z[i] = cmul(z[i], khat[i]);
     __syncthreads();
-    for (int h = 1; h < M; h <<= 1) {
+    for (h = 1; 2 * h < M; h <<= 2) {                   // spans h and 2h
+        for (int b = t; b < quarter; b += kFftThreads) {
+            const int j = b & (h - 1), i = ((b - j) << 2) + j;
+            double2 a0 = z[i], a1 = z[i + h], a2 = z[i + 2 * h], a3 = z[i + 3 * h];
+            const double2 w1 = tw[h - 1 + j];
+            dit(a0, a1, w1);
+            dit(a2, a3, w1);
+            dit(a0, a2, tw[2 * h - 1 + j]);
+            dit(a1, a3, tw[2 * h - 1 + j + h]);
+            z[i] = a0;
+            z[i + h] = a1;
+            z[i + 2 * h] = a2;
+            z[i + 3 * h] = a3;
+        }
+        __syncthreads();
+    }
+    if (h < M) {                                        // the last span alone
         for (int b = t; b < half; b += kFftThreads) {
-            const int j = b & (h - 1);
-            const int i = ((b - j) << 1) + j;
-            const double2 w = tw[h - 1 + j];
-            const double2 u = z[i], v = z[i + h];
-            // v times conj(w)
-            const double px = fma(v.x, w.x, v.y * w.y), py = fma(v.y, w.x, -v.x * w.y);
-            z[i] = make_double2(u.x + px, u.y + py);
-            z[i + h] = make_double2(u.x - px, u.y - py);
+            const int j = b & (h - 1), i = ((b - j) << 1) + j;
+            double2 u = z[i], v = z[i + h];
+            dit(u, v, tw[h - 1 + j]);
+            z[i] = u;
+            z[i + h] = v;
         }
         __syncthreads();
     }
