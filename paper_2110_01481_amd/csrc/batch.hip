@@ -654,6 +654,9 @@ struct Engine {
     abg_precision p{};
     int max_slots = 0, device = 0;
     hipStream_t s = nullptr, cap_stream = nullptr;
+    // second captured stream and the events that fork the AB chain onto it and join it
+    hipStream_t cap_stream2 = nullptr;
+    hipEvent_t fork_ev = nullptr, join_ev = nullptr;
     BatchInst *d_desc = nullptr;
     DevState *d_st = nullptr;
     int *d_tab = nullptr;
@@ -694,6 +697,9 @@ struct Engine {
         for (auto &e : tev)
             if (e) (void)hipEventDestroy(e);
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
+        if (cap_stream2) (void)hipStreamDestroy(cap_stream2);
+        if (fork_ev) (void)hipEventDestroy(fork_ev);
+        if (join_ev) (void)hipEventDestroy(join_ev);
         if (d_desc) (void)hipFree(d_desc);
         if (d_st) (void)hipFree(d_st);
         if (d_tab) (void)hipFree(d_tab);
@@ -754,16 +760,30 @@ struct Engine {
     }
 
     // begin + the three projector phases (idempotent between rounds: they recompute the
-    // round's z, t and q from w_k without advancing any problem)
-    template <typename TX> void enqueue_projectors_t(hipStream_t q, const Tiles &tl)
+    // round's z, t and q from w_k without advancing any problem). The BA chain (pad,
+    // forward, back) and the AB chain (back, pad, forward) touch disjoint problems and
+    // lists; with q2 the AB chain forks onto q2 and joins q after its last phase, so that
+    // in a captured round the two chains are independent branches of the graph.
+    template <typename TX> void enqueue_projectors_t(hipStream_t q, const Tiles &tl,
+                                                     hipStream_t q2 = nullptr)
     {
         begin_kernel<<<kNumTab, 256, 0, q>>>(d_desc, d_st, tv, max_slots, tl);
+        hipStream_t qa = q;
+        if (q2) {
+            (void)hipEventRecord(fork_ev, q);
+            (void)hipStreamWaitEvent(q2, fork_ev, 0);
+            qa = q2;
+        }
         bpad_kernel<TX><<<grid_proj, 256, 0, q>>>(d_desc, d_st, tv, kTPadBA, 0, tl);
-        enqueue_back<TX>(q, tl, kTBackAB, 0);
+        enqueue_back<TX>(qa, tl, kTBackAB, 0);
         bfwd_kernel<TX><<<grid_proj, 256, 0, q>>>(d_desc, d_st, tv, kTFwdBA, 0, tl);
-        bpad_kernel<TX><<<grid_proj, 256, 0, q>>>(d_desc, d_st, tv, kTPadAB, 1, tl);
+        bpad_kernel<TX><<<grid_proj, 256, 0, qa>>>(d_desc, d_st, tv, kTPadAB, 1, tl);
         enqueue_back<TX>(q, tl, kTBackBA, 1);
-        bfwd_kernel<TX><<<grid_proj, 256, 0, q>>>(d_desc, d_st, tv, kTFwdAB, 1, tl);
+        bfwd_kernel<TX><<<grid_proj, 256, 0, qa>>>(d_desc, d_st, tv, kTFwdAB, 1, tl);
+        if (q2) {
+            (void)hipEventRecord(join_ev, q2);
+            (void)hipStreamWaitEvent(q, join_ev, 0);
+        }
     }
 
     void enqueue_projectors(hipStream_t q, const Tiles &tl)
@@ -774,7 +794,7 @@ struct Engine {
 
     template <typename TX, typename TV> void enqueue_round_t(hipStream_t q)
     {
-        enqueue_projectors_t<TX>(q, tiles);
+        enqueue_projectors_t<TX>(q, tiles, cap_stream2);
         bmgs_kernel<TX, TV, kMgsSmallE><<<grid_mgs_s, kBlock, 0, q>>>(d_desc, d_st, tv, kTMgsS);
         bmgs_kernel<TX, TV, kMgsLargeE><<<grid_mgs_l, kBlock, 0, q>>>(d_desc, d_st, tv, kTMgsL);
         if constexpr (sizeof(TV) < 8)
@@ -1163,6 +1183,9 @@ int engine_create(abg_precision p, int max_slots, hipStream_t s, Engine **out)
     };
     if (hipGetDevice(&e->device) != hipSuccess) return bad();
     if (hipStreamCreateWithFlags(&e->cap_stream, hipStreamNonBlocking) != hipSuccess) return bad();
+    if (hipStreamCreateWithFlags(&e->cap_stream2, hipStreamNonBlocking) != hipSuccess) return bad();
+    if (hipEventCreateWithFlags(&e->fork_ev, hipEventDisableTiming) != hipSuccess) return bad();
+    if (hipEventCreateWithFlags(&e->join_ev, hipEventDisableTiming) != hipSuccess) return bad();
     const size_t tab_ints = (2 + kRanges) * kNumTab + 2 * (size_t)kNumTab * max_slots;
     if (hipMalloc(&e->d_desc, sizeof(BatchInst) * max_slots) != hipSuccess) return bad();
     if (hipMalloc(&e->d_st, sizeof(DevState) * max_slots) != hipSuccess) return bad();
