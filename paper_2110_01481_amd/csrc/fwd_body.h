@@ -104,7 +104,8 @@ template <> struct Band<double> {
     {
         const double t = fma(-__builtin_amdgcn_fract(lo), b.invq, b.invq);
         // min of two finite values: the plain instruction (fmin would quieten the
-        // loop-invariant operand on every step)
+        // loop-invariant operand on every step); the length is the same in every lane
+        // (a wave walks one angle), so a scalar operand holds it
         double w;
         asm("v_min_f64 %0, %1, %2" : "=v"(w) : "s"(b.len), "v"(t));
         return w;
