@@ -13,7 +13,8 @@
 //             candidate test
 //
 // The work lists live in device memory and are rebuilt by `begin` every round, so the
-// graph never changes while problems join and leave. Blocks take work items from a
+// graph never changes while problems join and leave (two variants are kept: the AB and
+// BA projector chains in sequence, or as two branches while the problems are small). Blocks take work items from a
 // per-list ticket counter; an item's arithmetic depends only on its own problem, so a
 // problem's results are the same alone and in any mix.
 //
@@ -667,8 +668,9 @@ struct Engine {
     hipEvent_t ev[kSnapRing] = {};
     std::deque<int> inflight;
     int ring_next = 0;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    // the captured round, [0]: projector chains in sequence, [1]: as two branches
+    hipGraph_t graph[2] = {};
+    hipGraphExec_t exec[2] = {};
     bool dirty = true;
     Tiles tiles{0, 64, 2};
     int grid_proj = 0, grid_back = 0, grid_back64 = 0, grid_back_adj = 0, grid_back64_adj = 0;
@@ -690,8 +692,10 @@ struct Engine {
     ~Engine()
     {
         if (s) (void)hipStreamSynchronize(s);
-        if (exec) (void)hipGraphExecDestroy(exec);
-        if (graph) (void)hipGraphDestroy(graph);
+        for (int v = 0; v < 2; ++v) {
+            if (exec[v]) (void)hipGraphExecDestroy(exec[v]);
+            if (graph[v]) (void)hipGraphDestroy(graph[v]);
+        }
         for (auto &e : ev)
             if (e) (void)hipEventDestroy(e);
         for (auto &e : tev)
@@ -792,9 +796,9 @@ struct Engine {
         else enqueue_projectors_t<float>(q, tl);
     }
 
-    template <typename TX, typename TV> void enqueue_round_t(hipStream_t q)
+    template <typename TX, typename TV> void enqueue_round_t(hipStream_t q, hipStream_t q2)
     {
-        enqueue_projectors_t<TX>(q, tiles, cap_stream2);
+        enqueue_projectors_t<TX>(q, tiles, q2);
         bmgs_kernel<TX, TV, kMgsSmallE><<<grid_mgs_s, kBlock, 0, q>>>(d_desc, d_st, tv, kTMgsS);
         bmgs_kernel<TX, TV, kMgsLargeE><<<grid_mgs_l, kBlock, 0, q>>>(d_desc, d_st, tv, kTMgsL);
         if constexpr (sizeof(TV) < 8)
@@ -804,21 +808,44 @@ struct Engine {
         bres_kernel<TX, TV><<<grid_res, kBlock, 0, q>>>(d_desc, d_st, tv, tiles);
     }
 
-    void enqueue_round(hipStream_t q)
+    void enqueue_round(hipStream_t q, hipStream_t q2)
     {
-        if (p.proj == ABG_F64) enqueue_round_t<double, double>(q);
-        else if (p.basis == ABG_F32) enqueue_round_t<float, float>(q);
-        else enqueue_round_t<float, bf16>(q);
+        if (p.proj == ABG_F64) enqueue_round_t<double, double>(q, q2);
+        else if (p.basis == ABG_F32) enqueue_round_t<float, float>(q, q2);
+        else enqueue_round_t<float, bf16>(q, q2);
     }
 
-    int capture()
+    // Whether a round's AB chain runs beside its BA chain: it fills the tails of the
+    // persistent projector kernels when the problems are small, but once one problem's
+    // image and sinogram take a sizable share of the 256 MB Infinity Cache, the problems
+    // of the two chains evict each other's data (measured: a mix with N <= 1024 5-9%
+    // faster, the served stream with 2048^2 requests 2.5% slower).
+    static constexpr double kForkMaxBytes = 32e6;
+    bool fork_chains() const
     {
-        if (exec) BCK(hipGraphExecDestroy(exec));
-        if (graph) BCK(hipGraphDestroy(graph));
-        exec = nullptr;
-        graph = nullptr;
+        double most = 0.0;
+        const size_t es = dtype_size(p.proj);
+        for (const auto &sl : slots)
+            if (sl.phase != kFree && sl.g)
+                most = std::max(most, (double)es * ((double)sl.g->N * sl.g->N + (double)sl.g->m()));
+        return most < kForkMaxBytes;
+    }
+
+    // Drops both captured variants once the tiles changed; captures variant v if absent.
+    int capture(int v)
+    {
+        if (dirty) {
+            for (int u = 0; u < 2; ++u) {
+                if (exec[u]) BCK(hipGraphExecDestroy(exec[u]));
+                if (graph[u]) BCK(hipGraphDestroy(graph[u]));
+                exec[u] = nullptr;
+                graph[u] = nullptr;
+            }
+            dirty = false;
+        }
+        if (exec[v]) return ABG_OK;
         BCK(hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal));
-        enqueue_round(cap_stream);
+        enqueue_round(cap_stream, v ? cap_stream2 : nullptr);
         hipError_t le = hipGetLastError();
         hipGraph_t gr = nullptr;
         hipError_t ee = hipStreamEndCapture(cap_stream, &gr);
@@ -826,9 +853,8 @@ struct Engine {
             if (gr) (void)hipGraphDestroy(gr);
             return fail(ABG_EHIP);
         }
-        graph = gr;
-        BCK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
-        dirty = false;
+        graph[v] = gr;
+        BCK(hipGraphInstantiate(&exec[v], graph[v], nullptr, nullptr, 0));
         return ABG_OK;
     }
 
@@ -1130,15 +1156,16 @@ struct Engine {
             if (rc) return rc;
         }
         if (n_in(kRunning) > 0) {
-            if (dirty) {
-                int rc = capture();
+            const int v = fork_chains() ? 1 : 0;
+            if (dirty || !exec[v]) {
+                int rc = capture(v);
                 if (rc) return rc;
             }
             // the round's Gram-Schmidt grids take what the device holds: the whole
             // budget, returned by a stream callback once the round has run
             GroupBudget &budget = device_group_budget();
             budget.acquire(GroupBudget::kUnits);
-            hipError_t e = hipGraphLaunch(exec, s);
+            hipError_t e = hipGraphLaunch(exec[v], s);
             if (e == hipSuccess) e = hipLaunchHostFunc(s, release_round, &budget);
             if (e != hipSuccess) {
                 (void)hipStreamSynchronize(s);
