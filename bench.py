@@ -106,7 +106,8 @@ def summarize_counters(d: str, kernel_key: str = "forward_kernel_f32",
     if os.path.exists(sq_csv):
         sq = _counter_means(sq_csv, kname)
         data["valu_wave_insts_per_dispatch"] = round(sq["SQ_INSTS_VALU"], 1)
-        data["vmem_read_wave_insts_per_dispatch"] = round(sq["SQ_INSTS_VMEM_RD"], 1)
+        if "SQ_INSTS_VMEM_RD" in sq:
+            data["vmem_read_wave_insts_per_dispatch"] = round(sq["SQ_INSTS_VMEM_RD"], 1)
     l2_csv = os.path.join(d, "l2", "run_counter_collection.csv")
     if os.path.exists(l2_csv):
         # L2 (TCC) hit rate = hits / (hits + misses) per kernel of the solve

@@ -380,6 +380,16 @@ int abg_ncp_force_goertzel(int on);
  * lg_angles outside -1..2. */
 int abg_fp_force_block_shape(int lg_angles);
 
+/* Share of the four-angle forward-projector blocks (line model) that stage each band
+ * row's columns in LDS and read their taps there, in eighths (0..8), spread over the grid;
+ * the other blocks read their taps from the image copies. The two kinds take their taps
+ * through different units of a compute unit, so a mix of them gathers faster than either
+ * alone. -1 (the default) restores the automatic share: three eighths in FP32, none in
+ * FP64. Results are bit-identical for
+ * every share. Process-wide; for tests and measurements. Returns ABG_OK, or ABG_EINVAL
+ * for eighths outside -1..8. */
+int abg_fp_force_stage_share(int eighths);
+
 /* Releases what the library holds process-wide beyond geometries and engines: the
  * profiling events (profiling is switched off; accumulated counts are kept) and the idle
  * pooled pinned scalar slots and events of single solves (a solve leases one set for its

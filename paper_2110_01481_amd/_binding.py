@@ -39,7 +39,7 @@ EXPORTS = ["abg_create_geometry", "abg_destroy_geometry", "abg_geometry_sizes",
            "abg_mgs_force_stream", "abg_geometry_set_model", "abg_geometry_get_model",
            "abg_geometry_set_strip_threshold", "abg_lsq_workspace_bytes", "abg_lsqr", "abg_lsmr",
            "abg_gmres_error_history", "abg_release_process_resources", "abg_fp_apply_noalloc",
-           "abg_ncp_force_goertzel", "abg_fp_force_block_shape"]
+           "abg_ncp_force_goertzel", "abg_fp_force_block_shape", "abg_fp_force_stage_share"]
 
 
 class AbgError(RuntimeError):
@@ -142,6 +142,7 @@ def load_library(path: str | None = None):
     lib.abg_mgs_force_stream.argtypes = [i]
     lib.abg_ncp_force_goertzel.argtypes = [i]
     lib.abg_fp_force_block_shape.argtypes = [i]
+    lib.abg_fp_force_stage_share.argtypes = [i]
     lib.abg_geometry_set_model.argtypes = [vp, i]
     lib.abg_geometry_get_model.argtypes = [vp, ctypes.POINTER(i)]
     lib.abg_geometry_set_strip_threshold.argtypes = [vp, ctypes.c_double, _dp]
@@ -465,6 +466,13 @@ def mgs_force_stream(on: bool = True):
 def ncp_force_goertzel(on: bool = True):
     """NCP periodograms by Goertzel's recurrence for every row length (abg_ncp_force_goertzel)."""
     load_library().abg_ncp_force_goertzel(1 if on else 0)
+
+
+def fp_force_stage_share(eighths: int = -1):
+    """Eighths (0..8) of the four-angle forward blocks that stage their band rows in LDS;
+    -1 restores the automatic share (abg_fp_force_stage_share). Results are bit-identical
+    for every share."""
+    _check(load_library().abg_fp_force_stage_share(int(eighths)), "abg_fp_force_stage_share")
 
 
 def fp_force_block_shape(lg_angles: int = -1):

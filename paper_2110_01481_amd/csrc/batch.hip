@@ -100,6 +100,8 @@ struct Tiles {
                      // shape single solves of its geometry use
     int ang_block;   // back projectors: angles staged in LDS per round (64 or 128)
     int sched;       // item schedule of the projector and residual lists (for_each_item)
+    int stage = 0;   // eighths of the four-angle forward items that stage their band rows
+                     // in LDS (set at launch from the single-solve rule)
 };
 
 namespace {
@@ -372,9 +374,10 @@ __global__ __launch_bounds__(256) void bpad_kernel(const BatchInst *__restrict__
 
 // mode 0: BA, z = A w_k (column k of Z);  mode 1: AB, q = A t
 template <typename T>
-__global__ __launch_bounds__(256) void bfwd_kernel(const BatchInst *__restrict__ D, const DevState *S,
+__global__ __launch_bounds__(256, 8) void bfwd_kernel(const BatchInst *__restrict__ D, const DevState *S,
                                                    TabView tv, int t, int mode, Tiles tl)
 {
+    __shared__ FwdStageLds<T> lds;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     for_each_item(tv, t, tl.sched, [&](int slot, int local) {
@@ -386,6 +389,16 @@ __global__ __launch_bounds__(256) void bfwd_kernel(const BatchInst *__restrict__
         const int wpa = rays / 64;       // waves per angle
         const int apb = 256 / rays;      // angles per block
         const int nrg = (d.n_det + rays - 1) / rays;
+        // a share of the four-angle items, spread by a hash of the item, walks with its band
+        // rows staged in LDS (the whole block, before any wave leaves)
+        if (rays == 64 && tl.stage > 0 &&
+            (int)(((unsigned)local * 0x9E3779B1u + (unsigned)slot * 0x85EBCA6Bu) >> 29) < tl.stage) {
+            T *y = mode == 0 ? zcol<T>(d, k) : gfield<T>(d.q);
+            forward_block_staged(gfield<const T>(d.xr), gfield<const T>(d.xc), y,
+                                 gfield<const AngleParams>(d.ang), (local / nrg) * 4,
+                                 (local % nrg) * 64, d.N, d.S, d.n_ang, d.n_det, d.ds, d.s0, lds);
+            return;
+        }
         const int a = (local / nrg) * apb + wave / wpa;
         const int i = (local % nrg) * rays + (wave % wpa) * 64 + lane;
         if (a >= d.n_ang) return;   // whole waves
@@ -772,6 +785,8 @@ struct Engine {
                                                      hipStream_t q2 = nullptr)
     {
         begin_kernel<<<kNumTab, 256, 0, q>>>(d_desc, d_st, tv, max_slots, tl);
+        Tiles tf = tl;
+        tf.stage = fwd_stage_eighths(p.proj);
         hipStream_t qa = q;
         if (q2) {
             (void)hipEventRecord(fork_ev, q);
@@ -780,10 +795,10 @@ struct Engine {
         }
         bpad_kernel<TX><<<grid_proj, 256, 0, q>>>(d_desc, d_st, tv, kTPadBA, 0, tl);
         enqueue_back<TX>(qa, tl, kTBackAB, 0);
-        bfwd_kernel<TX><<<grid_proj, 256, 0, q>>>(d_desc, d_st, tv, kTFwdBA, 0, tl);
+        bfwd_kernel<TX><<<grid_proj, 256, 0, q>>>(d_desc, d_st, tv, kTFwdBA, 0, tf);
         bpad_kernel<TX><<<grid_proj, 256, 0, qa>>>(d_desc, d_st, tv, kTPadAB, 1, tl);
         enqueue_back<TX>(q, tl, kTBackBA, 1);
-        bfwd_kernel<TX><<<grid_proj, 256, 0, qa>>>(d_desc, d_st, tv, kTFwdAB, 1, tl);
+        bfwd_kernel<TX><<<grid_proj, 256, 0, qa>>>(d_desc, d_st, tv, kTFwdAB, 1, tf);
         if (q2) {
             (void)hipEventRecord(join_ev, q2);
             (void)hipStreamWaitEvent(q, join_ev, 0);

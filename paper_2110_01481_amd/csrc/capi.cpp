@@ -663,6 +663,13 @@ int abg_fp_force_block_shape(int lg_angles)
     return ABG_OK;
 }
 
+int abg_fp_force_stage_share(int eighths)
+{
+    if (eighths < -1 || eighths > 8) return ABG_EINVAL;
+    fwd_force_stage_eighths(eighths);
+    return ABG_OK;
+}
+
 int abg_release_process_resources(void)
 {
     {

@@ -475,5 +475,166 @@ __device__ inline void forward_ray_strip(const T *__restrict__ xr, const T *__re
     if (i < n_det) y[(size_t)a * n_det + i] = acc;
 }
 
+// ---- line model, four angles per block, band rows staged in LDS -------------------------
+// The forward walk above issues one 64-lane gather per band and wave, and the texture
+// path takes them at four lane addresses per cycle: that rate bounds it. A block of four
+// adjacent angles (one wave each) and the same 64 rays reads nearly the same columns of
+// every band row in all four waves, so here each band row's columns the block can touch
+// are copied once into LDS by one 16-byte load per lane (a quarter of the addresses), and
+// the waves read their taps from there. Everything else is the walk above, band by band
+// in the same order: the results are the same bits. The LDS returns a band's taps no
+// faster than the texture path does, so this walk alone is slower; run beside the
+// direct walk in the same launch it takes its taps through the other unit.
+//
+// The window of band r starts at org(r) and holds kStageCols columns. For angle i the
+// leftmost lane sits at lmin_i + r m_i and the rightmost at rmax_i + r m_i (padded
+// columns; lanes are monotone in their offset), so the columns the block touches lie in
+// [min_i(lmin_i + r m_i), max_i(rmax_i + r m_i) + 2]. The lower edge is concave in r and
+// the upper convex, so their chords over the block's bands bound them from below and
+// from above, and the window's width is checked at the two end bands only. org(r)
+// follows the lower chord in 32.32 fixed point on the scalar unit. Blocks whose angles
+// differ in orientation, include an axis-aligned or a missing angle, or need a wider
+// window take the walk above.
+constexpr int kStageBands = 8;
+template <typename T> constexpr int kStageCols = 64 * 16 / (int)sizeof(T);
+
+template <typename T> struct FwdStageLds {
+    T win[2][kStageBands][kStageCols<T>];
+    double lmin[4], rmax[4], m[4];
+    int r0[4], r1[4], kind[4];
+};
+
+__device__ inline double lane_value_f64(double v, int l)
+{
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = __builtin_amdgcn_readlane((unsigned)b, l);
+    const unsigned hi = __builtin_amdgcn_readlane((unsigned)(b >> 32), l);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+__device__ inline long long uniform_ll(long long v)
+{
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)((unsigned long long)v >> 32));
+    return (long long)(((unsigned long long)hi << 32) | lo);
+}
+
+// Angles a0 .. a0 + 3 (wave w takes a0 + w), rays ray0 .. ray0 + 63 of each. All four
+// waves call it (also for angles past n_ang); it starts with a block-wide barrier, so
+// that consecutive calls of a block may share L.
+template <typename T>
+__device__ inline void forward_block_staged(const T *__restrict__ xr, const T *__restrict__ xc,
+                                            T *__restrict__ y, const AngleParams *__restrict__ ang,
+                                            int a0, int ray0, int N, int S, int n_ang, int n_det,
+                                            double ds, double s0, FwdStageLds<T> &L)
+{
+    constexpr int W = kStageCols<T>;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+    const int a = a0 + wave, i = ray0 + lane;
+    int kind = 0, wr0 = 0, wr1 = 0;
+    double lo0 = 0.0, lmin = 0.0, rmax = 0.0, m = 0.0;
+    AngleParams P{};
+    if (a < n_ang) {
+        P = ang[a];
+        if (!P.axis) {
+            kind = P.steep ? 1 : 2;
+            const double half = 0.5 * N;
+            const double si = s0 + (double)i * ds;
+            const double u0 = fma(si, P.inv, fma(-half, P.m, half));
+            lo0 = u0 + fmin(P.m, 0.0);
+            int r0, r1;
+            band_range(lo0, P.m, N, 0.0, i < n_det, r0, r1);
+            wr0 = __builtin_amdgcn_readfirstlane(wave_min_i(r0));
+            wr1 = __builtin_amdgcn_readfirstlane(wave_max_i(r1));
+            const double l0 = lane_value_f64(lo0, 0), l63 = lane_value_f64(lo0, 63);
+            lmin = fmin(l0, l63) + kPad;
+            rmax = fmax(l0, l63) + kPad;
+            m = P.m;
+        }
+    }
+    __syncthreads();                                   // the previous call is done with L
+    if (lane == 0) {
+        L.kind[wave] = kind;
+        L.r0[wave] = wr0;
+        L.r1[wave] = wr1;
+        L.lmin[wave] = lmin;
+        L.rmax[wave] = rmax;
+        L.m[wave] = m;
+    }
+    __syncthreads();
+    // the block's choice, the same in every wave
+    bool staged = L.kind[0] != 0;
+    int rb0 = N, rb1 = 0;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        staged = staged && L.kind[v] == L.kind[0];
+        rb0 = min(rb0, L.r0[v]);
+        rb1 = max(rb1, L.r1[v]);
+    }
+    double lb = 1e300, le = 1e300, hb = -1e300, he = -1e300;
+    if (staged && rb0 < rb1) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            lb = fmin(lb, fma((double)rb0, L.m[v], L.lmin[v]));
+            le = fmin(le, fma((double)(rb1 - 1), L.m[v], L.lmin[v]));
+            hb = fmax(hb, fma((double)rb0, L.m[v], L.rmax[v]));
+            he = fmax(he, fma((double)(rb1 - 1), L.m[v], L.rmax[v]));
+        }
+        // taps reach 2 columns right of a lane's position (truncation of a negative
+        // position adds one); org sits 2 below the lower chord
+        staged = fmax(hb - lb, he - le) + 6.0 <= (double)W;
+    }
+    if (!staged) {
+        if (a < n_ang) forward_ray(xr, xc, y, ang, a, i, N, S, n_det, ds, s0);
+        return;
+    }
+    T acc = T(0);
+    if (rb0 < rb1) {
+        const T *img = L.kind[0] == 1 ? xr : xc;       // padded rows
+        const double slope = rb1 - 1 > rb0 ? (le - lb) / (double)(rb1 - 1 - rb0) : 0.0;
+        const long long ofx0 = uniform_ll(__double2ll_rn((lb - 2.0) * 0x1p32));
+        const long long dfx = uniform_ll(__double2ll_rn(slope * 0x1p32));
+        auto org_of = [&](int r) { return (int)((ofx0 + (long long)(r - rb0) * dfx) >> 32); };
+        auto stage = [&](int cb, int par) {
+#pragma unroll
+            for (int q = 0; q < kStageBands / 4; ++q) {
+                const int r = cb + wave + 4 * q;
+                if (r < rb1) {
+                    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                        const_cast<T *>(img + (size_t)r * S), (short)0, S * (int)sizeof(T),
+                        kRawBufferFlags);
+                    __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                        rs, (__attribute__((address_space(3))) void *)&L.win[par][r - cb][0], 16,
+                        org_of(r) * (int)sizeof(T) + lane * 16, 0, 0, 0);
+                }
+            }
+        };
+        Band<T> band(fma((double)wr0, P.m, lo0), P.m);
+        const BandWeights<T> bw(P.invq, P.len);
+        stage(rb0, 0);
+        int par = 0;
+        for (int cb = rb0; cb < rb1; cb += kStageBands, par ^= 1) {
+            __builtin_amdgcn_s_waitcnt(0);                 // this wave's rows have landed
+            __syncthreads();                               // every wave's rows, and the other
+                                                           // buffer is free again
+            if (cb + kStageBands < rb1) stage(cb + kStageBands, par ^ 1);
+            const int e0 = max(cb, wr0), e1 = min(cb + kStageBands, wr1);
+            for (int r = e0; r < e1; ++r) {
+                const int c = band.column_raw();
+                const T w = band.left_length(bw);
+                band.next();
+                // the column within the window as one vector value (kept whole, so that
+                // both taps come from one address)
+                int off = c - org_of(r);
+                asm volatile("" : "+v"(off));
+                const Taps<T> t = *reinterpret_cast<const Taps<T> *>(&L.win[par][r - cb][off]);
+                acc = fma(w, t.a, acc);
+                acc = fma(bw.len - w, t.b, acc);
+            }
+        }
+    }
+    if (a < n_ang && i < n_det) y[(size_t)a * n_det + i] = acc;
+}
+
 }  // namespace
 }  // namespace abg

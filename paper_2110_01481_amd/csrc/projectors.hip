@@ -75,6 +75,29 @@ __global__ __launch_bounds__(kFwdBlock) void forward_kernel(
     forward_ray(xr, xc, y, ang, a, sh.lane_ray(wave), N, S, n_det, ds, s0);
 }
 
+// Line model, four angles per block: a share of the blocks (stage_eighths of every 8,
+// spread over the grid by a hash of the block index) walk with their band rows staged in
+// LDS, the others take their taps straight from the image copies.
+template <typename T>
+__global__ __launch_bounds__(kFwdBlock) void forward_mixed_kernel(
+    const T *__restrict__ xr, const T *__restrict__ xc, T *__restrict__ y,
+    const AngleParams *__restrict__ ang, int N, int S, int n_ang, int n_det, double ds,
+    double s0, const DevState *st, int k, int stage_eighths)
+{
+    if (halted(st, k)) return;
+    __shared__ FwdStageLds<T> lds;
+    const unsigned b = blockIdx.y * gridDim.x + blockIdx.x;
+    if ((int)((b * 0x9E3779B1u) >> 29) < stage_eighths) {
+        forward_block_staged(xr, xc, y, ang, blockIdx.y * 4, blockIdx.x * 64, N, S, n_ang, n_det,
+                             ds, s0, lds);
+        return;
+    }
+    const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+    const int a = blockIdx.y * 4 + wave;
+    if (a >= n_ang) return;
+    forward_ray(xr, xc, y, ang, a, blockIdx.x * 64 + ((int)threadIdx.x & 63), N, S, n_det, ds, s0);
+}
+
 // Strip (MODEL = ABG_FP_STRIP) and interpolation (ABG_FP_JOSEPH) models.
 template <typename T, int MODEL>
 __global__ __launch_bounds__(kFwdBlock) void forward_model_kernel(
@@ -148,6 +171,15 @@ hipError_t forward_t(const Geometry &g, const void *x, void *y, void *ws, hipStr
     const int apb = 1 << sh.lg_apb, rays = kFwdBlock >> sh.lg_apb;
     dim3 grid((g.n_det + rays - 1) / rays, (g.n_ang + apb - 1) / apb);
     const double s0 = -0.5 * (g.n_det - 1) * g.ds;
+    const int stage = fwd_stage_eighths(sizeof(T) == 8 ? ABG_F64 : ABG_F32);
+    if (sh.lg_apb == 2 && g.model == ABG_FP_LINE && stage > 0) {
+        ProfScope ps(kProfFwd, s, st ? k : 0, true);
+        hipExtLaunchKernelGGL(forward_mixed_kernel<T>, grid, dim3(kFwdBlock), 0, s, ps.e0, ps.e1, 0,
+                              (const T *)xr, (const T *)xc, static_cast<T *>(y),
+                              (const AngleParams *)g.dev, N, S, g.n_ang, g.n_det, g.ds, s0, st, k,
+                              stage);
+        return hipGetLastError();
+    }
     {
         // timed at the kernel's own start and end when profiling is on
         ProfScope ps(kProfFwd, s, st ? k : 0, true);
@@ -214,6 +246,24 @@ int fwd_lg_angles_per_block(const Geometry &g)
 }
 
 void fwd_force_block_shape(int lg_apb) { g_fwd_force_lg.store(lg_apb >= 0 && lg_apb <= 2 ? lg_apb : -1); }
+
+namespace {
+std::atomic<int> g_fwd_stage{-1};
+}  // namespace
+// Eighths of the four-angle forward blocks (line model) that stage their band rows in
+// LDS, from measurements on gfx950 (all shares give the same bits; ms per apply at
+// 0 / 2 / 3 eighths): FP32 three eighths (2048^2 x 1800 angles 3.10 / 2.77 / 2.72, 1024^2
+// x 900 0.45 / 0.41 / 0.41, 768^2 x 900 over 120 degrees 0.31 / 0.26 / 0.26, 2048^2 x
+// 600 1.16 / 1.08 / 1.08). FP64 none: its gathers return twice the bytes, and the mix
+// gains at most a few per cent where adjacent angles are close (2048^2 x 1800 3.15-3.20 /
+// 3.10-3.16) and loses where they are not (2048^2 x 600 1.33-1.37 / 1.41-1.42).
+int fwd_stage_eighths(int dtype)
+{
+    const int forced = g_fwd_stage.load(std::memory_order_relaxed);
+    if (forced >= 0) return forced;
+    return dtype == ABG_F64 ? 0 : 3;
+}
+void fwd_force_stage_eighths(int e) { g_fwd_stage.store(e >= 0 && e <= 8 ? e : -1); }
 
 size_t fp_workspace_bytes(const Geometry &g, int dtype)
 {

@@ -87,8 +87,10 @@ def test_gpu_adjoint_identity(gpu_lib, kw):
 @pytest.mark.parametrize("dt", ["f64", "f32"])
 def test_forward_block_shapes_bit_identical(gpu_lib, kw, dt):
     """The forward projectors' block shapes (one, two or four angles per block) change
-    only which rays run together: every model gives bit-identical sinograms for every
-    shape, on ragged angle counts (waves past the last angle) and ragged detector rows.
+    only which rays run together, and a four-angle block that stages its band rows in LDS
+    only where its taps are read: every model gives bit-identical sinograms for every
+    shape and share of staged blocks (none, three eighths, all), on ragged angle counts
+    (waves past the last angle) and ragged detector rows.
     The automatic shape is four angles per block for the 1030^2 geometry, two for
     n_det = 91, 183 or 300, one for the others."""
     import torch
@@ -106,9 +108,15 @@ def test_forward_block_shapes_bit_identical(gpu_lib, kw, dt):
             for lg in (0, 1, 2):
                 abg.fp_force_block_shape(lg)
                 assert torch.equal(gg.fp(x), auto), (model, lg)
+            abg.fp_force_block_shape(2)
+            for share in (0, 3, 8):
+                abg.fp_force_stage_share(share)
+                assert torch.equal(gg.fp(x), auto), (model, "stage", share)
+            abg.fp_force_stage_share(-1)
             gg.close()
     finally:
         abg.fp_force_block_shape(-1)
+        abg.fp_force_stage_share(-1)
 
 
 def test_back_projection_of_a_sinogram_over_2gib(gpu_lib):
