@@ -373,7 +373,7 @@ int abg_ncp_force_goertzel(int on);
 /* Block shape of the forward projectors (line, strip and Joseph models): each block of
  * 256 threads takes 2^lg_angles consecutive angles and 256 / 2^lg_angles consecutive rays
  * of each (0: one angle, 1: two, 2: four). -1 (the default) chooses by image size: four
- * angles for N > 640, else one, or two where that leaves fewer lanes of the last block of
+ * angles for N > 512, else one, or two where that leaves fewer lanes of the last block of
  * each angle idle. The shape changes only
  * which rays run together, never a ray's arithmetic: results are bit-identical for every
  * shape. Process-wide; for tests and measurements. Returns ABG_OK, or ABG_EINVAL for
@@ -384,9 +384,10 @@ int abg_fp_force_block_shape(int lg_angles);
  * row's columns in LDS and read their taps there, in eighths (0..8), spread over the grid;
  * the other blocks read their taps from the image copies. The two kinds take their taps
  * through different units of a compute unit, so a mix of them gathers faster than either
- * alone. -1 (the default) restores the automatic share: three eighths in FP32, none in
- * FP64. Results are bit-identical for
- * every share. Process-wide; for tests and measurements. Returns ABG_OK, or ABG_EINVAL
+ * alone. -1 (the default) restores the automatic share: three eighths in FP32; in FP64
+ * two at N = 1024 and three below while N times the angle step (radians) is at most 4,
+ * else none (the engine's forward items: FP32 three, FP64 none). Results are
+ * bit-identical for every share. Process-wide; for tests and measurements. Returns ABG_OK, or ABG_EINVAL
  * for eighths outside -1..8. */
 int abg_fp_force_stage_share(int eighths);
 

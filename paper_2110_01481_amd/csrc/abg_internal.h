@@ -215,6 +215,7 @@ void fwd_force_block_shape(int lg_apb);
 // geometry: the choice single solves make, or the forced one.
 int fwd_lg_angles_per_block(const Geometry &g);
 int fwd_stage_eighths(int dtype);
+int fwd_stage_eighths(const Geometry &g, int dtype);
 void fwd_force_stage_eighths(int eighths);
 // d_k of the residual r into st->ncp; raises the NCP stop for step k when k >= 2 and
 // d_k > d_{k-1}. `snap`: as for launch_combine.

@@ -171,7 +171,7 @@ hipError_t forward_t(const Geometry &g, const void *x, void *y, void *ws, hipStr
     const int apb = 1 << sh.lg_apb, rays = kFwdBlock >> sh.lg_apb;
     dim3 grid((g.n_det + rays - 1) / rays, (g.n_ang + apb - 1) / apb);
     const double s0 = -0.5 * (g.n_det - 1) * g.ds;
-    const int stage = fwd_stage_eighths(sizeof(T) == 8 ? ABG_F64 : ABG_F32);
+    const int stage = fwd_stage_eighths(g, sizeof(T) == 8 ? ABG_F64 : ABG_F32);
     if (sh.lg_apb == 2 && g.model == ABG_FP_LINE && stage > 0) {
         ProfScope ps(kProfFwd, s, st ? k : 0, true);
         hipExtLaunchKernelGGL(forward_mixed_kernel<T>, grid, dim3(kFwdBlock), 0, s, ps.e0, ps.e1, 0,
@@ -228,7 +228,8 @@ std::atomic<int> g_fwd_force_lg{-1};
 
 
 // Angles per block of the forward projectors (log2), from measurements on gfx950 (all
-// shapes give the same bits). Four angles per block pay from N = 768 up: the 4 MB L2 of
+// shapes give the same bits). Four angles per block pay above N = 512 (640^2 x 720
+// angles x 907 bins: 244 us with one angle per block, 177 with four): the 4 MB L2 of
 // an XCD holds only about three band steps of the rows its resident waves read, so rows
 // are reused only by waves walking nearly the same rows at nearly the same time -- the
 // waves of one block at adjacent angles (FP64: 9% faster at 768^2, 27% at 2048^2, 42% at
@@ -240,7 +241,7 @@ int fwd_lg_angles_per_block(const Geometry &g)
 {
     const int forced = g_fwd_force_lg.load(std::memory_order_relaxed);
     if (forced >= 0) return forced;
-    if (g.N > 640) return 2;
+    if (g.N > 512) return 2;
     const long long lanes1 = (g.n_det + 255LL) / 256 * 256, lanes2 = (g.n_det + 127LL) / 128 * 128;
     return lanes2 < lanes1 ? 1 : 0;
 }
@@ -251,17 +252,34 @@ namespace {
 std::atomic<int> g_fwd_stage{-1};
 }  // namespace
 // Eighths of the four-angle forward blocks (line model) that stage their band rows in
-// LDS, from measurements on gfx950 (all shares give the same bits; ms per apply at
-// 0 / 2 / 3 eighths): FP32 three eighths (2048^2 x 1800 angles 3.10 / 2.77 / 2.72, 1024^2
-// x 900 0.45 / 0.41 / 0.41, 768^2 x 900 over 120 degrees 0.31 / 0.26 / 0.26, 2048^2 x
-// 600 1.16 / 1.08 / 1.08). FP64 none: its gathers return twice the bytes, and the mix
-// gains at most a few per cent where adjacent angles are close (2048^2 x 1800 3.15-3.20 /
-// 3.10-3.16) and loses where they are not (2048^2 x 600 1.33-1.37 / 1.41-1.42).
+// LDS, from measurements on gfx950 (all shares give the same bits; times per apply at
+// 0 / 2 / 3 eighths): FP32 three eighths (2048^2 x 1800 angles 3.10 / 2.77 / 2.72 ms,
+// 1024^2 x 900 0.45 / 0.41 / 0.41 ms, 640^2 x 720 177 / 166 / 161 us, 256^2 x 360 50 / 43
+// / 42 us, 2048^2 x 600 1.16 / 1.08 / 1.08 ms). FP64, whose gathers return twice the
+// bytes: two eighths at 1024^2 (0.47-0.53 / 0.44-0.47 ms), three below (640^2 x 720 190 /
+// 174 / 175 us, 384^2 x 600 80 / 79 / 74, 256^2 x 360 53 / 52 / 43), where the four
+// angles of a block stay close (N times the angle step at most 4 px; 2048^2 x 600, at
+// 10.7, 1.33-1.37 / 1.41-1.42 ms), and none above 1024 (2048^2 x 1800 3.15-3.23 /
+// 3.10-3.18 / 3.20 ms, within what boxes differ by). The engine's forward items take the
+// FP32 / FP64 rule without the geometry.
 int fwd_stage_eighths(int dtype)
 {
     const int forced = g_fwd_stage.load(std::memory_order_relaxed);
     if (forced >= 0) return forced;
     return dtype == ABG_F64 ? 0 : 3;
+}
+int fwd_stage_eighths(const Geometry &g, int dtype)
+{
+    const int forced = g_fwd_stage.load(std::memory_order_relaxed);
+    if (forced >= 0) return forced;
+    if (dtype != ABG_F64) return 3;
+    if (g.N > 1024) return 0;
+    // mean step between listed angles (degrees), in radians
+    const double step = g.n_ang > 1 ? std::fabs(g.theta.back() - g.theta.front()) / (g.n_ang - 1) *
+                                          (3.14159265358979323846 / 180.0)
+                                    : 1.0;
+    if (g.N * step > 4.0) return 0;
+    return g.N >= 1024 ? 2 : 3;
 }
 void fwd_force_stage_eighths(int e) { g_fwd_stage.store(e >= 0 && e <= 8 ? e : -1); }
 
