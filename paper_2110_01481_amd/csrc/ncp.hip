@@ -264,12 +264,22 @@ __global__ __launch_bounds__(kFftThreads) void ncp_fft_rows_kernel(
         }
         __syncthreads();
     }
-    for (int i = t; i < M; i += kFftThreads) z[i] = cmul(z[i], khat[i]);
-    __syncthreads();
+    // the product with the kernel's transform: in the first inverse step's loads, or a
+    // pass of its own when that step is a single span (M = 2)
+    if (M <= 2) {
+        for (int i = t; i < M; i += kFftThreads) z[i] = cmul(z[i], khat[i]);
+        __syncthreads();
+    }
     for (h = 1; 2 * h < M; h <<= 2) {                   // spans h and 2h
         for (int b = t; b < quarter; b += kFftThreads) {
             const int j = b & (h - 1), i = ((b - j) << 2) + j;
             double2 a0 = z[i], a1 = z[i + h], a2 = z[i + 2 * h], a3 = z[i + 3 * h];
+            if (h == 1) {
+                a0 = cmul(a0, khat[i]);
+                a1 = cmul(a1, khat[i + 1]);
+                a2 = cmul(a2, khat[i + 2]);
+                a3 = cmul(a3, khat[i + 3]);
+            }
             const double2 w1 = tw[h - 1 + j];
             dit(a0, a1, w1);
             dit(a2, a3, w1);
