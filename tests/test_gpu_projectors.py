@@ -82,7 +82,8 @@ def test_gpu_adjoint_identity(gpu_lib, kw):
     assert abs(lhs - rhs) <= 1e-12 * (abs(lhs) + abs(rhs))
 
 
-@pytest.mark.parametrize("kw", GEOMS + [dict(N=512, n_ang=7, n_det=725), dict(N=1030, n_ang=6, n_det=1459)],
+@pytest.mark.parametrize("kw", GEOMS + [dict(N=512, n_ang=7, n_det=725), dict(N=1030, n_ang=6, n_det=1459),
+                                 dict(N=600, n_ang=721, n_det=851, ang_range=150.0)],
                          ids=_ids)
 @pytest.mark.parametrize("dt", ["f64", "f32"])
 def test_forward_block_shapes_bit_identical(gpu_lib, kw, dt):
@@ -91,8 +92,9 @@ def test_forward_block_shapes_bit_identical(gpu_lib, kw, dt):
     only where its taps are read: every model gives bit-identical sinograms for every
     shape and share of staged blocks (none, three eighths, all), on ragged angle counts
     (waves past the last angle) and ragged detector rows.
-    The automatic shape is four angles per block for the 1030^2 geometry, two for
-    n_det = 91, 183 or 300, one for the others."""
+    The automatic shape is four angles per block for the 600^2 and 1030^2 geometries
+    (600^2 with 721 close angles also stages a share of its blocks in FP64 and FP32),
+    two for n_det = 91, 183 or 300, one for the others."""
     import torch
     import paper_2110_01481_amd as abg
     tdt = torch.float64 if dt == "f64" else torch.float32
