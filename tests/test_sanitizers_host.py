@@ -7,7 +7,7 @@
 * the library with its host code instrumented (paper_2110_01481_amd/build.py
   build_host_sanitized: -Xarch_host before every -fsanitize=, device code as usual) driven
   by an instrumented C++ program through every C-ABI entry point: invalid arguments here;
-  on a GPU machine the same program also runs solves of every kind (test_gpu_sanitized_host).
+  with a GPU the same program also runs solves of every kind (test_gpu_sanitized_host).
 """
 import os
 import subprocess
