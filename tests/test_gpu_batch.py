@@ -100,6 +100,36 @@ def test_alone_equals_mix_bitwise(gpu_lib, mix):
         assert np.array_equal(alone.ls_hist, in_mix[i].ls_hist)
 
 
+def test_round_graph_variants_give_the_same_bits(gpu_lib, mix):
+    """The engine runs a round's AB and BA projector chains as two graph branches while
+    every problem's image and sinogram stay under 32 MB, and in sequence otherwise. With
+    one 2048^2 x 1800 x 2897 problem (38 MB in FP32, three steps) beside the small mix,
+    the first rounds take the sequential graph and the later ones the branched graph:
+    every problem's result equals its result alone, bit for bit."""
+    import torch
+    abg = gpu_lib
+    N, n_ang, n_det = 2048, 1800, 2897
+    gbig = abg.Geometry(N, n_ang, n_det)
+    rng = np.random.default_rng(7)
+    bbig = torch.tensor(rng.uniform(size=n_ang * n_det), dtype=torch.float32, device="cuda")
+
+    def big(tag=0):
+        return abg.Problem(g=gbig, method="ba", b=bbig, k_max=3, stop="none", tag=tag)
+
+    eng = abg.Engine(proj="f32", basis="f32", max_slots=len(mix) + 1)
+    probs = [c.problem(abg, torch.float32, tag=i) for i, c in enumerate(mix)] + [big(len(mix))]
+    in_mix = eng.run(probs)
+    alone_big = abg.Engine(proj="f32", basis="f32", max_slots=1).run([big()])[0]
+    assert alone_big.k_done == in_mix[-1].k_done and alone_big.status == in_mix[-1].status
+    assert torch.equal(alone_big.x, in_mix[-1].x)
+    assert np.array_equal(alone_big.ls_hist, in_mix[-1].ls_hist)
+    for i in (0, 1, 3, 6):
+        alone = abg.Engine(proj="f32", basis="f32", max_slots=1).run([mix[i].problem(abg, torch.float32)])[0]
+        assert alone.k_stop == in_mix[i].k_stop and alone.status == in_mix[i].status
+        assert torch.equal(alone.x, in_mix[i].x), i
+    gbig.close()
+
+
 def test_continuous_admission_through_few_slots(gpu_lib, mix):
     """Eight problems through three slots, submitted as slots free up (slots are reused
     while other problems are mid-solve): results equal the all-at-once mix bit for bit."""
