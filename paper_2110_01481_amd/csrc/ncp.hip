@@ -10,7 +10,7 @@
 // Bluestein's chirp transform: with c_i = exp(-pi i i^2/n), 2ij = i^2 + j^2 - (j-i)^2
 // gives X_j = c_j sum_i (r_i c_i) conj(c_{j-i}), a linear convolution of length 2n-1,
 // done cyclically with two power-of-two FFTs of length M >= 2n-1 held in LDS (M <= 8192:
-// 128 KB of complex FP64). One block transforms two rows at once, packed as the real and
+// 128 KB of complex FP64, 144 KB with one padding slot per eight). One block transforms two rows at once, packed as the real and
 // imaginary part of one complex row (the rows are real; their spectra are separated by
 // conjugate symmetry after the final chirp); the 1/M of the inverse transform cancels in
 // the normalisation. The
@@ -109,8 +109,17 @@ __global__ __launch_bounds__(kBlock) void ncp_colsum_kernel(const double *__rest
     const int j = blockIdx.x * kBlock + threadIdx.x;
     const int a0 = blockIdx.y * rows_per, a1 = min(n_ang, a0 + rows_per);
     if (j >= q) return;
+    // in row order, eight rows' loads issued before their adds
     double s = 0.0;
-    for (int a = a0; a < a1; ++a) s += crow[(size_t)a * q + j];
+    int a = a0;
+    for (; a + 8 <= a1; a += 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = crow[(size_t)(a + u) * q + j];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    for (; a < a1; ++a) s += crow[(size_t)a * q + j];
     colsum[(size_t)blockIdx.y * q + j] = s;
 }
 
@@ -127,7 +136,15 @@ __global__ __launch_bounds__(kBlock) void ncp_dist_kernel(const double *__restri
     double d2 = 0.0;
     if (j < q) {
         double s = 0.0;
-        for (int c = 0; c < n_chunks; ++c) s += colsum[(size_t)c * q + j];
+        int c = 0;
+        for (; c + 8 <= n_chunks; c += 8) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = colsum[(size_t)(c + u) * q + j];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s += v[u];
+        }
+        for (; c < n_chunks; ++c) s += colsum[(size_t)c * q + j];
         const double dev = s / (double)n_ang - (double)(j + 1) / (double)q;
         d2 = dev * dev;
     }
@@ -191,26 +208,39 @@ __global__ __launch_bounds__(kFftThreads) void ncp_fft_rows_kernel(
     const double2 *__restrict__ khat, const double2 *__restrict__ tw, double *__restrict__ crow,
     const DevState *st, int k)
 {
-    extern __shared__ double2 z[];          // M values
+    extern __shared__ double2 zs[];         // M values in M + M / 8 slots
     __shared__ double wsum[2][kFftThreads / 64];
     __shared__ double total_s[2];
     if (halted(st, k)) return;
+    // element i at i + i / 8: a lane's run of 4 or 8 consecutive elements (the passes of
+    // short spans) and runs of consecutive lanes both spread over the LDS banks
+    auto z = [&](int i) -> double2 & { return zs[i + (i >> 3)]; };
     const int t = threadIdx.x;
     const int ra = 2 * (int)blockIdx.x, rb = ra + 1;
     const bool has_b = rb < n_ang;
     const T *src_a = r + (size_t)ra * n_det;
     const T *src_b = r + (size_t)(has_b ? rb : ra) * n_det;
+    // all of a thread's loads issued before the first is used (M / kFftThreads <= 8)
     int nz_a = 0, nz_b = 0;
-    for (int i = t; i < M; i += kFftThreads) {
-        double2 v = make_double2(0.0, 0.0);
-        if (i < n_det) {
-            const double xa = (double)src_a[i];
-            const double xb = has_b ? (double)src_b[i] : 0.0;
-            nz_a |= xa != 0.0;
-            nz_b |= xb != 0.0;
-            v = cmul(make_double2(xa, xb), chirp[i]);
+    {
+        constexpr int kPer = kFftMaxM / kFftThreads;
+        double xa[kPer], xb[kPer];
+        double2 c[kPer];
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int i = t + u * kFftThreads;
+            const bool in = i < n_det;
+            xa[u] = in ? (double)src_a[i] : 0.0;
+            xb[u] = in && has_b ? (double)src_b[i] : 0.0;
+            c[u] = in ? chirp[i] : make_double2(0.0, 0.0);
         }
-        z[i] = v;
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int i = t + u * kFftThreads;
+            nz_a |= xa[u] != 0.0;
+            nz_b |= xb[u] != 0.0;
+            if (i < M) z(i) = cmul(make_double2(xa[u], xb[u]), c[u]);
+        }
     }
     const bool live_a = __syncthreads_or(nz_a) != 0;
     const bool live_b = __syncthreads_or(nz_b) != 0;
@@ -229,98 +259,135 @@ __global__ __launch_bounds__(kFftThreads) void ncp_fft_rows_kernel(
         v = make_double2(u.x - px, u.y - py);
         u = make_double2(u.x + px, u.y + py);
     };
-    // Two consecutive passes run as one: a thread takes the four elements that the two
-    // spans join (offsets j, j + g, j + 2g, j + 3g of a block of 4g) through both passes
-    // in registers -- the same operations on every element as two radix-2 passes, with
-    // half the LDS traffic and barriers.
+    // Two or three consecutive passes run as one: a thread takes the 4 (8) elements that
+    // the spans join (offsets j + m g of a block of 4g (8g)) through the passes in
+    // registers -- the same operations on every element as the radix-2 passes, with a
+    // half (a third) of the LDS traffic and barriers. The product with the kernel's
+    // transform is taken in the loads of the inverse transform's first pass (span 1).
     int lg = 0;
     while ((1 << lg) < M) ++lg;
-    int h = half;
-    if (lg & 1) {                                       // odd number of passes: one alone
+    const int eighth = M >> 3;
+    auto pass1 = [&](int h, bool inv) {                 // span h alone
         for (int b = t; b < half; b += kFftThreads) {
             const int j = b & (h - 1), i = ((b - j) << 1) + j;
-            double2 u = z[i], v = z[i + h];
-            dif(u, v, tw[h - 1 + j]);
-            z[i] = u;
-            z[i + h] = v;
+            double2 u = z(i), v = z(i + h);
+            if (inv) {
+                if (h == 1) {
+                    u = cmul(u, khat[i]);
+                    v = cmul(v, khat[i + 1]);
+                }
+                dit(u, v, tw[h - 1 + j]);
+            } else {
+                dif(u, v, tw[h - 1 + j]);
+            }
+            z(i) = u;
+            z(i + h) = v;
         }
         __syncthreads();
-        h >>= 1;
-    }
-    for (; h >= 2; h >>= 2) {                           // spans h and h / 2
-        const int g = h >> 1;
+    };
+    auto pass2 = [&](int g, bool inv) {                 // spans 2g, g (forward); g, 2g
         for (int b = t; b < quarter; b += kFftThreads) {
             const int j = b & (g - 1), i = ((b - j) << 2) + j;
-            double2 a0 = z[i], a1 = z[i + g], a2 = z[i + 2 * g], a3 = z[i + 3 * g];
-            dif(a0, a2, tw[h - 1 + j]);
-            dif(a1, a3, tw[h - 1 + j + g]);
-            const double2 w2 = tw[g - 1 + j];
-            dif(a0, a1, w2);
-            dif(a2, a3, w2);
-            z[i] = a0;
-            z[i + g] = a1;
-            z[i + 2 * g] = a2;
-            z[i + 3 * g] = a3;
-        }
-        __syncthreads();
-    }
-    // the product with the kernel's transform: in the first inverse step's loads, or a
-    // pass of its own when that step is a single span (M = 2)
-    if (M <= 2) {
-        for (int i = t; i < M; i += kFftThreads) z[i] = cmul(z[i], khat[i]);
-        __syncthreads();
-    }
-    for (h = 1; 2 * h < M; h <<= 2) {                   // spans h and 2h
-        for (int b = t; b < quarter; b += kFftThreads) {
-            const int j = b & (h - 1), i = ((b - j) << 2) + j;
-            double2 a0 = z[i], a1 = z[i + h], a2 = z[i + 2 * h], a3 = z[i + 3 * h];
-            if (h == 1) {
-                a0 = cmul(a0, khat[i]);
-                a1 = cmul(a1, khat[i + 1]);
-                a2 = cmul(a2, khat[i + 2]);
-                a3 = cmul(a3, khat[i + 3]);
+            double2 a0 = z(i), a1 = z(i + g), a2 = z(i + 2 * g), a3 = z(i + 3 * g);
+            if (inv) {
+                if (g == 1) {
+                    a0 = cmul(a0, khat[i]);
+                    a1 = cmul(a1, khat[i + 1]);
+                    a2 = cmul(a2, khat[i + 2]);
+                    a3 = cmul(a3, khat[i + 3]);
+                }
+                const double2 w1 = tw[g - 1 + j];
+                dit(a0, a1, w1);
+                dit(a2, a3, w1);
+                dit(a0, a2, tw[2 * g - 1 + j]);
+                dit(a1, a3, tw[2 * g - 1 + j + g]);
+            } else {
+                dif(a0, a2, tw[2 * g - 1 + j]);
+                dif(a1, a3, tw[2 * g - 1 + j + g]);
+                const double2 w1 = tw[g - 1 + j];
+                dif(a0, a1, w1);
+                dif(a2, a3, w1);
             }
-            const double2 w1 = tw[h - 1 + j];
-            dit(a0, a1, w1);
-            dit(a2, a3, w1);
-            dit(a0, a2, tw[2 * h - 1 + j]);
-            dit(a1, a3, tw[2 * h - 1 + j + h]);
-            z[i] = a0;
-            z[i + h] = a1;
-            z[i + 2 * h] = a2;
-            z[i + 3 * h] = a3;
+            z(i) = a0;
+            z(i + g) = a1;
+            z(i + 2 * g) = a2;
+            z(i + 3 * g) = a3;
         }
         __syncthreads();
-    }
-    if (h < M) {                                        // the last span alone
-        for (int b = t; b < half; b += kFftThreads) {
-            const int j = b & (h - 1), i = ((b - j) << 1) + j;
-            double2 u = z[i], v = z[i + h];
-            dit(u, v, tw[h - 1 + j]);
-            z[i] = u;
-            z[i + h] = v;
+    };
+    auto pass3 = [&](int g, bool inv) {                 // spans 4g, 2g, g; g, 2g, 4g
+        for (int b = t; b < eighth; b += kFftThreads) {
+            const int j = b & (g - 1), i = ((b - j) << 3) + j;
+            double2 a[8];
+#pragma unroll
+            for (int m = 0; m < 8; ++m) a[m] = z(i + m * g);
+            const double2 w2a = tw[2 * g - 1 + j], w2b = tw[2 * g - 1 + j + g];
+            const double2 w1 = tw[g - 1 + j];
+            if (inv) {
+                if (g == 1) {
+#pragma unroll
+                    for (int m = 0; m < 8; ++m) a[m] = cmul(a[m], khat[i + m]);
+                }
+#pragma unroll
+                for (int m = 0; m < 8; m += 2) dit(a[m], a[m + 1], w1);
+                dit(a[0], a[2], w2a);
+                dit(a[1], a[3], w2b);
+                dit(a[4], a[6], w2a);
+                dit(a[5], a[7], w2b);
+#pragma unroll
+                for (int m = 0; m < 4; ++m) dit(a[m], a[m + 4], tw[4 * g - 1 + j + m * g]);
+            } else {
+#pragma unroll
+                for (int m = 0; m < 4; ++m) dif(a[m], a[m + 4], tw[4 * g - 1 + j + m * g]);
+                dif(a[0], a[2], w2a);
+                dif(a[1], a[3], w2b);
+                dif(a[4], a[6], w2a);
+                dif(a[5], a[7], w2b);
+#pragma unroll
+                for (int m = 0; m < 8; m += 2) dif(a[m], a[m + 1], w1);
+            }
+#pragma unroll
+            for (int m = 0; m < 8; ++m) z(i + m * g) = a[m];
         }
         __syncthreads();
+    };
+    // forward: spans M/2 .. 1, the lg mod 3 largest first
+    int h = half;
+    if (lg % 3 == 1) {
+        pass1(h, false);
+        h >>= 1;
+    } else if (lg % 3 == 2) {
+        pass2(h >> 1, false);
+        h >>= 2;
     }
+    for (; h >= 4; h >>= 3) pass3(h >> 2, false);
+    // inverse: spans 1 .. M/2, the lg mod 3 largest last
+    for (h = 1; 8 * h <= M; h <<= 3) pass3(h, true);
+    if (lg % 3 == 1) pass1(h, true);
+    else if (lg % 3 == 2) pass2(h, true);
     // both rows' periodograms at frequency j (up to the common factor M^2 / 4)
     auto power = [&](int j, double &pa, double &pb) {
-        const double2 zj = cmul(z[j], chirp[j]);
-        const double2 zn = cmul(z[n_det - j], chirp[n_det - j]);
+        const double2 zj = cmul(z(j), chirp[j]);
+        const double2 zn = cmul(z(n_det - j), chirp[n_det - j]);
         const double ax = zj.x + zn.x, ay = zj.y - zn.y;    // 2 X_a
         const double bx = zj.y + zn.y, by = zn.x - zj.x;    // 2 X_b
         pa = fma(ax, ax, ay * ay);
         pb = fma(bx, bx, by * by);
     };
-    // thread t owns frequencies j = 1 + t*J .. (t+1)*J; fixed-order prefix over threads
+    // thread t owns frequencies j = 1 + t*J .. (t+1)*J (J <= 2, as q <= (M + 1) / 4);
+    // their powers are formed once, with every load issued up front (a frequency past the
+    // thread's share reads frequency q and is dropped); fixed-order prefix over threads
+    constexpr int kMaxJ = (kFftMaxM / 4 + kFftThreads - 1) / kFftThreads;
     const int J = (q + kFftThreads - 1) / kFftThreads;
     double own_a = 0.0, own_b = 0.0;
-    for (int u = 0; u < J; ++u) {
-        const int j = 1 + t * J + u;
-        if (j <= q) {
-            double pa, pb;
-            power(j, pa, pb);
-            own_a += pa;
-            own_b += pb;
+    double pa[kMaxJ], pb[kMaxJ];
+#pragma unroll
+    for (int u = 0; u < kMaxJ; ++u) power(min(1 + t * J + u, q), pa[u], pb[u]);
+#pragma unroll
+    for (int u = 0; u < kMaxJ; ++u) {
+        if (u < J && 1 + t * J + u <= q) {
+            own_a += pa[u];
+            own_b += pb[u];
         }
     }
     // inclusive scans within the wave, then wave totals in order
@@ -350,13 +417,12 @@ __global__ __launch_bounds__(kFftThreads) void ncp_fft_rows_kernel(
     __syncthreads();
     const double total_a = live_a ? total_s[0] : 0.0, total_b = live_b ? total_s[1] : 0.0;
     double acc_a = wsum[0][wv] + inc_a - own_a, acc_b = wsum[1][wv] + inc_b - own_b;
-    for (int u = 0; u < J; ++u) {
+#pragma unroll
+    for (int u = 0; u < kMaxJ; ++u) {
         const int j = 1 + t * J + u;
-        if (j <= q) {
-            double pa, pb;
-            power(j, pa, pb);
-            acc_a += pa;
-            acc_b += pb;
+        if (u < J && j <= q) {
+            acc_a += pa[u];
+            acc_b += pb[u];
             const double white = (double)j / (double)q;
             crow[(size_t)ra * q + (j - 1)] = total_a > 0.0 ? acc_a / total_a : white;
             if (has_b) crow[(size_t)rb * q + (j - 1)] = total_b > 0.0 ? acc_b / total_b : white;
@@ -472,7 +538,7 @@ hipError_t fft_rows_go(const Geometry &g, int M, const void *r, double *crow, in
     const double2 *chirp, *khat, *tw;
     hipError_t e = ncp_tables(g, M, &chirp, &khat, &tw);
     if (e != hipSuccess) return e;
-    ncp_fft_rows_kernel<T><<<(g.n_ang + 1) / 2, kFftThreads, (size_t)M * sizeof(double2), s>>>(
+    ncp_fft_rows_kernel<T><<<(g.n_ang + 1) / 2, kFftThreads, (size_t)(M + M / 8) * sizeof(double2), s>>>(
         static_cast<const T *>(r), g.n_ang, g.n_det, q, M, chirp, khat, tw, crow, st, k);
     return hipGetLastError();
 }
