@@ -264,6 +264,35 @@ def test_ncp_odd_angle_counts_and_even_rows(gpu_lib, method, n_ang, n_det):
         assert _rel(r.x.double().cpu().numpy(), ref.x) <= tol
 
 
+@pytest.mark.parametrize("N,n_ang,n_det", [(40, 12, 64), (110, 12, 200), (170, 12, 300),
+                                           (400, 10, 725), (780, 8, 1449)])
+def test_ncp_transform_lengths(gpu_lib, N, n_ang, n_det):
+    """The chirp transform's length M (the power of two >= 2 n_det - 1) sets how its
+    radix-2 passes group into register steps of three (and one of one or two spans): rows
+    of 64, 200, 300, 725 and 1449 bins give M = 128, 512, 1024, 2048 and 4096, every
+    residue of log2 M mod 3 and both sizes of the leftover step. Against the oracle's NCP
+    (Sec. 6.3): the same k_NCP, d_k within 1e-9 (FP64) / 1e-4 (FP32), both methods."""
+    import torch
+    import paper_2110_01481_amd as abg
+    go = O.Geometry(N, n_ang, n_det)
+    gg = abg.Geometry(N, n_ang, n_det)
+    xb = W.ellipse_phantom(N, 5, W.rng(96, n_det, W.STREAM_PHANTOM))
+    b, _ = W.add_noise(go.A(xb), 0.02, W.rng(96, n_det, W.STREAM_NOISE).standard_normal(go.m))
+    for method in ("ab", "ba"):
+        f = O.ab_gmres if method == "ab" else O.ba_gmres
+        ref = f(go.A, go.B_hat, b, 12, stop="ncp", ncp_shape=(go.n_ang, go.n_det))
+        for dt in ("f64", "f32"):
+            tdt = torch.float64 if dt == "f64" else torch.float32
+            r = abg.gmres(method, gg, torch.tensor(b, dtype=tdt, device="cuda"), 12,
+                          stop="ncp", basis=dt)
+            assert r.k_stop == ref.k_stop, (method, dt, r.k_stop, ref.k_stop)
+            n = min(len(ref.ncp), len(r.ncp_hist))
+            assert n >= 2
+            assert np.allclose(r.ncp_hist[:n], ref.ncp[:n], rtol=1e-9 if dt == "f64" else 1e-4,
+                               atol=1e-12), (method, dt,
+                                             np.abs(r.ncp_hist[:n] / np.asarray(ref.ncp[:n]) - 1).max())
+
+
 def test_ragged_geometry_and_initial_guess(gpu_lib):
     import torch
     import paper_2110_01481_amd as abg
