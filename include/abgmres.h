@@ -115,7 +115,11 @@ typedef struct {
     int k_done;          /* Arnoldi steps performed                                         */
     int status;          /* same value the call returns                                    */
     int n_literal;       /* explicit ||b - A x_k|| evaluations made for the DP decision     */
-    double res_norm;     /* ||b - A x||_2 of the returned x, evaluated explicitly           */
+    double res_norm;     /* ||b - A x||_2 of the returned x: evaluated explicitly, except   */
+                         /* BA-GMRES with the NCP rule, where it is the norm of the         */
+                         /* residual the rule evaluated for that iterate, b - A x_0 -       */
+                         /* sum_i y_i (A w_i) from the step's stored products A w_i (equal  */
+                         /* to b - A x up to the rounding of the sum; no further projection)*/
     double ncp_dist;     /* NCP distance d of the returned iterate (NCP runs)               */
     double beta;         /* ||r_0||_2                                                       */
     double *res_hist;    /* ||b - A x_k||_2 per k (DP and NCP runs), else untouched        */

@@ -562,6 +562,11 @@ int run_solver(const Geometry &g, int method, int kind, const void *b, const voi
         int best_k = 0;
         int k_sel = 0;        // step whose iterate is returned
         bool x_built = false; // x already holds x_{k_sel}, and res_final its residual
+        // BA-GMRES with the NCP rule: ||r_k|| of the residual each step forms for the rule,
+        // r_k = b - A x_0 - sum_i y_i (A w_i) from the stored products A w_i and the
+        // coefficients x_k is built from (b - A x_k up to the rounding of the sum)
+        const bool res_from_steps = method == ABG_METHOD_BA && st.kind == ABG_STOP_NCP;
+        std::vector<double> res_k(res_from_steps ? k_max + 1 : 0, 0.0);
         RC(S.enqueue_step(1));
         for (int k = 1; k <= k_max && k_sel == 0; ++k) {
             if (k < k_max) RC(S.enqueue_step(k + 1));
@@ -606,6 +611,7 @@ int run_solver(const Geometry &g, int method, int kind, const void *b, const voi
                 hist(info ? info->res_hist : nullptr, k, rk);
             } else if (st.kind == ABG_STOP_NCP) {
                 hist(info ? info->res_hist : nullptr, k, sk.res);
+                if (res_from_steps) res_k[k] = sk.res;
                 hist(info ? info->ncp_hist : nullptr, k, sk.ncp);
                 if (stop_here) {
                     k_sel = k - 1;   // d_k > d_{k-1}: x_{k-1} was closest to white noise
@@ -648,11 +654,16 @@ int run_solver(const Geometry &g, int method, int kind, const void *b, const voi
             k_stop = k_sel;
             if (!x_built) {
                 RC(S.build_x(S.ycol(k_sel), k_sel, x0, x));
-                // explicit residual of the returned iterate (a DP-confirmed iterate has
-                // it already); a NaN/Inf anywhere in b shows here
-                RC(S.literal_residual(b, x));
-                RC(S.sync_read(hs));
-                res_final = hs.res;
+                if (res_from_steps) {
+                    // the returned iterate's residual was formed at its own step
+                    res_final = res_k[k_sel];
+                } else {
+                    // explicit residual of the returned iterate (a DP-confirmed iterate
+                    // has it already); a NaN/Inf anywhere in b shows here
+                    RC(S.literal_residual(b, x));
+                    RC(S.sync_read(hs));
+                    res_final = hs.res;
+                }
             }
             if (!std::isfinite(res_final)) return ABG_ENAN;
         }

@@ -235,6 +235,23 @@ def test_ncp_same_k(gpu_lib, cfg1, method, path):
         assert _rel(r.x.double().cpu().numpy(), ref.x) <= tol
 
 
+@pytest.mark.parametrize("method", ["ab", "ba"])
+def test_ncp_res_norm_is_the_returned_iterates_residual(gpu_lib, cfg1, method):
+    """res_norm of an NCP solve is ||b - A x|| of the iterate it returns: in BA-GMRES the
+    norm of the residual the rule formed at that step from the stored products A w_i, in
+    AB-GMRES an explicit evaluation. Against the oracle's A applied to the returned x
+    (FP64 projector input): within 1e-12 (FP64) / 1e-4 (FP32: the projector's output
+    rounding, ~1e-7 of ||b||, against a residual of ~1% of ||b||)."""
+    go, gg, _, b, _ = cfg1
+    for dt in ("f64", "f32"):
+        r = _solve(method, gg, b, 30, dt=dt, stop="ncp")
+        x = r.x.double().cpu().numpy()
+        bb = b if dt == "f64" else b.astype(np.float32).astype(np.float64)
+        lit = np.linalg.norm(bb - go.A(x))
+        assert abs(r.res_norm - lit) <= (1e-12 if dt == "f64" else 1e-4) * lit, (dt, r.res_norm, lit)
+        assert r.res_hist[r.k_stop - 1] == r.res_norm or method == "ab"
+
+
 @pytest.mark.parametrize("n_ang,n_det", [(37, 69), (45, 100)])
 @pytest.mark.parametrize("method", ["ab", "ba"])
 def test_ncp_odd_angle_counts_and_even_rows(gpu_lib, method, n_ang, n_det):
