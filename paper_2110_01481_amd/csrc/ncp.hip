@@ -10,10 +10,10 @@
 // Bluestein's chirp transform: with c_i = exp(-pi i i^2/n), 2ij = i^2 + j^2 - (j-i)^2
 // gives X_j = c_j sum_i (r_i c_i) conj(c_{j-i}), a linear convolution of length 2n-1,
 // done cyclically with two power-of-two FFTs of length M >= 2n-1 held in LDS (M <= 8192:
-// 128 KB of complex FP64, 144 KB with one padding slot per eight). One block transforms two rows at once, packed as the real and
-// imaginary part of one complex row (the rows are real; their spectra are separated by
-// conjugate symmetry after the final chirp); the 1/M of the inverse transform cancels in
-// the normalisation. The
+// 128 KB of complex FP64, 144 KB with one padding slot per eight). One block transforms
+// two rows at once, packed as the real and imaginary part of one complex row (the rows are
+// real; their spectra are separated by conjugate symmetry after the final chirp); the 1/M
+// of the inverse transform cancels in the normalisation. The
 // transform of the fixed chirp kernel conj(c_t), the chirp c_i and the twiddle factors
 // are computed once per geometry on the host (FP64) and kept on the device. Short rows
 // (n < 64) and rows too long for LDS use Goertzel's recurrence per frequency instead
@@ -538,7 +538,8 @@ hipError_t fft_rows_go(const Geometry &g, int M, const void *r, double *crow, in
     const double2 *chirp, *khat, *tw;
     hipError_t e = ncp_tables(g, M, &chirp, &khat, &tw);
     if (e != hipSuccess) return e;
-    ncp_fft_rows_kernel<T><<<(g.n_ang + 1) / 2, kFftThreads, (size_t)(M + M / 8) * sizeof(double2), s>>>(
+    const size_t lds = (size_t)(M + M / 8) * sizeof(double2);   // skewed: one slot per eight
+    ncp_fft_rows_kernel<T><<<(g.n_ang + 1) / 2, kFftThreads, lds, s>>>(
         static_cast<const T *>(r), g.n_ang, g.n_det, q, M, chirp, khat, tw, crow, st, k);
     return hipGetLastError();
 }
